@@ -1,0 +1,223 @@
+"""FP64 CPU oracle for the t-product toolbox (Lu, 2018).
+
+TEST INFRASTRUCTURE ONLY.  Only the tests, the smoke check and the CPU-baseline
+leg of the benchmark may import this package; the GPU product path never does.
+It shares no code with the GPU library: the C sources here are compiled with
+gcc into ``liboracle.so`` and follow the paper's definitions and algorithms in
+double precision (see the header of ``tp_oracle.c`` for the readings taken).
+
+Arrays are numpy, C-contiguous, with the tube index last: a real tensor of
+size n1 x n2 x n3 is ``np.ndarray((n1, n2, n3), float64)``.
+"""
+import ctypes
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_LIB_PATH = os.path.join(_HERE, "liboracle.so")
+_lib = None
+
+_D = ctypes.POINTER(ctypes.c_double)
+_I = ctypes.c_int
+
+
+def _load():
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(_LIB_PATH):
+        from . import build as _b
+        _b.build()
+    lib = ctypes.CDLL(_LIB_PATH)
+    sig = {
+        "or_set_threads": (None, [_I]),
+        "or_get_threads": (_I, []),
+        "or_dft3": (None, [_D, _I, _I, _I, _I, _D]),
+        "or_bcirc": (None, [_D, _I, _I, _I, _D]),
+        "or_unfold": (None, [_D, _I, _I, _I, _D]),
+        "or_fold": (None, [_D, _I, _I, _I, _D]),
+        "or_tprod_def": (None, [_D, _D, _I, _I, _I, _I, _D]),
+        "or_tprod_def_entries": (None, [_D, _D, _I, _I, _I, _I,
+                                        ctypes.POINTER(ctypes.c_longlong), ctypes.c_longlong, _D]),
+        "or_tprod_fft": (None, [_D, _D, _I, _I, _I, _I, _D]),
+        "or_tran": (None, [_D, _I, _I, _I, _D]),
+        "or_teye": (None, [_I, _I, _D]),
+        "or_svd": (_I, [_D, _I, _I, _I, _D, _D, _D]),
+        "or_tsvd": (_I, [_D, _I, _I, _I, _D, _D, _D, _D]),
+        "or_slice_sigma": (_I, [_D, _I, _I, _I, _D]),
+        "or_tnn": (ctypes.c_double, [_D, _I, _I, _I]),
+        "or_tsn": (ctypes.c_double, [_D, _I, _I, _I]),
+        "or_prox_tnn": (_I, [_D, _I, _I, _I, ctypes.c_double, _D]),
+        "or_svt_real": (_I, [_D, _I, _I, ctypes.c_double, _D]),
+    }
+    for name, (res, args) in sig.items():
+        f = getattr(lib, name)
+        f.restype = res
+        f.argtypes = args
+    _lib = lib
+    return lib
+
+
+def _dp(a):
+    return a.ctypes.data_as(_D)
+
+
+def _real(a):
+    return np.ascontiguousarray(a, dtype=np.float64)
+
+
+def _cplx(a):
+    return np.ascontiguousarray(a, dtype=np.complex128)
+
+
+def set_threads(n: int) -> None:
+    _load().or_set_threads(int(n))
+
+
+def get_threads() -> int:
+    return int(_load().or_get_threads())
+
+
+def dft3(X, inverse=False):
+    """eq (2) along mode 3 (or F^*/n3 of eq (1) when inverse)."""
+    X = _cplx(X)
+    n1, n2, n3 = X.shape
+    Y = np.empty_like(X)
+    _load().or_dft3(_dp(X), n1, n2, n3, int(bool(inverse)), _dp(Y))
+    return Y
+
+
+def bcirc(A):
+    A = _real(A)
+    n1, n2, n3 = A.shape
+    M = np.empty((n1 * n3, n2 * n3))
+    _load().or_bcirc(_dp(A), n1, n2, n3, _dp(M))
+    return M
+
+
+def unfold(A):
+    A = _real(A)
+    n1, n2, n3 = A.shape
+    M = np.empty((n1 * n3, n2))
+    _load().or_unfold(_dp(A), n1, n2, n3, _dp(M))
+    return M
+
+
+def fold(M, n1, n2, n3):
+    M = _real(M)
+    assert M.shape == (n1 * n3, n2)
+    A = np.empty((n1, n2, n3))
+    _load().or_fold(_dp(M), n1, n2, n3, _dp(A))
+    return A
+
+
+def tprod(A, B):
+    """Definition 2.1 (eq (9)) evaluated block row by block row."""
+    A, B = _real(A), _real(B)
+    n1, n2, n3 = A.shape
+    assert B.shape[0] == n2 and B.shape[2] == n3
+    l = B.shape[1]
+    C = np.empty((n1, l, n3))
+    _load().or_tprod_def(_dp(A), _dp(B), n1, n2, l, n3, _dp(C))
+    return C
+
+
+def tprod_entries(A, B, flat_idx):
+    """eq (9) at flat indices (i*l + j)*n3 + t of C."""
+    A, B = _real(A), _real(B)
+    n1, n2, n3 = A.shape
+    l = B.shape[1]
+    idx = np.ascontiguousarray(flat_idx, dtype=np.int64)
+    out = np.empty(idx.shape[0])
+    _load().or_tprod_def_entries(_dp(A), _dp(B), n1, n2, l, n3,
+                                 idx.ctypes.data_as(ctypes.POINTER(ctypes.c_longlong)),
+                                 idx.shape[0], _dp(out))
+    return out
+
+
+def tprod_fft(A, B):
+    """Algorithm 1 in FP64 (plain DFT, no FFT)."""
+    A, B = _real(A), _real(B)
+    n1, n2, n3 = A.shape
+    l = B.shape[1]
+    C = np.empty((n1, l, n3))
+    _load().or_tprod_fft(_dp(A), _dp(B), n1, n2, l, n3, _dp(C))
+    return C
+
+
+def tran(A):
+    A = _real(A)
+    n1, n2, n3 = A.shape
+    At = np.empty((n2, n1, n3))
+    _load().or_tran(_dp(A), n1, n2, n3, _dp(At))
+    return At
+
+
+def teye(n, n3):
+    Ie = np.empty((n, n, n3))
+    _load().or_teye(n, n3, _dp(Ie))
+    return Ie
+
+
+def svd(M, full=False):
+    """One-sided Jacobi SVD of a complex (or real) matrix: (U, sigma, V, sweeps)."""
+    M = _cplx(M)
+    m, n = M.shape
+    p = min(m, n)
+    sig = np.empty(p)
+    U = np.empty((m, m if full else p), dtype=np.complex128)
+    V = np.empty((n, n if full else p), dtype=np.complex128)
+    rc = _load().or_svd(_dp(M), m, n, int(bool(full)), _dp(sig), _dp(U), _dp(V))
+    return U, sig, V, rc
+
+
+def tsvd(A):
+    """Algorithm 2: returns (U, S, V, max_imag, status)."""
+    A = _real(A)
+    n1, n2, n3 = A.shape
+    U = np.empty((n1, n1, n3))
+    S = np.empty((n1, n2, n3))
+    V = np.empty((n2, n2, n3))
+    mi = ctypes.c_double(0.0)
+    rc = _load().or_tsvd(_dp(A), n1, n2, n3, _dp(U), _dp(S), _dp(V), ctypes.byref(mi))
+    return U, S, V, mi.value, rc
+
+
+def slice_sigma(A):
+    A = _real(A)
+    n1, n2, n3 = A.shape
+    sig = np.empty((n3, min(n1, n2)))
+    _load().or_slice_sigma(_dp(A), n1, n2, n3, _dp(sig))
+    return sig
+
+
+def tnn(A):
+    A = _real(A)
+    n1, n2, n3 = A.shape
+    return float(_load().or_tnn(_dp(A), n1, n2, n3))
+
+
+def tsn(A):
+    A = _real(A)
+    n1, n2, n3 = A.shape
+    return float(_load().or_tsn(_dp(A), n1, n2, n3))
+
+
+def prox_tnn(Y, tau):
+    """Algorithm 3 (t-SVT) in FP64."""
+    Y = _real(Y)
+    n1, n2, n3 = Y.shape
+    X = np.empty_like(Y)
+    rc = _load().or_prox_tnn(_dp(Y), n1, n2, n3, float(tau), _dp(X))
+    if rc < 0:
+        raise ValueError("tau must be >= 0")
+    return X
+
+
+def svt_real(M, tau):
+    M = _real(M)
+    m, n = M.shape
+    out = np.empty_like(M)
+    _load().or_svt_real(_dp(M), m, n, float(tau), _dp(out))
+    return out

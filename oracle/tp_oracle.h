@@ -1,0 +1,84 @@
+/*
+ * tp_oracle.h -- FP64 CPU oracle for the t-product toolbox (Lu, 2018).
+ *
+ * TEST INFRASTRUCTURE ONLY.  Nothing on the product path may include, link or
+ * call this library: only the test suite, the smoke check and the CPU-baseline
+ * leg of the benchmark use it.  It shares no code with the GPU library.
+ *
+ * Conventions (all buffers are host memory owned by the caller):
+ *   - a real tensor A of size n1 x n2 x n3 is row-major with the tube index
+ *     last: A(i,j,t) = A[(i*n2 + j)*n3 + t], 0-based (the paper is 1-based);
+ *   - a complex tensor uses the same index order with C99 double complex
+ *     elements (interleaved re, im);
+ *   - a matrix is row-major: M(i,j) = M[i*ncols + j].
+ *
+ * Every routine computes in double precision.  Functions that return int
+ * return 0 on success, a positive sweep-cap code when a Jacobi iteration did
+ * not converge, or a negative value on a bad argument.
+ */
+#ifndef TP_ORACLE_H
+#define TP_ORACLE_H
+
+#include <complex.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef double _Complex or_cplx;
+
+/* threads used by the OpenMP loops (0 = library default) */
+void or_set_threads(int nthreads);
+int or_get_threads(void);
+
+/* Section 2.2, eq (2) and eq (1): DFT along every mode-3 tube, or its inverse
+ * F^* / n3 when inverse != 0.  X and Y may not alias. */
+void or_dft3(const or_cplx* X, int n1, int n2, int n3, int inverse, or_cplx* Y);
+
+/* Section 2.2, eq (6): bcirc(A), an (n1*n3) x (n2*n3) real matrix. */
+void or_bcirc(const double* A, int n1, int n2, int n3, double* M);
+/* Section 2.3: unfold(A) is (n1*n3) x n2; fold is its inverse. */
+void or_unfold(const double* A, int n1, int n2, int n3, double* M);
+void or_fold(const double* M, int n1, int n2, int n3, double* A);
+
+/* Definition 2.1, eq (9), evaluated block row by block row:
+ * C^(r) = sum_c A^((r-c) mod n3) B^(c). */
+void or_tprod_def(const double* A, const double* B, int n1, int n2, int l, int n3, double* C);
+/* the same definition at selected flat indices of C (idx[e] = (i*l + j)*n3 + t) */
+void or_tprod_def_entries(const double* A, const double* B, int n1, int n2, int l, int n3,
+                          const long long* idx, long long nidx, double* out);
+/* Algorithm 1: DFT, products of the ceil((n3+1)/2) leading Fourier slices,
+ * conjugate fill of the rest, inverse DFT (real part returned). */
+void or_tprod_fft(const double* A, const double* B, int n1, int n2, int l, int n3, double* C);
+
+/* Definition 2.2 (conjugate transpose of a real tensor) and Definition 2.3. */
+void or_tran(const double* A, int n1, int n2, int n3, double* At);
+void or_teye(int n, int n3, double* Ieye);
+
+/* SVD of an m x n complex matrix by one-sided Jacobi.  sigma[min(m,n)] is
+ * sorted in decreasing order.  full != 0: U is m x m and V is n x n (bases
+ * completed); full == 0: U is m x p and V is n x p, p = min(m,n).  U or V may
+ * be NULL.  Returns the number of sweeps (>= 0) or -1 if the sweep cap hit. */
+int or_svd(const or_cplx* M, int m, int n, int full, double* sigma, or_cplx* U, or_cplx* V);
+
+/* Theorem 2.2 / Algorithm 2.  U is n1 x n1 x n3, S is n1 x n2 x n3, V is
+ * n2 x n2 x n3.  maximag (may be NULL) receives the largest imaginary part
+ * left by the inverse DFTs (it should be rounding noise). */
+int or_tsvd(const double* A, int n1, int n2, int n3, double* U, double* S, double* V,
+            double* maximag);
+/* singular values of every Fourier slice: sig is n3 x min(n1,n2), row k for
+ * slice k (all n3 slices, no symmetry used). */
+int or_slice_sigma(const double* A, int n1, int n2, int n3, double* sig);
+/* Definition 2.9 with eq (14): sum_i S(i,i,1) = (1/n3) sum_k ||Abar^(k)||_* . */
+double or_tnn(const double* A, int n1, int n2, int n3);
+/* Definition 2.8 with eq (17): ||bcirc(A)|| = max_k sigma_1(Abar^(k)). */
+double or_tsn(const double* A, int n1, int n2, int n3);
+/* Theorem 2.3 / Algorithm 3: Prox of the TNN at tau. */
+int or_prox_tnn(const double* Y, int n1, int n2, int n3, double tau, double* X);
+/* matrix singular value thresholding U (S - tau)_+ V^* of a real m x n matrix */
+int or_svt_real(const double* M, int m, int n, double tau, double* out);
+
+#ifdef __cplusplus
+}
+#endif
+#endif
