@@ -1,0 +1,75 @@
+/*
+ * tp.h -- C ABI of the gfx950 (MI355X) t-product library libtp.so.
+ *
+ * The library computes the Fourier-domain slice pipeline of the t-product
+ * toolbox (C. Lu, "Tensor-Tensor Product Toolbox", 2018): a real DFT along
+ * every mode-3 tube, one dense operation on each of the ceil((n3+1)/2)
+ * leading Fourier slices, and the inverse DFT.
+ *
+ * Conventions shared by every entry point
+ *   Tensors   An n1 x n2 x n3 real tensor is FP32, row-major with the tube
+ *             index last: A(i,j,t) is A[(i*n2 + j)*n3 + t] (0-based; the paper
+ *             indexes from 1).  This is the layout of a contiguous
+ *             (n1, n2, n3) array.
+ *   Memory    Every tensor, output and workspace pointer is device memory of
+ *             the current HIP device, owned by the caller; inputs are not
+ *             modified.  Inputs and outputs must not overlap.
+ *   Workspace Scratch memory is passed in by the caller: its size comes from
+ *             the matching *_workspace_size query and must be at least that
+ *             large.  The library allocates no device memory and does not
+ *             synchronise; every call only enqueues kernels on `stream`
+ *             (a hipStream_t, NULL for the default stream).
+ *   Errors    Arguments are checked on the host before anything is enqueued;
+ *             a negative tp_status is returned and nothing runs.  TP_ERR_HIP
+ *             reports a failed kernel launch (hipGetLastError).  Outcomes that
+ *             are only known on the device go to an optional per-slice int
+ *             array `info` (device memory, floor(n3/2)+1 entries).
+ *   Sizes     1 <= n3 <= 1024; n1, n2, l >= 1; element counts < 2^31 per slice.
+ */
+#ifndef TP_H
+#define TP_H
+
+#include <stddef.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum tp_status {
+    TP_OK = 0,
+    TP_ERR_ARG = -1,         /* null pointer, negative or NaN scalar, bad enum */
+    TP_ERR_SHAPE = -2,       /* non-positive or unsupported size */
+    TP_ERR_WORKSPACE = -3,   /* workspace missing or smaller than the query */
+    TP_ERR_HIP = -4,         /* a kernel launch failed */
+    TP_ERR_UNSUPPORTED = -5  /* valid request the library does not handle */
+} tp_status;
+
+/* Arithmetic of the slice products (tp_tprod).  All accumulate in FP32.
+ *   TP_PREC_FP32    FP32 matrix-core products.
+ *   TP_PREC_BF16X3  each FP32 operand split into bf16 hi + lo (both rounded to
+ *                   nearest even); hi*hi + hi*lo + lo*hi on bf16 matrix cores.
+ *   TP_PREC_BF16    hi*hi only (operands rounded to bf16). */
+typedef enum tp_prec { TP_PREC_FP32 = 0, TP_PREC_BF16X3 = 1, TP_PREC_BF16 = 2 } tp_prec;
+
+/* Human-readable name of a tp_status value. */
+const char* tp_status_string(int status);
+
+/* Library ABI version (major*100 + minor). */
+int tp_version(void);
+
+/*
+ * t-product C = A * B (Definition 2.1, eq (9)), computed by Algorithm 1:
+ * DFT of every tube of A and B, Cbar^(k) = Abar^(k) Bbar^(k) for the
+ * floor(n3/2)+1 leading slices (eq (10)), inverse DFT (the remaining slices
+ * are the conjugates, implicit in the real inverse transform).
+ *   A  n1 x n2 x n3 (input)       B  n2 x l x n3 (input)
+ *   C  n1 x l x n3 (output)       prec  a tp_prec value
+ */
+size_t tp_tprod_workspace_size(int n1, int n2, int l, int n3, int prec);
+int tp_tprod(const float* A, const float* B, float* C, int n1, int n2, int l, int n3, int prec,
+             void* workspace, size_t workspace_bytes, void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* TP_H */

@@ -1,0 +1,73 @@
+"""MI355X (gfx950) t-product library: Python binding of libtp.so.
+
+The functions here have the names of the C entry points in include/tp.h and
+only marshal arguments: tensors are torch CUDA (HIP) float32 tensors, the
+outputs and the workspace are allocated with torch on the tensors' device,
+and the kernels are enqueued on torch's current stream.  Every step of the
+computation runs in the library's HIP kernels.
+"""
+import torch
+
+from . import _lib
+from ._lib import TPError
+
+TP_PREC_FP32 = 0
+TP_PREC_BF16X3 = 1
+TP_PREC_BF16 = 2
+_PREC = {"fp32": TP_PREC_FP32, "bf16x3": TP_PREC_BF16X3, "bf16": TP_PREC_BF16}
+
+__all__ = ["tp_tprod", "tp_tprod_workspace_size", "TPError", "TP_PREC_FP32", "TP_PREC_BF16X3",
+           "TP_PREC_BF16", "library_path"]
+
+
+def library_path():
+    return _lib.LIB_PATH
+
+
+def _prec(p):
+    return _PREC[p] if isinstance(p, str) else int(p)
+
+
+def _dev_tensor(x, name, ndim=3):
+    if not isinstance(x, torch.Tensor) or not x.is_cuda:
+        raise TypeError(f"{name} must be a torch tensor on a GPU device")
+    if x.dtype != torch.float32:
+        raise TypeError(f"{name} must be float32")
+    if x.dim() != ndim:
+        raise ValueError(f"{name} must have {ndim} dimensions")
+    return x.contiguous()
+
+
+def _stream(dev):
+    return ctypes_void(torch.cuda.current_stream(dev).cuda_stream)
+
+
+def ctypes_void(v):
+    import ctypes
+    return ctypes.c_void_p(int(v))
+
+
+def _workspace(nbytes, dev):
+    return torch.empty(max(int(nbytes), 1), dtype=torch.uint8, device=dev)
+
+
+def tp_tprod_workspace_size(n1, n2, l, n3, prec="fp32"):
+    return int(_lib.load().tp_tprod_workspace_size(n1, n2, l, n3, _prec(prec)))
+
+
+def tp_tprod(A, B, prec="fp32", out=None, workspace=None):
+    """C = A * B (Definition 2.1) through Algorithm 1 on the GPU."""
+    lib = _lib.load()
+    A = _dev_tensor(A, "A")
+    B = _dev_tensor(B, "B")
+    n1, n2, n3 = A.shape
+    if B.shape[0] != n2 or B.shape[2] != n3:
+        raise ValueError(f"shape mismatch: A {tuple(A.shape)}, B {tuple(B.shape)}")
+    l = B.shape[1]
+    C = out if out is not None else torch.empty((n1, l, n3), dtype=torch.float32, device=A.device)
+    ws_bytes = lib.tp_tprod_workspace_size(n1, n2, l, n3, _prec(prec))
+    ws = workspace if workspace is not None else _workspace(ws_bytes, A.device)
+    st = lib.tp_tprod(A.data_ptr(), B.data_ptr(), C.data_ptr(), n1, n2, l, n3, _prec(prec),
+                      ws.data_ptr(), ws.numel(), _stream(A.device))
+    _lib.check("tp_tprod", st)
+    return C

@@ -1,0 +1,56 @@
+"""ctypes binding of libtp.so (argument marshalling only).
+
+Every computation runs in the HIP kernels of libtp.so.  torch supplies device
+memory (outputs and the workspace) and the current stream; nothing here
+computes on the host, and there is no fallback: if libtp.so is missing or the
+device is not a GPU, calls raise.
+"""
+import ctypes
+import os
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libtp.so")
+
+_VP = ctypes.c_void_p
+_I = ctypes.c_int
+_SZ = ctypes.c_size_t
+_F = ctypes.c_float
+
+# name -> (restype, argtypes); must match include/tp.h
+SIGNATURES = {
+    "tp_status_string": (ctypes.c_char_p, [_I]),
+    "tp_version": (_I, []),
+    "tp_tprod_workspace_size": (_SZ, [_I, _I, _I, _I, _I]),
+    "tp_tprod": (_I, [_VP, _VP, _VP, _I, _I, _I, _I, _I, _VP, _SZ, _VP]),
+}
+
+_lib = None
+
+
+class TPError(RuntimeError):
+    def __init__(self, fn, status):
+        self.status = status
+        msg = load().tp_status_string(status).decode()
+        super().__init__(f"{fn} failed with status {status} ({msg})")
+
+
+def load():
+    """Load libtp.so (raises when it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"libtp.so not found at {LIB_PATH}: build it with "
+                           "`python -m paper_1806_07247_amd.build` (hipcc, gfx950)")
+    lib = ctypes.CDLL(LIB_PATH)
+    for name, (res, args) in SIGNATURES.items():
+        f = getattr(lib, name)
+        f.restype = res
+        f.argtypes = args
+    _lib = lib
+    return lib
+
+
+def check(fn, status):
+    if status != 0:
+        raise TPError(fn, status)

@@ -1,0 +1,333 @@
+// Real DFT along the mode-3 tubes (Section 2.2, eq (2); fft(A,[],3) of
+// Algorithms 1-3, step 1) and its inverse (step 3), for gfx950.
+//
+// Layout: the tensor is tube-major (n1, n2, n3), so a block of consecutive
+// tubes is one contiguous span of memory.  A workgroup of one wavefront takes
+// 64 tubes, reads their span fully coalesced into LDS, and each lane then
+// transforms one tube in registers.  The Fourier side is slice-major planar
+// complex: bin k of tube q is re[k*ntubes + q], im[k*ntubes + q], so the
+// per-bin stores of a wavefront are 64 consecutive floats; the transpose from
+// tube-major to slice-major costs no extra pass.
+//
+// Only the floor(n3/2)+1 leading bins are produced (Lemma 2.1 / eq (8)): the
+// others are the conjugates of these.  The inverse reads the same half
+// spectrum and forms the conjugate fill of step 2 implicitly.
+//
+// Power-of-two n3 (4..128): a complex FFT of length n3/2 on the packed
+// sequence z_t = x_2t + i x_2t+1 (radix-2, fully unrolled in registers), then
+// the even/odd split.  Other n3: a direct DFT per lane.  Twiddles are
+// computed per workgroup in double precision (sincospi) and rounded once.
+#include "tp_internal.h"
+
+namespace tp {
+namespace {
+
+constexpr int kTubes = 64;  // tubes per workgroup (one wavefront)
+
+__device__ void fill_twiddles(float2* tw, int n)
+{
+    for (int j = threadIdx.x; j < n; j += blockDim.x) {
+        double s, c;
+        sincospi(-2.0 * (double)j / (double)n, &s, &c);  // W_n^j = exp(-2 pi i j / n)
+        tw[j] = make_float2((float)c, (float)s);
+    }
+}
+
+template <int M>
+__device__ constexpr int bitrev(int t)
+{
+    int r = 0;
+    for (int b = 1; b < M; b <<= 1) {
+        r = (r << 1) | (t & 1);
+        t >>= 1;
+    }
+    return r;
+}
+
+// In-place radix-2 DIT FFT of length M = N/2 on bit-reversed input.  The
+// twiddle W_len^j is W_N^(j*N/len) from the length-N table; INV conjugates it.
+template <int N, bool INV>
+__device__ __forceinline__ void cfft_half(float (&zr)[N / 2], float (&zi)[N / 2], const float2* tw)
+{
+    constexpr int M = N / 2;
+#pragma unroll
+    for (int len = 2; len <= M; len <<= 1) {
+#pragma unroll
+        for (int b = 0; b < M; b += len) {
+#pragma unroll
+            for (int j = 0; j < len / 2; ++j) {
+                const int i0 = b + j, i1 = i0 + len / 2;
+                float tr, ti;
+                if (j == 0) {
+                    tr = zr[i1];
+                    ti = zi[i1];
+                } else {
+                    float2 w = tw[j * (N / len)];
+                    if (INV) w.y = -w.y;
+                    tr = zr[i1] * w.x - zi[i1] * w.y;
+                    ti = zr[i1] * w.y + zi[i1] * w.x;
+                }
+                zr[i1] = zr[i0] - tr;
+                zi[i1] = zi[i0] - ti;
+                zr[i0] += tr;
+                zi[i0] += ti;
+            }
+        }
+    }
+}
+
+// coalesced copy of nt*n floats from global into the padded LDS tile (row per tube)
+__device__ __forceinline__ void load_tile(const float* __restrict__ src, float* buf, int nt, int n, int ld)
+{
+    const int total = nt * n;
+    if ((n & 3) == 0 && (reinterpret_cast<uintptr_t>(src) & 15) == 0) {
+        for (int e = threadIdx.x * 4; e < total; e += blockDim.x * 4) {
+            const float4 v = *reinterpret_cast<const float4*>(src + e);
+            float* d = buf + (e / n) * ld + (e % n);
+            d[0] = v.x;
+            d[1] = v.y;
+            d[2] = v.z;
+            d[3] = v.w;
+        }
+    } else {
+        for (int e = threadIdx.x; e < total; e += blockDim.x) buf[(e / n) * ld + (e % n)] = src[e];
+    }
+}
+
+__device__ __forceinline__ void store_tile(float* __restrict__ dst, const float* buf, int nt, int n, int ld)
+{
+    const int total = nt * n;
+    if ((n & 3) == 0 && (reinterpret_cast<uintptr_t>(dst) & 15) == 0) {
+        for (int e = threadIdx.x * 4; e < total; e += blockDim.x * 4) {
+            const float* s = buf + (e / n) * ld + (e % n);
+            *reinterpret_cast<float4*>(dst + e) = make_float4(s[0], s[1], s[2], s[3]);
+        }
+    } else {
+        for (int e = threadIdx.x; e < total; e += blockDim.x) dst[e] = buf[(e / n) * ld + (e % n)];
+    }
+}
+
+template <int N>
+__global__ __launch_bounds__(kTubes) void k_rfft_pow2(const float* __restrict__ x, float* __restrict__ re,
+                                                       float* __restrict__ im, long long ntubes)
+{
+    constexpr int M = N / 2, LD = N + 1;
+    __shared__ float2 tw[N];
+    __shared__ float buf[kTubes * LD];
+    fill_twiddles(tw, N);
+    const int tid = threadIdx.x;
+    for (long long base = (long long)blockIdx.x * kTubes; base < ntubes; base += (long long)gridDim.x * kTubes) {
+        const int nt = (int)min<long long>(kTubes, ntubes - base);
+        __syncthreads();
+        load_tile(x + base * N, buf, nt, N, LD);
+        __syncthreads();
+        if (tid < nt) {
+            float zr[M], zi[M];
+            const float* xt = buf + tid * LD;
+#pragma unroll
+            for (int t = 0; t < M; ++t) {
+                zr[bitrev<M>(t)] = xt[2 * t];
+                zi[bitrev<M>(t)] = xt[2 * t + 1];
+            }
+            cfft_half<N, false>(zr, zi, tw);
+            const long long q = base + tid;
+            // X_k = E_k + W_N^k O_k with E = (Z_k + conj Z_{M-k})/2, O = -i (Z_k - conj Z_{M-k})/2
+            re[q] = zr[0] + zi[0];
+            im[q] = 0.0f;
+            re[(long long)M * ntubes + q] = zr[0] - zi[0];
+            im[(long long)M * ntubes + q] = 0.0f;
+#pragma unroll
+            for (int k = 1; k < M; ++k) {
+                const float ar = zr[k], ai = zi[k], br = zr[M - k], bi = -zi[M - k];
+                const float er = 0.5f * (ar + br), ei = 0.5f * (ai + bi);
+                const float dr = 0.5f * (ar - br), di = 0.5f * (ai - bi);
+                const float orr = di, oi = -dr;
+                const float2 w = tw[k];
+                re[(long long)k * ntubes + q] = er + (w.x * orr - w.y * oi);
+                im[(long long)k * ntubes + q] = ei + (w.x * oi + w.y * orr);
+            }
+        }
+    }
+}
+
+template <int N>
+__global__ __launch_bounds__(kTubes) void k_irfft_pow2(const float* __restrict__ re, const float* __restrict__ im,
+                                                        float* __restrict__ x, long long ntubes)
+{
+    constexpr int M = N / 2, LD = N + 1;
+    __shared__ float2 tw[N];
+    __shared__ float buf[kTubes * LD];
+    fill_twiddles(tw, N);
+    const int tid = threadIdx.x;
+    const float scale = 1.0f / (float)N;
+    for (long long base = (long long)blockIdx.x * kTubes; base < ntubes; base += (long long)gridDim.x * kTubes) {
+        const int nt = (int)min<long long>(kTubes, ntubes - base);
+        __syncthreads();
+        if (tid < nt) {
+            const long long q = base + tid;
+            float xr[M + 1], xi[M + 1];
+#pragma unroll
+            for (int k = 0; k <= M; ++k) {
+                xr[k] = re[(long long)k * ntubes + q];
+                xi[k] = (k == 0 || k == M) ? 0.0f : im[(long long)k * ntubes + q];
+            }
+            // 2 Z_k = (X_k + conj X_{M-k}) + i W_N^{-k} (X_k - conj X_{M-k})
+            float zr[M], zi[M];
+#pragma unroll
+            for (int k = 0; k < M; ++k) {
+                const float ar = xr[k], ai = xi[k], br = xr[M - k], bi = -xi[M - k];
+                const float sr = ar + br, si = ai + bi, dr = ar - br, di = ai - bi;
+                const float2 w = tw[k];  // conj applied below
+                const float tr = w.x * dr + w.y * di;
+                const float ti = w.x * di - w.y * dr;
+                zr[bitrev<M>(k)] = sr - ti;
+                zi[bitrev<M>(k)] = si + tr;
+            }
+            cfft_half<N, true>(zr, zi, tw);
+            float* xt = buf + tid * LD;
+#pragma unroll
+            for (int t = 0; t < M; ++t) {
+                xt[2 * t] = zr[t] * scale;
+                xt[2 * t + 1] = zi[t] * scale;
+            }
+        }
+        __syncthreads();
+        store_tile(x + base * N, buf, nt, N, LD);
+    }
+}
+
+// direct DFT of any length n: X_k = sum_t x_t W_n^(k t), k < n/2+1
+__global__ void k_rdft_any(const float* __restrict__ x, float* __restrict__ re, float* __restrict__ im,
+                           long long ntubes, int n)
+{
+    extern __shared__ float smem[];
+    float2* tw = reinterpret_cast<float2*>(smem);
+    float* buf = smem + 2 * n;
+    const int ld = n + 1, h = n / 2 + 1, tpb = blockDim.x, tid = threadIdx.x;
+    fill_twiddles(tw, n);
+    for (long long base = (long long)blockIdx.x * tpb; base < ntubes; base += (long long)gridDim.x * tpb) {
+        const int nt = (int)min<long long>(tpb, ntubes - base);
+        __syncthreads();
+        load_tile(x + base * n, buf, nt, n, ld);
+        __syncthreads();
+        if (tid < nt) {
+            const long long q = base + tid;
+            const float* xt = buf + tid * ld;
+            for (int k = 0; k < h; ++k) {
+                float sr = 0.0f, si = 0.0f;
+                int e = 0;
+                for (int t = 0; t < n; ++t) {
+                    const float v = xt[t];
+                    const float2 w = tw[e];
+                    sr += v * w.x;
+                    si += v * w.y;
+                    e += k;
+                    if (e >= n) e -= n;
+                }
+                re[(long long)k * ntubes + q] = sr;
+                im[(long long)k * ntubes + q] = (k == 0 || 2 * k == n) ? 0.0f : si;
+            }
+        }
+    }
+}
+
+// x_t = (1/n) [X_0 + (-1)^t X_{n/2} + 2 sum_{0<k<n/2} Re(X_k W_n^(-k t))]
+__global__ void k_irdft_any(const float* __restrict__ re, const float* __restrict__ im, float* __restrict__ x,
+                            long long ntubes, int n)
+{
+    extern __shared__ float smem[];
+    float2* tw = reinterpret_cast<float2*>(smem);
+    float* buf = smem + 2 * n;
+    const int ld = n + 1, kmax = (n - 1) / 2, tpb = blockDim.x, tid = threadIdx.x;
+    const float scale = 1.0f / (float)n;
+    fill_twiddles(tw, n);
+    for (long long base = (long long)blockIdx.x * tpb; base < ntubes; base += (long long)gridDim.x * tpb) {
+        const int nt = (int)min<long long>(tpb, ntubes - base);
+        __syncthreads();
+        if (tid < nt) {
+            const long long q = base + tid;
+            float* xt = buf + tid * ld;
+            const float x0 = re[q];
+            const float xn = (n % 2 == 0) ? re[(long long)(n / 2) * ntubes + q] : 0.0f;
+            for (int t = 0; t < n; ++t) xt[t] = x0 + ((t & 1) ? -xn : xn);
+            for (int k = 1; k <= kmax; ++k) {
+                const float a = 2.0f * re[(long long)k * ntubes + q];
+                const float b = 2.0f * im[(long long)k * ntubes + q];
+                int e = 0;
+                for (int t = 0; t < n; ++t) {
+                    const float2 w = tw[e];
+                    xt[t] += a * w.x + b * w.y;
+                    e += k;
+                    if (e >= n) e -= n;
+                }
+            }
+            for (int t = 0; t < n; ++t) xt[t] *= scale;
+        }
+        __syncthreads();
+        store_tile(x + base * n, buf, nt, n, ld);
+    }
+}
+
+inline int grid_for(long long ntubes, int tpb)
+{
+    long long g = (ntubes + tpb - 1) / tpb;
+    const long long cap = 256LL * 16;  // enough waves to fill 256 CUs; the rest loops
+    return (int)(g < cap ? (g > 0 ? g : 1) : cap);
+}
+
+int any_tubes_per_block(int n)
+{
+    int tpb = 64;
+    while (tpb > 8 && (size_t)(4 * tpb * (n + 1) + 8 * n) > 64 * 1024) tpb /= 2;
+    return tpb;
+}
+
+}  // namespace
+
+hipError_t launch_rfft(const float* x, float* re, float* im, long long ntubes, int n3, hipStream_t s)
+{
+    if (ntubes <= 0) return hipSuccess;
+    const int g = grid_for(ntubes, kTubes);
+    switch (n3) {
+#define TP_RFFT_CASE(N) \
+    case N: k_rfft_pow2<N><<<g, kTubes, 0, s>>>(x, re, im, ntubes); return hipGetLastError();
+        TP_RFFT_CASE(4)
+        TP_RFFT_CASE(8)
+        TP_RFFT_CASE(16)
+        TP_RFFT_CASE(32)
+        TP_RFFT_CASE(64)
+        TP_RFFT_CASE(128)
+#undef TP_RFFT_CASE
+        default: break;
+    }
+    const int tpb = any_tubes_per_block(n3);
+    const size_t lds = (size_t)(4 * tpb * (n3 + 1) + 8 * n3);
+    k_rdft_any<<<grid_for(ntubes, tpb), tpb, lds, s>>>(x, re, im, ntubes, n3);
+    return hipGetLastError();
+}
+
+hipError_t launch_irfft(const float* re, const float* im, float* x, long long ntubes, int n3, hipStream_t s)
+{
+    if (ntubes <= 0) return hipSuccess;
+    const int g = grid_for(ntubes, kTubes);
+    switch (n3) {
+#define TP_IRFFT_CASE(N) \
+    case N: k_irfft_pow2<N><<<g, kTubes, 0, s>>>(re, im, x, ntubes); return hipGetLastError();
+        TP_IRFFT_CASE(4)
+        TP_IRFFT_CASE(8)
+        TP_IRFFT_CASE(16)
+        TP_IRFFT_CASE(32)
+        TP_IRFFT_CASE(64)
+        TP_IRFFT_CASE(128)
+#undef TP_IRFFT_CASE
+        default: break;
+    }
+    const int tpb = any_tubes_per_block(n3);
+    const size_t lds = (size_t)(4 * tpb * (n3 + 1) + 8 * n3);
+    k_irdft_any<<<grid_for(ntubes, tpb), tpb, lds, s>>>(re, im, x, ntubes, n3);
+    return hipGetLastError();
+}
+
+size_t max_fft_length() { return 1024; }
+
+}  // namespace tp

@@ -1,0 +1,99 @@
+// Internal declarations of the gfx950 t-product library (not installed).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stddef.h>
+#include <stdint.h>
+
+#include "tp.h"
+
+namespace tp {
+
+constexpr size_t kAlign = 256;
+
+inline size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
+
+// number of Fourier slices that get a dense operation: ceil((n3+1)/2) = floor(n3/2)+1
+inline int half_slices(int n3) { return n3 / 2 + 1; }
+
+// Linear carve-out of the caller's workspace.
+struct Arena {
+    char* base;
+    size_t cap;
+    size_t used = 0;
+    bool ok = true;
+    Arena(void* p, size_t n) : base(static_cast<char*>(p)), cap(n) {}
+    template <class T>
+    T* take(size_t count) {
+        size_t bytes = align_up(count * sizeof(T));
+        if (used + bytes > cap || (base == nullptr && bytes)) {
+            ok = false;
+            used += bytes;
+            return nullptr;
+        }
+        T* p = reinterpret_cast<T*>(base + used);
+        used += bytes;
+        return p;
+    }
+};
+
+// Planar complex slice stack: re and im planes, each nslices x rows x cols.
+struct Planes {
+    float* re;
+    float* im;
+};
+
+// ---------------------------------------------------------------- FFT ----
+// Forward real DFT of every tube of the tube-major tensor x (ntubes x n3) into
+// the first floor(n3/2)+1 slices of planar (re, im), slice-major: element k of
+// tube q lands at re[k*ntubes + q].
+hipError_t launch_rfft(const float* x, float* re, float* im, long long ntubes, int n3, hipStream_t s);
+// Inverse of the above: x = (1/n3) sum over the full conjugate-symmetric
+// spectrum; the imaginary parts of slice 0 (and n3/2 for even n3) are ignored.
+hipError_t launch_irfft(const float* re, const float* im, float* x, long long ntubes, int n3, hipStream_t s);
+
+// ---------------------------------------------------------- slice GEMM ----
+enum Op { OP_N = 0, OP_C = 1 };  // op(X) = X or X^* (conjugate transpose)
+
+struct CgemmArgs {
+    const float* ar;
+    const float* ai;
+    long long lda, sa;  // row stride, slice stride (elements)
+    const float* br;
+    const float* bi;
+    long long ldb, sb;
+    float* cr;
+    float* ci;
+    long long ldc, sc;
+    int m, n, k;         // op(A) is m x k, op(B) is k x n
+    int nslices;
+    int real_first;      // slice 0 is real (imaginary planes are zero)
+    int real_last;       // slice nslices-1 is real
+    const int* kdyn;     // optional per-slice inner dimension (<= k), device
+};
+
+hipError_t launch_cgemm(const CgemmArgs& a, int opa, int opb, int prec, hipStream_t s);
+
+// -------------------------------------------------------------- Jacobi ----
+struct JacobiArgs {
+    const float* yr;  // input slices (planar, row-major m x n per slice)
+    const float* yi;
+    float* wr;        // output: rotated columns, row-major rows x p per slice
+    float* wi;
+    float* sigma;     // p per slice (unsorted norms of the rotated columns)
+    int* info;        // per slice sweeps-cap flag (may be null)
+    int m, n;         // slice shape
+    int nslices;
+    int max_sweeps;
+    int transpose;    // work on Y^* (used when m < n)
+};
+hipError_t launch_jacobi(const JacobiArgs& a, void* scratch, size_t scratch_bytes, hipStream_t s);
+size_t jacobi_scratch_bytes(int m, int n, int nslices);
+
+}  // namespace tp
+
+#define TP_TRY(expr)                                  \
+    do {                                              \
+        hipError_t _e = (expr);                       \
+        if (_e != hipSuccess) return TP_ERR_HIP;      \
+    } while (0)
