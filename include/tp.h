@@ -69,6 +69,34 @@ size_t tp_tprod_workspace_size(int n1, int n2, int l, int n3, int prec);
 int tp_tprod(const float* A, const float* B, float* C, int n1, int n2, int l, int n3, int prec,
              void* workspace, size_t workspace_bytes, void* stream);
 
+/*
+ * Proximal operator of the tensor nuclear norm, X = Prox_tau(Y) (eq (19)),
+ * computed by Algorithm 3 (t-SVT, Theorem 2.3): DFT of the tubes of Y; for
+ * each of the floor(n3/2)+1 leading Fourier slices a full SVD by one-sided
+ * Jacobi and W^(k) = U (S - tau)_+ V^* (formed as U_J D U_J^* Y^(k) with
+ * D = diag((1 - tau/sigma_j)_+), which needs no V); inverse DFT.
+ *   Y, X   n1 x n2 x n3 (input, output)
+ *   tau    >= 0 (tau = 0 returns Y up to rounding); NaN or < 0: TP_ERR_ARG
+ *   info   optional device int[floor(n3/2)+1]: 0 = Jacobi converged,
+ *          1 = sweep cap reached (the result is still written)
+ *   rank   optional device int[floor(n3/2)+1]: #{sigma_j > tau} per slice
+ */
+size_t tp_prox_tnn_workspace_size(int n1, int n2, int n3);
+int tp_prox_tnn(const float* Y, float* X, int n1, int n2, int n3, float tau, int* info, int* rank,
+                void* workspace, size_t workspace_bytes, void* stream);
+
+/*
+ * Tensor nuclear norm (Definition 2.9 with eq (14)):
+ *   ||A||_* = sum_i S(i,i,1) = (1/n3) sum_k sum_i sigma_i(Abar^(k)),
+ * summed over all n3 slices through the conjugate symmetry of eq (8) (the
+ * DC and, for even n3, middle slices once, the others twice), in FP64.
+ *   out    device double (output)
+ *   info   as for tp_prox_tnn
+ */
+size_t tp_tnn_workspace_size(int n1, int n2, int n3);
+int tp_tnn(const float* A, int n1, int n2, int n3, double* out, int* info, void* workspace,
+           size_t workspace_bytes, void* stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -16,8 +16,9 @@ TP_PREC_BF16X3 = 1
 TP_PREC_BF16 = 2
 _PREC = {"fp32": TP_PREC_FP32, "bf16x3": TP_PREC_BF16X3, "bf16": TP_PREC_BF16}
 
-__all__ = ["tp_tprod", "tp_tprod_workspace_size", "TPError", "TP_PREC_FP32", "TP_PREC_BF16X3",
-           "TP_PREC_BF16", "library_path"]
+__all__ = ["tp_tprod", "tp_tprod_workspace_size", "tp_prox_tnn", "tp_prox_tnn_workspace_size",
+           "tp_tnn", "tp_tnn_workspace_size", "half_slices", "TPError", "TP_PREC_FP32",
+           "TP_PREC_BF16X3", "TP_PREC_BF16", "library_path"]
 
 
 def library_path():
@@ -71,3 +72,50 @@ def tp_tprod(A, B, prec="fp32", out=None, workspace=None):
                       ws.data_ptr(), ws.numel(), _stream(A.device))
     _lib.check("tp_tprod", st)
     return C
+
+
+def half_slices(n3):
+    """ceil((n3+1)/2) = floor(n3/2)+1: Fourier slices that get a dense operation."""
+    return n3 // 2 + 1
+
+
+def _ptr(t):
+    return None if t is None else t.data_ptr()
+
+
+def tp_prox_tnn_workspace_size(n1, n2, n3):
+    return int(_lib.load().tp_prox_tnn_workspace_size(n1, n2, n3))
+
+
+def tp_prox_tnn(Y, tau, out=None, info=None, rank=None, workspace=None):
+    """X = Prox_tau(Y) (eq (19)) by Algorithm 3 on the GPU.
+
+    info / rank: optional int32 device tensors of half_slices(n3) entries."""
+    lib = _lib.load()
+    Y = _dev_tensor(Y, "Y")
+    n1, n2, n3 = Y.shape
+    X = out if out is not None else torch.empty_like(Y)
+    ws_bytes = lib.tp_prox_tnn_workspace_size(n1, n2, n3)
+    ws = workspace if workspace is not None else _workspace(ws_bytes, Y.device)
+    st = lib.tp_prox_tnn(Y.data_ptr(), X.data_ptr(), n1, n2, n3, float(tau), _ptr(info), _ptr(rank),
+                         ws.data_ptr(), ws.numel(), _stream(Y.device))
+    _lib.check("tp_prox_tnn", st)
+    return X
+
+
+def tp_tnn_workspace_size(n1, n2, n3):
+    return int(_lib.load().tp_tnn_workspace_size(n1, n2, n3))
+
+
+def tp_tnn(A, out=None, info=None, workspace=None):
+    """Tensor nuclear norm (Definition 2.9); returns a 0-d float64 device tensor."""
+    lib = _lib.load()
+    A = _dev_tensor(A, "A")
+    n1, n2, n3 = A.shape
+    res = out if out is not None else torch.empty((), dtype=torch.float64, device=A.device)
+    ws_bytes = lib.tp_tnn_workspace_size(n1, n2, n3)
+    ws = workspace if workspace is not None else _workspace(ws_bytes, A.device)
+    st = lib.tp_tnn(A.data_ptr(), n1, n2, n3, res.data_ptr(), _ptr(info), ws.data_ptr(), ws.numel(),
+                    _stream(A.device))
+    _lib.check("tp_tnn", st)
+    return res

@@ -22,6 +22,10 @@ SIGNATURES = {
     "tp_version": (_I, []),
     "tp_tprod_workspace_size": (_SZ, [_I, _I, _I, _I, _I]),
     "tp_tprod": (_I, [_VP, _VP, _VP, _I, _I, _I, _I, _I, _VP, _SZ, _VP]),
+    "tp_prox_tnn_workspace_size": (_SZ, [_I, _I, _I]),
+    "tp_prox_tnn": (_I, [_VP, _VP, _I, _I, _I, _F, _VP, _VP, _VP, _SZ, _VP]),
+    "tp_tnn_workspace_size": (_SZ, [_I, _I, _I]),
+    "tp_tnn": (_I, [_VP, _I, _I, _I, _VP, _VP, _VP, _SZ, _VP]),
 }
 
 _lib = None

@@ -80,15 +80,24 @@ struct JacobiArgs {
     const float* yi;
     float* wr;        // output: rotated columns, row-major rows x p per slice
     float* wi;
-    float* sigma;     // p per slice (unsorted norms of the rotated columns)
+    double* sigma;    // p per slice (unsorted norms of the rotated columns)
     int* info;        // per slice sweeps-cap flag (may be null)
     int m, n;         // slice shape
     int nslices;
     int max_sweeps;
     int transpose;    // work on Y^* (used when m < n)
+    double tol;       // rotate a pair when |x^* y| > tol ||x|| ||y||
 };
 hipError_t launch_jacobi(const JacobiArgs& a, void* scratch, size_t scratch_bytes, hipStream_t s);
 size_t jacobi_scratch_bytes(int m, int n, int nslices);
+// Jacobi convergence threshold for an R-row work matrix of FP32 data
+inline double jacobi_tol(int rows) { return __builtin_sqrt((double)(rows > 4 ? rows : 4)) * 0x1p-23; }
+
+// columns w_j of each slice scaled by sqrt((1 - tau/sigma_j)_+) / sigma_j; keep = #{sigma_j > tau}
+hipError_t launch_shrink(float* wr, float* wi, const double* sigma, int* keep, int R, int P, int nslices, double tau,
+                         hipStream_t s);
+// (1/n3) sum over all n3 slices of the singular values, from the half spectrum
+hipError_t launch_tnn_reduce(const double* sigma, int nslices, int P, int n3, double* out, hipStream_t s);
 
 }  // namespace tp
 
