@@ -77,8 +77,9 @@ int tp_tprod(const float* A, const float* B, float* C, int n1, int n2, int l, in
  * D = diag((1 - tau/sigma_j)_+), which needs no V); inverse DFT.
  *   Y, X   n1 x n2 x n3 (input, output)
  *   tau    >= 0 (tau = 0 returns Y up to rounding); NaN or < 0: TP_ERR_ARG
- *   info   optional device int[floor(n3/2)+1]: 0 = Jacobi converged,
- *          1 = sweep cap reached (the result is still written)
+ *   info   optional device int[floor(n3/2)+1]: the number of Jacobi sweeps
+ *          used by each slice (> 0), negated when the sweep cap (30) was
+ *          reached without convergence (the result is still written)
  *   rank   optional device int[floor(n3/2)+1]: #{sigma_j > tau} per slice
  */
 size_t tp_prox_tnn_workspace_size(int n1, int n2, int n3);
@@ -96,6 +97,19 @@ int tp_prox_tnn(const float* Y, float* X, int n1, int n2, int n3, float tau, int
 size_t tp_tnn_workspace_size(int n1, int n2, int n3);
 int tp_tnn(const float* A, int n1, int n2, int n3, double* out, int* info, void* workspace,
            size_t workspace_bytes, void* stream);
+
+/*
+ * Stage timing (a profiling aid; not for use under stream capture).  While
+ * enabled, every entry point records a HIP event on its stream before and
+ * after each kernel it enqueues.  tp_trace_collect waits for those events and
+ * writes, in launch order, the kernel id and its elapsed time in ms for up to
+ * `capacity` launches; it returns the number of launches recorded since the
+ * last collect (or a negative tp_status) and forgets them.
+ * Kernel ids: 0 rfft, 1 irfft, 2 cgemm, 3 jacobi, 4 shrink, 5 tnn_reduce.
+ */
+int tp_trace_enable(int enable);
+int tp_trace_collect(int* kernel_ids, float* ms, int capacity);
+const char* tp_kernel_name(int id);
 
 #ifdef __cplusplus
 }

@@ -26,6 +26,9 @@ SIGNATURES = {
     "tp_prox_tnn": (_I, [_VP, _VP, _I, _I, _I, _F, _VP, _VP, _VP, _SZ, _VP]),
     "tp_tnn_workspace_size": (_SZ, [_I, _I, _I]),
     "tp_tnn": (_I, [_VP, _I, _I, _I, _VP, _VP, _VP, _SZ, _VP]),
+    "tp_trace_enable": (_I, [_I]),
+    "tp_trace_collect": (_I, [ctypes.POINTER(_I), ctypes.POINTER(_F), _I]),
+    "tp_kernel_name": (ctypes.c_char_p, [_I]),
 }
 
 _lib = None

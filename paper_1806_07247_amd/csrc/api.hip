@@ -109,8 +109,8 @@ int tp_tprod(const float* A, const float* B, float* C, int n1, int n2, int l, in
     const int h = tp::half_slices(n3);
 
     // Algorithm 1, step 1: DFT of the tubes of A and B
-    TP_TRY(tp::launch_rfft(A, L.a.re, L.a.im, (long long)n1 * n2, n3, s));
-    TP_TRY(tp::launch_rfft(B, L.b.re, L.b.im, (long long)n2 * l, n3, s));
+    TP_LAUNCH(tp::K_RFFT, s, tp::launch_rfft(A, L.a.re, L.a.im, (long long)n1 * n2, n3, s));
+    TP_LAUNCH(tp::K_RFFT, s, tp::launch_rfft(B, L.b.re, L.b.im, (long long)n2 * l, n3, s));
     // step 2: Cbar^(k) = Abar^(k) Bbar^(k), k < floor(n3/2)+1
     tp::CgemmArgs g{};
     g.ar = L.a.re;
@@ -132,9 +132,9 @@ int tp_tprod(const float* A, const float* B, float* C, int n1, int n2, int l, in
     g.real_first = 1;
     g.real_last = (n3 % 2 == 0) ? 1 : 0;
     g.kdyn = nullptr;
-    TP_TRY(tp::launch_cgemm(g, tp::OP_N, tp::OP_N, prec, s));
+    TP_LAUNCH(tp::K_CGEMM, s, tp::launch_cgemm(g, tp::OP_N, tp::OP_N, prec, s));
     // step 3: inverse DFT (conjugate fill implicit)
-    TP_TRY(tp::launch_irfft(L.c.re, L.c.im, C, (long long)n1 * l, n3, s));
+    TP_LAUNCH(tp::K_IRFFT, s, tp::launch_irfft(L.c.re, L.c.im, C, (long long)n1 * l, n3, s));
     return TP_OK;
 }
 
@@ -162,7 +162,7 @@ int tp_prox_tnn(const float* Y, float* X, int n1, int n2, int n3, float tau, int
     const long long mn = (long long)n1 * n2;
 
     // Algorithm 3, step 1
-    TP_TRY(tp::launch_rfft(Y, L.ybar.re, L.ybar.im, mn, n3, s));
+    TP_LAUNCH(tp::K_RFFT, s, tp::launch_rfft(Y, L.ybar.re, L.ybar.im, mn, n3, s));
     // step 2: SVD of each leading slice ...
     tp::JacobiArgs j{};
     j.yr = L.ybar.re;
@@ -177,9 +177,9 @@ int tp_prox_tnn(const float* Y, float* X, int n1, int n2, int n3, float tau, int
     j.max_sweeps = kDefaultSweeps;
     j.transpose = tr ? 1 : 0;
     j.tol = tp::jacobi_tol(R);
-    TP_TRY(tp::launch_jacobi(j, L.jscratch, L.jscratch_bytes, s));
+    TP_LAUNCH(tp::K_JACOBI, s, tp::launch_jacobi(j, L.jscratch, L.jscratch_bytes, s));
     // ... shrinkage (eq (21)): scaled columns sqrt(d_j)/sigma_j w_j
-    TP_TRY(tp::launch_shrink(L.w.re, L.w.im, L.sigma, rank ? rank : L.keep, R, P, h, (double)tau, s));
+    TP_LAUNCH(tp::K_SHRINK, s, tp::launch_shrink(L.w.re, L.w.im, L.sigma, rank ? rank : L.keep, R, P, h, (double)tau, s));
     // ... and W = U (S - tau)_+ V^* as two slice products
     tp::CgemmArgs g{};
     g.nslices = h;
@@ -191,27 +191,27 @@ int tp_prox_tnn(const float* Y, float* X, int n1, int n2, int n3, float tau, int
         g.br = L.ybar.re; g.bi = L.ybar.im; g.ldb = n2; g.sb = mn;
         g.cr = L.t.re; g.ci = L.t.im; g.ldc = p; g.sc = (long long)p * p;
         g.m = n2; g.n = n2; g.k = n1;
-        TP_TRY(tp::launch_cgemm(g, tp::OP_C, tp::OP_N, TP_PREC_FP32, s));
+        TP_LAUNCH(tp::K_CGEMM, s, tp::launch_cgemm(g, tp::OP_C, tp::OP_N, TP_PREC_FP32, s));
         g.ar = L.w.re; g.ai = L.w.im; g.lda = n2; g.sa = mn;
         g.br = L.t.re; g.bi = L.t.im; g.ldb = p; g.sb = (long long)p * p;
         g.cr = L.ybar.re; g.ci = L.ybar.im; g.ldc = n2; g.sc = mn;
         g.m = n1; g.n = n2; g.k = n2;
-        TP_TRY(tp::launch_cgemm(g, tp::OP_N, tp::OP_N, TP_PREC_FP32, s));
+        TP_LAUNCH(tp::K_CGEMM, s, tp::launch_cgemm(g, tp::OP_N, tp::OP_N, TP_PREC_FP32, s));
     } else {
         // T = Ybar Bhat (m x m), then W = T Bhat^* (m x n); Bhat is n x m
         g.ar = L.ybar.re; g.ai = L.ybar.im; g.lda = n2; g.sa = mn;
         g.br = L.w.re; g.bi = L.w.im; g.ldb = n1; g.sb = mn;
         g.cr = L.t.re; g.ci = L.t.im; g.ldc = p; g.sc = (long long)p * p;
         g.m = n1; g.n = n1; g.k = n2;
-        TP_TRY(tp::launch_cgemm(g, tp::OP_N, tp::OP_N, TP_PREC_FP32, s));
+        TP_LAUNCH(tp::K_CGEMM, s, tp::launch_cgemm(g, tp::OP_N, tp::OP_N, TP_PREC_FP32, s));
         g.ar = L.t.re; g.ai = L.t.im; g.lda = p; g.sa = (long long)p * p;
         g.br = L.w.re; g.bi = L.w.im; g.ldb = n1; g.sb = mn;
         g.cr = L.ybar.re; g.ci = L.ybar.im; g.ldc = n2; g.sc = mn;
         g.m = n1; g.n = n2; g.k = n1;
-        TP_TRY(tp::launch_cgemm(g, tp::OP_N, tp::OP_C, TP_PREC_FP32, s));
+        TP_LAUNCH(tp::K_CGEMM, s, tp::launch_cgemm(g, tp::OP_N, tp::OP_C, TP_PREC_FP32, s));
     }
     // step 3: inverse DFT (conjugate fill implicit)
-    TP_TRY(tp::launch_irfft(L.ybar.re, L.ybar.im, X, mn, n3, s));
+    TP_LAUNCH(tp::K_IRFFT, s, tp::launch_irfft(L.ybar.re, L.ybar.im, X, mn, n3, s));
     (void)R;
     return TP_OK;
 }
@@ -235,7 +235,7 @@ int tp_tnn(const float* A, int n1, int n2, int n3, double* out, int* info, void*
     hipStream_t s = as_stream(stream);
     const int h = tp::half_slices(n3);
     const bool tr = n1 < n2;
-    TP_TRY(tp::launch_rfft(A, L.ybar.re, L.ybar.im, (long long)n1 * n2, n3, s));
+    TP_LAUNCH(tp::K_RFFT, s, tp::launch_rfft(A, L.ybar.re, L.ybar.im, (long long)n1 * n2, n3, s));
     tp::JacobiArgs j{};
     j.yr = L.ybar.re;
     j.yi = L.ybar.im;
@@ -247,8 +247,8 @@ int tp_tnn(const float* A, int n1, int n2, int n3, double* out, int* info, void*
     j.max_sweeps = kDefaultSweeps;
     j.transpose = tr ? 1 : 0;
     j.tol = tp::jacobi_tol(tr ? n2 : n1);
-    TP_TRY(tp::launch_jacobi(j, L.jscratch, L.jscratch_bytes, s));
-    TP_TRY(tp::launch_tnn_reduce(L.sigma, h, tr ? n1 : n2, n3, out, s));
+    TP_LAUNCH(tp::K_JACOBI, s, tp::launch_jacobi(j, L.jscratch, L.jscratch_bytes, s));
+    TP_LAUNCH(tp::K_TNN_REDUCE, s, tp::launch_tnn_reduce(L.sigma, h, tr ? n1 : n2, n3, out, s));
     return TP_OK;
 }
 

@@ -14,7 +14,8 @@
 // take the same decision), and when |gamma| > tol sqrt(alpha beta) applies
 // the rotation that zeroes gamma.  The rotation (zeta, t, c, s and the phase
 // of gamma) is computed in FP64 and applied to the FP32 columns.  The
-// iteration stops after a sweep without rotations, or at max_sweeps (info=1).
+// iteration stops after a sweep without rotations (info = sweeps used), or at
+// max_sweeps (info = -max_sweeps).
 //
 // Real slices stay real: with zero imaginary parts gamma is real, its phase
 // is +-1 and every update keeps the imaginary parts at zero.
@@ -161,7 +162,7 @@ __global__ __launch_bounds__(256) void k_jacobi(JacobiArgs a, float2* __restrict
             wi[e] = v.y;
         }
     }
-    if (a.info && tid == 0) a.info[s] = converged ? 0 : 1;
+    if (a.info && tid == 0) a.info[s] = converged ? (sweep > 0 ? sweep : 1) : -sweep;
 }
 
 constexpr size_t kMaxLds = 160 * 1024 - 1024;

@@ -81,7 +81,7 @@ struct JacobiArgs {
     float* wr;        // output: rotated columns, row-major rows x p per slice
     float* wi;
     double* sigma;    // p per slice (unsorted norms of the rotated columns)
-    int* info;        // per slice sweeps-cap flag (may be null)
+    int* info;        // per slice: sweeps used, negated when the cap was hit (may be null)
     int m, n;         // slice shape
     int nslices;
     int max_sweeps;
@@ -99,7 +99,33 @@ hipError_t launch_shrink(float* wr, float* wi, const double* sigma, int* keep, i
 // (1/n3) sum over all n3 slices of the singular values, from the half spectrum
 hipError_t launch_tnn_reduce(const double* sigma, int nslices, int P, int n3, double* out, hipStream_t s);
 
+// ------------------------------------------------------------- tracing ----
+enum KernelId { K_RFFT = 0, K_IRFFT = 1, K_CGEMM = 2, K_JACOBI = 3, K_SHRINK = 4, K_TNN_REDUCE = 5 };
+
+// Records HIP events around the launches in its scope while tracing is on.
+class TraceScope {
+   public:
+    TraceScope(hipStream_t s, int id);
+    ~TraceScope();
+
+   private:
+    hipStream_t stream_;
+    int id_;
+    void* start_;
+};
+
 }  // namespace tp
+
+// enqueue one stage: trace it, and turn a launch failure into TP_ERR_HIP
+#define TP_LAUNCH(id, stream, expr)                   \
+    do {                                              \
+        hipError_t _e;                                \
+        {                                             \
+            tp::TraceScope _ts((stream), (id));       \
+            _e = (expr);                              \
+        }                                             \
+        if (_e != hipSuccess) return TP_ERR_HIP;      \
+    } while (0)
 
 #define TP_TRY(expr)                                  \
     do {                                              \

@@ -1,0 +1,93 @@
+// Stage timing: HIP events recorded around every kernel the entry points
+// enqueue, while enabled.  Used by the benchmark to time each kernel on the
+// stream it runs on.  Events are pooled; nothing here runs on the device.
+#include <mutex>
+#include <vector>
+
+#include "tp_internal.h"
+
+namespace tp {
+namespace {
+
+struct Rec {
+    hipEvent_t a, b;
+    int id;
+};
+
+std::mutex g_mu;
+bool g_on = false;
+std::vector<hipEvent_t> g_pool;
+std::vector<Rec> g_recs;
+
+hipEvent_t take_event()
+{
+    if (!g_pool.empty()) {
+        hipEvent_t e = g_pool.back();
+        g_pool.pop_back();
+        return e;
+    }
+    hipEvent_t e = nullptr;
+    if (hipEventCreate(&e) != hipSuccess) return nullptr;
+    return e;
+}
+
+const char* const kNames[] = {"rfft", "irfft", "cgemm", "jacobi", "shrink", "tnn_reduce"};
+
+}  // namespace
+
+TraceScope::TraceScope(hipStream_t s, int id) : stream_(s), id_(id), start_(nullptr)
+{
+    std::lock_guard<std::mutex> lk(g_mu);
+    if (!g_on) return;
+    start_ = take_event();
+    if (start_) hipEventRecord(static_cast<hipEvent_t>(start_), s);
+}
+
+TraceScope::~TraceScope()
+{
+    if (!start_) return;
+    std::lock_guard<std::mutex> lk(g_mu);
+    hipEvent_t b = take_event();
+    if (!b) return;
+    hipEventRecord(b, stream_);
+    g_recs.push_back(Rec{static_cast<hipEvent_t>(start_), b, id_});
+}
+
+}  // namespace tp
+
+extern "C" {
+
+int tp_trace_enable(int enable)
+{
+    std::lock_guard<std::mutex> lk(tp::g_mu);
+    tp::g_on = enable != 0;
+    return TP_OK;
+}
+
+int tp_trace_collect(int* kernel_ids, float* ms, int capacity)
+{
+    std::lock_guard<std::mutex> lk(tp::g_mu);
+    int n = 0;
+    for (const tp::Rec& r : tp::g_recs) {
+        if (hipEventSynchronize(r.b) != hipSuccess) return TP_ERR_HIP;
+        float t = 0.0f;
+        if (hipEventElapsedTime(&t, r.a, r.b) != hipSuccess) return TP_ERR_HIP;
+        if (n < capacity) {
+            if (kernel_ids) kernel_ids[n] = r.id;
+            if (ms) ms[n] = t;
+        }
+        ++n;
+        tp::g_pool.push_back(r.a);
+        tp::g_pool.push_back(r.b);
+    }
+    tp::g_recs.clear();
+    return n;
+}
+
+const char* tp_kernel_name(int id)
+{
+    if (id < 0 || id >= (int)(sizeof(tp::kNames) / sizeof(tp::kNames[0]))) return "unknown";
+    return tp::kNames[id];
+}
+
+}  // extern "C"

@@ -49,7 +49,7 @@ def test_prox_matches_oracle(tp, orc, shape, frac):
     err = rel_fro(X, ref) if np.linalg.norm(ref) > 0 else np.abs(X).max()
     say(f"  rel.err {err:.3e} info {info.cpu().numpy().tolist()} rank {rank.cpu().numpy().tolist()}")
     assert err <= 1e-4
-    assert int(info.sum()) == 0
+    assert int(info.min()) > 0
     sig = orc.slice_sigma(Y)[:h]
     assert np.array_equal(rank.cpu().numpy(), (sig > np.float32(tau)).sum(axis=1)) or frac == 0.0
 
@@ -91,7 +91,7 @@ def test_prox_low_rank_plus_sparse_config(tp, orc):
     err = rel_fro(X, ref)
     say(f"  rel.err {err:.3e} info {info.cpu().numpy().tolist()}")
     assert err <= 1e-4
-    assert int(info.sum()) == 0
+    assert int(info.min()) > 0
 
 
 def test_prox_deterministic(tp):
