@@ -70,6 +70,24 @@ int tp_tprod(const float* A, const float* B, float* C, int n1, int n2, int l, in
              void* workspace, size_t workspace_bytes, void* stream);
 
 /*
+ * t-SVD A = U * S * V^* (Theorem 2.2), computed by Algorithm 2: DFT of the
+ * tubes of A; for each of the floor(n3/2)+1 leading Fourier slices a full
+ * SVD by one-sided Jacobi (real rotations on the real DC and, for even n3,
+ * middle slices, so that U, S, V come out real), singular values sorted in
+ * decreasing order (so eq (13) holds), left/right bases completed to square
+ * unitary matrices; inverse DFTs of Ubar, Sbar, Vbar (the trailing slices are
+ * the conjugates, implicit in the real inverse transform).
+ *   A  n1 x n2 x n3 (input)
+ *   U  n1 x n1 x n3, S n1 x n2 x n3 (f-diagonal), V n2 x n2 x n3 (outputs)
+ *   info  as for tp_prox_tnn
+ * U and V are unique only up to the usual SVD freedoms (phases, rotations
+ * inside repeated singular values, the completed bases); S is unique.
+ */
+size_t tp_tsvd_workspace_size(int n1, int n2, int n3);
+int tp_tsvd(const float* A, float* U, float* S, float* V, int n1, int n2, int n3, int* info,
+            void* workspace, size_t workspace_bytes, void* stream);
+
+/*
  * Proximal operator of the tensor nuclear norm, X = Prox_tau(Y) (eq (19)),
  * computed by Algorithm 3 (t-SVT, Theorem 2.3): DFT of the tubes of Y; for
  * each of the floor(n3/2)+1 leading Fourier slices a full SVD by one-sided
@@ -78,7 +96,8 @@ int tp_tprod(const float* A, const float* B, float* C, int n1, int n2, int l, in
  *   Y, X   n1 x n2 x n3 (input, output)
  *   tau    >= 0 (tau = 0 returns Y up to rounding); NaN or < 0: TP_ERR_ARG
  *   info   optional device int[floor(n3/2)+1]: the number of Jacobi sweeps
- *          used by each slice (> 0), negated when the sweep cap (30) was
+ *          used by each slice (> 0), negated when the sweep cap (30 unless
+ *          changed with TP_PARAM_JACOBI_SWEEPS) was
  *          reached without convergence (the result is still written)
  *   rank   optional device int[floor(n3/2)+1]: #{sigma_j > tau} per slice
  */
@@ -99,13 +118,42 @@ int tp_tnn(const float* A, int n1, int n2, int n3, double* out, int* info, void*
            size_t workspace_bytes, void* stream);
 
 /*
+ * Tunable launch parameters (process-wide, host side).  They select among
+ * equivalent kernel schedules: results stay within the documented
+ * tolerances for every setting, but workspace sizes may change, so query them
+ * after setting.  tp_set_param returns TP_ERR_ARG for an unknown key or a
+ * negative value; 0 restores the default of a key.  tp_get_param returns the
+ * value in effect (the default when unset), or -1 for an unknown key.
+ *   TP_PARAM_JACOBI_BLOCK         block width of the multi-workgroup Jacobi
+ *                                 (0 = chosen from the slice height)
+ *   TP_PARAM_JACOBI_MODE          0 auto, 1 one workgroup per slice when the
+ *                                 slice fits in LDS, 2 always multi-workgroup
+ *   TP_PARAM_JACOBI_BLOCKED_BELOW auto mode: slices that fit in LDS go
+ *                                 multi-workgroup when fewer than this many
+ *                                 slices are processed (default 128)
+ *   TP_PARAM_JACOBI_SWEEPS        sweep cap (default 30)
+ *   TP_PARAM_GEMM_VARIANT         slice GEMM tile variant (0 = default)
+ */
+enum {
+    TP_PARAM_JACOBI_BLOCK = 0,
+    TP_PARAM_JACOBI_MODE = 1,
+    TP_PARAM_JACOBI_BLOCKED_BELOW = 2,
+    TP_PARAM_JACOBI_SWEEPS = 3,
+    TP_PARAM_GEMM_VARIANT = 4,
+    TP_PARAM_COUNT = 5
+};
+int tp_set_param(int key, int value);
+int tp_get_param(int key);
+
+/*
  * Stage timing (a profiling aid; not for use under stream capture).  While
  * enabled, every entry point records a HIP event on its stream before and
  * after each kernel it enqueues.  tp_trace_collect waits for those events and
  * writes, in launch order, the kernel id and its elapsed time in ms for up to
  * `capacity` launches; it returns the number of launches recorded since the
  * last collect (or a negative tp_status) and forgets them.
- * Kernel ids: 0 rfft, 1 irfft, 2 cgemm, 3 jacobi, 4 shrink, 5 tnn_reduce.
+ * Kernel ids: 0 rfft, 1 irfft, 2 cgemm, 3 jacobi, 4 shrink, 5 tnn_reduce,
+ * 6 tsvd_finish.
  */
 int tp_trace_enable(int enable);
 int tp_trace_collect(int* kernel_ids, float* ms, int capacity);

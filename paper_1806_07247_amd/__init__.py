@@ -16,7 +16,7 @@ TP_PREC_BF16X3 = 1
 TP_PREC_BF16 = 2
 _PREC = {"fp32": TP_PREC_FP32, "bf16x3": TP_PREC_BF16X3, "bf16": TP_PREC_BF16}
 
-__all__ = ["tp_tprod", "tp_tprod_workspace_size", "tp_prox_tnn", "tp_prox_tnn_workspace_size",
+__all__ = ["tp_tprod", "tp_tprod_workspace_size", "tp_tsvd", "tp_tsvd_workspace_size", "tp_prox_tnn", "tp_prox_tnn_workspace_size",
            "tp_tnn", "tp_tnn_workspace_size", "half_slices", "TPError", "TP_PREC_FP32",
            "TP_PREC_BF16X3", "TP_PREC_BF16", "library_path"]
 
@@ -119,3 +119,23 @@ def tp_tnn(A, out=None, info=None, workspace=None):
                     _stream(A.device))
     _lib.check("tp_tnn", st)
     return res
+
+
+def tp_tsvd_workspace_size(n1, n2, n3):
+    return int(_lib.load().tp_tsvd_workspace_size(n1, n2, n3))
+
+
+def tp_tsvd(A, info=None, workspace=None):
+    """t-SVD A = U * S * V^* (Theorem 2.2) by Algorithm 2; returns (U, S, V)."""
+    lib = _lib.load()
+    A = _dev_tensor(A, "A")
+    n1, n2, n3 = A.shape
+    U = torch.empty((n1, n1, n3), dtype=torch.float32, device=A.device)
+    S = torch.empty((n1, n2, n3), dtype=torch.float32, device=A.device)
+    V = torch.empty((n2, n2, n3), dtype=torch.float32, device=A.device)
+    ws_bytes = lib.tp_tsvd_workspace_size(n1, n2, n3)
+    ws = workspace if workspace is not None else _workspace(ws_bytes, A.device)
+    st = lib.tp_tsvd(A.data_ptr(), U.data_ptr(), S.data_ptr(), V.data_ptr(), n1, n2, n3, _ptr(info),
+                     ws.data_ptr(), ws.numel(), _stream(A.device))
+    _lib.check("tp_tsvd", st)
+    return U, S, V

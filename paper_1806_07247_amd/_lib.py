@@ -22,10 +22,14 @@ SIGNATURES = {
     "tp_version": (_I, []),
     "tp_tprod_workspace_size": (_SZ, [_I, _I, _I, _I, _I]),
     "tp_tprod": (_I, [_VP, _VP, _VP, _I, _I, _I, _I, _I, _VP, _SZ, _VP]),
+    "tp_tsvd_workspace_size": (_SZ, [_I, _I, _I]),
+    "tp_tsvd": (_I, [_VP, _VP, _VP, _VP, _I, _I, _I, _VP, _VP, _SZ, _VP]),
     "tp_prox_tnn_workspace_size": (_SZ, [_I, _I, _I]),
     "tp_prox_tnn": (_I, [_VP, _VP, _I, _I, _I, _F, _VP, _VP, _VP, _SZ, _VP]),
     "tp_tnn_workspace_size": (_SZ, [_I, _I, _I]),
     "tp_tnn": (_I, [_VP, _I, _I, _I, _VP, _VP, _VP, _SZ, _VP]),
+    "tp_set_param": (_I, [_I, _I]),
+    "tp_get_param": (_I, [_I]),
     "tp_trace_enable": (_I, [_I]),
     "tp_trace_collect": (_I, [ctypes.POINTER(_I), ctypes.POINTER(_F), _I]),
     "tp_kernel_name": (ctypes.c_char_p, [_I]),

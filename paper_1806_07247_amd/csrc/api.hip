@@ -61,13 +61,45 @@ tp::Arena svt_arena(void* ws, size_t bytes, int n1, int n2, int n3, bool recon, 
         t.keep = ar.take<int>(h);
     }
     t.sigma = ar.take<double>(h * P);
-    t.jscratch_bytes = tp::jacobi_scratch_bytes(n1, n2, (int)h);
+    t.jscratch_bytes = tp::jacobi_scratch_bytes(n1, n2, (int)h, false);
     t.jscratch = t.jscratch_bytes ? ar.take<char>(t.jscratch_bytes) : nullptr;
     if (L) *L = t;
     return ar;
 }
 
-constexpr int kDefaultSweeps = 30;
+
+// Workspace of tsvd.
+struct TsvdLayout {
+    tp::Planes abar, l, q, s;
+    float2* cols;
+    float2* v;
+    double* sigma;
+    void* jscratch;
+    size_t jscratch_bytes;
+};
+
+tp::Arena tsvd_arena(void* ws, size_t bytes, int n1, int n2, int n3, TsvdLayout* L)
+{
+    const size_t h = (size_t)tp::half_slices(n3);
+    const size_t R = n1 >= n2 ? n1 : n2, P = n1 >= n2 ? n2 : n1, mn = (size_t)n1 * n2;
+    tp::Arena ar(ws, bytes);
+    TsvdLayout t{};
+    t.abar.re = ar.take<float>(h * mn);
+    t.abar.im = ar.take<float>(h * mn);
+    t.cols = ar.take<float2>(h * R * P);
+    t.v = ar.take<float2>(h * P * P);
+    t.sigma = ar.take<double>(h * P);
+    t.l.re = ar.take<float>(h * R * R);
+    t.l.im = ar.take<float>(h * R * R);
+    t.q.re = ar.take<float>(h * P * P);
+    t.q.im = ar.take<float>(h * P * P);
+    t.s.re = ar.take<float>(h * mn);
+    t.s.im = ar.take<float>(h * mn);
+    t.jscratch_bytes = tp::jacobi_scratch_bytes(n1, n2, (int)h, true);
+    t.jscratch = t.jscratch_bytes ? ar.take<char>(t.jscratch_bytes) : nullptr;
+    if (L) *L = t;
+    return ar;
+}
 
 }  // namespace
 
@@ -174,7 +206,7 @@ int tp_prox_tnn(const float* Y, float* X, int n1, int n2, int n3, float tau, int
     j.m = n1;
     j.n = n2;
     j.nslices = h;
-    j.max_sweeps = kDefaultSweeps;
+    j.max_sweeps = tp::param(TP_PARAM_JACOBI_SWEEPS);
     j.transpose = tr ? 1 : 0;
     j.tol = tp::jacobi_tol(R);
     TP_LAUNCH(tp::K_JACOBI, s, tp::launch_jacobi(j, L.jscratch, L.jscratch_bytes, s));
@@ -244,11 +276,60 @@ int tp_tnn(const float* A, int n1, int n2, int n3, double* out, int* info, void*
     j.m = n1;
     j.n = n2;
     j.nslices = h;
-    j.max_sweeps = kDefaultSweeps;
+    j.max_sweeps = tp::param(TP_PARAM_JACOBI_SWEEPS);
     j.transpose = tr ? 1 : 0;
     j.tol = tp::jacobi_tol(tr ? n2 : n1);
     TP_LAUNCH(tp::K_JACOBI, s, tp::launch_jacobi(j, L.jscratch, L.jscratch_bytes, s));
     TP_LAUNCH(tp::K_TNN_REDUCE, s, tp::launch_tnn_reduce(L.sigma, h, tr ? n1 : n2, n3, out, s));
+    return TP_OK;
+}
+
+size_t tp_tsvd_workspace_size(int n1, int n2, int n3)
+{
+    if (bad_dim(n1) || bad_dim(n2) || bad_dim(n3)) return 0;
+    return tsvd_arena(nullptr, 0, n1, n2, n3, nullptr).used;
+}
+
+int tp_tsvd(const float* A, float* U, float* S, float* V, int n1, int n2, int n3, int* info, void* workspace,
+            size_t workspace_bytes, void* stream)
+{
+    if (!A || !U || !S || !V) return TP_ERR_ARG;
+    if (bad_dim(n1) || bad_dim(n2) || bad_dim(n3) || n3 > kMaxN3) return TP_ERR_SHAPE;
+    if (bad_slice(n1, n2) || bad_slice(n1, n1) || bad_slice(n2, n2)) return TP_ERR_SHAPE;
+    if ((n1 < n2 ? n2 : n1) > 2048) return TP_ERR_UNSUPPORTED;
+    TsvdLayout L;
+    tp::Arena ar = tsvd_arena(workspace, workspace_bytes, n1, n2, n3, &L);
+    if (!ar.ok) return TP_ERR_WORKSPACE;
+    hipStream_t s = as_stream(stream);
+    const int h = tp::half_slices(n3);
+    const bool tr = n1 < n2;
+    const int R = tr ? n2 : n1, P = tr ? n1 : n2;
+    // Algorithm 2, step 1
+    TP_LAUNCH(tp::K_RFFT, s, tp::launch_rfft(A, L.abar.re, L.abar.im, (long long)n1 * n2, n3, s));
+    // step 2: SVD of each leading slice (real Jacobi on the real slices), bases sorted and completed
+    tp::JacobiArgs j{};
+    j.yr = L.abar.re;
+    j.yi = L.abar.im;
+    j.sigma = L.sigma;
+    j.info = info;
+    j.m = n1;
+    j.n = n2;
+    j.nslices = h;
+    j.max_sweeps = tp::param(TP_PARAM_JACOBI_SWEEPS);
+    j.transpose = tr ? 1 : 0;
+    j.tol = tp::jacobi_tol(R);
+    j.cols = L.cols;
+    j.qout = L.v;
+    TP_LAUNCH(tp::K_JACOBI, s, tp::launch_jacobi(j, L.jscratch, L.jscratch_bytes, s));
+    TP_LAUNCH(tp::K_TSVD_FINISH, s,
+              tp::launch_tsvd_finish(L.cols, L.sigma, L.v, L.l, L.q, L.s, R, P, n1, n2, h, s));
+    // A = L S Q^* slice-wise (or Q S L^* for the transposed work matrix)
+    const tp::Planes& ub = tr ? L.q : L.l;
+    const tp::Planes& vb = tr ? L.l : L.q;
+    // step 3: inverse DFTs (conjugate fill of the trailing slices implicit)
+    TP_LAUNCH(tp::K_IRFFT, s, tp::launch_irfft(ub.re, ub.im, U, (long long)n1 * n1, n3, s));
+    TP_LAUNCH(tp::K_IRFFT, s, tp::launch_irfft(L.s.re, L.s.im, S, (long long)n1 * n2, n3, s));
+    TP_LAUNCH(tp::K_IRFFT, s, tp::launch_irfft(vb.re, vb.im, V, (long long)n2 * n2, n3, s));
     return TP_OK;
 }
 

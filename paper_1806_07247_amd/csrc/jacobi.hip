@@ -7,11 +7,11 @@
 // workspace buffer.  A sweep visits all P(P-1)/2 column pairs in P'-1 steps of
 // P'/2 disjoint pairs (round-robin "circle" order, P' = P rounded up to even);
 // a barrier separates steps.  A group of G lanes handles one pair: each lane
-// holds RPL rows of both columns in registers, accumulates
+// holds RPL rows of both columns in registers, accumulates its part of
 //   alpha = ||x||^2, beta = ||y||^2, gamma = x^* y
-// in FP64 (products of FP32 values are exact in FP64), reduces them with an
-// xor butterfly (every lane ends with bitwise identical sums, so all lanes
-// take the same decision), and when |gamma| > tol sqrt(alpha beta) applies
+// in FP32, and the group sums the parts in FP64 with a butterfly of DPP moves
+// (every lane ends with bitwise identical sums, so all lanes take the same
+// decision); when |gamma| > tol sqrt(alpha beta) it applies
 // the rotation that zeroes gamma.  The rotation (zeta, t, c, s and the phase
 // of gamma) is computed in FP64 and applied to the FP32 columns.  The
 // iteration stops after a sweep without rotations (info = sweeps used), or at
@@ -31,18 +31,179 @@ namespace {
 // (even) columns: position 0 is fixed, the others rotate.
 __device__ __forceinline__ int rr_col(int pos, int step, int np)
 {
-    return pos == 0 ? 0 : 1 + (pos - 1 + step) % (np - 1);
+    if (pos == 0) return 0;
+    int c = pos - 1 + step;  // < 2 (np - 1)
+    if (c >= np - 1) c -= np - 1;
+    return 1 + c;
 }
 
+// DPP move of a double within a row of 16 lanes
+template <int CTRL>
+__device__ __forceinline__ double dpp_f64(double v)
+{
+    const long long u = __builtin_bit_cast(long long, v);
+    const int lo = __builtin_amdgcn_update_dpp(0, (int)(u & 0xffffffff), CTRL, 0xf, 0xf, false);
+    const int hi = __builtin_amdgcn_update_dpp(0, (int)(u >> 32), CTRL, 0xf, 0xf, false);
+    return __builtin_bit_cast(double, ((long long)hi << 32) | (unsigned int)lo);
+}
+
+// Sum over the G lanes of a group.  Each level adds a partner's value with a
+// commutative add, so every lane of the group ends with the same bits.
+// Partners: lane^1, lane^2 (quad permutations), the mirror within 8 lanes and
+// within 16 lanes (DPP), then lane^16, lane^32 for wider groups.
 template <int G>
 __device__ __forceinline__ double group_sum(double v)
 {
+    if (G >= 2) v += dpp_f64<0xB1>(v);   // quad_perm [1,0,3,2]
+    if (G >= 4) v += dpp_f64<0x4E>(v);   // quad_perm [2,3,0,1]
+    if (G >= 8) v += dpp_f64<0x141>(v);  // row_half_mirror
+    if (G >= 16) v += dpp_f64<0x140>(v); // row_mirror
 #pragma unroll
-    for (int m = G / 2; m >= 1; m >>= 1) v += __shfl_xor(v, m, G);
+    for (int m = 16; m < G; m <<= 1) v += __shfl_xor(v, m, G);
     return v;
 }
 
-template <int G, int RPL, bool LDS>
+// One Jacobi rotation of columns p and q (each R long, stride ldr in `work`)
+// by the G lanes of a group; gl is the lane within the group.  Returns true
+// when the pair was rotated (identically in every lane of the group).
+template <int G, int RPL, bool WITHV>
+__device__ __forceinline__ bool jacobi_pair(float2* work, int ldr, int p, int q, int R, int gl, double tol2,
+                                            float2* vw, int ldv, int P)
+{
+    float2* xc = work + (long long)p * ldr;
+    float2* yc = work + (long long)q * ldr;
+    float2 x[RPL], y[RPL];
+    double al, be, gr, gi;
+    float pa = 0.f, pb = 0.f, pr = 0.f, pi = 0.f;
+#pragma unroll
+    for (int t = 0; t < RPL; ++t) {
+        const int i = gl + G * t;
+        if (i < R) {
+            x[t] = xc[i];
+            y[t] = yc[i];
+        } else {
+            x[t] = make_float2(0.f, 0.f);
+            y[t] = make_float2(0.f, 0.f);
+        }
+        pa = fmaf(x[t].x, x[t].x, fmaf(x[t].y, x[t].y, pa));
+        pb = fmaf(y[t].x, y[t].x, fmaf(y[t].y, y[t].y, pb));
+        pr = fmaf(x[t].x, y[t].x, fmaf(x[t].y, y[t].y, pr));
+        pi = fmaf(x[t].x, y[t].y, fmaf(-x[t].y, y[t].x, pi));
+    }
+    // per-lane partial sums of RPL rows in FP32 (relative error ~RPL u32, far
+    // below the rotation threshold); the cross-lane sums and everything after
+    // them in FP64
+    al = group_sum<G>((double)pa);
+    be = group_sum<G>((double)pb);
+    gr = group_sum<G>((double)pr);
+    gi = group_sum<G>((double)pi);
+    const double g2 = gr * gr + gi * gi;
+    // rotate when |gamma| > tol sqrt(alpha beta)
+    if (!(g2 > 0.0 && g2 > tol2 * al * be)) return false;
+    // x' = c x - s conj(e) y,  y' = s e x + c y,  e = gamma/|gamma|,
+    // t = s/c the smaller root of t^2 + 2 zeta t - 1 = 0, zeta = (beta - alpha)/(2|gamma|)
+    const double g = sqrt(g2);
+    const double ig = 1.0 / g;
+    const double zeta = 0.5 * (be - al) * ig;
+    const double t = copysign(1.0, zeta) / (fabs(zeta) + sqrt(fma(zeta, zeta, 1.0)));
+    const double c = 1.0 / sqrt(fma(t, t, 1.0));
+    const double sn = c * t;
+    const float cf = (float)c;
+    const float sr = (float)(sn * gr * ig), si = (float)(sn * gi * ig);  // s e
+#pragma unroll
+    for (int t2 = 0; t2 < RPL; ++t2) {
+        const int i = gl + G * t2;
+        if (i < R) {
+            const float2 xv = x[t2], yv = y[t2];
+            // s conj(e) y = (sr yr + si yi, sr yi - si yr);  s e x = (sr xr - si xi, sr xi + si xr)
+            xc[i] = make_float2(cf * xv.x - (sr * yv.x + si * yv.y), cf * xv.y - (sr * yv.y - si * yv.x));
+            yc[i] = make_float2((sr * xv.x - si * xv.y) + cf * yv.x, (sr * xv.y + si * xv.x) + cf * yv.y);
+        }
+    }
+    if (WITHV) {  // the same rotation on columns p, q of V (P rows)
+        float2* vx = vw + (long long)p * ldv;
+        float2* vy = vw + (long long)q * ldv;
+#pragma unroll
+        for (int t2 = 0; t2 < RPL; ++t2) {
+            const int i = gl + G * t2;
+            if (i < P) {
+                const float2 xv = vx[i], yv = vy[i];
+                vx[i] = make_float2(cf * xv.x - (sr * yv.x + si * yv.y), cf * xv.y - (sr * yv.y - si * yv.x));
+                vy[i] = make_float2((sr * xv.x - si * xv.y) + cf * yv.x, (sr * xv.y + si * xv.x) + cf * yv.y);
+            }
+        }
+    }
+    return true;
+}
+
+__device__ __forceinline__ void set_identity(float2* v, int P, int w, int nw)
+{
+    for (int e = w; e < P * P; e += nw) v[e] = make_float2((e / P) == (e % P) ? 1.0f : 0.0f, 0.0f);
+}
+
+// Copies slice s of the planar row-major input into the column-major work
+// matrix (conjugate transpose when a.transpose); worker w of nw.
+__device__ __forceinline__ void load_work(const JacobiArgs& a, int s, float2* work, int R, int P, int w, int nw)
+{
+    const long long so = (long long)s * a.m * a.n;
+    const float* yr = a.yr + so;
+    const float* yi = a.yi + so;
+    const int total = R * P;
+    if (!a.transpose) {
+        for (int e = w; e < total; e += nw) {  // Y row-major m x n: e = i*n + j
+            const int i = e / P, j = e % P;
+            work[(long long)j * R + i] = make_float2(yr[e], yi[e]);
+        }
+    } else {
+        for (int e = w; e < total; e += nw) {  // column j of Y^* = conj(row j of Y)
+            const int j = e / R, i = e % R;
+            work[(long long)j * R + i] = make_float2(yr[e], -yi[e]);
+        }
+    }
+}
+
+// Column norms (FP64) and the rotated columns (row-major R x P, planar), by
+// workgroup wg of nwg working on slice s.
+template <int G>
+__device__ __forceinline__ void store_result(const JacobiArgs& a, int s, const float2* work, int R, int P, int wg,
+                                             int nwg)
+{
+    const int gl = threadIdx.x % G, ngroups = blockDim.x / G;
+    double* sig = a.sigma + (long long)s * P;
+    for (int j = wg * ngroups + threadIdx.x / G; j < P; j += nwg * ngroups) {
+        double acc = 0.0;
+        for (int i = gl; i < R; i += G) {
+            const float2 v = work[(long long)j * R + i];
+            acc = fma((double)v.x, (double)v.x, fma((double)v.y, (double)v.y, acc));
+        }
+        acc = group_sum<G>(acc);
+        if (gl == 0) sig[j] = sqrt(acc);
+    }
+    if (a.wr) {
+        float* wr = a.wr + (long long)s * R * P;
+        float* wi = a.wi + (long long)s * R * P;
+        const int total = R * P;
+        for (int e = wg * blockDim.x + threadIdx.x; e < total; e += nwg * blockDim.x) {
+            const int i = e / P, j = e % P;
+            const float2 v = work[(long long)j * R + i];
+            wr[e] = v.x;
+            wi[e] = v.y;
+        }
+    }
+    if (a.cols) {
+        float2* c = a.cols + (long long)s * R * P;
+        for (int e = wg * blockDim.x + threadIdx.x; e < R * P; e += nwg * blockDim.x) c[e] = work[e];
+    }
+}
+
+__device__ __forceinline__ void store_q(const JacobiArgs& a, int s, const float2* q, int P, int wg, int nwg)
+{
+    float2* o = a.qout + (long long)s * P * P;
+    for (int e = wg * blockDim.x + threadIdx.x; e < P * P; e += nwg * blockDim.x) o[e] = q[e];
+}
+
+// ---- whole slice in one workgroup (LDS when it fits, else workspace) ----
+template <int G, int RPL, bool LDS, bool WITHV>
 __global__ __launch_bounds__(256) void k_jacobi(JacobiArgs a, float2* __restrict__ gwork)
 {
     extern __shared__ float2 lwork[];
@@ -50,32 +211,18 @@ __global__ __launch_bounds__(256) void k_jacobi(JacobiArgs a, float2* __restrict
     const int s = blockIdx.x;
     const int R = a.transpose ? a.n : a.m;
     const int P = a.transpose ? a.m : a.n;
-    const int ldr = R;
-    float2* work = LDS ? lwork : gwork + (long long)s * R * P;
-    const long long so = (long long)s * a.m * a.n;
-    const float* yr = a.yr + so;
-    const float* yi = a.yi + so;
-    const int tid = threadIdx.x, nthr = blockDim.x;
-
-    // load the work matrix, column-major
-    const int total = R * P;
-    if (!a.transpose) {
-        for (int e = tid; e < total; e += nthr) {  // Y is row-major m x n: e = i*n + j
-            const int i = e / P, j = e % P;
-            work[j * ldr + i] = make_float2(yr[e], yi[e]);
-        }
-    } else {
-        for (int e = tid; e < total; e += nthr) {  // column j of Y^* is conj(row j of Y)
-            const int j = e / R, i = e % R;
-            work[j * ldr + i] = make_float2(yr[e], -yi[e]);
-        }
-    }
+    const long long per = (long long)R * P + (WITHV ? (long long)P * P : 0);
+    float2* work = LDS ? lwork : gwork + (long long)s * per;
+    float2* vw = work + (long long)R * P;
+    const int tid = threadIdx.x;
+    load_work(a, s, work, R, P, tid, blockDim.x);
+    if (WITHV) set_identity(vw, P, tid, blockDim.x);
     if (tid == 0) rotated = 0;
     __syncthreads();
 
     const int np = P + (P & 1);
-    const int group = tid / G, gl = tid % G, ngroups = nthr / G;
-    const double tol = a.tol;
+    const int group = tid / G, gl = tid % G, ngroups = blockDim.x / G;
+    const double tol2 = a.tol * a.tol;
     int sweep = 0;
     bool converged = (P < 2);
     while (!converged && sweep < a.max_sweeps) {
@@ -84,53 +231,7 @@ __global__ __launch_bounds__(256) void k_jacobi(JacobiArgs a, float2* __restrict
                 const int p = rr_col(pair, step, np);
                 const int q = rr_col(np - 1 - pair, step, np);
                 if (p >= P || q >= P) continue;
-                float2* xc = work + p * ldr;
-                float2* yc = work + q * ldr;
-                float2 x[RPL], y[RPL];
-                double al = 0.0, be = 0.0, gr = 0.0, gi = 0.0;
-#pragma unroll
-                for (int t = 0; t < RPL; ++t) {
-                    const int i = gl + G * t;
-                    if (i < R) {
-                        x[t] = xc[i];
-                        y[t] = yc[i];
-                    } else {
-                        x[t] = make_float2(0.f, 0.f);
-                        y[t] = make_float2(0.f, 0.f);
-                    }
-                    const double xr = x[t].x, xi = x[t].y, yr_ = y[t].x, yi_ = y[t].y;
-                    al = fma(xr, xr, fma(xi, xi, al));
-                    be = fma(yr_, yr_, fma(yi_, yi_, be));
-                    gr = fma(xr, yr_, fma(xi, yi_, gr));
-                    gi = fma(xr, yi_, fma(-xi, yr_, gi));
-                }
-                al = group_sum<G>(al);
-                be = group_sum<G>(be);
-                gr = group_sum<G>(gr);
-                gi = group_sum<G>(gi);
-                const double g = sqrt(gr * gr + gi * gi);
-                if (g > 0.0 && g > tol * sqrt(al) * sqrt(be)) {
-                    // x' = c x - s conj(e) y,  y' = s e x + c y,  e = gamma/|gamma|
-                    const double zeta = (be - al) / (2.0 * g);
-                    const double t = (zeta >= 0.0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
-                    const double c = 1.0 / sqrt(1.0 + t * t);
-                    const double sn = c * t;
-                    const double er = gr / g, ei = gi / g;
-                    const float cf = (float)c;
-                    const float sr = (float)(sn * er), si = (float)(sn * ei);  // s e
-#pragma unroll
-                    for (int t2 = 0; t2 < RPL; ++t2) {
-                        const int i = gl + G * t2;
-                        if (i < R) {
-                            const float2 xv = x[t2], yv = y[t2];
-                            // s conj(e) y = (sr*yr + si*yi, sr*yi - si*yr)
-                            xc[i] = make_float2(cf * xv.x - (sr * yv.x + si * yv.y), cf * xv.y - (sr * yv.y - si * yv.x));
-                            // s e x = (sr*xr - si*xi, sr*xi + si*xr)
-                            yc[i] = make_float2((sr * xv.x - si * xv.y) + cf * yv.x, (sr * xv.y + si * xv.x) + cf * yv.y);
-                        }
-                    }
-                    if (gl == 0) rotated = 1;
-                }
+                if (jacobi_pair<G, RPL, WITHV>(work, R, p, q, R, gl, tol2, vw, P, P) && gl == 0) rotated = 1;
             }
             __syncthreads();
         }
@@ -140,58 +241,268 @@ __global__ __launch_bounds__(256) void k_jacobi(JacobiArgs a, float2* __restrict
         if (tid == 0) rotated = 0;
         __syncthreads();
     }
-
-    // column norms in FP64 and the rotated columns, row-major R x P
-    double* sig = a.sigma + (long long)s * P;
-    for (int j = tid / G; j < P; j += ngroups) {
-        double acc = 0.0;
-        for (int i = gl; i < R; i += G) {
-            const float2 v = work[j * ldr + i];
-            acc = fma((double)v.x, (double)v.x, fma((double)v.y, (double)v.y, acc));
-        }
-        acc = group_sum<G>(acc);
-        if (gl == 0) sig[j] = sqrt(acc);
-    }
-    if (a.wr) {
-        float* wr = a.wr + (long long)s * R * P;
-        float* wi = a.wi + (long long)s * R * P;
-        for (int e = tid; e < total; e += nthr) {
-            const int i = e / P, j = e % P;
-            const float2 v = work[j * ldr + i];
-            wr[e] = v.x;
-            wi[e] = v.y;
-        }
-    }
+    store_result<G>(a, s, work, R, P, 0, 1);
+    if (WITHV) store_q(a, s, vw, P, 0, 1);
     if (a.info && tid == 0) a.info[s] = converged ? (sweep > 0 ? sweep : 1) : -sweep;
 }
 
-constexpr size_t kMaxLds = 160 * 1024 - 1024;
+// ---- block Jacobi: several workgroups per slice, one launch per block step ----
+// The P columns are cut into nb (even) blocks of width b.  A sweep is nb-1
+// block steps of the circle order over blocks; in a block step, workgroup bp
+// of a slice stages its two blocks in LDS and rotates their pairs: at block
+// step 0 every pair among its 2b columns (this covers the pairs inside each
+// block once per sweep), later only the b x b pairs across the two blocks, so
+// a sweep visits every column pair exactly once.  Per-slice rotation flags in
+// three rotating buffers tell, at the start of sweep k, whether sweep k-1 had
+// any rotation; a slice without is converged and its workgroups return.
+struct BlockArgs {
+    float2* work;   // [nslices][P][R] column-major
+    float2* v;      // [nslices][P][P] column-major (accumulated rotations) or null
+    int* rot;       // [3][nslices]
+    int* done;      // [nslices]: sweeps used, 0 while running
+    int R, P, nslices, nb, b, sweep, bstep;
+    double tol2;
+};
 
-template <int G, int RPL>
-hipError_t launch_rpl(const JacobiArgs& a, void* scratch, int R, int P, hipStream_t st)
+__device__ __forceinline__ int block_cols(int beta, int b, int P)
 {
-    const size_t lds = (size_t)R * P * sizeof(float2);
-    if (lds <= kMaxLds) {
-        auto kern = k_jacobi<G, RPL, true>;
-        static bool attr = false;
-        if (!attr) {
-            hipError_t e = hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)kMaxLds);
-            if (e != hipSuccess) return e;
-            attr = true;
+    const int lo = beta * b;
+    return lo >= P ? 0 : min(b, P - lo);
+}
+
+template <int G, int RPL, bool WITHV>
+__global__ __launch_bounds__(512) void k_jacobi_block(BlockArgs a)
+{
+    extern __shared__ float2 lds[];
+    __shared__ int rotated;
+    const int s = blockIdx.y, bp = blockIdx.x, tid = threadIdx.x;
+    const int ns = a.nslices;
+    if (bp == 0 && a.bstep == 0 && tid == 0) a.rot[((a.sweep + 1) % 3) * ns + s] = 0;
+    if (a.sweep > 0 && a.rot[((a.sweep - 1) % 3) * ns + s] == 0) {
+        if (bp == 0 && tid == 0 && a.done[s] == 0) a.done[s] = a.sweep;
+        return;
+    }
+    const int b1 = rr_col(bp, a.bstep, a.nb), b2 = rr_col(a.nb - 1 - bp, a.bstep, a.nb);
+    const int c1 = block_cols(b1, a.b, a.P), c2 = block_cols(b2, a.b, a.P);
+    const int R = a.R, L = c1 + c2;
+    const int P = a.P;
+    float2* slice = a.work + (long long)s * P * R;
+    float2* vslice = a.v + (long long)s * P * P;
+    float2* vl = lds + 2 * a.b * R;  // staged columns of V, P rows each
+    // stage the two blocks: local columns 0..c1-1 and c1..L-1
+    for (int e = tid; e < L * R; e += blockDim.x) {
+        const int lj = e / R, i = e % R;
+        const int j = lj < c1 ? b1 * a.b + lj : b2 * a.b + (lj - c1);
+        lds[e] = slice[(long long)j * R + i];
+    }
+    if (WITHV)
+        for (int e = tid; e < L * P; e += blockDim.x) {
+            const int lj = e / P, i = e % P;
+            const int j = lj < c1 ? b1 * a.b + lj : b2 * a.b + (lj - c1);
+            vl[e] = vslice[(long long)j * P + i];
         }
+    if (tid == 0) rotated = 0;
+    __syncthreads();
+    const int group = tid / G, gl = tid % G, ngroups = blockDim.x / G;
+    if (a.bstep == 0) {
+        const int np = L + (L & 1);
+        for (int step = 0; step < np - 1; ++step) {
+            for (int pair = group; pair < np / 2; pair += ngroups) {
+                const int p = rr_col(pair, step, np), q = rr_col(np - 1 - pair, step, np);
+                if (p >= L || q >= L) continue;
+                if (jacobi_pair<G, RPL, WITHV>(lds, R, p, q, R, gl, a.tol2, vl, P, P) && gl == 0) rotated = 1;
+            }
+            __syncthreads();
+        }
+    } else {
+        const int w = max(c1, c2);
+        for (int step = 0; step < w; ++step) {
+            for (int i = group; i < w; i += ngroups) {
+                const int j = (i + step) < w ? i + step : i + step - w;
+                if (i >= c1 || j >= c2) continue;
+                if (jacobi_pair<G, RPL, WITHV>(lds, R, i, c1 + j, R, gl, a.tol2, vl, P, P) && gl == 0) rotated = 1;
+            }
+            __syncthreads();
+        }
+    }
+    for (int e = tid; e < L * R; e += blockDim.x) {
+        const int lj = e / R, i = e % R;
+        const int j = lj < c1 ? b1 * a.b + lj : b2 * a.b + (lj - c1);
+        slice[(long long)j * R + i] = lds[e];
+    }
+    if (WITHV)
+        for (int e = tid; e < L * P; e += blockDim.x) {
+            const int lj = e / P, i = e % P;
+            const int j = lj < c1 ? b1 * a.b + lj : b2 * a.b + (lj - c1);
+            vslice[(long long)j * P + i] = vl[e];
+        }
+    if (rotated && tid == 0) atomicOr(&a.rot[(a.sweep % 3) * ns + s], 1);
+}
+
+__global__ __launch_bounds__(256) void k_jacobi_block_init(JacobiArgs a, float2* work, float2* v, int* rot, int* done)
+{
+    const int s = blockIdx.y;
+    const int R = a.transpose ? a.n : a.m;
+    const int P = a.transpose ? a.m : a.n;
+    const int w = blockIdx.x * blockDim.x + threadIdx.x, nw = gridDim.x * blockDim.x;
+    load_work(a, s, work + (long long)s * R * P, R, P, w, nw);
+    if (v) set_identity(v + (long long)s * P * P, P, w, nw);
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        rot[s] = 0;
+        rot[a.nslices + s] = 0;
+        rot[2 * a.nslices + s] = 0;
+        done[s] = 0;
+    }
+}
+
+template <int G>
+__global__ __launch_bounds__(256) void k_jacobi_block_finish(JacobiArgs a, const float2* work, const float2* v,
+                                                             const int* rot, const int* done, int sweeps_run)
+{
+    const int s = blockIdx.y;
+    const int R = a.transpose ? a.n : a.m;
+    const int P = a.transpose ? a.m : a.n;
+    store_result<G>(a, s, work + (long long)s * R * P, R, P, blockIdx.x, gridDim.x);
+    if (v) store_q(a, s, v + (long long)s * P * P, P, blockIdx.x, gridDim.x);
+    if (a.info && blockIdx.x == 0 && threadIdx.x == 0) {
+        int d = done[s];
+        if (d == 0 && sweeps_run > 0 && rot[((sweeps_run - 1) % 3) * a.nslices + s] == 0) d = sweeps_run;
+        a.info[s] = d > 0 ? d : -sweeps_run;
+    }
+}
+
+constexpr size_t kMaxLds = 160 * 1024 - 1024;
+constexpr size_t kBlockLds = 80 * 1024;  // two workgroups per CU
+
+template <class K>
+hipError_t allow_lds(K kern, size_t bytes)
+{
+    if (bytes <= 64 * 1024) return hipSuccess;
+    return hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)kMaxLds);
+}
+
+// bytes of one slice's work matrix (R x P) and, with V, its P x P rotations
+size_t whole_bytes(int R, int P, bool withv)
+{
+    return ((size_t)R * P + (withv ? (size_t)P * P : 0)) * sizeof(float2);
+}
+
+template <int G, int RPL, bool WITHV>
+hipError_t launch_whole(const JacobiArgs& a, void* scratch, int R, int P, hipStream_t st)
+{
+    const size_t lds = whole_bytes(R, P, WITHV);
+    if (lds <= kMaxLds) {
+        auto kern = k_jacobi<G, RPL, true, WITHV>;
+        hipError_t e = allow_lds(kern, lds);
+        if (e != hipSuccess) return e;
         kern<<<a.nslices, 256, lds, st>>>(a, nullptr);
     } else {
-        k_jacobi<G, RPL, false><<<a.nslices, 256, 0, st>>>(a, static_cast<float2*>(scratch));
+        k_jacobi<G, RPL, false, WITHV><<<a.nslices, 256, 0, st>>>(a, static_cast<float2*>(scratch));
     }
     return hipGetLastError();
 }
 
+// block width: the two staged blocks (work columns, plus V columns when
+// accumulating) fit kBlockLds, at most 32 pairs per step (or the tuned width)
+int block_width(int R, int P, bool withv)
+{
+    const size_t col = (size_t)(R + (withv ? P : 0)) * sizeof(float2);
+    const int bmax = (int)(kMaxLds / (2 * col));
+    int b = (int)(kBlockLds / (2 * col));
+    if (b > 32) b = 32;
+    const int tuned = param(TP_PARAM_JACOBI_BLOCK);
+    if (tuned > 0) b = tuned < bmax ? tuned : bmax;
+    if (b < 1) b = 1;
+    const int nb = (P + b - 1) / b;
+    if (nb < 2) return 0;
+    return b;
+}
+
+struct BlockPlan {
+    int b, nb;
+    size_t work_bytes, v_bytes, flag_bytes;
+};
+
+BlockPlan block_plan(int R, int P, int nslices, bool withv)
+{
+    BlockPlan pl{};
+    pl.b = block_width(R, P, withv);
+    if (pl.b == 0) return pl;
+    pl.nb = (P + pl.b - 1) / pl.b;
+    pl.nb += pl.nb & 1;
+    pl.work_bytes = align_up((size_t)R * P * nslices * sizeof(float2));
+    pl.v_bytes = withv ? align_up((size_t)P * P * nslices * sizeof(float2)) : 0;
+    pl.flag_bytes = align_up(4 * (size_t)nslices * sizeof(int));
+    return pl;
+}
+
+template <int G, int RPL, bool WITHV>
+hipError_t launch_blocked(const JacobiArgs& a, void* scratch, int R, int P, const BlockPlan& pl, hipStream_t st)
+{
+    char* base = static_cast<char*>(scratch);
+    float2* work = reinterpret_cast<float2*>(base);
+    float2* v = WITHV ? reinterpret_cast<float2*>(base + pl.work_bytes) : nullptr;
+    int* rot = reinterpret_cast<int*>(base + pl.work_bytes + pl.v_bytes);
+    int* done = rot + 3 * a.nslices;
+    const size_t per = (size_t)R * P;
+    const int chunks = (int)(per / (256 * 8) + 1) < 64 ? (int)(per / (256 * 8) + 1) : 64;
+    k_jacobi_block_init<<<dim3(chunks, a.nslices), 256, 0, st>>>(a, work, v, rot, done);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    BlockArgs b{work, v, rot, done, R, P, a.nslices, pl.nb, pl.b, 0, 0, a.tol * a.tol};
+    const int threads = min(512, ((pl.b * G + 63) / 64) * 64);
+    const size_t lds = (size_t)2 * pl.b * (R + (WITHV ? P : 0)) * sizeof(float2);
+    auto kern = k_jacobi_block<G, RPL, WITHV>;
+    e = allow_lds(kern, lds);
+    if (e != hipSuccess) return e;
+    dim3 grid(pl.nb / 2, a.nslices);
+    for (int sw = 0; sw < a.max_sweeps; ++sw) {
+        b.sweep = sw;
+        for (int bs = 0; bs < pl.nb - 1; ++bs) {
+            b.bstep = bs;
+            kern<<<grid, threads, lds, st>>>(b);
+            e = hipGetLastError();
+            if (e != hipSuccess) return e;
+        }
+    }
+    k_jacobi_block_finish<G><<<dim3(chunks, a.nslices), 256, 0, st>>>(a, work, v, rot, done, a.max_sweeps);
+    return hipGetLastError();
+}
+
+// slices too large for LDS, or too few of them to fill the GPU, go blocked
+bool use_blocked(int R, int P, int nslices, bool withv)
+{
+    if (block_width(R, P, withv) == 0) return false;
+    if (whole_bytes(R, P, withv) > kMaxLds) return true;
+    const int mode = param(TP_PARAM_JACOBI_MODE);
+    if (mode == 1) return false;
+    if (mode == 2) return true;
+    return nslices < param(TP_PARAM_JACOBI_BLOCKED_BELOW) && P >= 64;
+}
+
+template <int G, int RPL>
+hipError_t launch_rpl(const JacobiArgs& a, void* scratch, int R, int P, hipStream_t st)
+{
+    const bool withv = a.qout != nullptr;
+    if (use_blocked(R, P, a.nslices, withv)) {
+        const BlockPlan pl = block_plan(R, P, a.nslices, withv);
+        return withv ? launch_blocked<G, RPL, true>(a, scratch, R, P, pl, st)
+                     : launch_blocked<G, RPL, false>(a, scratch, R, P, pl, st);
+    }
+    return withv ? launch_whole<G, RPL, true>(a, scratch, R, P, st) : launch_whole<G, RPL, false>(a, scratch, R, P, st);
+}
+
 }  // namespace
 
-size_t jacobi_scratch_bytes(int m, int n, int nslices)
+size_t jacobi_scratch_bytes(int m, int n, int nslices, bool withv)
 {
-    const size_t lds = (size_t)m * n * sizeof(float2);
-    return lds <= kMaxLds ? 0 : lds * nslices;
+    const int R = m >= n ? m : n, P = m >= n ? n : m;
+    if (use_blocked(R, P, nslices, withv)) {
+        const BlockPlan pl = block_plan(R, P, nslices, withv);
+        return pl.work_bytes + pl.v_bytes + pl.flag_bytes;
+    }
+    const size_t b = whole_bytes(R, P, withv);
+    return b <= kMaxLds ? 0 : b * nslices;
 }
 
 hipError_t launch_jacobi(const JacobiArgs& a, void* scratch, size_t scratch_bytes, hipStream_t st)
@@ -199,7 +510,7 @@ hipError_t launch_jacobi(const JacobiArgs& a, void* scratch, size_t scratch_byte
     if (a.nslices <= 0) return hipSuccess;
     const int R = a.transpose ? a.n : a.m;
     const int P = a.transpose ? a.m : a.n;
-    if (jacobi_scratch_bytes(a.m, a.n, a.nslices) > scratch_bytes) return hipErrorInvalidValue;
+    if (jacobi_scratch_bytes(a.m, a.n, a.nslices, a.qout != nullptr) > scratch_bytes) return hipErrorInvalidValue;
     if (R <= 32) return launch_rpl<16, 2>(a, scratch, R, P, st);
     if (R <= 64) return launch_rpl<16, 4>(a, scratch, R, P, st);
     if (R <= 128) return launch_rpl<16, 8>(a, scratch, R, P, st);
@@ -277,6 +588,163 @@ hipError_t launch_shrink(float* wr, float* wi, const double* sigma, int* keep, i
 hipError_t launch_tnn_reduce(const double* sigma, int nslices, int P, int n3, double* out, hipStream_t st)
 {
     k_tnn_reduce<<<1, 256, 0, st>>>(sigma, nslices, P, n3, out);
+    return hipGetLastError();
+}
+
+}  // namespace tp
+
+// ------------------------------------------------------------- t-SVD out --
+namespace tp {
+namespace {
+
+// Per slice (one workgroup): sort the singular values in decreasing order
+// (ties by index), and write the full bases and the diagonal of S^(k):
+//   L (R x R): column r = w_perm(r) / sigma_perm(r) for sigma > 0, the rest
+//              completed to an orthonormal basis: each missing column is the
+//              unit vector e_c with the largest component outside the span so
+//              far, orthogonalised twice (classical Gram-Schmidt) and
+//              normalised;
+//   Q (P x P): column r = v_perm(r);
+//   S (m x n): S(r, r) = sigma_perm(r), zero elsewhere.
+// All outputs are row-major planar slices.
+__global__ __launch_bounds__(256) void k_tsvd_finish(const float2* __restrict__ cols, const double* __restrict__ sigma,
+                                                     const float2* __restrict__ q, float* __restrict__ lr,
+                                                     float* __restrict__ li, float* __restrict__ qr,
+                                                     float* __restrict__ qi, float* __restrict__ sr,
+                                                     float* __restrict__ si, int R, int P, int m, int n)
+{
+    extern __shared__ char smem[];
+    int* perm = reinterpret_cast<int*>(smem);                               // P
+    double2* w = reinterpret_cast<double2*>(smem + align_up(P * sizeof(int)));  // R
+    double2* coef = w + R;                                                  // R
+    __shared__ double red[256];
+    __shared__ int redi[256];
+    const int s = blockIdx.x, tid = threadIdx.x, nt = blockDim.x;
+    const double* sg = sigma + (long long)s * P;
+    const float2* cs = cols + (long long)s * R * P;
+    const float2* qs = q + (long long)s * P * P;
+    float* Lr = lr + (long long)s * R * R;
+    float* Li = li + (long long)s * R * R;
+
+    for (int j = tid; j < P; j += nt) {
+        int rank = 0;
+        for (int i = 0; i < P; ++i) rank += (sg[i] > sg[j] || (sg[i] == sg[j] && i < j)) ? 1 : 0;
+        perm[rank] = j;
+    }
+    __syncthreads();
+    // Q columns and S diagonal
+    for (int e = tid; e < P * P; e += nt) {
+        const int i = e / P, r = e % P;
+        const float2 v = qs[(long long)perm[r] * P + i];
+        qr[(long long)s * P * P + e] = v.x;
+        qi[(long long)s * P * P + e] = v.y;
+    }
+    for (int e = tid; e < m * n; e += nt) {
+        const int i = e / n, j = e % n;
+        sr[(long long)s * m * n + e] = (i == j) ? (float)sg[perm[i]] : 0.0f;
+        si[(long long)s * m * n + e] = 0.0f;
+    }
+    // leading columns of L
+    int rank = 0;
+    for (int r = 0; r < P; ++r) rank += sg[perm[r]] > 0.0 ? 1 : 0;
+    for (int e = tid; e < R * R; e += nt) {
+        const int i = e / R, r = e % R;
+        float vr = 0.0f, vi = 0.0f;
+        if (r < rank) {
+            const float2 v = cs[(long long)perm[r] * R + i];
+            const double inv = 1.0 / sg[perm[r]];
+            vr = (float)(v.x * inv);
+            vi = (float)(v.y * inv);
+        }
+        Lr[e] = vr;
+        Li[e] = vi;
+    }
+    __syncthreads();
+    // completion
+    for (int r = rank; r < R; ++r) {
+        double best = -1.0;
+        int bi = 0;
+        for (int c = tid; c < R; c += nt) {
+            double in = 0.0;
+            for (int qq = 0; qq < r; ++qq) {
+                const double a = Lr[(long long)c * R + qq], b = Li[(long long)c * R + qq];
+                in += a * a + b * b;
+            }
+            if (1.0 - in > best) {
+                best = 1.0 - in;
+                bi = c;
+            }
+        }
+        red[tid] = best;
+        redi[tid] = bi;
+        __syncthreads();
+        for (int h = nt / 2; h > 0; h >>= 1) {
+            if (tid < h) {
+                const double o = red[tid + h];
+                const int oi = redi[tid + h];
+                if (o > red[tid] || (o == red[tid] && oi < redi[tid])) {
+                    red[tid] = o;
+                    redi[tid] = oi;
+                }
+            }
+            __syncthreads();
+        }
+        const int c = redi[0];
+        for (int i = tid; i < R; i += nt) w[i] = make_double2(i == c ? 1.0 : 0.0, 0.0);
+        __syncthreads();
+        for (int pass = 0; pass < 2; ++pass) {
+            for (int qq = tid; qq < r; qq += nt) {  // coef_q = L(:,q)^* w
+                double ar = 0.0, ai = 0.0;
+                for (int i = 0; i < R; ++i) {
+                    const double lr_ = Lr[(long long)i * R + qq], li_ = Li[(long long)i * R + qq];
+                    ar += lr_ * w[i].x + li_ * w[i].y;
+                    ai += lr_ * w[i].y - li_ * w[i].x;
+                }
+                coef[qq] = make_double2(ar, ai);
+            }
+            __syncthreads();
+            for (int i = tid; i < R; i += nt) {  // w -= sum_q coef_q L(:,q)
+                double ar = w[i].x, ai = w[i].y;
+                for (int qq = 0; qq < r; ++qq) {
+                    const double lr_ = Lr[(long long)i * R + qq], li_ = Li[(long long)i * R + qq];
+                    ar -= coef[qq].x * lr_ - coef[qq].y * li_;
+                    ai -= coef[qq].x * li_ + coef[qq].y * lr_;
+                }
+                w[i] = make_double2(ar, ai);
+            }
+            __syncthreads();
+        }
+        double nrm = 0.0;
+        for (int i = tid; i < R; i += nt) nrm += w[i].x * w[i].x + w[i].y * w[i].y;
+        red[tid] = nrm;
+        __syncthreads();
+        for (int h = nt / 2; h > 0; h >>= 1) {
+            if (tid < h) red[tid] += red[tid + h];
+            __syncthreads();
+        }
+        const double inv = 1.0 / sqrt(red[0]);
+        for (int i = tid; i < R; i += nt) {
+            Lr[(long long)i * R + r] = (float)(w[i].x * inv);
+            Li[(long long)i * R + r] = (float)(w[i].y * inv);
+        }
+        __syncthreads();
+    }
+}
+
+}  // namespace
+
+size_t tsvd_finish_lds(int R, int P) { return align_up(P * sizeof(int)) + 2 * (size_t)R * sizeof(double2); }
+
+hipError_t launch_tsvd_finish(const float2* cols, const double* sigma, const float2* q, Planes L, Planes Q, Planes S,
+                              int R, int P, int m, int n, int nslices, hipStream_t st)
+{
+    const size_t lds = tsvd_finish_lds(R, P);
+    if (lds > 64 * 1024) {
+        hipError_t e = hipFuncSetAttribute((const void*)k_tsvd_finish, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                           160 * 1024 - 1024);
+        if (e != hipSuccess) return e;
+    }
+    k_tsvd_finish<<<nslices, 256, lds, st>>>(cols, sigma, q, L.re, L.im, Q.re, Q.im, S.re, S.im, R, P, m, n);
     return hipGetLastError();
 }
 

@@ -1,6 +1,6 @@
-// Stage timing: HIP events recorded around every kernel the entry points
-// enqueue, while enabled.  Used by the benchmark to time each kernel on the
-// stream it runs on.  Events are pooled; nothing here runs on the device.
+// Host-side runtime services: tunable launch parameters and stage timing
+// (HIP events recorded around every kernel the entry points enqueue, while
+// enabled).  Nothing here runs on the device.
 #include <mutex>
 #include <vector>
 
@@ -31,7 +31,7 @@ hipEvent_t take_event()
     return e;
 }
 
-const char* const kNames[] = {"rfft", "irfft", "cgemm", "jacobi", "shrink", "tnn_reduce"};
+const char* const kNames[] = {"rfft", "irfft", "cgemm", "jacobi", "shrink", "tnn_reduce", "tsvd_finish"};
 
 }  // namespace
 
@@ -53,9 +53,34 @@ TraceScope::~TraceScope()
     g_recs.push_back(Rec{static_cast<hipEvent_t>(start_), b, id_});
 }
 
+namespace {
+int g_params[TP_PARAM_COUNT] = {0, 0, 0, 0, 0};
+const int kDefaults[TP_PARAM_COUNT] = {0, 0, 128, 30, 0};
+}  // namespace
+
+int param(int key)
+{
+    if (key < 0 || key >= TP_PARAM_COUNT) return 0;
+    const int v = __atomic_load_n(&g_params[key], __ATOMIC_RELAXED);
+    return v > 0 ? v : kDefaults[key];
+}
+
 }  // namespace tp
 
 extern "C" {
+
+int tp_set_param(int key, int value)
+{
+    if (key < 0 || key >= TP_PARAM_COUNT || value < 0) return TP_ERR_ARG;
+    __atomic_store_n(&tp::g_params[key], value, __ATOMIC_RELAXED);
+    return TP_OK;
+}
+
+int tp_get_param(int key)
+{
+    if (key < 0 || key >= TP_PARAM_COUNT) return -1;
+    return tp::param(key);
+}
 
 int tp_trace_enable(int enable)
 {

@@ -11,7 +11,7 @@ namespace tp {
 
 constexpr size_t kAlign = 256;
 
-inline size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
+__host__ __device__ inline size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
 
 // number of Fourier slices that get a dense operation: ceil((n3+1)/2) = floor(n3/2)+1
 inline int half_slices(int n3) { return n3 / 2 + 1; }
@@ -87,11 +87,17 @@ struct JacobiArgs {
     int max_sweeps;
     int transpose;    // work on Y^* (used when m < n)
     double tol;       // rotate a pair when |x^* y| > tol ||x|| ||y||
+    float2* cols;     // optional: rotated columns, column-major R x P per slice
+    float2* qout;     // optional: accumulated rotations V, column-major P x P per slice
 };
 hipError_t launch_jacobi(const JacobiArgs& a, void* scratch, size_t scratch_bytes, hipStream_t s);
-size_t jacobi_scratch_bytes(int m, int n, int nslices);
+size_t jacobi_scratch_bytes(int m, int n, int nslices, bool withv);
 // Jacobi convergence threshold for an R-row work matrix of FP32 data
 inline double jacobi_tol(int rows) { return __builtin_sqrt((double)(rows > 4 ? rows : 4)) * 0x1p-23; }
+
+// t-SVD outputs from the Jacobi results: sorted bases L (R x R, completed), Q (P x P), diagonal S (m x n)
+hipError_t launch_tsvd_finish(const float2* cols, const double* sigma, const float2* q, Planes L, Planes Q, Planes S,
+                              int R, int P, int m, int n, int nslices, hipStream_t s);
 
 // columns w_j of each slice scaled by sqrt((1 - tau/sigma_j)_+) / sigma_j; keep = #{sigma_j > tau}
 hipError_t launch_shrink(float* wr, float* wi, const double* sigma, int* keep, int R, int P, int nslices, double tau,
@@ -99,8 +105,12 @@ hipError_t launch_shrink(float* wr, float* wi, const double* sigma, int* keep, i
 // (1/n3) sum over all n3 slices of the singular values, from the half spectrum
 hipError_t launch_tnn_reduce(const double* sigma, int nslices, int P, int n3, double* out, hipStream_t s);
 
+// ------------------------------------------------------------ tunables ----
+// current value of a TP_PARAM_* setting (tp_set_param), default if unset
+int param(int key);
+
 // ------------------------------------------------------------- tracing ----
-enum KernelId { K_RFFT = 0, K_IRFFT = 1, K_CGEMM = 2, K_JACOBI = 3, K_SHRINK = 4, K_TNN_REDUCE = 5 };
+enum KernelId { K_RFFT = 0, K_IRFFT = 1, K_CGEMM = 2, K_JACOBI = 3, K_SHRINK = 4, K_TNN_REDUCE = 5, K_TSVD_FINISH = 6 };
 
 // Records HIP events around the launches in its scope while tracing is on.
 class TraceScope {
