@@ -51,6 +51,17 @@ def _load():
         "or_prox_tnn": (_I, [_D, _I, _I, _I, ctypes.c_double, _D]),
         "or_svt_real": (_I, [_D, _I, _I, ctypes.c_double, _D]),
     }
+    U32 = ctypes.POINTER(ctypes.c_uint)
+    IP = ctypes.POINTER(ctypes.c_int)
+    sig.update({
+        "or_philox4x32_10": (None, [U32, U32, U32]),
+        "or_sketch_matrix": (None, [_I, _I, _I, _I, ctypes.c_ulonglong, _D]),
+        "or_cholqr2": (_I, [_D, _I, _I, _I, _D]),
+        "or_prox_tnn_rsvd": (_I, [_D, _I, _I, _I, ctypes.c_double, IP, _I, _I, _I, ctypes.c_ulonglong, _D, IP, IP]),
+        "or_mlp_param_count": (_I, [_I, _I]),
+        "or_mlp_forward": (None, [_D, _I, _I, _D, _I, _D]),
+        "or_mlp_loss_grad": (ctypes.c_double, [_D, _I, _I, _D, _D, _I, ctypes.c_double, _D]),
+    })
     for name, (res, args) in sig.items():
         f = getattr(lib, name)
         f.restype = res
@@ -221,3 +232,68 @@ def svt_real(M, tau):
     out = np.empty_like(M)
     _load().or_svt_real(_dp(M), m, n, float(tau), _dp(out))
     return out
+
+
+# ---------------------------------------------------------- learned rank --
+def philox4x32_10(ctr, key):
+    """Philox4x32-10 (Salmon et al., SC'11): 4 counter words, 2 key words -> 4 words."""
+    c = (ctypes.c_uint * 4)(*[int(v) & 0xFFFFFFFF for v in ctr])
+    k = (ctypes.c_uint * 2)(*[int(v) & 0xFFFFFFFF for v in key])
+    o = (ctypes.c_uint * 4)()
+    _load().or_philox4x32_10(c, k, o)
+    return [int(v) for v in o]
+
+
+def sketch_matrix(n, l, slice_index, real, seed):
+    Om = np.empty((n, l), dtype=np.complex128)
+    _load().or_sketch_matrix(n, l, slice_index, int(bool(real)), int(seed), _dp(Om))
+    return Om
+
+
+def cholqr2(Y, lact=None):
+    """CholeskyQR2 of Y (m x l): returns (Q, R, status)."""
+    Q = _cplx(Y).copy()
+    m, l = Q.shape
+    R = np.empty((l, l), dtype=np.complex128)
+    st = _load().or_cholqr2(_dp(Q), m, l, l if lact is None else int(lact), _dp(R))
+    return Q, R, st
+
+
+def prox_tnn_rsvd(Y, tau, kpred, oversample=10, power=2, lfull=None, seed=0):
+    """Randomized-SVD prox (see tp_oracle.h): returns (X, fallback, rank)."""
+    Y = _real(Y)
+    n1, n2, n3 = Y.shape
+    h = n3 // 2 + 1
+    kp = np.ascontiguousarray(kpred, dtype=np.int32)
+    assert kp.shape == (h,)
+    X = np.empty_like(Y)
+    fb = np.zeros(h, dtype=np.int32)
+    rk = np.zeros(h, dtype=np.int32)
+    IP = ctypes.POINTER(ctypes.c_int)
+    if lfull is None:
+        lfull = min(n1, n2) + 1
+    st = _load().or_prox_tnn_rsvd(_dp(Y), n1, n2, n3, float(tau), kp.ctypes.data_as(IP), int(oversample),
+                                  int(power), int(lfull), int(seed), _dp(X), fb.ctypes.data_as(IP),
+                                  rk.ctypes.data_as(IP))
+    if st < 0:
+        raise ValueError("tau must be >= 0")
+    return X, fb, rk
+
+
+def mlp_param_count(d, h):
+    return int(_load().or_mlp_param_count(d, h))
+
+
+def mlp_forward(params, X, d, h):
+    X = _real(X)
+    y = np.empty(X.shape[0])
+    _load().or_mlp_forward(_dp(_real(params)), d, h, _dp(X), X.shape[0], _dp(y))
+    return y
+
+
+def mlp_loss_grad(params, X, t, d, h, under=4.0):
+    params = _real(params)
+    X, t = _real(X), _real(t)
+    g = np.empty_like(params)
+    loss = _load().or_mlp_loss_grad(_dp(params), d, h, _dp(X), _dp(t), X.shape[0], float(under), _dp(g))
+    return float(loss), g

@@ -82,3 +82,57 @@ int or_svt_real(const double* M, int m, int n, double tau, double* out);
 }
 #endif
 #endif
+
+#ifndef TP_ORACLE_LEARNED_H
+#define TP_ORACLE_LEARNED_H
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* Philox4x32-10 counter-based generator (Salmon, Moraes, Dror, Shaw, SC'11):
+ * ten rounds of the 4x32 Philox S-box on counter ctr[4] with key key[2]. */
+void or_philox4x32_10(const unsigned int ctr[4], const unsigned int key[2], unsigned int out[4]);
+
+/* The Gaussian test matrix of the randomized range finder for slice `slice`:
+ * entry (i, j) (i < n rows, j < l columns) comes from Philox on counter
+ * {i, j, slice, 0} with key {seed low, seed high}; the first two outputs x0, x1
+ * give u = (x + 0.5) 2^-32 and by Box-Muller z0 = sqrt(-2 ln u0) cos(2 pi u1),
+ * z1 = sqrt(-2 ln u0) sin(2 pi u1).  Complex slices: (z0 + i z1)/sqrt(2);
+ * real slices: z0.  Values are rounded to float, then widened.  Om is n x l
+ * row-major complex. */
+void or_sketch_matrix(int n, int l, int slice, int real, unsigned long long seed, or_cplx* Om);
+
+/* CholeskyQR2 of the m x l complex matrix Y (row-major, in place -> Q), with
+ * R (l x l upper triangular, row-major) the product of both factors.  Columns
+ * j >= lact are zero on input and output (R = identity there).  A shift
+ * 1e-13 * trace(G)/lact is added to the Gram diagonal before the first
+ * Cholesky (the second Gram is close to the identity and is not shifted). */
+int or_cholqr2(or_cplx* Y, int m, int l, int lact, or_cplx* R);
+
+/* Prox of the TNN (Theorem 2.3) with each leading Fourier slice's SVT done
+ * on a randomized range (Halko, Martinsson, Tropp 2011): for slice k with
+ * predicted count kpred[k], l = min(kpred[k] + oversample, min(n1, n2));
+ * Y = Abar Om; `power` times {Z = Abar^* Q, Y = Abar Z}, every product
+ * re-orthonormalised by CholeskyQR2; Bh = Abar^* Q; (Q2, R2) = CholeskyQR2(Bh);
+ * SVD of R2^*; W = Q T Q2^* with T = U_r (S - tau)_+ V_r^*.  The slice falls
+ * back to the full SVD (Algorithm 3) when l >= lfull or when the (kpred+1)-th
+ * singular value of R2^* is not below tau.  fallback[k] (may be NULL)
+ * receives 1 for a fallback, rank[k] (may be NULL) the number of singular
+ * values above tau that were used. */
+int or_prox_tnn_rsvd(const double* Y, int n1, int n2, int n3, double tau, const int* kpred, int oversample,
+                     int power, int lfull, unsigned long long seed, double* X, int* fallback, int* rank);
+
+/* MLP with ReLU hidden layers: sizes d -> h -> h -> h -> 1.  Parameters packed
+ * as W1 (h x d, row-major), b1 (h), W2 (h x h), b2, W3 (h x h), b3, w4 (h), b4.
+ * or_mlp_forward: y[s] for the N rows of X (N x d).
+ * or_mlp_loss_grad: loss = mean_s c(e_s) e_s^2 with e_s = y_s - t_s and
+ * c(e) = 1 for e >= 0, `under` for e < 0; grad receives d loss / d params. */
+int or_mlp_param_count(int d, int h);
+void or_mlp_forward(const double* params, int d, int h, const double* X, int N, double* y);
+double or_mlp_loss_grad(const double* params, int d, int h, const double* X, const double* t, int N,
+                        double under, double* grad);
+
+#ifdef __cplusplus
+}
+#endif
+#endif
