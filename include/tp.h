@@ -106,6 +106,73 @@ int tp_prox_tnn(const float* Y, float* X, int n1, int n2, int n3, float tau, int
                 void* workspace, size_t workspace_bytes, void* stream);
 
 /*
+ * Learned-rank prox_tnn: the same operator as tp_prox_tnn (Theorem 2.3), with
+ * each leading Fourier slice's SVT computed on a randomized range whose width
+ * is predicted per slice.  Per slice k: features of the slice (below) go
+ * through the MLP (or fixed_rank is used) to give kpred, the predicted number
+ * of singular values above tau; l = min(kpred + oversample, min(n1, n2));
+ * Y = Ybar^(k) Om with the Gaussian sketch Om (Philox4x32-10 on counter
+ * {row, column, slice, 0}, key = seed; Box-Muller; real on the real slices);
+ * power_iters times {Z = Ybar^* Q, Y = Ybar Z}, every product re-orthonormalised
+ * by CholeskyQR2 (Gram, Cholesky and inverse in FP64); Bh = Ybar^* Q =
+ * Q2 R2 (CholeskyQR2); one-sided Jacobi SVD of R2^* = U_r S V_r^*; and
+ * W^(k) = Q U_r (S - tau)_+ V_r^* Q2^*.  A slice falls back to the full SVD
+ * path of tp_prox_tnn when l > max_rank, or when the check sigma_(kpred+1) <
+ * tau fails on the singular values of R2^*.  With l = min(n1,n2) or an exact
+ * rank <= l the result equals tp_prox_tnn's up to rounding.
+ *   opts       required (see tp_learned_opts); rank, fallback, info optional
+ *              device int[floor(n3/2)+1]: the number of singular values
+ *              above tau used, 1 for a fallback slice, and the Jacobi sweeps of
+ *              the fallback slices (0 for the others).
+ * Unlike the other entry points this call waits once for the stream (it reads
+ * which slices fell back before enqueueing their full SVD).
+ * Features (TP_MLP_INPUTS = 8, FP32, per slice): log(tau / rms sigma) with
+ * rms sigma = ||Ybar^(k)||_F / sqrt(min(n1,n2)); log(max column norm / tau);
+ * prev_rank/min(n1,n2) and 1 when prev_rank is given (else 0, 0);
+ * k/(n3/2); 1 for a real slice; log(min(n1,n2))/8; log(max(n1,n2)/min(n1,n2));
+ * each clamped to [-30, 30].  The MLP maps them to y and
+ * kpred = round(expm1(y * log1p(min(n1,n2)))) clipped to [0, min(n1,n2)].
+ */
+#define TP_MLP_INPUTS 8
+#define TP_MLP_HIDDEN 64
+typedef struct tp_learned_opts {
+    const float* mlp;          /* device MLP parameters (tp_mlp_param_count floats) or NULL */
+    int fixed_rank;            /* kpred of every slice when mlp is NULL */
+    const int* prev_rank;      /* device int[floor(n3/2)+1] or NULL (a feature) */
+    int oversample;            /* extra sketch columns (the paper setting: 10) */
+    int power_iters;           /* subspace iterations (2) */
+    int max_rank;              /* l_max <= 64: wider slices use the full SVD */
+    unsigned long long seed;   /* sketch seed */
+} tp_learned_opts;
+size_t tp_prox_tnn_learned_workspace_size(int n1, int n2, int n3, int max_rank);
+int tp_prox_tnn_learned(const float* Y, float* X, int n1, int n2, int n3, float tau,
+                        const tp_learned_opts* opts, int* rank, int* fallback, int* info,
+                        void* workspace, size_t workspace_bytes, void* stream);
+/* the per-slice features above, feats is device float[(floor(n3/2)+1) * 8] */
+size_t tp_slice_features_workspace_size(int n1, int n2, int n3);
+int tp_slice_features(const float* Y, int n1, int n2, int n3, float tau, const int* prev_rank,
+                      float* feats, void* workspace, size_t workspace_bytes, void* stream);
+
+/*
+ * Rank-predicting MLP: TP_MLP_INPUTS -> 64 -> 64 -> 64 -> 1, ReLU hidden
+ * layers.  Parameters (device float, tp_mlp_param_count() of them) are packed
+ * W1 (64 x 8, row-major), b1 (64), W2 (64 x 64), b2, W3 (64 x 64), b3,
+ * w4 (64), b4 (1).  x is batch x 8 row-major, y and t are batch floats.
+ * tp_mlp_loss_grad: loss = mean_s c(e_s) e_s^2 with e_s = y_s - t_s and
+ * c(e) = 1 for e >= 0, `under` for e < 0 (under-prediction costs a fallback);
+ * grad receives d loss / d params and loss (device float) its value; the sums
+ * over the batch run in index order (bitwise reproducible).
+ * tp_mlp_adam: Adam step number `step` (>= 1) on params with moments m, v.
+ */
+int tp_mlp_param_count(void);
+int tp_mlp_forward(const float* params, const float* x, float* y, int batch, void* stream);
+size_t tp_mlp_train_workspace_size(int batch);
+int tp_mlp_loss_grad(const float* params, const float* x, const float* t, int batch, float under,
+                     float* grad, float* loss, void* workspace, size_t workspace_bytes, void* stream);
+int tp_mlp_adam(float* params, const float* grad, float* m, float* v, int step, float lr, float beta1,
+                float beta2, float eps, void* stream);
+
+/*
  * Tensor nuclear norm (Definition 2.9 with eq (14)):
  *   ||A||_* = sum_i S(i,i,1) = (1/n3) sum_k sum_i sigma_i(Abar^(k)),
  * summed over all n3 slices through the conjugate symmetry of eq (8) (the
@@ -153,7 +220,8 @@ int tp_get_param(int key);
  * `capacity` launches; it returns the number of launches recorded since the
  * last collect (or a negative tp_status) and forgets them.
  * Kernel ids: 0 rfft, 1 irfft, 2 cgemm, 3 jacobi, 4 shrink, 5 tnn_reduce,
- * 6 tsvd_finish.
+ * 6 tsvd_finish, 7 features, 8 predict, 9 sketch, 10 cholqr, 11 rsvd_check,
+ * 12 gather, 13 mlp.
  */
 int tp_trace_enable(int enable);
 int tp_trace_collect(int* kernel_ids, float* ms, int capacity);

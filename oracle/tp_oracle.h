@@ -122,6 +122,13 @@ int or_cholqr2(or_cplx* Y, int m, int l, int lact, or_cplx* R);
 int or_prox_tnn_rsvd(const double* Y, int n1, int n2, int n3, double tau, const int* kpred, int oversample,
                      int power, int lfull, unsigned long long seed, double* X, int* fallback, int* rank);
 
+/* Per-slice features of the rank predictor, for the floor(n3/2)+1 leading
+ * Fourier slices (row k of feats, 8 values): log(tau / (||Ybar^(k)||_F /
+ * sqrt(p))), log(max column norm / tau), prev[k]/p and 1 (0, 0 without prev),
+ * k/(n3/2), 1 for a real slice, log(p)/8, log(max(n1,n2)/p); p = min(n1,n2);
+ * the first two clamped to [-30, 30]. */
+void or_slice_features(const double* Y, int n1, int n2, int n3, double tau, const int* prev, double* feats);
+
 /* MLP with ReLU hidden layers: sizes d -> h -> h -> h -> 1.  Parameters packed
  * as W1 (h x d, row-major), b1 (h), W2 (h x h), b2, W3 (h x h), b3, w4 (h), b4.
  * or_mlp_forward: y[s] for the N rows of X (N x d).

@@ -393,3 +393,38 @@ double or_mlp_loss_grad(const double* params, int d, int h, const double* X, con
     free(z);
     return loss / N;
 }
+
+/* ---------------------------------------------------------- features -- */
+void or_slice_features(const double* Y, int n1, int n2, int n3, double tau, const int* prev, double* feats)
+{
+    const int h = n3 / 2 + 1, p = n1 < n2 ? n1 : n2;
+    const i64 tot = (i64)n1 * n2 * n3;
+    or_cplx* zy = (or_cplx*)xmalloc(sizeof(or_cplx) * (size_t)tot);
+    or_cplx* Yb = (or_cplx*)xmalloc(sizeof(or_cplx) * (size_t)tot);
+    for (i64 e = 0; e < tot; ++e) zy[e] = Y[e];
+    or_dft3(zy, n1, n2, n3, 0, Yb);
+    for (int k = 0; k < h; ++k) {
+        double nrm2 = 0.0, cmax = 0.0;
+        for (int j = 0; j < n2; ++j) {
+            double c = 0.0;
+            for (int i = 0; i < n1; ++i) {
+                const or_cplx v = Yb[((i64)i * n2 + j) * n3 + k];
+                c += creal(v) * creal(v) + cimag(v) * cimag(v);
+            }
+            nrm2 += c;
+            cmax = fmax(cmax, c);
+        }
+        const double t2 = tau * tau;
+        double* f = feats + (i64)k * 8;
+        f[0] = (nrm2 > 0.0 && t2 > 0.0) ? fmin(30.0, fmax(-30.0, 0.5 * log(t2 * p / nrm2))) : -30.0;
+        f[1] = (cmax > 0.0 && t2 > 0.0) ? fmin(30.0, fmax(-30.0, 0.5 * log(cmax / t2))) : (cmax > 0.0 ? 30.0 : -30.0);
+        f[2] = prev ? (double)prev[k] / p : 0.0;
+        f[3] = prev ? 1.0 : 0.0;
+        f[4] = n3 > 1 ? (double)k / (double)(n3 / 2 > 0 ? n3 / 2 : 1) : 0.0;
+        f[5] = (k == 0 || (n3 % 2 == 0 && k == n3 / 2)) ? 1.0 : 0.0;
+        f[6] = log((double)p) / 8.0;
+        f[7] = log((double)(n1 > n2 ? n1 : n2) / (double)p);
+    }
+    free(zy);
+    free(Yb);
+}

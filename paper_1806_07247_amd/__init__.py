@@ -6,6 +6,8 @@ outputs and the workspace are allocated with torch on the tensors' device,
 and the kernels are enqueued on torch's current stream.  Every step of the
 computation runs in the library's HIP kernels.
 """
+import ctypes
+
 import torch
 
 from . import _lib
@@ -17,7 +19,9 @@ TP_PREC_BF16 = 2
 _PREC = {"fp32": TP_PREC_FP32, "bf16x3": TP_PREC_BF16X3, "bf16": TP_PREC_BF16}
 
 __all__ = ["tp_tprod", "tp_tprod_workspace_size", "tp_tsvd", "tp_tsvd_workspace_size", "tp_prox_tnn", "tp_prox_tnn_workspace_size",
-           "tp_tnn", "tp_tnn_workspace_size", "half_slices", "TPError", "TP_PREC_FP32",
+           "tp_tnn", "tp_tnn_workspace_size", "tp_prox_tnn_learned", "tp_prox_tnn_learned_workspace_size",
+           "tp_slice_features", "tp_mlp_param_count", "tp_mlp_forward", "tp_mlp_loss_grad", "tp_mlp_adam",
+           "half_slices", "TPError", "TP_PREC_FP32",
            "TP_PREC_BF16X3", "TP_PREC_BF16", "library_path"]
 
 
@@ -139,3 +143,75 @@ def tp_tsvd(A, info=None, workspace=None):
                      ws.data_ptr(), ws.numel(), _stream(A.device))
     _lib.check("tp_tsvd", st)
     return U, S, V
+
+
+def tp_prox_tnn_learned_workspace_size(n1, n2, n3, max_rank=64):
+    return int(_lib.load().tp_prox_tnn_learned_workspace_size(n1, n2, n3, max_rank))
+
+
+def tp_prox_tnn_learned(Y, tau, mlp=None, fixed_rank=0, prev_rank=None, oversample=10, power_iters=2,
+                        max_rank=64, seed=0, out=None, rank=None, fallback=None, info=None, workspace=None):
+    """Learned-rank prox (see include/tp.h); mlp is a float32 device tensor of
+    tp_mlp_param_count() parameters or None (then every slice uses fixed_rank).
+    rank / fallback / info: optional int32 device tensors of half_slices(n3)."""
+    lib = _lib.load()
+    Y = _dev_tensor(Y, "Y")
+    n1, n2, n3 = Y.shape
+    X = out if out is not None else torch.empty_like(Y)
+    opts = _lib.LearnedOpts(_ptr(mlp), int(fixed_rank), _ptr(prev_rank), int(oversample), int(power_iters),
+                            int(max_rank), int(seed) & 0xFFFFFFFFFFFFFFFF)
+    ws_bytes = lib.tp_prox_tnn_learned_workspace_size(n1, n2, n3, int(max_rank))
+    ws = workspace if workspace is not None else _workspace(ws_bytes, Y.device)
+    st = lib.tp_prox_tnn_learned(Y.data_ptr(), X.data_ptr(), n1, n2, n3, float(tau), ctypes.byref(opts),
+                                 _ptr(rank), _ptr(fallback), _ptr(info), ws.data_ptr(), ws.numel(),
+                                 _stream(Y.device))
+    _lib.check("tp_prox_tnn_learned", st)
+    return X
+
+
+def tp_slice_features(Y, tau, prev_rank=None, workspace=None):
+    """Per-slice features of the rank predictor: (half_slices(n3), 8) float32 device tensor."""
+    lib = _lib.load()
+    Y = _dev_tensor(Y, "Y")
+    n1, n2, n3 = Y.shape
+    f = torch.empty((half_slices(n3), 8), dtype=torch.float32, device=Y.device)
+    ws_bytes = lib.tp_slice_features_workspace_size(n1, n2, n3)
+    ws = workspace if workspace is not None else _workspace(ws_bytes, Y.device)
+    st = lib.tp_slice_features(Y.data_ptr(), n1, n2, n3, float(tau), _ptr(prev_rank), f.data_ptr(), ws.data_ptr(),
+                               ws.numel(), _stream(Y.device))
+    _lib.check("tp_slice_features", st)
+    return f
+
+
+def tp_mlp_param_count():
+    return int(_lib.load().tp_mlp_param_count())
+
+
+def tp_mlp_forward(params, x):
+    lib = _lib.load()
+    x = x.contiguous()
+    y = torch.empty(x.shape[0], dtype=torch.float32, device=x.device)
+    _lib.check("tp_mlp_forward", lib.tp_mlp_forward(params.data_ptr(), x.data_ptr(), y.data_ptr(), x.shape[0],
+                                                    _stream(x.device)))
+    return y
+
+
+def tp_mlp_loss_grad(params, x, t, under=4.0, grad=None, loss=None, workspace=None):
+    """Returns (grad, loss) device tensors of the asymmetric squared loss."""
+    lib = _lib.load()
+    x, t = x.contiguous(), t.contiguous()
+    b = x.shape[0]
+    g = grad if grad is not None else torch.empty_like(params)
+    l = loss if loss is not None else torch.empty((), dtype=torch.float32, device=x.device)
+    ws = workspace if workspace is not None else _workspace(lib.tp_mlp_train_workspace_size(b), x.device)
+    _lib.check("tp_mlp_loss_grad", lib.tp_mlp_loss_grad(params.data_ptr(), x.data_ptr(), t.data_ptr(), b,
+                                                        float(under), g.data_ptr(), l.data_ptr(), ws.data_ptr(),
+                                                        ws.numel(), _stream(x.device)))
+    return g, l
+
+
+def tp_mlp_adam(params, grad, m, v, step, lr=1e-3, beta1=0.9, beta2=0.999, eps=1e-8):
+    lib = _lib.load()
+    _lib.check("tp_mlp_adam", lib.tp_mlp_adam(params.data_ptr(), grad.data_ptr(), m.data_ptr(), v.data_ptr(),
+                                              int(step), float(lr), float(beta1), float(beta2), float(eps),
+                                              _stream(params.device)))

@@ -35,6 +35,28 @@ SIGNATURES = {
     "tp_kernel_name": (ctypes.c_char_p, [_I]),
 }
 
+_U64 = ctypes.c_ulonglong
+
+
+class LearnedOpts(ctypes.Structure):
+    """tp_learned_opts of include/tp.h"""
+    _fields_ = [("mlp", _VP), ("fixed_rank", _I), ("prev_rank", _VP), ("oversample", _I),
+                ("power_iters", _I), ("max_rank", _I), ("seed", _U64)]
+
+
+SIGNATURES.update({
+    "tp_prox_tnn_learned_workspace_size": (_SZ, [_I, _I, _I, _I]),
+    "tp_prox_tnn_learned": (_I, [_VP, _VP, _I, _I, _I, _F, ctypes.POINTER(LearnedOpts), _VP, _VP, _VP, _VP, _SZ,
+                                 _VP]),
+    "tp_slice_features_workspace_size": (_SZ, [_I, _I, _I]),
+    "tp_slice_features": (_I, [_VP, _I, _I, _I, _F, _VP, _VP, _VP, _SZ, _VP]),
+    "tp_mlp_param_count": (_I, []),
+    "tp_mlp_forward": (_I, [_VP, _VP, _VP, _I, _VP]),
+    "tp_mlp_train_workspace_size": (_SZ, [_I]),
+    "tp_mlp_loss_grad": (_I, [_VP, _VP, _VP, _I, _F, _VP, _VP, _VP, _SZ, _VP]),
+    "tp_mlp_adam": (_I, [_VP, _VP, _VP, _VP, _I, _F, _F, _F, _F, _VP]),
+})
+
 _lib = None
 
 

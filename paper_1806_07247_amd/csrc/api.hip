@@ -1,6 +1,8 @@
 // C-ABI entry points of libtp.so: argument checks, workspace carving and the
 // kernel sequence of each operation.  See include/tp.h for the contract.
 #include <cmath>
+#include <utility>
+#include <vector>
 
 #include "tp_internal.h"
 
@@ -45,7 +47,7 @@ struct SvtLayout {
     size_t jscratch_bytes;
 };
 
-tp::Arena svt_arena(void* ws, size_t bytes, int n1, int n2, int n3, bool recon, SvtLayout* L)
+tp::Arena svt_arena(void* ws, size_t bytes, int n1, int n2, int n3, bool recon, SvtLayout* L, bool any_count = false)
 {
     const size_t h = (size_t)tp::half_slices(n3);
     const size_t mn = (size_t)n1 * n2, p = (size_t)(n1 < n2 ? n1 : n2), P = p;
@@ -62,11 +64,175 @@ tp::Arena svt_arena(void* ws, size_t bytes, int n1, int n2, int n3, bool recon, 
     }
     t.sigma = ar.take<double>(h * P);
     t.jscratch_bytes = tp::jacobi_scratch_bytes(n1, n2, (int)h, false);
+    if (any_count) {  // any batch of up to h slices (a compact set of fallback slices)
+        const size_t one = tp::jacobi_scratch_bytes(n1, n2, 1, false);
+        if (one * h + 4096 > t.jscratch_bytes) t.jscratch_bytes = one * h + 4096;
+    }
     t.jscratch = t.jscratch_bytes ? ar.take<char>(t.jscratch_bytes) : nullptr;
     if (L) *L = t;
     return ar;
 }
 
+
+
+// Matrix SVT W^(k) = U (S - tau)_+ V^* of `nslices` slices held in yb (planar
+// row-major n1 x n2 per slice), written back to yb: one-sided Jacobi on each
+// slice (or its conjugate transpose when wide), shrinkage of the rotated
+// columns, then W = What What^* Ybar (or Ybar Bhat Bhat^*) as two products.
+int run_svt(const SvtLayout& L, tp::Planes yb, int n1, int n2, int nslices, int real_first, int real_last,
+            double tau, int* info, int* rank, hipStream_t s)
+{
+    const bool tr = n1 < n2;
+    const int R = tr ? n2 : n1, P = tr ? n1 : n2, p = P;
+    const long long mn = (long long)n1 * n2;
+    const int h = nslices;
+    tp::JacobiArgs j{};
+    j.yr = yb.re;
+    j.yi = yb.im;
+    j.wr = L.w.re;
+    j.wi = L.w.im;
+    j.sigma = L.sigma;
+    j.info = info;
+    j.m = n1;
+    j.n = n2;
+    j.nslices = h;
+    j.max_sweeps = tp::param(TP_PARAM_JACOBI_SWEEPS);
+    j.transpose = tr ? 1 : 0;
+    j.tol = tp::jacobi_tol(R);
+    TP_LAUNCH(tp::K_JACOBI, s, tp::launch_jacobi(j, L.jscratch, L.jscratch_bytes, s));
+    // shrinkage (eq (21)): scaled columns sqrt(d_j)/sigma_j w_j
+    TP_LAUNCH(tp::K_SHRINK, s, tp::launch_shrink(L.w.re, L.w.im, L.sigma, rank ? rank : L.keep, R, P, h, tau, s));
+    // W = U (S - tau)_+ V^* as two slice products
+    tp::CgemmArgs g{};
+    g.nslices = h;
+    g.real_first = real_first;
+    g.real_last = real_last;
+    if (!tr) {
+        // T = What^* Ybar (n x n), then W = What T (m x n)
+        g.ar = L.w.re; g.ai = L.w.im; g.lda = n2; g.sa = mn;
+        g.br = yb.re; g.bi = yb.im; g.ldb = n2; g.sb = mn;
+        g.cr = L.t.re; g.ci = L.t.im; g.ldc = p; g.sc = (long long)p * p;
+        g.m = n2; g.n = n2; g.k = n1;
+        TP_LAUNCH(tp::K_CGEMM, s, tp::launch_cgemm(g, tp::OP_C, tp::OP_N, TP_PREC_FP32, s));
+        g.ar = L.w.re; g.ai = L.w.im; g.lda = n2; g.sa = mn;
+        g.br = L.t.re; g.bi = L.t.im; g.ldb = p; g.sb = (long long)p * p;
+        g.cr = yb.re; g.ci = yb.im; g.ldc = n2; g.sc = mn;
+        g.m = n1; g.n = n2; g.k = n2;
+        TP_LAUNCH(tp::K_CGEMM, s, tp::launch_cgemm(g, tp::OP_N, tp::OP_N, TP_PREC_FP32, s));
+    } else {
+        // T = Ybar Bhat (m x m), then W = T Bhat^* (m x n); Bhat is n x m
+        g.ar = yb.re; g.ai = yb.im; g.lda = n2; g.sa = mn;
+        g.br = L.w.re; g.bi = L.w.im; g.ldb = n1; g.sb = mn;
+        g.cr = L.t.re; g.ci = L.t.im; g.ldc = p; g.sc = (long long)p * p;
+        g.m = n1; g.n = n1; g.k = n2;
+        TP_LAUNCH(tp::K_CGEMM, s, tp::launch_cgemm(g, tp::OP_N, tp::OP_N, TP_PREC_FP32, s));
+        g.ar = L.t.re; g.ai = L.t.im; g.lda = p; g.sa = (long long)p * p;
+        g.br = L.w.re; g.bi = L.w.im; g.ldb = n1; g.sb = mn;
+        g.cr = yb.re; g.ci = yb.im; g.ldc = n2; g.sc = mn;
+        g.m = n1; g.n = n2; g.k = n1;
+        TP_LAUNCH(tp::K_CGEMM, s, tp::launch_cgemm(g, tp::OP_N, tp::OP_C, TP_PREC_FP32, s));
+    }
+    return TP_OK;
+}
+
+
+// Workspace of the learned-rank prox.
+struct LearnedLayout {
+    SvtLayout full;                 // full path, sized for any batch of up to h slices
+    tp::Planes wbar;                // thresholded slices (m x n)
+    tp::Planes cy;                  // compact fallback slices (m x n)
+    tp::Planes om, ya, yb, za, zb;  // sketch (n x L), ranges (m x L), co-ranges (n x L)
+    tp::Planes rinv, rh, T, m1;     // L x L, L x L, L x L, L x n
+    double2* part;
+    double2* rtot;
+    float2* jcols;
+    float2* jv;
+    double* jsig;
+    float* feats;
+    int *kpred, *lact, *fb, *rank, *status, *idx, *cinfo, *crank;
+};
+
+tp::Arena learned_arena(void* ws, size_t bytes, int n1, int n2, int n3, int Lw, LearnedLayout* out)
+{
+    const size_t h = (size_t)tp::half_slices(n3), mn = (size_t)n1 * n2, L = (size_t)Lw;
+    LearnedLayout t{};
+    tp::Arena ar(ws, bytes);
+    SvtLayout f{};
+    // the full-path buffers first (svt_arena's own layout), then the rest
+    tp::Arena fa = svt_arena(ws, bytes, n1, n2, n3, true, &f, true);
+    ar.used = fa.used;
+    ar.ok = fa.ok;
+    t.full = f;
+    auto planes = [&](size_t count) {
+        tp::Planes pl;
+        pl.re = ar.take<float>(count);
+        pl.im = ar.take<float>(count);
+        return pl;
+    };
+    t.wbar = planes(h * mn);
+    t.cy = planes(h * mn);
+    t.om = planes(h * n2 * L);
+    t.ya = planes(h * n1 * L);
+    t.yb = planes(h * n1 * L);
+    t.za = planes(h * n2 * L);
+    t.zb = planes(h * n2 * L);
+    t.rinv = planes(h * L * L);
+    t.rh = planes(h * L * L);
+    t.T = planes(h * L * L);
+    t.m1 = planes(h * L * n2);
+    const int mx = n1 > n2 ? n1 : n2;
+    t.part = reinterpret_cast<double2*>(ar.take<char>(tp::cholqr_part_bytes(mx, Lw, (int)h)));
+    t.rtot = ar.take<double2>(h * L * L);
+    t.jcols = ar.take<float2>(h * L * L);
+    t.jv = ar.take<float2>(h * L * L);
+    t.jsig = ar.take<double>(h * L);
+    t.feats = ar.take<float>(h * TP_MLP_INPUTS);
+    t.kpred = ar.take<int>(h);
+    t.lact = ar.take<int>(h);
+    t.fb = ar.take<int>(h);
+    t.rank = ar.take<int>(h);
+    t.status = ar.take<int>(h);
+    t.idx = ar.take<int>(h);
+    t.cinfo = ar.take<int>(h);
+    t.crank = ar.take<int>(h);
+    if (out) *out = t;
+    return ar;
+}
+
+// slice GEMM of planar stacks: C = op(A) op(B) with op(A) m x k, op(B) k x n
+int gemm(tp::Planes a, long long lda, long long sa, int opa, tp::Planes b, long long ldb, long long sb, int opb,
+         tp::Planes c, long long ldc, long long sc, int m, int n, int k, int nslices, int real_last, hipStream_t s)
+{
+    tp::CgemmArgs g{};
+    g.ar = a.re; g.ai = a.im; g.lda = lda; g.sa = sa;
+    g.br = b.re; g.bi = b.im; g.ldb = ldb; g.sb = sb;
+    g.cr = c.re; g.ci = c.im; g.ldc = ldc; g.sc = sc;
+    g.m = m; g.n = n; g.k = k;
+    g.nslices = nslices;
+    g.real_first = 1;
+    g.real_last = real_last;
+    TP_LAUNCH(tp::K_CGEMM, s, tp::launch_cgemm(g, opa, opb, TP_PREC_FP32, s));
+    return TP_OK;
+}
+
+// CholeskyQR2 of y (rows x L per slice) in place, tmp of the same size; with
+// want_r the combined R of both passes is kept and R^* written to Lw.rh
+int cholqr2(LearnedLayout& Lw, tp::Planes y, tp::Planes tmp, int rows, int L, int h, int real_last, bool want_r,
+            hipStream_t s)
+{
+    tp::Planes src = y, dst = tmp;
+    for (int pass = 0; pass < 2; ++pass) {
+        TP_LAUNCH(tp::K_CHOLQR, s,
+                  tp::launch_cholqr_pass(src.re, src.im, rows, L, Lw.lact, h, pass, Lw.part, Lw.rinv.re, Lw.rinv.im,
+                                         want_r ? Lw.rtot : nullptr, want_r ? Lw.rh.re : nullptr,
+                                         want_r ? Lw.rh.im : nullptr, Lw.status, s));
+        const int st = gemm(src, L, (long long)rows * L, tp::OP_N, Lw.rinv, L, (long long)L * L, tp::OP_N, dst, L,
+                            (long long)rows * L, rows, L, L, h, real_last, s);
+        if (st != TP_OK) return st;
+        std::swap(src, dst);
+    }
+    return TP_OK;
+}
 
 // Workspace of tsvd.
 struct TsvdLayout {
@@ -189,62 +355,15 @@ int tp_prox_tnn(const float* Y, float* X, int n1, int n2, int n3, float tau, int
     if (!ar.ok) return TP_ERR_WORKSPACE;
     hipStream_t s = as_stream(stream);
     const int h = tp::half_slices(n3);
-    const bool tr = n1 < n2;           // work on Ybar^* when the slices are wide
-    const int R = tr ? n2 : n1, P = tr ? n1 : n2, p = P;
     const long long mn = (long long)n1 * n2;
 
     // Algorithm 3, step 1
     TP_LAUNCH(tp::K_RFFT, s, tp::launch_rfft(Y, L.ybar.re, L.ybar.im, mn, n3, s));
-    // step 2: SVD of each leading slice ...
-    tp::JacobiArgs j{};
-    j.yr = L.ybar.re;
-    j.yi = L.ybar.im;
-    j.wr = L.w.re;
-    j.wi = L.w.im;
-    j.sigma = L.sigma;
-    j.info = info;
-    j.m = n1;
-    j.n = n2;
-    j.nslices = h;
-    j.max_sweeps = tp::param(TP_PARAM_JACOBI_SWEEPS);
-    j.transpose = tr ? 1 : 0;
-    j.tol = tp::jacobi_tol(R);
-    TP_LAUNCH(tp::K_JACOBI, s, tp::launch_jacobi(j, L.jscratch, L.jscratch_bytes, s));
-    // ... shrinkage (eq (21)): scaled columns sqrt(d_j)/sigma_j w_j
-    TP_LAUNCH(tp::K_SHRINK, s, tp::launch_shrink(L.w.re, L.w.im, L.sigma, rank ? rank : L.keep, R, P, h, (double)tau, s));
-    // ... and W = U (S - tau)_+ V^* as two slice products
-    tp::CgemmArgs g{};
-    g.nslices = h;
-    g.real_first = 1;
-    g.real_last = (n3 % 2 == 0) ? 1 : 0;
-    if (!tr) {
-        // T = What^* Ybar (n x n), then W = What T (m x n)
-        g.ar = L.w.re; g.ai = L.w.im; g.lda = n2; g.sa = mn;
-        g.br = L.ybar.re; g.bi = L.ybar.im; g.ldb = n2; g.sb = mn;
-        g.cr = L.t.re; g.ci = L.t.im; g.ldc = p; g.sc = (long long)p * p;
-        g.m = n2; g.n = n2; g.k = n1;
-        TP_LAUNCH(tp::K_CGEMM, s, tp::launch_cgemm(g, tp::OP_C, tp::OP_N, TP_PREC_FP32, s));
-        g.ar = L.w.re; g.ai = L.w.im; g.lda = n2; g.sa = mn;
-        g.br = L.t.re; g.bi = L.t.im; g.ldb = p; g.sb = (long long)p * p;
-        g.cr = L.ybar.re; g.ci = L.ybar.im; g.ldc = n2; g.sc = mn;
-        g.m = n1; g.n = n2; g.k = n2;
-        TP_LAUNCH(tp::K_CGEMM, s, tp::launch_cgemm(g, tp::OP_N, tp::OP_N, TP_PREC_FP32, s));
-    } else {
-        // T = Ybar Bhat (m x m), then W = T Bhat^* (m x n); Bhat is n x m
-        g.ar = L.ybar.re; g.ai = L.ybar.im; g.lda = n2; g.sa = mn;
-        g.br = L.w.re; g.bi = L.w.im; g.ldb = n1; g.sb = mn;
-        g.cr = L.t.re; g.ci = L.t.im; g.ldc = p; g.sc = (long long)p * p;
-        g.m = n1; g.n = n1; g.k = n2;
-        TP_LAUNCH(tp::K_CGEMM, s, tp::launch_cgemm(g, tp::OP_N, tp::OP_N, TP_PREC_FP32, s));
-        g.ar = L.t.re; g.ai = L.t.im; g.lda = p; g.sa = (long long)p * p;
-        g.br = L.w.re; g.bi = L.w.im; g.ldb = n1; g.sb = mn;
-        g.cr = L.ybar.re; g.ci = L.ybar.im; g.ldc = n2; g.sc = mn;
-        g.m = n1; g.n = n2; g.k = n1;
-        TP_LAUNCH(tp::K_CGEMM, s, tp::launch_cgemm(g, tp::OP_N, tp::OP_C, TP_PREC_FP32, s));
-    }
+    // step 2: matrix SVT of each leading slice, in place in L.ybar
+    const int st = run_svt(L, L.ybar, n1, n2, h, 1, (n3 % 2 == 0) ? 1 : 0, (double)tau, info, rank, s);
+    if (st != TP_OK) return st;
     // step 3: inverse DFT (conjugate fill implicit)
     TP_LAUNCH(tp::K_IRFFT, s, tp::launch_irfft(L.ybar.re, L.ybar.im, X, mn, n3, s));
-    (void)R;
     return TP_OK;
 }
 
@@ -330,6 +449,175 @@ int tp_tsvd(const float* A, float* U, float* S, float* V, int n1, int n2, int n3
     TP_LAUNCH(tp::K_IRFFT, s, tp::launch_irfft(ub.re, ub.im, U, (long long)n1 * n1, n3, s));
     TP_LAUNCH(tp::K_IRFFT, s, tp::launch_irfft(L.s.re, L.s.im, S, (long long)n1 * n2, n3, s));
     TP_LAUNCH(tp::K_IRFFT, s, tp::launch_irfft(vb.re, vb.im, V, (long long)n2 * n2, n3, s));
+    return TP_OK;
+}
+
+size_t tp_prox_tnn_learned_workspace_size(int n1, int n2, int n3, int max_rank)
+{
+    if (bad_dim(n1) || bad_dim(n2) || bad_dim(n3) || max_rank < 1 || max_rank > tp::kMaxL) return 0;
+    return learned_arena(nullptr, 0, n1, n2, n3, max_rank, nullptr).used;
+}
+
+int tp_prox_tnn_learned(const float* Y, float* X, int n1, int n2, int n3, float tau, const tp_learned_opts* opts,
+                        int* rank, int* fallback, int* info, void* workspace, size_t workspace_bytes, void* stream)
+{
+    if (!Y || !X || !opts) return TP_ERR_ARG;
+    if (!(tau >= 0.0f) || std::isinf(tau)) return TP_ERR_ARG;
+    if (opts->max_rank < 1 || opts->max_rank > tp::kMaxL || opts->oversample < 0 || opts->power_iters < 0 ||
+        opts->power_iters > 16 || (!opts->mlp && opts->fixed_rank < 0))
+        return TP_ERR_ARG;
+    if (bad_dim(n1) || bad_dim(n2) || bad_dim(n3) || n3 > kMaxN3) return TP_ERR_SHAPE;
+    if (bad_slice(n1, n2)) return TP_ERR_SHAPE;
+    if ((n1 < n2 ? n2 : n1) > 2048) return TP_ERR_UNSUPPORTED;
+    const int L = opts->max_rank;
+    LearnedLayout W;
+    tp::Arena ar = learned_arena(workspace, workspace_bytes, n1, n2, n3, L, &W);
+    if (!ar.ok) return TP_ERR_WORKSPACE;
+    hipStream_t s = as_stream(stream);
+    const int h = tp::half_slices(n3), p = n1 < n2 ? n1 : n2, rl = (n3 % 2 == 0) ? 1 : 0;
+    const long long mn = (long long)n1 * n2;
+    int* fb = fallback ? fallback : W.fb;
+    int* rk = rank ? rank : W.rank;
+    tp::Planes ybar = W.full.ybar;
+
+    TP_LAUNCH(tp::K_RFFT, s, tp::launch_rfft(Y, ybar.re, ybar.im, mn, n3, s));
+    // predicted count per slice and sketch width
+    TP_LAUNCH(tp::K_FEATURES, s,
+              tp::launch_features(ybar.re, ybar.im, n1, n2, n3, h, (double)tau, opts->prev_rank, W.feats, s));
+    TP_LAUNCH(tp::K_PREDICT, s,
+              tp::launch_predict(opts->mlp, W.feats, h, p, opts->fixed_rank, opts->oversample, L, W.kpred, W.lact,
+                                 fb, rk, s));
+    TP_TRY(hipMemsetAsync(W.status, 0, h * sizeof(int), s));
+    // range finder: Y = Ybar Om, re-orthonormalised; power iterations
+    TP_LAUNCH(tp::K_SKETCH, s, tp::launch_sketch(W.om.re, W.om.im, n2, L, W.lact, h, n3, opts->seed, s));
+    int st = gemm(ybar, n2, mn, tp::OP_N, W.om, L, (long long)n2 * L, tp::OP_N, W.ya, L, (long long)n1 * L, n1, L, n2,
+                  h, rl, s);
+    if (st == TP_OK) st = cholqr2(W, W.ya, W.yb, n1, L, h, rl, false, s);
+    for (int it = 0; st == TP_OK && it < opts->power_iters; ++it) {
+        st = gemm(ybar, n2, mn, tp::OP_C, W.ya, L, (long long)n1 * L, tp::OP_N, W.za, L, (long long)n2 * L, n2, L, n1,
+                  h, rl, s);
+        if (st == TP_OK) st = cholqr2(W, W.za, W.zb, n2, L, h, rl, false, s);
+        if (st == TP_OK)
+            st = gemm(ybar, n2, mn, tp::OP_N, W.za, L, (long long)n2 * L, tp::OP_N, W.ya, L, (long long)n1 * L, n1, L,
+                      n2, h, rl, s);
+        if (st == TP_OK) st = cholqr2(W, W.ya, W.yb, n1, L, h, rl, false, s);
+    }
+    // Bh = Ybar^* Q = Q2 R2
+    if (st == TP_OK)
+        st = gemm(ybar, n2, mn, tp::OP_C, W.ya, L, (long long)n1 * L, tp::OP_N, W.za, L, (long long)n2 * L, n2, L, n1, h,
+                  rl, s);
+    if (st == TP_OK) st = cholqr2(W, W.za, W.zb, n2, L, h, rl, true, s);
+    if (st != TP_OK) return st;
+    // SVD of R2^* (one workgroup per slice, LDS), check, core T
+    tp::JacobiArgs j{};
+    j.yr = W.rh.re;
+    j.yi = W.rh.im;
+    j.sigma = W.jsig;
+    j.m = L;
+    j.n = L;
+    j.nslices = h;
+    j.max_sweeps = tp::param(TP_PARAM_JACOBI_SWEEPS);
+    j.tol = tp::jacobi_tol(L);
+    j.cols = W.jcols;
+    j.qout = W.jv;
+    j.whole = 1;
+    TP_LAUNCH(tp::K_JACOBI, s, tp::launch_jacobi(j, nullptr, 0, s));
+    TP_LAUNCH(tp::K_RSVD_CHECK, s,
+              tp::launch_rsvd_check(W.jcols, W.jsig, W.jv, W.kpred, W.lact, L, (double)tau, W.T, fb, rk, h, s));
+    // W = Q (T Q2^*)
+    st = gemm(W.T, L, (long long)L * L, tp::OP_N, W.za, L, (long long)n2 * L, tp::OP_C, W.m1, n2, (long long)L * n2, L,
+              n2, L, h, rl, s);
+    if (st == TP_OK)
+        st = gemm(W.ya, L, (long long)n1 * L, tp::OP_N, W.m1, n2, (long long)L * n2, tp::OP_N, W.wbar, n2, mn, n1, n2,
+                  L, h, rl, s);
+    if (st != TP_OK) return st;
+    // fallback slices: full SVD on a compact batch
+    std::vector<int> hfb(h), hidx;
+    TP_TRY(hipMemcpyAsync(hfb.data(), fb, h * sizeof(int), hipMemcpyDeviceToHost, s));
+    TP_TRY(hipStreamSynchronize(s));
+    for (int k = 0; k < h; ++k)
+        if (hfb[k]) hidx.push_back(k);
+    const int cnt = (int)hidx.size();
+    std::vector<int> hinfo(h, 0);
+    if (cnt > 0) {
+        TP_TRY(hipMemcpy(W.idx, hidx.data(), cnt * sizeof(int), hipMemcpyHostToDevice));
+        TP_LAUNCH(tp::K_GATHER, s, tp::launch_gather(ybar.re, ybar.im, W.cy.re, W.cy.im, W.idx, cnt, mn, false, s));
+        SvtLayout F = W.full;
+        st = run_svt(F, W.cy, n1, n2, cnt, 0, 0, (double)tau, info ? W.cinfo : nullptr, W.crank, s);
+        if (st != TP_OK) return st;
+        TP_LAUNCH(tp::K_GATHER, s, tp::launch_gather(W.cy.re, W.cy.im, W.wbar.re, W.wbar.im, W.idx, cnt, mn, true, s));
+        std::vector<int> crank(cnt), cinfo(cnt, 0);
+        TP_TRY(hipMemcpyAsync(crank.data(), W.crank, cnt * sizeof(int), hipMemcpyDeviceToHost, s));
+        if (info) TP_TRY(hipMemcpyAsync(cinfo.data(), W.cinfo, cnt * sizeof(int), hipMemcpyDeviceToHost, s));
+        TP_TRY(hipStreamSynchronize(s));
+        std::vector<int> hrank(h);
+        TP_TRY(hipMemcpy(hrank.data(), rk, h * sizeof(int), hipMemcpyDeviceToHost));
+        for (int c = 0; c < cnt; ++c) {
+            hrank[hidx[c]] = crank[c];
+            hinfo[hidx[c]] = cinfo[c];
+        }
+        TP_TRY(hipMemcpy(rk, hrank.data(), h * sizeof(int), hipMemcpyHostToDevice));
+    }
+    if (info) TP_TRY(hipMemcpy(info, hinfo.data(), h * sizeof(int), hipMemcpyHostToDevice));
+    TP_LAUNCH(tp::K_IRFFT, s, tp::launch_irfft(W.wbar.re, W.wbar.im, X, mn, n3, s));
+    return TP_OK;
+}
+
+size_t tp_slice_features_workspace_size(int n1, int n2, int n3)
+{
+    if (bad_dim(n1) || bad_dim(n2) || bad_dim(n3)) return 0;
+    const size_t h = (size_t)tp::half_slices(n3);
+    return 2 * tp::align_up(h * n1 * n2 * sizeof(float));
+}
+
+int tp_slice_features(const float* Y, int n1, int n2, int n3, float tau, const int* prev_rank, float* feats,
+                      void* workspace, size_t workspace_bytes, void* stream)
+{
+    if (!Y || !feats) return TP_ERR_ARG;
+    if (!(tau >= 0.0f) || std::isinf(tau)) return TP_ERR_ARG;
+    if (bad_dim(n1) || bad_dim(n2) || bad_dim(n3) || n3 > kMaxN3 || bad_slice(n1, n2)) return TP_ERR_SHAPE;
+    const size_t h = (size_t)tp::half_slices(n3);
+    tp::Arena ar(workspace, workspace_bytes);
+    float* re = ar.take<float>(h * n1 * n2);
+    float* im = ar.take<float>(h * n1 * n2);
+    if (!ar.ok) return TP_ERR_WORKSPACE;
+    hipStream_t s = as_stream(stream);
+    TP_LAUNCH(tp::K_RFFT, s, tp::launch_rfft(Y, re, im, (long long)n1 * n2, n3, s));
+    TP_LAUNCH(tp::K_FEATURES, s, tp::launch_features(re, im, n1, n2, n3, (int)h, (double)tau, prev_rank, feats, s));
+    return TP_OK;
+}
+
+int tp_mlp_param_count(void) { return tp::mlp_param_count(); }
+
+int tp_mlp_forward(const float* params, const float* x, float* y, int batch, void* stream)
+{
+    if (!params || !x || !y || batch < 0) return TP_ERR_ARG;
+    if (batch == 0) return TP_OK;
+    hipStream_t s = as_stream(stream);
+    TP_LAUNCH(tp::K_MLP, s, tp::launch_mlp_forward(params, x, y, batch, s));
+    return TP_OK;
+}
+
+size_t tp_mlp_train_workspace_size(int batch) { return batch > 0 ? tp::mlp_train_bytes(batch) : 0; }
+
+int tp_mlp_loss_grad(const float* params, const float* x, const float* t, int batch, float under, float* grad,
+                     float* loss, void* workspace, size_t workspace_bytes, void* stream)
+{
+    if (!params || !x || !t || !grad || !loss || batch <= 0 || !(under > 0.0f)) return TP_ERR_ARG;
+    if (!workspace || workspace_bytes < tp::mlp_train_bytes(batch)) return TP_ERR_WORKSPACE;
+    hipStream_t s = as_stream(stream);
+    TP_LAUNCH(tp::K_MLP, s, tp::launch_mlp_loss_grad(params, x, t, batch, under, grad, loss, workspace, s));
+    return TP_OK;
+}
+
+int tp_mlp_adam(float* params, const float* grad, float* m, float* v, int step, float lr, float beta1, float beta2,
+                float eps, void* stream)
+{
+    if (!params || !grad || !m || !v || step < 1 || !(lr > 0.0f) || !(beta1 >= 0.0f && beta1 < 1.0f) ||
+        !(beta2 >= 0.0f && beta2 < 1.0f) || !(eps > 0.0f))
+        return TP_ERR_ARG;
+    hipStream_t s = as_stream(stream);
+    TP_LAUNCH(tp::K_MLP, s, tp::launch_adam(params, grad, m, v, tp::mlp_param_count(), step, lr, beta1, beta2, eps, s));
     return TP_OK;
 }
 

@@ -484,7 +484,7 @@ template <int G, int RPL>
 hipError_t launch_rpl(const JacobiArgs& a, void* scratch, int R, int P, hipStream_t st)
 {
     const bool withv = a.qout != nullptr;
-    if (use_blocked(R, P, a.nslices, withv)) {
+    if (!(a.whole && whole_bytes(R, P, withv) <= kMaxLds) && use_blocked(R, P, a.nslices, withv)) {
         const BlockPlan pl = block_plan(R, P, a.nslices, withv);
         return withv ? launch_blocked<G, RPL, true>(a, scratch, R, P, pl, st)
                      : launch_blocked<G, RPL, false>(a, scratch, R, P, pl, st);
@@ -497,7 +497,7 @@ hipError_t launch_rpl(const JacobiArgs& a, void* scratch, int R, int P, hipStrea
 size_t jacobi_scratch_bytes(int m, int n, int nslices, bool withv)
 {
     const int R = m >= n ? m : n, P = m >= n ? n : m;
-    if (use_blocked(R, P, nslices, withv)) {
+    if (use_blocked(R, P, nslices, withv)) {  // (an upper bound when a call forces one workgroup per slice)
         const BlockPlan pl = block_plan(R, P, nslices, withv);
         return pl.work_bytes + pl.v_bytes + pl.flag_bytes;
     }
@@ -510,7 +510,9 @@ hipError_t launch_jacobi(const JacobiArgs& a, void* scratch, size_t scratch_byte
     if (a.nslices <= 0) return hipSuccess;
     const int R = a.transpose ? a.n : a.m;
     const int P = a.transpose ? a.m : a.n;
-    if (jacobi_scratch_bytes(a.m, a.n, a.nslices, a.qout != nullptr) > scratch_bytes) return hipErrorInvalidValue;
+    const bool withv = a.qout != nullptr;
+    const bool whole_fits = a.whole && whole_bytes(R, P, withv) <= kMaxLds;
+    if (!whole_fits && jacobi_scratch_bytes(a.m, a.n, a.nslices, withv) > scratch_bytes) return hipErrorInvalidValue;
     if (R <= 32) return launch_rpl<16, 2>(a, scratch, R, P, st);
     if (R <= 64) return launch_rpl<16, 4>(a, scratch, R, P, st);
     if (R <= 128) return launch_rpl<16, 8>(a, scratch, R, P, st);

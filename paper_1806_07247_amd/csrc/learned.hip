@@ -1,0 +1,638 @@
+// Learned-rank prox_tnn: per-slice features, a small MLP that predicts the
+// number of singular values above tau, a randomized range finder sized by
+// that prediction (Halko, Martinsson, Tropp 2011) with FP64 CholeskyQR2
+// re-orthonormalisation, the check sigma_(k+1) < tau, and the MLP's training
+// kernels.  The exact operation it approximates is Theorem 2.3.
+//
+// Sizes: L is the padded sketch width (l_max, <= kMaxL); each slice uses its
+// own l = lact[s] <= L leading columns, the others are kept at zero.
+#include <cmath>
+
+#include "tp_internal.h"
+
+namespace tp {
+namespace {
+
+// ------------------------------------------------------------------ Philox --
+// Philox4x32-10 (Salmon, Moraes, Dror, Shaw, SC'11).
+__device__ __forceinline__ void philox4x32_10(unsigned int c[4], unsigned int k0, unsigned int k1)
+{
+#pragma unroll
+    for (int r = 0; r < 10; ++r) {
+        if (r > 0) {
+            k0 += 0x9E3779B9u;
+            k1 += 0xBB67AE85u;
+        }
+        const unsigned long long p0 = (unsigned long long)0xD2511F53u * c[0];
+        const unsigned long long p1 = (unsigned long long)0xCD9E8D57u * c[2];
+        const unsigned int n0 = (unsigned int)(p1 >> 32) ^ c[1] ^ k0;
+        const unsigned int n2 = (unsigned int)(p0 >> 32) ^ c[3] ^ k1;
+        c[1] = (unsigned int)p1;
+        c[3] = (unsigned int)p0;
+        c[0] = n0;
+        c[2] = n2;
+    }
+}
+
+__device__ __forceinline__ bool is_real_slice(int s, int n3) { return s == 0 || (n3 % 2 == 0 && s == n3 / 2); }
+
+// Om (n x L per slice, planar row-major): entry (i, j) from Philox on counter
+// {i, j, slice, 0}, key {seed lo, seed hi}; Box-Muller in FP64 on
+// u = (x + 0.5) 2^-32; complex slices (z0 + i z1)/sqrt(2), real slices z0;
+// zero for j >= lact[slice].
+__global__ __launch_bounds__(256) void k_sketch(float* __restrict__ omr, float* __restrict__ omi, int n, int L,
+                                                const int* __restrict__ lact, int nslices, int n3,
+                                                unsigned long long seed)
+{
+    const long long total = (long long)nslices * n * L;
+    for (long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x; e < total;
+         e += (long long)gridDim.x * blockDim.x) {
+        const int s = (int)(e / ((long long)n * L));
+        const int rem = (int)(e % ((long long)n * L));
+        const int i = rem / L, j = rem % L;
+        float vr = 0.0f, vi = 0.0f;
+        if (j < lact[s]) {
+            unsigned int c[4] = {(unsigned int)i, (unsigned int)j, (unsigned int)s, 0u};
+            philox4x32_10(c, (unsigned int)seed, (unsigned int)(seed >> 32));
+            const double u0 = ((double)c[0] + 0.5) * 0x1p-32, u1 = ((double)c[1] + 0.5) * 0x1p-32;
+            const double rad = sqrt(-2.0 * log(u0));
+            double sn, cs;
+            sincospi(2.0 * u1, &sn, &cs);
+            if (is_real_slice(s, n3)) {
+                vr = (float)(rad * cs);
+            } else {
+                vr = (float)(rad * cs * 0.70710678118654752440);
+                vi = (float)(rad * sn * 0.70710678118654752440);
+            }
+        }
+        omr[e] = vr;
+        omi[e] = vi;
+    }
+}
+
+// ------------------------------------------------------------ CholeskyQR --
+// Partial Gram G_w = Y_w^* Y_w (FP64) of the rows handled by workgroup w of
+// nsplit, for the lact leading columns; Y is m x L planar row-major.
+__global__ __launch_bounds__(256) void k_gram(const float* __restrict__ yr, const float* __restrict__ yi, int m,
+                                              int L, const int* __restrict__ lact, double2* __restrict__ part,
+                                              int nsplit)
+{
+    constexpr int CH = 32;  // rows per LDS chunk
+    __shared__ float2 tile[CH * 64];
+    const int s = blockIdx.y, w = blockIdx.x, tid = threadIdx.x;
+    const int la = lact[s];
+    const int r0 = (int)((long long)m * w / nsplit), r1 = (int)((long long)m * (w + 1) / nsplit);
+    const float* Yr = yr + (long long)s * m * L;
+    const float* Yi = yi + (long long)s * m * L;
+    constexpr int PER = 64 * 64 / 256;
+    double ar[PER], ai[PER];
+#pragma unroll
+    for (int u = 0; u < PER; ++u) ar[u] = ai[u] = 0.0;
+    for (int c0 = r0; c0 < r1; c0 += CH) {
+        const int nr = min(CH, r1 - c0);
+        __syncthreads();
+        for (int e = tid; e < nr * L; e += blockDim.x) {
+            const int i = e / L, j = e % L;
+            tile[i * 64 + j] = make_float2(Yr[(long long)(c0 + i) * L + j], Yi[(long long)(c0 + i) * L + j]);
+        }
+        __syncthreads();
+#pragma unroll
+        for (int u = 0; u < PER; ++u) {
+            const int e = tid + u * 256;
+            const int a = e / 64, b = e % 64;
+            if (a < la && b < la) {
+                for (int i = 0; i < nr; ++i) {
+                    const float2 x = tile[i * 64 + a], y = tile[i * 64 + b];
+                    // conj(x) y
+                    ar[u] = fma((double)x.x, (double)y.x, fma((double)x.y, (double)y.y, ar[u]));
+                    ai[u] = fma((double)x.x, (double)y.y, fma(-(double)x.y, (double)y.x, ai[u]));
+                }
+            }
+        }
+    }
+    double2* out = part + ((long long)s * nsplit + w) * L * L;
+#pragma unroll
+    for (int u = 0; u < PER; ++u) {
+        const int e = tid + u * 256;
+        const int a = e / 64, b = e % 64;
+        if (a < L && b < L) out[a * L + b] = make_double2(ar[u], ai[u]);
+    }
+}
+
+// Per slice: G = sum of the partial Grams (fixed order); in pass 0 a diagonal
+// shift 1e-13 trace(G)/lact; Cholesky G = R^* R (FP64, in LDS); Rinv = R^{-1}
+// written as FP32 planar (identity on the inactive columns); optionally
+// Rtot <- R Rtot (FP64) and R2^* (FP32 planar, zero outside the active block).
+__global__ __launch_bounds__(256) void k_chol(const double2* __restrict__ part, int nsplit, int L,
+                                              const int* __restrict__ lact, int pass, float* __restrict__ rir,
+                                              float* __restrict__ rii, double2* __restrict__ rtot,
+                                              float* __restrict__ rhr, float* __restrict__ rhi,
+                                              int* __restrict__ status)
+{
+    extern __shared__ double2 sh[];
+    double2* R = sh;            // L x L
+    double2* X = sh + L * L;    // L x L (inverse, then R Rtot)
+    __shared__ double sd;
+    const int s = blockIdx.x, tid = threadIdx.x, nt = blockDim.x;
+    const int la = lact[s];
+    const double2* P = part + (long long)s * nsplit * L * L;
+    for (int e = tid; e < L * L; e += nt) {
+        double2 g = make_double2(0.0, 0.0);
+        for (int w = 0; w < nsplit; ++w) {
+            const double2 v = P[(long long)w * L * L + e];
+            g.x += v.x;
+            g.y += v.y;
+        }
+        R[e] = g;
+    }
+    __syncthreads();
+    if (tid == 0) {
+        double tr = 0.0;
+        for (int a = 0; a < la; ++a) tr += R[a * L + a].x;
+        sd = (pass == 0 && la > 0) ? 1e-13 * tr / la : 0.0;
+    }
+    __syncthreads();
+    for (int a = tid; a < la; a += nt) R[a * L + a].x += sd;
+    __syncthreads();
+    // in-place Cholesky on the upper triangle: row j of R from rows k < j
+    for (int j = 0; j < L; ++j) {
+        if (tid == 0) {
+            double d = 1.0;
+            if (j < la) {
+                d = R[j * L + j].x;
+                for (int k = 0; k < j; ++k) d -= R[k * L + j].x * R[k * L + j].x + R[k * L + j].y * R[k * L + j].y;
+                if (!(d > 0.0)) {
+                    if (status) status[s] = 1;
+                    d = 1e-300;
+                }
+            }
+            R[j * L + j] = make_double2(sqrt(d), 0.0);
+        }
+        __syncthreads();
+        const double inv = 1.0 / R[j * L + j].x;
+        for (int c = j + 1 + tid; c < L; c += nt) {
+            double2 v = make_double2(0.0, 0.0);
+            if (j < la && c < la) {
+                v = R[j * L + c];
+                for (int k = 0; k < j; ++k) {  // - conj(R_kj) R_kc
+                    const double2 a = R[k * L + j], b = R[k * L + c];
+                    v.x -= a.x * b.x + a.y * b.y;
+                    v.y -= a.x * b.y - a.y * b.x;
+                }
+                v.x *= inv;
+                v.y *= inv;
+            }
+            R[j * L + c] = v;
+        }
+        for (int c = tid; c < j; c += nt) R[j * L + c] = make_double2(0.0, 0.0);  // lower part
+        __syncthreads();
+    }
+    // X = R^{-1}, row j by thread j: X_jj = 1/R_jj, X_jc = -(sum_{j<=k<c} X_jk R_kc)/R_cc
+    for (int j = tid; j < L; j += nt) {
+        for (int c = 0; c < j; ++c) X[j * L + c] = make_double2(0.0, 0.0);
+        X[j * L + j] = make_double2(1.0 / R[j * L + j].x, 0.0);
+        for (int c = j + 1; c < L; ++c) {
+            double vr = 0.0, vi = 0.0;
+            for (int k = j; k < c; ++k) {
+                const double2 a = X[j * L + k], b = R[k * L + c];
+                vr += a.x * b.x - a.y * b.y;
+                vi += a.x * b.y + a.y * b.x;
+            }
+            const double ic = 1.0 / R[c * L + c].x;
+            X[j * L + c] = make_double2(-vr * ic, -vi * ic);
+        }
+    }
+    __syncthreads();
+    for (int e = tid; e < L * L; e += nt) {
+        rir[(long long)s * L * L + e] = (float)X[e].x;
+        rii[(long long)s * L * L + e] = (float)X[e].y;
+    }
+    __syncthreads();
+    if (rtot) {
+        double2* T = rtot + (long long)s * L * L;
+        if (pass == 0) {
+            for (int e = tid; e < L * L; e += nt) X[e] = R[e];
+        } else {
+            for (int e = tid; e < L * L; e += nt) {  // X = R Rtot
+                const int a = e / L, b = e % L;
+                double vr = 0.0, vi = 0.0;
+                for (int k = 0; k < L; ++k) {
+                    const double2 u = R[a * L + k], v = T[k * L + b];
+                    vr += u.x * v.x - u.y * v.y;
+                    vi += u.x * v.y + u.y * v.x;
+                }
+                X[e] = make_double2(vr, vi);
+            }
+        }
+        __syncthreads();
+        for (int e = tid; e < L * L; e += nt) T[e] = X[e];
+        if (rhr && pass == 1) {  // R2^* restricted to the active block
+            for (int e = tid; e < L * L; e += nt) {
+                const int a = e / L, b = e % L;
+                const bool in = a < la && b < la;
+                const double2 v = X[b * L + a];
+                rhr[(long long)s * L * L + e] = in ? (float)v.x : 0.0f;
+                rhi[(long long)s * L * L + e] = in ? (float)(-v.y) : 0.0f;
+            }
+        }
+    }
+}
+
+// ------------------------------------------------------ check and core T --
+// sigma_j, C_r (cols, column-major L x L), V_r (column-major L x L) from the
+// Jacobi SVD of R2^*.  fallback[s] = 1 when #{sigma_j >= tau} > kpred[s]
+// (the check sigma_(k+1) < tau fails) or when the slice was already sent to
+// the full SVD; T = C_r diag((sigma - tau)_+ / sigma) V_r^* (planar, L x L).
+__global__ __launch_bounds__(256) void k_rsvd_check(const float2* __restrict__ cols, const double* __restrict__ sigma,
+                                                    const float2* __restrict__ vr, const int* __restrict__ kpred,
+                                                    const int* __restrict__ lact, int L, double tau,
+                                                    float* __restrict__ tr, float* __restrict__ ti,
+                                                    int* __restrict__ fallback, int* __restrict__ rank)
+{
+    __shared__ double scale[64];
+    __shared__ int above;
+    const int s = blockIdx.x, tid = threadIdx.x;
+    const double* sg = sigma + (long long)s * L;
+    if (tid == 0) {
+        int ge = 0, gt = 0;
+        for (int j = 0; j < lact[s]; ++j) {
+            ge += sg[j] >= tau ? 1 : 0;
+            gt += sg[j] > tau ? 1 : 0;
+        }
+        above = gt;
+        if (ge > kpred[s] && lact[s] > 0) fallback[s] = 1;
+        if (fallback[s] == 0 && rank) rank[s] = gt;
+    }
+    for (int j = tid; j < L; j += blockDim.x)
+        scale[j] = (j < lact[s] && sg[j] > tau) ? (sg[j] - tau) / sg[j] : 0.0;
+    __syncthreads();
+    (void)above;
+    const float2* C = cols + (long long)s * L * L;
+    const float2* V = vr + (long long)s * L * L;
+    for (int e = tid; e < L * L; e += blockDim.x) {
+        const int a = e / L, b = e % L;
+        double vr_ = 0.0, vi_ = 0.0;
+        for (int j = 0; j < L; ++j) {
+            if (scale[j] == 0.0) continue;
+            const float2 c = C[(long long)j * L + a], v = V[(long long)j * L + b];  // C(a,j) conj(V(b,j))
+            vr_ += scale[j] * ((double)c.x * v.x + (double)c.y * v.y);
+            vi_ += scale[j] * ((double)c.y * v.x - (double)c.x * v.y);
+        }
+        tr[(long long)s * L * L + e] = (float)vr_;
+        ti[(long long)s * L * L + e] = (float)vi_;
+    }
+}
+
+// ---------------------------------------------------------------- features --
+// Per slice: f = [log(tau/rms sigma), log(max column norm / tau), prev/p,
+// has_prev, frequency, real, log(p)/8, log(max(m,n)/p)], clamped to [-30, 30].
+__global__ __launch_bounds__(256) void k_features(const float* __restrict__ yr, const float* __restrict__ yi, int m,
+                                                  int n, int n3, int nslices, double tau,
+                                                  const int* __restrict__ prev, float* __restrict__ feats)
+{
+    __shared__ double red[256];
+    __shared__ double redm[256];
+    const int s = blockIdx.x, tid = threadIdx.x;
+    const float* Yr = yr + (long long)s * m * n;
+    const float* Yi = yi + (long long)s * m * n;
+    double tot = 0.0, cmax = 0.0;
+    for (int j = tid; j < n; j += blockDim.x) {
+        double c = 0.0;
+        for (int i = 0; i < m; ++i) {
+            const double a = Yr[(long long)i * n + j], b = Yi[(long long)i * n + j];
+            c += a * a + b * b;
+        }
+        tot += c;
+        cmax = fmax(cmax, c);
+    }
+    red[tid] = tot;
+    redm[tid] = cmax;
+    __syncthreads();
+    for (int w = blockDim.x / 2; w > 0; w >>= 1) {
+        if (tid < w) {
+            red[tid] += red[tid + w];
+            redm[tid] = fmax(redm[tid], redm[tid + w]);
+        }
+        __syncthreads();
+    }
+    if (tid == 0) {
+        const int p = m < n ? m : n;
+        const double nrm2 = red[0], cm = redm[0], t2 = tau * tau;
+        auto clampf = [](double v) { return (float)fmin(30.0, fmax(-30.0, v)); };
+        float* f = feats + (long long)s * TP_MLP_INPUTS;
+        f[0] = (nrm2 > 0.0 && t2 > 0.0) ? clampf(0.5 * log(t2 * p / nrm2)) : -30.0f;
+        f[1] = (cm > 0.0 && t2 > 0.0) ? clampf(0.5 * log(cm / t2)) : (cm > 0.0 ? 30.0f : -30.0f);
+        f[2] = prev ? (float)prev[s] / (float)p : 0.0f;
+        f[3] = prev ? 1.0f : 0.0f;
+        f[4] = n3 > 1 ? (float)s / (float)(n3 / 2 > 0 ? n3 / 2 : 1) : 0.0f;
+        f[5] = is_real_slice(s, n3) ? 1.0f : 0.0f;
+        f[6] = (float)(log((double)p) / 8.0);
+        f[7] = (float)log((double)(m > n ? m : n) / (double)p);
+    }
+}
+
+// --------------------------------------------------------------------- MLP --
+constexpr int D = TP_MLP_INPUTS, H = TP_MLP_HIDDEN;
+
+struct MlpOffsets {
+    static constexpr int W1 = 0, B1 = W1 + H * D, W2 = B1 + H, B2 = W2 + H * H, W3 = B2 + H, B3 = W3 + H * H,
+                         W4 = B3 + H, B4 = W4 + H, COUNT = B4 + 1;
+};
+
+__device__ __forceinline__ float mlp_eval(const float* p, const float* x, float* z1, float* z2, float* z3)
+{
+    using O = MlpOffsets;
+    for (int i = 0; i < H; ++i) {
+        float v = p[O::B1 + i];
+        for (int j = 0; j < D; ++j) v = fmaf(p[O::W1 + i * D + j], x[j], v);
+        z1[i] = v;
+    }
+    for (int i = 0; i < H; ++i) {
+        float v = p[O::B2 + i];
+        for (int j = 0; j < H; ++j) v = fmaf(p[O::W2 + i * H + j], fmaxf(z1[j], 0.0f), v);
+        z2[i] = v;
+    }
+    for (int i = 0; i < H; ++i) {
+        float v = p[O::B3 + i];
+        for (int j = 0; j < H; ++j) v = fmaf(p[O::W3 + i * H + j], fmaxf(z2[j], 0.0f), v);
+        z3[i] = v;
+    }
+    float y = p[O::B4];
+    for (int j = 0; j < H; ++j) y = fmaf(p[O::W4 + j], fmaxf(z3[j], 0.0f), y);
+    return y;
+}
+
+// y[s] = MLP(x[s]) for a batch (one thread per sample; weights in LDS)
+__global__ __launch_bounds__(64) void k_mlp_forward(const float* __restrict__ params, const float* __restrict__ x,
+                                                    float* __restrict__ y, int batch)
+{
+    __shared__ float p[MlpOffsets::COUNT];
+    for (int e = threadIdx.x; e < MlpOffsets::COUNT; e += blockDim.x) p[e] = params[e];
+    __syncthreads();
+    const int s = blockIdx.x * blockDim.x + threadIdx.x;
+    if (s >= batch) return;
+    float z[3 * H];
+    y[s] = mlp_eval(p, x + (long long)s * D, z, z + H, z + 2 * H);
+}
+
+// Rank prediction: kpred = round(expm1(y log1p(p))) clipped to [0, p] (or the
+// fixed rank), lact = min(kpred + oversample, p); slices with lact > L go to
+// the full SVD (fallback = 1, lact = 0).
+__global__ __launch_bounds__(64) void k_predict(const float* __restrict__ params, const float* __restrict__ feats,
+                                                int nslices, int p, int fixed_rank, int oversample, int L,
+                                                int* __restrict__ kpred, int* __restrict__ lact,
+                                                int* __restrict__ fallback, int* __restrict__ rank)
+{
+    __shared__ float w[MlpOffsets::COUNT];
+    if (params)
+        for (int e = threadIdx.x; e < MlpOffsets::COUNT; e += blockDim.x) w[e] = params[e];
+    __syncthreads();
+    const int s = blockIdx.x * blockDim.x + threadIdx.x;
+    if (s >= nslices) return;
+    int k = fixed_rank;
+    if (params) {
+        float z[3 * H];
+        const float yv = mlp_eval(w, feats + (long long)s * D, z, z + H, z + 2 * H);
+        const double kk = expm1((double)yv * log1p((double)p));
+        k = (int)fmin((double)p, fmax(0.0, rint(kk)));
+    }
+    k = k < 0 ? 0 : (k > p ? p : k);
+    int l = k + oversample;
+    if (l > p) l = p;
+    kpred[s] = k;
+    fallback[s] = 0;
+    if (rank) rank[s] = 0;
+    if (l > L) {
+        fallback[s] = 1;
+        l = 0;
+    }
+    lact[s] = l;
+}
+
+// Training: per sample forward and backward deltas of the asymmetric squared
+// loss c(e) e^2 / N (c = 1 for e >= 0, `under` for e < 0); stores the
+// pre-activations z1..z3, the deltas d1..d3 and the loss term.
+__global__ __launch_bounds__(64) void k_mlp_fwd_bwd(const float* __restrict__ params, const float* __restrict__ x,
+                                                    const float* __restrict__ t, int batch, float under,
+                                                    float* __restrict__ zs, float* __restrict__ ds,
+                                                    float* __restrict__ lterm)
+{
+    using O = MlpOffsets;
+    __shared__ float p[O::COUNT];
+    for (int e = threadIdx.x; e < O::COUNT; e += blockDim.x) p[e] = params[e];
+    __syncthreads();
+    const int s = blockIdx.x * blockDim.x + threadIdx.x;
+    if (s >= batch) return;
+    float z[3 * H], d[3 * H];
+    float *z1 = z, *z2 = z + H, *z3 = z + 2 * H, *d1 = d, *d2 = d + H, *d3 = d + 2 * H;
+    const float y = mlp_eval(p, x + (long long)s * D, z1, z2, z3);
+    const float e = y - t[s];
+    const float c = e >= 0.0f ? 1.0f : under;
+    const float dy = 2.0f * c * e / (float)batch;
+    lterm[s] = c * e * e;
+    for (int j = 0; j < H; ++j) d3[j] = z3[j] > 0.0f ? dy * p[O::W4 + j] : 0.0f;
+    for (int j = 0; j < H; ++j) {
+        float v = 0.0f;
+        for (int i = 0; i < H; ++i) v = fmaf(p[O::W3 + i * H + j], d3[i], v);
+        d2[j] = z2[j] > 0.0f ? v : 0.0f;
+    }
+    for (int j = 0; j < H; ++j) {
+        float v = 0.0f;
+        for (int i = 0; i < H; ++i) v = fmaf(p[O::W2 + i * H + j], d2[i], v);
+        d1[j] = z1[j] > 0.0f ? v : 0.0f;
+    }
+    float* zo = zs + (long long)s * 3 * H;
+    float* dd = ds + (long long)s * 4 * H;
+    for (int j = 0; j < 3 * H; ++j) zo[j] = z[j];
+    for (int j = 0; j < 3 * H; ++j) dd[j] = d[j];
+    dd[3 * H] = dy;
+}
+
+// grad[param] = sum over samples in index order (deterministic, no atomics)
+__global__ __launch_bounds__(256) void k_mlp_grad(const float* __restrict__ x, const float* __restrict__ zs,
+                                                  const float* __restrict__ ds, const float* __restrict__ lterm,
+                                                  int batch, float* __restrict__ grad, float* __restrict__ loss)
+{
+    using O = MlpOffsets;
+    const int q = blockIdx.x * blockDim.x + threadIdx.x;
+    if (q == O::COUNT) {
+        float acc = 0.0f;
+        for (int s = 0; s < batch; ++s) acc += lterm[s];
+        *loss = acc / (float)batch;
+        return;
+    }
+    if (q > O::COUNT) return;
+    float acc = 0.0f;
+    // locate parameter q: delta index di (layer l, unit i) and activation source
+    for (int s = 0; s < batch; ++s) {
+        const float* z = zs + (long long)s * 3 * H;
+        const float* d = ds + (long long)s * 4 * H;
+        float v;
+        if (q < O::B1) {
+            const int i = (q - O::W1) / D, j = (q - O::W1) % D;
+            v = d[i] * x[(long long)s * D + j];
+        } else if (q < O::W2) {
+            v = d[q - O::B1];
+        } else if (q < O::B2) {
+            const int i = (q - O::W2) / H, j = (q - O::W2) % H;
+            v = d[H + i] * fmaxf(z[j], 0.0f);
+        } else if (q < O::W3) {
+            v = d[H + (q - O::B2)];
+        } else if (q < O::B3) {
+            const int i = (q - O::W3) / H, j = (q - O::W3) % H;
+            v = d[2 * H + i] * fmaxf(z[H + j], 0.0f);
+        } else if (q < O::W4) {
+            v = d[2 * H + (q - O::B3)];
+        } else if (q < O::B4) {
+            v = d[3 * H] * fmaxf(z[2 * H + (q - O::W4)], 0.0f);
+        } else {
+            v = d[3 * H];
+        }
+        acc += v;
+    }
+    grad[q] = acc;
+}
+
+__global__ __launch_bounds__(256) void k_adam(float* __restrict__ p, const float* __restrict__ g, float* __restrict__ m,
+                                              float* __restrict__ v, int count, float lr, float b1, float b2,
+                                              float eps, float c1, float c2)
+{
+    const int q = blockIdx.x * blockDim.x + threadIdx.x;
+    if (q >= count) return;
+    const float gq = g[q];
+    const float mq = b1 * m[q] + (1.0f - b1) * gq;
+    const float vq = b2 * v[q] + (1.0f - b2) * gq * gq;
+    m[q] = mq;
+    v[q] = vq;
+    p[q] -= lr * (mq / c1) / (sqrtf(vq / c2) + eps);
+}
+
+// copy slices idx[0..cnt) of a planar stack into / out of a compact stack
+__global__ __launch_bounds__(256) void k_gather(const float* __restrict__ sr, const float* __restrict__ si,
+                                                float* __restrict__ dr, float* __restrict__ di,
+                                                const int* __restrict__ idx, int cnt, long long per, int scatter)
+{
+    const long long total = (long long)cnt * per;
+    for (long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x; e < total;
+         e += (long long)gridDim.x * blockDim.x) {
+        const long long c = e / per, o = e % per;
+        const long long full = (long long)idx[c] * per + o;
+        if (scatter) {
+            dr[full] = sr[e];
+            di[full] = si[e];
+        } else {
+            dr[e] = sr[full];
+            di[e] = si[full];
+        }
+    }
+}
+
+inline int blocks_for(long long n, int tpb, int cap = 8192)
+{
+    long long b = (n + tpb - 1) / tpb;
+    return (int)(b < 1 ? 1 : (b > cap ? cap : b));
+}
+
+}  // namespace
+
+int mlp_param_count() { return MlpOffsets::COUNT; }
+
+hipError_t launch_sketch(float* omr, float* omi, int n, int L, const int* lact, int nslices, int n3,
+                         unsigned long long seed, hipStream_t st)
+{
+    k_sketch<<<blocks_for((long long)nslices * n * L, 256), 256, 0, st>>>(omr, omi, n, L, lact, nslices, n3, seed);
+    return hipGetLastError();
+}
+
+int gram_split(int m) { return m >= 2048 ? 16 : (m >= 256 ? 8 : 1); }
+
+hipError_t launch_cholqr_pass(const float* yr, const float* yi, int m, int L, const int* lact, int nslices,
+                              int pass, double2* part, float* rir, float* rii, double2* rtot, float* rhr,
+                              float* rhi, int* status, hipStream_t st)
+{
+    if (L > kMaxL) return hipErrorInvalidValue;
+    const int ns = gram_split(m);
+    k_gram<<<dim3(ns, nslices), 256, 0, st>>>(yr, yi, m, L, lact, part, ns);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    const size_t lds = 2 * (size_t)L * L * sizeof(double2);
+    if (lds > 64 * 1024) {
+        e = hipFuncSetAttribute((const void*)k_chol, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024 - 1024);
+        if (e != hipSuccess) return e;
+    }
+    k_chol<<<nslices, 256, lds, st>>>(part, ns, L, lact, pass, rir, rii, rtot, rhr, rhi, status);
+    return hipGetLastError();
+}
+
+size_t cholqr_part_bytes(int m, int L, int nslices)
+{
+    return align_up((size_t)gram_split(m) * nslices * L * L * sizeof(double2));
+}
+
+hipError_t launch_rsvd_check(const float2* cols, const double* sigma, const float2* vr, const int* kpred,
+                             const int* lact, int L, double tau, Planes T, int* fallback, int* rank, int nslices,
+                             hipStream_t st)
+{
+    k_rsvd_check<<<nslices, 256, 0, st>>>(cols, sigma, vr, kpred, lact, L, tau, T.re, T.im, fallback, rank);
+    return hipGetLastError();
+}
+
+hipError_t launch_features(const float* yr, const float* yi, int m, int n, int n3, int nslices, double tau,
+                           const int* prev, float* feats, hipStream_t st)
+{
+    k_features<<<nslices, 256, 0, st>>>(yr, yi, m, n, n3, nslices, tau, prev, feats);
+    return hipGetLastError();
+}
+
+hipError_t launch_predict(const float* params, const float* feats, int nslices, int p, int fixed_rank,
+                          int oversample, int L, int* kpred, int* lact, int* fallback, int* rank, hipStream_t st)
+{
+    k_predict<<<(nslices + 63) / 64, 64, 0, st>>>(params, feats, nslices, p, fixed_rank, oversample, L, kpred, lact,
+                                                  fallback, rank);
+    return hipGetLastError();
+}
+
+hipError_t launch_mlp_forward(const float* params, const float* x, float* y, int batch, hipStream_t st)
+{
+    k_mlp_forward<<<(batch + 63) / 64, 64, 0, st>>>(params, x, y, batch);
+    return hipGetLastError();
+}
+
+size_t mlp_train_bytes(int batch)
+{
+    return align_up((size_t)batch * 3 * H * sizeof(float)) + align_up((size_t)batch * 4 * H * sizeof(float)) +
+           align_up((size_t)batch * sizeof(float));
+}
+
+hipError_t launch_mlp_loss_grad(const float* params, const float* x, const float* t, int batch, float under,
+                                float* grad, float* loss, void* ws, hipStream_t st)
+{
+    char* b = static_cast<char*>(ws);
+    float* zs = reinterpret_cast<float*>(b);
+    float* ds = reinterpret_cast<float*>(b + align_up((size_t)batch * 3 * H * sizeof(float)));
+    float* lt = reinterpret_cast<float*>(b + align_up((size_t)batch * 3 * H * sizeof(float)) +
+                                         align_up((size_t)batch * 4 * H * sizeof(float)));
+    k_mlp_fwd_bwd<<<(batch + 63) / 64, 64, 0, st>>>(params, x, t, batch, under, zs, ds, lt);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    k_mlp_grad<<<(MlpOffsets::COUNT + 1 + 255) / 256, 256, 0, st>>>(x, zs, ds, lt, batch, grad, loss);
+    return hipGetLastError();
+}
+
+hipError_t launch_adam(float* p, const float* g, float* m, float* v, int count, int step, float lr, float b1, float b2,
+                       float eps, hipStream_t st)
+{
+    const float c1 = 1.0f - powf(b1, (float)step), c2 = 1.0f - powf(b2, (float)step);
+    k_adam<<<(count + 255) / 256, 256, 0, st>>>(p, g, m, v, count, lr, b1, b2, eps, c1, c2);
+    return hipGetLastError();
+}
+
+hipError_t launch_gather(const float* sr, const float* si, float* dr, float* di, const int* idx, int cnt,
+                         long long per, bool scatter, hipStream_t st)
+{
+    if (cnt <= 0) return hipSuccess;
+    k_gather<<<blocks_for((long long)cnt * per, 256), 256, 0, st>>>(sr, si, dr, di, idx, cnt, per, scatter ? 1 : 0);
+    return hipGetLastError();
+}
+
+}  // namespace tp

@@ -31,7 +31,8 @@ hipEvent_t take_event()
     return e;
 }
 
-const char* const kNames[] = {"rfft", "irfft", "cgemm", "jacobi", "shrink", "tnn_reduce", "tsvd_finish"};
+const char* const kNames[] = {"rfft",    "irfft",   "cgemm",  "jacobi",     "shrink", "tnn_reduce", "tsvd_finish",
+                              "features", "predict", "sketch", "cholqr", "rsvd_check", "gather",     "mlp"};
 
 }  // namespace
 

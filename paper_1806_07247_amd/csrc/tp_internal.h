@@ -89,6 +89,7 @@ struct JacobiArgs {
     double tol;       // rotate a pair when |x^* y| > tol ||x|| ||y||
     float2* cols;     // optional: rotated columns, column-major R x P per slice
     float2* qout;     // optional: accumulated rotations V, column-major P x P per slice
+    int whole;        // 1: one workgroup per slice whenever the slice fits in LDS
 };
 hipError_t launch_jacobi(const JacobiArgs& a, void* scratch, size_t scratch_bytes, hipStream_t s);
 size_t jacobi_scratch_bytes(int m, int n, int nslices, bool withv);
@@ -105,12 +106,42 @@ hipError_t launch_shrink(float* wr, float* wi, const double* sigma, int* keep, i
 // (1/n3) sum over all n3 slices of the singular values, from the half spectrum
 hipError_t launch_tnn_reduce(const double* sigma, int nslices, int P, int n3, double* out, hipStream_t s);
 
+// ------------------------------------------------------------- learned ----
+constexpr int kMaxL = 64;  // widest randomized sketch (l_max)
+int mlp_param_count();
+hipError_t launch_sketch(float* omr, float* omi, int n, int L, const int* lact, int nslices, int n3,
+                         unsigned long long seed, hipStream_t s);
+size_t cholqr_part_bytes(int m, int L, int nslices);
+// one CholeskyQR pass on Y (m x L per slice): Gram in FP64, Cholesky, Rinv (FP32 planar);
+// rtot/rhr/rhi optional (accumulated R and, after pass 1, R^* restricted to the active block)
+hipError_t launch_cholqr_pass(const float* yr, const float* yi, int m, int L, const int* lact, int nslices, int pass,
+                              double2* part, float* rir, float* rii, double2* rtot, float* rhr, float* rhi,
+                              int* status, hipStream_t s);
+hipError_t launch_rsvd_check(const float2* cols, const double* sigma, const float2* vr, const int* kpred,
+                             const int* lact, int L, double tau, Planes T, int* fallback, int* rank, int nslices,
+                             hipStream_t s);
+hipError_t launch_features(const float* yr, const float* yi, int m, int n, int n3, int nslices, double tau,
+                           const int* prev, float* feats, hipStream_t s);
+hipError_t launch_predict(const float* params, const float* feats, int nslices, int p, int fixed_rank, int oversample,
+                          int L, int* kpred, int* lact, int* fallback, int* rank, hipStream_t s);
+hipError_t launch_mlp_forward(const float* params, const float* x, float* y, int batch, hipStream_t s);
+size_t mlp_train_bytes(int batch);
+hipError_t launch_mlp_loss_grad(const float* params, const float* x, const float* t, int batch, float under,
+                                float* grad, float* loss, void* ws, hipStream_t s);
+hipError_t launch_adam(float* p, const float* g, float* m, float* v, int count, int step, float lr, float b1, float b2,
+                       float eps, hipStream_t s);
+hipError_t launch_gather(const float* sr, const float* si, float* dr, float* di, const int* idx, int cnt, long long per,
+                         bool scatter, hipStream_t s);
+
 // ------------------------------------------------------------ tunables ----
 // current value of a TP_PARAM_* setting (tp_set_param), default if unset
 int param(int key);
 
 // ------------------------------------------------------------- tracing ----
-enum KernelId { K_RFFT = 0, K_IRFFT = 1, K_CGEMM = 2, K_JACOBI = 3, K_SHRINK = 4, K_TNN_REDUCE = 5, K_TSVD_FINISH = 6 };
+enum KernelId {
+    K_RFFT = 0, K_IRFFT = 1, K_CGEMM = 2, K_JACOBI = 3, K_SHRINK = 4, K_TNN_REDUCE = 5, K_TSVD_FINISH = 6,
+    K_FEATURES = 7, K_PREDICT = 8, K_SKETCH = 9, K_CHOLQR = 10, K_RSVD_CHECK = 11, K_GATHER = 12, K_MLP = 13
+};
 
 // Records HIP events around the launches in its scope while tracing is on.
 class TraceScope {

@@ -1,0 +1,167 @@
+"""GPU parity of the learned-rank path against the FP64 oracle: MLP forward
+and gradient, Adam, slice features, and the randomized-SVD prox (exact on
+low-rank slices, forced fallback, agreement with the oracle's randomized prox
+on the same Philox sketch).  Tolerances: MLP 1e-5 relative (FP32 vs FP64),
+prox 1e-4 relative Frobenius."""
+import numpy as np
+import pytest
+
+from helpers import rel_fro, say
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+D, H = 8, 64
+
+
+@pytest.fixture(scope="module")
+def tp():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_1806_07247_amd as tp
+    tp._lib.load()
+    return tp
+
+
+def gpu(x, dtype=np.float32):
+    return torch.from_numpy(np.ascontiguousarray(x, dtype=dtype)).to("cuda:0")
+
+
+def rand_params(orc, seed):
+    rng = np.random.default_rng(seed)
+    n = orc.mlp_param_count(D, H)
+    return (rng.standard_normal(n) * 0.3).astype(np.float32)
+
+
+def test_mlp_param_count(tp, orc):
+    assert tp.tp_mlp_param_count() == orc.mlp_param_count(D, H)
+
+
+def test_mlp_forward_and_grad(tp, orc):
+    rng = np.random.default_rng(5)
+    p = rand_params(orc, 1)
+    X = rng.standard_normal((1000, D)).astype(np.float32)
+    t = rng.standard_normal(1000).astype(np.float32)
+    y = tp.tp_mlp_forward(gpu(p), gpu(X)).cpu().numpy()
+    yref = orc.mlp_forward(p, X, D, H)
+    assert np.abs(y - yref).max() <= 1e-5 * max(1.0, np.abs(yref).max())
+    g, l = tp.tp_mlp_loss_grad(gpu(p), gpu(X), gpu(t), under=4.0)
+    lref, gref = orc.mlp_loss_grad(p, X, t, D, H, under=4.0)
+    say(f"loss {float(l):.6f} vs {lref:.6f}; grad max diff {np.abs(g.cpu().numpy() - gref).max():.2e}")
+    assert abs(float(l) - lref) <= 1e-5 * max(1.0, abs(lref))
+    assert np.abs(g.cpu().numpy() - gref).max() <= 1e-5 * max(1.0, np.abs(gref).max())
+    g2, _ = tp.tp_mlp_loss_grad(gpu(p), gpu(X), gpu(t), under=4.0)
+    assert torch.equal(g, g2)  # deterministic reduction order
+
+
+def test_adam_step(tp):
+    rng = np.random.default_rng(8)
+    n = tp.tp_mlp_param_count()
+    p, g = rng.standard_normal(n).astype(np.float32), rng.standard_normal(n).astype(np.float32)
+    m, v = rng.standard_normal(n).astype(np.float32) * 0.1, np.abs(rng.standard_normal(n)).astype(np.float32) * 0.1
+    P, G, M, V = gpu(p), gpu(g), gpu(m), gpu(v)
+    tp.tp_mlp_adam(P, G, M, V, step=3, lr=1e-2, beta1=0.9, beta2=0.999, eps=1e-8)
+    m2 = 0.9 * m + 0.1 * g
+    v2 = 0.999 * v + 0.001 * g * g
+    p2 = p - 1e-2 * (m2 / (1 - 0.9 ** 3)) / (np.sqrt(v2 / (1 - 0.999 ** 3)) + 1e-8)
+    assert np.allclose(P.cpu().numpy(), p2, rtol=1e-5, atol=1e-6)
+
+
+@pytest.mark.parametrize("shape", [(20, 30, 8), (33, 17, 5), (64, 64, 1)])
+def test_features(tp, orc, shape):
+    from paper_1806_07247_amd import inputs
+    Y = inputs.random_tensor(shape, seed=3)
+    h = shape[2] // 2 + 1
+    prev = np.arange(h, dtype=np.int32) % 5
+    for pv in (None, prev):
+        f = tp.tp_slice_features(gpu(Y), 0.7, None if pv is None else gpu(pv, np.int32)).cpu().numpy()
+        ref = orc.slice_features(Y, np.float32(0.7), pv)
+        assert np.abs(f - ref).max() < 1e-5
+
+
+def lowrank(orc, n1, n2, n3, r, seed, noise=0.0):
+    rng = np.random.default_rng(seed)
+    A = orc.tprod(rng.standard_normal((n1, r, n3)), rng.standard_normal((r, n2, n3)))
+    if noise:
+        A = A + noise * rng.standard_normal(A.shape)
+    return A.astype(np.float32)
+
+
+@pytest.mark.parametrize("n1,n2,n3,r", [(64, 48, 6, 3), (40, 70, 5, 4), (128, 128, 8, 6), (200, 160, 4, 10)])
+def test_learned_prox_exact_on_low_rank(tp, orc, n1, n2, n3, r):
+    Y = lowrank(orc, n1, n2, n3, r, seed=n1 + r)
+    tau = 0.2 * orc.tsn(Y)
+    h = n3 // 2 + 1
+    say(f"learned prox low-rank {n1}x{n2}x{n3} r={r}")
+    fb = torch.zeros(h, dtype=torch.int32, device="cuda:0")
+    rk = torch.zeros(h, dtype=torch.int32, device="cuda:0")
+    X = tp.tp_prox_tnn_learned(gpu(Y), tau, fixed_rank=r, oversample=6, power_iters=2, max_rank=32, seed=4,
+                               rank=rk, fallback=fb).cpu().numpy()
+    ref = orc.prox_tnn(Y, np.float32(tau))
+    err = rel_fro(X, ref)
+    say(f"  rel.err {err:.2e} fallback {fb.cpu().numpy().tolist()} rank {rk.cpu().numpy().tolist()}")
+    assert err <= 1e-4
+    assert int(fb.sum()) == 0
+    sig = orc.slice_sigma(Y)[:h]
+    assert np.array_equal(rk.cpu().numpy(), (sig > np.float32(tau)).sum(axis=1))
+
+
+def test_learned_prox_matches_oracle_rsvd(tp, orc):
+    """Same Philox sketch, same predicted counts: GPU (FP32 data, FP64
+    CholeskyQR and rotations) against the FP64 oracle of the randomized prox."""
+    Y = lowrank(orc, 96, 80, 6, 5, seed=11, noise=0.05)
+    tau = 0.15 * orc.tsn(Y)
+    h = 4
+    kp = np.full(h, 5, dtype=np.int32)
+    fb = torch.zeros(h, dtype=torch.int32, device="cuda:0")
+    X = tp.tp_prox_tnn_learned(gpu(Y), tau, fixed_rank=5, oversample=4, power_iters=2, max_rank=16, seed=99,
+                               fallback=fb).cpu().numpy()
+    ref, fbr, _ = orc.prox_tnn_rsvd(Y, np.float32(tau), kp, oversample=4, power=2, lfull=17, seed=99)
+    err = rel_fro(X, ref)
+    say(f"  vs oracle rsvd: rel.err {err:.2e}, fallback gpu {fb.cpu().numpy().tolist()} oracle {fbr.tolist()}")
+    assert np.array_equal(fb.cpu().numpy(), fbr)
+    assert err <= 1e-4
+    exact = orc.prox_tnn(Y, np.float32(tau))
+    say(f"  vs exact prox: rel.err {rel_fro(X, exact):.2e}")
+
+
+def test_learned_prox_forced_fallback(tp, orc):
+    """k = 0 predicted on full-rank slices: every check fails, every slice goes
+    through the full SVD, and the result is the exact prox."""
+    from paper_1806_07247_amd import inputs
+    Y = inputs.random_tensor((48, 40, 6), seed=21)
+    tau = 0.05 * orc.tsn(Y)
+    h = 4
+    fb = torch.zeros(h, dtype=torch.int32, device="cuda:0")
+    info = torch.zeros(h, dtype=torch.int32, device="cuda:0")
+    X = tp.tp_prox_tnn_learned(gpu(Y), tau, fixed_rank=0, oversample=3, max_rank=16, fallback=fb,
+                               info=info).cpu().numpy()
+    assert int(fb.sum()) == h and int(info.min()) > 0
+    assert rel_fro(X, orc.prox_tnn(Y, np.float32(tau))) <= 1e-4
+    # l > max_rank also goes to the full SVD
+    fb.zero_()
+    X = tp.tp_prox_tnn_learned(gpu(Y), tau, fixed_rank=30, oversample=10, max_rank=16, fallback=fb).cpu().numpy()
+    assert int(fb.sum()) == h
+    assert rel_fro(X, orc.prox_tnn(Y, np.float32(tau))) <= 1e-4
+
+
+def test_learned_prox_with_mlp_runs(tp, orc):
+    """An MLP whose output is the constant log1p(4)/log1p(p) predicts k = 4."""
+    Y = lowrank(orc, 50, 50, 4, 4, seed=2)
+    n = tp.tp_mlp_param_count()
+    p = np.zeros(n, dtype=np.float32)
+    p[-1] = np.log1p(4) / np.log1p(50)
+    h = 3
+    rk = torch.zeros(h, dtype=torch.int32, device="cuda:0")
+    fb = torch.zeros(h, dtype=torch.int32, device="cuda:0")
+    tau = 0.1 * orc.tsn(Y)
+    X = tp.tp_prox_tnn_learned(gpu(Y), tau, mlp=gpu(p), oversample=5, max_rank=16, rank=rk, fallback=fb).cpu().numpy()
+    assert int(fb.sum()) == 0
+    assert rel_fro(X, orc.prox_tnn(Y, np.float32(tau))) <= 1e-4
+
+
+def test_learned_prox_deterministic(tp, orc):
+    Y = gpu(lowrank(orc, 70, 60, 6, 5, seed=3, noise=0.01))
+    a = tp.tp_prox_tnn_learned(Y, 1.0, fixed_rank=5, max_rank=24, seed=1)
+    b = tp.tp_prox_tnn_learned(Y, 1.0, fixed_rank=5, max_rank=24, seed=1)
+    assert torch.equal(a, b)
