@@ -118,14 +118,20 @@ int tp_prox_tnn(const float* Y, float* X, int n1, int n2, int n3, float tau, int
  * Q2 R2 (CholeskyQR2); one-sided Jacobi SVD of R2^* = U_r S V_r^*; and
  * W^(k) = Q U_r (S - tau)_+ V_r^* Q2^*.  A slice falls back to the full SVD
  * path of tp_prox_tnn when l > max_rank, or when the check sigma_(kpred+1) <
- * tau fails on the singular values of R2^*.  With l = min(n1,n2) or an exact
- * rank <= l the result equals tp_prox_tnn's up to rounding.
+ * tau fails on the singular values of R2^*.  With accuracy > 0, the kept
+ * Ritz triplets (u_j, sigma_j, v_j), sigma_j > tau, are checked a posteriori:
+ * when sum_j ||Ybar v_j - sigma_j u_j||^2 > accuracy^2 sum_j (sigma_j - tau)^2
+ * on some slice, all slices get one more power iteration, up to
+ * max_power_iters in total, and slices still failing then fall back.
+ * With l = min(n1,n2) or an exact rank <= l the result equals tp_prox_tnn's
+ * up to rounding.
  *   opts       required (see tp_learned_opts); rank, fallback, info optional
  *              device int[floor(n3/2)+1]: the number of singular values
  *              above tau used, 1 for a fallback slice, and the Jacobi sweeps of
  *              the fallback slices (0 for the others).
- * Unlike the other entry points this call waits once for the stream (it reads
- * which slices fell back before enqueueing their full SVD).
+ * Unlike the other entry points this call waits for the stream (once, plus
+ * once per accuracy check): it reads which slices fell back before enqueueing
+ * their full SVD.
  * Features (TP_MLP_INPUTS = 8, FP32, per slice): log(tau / rms sigma) with
  * rms sigma = ||Ybar^(k)||_F / sqrt(min(n1,n2)); log(max column norm / tau);
  * prev_rank/min(n1,n2) and 1 when prev_rank is given (else 0, 0);
@@ -143,6 +149,8 @@ typedef struct tp_learned_opts {
     int power_iters;           /* subspace iterations (2) */
     int max_rank;              /* l_max <= 64: wider slices use the full SVD */
     unsigned long long seed;   /* sketch seed */
+    float accuracy;            /* a posteriori residual tolerance, 0 = no check */
+    int max_power_iters;       /* cap on power iterations with the check */
 } tp_learned_opts;
 size_t tp_prox_tnn_learned_workspace_size(int n1, int n2, int n3, int max_rank);
 int tp_prox_tnn_learned(const float* Y, float* X, int n1, int n2, int n3, float tau,

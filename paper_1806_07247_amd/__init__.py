@@ -150,7 +150,8 @@ def tp_prox_tnn_learned_workspace_size(n1, n2, n3, max_rank=64):
 
 
 def tp_prox_tnn_learned(Y, tau, mlp=None, fixed_rank=0, prev_rank=None, oversample=10, power_iters=2,
-                        max_rank=64, seed=0, out=None, rank=None, fallback=None, info=None, workspace=None):
+                        max_rank=64, seed=0, accuracy=2e-5, max_power_iters=8, out=None, rank=None, fallback=None,
+                        info=None, workspace=None):
     """Learned-rank prox (see include/tp.h); mlp is a float32 device tensor of
     tp_mlp_param_count() parameters or None (then every slice uses fixed_rank).
     rank / fallback / info: optional int32 device tensors of half_slices(n3)."""
@@ -159,7 +160,7 @@ def tp_prox_tnn_learned(Y, tau, mlp=None, fixed_rank=0, prev_rank=None, oversamp
     n1, n2, n3 = Y.shape
     X = out if out is not None else torch.empty_like(Y)
     opts = _lib.LearnedOpts(_ptr(mlp), int(fixed_rank), _ptr(prev_rank), int(oversample), int(power_iters),
-                            int(max_rank), int(seed) & 0xFFFFFFFFFFFFFFFF)
+                            int(max_rank), int(seed) & 0xFFFFFFFFFFFFFFFF, float(accuracy), int(max_power_iters))
     ws_bytes = lib.tp_prox_tnn_learned_workspace_size(n1, n2, n3, int(max_rank))
     ws = workspace if workspace is not None else _workspace(ws_bytes, Y.device)
     st = lib.tp_prox_tnn_learned(Y.data_ptr(), X.data_ptr(), n1, n2, n3, float(tau), ctypes.byref(opts),

@@ -41,7 +41,7 @@ _U64 = ctypes.c_ulonglong
 class LearnedOpts(ctypes.Structure):
     """tp_learned_opts of include/tp.h"""
     _fields_ = [("mlp", _VP), ("fixed_rank", _I), ("prev_rank", _VP), ("oversample", _I),
-                ("power_iters", _I), ("max_rank", _I), ("seed", _U64)]
+                ("power_iters", _I), ("max_rank", _I), ("seed", _U64), ("accuracy", _F), ("max_power_iters", _I)]
 
 
 SIGNATURES.update({

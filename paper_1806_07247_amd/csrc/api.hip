@@ -1,6 +1,7 @@
 // C-ABI entry points of libtp.so: argument checks, workspace carving and the
 // kernel sequence of each operation.  See include/tp.h for the contract.
 #include <cmath>
+#include <algorithm>
 #include <utility>
 #include <vector>
 
@@ -149,7 +150,8 @@ struct LearnedLayout {
     float2* jv;
     double* jsig;
     float* feats;
-    int *kpred, *lact, *fb, *rank, *status, *idx, *cinfo, *crank;
+    tp::Planes vp, cp, t1, t2;      // V_r, U_r S (planar L x L), residual products (m x L)
+    int *kpred, *lact, *fb, *rank, *status, *idx, *cinfo, *crank, *prefb, *bad;
 };
 
 tp::Arena learned_arena(void* ws, size_t bytes, int n1, int n2, int n3, int Lw, LearnedLayout* out)
@@ -180,6 +182,10 @@ tp::Arena learned_arena(void* ws, size_t bytes, int n1, int n2, int n3, int Lw, 
     t.rh = planes(h * L * L);
     t.T = planes(h * L * L);
     t.m1 = planes(h * L * n2);
+    t.vp = planes(h * L * L);
+    t.cp = planes(h * L * L);
+    t.t1 = planes(h * n1 * L);
+    t.t2 = planes(h * n1 * L);
     const int mx = n1 > n2 ? n1 : n2;
     t.part = reinterpret_cast<double2*>(ar.take<char>(tp::cholqr_part_bytes(mx, Lw, (int)h)));
     t.rtot = ar.take<double2>(h * L * L);
@@ -195,6 +201,8 @@ tp::Arena learned_arena(void* ws, size_t bytes, int n1, int n2, int n3, int Lw, 
     t.idx = ar.take<int>(h);
     t.cinfo = ar.take<int>(h);
     t.crank = ar.take<int>(h);
+    t.prefb = ar.take<int>(h);
+    t.bad = ar.take<int>(h);
     if (out) *out = t;
     return ar;
 }
@@ -464,75 +472,116 @@ int tp_prox_tnn_learned(const float* Y, float* X, int n1, int n2, int n3, float 
     if (!Y || !X || !opts) return TP_ERR_ARG;
     if (!(tau >= 0.0f) || std::isinf(tau)) return TP_ERR_ARG;
     if (opts->max_rank < 1 || opts->max_rank > tp::kMaxL || opts->oversample < 0 || opts->power_iters < 0 ||
-        opts->power_iters > 16 || (!opts->mlp && opts->fixed_rank < 0))
+        opts->power_iters > 16 || opts->max_power_iters > 64 || !(opts->accuracy >= 0.0f) ||
+        (!opts->mlp && opts->fixed_rank < 0))
         return TP_ERR_ARG;
     if (bad_dim(n1) || bad_dim(n2) || bad_dim(n3) || n3 > kMaxN3) return TP_ERR_SHAPE;
     if (bad_slice(n1, n2)) return TP_ERR_SHAPE;
     if ((n1 < n2 ? n2 : n1) > 2048) return TP_ERR_UNSUPPORTED;
-    const int L = opts->max_rank;
     LearnedLayout W;
-    tp::Arena ar = learned_arena(workspace, workspace_bytes, n1, n2, n3, L, &W);
+    tp::Arena ar = learned_arena(workspace, workspace_bytes, n1, n2, n3, opts->max_rank, &W);
     if (!ar.ok) return TP_ERR_WORKSPACE;
     hipStream_t s = as_stream(stream);
     const int h = tp::half_slices(n3), p = n1 < n2 ? n1 : n2, rl = (n3 % 2 == 0) ? 1 : 0;
     const long long mn = (long long)n1 * n2;
     int* fb = fallback ? fallback : W.fb;
     int* rk = rank ? rank : W.rank;
-    tp::Planes ybar = W.full.ybar;
+    const tp::Planes ybar = W.full.ybar;
 
     TP_LAUNCH(tp::K_RFFT, s, tp::launch_rfft(Y, ybar.re, ybar.im, mn, n3, s));
     // predicted count per slice and sketch width
     TP_LAUNCH(tp::K_FEATURES, s,
               tp::launch_features(ybar.re, ybar.im, n1, n2, n3, h, (double)tau, opts->prev_rank, W.feats, s));
     TP_LAUNCH(tp::K_PREDICT, s,
-              tp::launch_predict(opts->mlp, W.feats, h, p, opts->fixed_rank, opts->oversample, L, W.kpred, W.lact,
-                                 fb, rk, s));
+              tp::launch_predict(opts->mlp, W.feats, h, p, opts->fixed_rank, opts->oversample, opts->max_rank,
+                                 W.kpred, W.lact, W.prefb, rk, s));
     TP_TRY(hipMemsetAsync(W.status, 0, h * sizeof(int), s));
-    // range finder: Y = Ybar Om, re-orthonormalised; power iterations
-    TP_LAUNCH(tp::K_SKETCH, s, tp::launch_sketch(W.om.re, W.om.im, n2, L, W.lact, h, n3, opts->seed, s));
-    int st = gemm(ybar, n2, mn, tp::OP_N, W.om, L, (long long)n2 * L, tp::OP_N, W.ya, L, (long long)n1 * L, n1, L, n2,
-                  h, rl, s);
-    if (st == TP_OK) st = cholqr2(W, W.ya, W.yb, n1, L, h, rl, false, s);
-    for (int it = 0; st == TP_OK && it < opts->power_iters; ++it) {
-        st = gemm(ybar, n2, mn, tp::OP_C, W.ya, L, (long long)n1 * L, tp::OP_N, W.za, L, (long long)n2 * L, n2, L, n1,
-                  h, rl, s);
-        if (st == TP_OK) st = cholqr2(W, W.za, W.zb, n2, L, h, rl, false, s);
-        if (st == TP_OK)
-            st = gemm(ybar, n2, mn, tp::OP_N, W.za, L, (long long)n2 * L, tp::OP_N, W.ya, L, (long long)n1 * L, n1, L,
-                      n2, h, rl, s);
+    // sketch width of this call: the widest predicted l, rounded up to 8
+    std::vector<int> hl(h), hpre(h), hbad(h), hfb(h);
+    TP_TRY(hipMemcpyAsync(hl.data(), W.lact, h * sizeof(int), hipMemcpyDeviceToHost, s));
+    TP_TRY(hipMemcpyAsync(hpre.data(), W.prefb, h * sizeof(int), hipMemcpyDeviceToHost, s));
+    TP_TRY(hipStreamSynchronize(s));
+    int lmax = 0;
+    for (int k = 0; k < h; ++k)
+        if (!hpre[k] && hl[k] > lmax) lmax = hl[k];
+    const int L = lmax > 0 ? std::min(((lmax + 7) / 8) * 8, opts->max_rank) : 0;
+
+    int st = TP_OK;
+    if (L == 0) {  // every slice goes to the full SVD
+        TP_TRY(hipMemcpyAsync(fb, W.prefb, h * sizeof(int), hipMemcpyDeviceToDevice, s));
+    } else {
+        const long long sy = (long long)n1 * L, sz = (long long)n2 * L, sl = (long long)L * L;
+        // range finder: Y = Ybar Om, re-orthonormalised; power iterations
+        TP_LAUNCH(tp::K_SKETCH, s, tp::launch_sketch(W.om.re, W.om.im, n2, L, W.lact, h, n3, opts->seed, s));
+        st = gemm(ybar, n2, mn, tp::OP_N, W.om, L, sz, tp::OP_N, W.ya, L, sy, n1, L, n2, h, rl, s);
         if (st == TP_OK) st = cholqr2(W, W.ya, W.yb, n1, L, h, rl, false, s);
+        auto power_iteration = [&]() {
+            int r = gemm(ybar, n2, mn, tp::OP_C, W.ya, L, sy, tp::OP_N, W.za, L, sz, n2, L, n1, h, rl, s);
+            if (r == TP_OK) r = cholqr2(W, W.za, W.zb, n2, L, h, rl, false, s);
+            if (r == TP_OK) r = gemm(ybar, n2, mn, tp::OP_N, W.za, L, sz, tp::OP_N, W.ya, L, sy, n1, L, n2, h, rl, s);
+            if (r == TP_OK) r = cholqr2(W, W.ya, W.yb, n1, L, h, rl, false, s);
+            return r;
+        };
+        for (int it = 0; st == TP_OK && it < opts->power_iters; ++it) st = power_iteration();
+        if (st != TP_OK) return st;
+        const int qmax = std::max(opts->max_power_iters, opts->power_iters);
+        int q = opts->power_iters;
+        while (true) {
+            // Bh = Ybar^* Q = Q2 R2
+            st = gemm(ybar, n2, mn, tp::OP_C, W.ya, L, sy, tp::OP_N, W.za, L, sz, n2, L, n1, h, rl, s);
+            if (st == TP_OK) st = cholqr2(W, W.za, W.zb, n2, L, h, rl, true, s);
+            if (st != TP_OK) return st;
+            // SVD of R2^* (one workgroup per slice, LDS), count check, core T
+            tp::JacobiArgs j{};
+            j.yr = W.rh.re;
+            j.yi = W.rh.im;
+            j.sigma = W.jsig;
+            j.m = L;
+            j.n = L;
+            j.nslices = h;
+            j.max_sweeps = tp::param(TP_PARAM_JACOBI_SWEEPS);
+            j.tol = tp::jacobi_tol(L);
+            j.cols = W.jcols;
+            j.qout = W.jv;
+            j.whole = 1;
+            TP_LAUNCH(tp::K_JACOBI, s, tp::launch_jacobi(j, nullptr, 0, s));
+            TP_LAUNCH(tp::K_RSVD_CHECK, s,
+                      tp::launch_rsvd_check(W.jcols, W.jsig, W.jv, W.kpred, W.lact, W.prefb, L, (double)tau, W.T, fb,
+                                            rk, h, s));
+            if (!(opts->accuracy > 0.0f)) break;
+            // a posteriori check: residuals Ybar v_j - sigma_j u_j of the kept Ritz triplets
+            TP_LAUNCH(tp::K_ACCURACY, s, tp::launch_cm_to_planar(W.jv, W.vp, L, h, s));
+            TP_LAUNCH(tp::K_ACCURACY, s, tp::launch_cm_to_planar(W.jcols, W.cp, L, h, s));
+            st = gemm(ybar, n2, mn, tp::OP_N, W.za, L, sz, tp::OP_N, W.yb, L, sy, n1, L, n2, h, rl, s);  // Ybar Q2
+            if (st == TP_OK) st = gemm(W.yb, L, sy, tp::OP_N, W.vp, L, sl, tp::OP_N, W.t1, L, sy, n1, L, L, h, rl, s);
+            if (st == TP_OK) st = gemm(W.ya, L, sy, tp::OP_N, W.cp, L, sl, tp::OP_N, W.t2, L, sy, n1, L, L, h, rl, s);
+            if (st != TP_OK) return st;
+            TP_LAUNCH(tp::K_ACCURACY, s,
+                      tp::launch_accuracy(W.t1, W.t2, W.jsig, W.lact, n1, L, (double)tau, (double)opts->accuracy,
+                                          W.bad, h, s));
+            TP_TRY(hipMemcpyAsync(hbad.data(), W.bad, h * sizeof(int), hipMemcpyDeviceToHost, s));
+            TP_TRY(hipMemcpyAsync(hfb.data(), fb, h * sizeof(int), hipMemcpyDeviceToHost, s));
+            TP_TRY(hipStreamSynchronize(s));
+            bool any = false;
+            for (int k = 0; k < h; ++k) any = any || (hbad[k] && !hfb[k]);
+            if (!any) break;
+            if (q >= qmax) {  // still inaccurate: those slices take the full SVD
+                for (int k = 0; k < h; ++k) hfb[k] = hfb[k] || hbad[k];
+                TP_TRY(hipMemcpy(fb, hfb.data(), h * sizeof(int), hipMemcpyHostToDevice));
+                break;
+            }
+            st = power_iteration();
+            if (st != TP_OK) return st;
+            ++q;
+        }
+        // W = Q (T Q2^*)
+        st = gemm(W.T, L, sl, tp::OP_N, W.za, L, sz, tp::OP_C, W.m1, n2, (long long)L * n2, L, n2, L, h, rl, s);
+        if (st == TP_OK)
+            st = gemm(W.ya, L, sy, tp::OP_N, W.m1, n2, (long long)L * n2, tp::OP_N, W.wbar, n2, mn, n1, n2, L, h, rl, s);
+        if (st != TP_OK) return st;
     }
-    // Bh = Ybar^* Q = Q2 R2
-    if (st == TP_OK)
-        st = gemm(ybar, n2, mn, tp::OP_C, W.ya, L, (long long)n1 * L, tp::OP_N, W.za, L, (long long)n2 * L, n2, L, n1, h,
-                  rl, s);
-    if (st == TP_OK) st = cholqr2(W, W.za, W.zb, n2, L, h, rl, true, s);
-    if (st != TP_OK) return st;
-    // SVD of R2^* (one workgroup per slice, LDS), check, core T
-    tp::JacobiArgs j{};
-    j.yr = W.rh.re;
-    j.yi = W.rh.im;
-    j.sigma = W.jsig;
-    j.m = L;
-    j.n = L;
-    j.nslices = h;
-    j.max_sweeps = tp::param(TP_PARAM_JACOBI_SWEEPS);
-    j.tol = tp::jacobi_tol(L);
-    j.cols = W.jcols;
-    j.qout = W.jv;
-    j.whole = 1;
-    TP_LAUNCH(tp::K_JACOBI, s, tp::launch_jacobi(j, nullptr, 0, s));
-    TP_LAUNCH(tp::K_RSVD_CHECK, s,
-              tp::launch_rsvd_check(W.jcols, W.jsig, W.jv, W.kpred, W.lact, L, (double)tau, W.T, fb, rk, h, s));
-    // W = Q (T Q2^*)
-    st = gemm(W.T, L, (long long)L * L, tp::OP_N, W.za, L, (long long)n2 * L, tp::OP_C, W.m1, n2, (long long)L * n2, L,
-              n2, L, h, rl, s);
-    if (st == TP_OK)
-        st = gemm(W.ya, L, (long long)n1 * L, tp::OP_N, W.m1, n2, (long long)L * n2, tp::OP_N, W.wbar, n2, mn, n1, n2,
-                  L, h, rl, s);
-    if (st != TP_OK) return st;
     // fallback slices: full SVD on a compact batch
-    std::vector<int> hfb(h), hidx;
+    std::vector<int> hidx;
     TP_TRY(hipMemcpyAsync(hfb.data(), fb, h * sizeof(int), hipMemcpyDeviceToHost, s));
     TP_TRY(hipStreamSynchronize(s));
     for (int k = 0; k < h; ++k)
@@ -546,12 +595,11 @@ int tp_prox_tnn_learned(const float* Y, float* X, int n1, int n2, int n3, float 
         st = run_svt(F, W.cy, n1, n2, cnt, 0, 0, (double)tau, info ? W.cinfo : nullptr, W.crank, s);
         if (st != TP_OK) return st;
         TP_LAUNCH(tp::K_GATHER, s, tp::launch_gather(W.cy.re, W.cy.im, W.wbar.re, W.wbar.im, W.idx, cnt, mn, true, s));
-        std::vector<int> crank(cnt), cinfo(cnt, 0);
+        std::vector<int> crank(cnt), cinfo(cnt, 0), hrank(h);
         TP_TRY(hipMemcpyAsync(crank.data(), W.crank, cnt * sizeof(int), hipMemcpyDeviceToHost, s));
         if (info) TP_TRY(hipMemcpyAsync(cinfo.data(), W.cinfo, cnt * sizeof(int), hipMemcpyDeviceToHost, s));
+        TP_TRY(hipMemcpyAsync(hrank.data(), rk, h * sizeof(int), hipMemcpyDeviceToHost, s));
         TP_TRY(hipStreamSynchronize(s));
-        std::vector<int> hrank(h);
-        TP_TRY(hipMemcpy(hrank.data(), rk, h * sizeof(int), hipMemcpyDeviceToHost));
         for (int c = 0; c < cnt; ++c) {
             hrank[hidx[c]] = crank[c];
             hinfo[hidx[c]] = cinfo[c];

@@ -2,7 +2,7 @@
 //   C^(s) = op(A^(s)) op(B^(s)),  s = 0 .. nslices-1,
 // the dense per-slice step of Algorithm 1 (Cbar^(i) = Abar^(i) Bbar^(i) for the
 // ceil((n3+1)/2) leading slices, eq (10)), also used for the reconstruction
-// products of the singular value thresholding.
+// products of the singular value thresholding and the randomized range finder.
 //
 // Complex products use the 4-real-product form  Cr = ArBr - AiBi,
 // Ci = ArBi + AiBr.  Real slices (the DC slice and, for even n3, the middle
@@ -15,10 +15,13 @@
 //          v_mfma_f32_16x16x32_bf16
 //   BF16   hi*hi only
 //
-// Tiling: 256 threads = 4 wavefronts in a 2x2 arrangement; workgroup tile
-// 64x64 (complex), wavefront tile 32x32 = 2x2 MFMA tiles of 16x16.  Operand
-// tiles are staged through LDS (double buffered) with the k index contiguous
-// so that each lane reads its MFMA operands with 16-byte LDS loads.
+// Tiling: 256 threads = 4 wavefronts; a workgroup tile of BM x BN (complex)
+// outputs is split WGM x WGN over the wavefronts, each wavefront owning
+// TM x TN MFMA tiles of 16 x 16.  Operand panels (BM x BK of op(A), BN x BK of
+// op(B)) are staged through LDS, double buffered, with k contiguous so that
+// each lane reads its MFMA operands with 16-byte LDS loads.  Tile shapes from
+// 64 x 64 to 256 x 16 cover square products and the skinny products of the
+// randomized SVD (a few dozen columns).
 #include "tp_internal.h"
 
 namespace tp {
@@ -28,7 +31,19 @@ typedef float floatx4 __attribute__((ext_vector_type(4)));
 typedef short shortx8 __attribute__((ext_vector_type(8)));
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 
-constexpr int BM = 64, BN = 64;
+template <int BM_, int BN_, int WGM_, int WGN_>
+struct Tile {
+    static constexpr int BM = BM_, BN = BN_, WGM = WGM_, WGN = WGN_;
+    static constexpr int WM = BM / WGM, WN = BN / WGN;
+    static constexpr int TM = WM / 16, TN = WN / 16;
+    static_assert(WGM * WGN == 4, "four wavefronts");
+    static_assert(TM >= 1 && TN >= 1 && WM % 16 == 0 && WN % 16 == 0, "16 x 16 MFMA tiles");
+};
+using T64x64 = Tile<64, 64, 2, 2>;
+using T128x128 = Tile<128, 128, 2, 2>;
+using T128x64 = Tile<128, 64, 2, 2>;
+using T128x32 = Tile<128, 32, 4, 1>;
+using T256x16 = Tile<256, 16, 4, 1>;
 
 struct SliceView {
     const float *ar, *ai, *br, *bi;
@@ -51,106 +66,103 @@ __device__ __forceinline__ SliceView slice_view(const CgemmArgs& p, int s)
     return v;
 }
 
-// Loads one BKxBM (A) and BKxBN (B) panel of op(A), op(B) into registers.
-// Each thread holds 4 consecutive elements of each plane.
-//   A, OP_N: thread -> (row t/ (BK/4) , k group)    contiguous along k
-//   A, OP_C: thread -> (k  t / 16, row group of 4)  contiguous along rows
-//   B, OP_N: thread -> (k  t / 16, col group of 4)  contiguous along cols
-//   B, OP_C: thread -> (col t / (BK/4), k group)    contiguous along k
-template <int OPA, int OPB, int BK>
+// Register staging of one BM x BK panel of op(A) and BN x BK panel of op(B):
+// the panels are cut in groups of 4 consecutive elements along the
+// contiguous direction of the source, groups spread over the 256 threads.
+//   A, OP_N: group -> (row, 4 k)    A, OP_C: group -> (k, 4 rows)
+//   B, OP_N: group -> (k, 4 cols)   B, OP_C: group -> (col, 4 k)
+template <int OPA, int OPB, int BM, int BN, int BK>
 struct PanelLoader {
-    static constexpr int KQ = BK / 4;            // float4 groups along k
-    static constexpr int NLOAD = (BM * BK) / 256 / 4;  // float4 groups per thread
-    float a_r[NLOAD][4], a_i[NLOAD][4], b_r[NLOAD][4], b_i[NLOAD][4];
+    static constexpr int KQ = BK / 4;
+    static constexpr int GA = BM * BK / 4, GB = BN * BK / 4;
+    static constexpr int NA = (GA + 255) / 256, NB = (GB + 255) / 256;
+    float a_r[NA][4], a_i[NA][4], b_r[NB][4], b_i[NB][4];
 
     __device__ __forceinline__ void load(const SliceView& v, const CgemmArgs& p, int m0, int n0, int k0, int tid)
     {
 #pragma unroll
-        for (int u = 0; u < NLOAD; ++u) {
-            const int t = tid + u * 256;
-            if (OPA == OP_N) {
-                const int r = t / KQ, kq = (t % KQ) * 4, row = m0 + r;
+        for (int u = 0; u < NA; ++u) {
+            const int g = tid + u * 256;
 #pragma unroll
-                for (int e = 0; e < 4; ++e) {
-                    const int kk = k0 + kq + e;
-                    const bool in = row < p.m && kk < v.K;
-                    const long long off = (long long)row * p.lda + kk;
-                    a_r[u][e] = in ? v.ar[off] : 0.0f;
-                    a_i[u][e] = in ? v.ai[off] : 0.0f;
+            for (int e = 0; e < 4; ++e) {
+                int row, kk;
+                long long off;
+                if (OPA == OP_N) {
+                    row = m0 + g / KQ;
+                    kk = k0 + (g % KQ) * 4 + e;
+                    off = (long long)row * p.lda + kk;
+                } else {
+                    kk = k0 + g / (BM / 4);
+                    row = m0 + (g % (BM / 4)) * 4 + e;
+                    off = (long long)kk * p.lda + row;
                 }
-            } else {
-                const int kk = k0 + t / (BM / 4), r4 = (t % (BM / 4)) * 4;
-#pragma unroll
-                for (int e = 0; e < 4; ++e) {
-                    const int row = m0 + r4 + e;
-                    const bool in = row < p.m && kk < v.K;
-                    const long long off = (long long)kk * p.lda + row;
-                    a_r[u][e] = in ? v.ar[off] : 0.0f;
-                    a_i[u][e] = in ? -v.ai[off] : 0.0f;
-                }
+                const bool in = g < GA && row < p.m && kk < v.K;
+                a_r[u][e] = in ? v.ar[off] : 0.0f;
+                a_i[u][e] = in ? (OPA == OP_C ? -v.ai[off] : v.ai[off]) : 0.0f;
             }
-            if (OPB == OP_N) {
-                const int kk = k0 + t / (BN / 4), c4 = (t % (BN / 4)) * 4;
+        }
 #pragma unroll
-                for (int e = 0; e < 4; ++e) {
-                    const int col = n0 + c4 + e;
-                    const bool in = col < p.n && kk < v.K;
-                    const long long off = (long long)kk * p.ldb + col;
-                    b_r[u][e] = in ? v.br[off] : 0.0f;
-                    b_i[u][e] = in ? v.bi[off] : 0.0f;
-                }
-            } else {
-                const int c = t / KQ, kq = (t % KQ) * 4, col = n0 + c;
+        for (int u = 0; u < NB; ++u) {
+            const int g = tid + u * 256;
 #pragma unroll
-                for (int e = 0; e < 4; ++e) {
-                    const int kk = k0 + kq + e;
-                    const bool in = col < p.n && kk < v.K;
-                    const long long off = (long long)col * p.ldb + kk;
-                    b_r[u][e] = in ? v.br[off] : 0.0f;
-                    b_i[u][e] = in ? -v.bi[off] : 0.0f;
+            for (int e = 0; e < 4; ++e) {
+                int col, kk;
+                long long off;
+                if (OPB == OP_N) {
+                    kk = k0 + g / (BN / 4);
+                    col = n0 + (g % (BN / 4)) * 4 + e;
+                    off = (long long)kk * p.ldb + col;
+                } else {
+                    col = n0 + g / KQ;
+                    kk = k0 + (g % KQ) * 4 + e;
+                    off = (long long)col * p.ldb + kk;
                 }
+                const bool in = g < GB && col < p.n && kk < v.K;
+                b_r[u][e] = in ? v.br[off] : 0.0f;
+                b_i[u][e] = in ? (OPB == OP_C ? -v.bi[off] : v.bi[off]) : 0.0f;
             }
         }
     }
 
-    // Writes the staged panel as sX[row][k] (row = m for A, n for B) with
-    // leading dimension LDK, via a per-element conversion functor.
+    // writes the panels as sA[row][k], sB[col][k] (leading dimension LDK)
     template <int LDK, class Store>
     __device__ __forceinline__ void store(int tid, Store&& st) const
     {
 #pragma unroll
-        for (int u = 0; u < NLOAD; ++u) {
-            const int t = tid + u * 256;
-            if (OPA == OP_N) {
-                const int r = t / KQ, kq = (t % KQ) * 4;
+        for (int u = 0; u < NA; ++u) {
+            const int g = tid + u * 256;
+            if (g >= GA) continue;
 #pragma unroll
-                for (int e = 0; e < 4; ++e) st.a(r * LDK + kq + e, a_r[u][e], a_i[u][e]);
-            } else {
-                const int kk = t / (BM / 4), r4 = (t % (BM / 4)) * 4;
-#pragma unroll
-                for (int e = 0; e < 4; ++e) st.a((r4 + e) * LDK + kk, a_r[u][e], a_i[u][e]);
+            for (int e = 0; e < 4; ++e) {
+                const int idx = (OPA == OP_N) ? (g / KQ) * LDK + (g % KQ) * 4 + e
+                                              : ((g % (BM / 4)) * 4 + e) * LDK + g / (BM / 4);
+                st.a(idx, a_r[u][e], a_i[u][e]);
             }
-            if (OPB == OP_N) {
-                const int kk = t / (BN / 4), c4 = (t % (BN / 4)) * 4;
+        }
 #pragma unroll
-                for (int e = 0; e < 4; ++e) st.b((c4 + e) * LDK + kk, b_r[u][e], b_i[u][e]);
-            } else {
-                const int c = t / KQ, kq = (t % KQ) * 4;
+        for (int u = 0; u < NB; ++u) {
+            const int g = tid + u * 256;
+            if (g >= GB) continue;
 #pragma unroll
-                for (int e = 0; e < 4; ++e) st.b(c * LDK + kq + e, b_r[u][e], b_i[u][e]);
+            for (int e = 0; e < 4; ++e) {
+                const int idx = (OPB == OP_N) ? ((g % (BN / 4)) * 4 + e) * LDK + g / (BN / 4)
+                                              : (g / KQ) * LDK + (g % KQ) * 4 + e;
+                st.b(idx, b_r[u][e], b_i[u][e]);
             }
         }
     }
 };
 
+template <class T>
 __device__ __forceinline__ void write_tile(const SliceView& v, const CgemmArgs& p, int m0, int n0, int wr, int wc,
-                                           int lane, const floatx4 (&accr)[2][2], const floatx4 (&acci)[2][2])
+                                           int lane, const floatx4 (&accr)[T::TM][T::TN],
+                                           const floatx4 (&acci)[T::TM][T::TN])
 {
     const int g = lane >> 4, c16 = lane & 15;
 #pragma unroll
-    for (int ti = 0; ti < 2; ++ti)
+    for (int ti = 0; ti < T::TM; ++ti)
 #pragma unroll
-        for (int tj = 0; tj < 2; ++tj)
+        for (int tj = 0; tj < T::TN; ++tj)
 #pragma unroll
             for (int j = 0; j < 4; ++j) {
                 const int row = m0 + wr + 16 * ti + 4 * g + j;
@@ -170,9 +182,10 @@ struct StoreF32 {
     __device__ __forceinline__ void b(int i, float r, float im) const { br[i] = r; bi[i] = im; }
 };
 
-template <int OPA, int OPB>
+template <int OPA, int OPB, class T>
 __global__ __launch_bounds__(256) void k_cgemm_f32(CgemmArgs p)
 {
+    constexpr int BM = T::BM, BN = T::BN, TM = T::TM, TN = T::TN;
     constexpr int BK = 16, LDK = BK + 4;
     __shared__ __attribute__((aligned(16))) float sAr[2][BM * LDK];
     __shared__ __attribute__((aligned(16))) float sAi[2][BM * LDK];
@@ -182,19 +195,19 @@ __global__ __launch_bounds__(256) void k_cgemm_f32(CgemmArgs p)
     const SliceView v = slice_view(p, blockIdx.z);
     const int m0 = blockIdx.y * BM, n0 = blockIdx.x * BN;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    const int wr = (wave >> 1) * 32, wc = (wave & 1) * 32;
+    const int wr = (wave / T::WGN) * T::WM, wc = (wave % T::WGN) * T::WN;
     const int g = lane >> 4, r16 = lane & 15;
 
-    floatx4 accr[2][2], acci[2][2];
+    floatx4 accr[TM][TN], acci[TM][TN];
 #pragma unroll
-    for (int ti = 0; ti < 2; ++ti)
+    for (int ti = 0; ti < TM; ++ti)
 #pragma unroll
-        for (int tj = 0; tj < 2; ++tj) {
+        for (int tj = 0; tj < TN; ++tj) {
             accr[ti][tj] = floatx4{0.f, 0.f, 0.f, 0.f};
             acci[ti][tj] = floatx4{0.f, 0.f, 0.f, 0.f};
         }
 
-    PanelLoader<OPA, OPB, BK> ld;
+    PanelLoader<OPA, OPB, BM, BN, BK> ld;
     const int nk = (v.K + BK - 1) / BK;
     if (nk > 0) {
         ld.load(v, p, m0, n0, 0, tid);
@@ -205,11 +218,14 @@ __global__ __launch_bounds__(256) void k_cgemm_f32(CgemmArgs p)
         const int cur = c & 1;
         if (c + 1 < nk) ld.load(v, p, m0, n0, (c + 1) * BK, tid);
         // lane (g, r16) of MFMA step s uses k = 4g + s: one 16-byte LDS read per operand
-        float4 fa_r[2], fa_i[2], fb_r[2], fb_i[2];
+        float4 fa_r[TM], fa_i[TM], fb_r[TN], fb_i[TN];
 #pragma unroll
-        for (int t = 0; t < 2; ++t) {
+        for (int t = 0; t < TM; ++t) {
             fa_r[t] = *reinterpret_cast<const float4*>(&sAr[cur][(wr + 16 * t + r16) * LDK + 4 * g]);
             fa_i[t] = *reinterpret_cast<const float4*>(&sAi[cur][(wr + 16 * t + r16) * LDK + 4 * g]);
+        }
+#pragma unroll
+        for (int t = 0; t < TN; ++t) {
             fb_r[t] = *reinterpret_cast<const float4*>(&sBr[cur][(wc + 16 * t + r16) * LDK + 4 * g]);
             fb_i[t] = *reinterpret_cast<const float4*>(&sBi[cur][(wc + 16 * t + r16) * LDK + 4 * g]);
         }
@@ -217,18 +233,18 @@ __global__ __launch_bounds__(256) void k_cgemm_f32(CgemmArgs p)
 #pragma unroll
             for (int s = 0; s < 4; ++s)
 #pragma unroll
-                for (int ti = 0; ti < 2; ++ti)
+                for (int ti = 0; ti < TM; ++ti)
 #pragma unroll
-                    for (int tj = 0; tj < 2; ++tj)
+                    for (int tj = 0; tj < TN; ++tj)
                         accr[ti][tj] = __builtin_amdgcn_mfma_f32_16x16x4f32(
                             (&fa_r[ti].x)[s], (&fb_r[tj].x)[s], accr[ti][tj], 0, 0, 0);
         } else {
 #pragma unroll
             for (int s = 0; s < 4; ++s)
 #pragma unroll
-                for (int ti = 0; ti < 2; ++ti)
+                for (int ti = 0; ti < TM; ++ti)
 #pragma unroll
-                    for (int tj = 0; tj < 2; ++tj) {
+                    for (int tj = 0; tj < TN; ++tj) {
                         const float ar = (&fa_r[ti].x)[s], ai = (&fa_i[ti].x)[s];
                         const float br = (&fb_r[tj].x)[s], bi = (&fb_i[tj].x)[s];
                         accr[ti][tj] = __builtin_amdgcn_mfma_f32_16x16x4f32(ar, br, accr[ti][tj], 0, 0, 0);
@@ -240,7 +256,7 @@ __global__ __launch_bounds__(256) void k_cgemm_f32(CgemmArgs p)
         if (c + 1 < nk) ld.template store<LDK>(tid, StoreF32{sAr[cur ^ 1], sAi[cur ^ 1], sBr[cur ^ 1], sBi[cur ^ 1]});
         __syncthreads();
     }
-    write_tile(v, p, m0, n0, wr, wc, lane, accr, acci);
+    write_tile<T>(v, p, m0, n0, wr, wc, lane, accr, acci);
 }
 
 // ------------------------------------------------------------- BF16 (x3) --
@@ -253,29 +269,29 @@ __device__ __forceinline__ unsigned short bf16_rne(float x)
 }
 __device__ __forceinline__ float bf16_to_f32(unsigned short h) { return __uint_as_float(((unsigned int)h) << 16); }
 
+// writes hi (and lo when splitting) bf16 planes: pointers [hi/lo][re/im]
 struct StoreBF16 {
-    unsigned short *arh, *ail, *aih, *arl, *brh, *brl, *bih, *bil;
+    unsigned short* a[2][2];
+    unsigned short* b[2][2];
     bool split;
-    __device__ __forceinline__ void a(int i, float r, float im) const
+    __device__ __forceinline__ void put(unsigned short* const (&d)[2][2], int i, float r, float im) const
     {
         const unsigned short rh = bf16_rne(r), ih = bf16_rne(im);
-        arh[i] = rh;
-        aih[i] = ih;
+        d[0][0][i] = rh;
+        d[0][1][i] = ih;
         if (split) {
-            arl[i] = bf16_rne(r - bf16_to_f32(rh));
-            ail[i] = bf16_rne(im - bf16_to_f32(ih));
+            d[1][0][i] = bf16_rne(r - bf16_to_f32(rh));
+            d[1][1][i] = bf16_rne(im - bf16_to_f32(ih));
         }
     }
-    __device__ __forceinline__ void b(int i, float r, float im) const
-    {
-        const unsigned short rh = bf16_rne(r), ih = bf16_rne(im);
-        brh[i] = rh;
-        bih[i] = ih;
-        if (split) {
-            brl[i] = bf16_rne(r - bf16_to_f32(rh));
-            bil[i] = bf16_rne(im - bf16_to_f32(ih));
-        }
-    }
+    __device__ __forceinline__ void a_(int i, float r, float im) const { put(a, i, r, im); }
+};
+
+template <class S>
+struct StoreAdapter {
+    const S& s;
+    __device__ __forceinline__ void a(int i, float r, float im) const { s.put(s.a, i, r, im); }
+    __device__ __forceinline__ void b(int i, float r, float im) const { s.put(s.b, i, r, im); }
 };
 
 __device__ __forceinline__ shortx8 neg_bf16x8(shortx8 v)
@@ -284,13 +300,14 @@ __device__ __forceinline__ shortx8 neg_bf16x8(shortx8 v)
                          (short)0x8000, (short)0x8000, (short)0x8000, (short)0x8000};
 }
 
-#define TP_MFMA_BF16(a, b, c)                                                                  \
+#define TP_MFMA_BF16(a, b, c)                                                                                  \
     __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8, (a)), __builtin_bit_cast(bf16x8, (b)), \
                                             (c), 0, 0, 0)
 
-template <int OPA, int OPB, bool SPLIT>
+template <int OPA, int OPB, class T, bool SPLIT>
 __global__ __launch_bounds__(256) void k_cgemm_bf16(CgemmArgs p)
 {
+    constexpr int BM = T::BM, BN = T::BN, TM = T::TM, TN = T::TN;
     constexpr int BK = 32, LDK = BK + 8;  // 16-byte aligned rows, staggered banks
     constexpr int NP = SPLIT ? 2 : 1;
     __shared__ __attribute__((aligned(16))) unsigned short sA[2][NP][2][BM * LDK];  // [buf][hi/lo][re/im]
@@ -299,48 +316,57 @@ __global__ __launch_bounds__(256) void k_cgemm_bf16(CgemmArgs p)
     const SliceView v = slice_view(p, blockIdx.z);
     const int m0 = blockIdx.y * BM, n0 = blockIdx.x * BN;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    const int wr = (wave >> 1) * 32, wc = (wave & 1) * 32;
+    const int wr = (wave / T::WGN) * T::WM, wc = (wave % T::WGN) * T::WN;
     const int g = lane >> 4, r16 = lane & 15;
 
-    floatx4 accr[2][2], acci[2][2];
+    floatx4 accr[TM][TN], acci[TM][TN];
 #pragma unroll
-    for (int ti = 0; ti < 2; ++ti)
+    for (int ti = 0; ti < TM; ++ti)
 #pragma unroll
-        for (int tj = 0; tj < 2; ++tj) {
+        for (int tj = 0; tj < TN; ++tj) {
             accr[ti][tj] = floatx4{0.f, 0.f, 0.f, 0.f};
             acci[ti][tj] = floatx4{0.f, 0.f, 0.f, 0.f};
         }
 
     auto storer = [&](int b) {
-        return StoreBF16{sA[b][0][0], sA[b][NP - 1][1], sA[b][0][1], sA[b][NP - 1][0],
-                         sB[b][0][0], sB[b][NP - 1][0], sB[b][0][1], sB[b][NP - 1][1], SPLIT};
+        StoreBF16 st;
+        for (int h = 0; h < 2; ++h)
+            for (int ri = 0; ri < 2; ++ri) {
+                st.a[h][ri] = sA[b][h < NP ? h : 0][ri];
+                st.b[h][ri] = sB[b][h < NP ? h : 0][ri];
+            }
+        st.split = SPLIT;
+        return st;
     };
 
-    PanelLoader<OPA, OPB, BK> ld;
+    PanelLoader<OPA, OPB, BM, BN, BK> ld;
     const int nk = (v.K + BK - 1) / BK;
     if (nk > 0) {
         ld.load(v, p, m0, n0, 0, tid);
-        ld.template store<LDK>(tid, storer(0));
+        const StoreBF16 st = storer(0);
+        ld.template store<LDK>(tid, StoreAdapter<StoreBF16>{st});
     }
     __syncthreads();
     for (int c = 0; c < nk; ++c) {
         const int cur = c & 1;
         if (c + 1 < nk) ld.load(v, p, m0, n0, (c + 1) * BK, tid);
         // 16x16x32 operands: lane (g, r16) holds k = 8g .. 8g+7 of row (col) r16
-        shortx8 fa[2][NP][2], fb[2][NP][2];
+        shortx8 fa[TM][NP][2], fb[TN][NP][2];
 #pragma unroll
-        for (int t = 0; t < 2; ++t)
+        for (int h = 0; h < NP; ++h)
 #pragma unroll
-            for (int h = 0; h < NP; ++h)
+            for (int ri = 0; ri < 2; ++ri) {
 #pragma unroll
-                for (int ri = 0; ri < 2; ++ri) {
+                for (int t = 0; t < TM; ++t)
                     fa[t][h][ri] = *reinterpret_cast<const shortx8*>(&sA[cur][h][ri][(wr + 16 * t + r16) * LDK + 8 * g]);
+#pragma unroll
+                for (int t = 0; t < TN; ++t)
                     fb[t][h][ri] = *reinterpret_cast<const shortx8*>(&sB[cur][h][ri][(wc + 16 * t + r16) * LDK + 8 * g]);
-                }
+            }
 #pragma unroll
-        for (int ti = 0; ti < 2; ++ti)
+        for (int ti = 0; ti < TM; ++ti)
 #pragma unroll
-            for (int tj = 0; tj < 2; ++tj) {
+            for (int tj = 0; tj < TN; ++tj) {
                 // terms (a-part, b-part): hi*hi, then hi*lo and lo*hi when splitting
 #pragma unroll
                 for (int term = 0; term < (SPLIT ? 3 : 1); ++term) {
@@ -355,23 +381,63 @@ __global__ __launch_bounds__(256) void k_cgemm_bf16(CgemmArgs p)
                     }
                 }
             }
-        if (c + 1 < nk) ld.template store<LDK>(tid, storer(cur ^ 1));
+        if (c + 1 < nk) {
+            const StoreBF16 st = storer(cur ^ 1);
+            ld.template store<LDK>(tid, StoreAdapter<StoreBF16>{st});
+        }
         __syncthreads();
     }
-    write_tile(v, p, m0, n0, wr, wc, lane, accr, acci);
+    write_tile<T>(v, p, m0, n0, wr, wc, lane, accr, acci);
+}
+
+template <class T>
+dim3 grid_of(const CgemmArgs& a)
+{
+    return dim3((a.n + T::BN - 1) / T::BN, (a.m + T::BM - 1) / T::BM, a.nslices);
+}
+
+template <int OPA, int OPB, class T>
+hipError_t launch_f32(const CgemmArgs& a, hipStream_t s)
+{
+    k_cgemm_f32<OPA, OPB, T><<<grid_of<T>(a), 256, 0, s>>>(a);
+    return hipGetLastError();
+}
+
+template <class T>
+hipError_t launch_bf16(const CgemmArgs& a, int prec, hipStream_t s)
+{
+    if (prec == TP_PREC_BF16X3)
+        k_cgemm_bf16<OP_N, OP_N, T, true><<<grid_of<T>(a), 256, 0, s>>>(a);
+    else
+        k_cgemm_bf16<OP_N, OP_N, T, false><<<grid_of<T>(a), 256, 0, s>>>(a);
+    return hipGetLastError();
 }
 
 template <int OPA, int OPB>
-hipError_t launch_ops(const CgemmArgs& a, int prec, hipStream_t s)
+hipError_t launch_ops(const CgemmArgs& a, int variant, hipStream_t s)
 {
-    dim3 grid((a.n + BN - 1) / BN, (a.m + BM - 1) / BM, a.nslices);
-    if (prec == TP_PREC_FP32)
-        k_cgemm_f32<OPA, OPB><<<grid, 256, 0, s>>>(a);
-    else if (prec == TP_PREC_BF16X3)
-        k_cgemm_bf16<OPA, OPB, true><<<grid, 256, 0, s>>>(a);
-    else
-        k_cgemm_bf16<OPA, OPB, false><<<grid, 256, 0, s>>>(a);
-    return hipGetLastError();
+    switch (variant) {
+        case 2: return launch_f32<OPA, OPB, T128x128>(a, s);
+        case 3: return launch_f32<OPA, OPB, T128x64>(a, s);
+        case 4: return launch_f32<OPA, OPB, T128x32>(a, s);
+        case 5: return launch_f32<OPA, OPB, T256x16>(a, s);
+        default: return launch_f32<OPA, OPB, T64x64>(a, s);
+    }
+}
+
+long long tiles(long long m, long long n, int bm, int bn, int ns) { return ((m + bm - 1) / bm) * ((n + bn - 1) / bn) * ns; }
+
+// tile variant: the tuned one if set, else by shape (skinny outputs get
+// narrow tiles; large products with enough tiles to fill the GPU get 128-wide)
+int pick_variant(const CgemmArgs& a)
+{
+    const int tuned = param(TP_PARAM_GEMM_VARIANT);
+    if (tuned >= 1 && tuned <= 5) return tuned;
+    if (a.n <= 16) return 5;
+    if (a.n <= 32) return 4;
+    if (a.m >= 256 && a.n >= 256 && tiles(a.m, a.n, 128, 128, a.nslices) >= 2048) return 2;
+    if (a.m >= 128 && tiles(a.m, a.n, 128, 64, a.nslices) >= 2048) return 3;
+    return 1;
 }
 
 }  // namespace
@@ -379,10 +445,21 @@ hipError_t launch_ops(const CgemmArgs& a, int prec, hipStream_t s)
 hipError_t launch_cgemm(const CgemmArgs& a, int opa, int opb, int prec, hipStream_t s)
 {
     if (a.m <= 0 || a.n <= 0 || a.nslices <= 0) return hipSuccess;
-    if (opa == OP_N && opb == OP_N) return launch_ops<OP_N, OP_N>(a, prec, s);
-    if (opa == OP_C && opb == OP_N) return launch_ops<OP_C, OP_N>(a, prec, s);
-    if (opa == OP_N && opb == OP_C) return launch_ops<OP_N, OP_C>(a, prec, s);
-    return launch_ops<OP_C, OP_C>(a, prec, s);
+    const int variant = pick_variant(a);
+    if (prec != TP_PREC_FP32) {
+        if (opa != OP_N || opb != OP_N) return hipErrorInvalidValue;
+        switch (variant) {
+            case 2: return launch_bf16<T128x128>(a, prec, s);
+            case 3: return launch_bf16<T128x64>(a, prec, s);
+            case 4:
+            case 5: return launch_bf16<T128x32>(a, prec, s);  // the 256-row split tile exceeds LDS
+            default: return launch_bf16<T64x64>(a, prec, s);
+        }
+    }
+    if (opa == OP_N && opb == OP_N) return launch_ops<OP_N, OP_N>(a, variant, s);
+    if (opa == OP_C && opb == OP_N) return launch_ops<OP_C, OP_N>(a, variant, s);
+    if (opa == OP_N && opb == OP_C) return launch_ops<OP_N, OP_C>(a, variant, s);
+    return launch_ops<OP_C, OP_C>(a, variant, s);
 }
 
 }  // namespace tp

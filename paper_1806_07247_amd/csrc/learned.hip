@@ -245,8 +245,8 @@ __global__ __launch_bounds__(256) void k_chol(const double2* __restrict__ part, 
 // the full SVD; T = C_r diag((sigma - tau)_+ / sigma) V_r^* (planar, L x L).
 __global__ __launch_bounds__(256) void k_rsvd_check(const float2* __restrict__ cols, const double* __restrict__ sigma,
                                                     const float2* __restrict__ vr, const int* __restrict__ kpred,
-                                                    const int* __restrict__ lact, int L, double tau,
-                                                    float* __restrict__ tr, float* __restrict__ ti,
+                                                    const int* __restrict__ lact, const int* __restrict__ prefb,
+                                                    int L, double tau, float* __restrict__ tr, float* __restrict__ ti,
                                                     int* __restrict__ fallback, int* __restrict__ rank)
 {
     __shared__ double scale[64];
@@ -260,7 +260,7 @@ __global__ __launch_bounds__(256) void k_rsvd_check(const float2* __restrict__ c
             gt += sg[j] > tau ? 1 : 0;
         }
         above = gt;
-        if (ge > kpred[s] && lact[s] > 0) fallback[s] = 1;
+        fallback[s] = (prefb[s] || (ge > kpred[s] && lact[s] > 0)) ? 1 : 0;
         if (fallback[s] == 0 && rank) rank[s] = gt;
     }
     for (int j = tid; j < L; j += blockDim.x)
@@ -280,6 +280,58 @@ __global__ __launch_bounds__(256) void k_rsvd_check(const float2* __restrict__ c
         }
         tr[(long long)s * L * L + e] = (float)vr_;
         ti[(long long)s * L * L + e] = (float)vi_;
+    }
+}
+
+// ---------------------------------------------------- a posteriori check --
+// column-major L x L (float2) to planar row-major L x L, per slice
+__global__ __launch_bounds__(256) void k_cm_to_planar(const float2* __restrict__ src, float* __restrict__ re,
+                                                      float* __restrict__ im, int L, int nslices)
+{
+    const long long total = (long long)nslices * L * L;
+    for (long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x; e < total;
+         e += (long long)gridDim.x * blockDim.x) {
+        const long long s = e / ((long long)L * L);
+        const int r = (int)(e % ((long long)L * L));
+        const int i = r / L, j = r % L;
+        const float2 v = src[s * L * L + (long long)j * L + i];
+        re[e] = v.x;
+        im[e] = v.y;
+    }
+}
+
+// Per slice: the kept Ritz triplets (sigma_j > tau) have right residuals
+// r_j = Ybar v_j - sigma_j u_j = T1 e_j - T2 e_j (T1 = Ybar Q2 V_r,
+// T2 = Q U_r S); the slice is inaccurate when
+//   sum_J ||r_j||^2 > delta^2 sum_J (sigma_j - tau)^2,
+// i.e. the residuals are not small against the thresholded part it keeps.
+__global__ __launch_bounds__(256) void k_accuracy(const float* __restrict__ t1r, const float* __restrict__ t1i,
+                                                  const float* __restrict__ t2r, const float* __restrict__ t2i,
+                                                  const double* __restrict__ sigma, const int* __restrict__ lact,
+                                                  int m, int L, double tau, double delta, int* __restrict__ bad)
+{
+    __shared__ double red[256];
+    const int s = blockIdx.x, tid = threadIdx.x;
+    const double* sg = sigma + (long long)s * L;
+    const long long off = (long long)s * m * L;
+    double num = 0.0;
+    for (long long e = tid; e < (long long)m * L; e += blockDim.x) {
+        const int j = (int)(e % L);
+        if (j >= lact[s] || !(sg[j] > tau)) continue;
+        const double dr = (double)t1r[off + e] - t2r[off + e], di = (double)t1i[off + e] - t2i[off + e];
+        num += dr * dr + di * di;
+    }
+    red[tid] = num;
+    __syncthreads();
+    for (int w = blockDim.x / 2; w > 0; w >>= 1) {
+        if (tid < w) red[tid] += red[tid + w];
+        __syncthreads();
+    }
+    if (tid == 0) {
+        double den = 0.0;
+        for (int j = 0; j < lact[s]; ++j)
+            if (sg[j] > tau) den += (sg[j] - tau) * (sg[j] - tau);
+        bad[s] = (den > 0.0 && red[0] > delta * delta * den) ? 1 : 0;
     }
 }
 
@@ -570,10 +622,23 @@ size_t cholqr_part_bytes(int m, int L, int nslices)
 }
 
 hipError_t launch_rsvd_check(const float2* cols, const double* sigma, const float2* vr, const int* kpred,
-                             const int* lact, int L, double tau, Planes T, int* fallback, int* rank, int nslices,
-                             hipStream_t st)
+                             const int* lact, const int* prefb, int L, double tau, Planes T, int* fallback, int* rank,
+                             int nslices, hipStream_t st)
 {
-    k_rsvd_check<<<nslices, 256, 0, st>>>(cols, sigma, vr, kpred, lact, L, tau, T.re, T.im, fallback, rank);
+    k_rsvd_check<<<nslices, 256, 0, st>>>(cols, sigma, vr, kpred, lact, prefb, L, tau, T.re, T.im, fallback, rank);
+    return hipGetLastError();
+}
+
+hipError_t launch_cm_to_planar(const float2* src, Planes dst, int L, int nslices, hipStream_t st)
+{
+    k_cm_to_planar<<<blocks_for((long long)nslices * L * L, 256), 256, 0, st>>>(src, dst.re, dst.im, L, nslices);
+    return hipGetLastError();
+}
+
+hipError_t launch_accuracy(Planes t1, Planes t2, const double* sigma, const int* lact, int m, int L, double tau,
+                           double delta, int* bad, int nslices, hipStream_t st)
+{
+    k_accuracy<<<nslices, 256, 0, st>>>(t1.re, t1.im, t2.re, t2.im, sigma, lact, m, L, tau, delta, bad);
     return hipGetLastError();
 }
 

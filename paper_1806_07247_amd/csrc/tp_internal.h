@@ -118,8 +118,11 @@ hipError_t launch_cholqr_pass(const float* yr, const float* yi, int m, int L, co
                               double2* part, float* rir, float* rii, double2* rtot, float* rhr, float* rhi,
                               int* status, hipStream_t s);
 hipError_t launch_rsvd_check(const float2* cols, const double* sigma, const float2* vr, const int* kpred,
-                             const int* lact, int L, double tau, Planes T, int* fallback, int* rank, int nslices,
-                             hipStream_t s);
+                             const int* lact, const int* prefb, int L, double tau, Planes T, int* fallback, int* rank,
+                             int nslices, hipStream_t s);
+hipError_t launch_cm_to_planar(const float2* src, Planes dst, int L, int nslices, hipStream_t s);
+hipError_t launch_accuracy(Planes t1, Planes t2, const double* sigma, const int* lact, int m, int L, double tau,
+                           double delta, int* bad, int nslices, hipStream_t s);
 hipError_t launch_features(const float* yr, const float* yi, int m, int n, int n3, int nslices, double tau,
                            const int* prev, float* feats, hipStream_t s);
 hipError_t launch_predict(const float* params, const float* feats, int nslices, int p, int fixed_rank, int oversample,
@@ -140,7 +143,8 @@ int param(int key);
 // ------------------------------------------------------------- tracing ----
 enum KernelId {
     K_RFFT = 0, K_IRFFT = 1, K_CGEMM = 2, K_JACOBI = 3, K_SHRINK = 4, K_TNN_REDUCE = 5, K_TSVD_FINISH = 6,
-    K_FEATURES = 7, K_PREDICT = 8, K_SKETCH = 9, K_CHOLQR = 10, K_RSVD_CHECK = 11, K_GATHER = 12, K_MLP = 13
+    K_FEATURES = 7, K_PREDICT = 8, K_SKETCH = 9, K_CHOLQR = 10, K_RSVD_CHECK = 11, K_GATHER = 12, K_MLP = 13,
+    K_ACCURACY = 14
 };
 
 // Records HIP events around the launches in its scope while tracing is on.

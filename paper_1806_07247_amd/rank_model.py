@@ -1,0 +1,167 @@
+"""Training and evaluation of the per-slice rank predictor.
+
+Training samples come from the method's own prox calls inside TRPCA-ADMM
+runs (trpca.py): for every call and every leading Fourier slice, the
+features of tp_slice_features (with the previous call's count of that slice)
+and the exact count k* of singular values above tau from the full-SVD prox.
+The target is t = log1p(k*) / log1p(min(n1, n2)); the network is trained on
+the GPU with the library's own kernels (tp_mlp_loss_grad, tp_mlp_adam) on the
+asymmetric squared loss (under-prediction weighted `under` times, since it
+costs a fallback to the full SVD).
+
+    python -m paper_1806_07247_amd.rank_model train [--out FILE] [--runs N] ...
+"""
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+import numpy as np
+import torch
+
+import paper_1806_07247_amd as tp
+from paper_1806_07247_amd import trpca
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+WEIGHTS = os.path.join(HERE, "rank_mlp_gfx950.npy")
+
+
+def init_params(seed=0):
+    """He-uniform weights, zero biases, packed as in include/tp.h."""
+    rng = np.random.default_rng(seed)
+    D, H = 8, 64
+    parts = []
+    for fan_in, fan_out in ((D, H), (H, H), (H, H), (H, 1)):
+        b = math.sqrt(6.0 / fan_in)
+        parts.append(rng.uniform(-b, b, size=fan_out * fan_in))
+        parts.append(np.zeros(fan_out))
+    p = np.concatenate(parts).astype(np.float32)
+    assert p.size == tp.tp_mlp_param_count()
+    return p
+
+
+def save(params, path=WEIGHTS, meta=None):
+    np.save(path, np.asarray(params, dtype=np.float32), allow_pickle=False)
+    if meta is not None:
+        with open(os.path.splitext(path)[0] + ".json", "w") as f:
+            json.dump(meta, f, indent=1, sort_keys=True)
+
+
+def load(path=WEIGHTS, device="cuda:0"):
+    p = np.load(path, allow_pickle=False)
+    return torch.from_numpy(p.astype(np.float32)).to(device)
+
+
+def label_prox(shape, device, max_rank=64, oversample=10):
+    """Exact per-slice counts at a fraction of the full-SVD cost: the learned
+    path with the widest sketch (kpred = max_rank - oversample) and the
+    a posteriori check; slices with more singular values above tau fall back
+    to the full SVD, whose count is exact as well."""
+    return trpca.ProxLearned(shape, device, mlp=None, fixed_rank=max_rank - oversample, oversample=oversample,
+                             max_rank=max_rank, use_prev=False)
+
+
+def rank_for(n, rng):
+    """Tubal rank of the learned-rank workload, r ~ U{5..40} at n = 1024,
+    scaled to smaller n."""
+    r = int(rng.integers(5, 41))
+    return max(2, int(round(r * n / 1024.0)))
+
+
+def collect(shapes, runs, seed0, device, max_iter=200, log=print):
+    """Features and targets from TRPCA runs on n x n x n3 problems (tubal rank
+    r, 5% +-1 outliers); the previous call's count of each slice is a feature."""
+    feats, targets = [], []
+    run = 0
+    for shape in shapes:
+        n, _, n3 = shape
+        for _ in range(runs):
+            seed = seed0 + run
+            run += 1
+            rng = np.random.default_rng(seed)
+            r = rank_for(n, rng)
+            X, _, _ = trpca.make_problem(n, n3, r, 0.05, seed, device)
+            prox = label_prox(shape, device)
+            prev = {"rank": None}
+
+            def record(Yin, tau, rank):
+                f = tp.tp_slice_features(Yin, tau, prev["rank"])
+                feats.append(f.cpu().numpy())
+                t = np.log1p(rank.cpu().numpy().astype(np.float64)) / np.log1p(min(shape[0], shape[1]))
+                targets.append(t)
+                prev["rank"] = rank.clone()
+
+            t0 = time.perf_counter()
+            res = trpca.trpca(X, prox, max_iter=max_iter, record=record)
+            log(f"  {shape} seed {seed} r {r}: {res['iters']} iterations, {prox.fallbacks} fallback slices, "
+                f"{time.perf_counter() - t0:.1f} s", file=sys.stderr, flush=True)
+    return np.concatenate(feats).astype(np.float32), np.concatenate(targets).astype(np.float32)
+
+
+def train(F, T, device, steps=3000, batch=4096, lr=2e-3, under=4.0, seed=0, log=print):
+    params = torch.from_numpy(init_params(seed)).to(device)
+    m = torch.zeros_like(params)
+    v = torch.zeros_like(params)
+    Fd = torch.from_numpy(F).to(device)
+    Td = torch.from_numpy(T).to(device)
+    n = F.shape[0]
+    rng = np.random.default_rng(seed + 1)
+    ws = torch.empty(tp._lib.load().tp_mlp_train_workspace_size(min(batch, n)), dtype=torch.uint8, device=device)
+    grad = torch.empty_like(params)
+    loss = torch.empty((), dtype=torch.float32, device=device)
+    hist = []
+    for step in range(1, steps + 1):
+        idx = torch.from_numpy(rng.choice(n, size=min(batch, n), replace=False)).to(device)
+        tp.tp_mlp_loss_grad(params, Fd[idx].contiguous(), Td[idx].contiguous(), under=under, grad=grad, loss=loss,
+                            workspace=ws)
+        lr_t = lr * (0.5 * (1 + math.cos(math.pi * step / steps)) * 0.9 + 0.1)
+        tp.tp_mlp_adam(params, grad, m, v, step, lr=lr_t)
+        if step % 250 == 0 or step == 1:
+            hist.append((step, float(loss)))
+            log(f"  step {step}: loss {float(loss):.5f}", file=sys.stderr, flush=True)
+    return params, hist
+
+
+def evaluate(params, F, T, device):
+    """Under-prediction rate and mean absolute error of the predicted counts;
+    p is recovered from the feature log(p)/8."""
+    y = tp.tp_mlp_forward(params, torch.from_numpy(F).to(device)).cpu().numpy()
+    p = np.rint(np.exp(F[:, 6].astype(np.float64) * 8.0))
+    kpred = np.clip(np.rint(np.expm1(y * np.log1p(p))), 0, p)
+    ktrue = np.rint(np.expm1(T * np.log1p(p)))
+    under = float(np.mean(kpred < ktrue))
+    mae = float(np.mean(np.abs(kpred - ktrue)))
+    return dict(under_rate=under, mae=mae)
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("cmd", choices=["train"])
+    ap.add_argument("--out", default=WEIGHTS)
+    ap.add_argument("--shapes", default="1024x1024x64,512x512x32,256x256x32")
+    ap.add_argument("--runs", type=int, default=12, help="ADMM runs per shape")
+    ap.add_argument("--max-iter", type=int, default=200)
+    ap.add_argument("--steps", type=int, default=3000)
+    ap.add_argument("--seed", type=int, default=0, help="first ADMM seed (the evaluation uses 10000 and up)")
+    args = ap.parse_args()
+    dev = torch.device("cuda:0")
+    t0 = time.perf_counter()
+    shapes = [tuple(int(v) for v in sh.split("x")) for sh in args.shapes.split(",")]
+    F, T = collect(shapes, args.runs, args.seed, dev, max_iter=args.max_iter)
+    t1 = time.perf_counter()
+    # hold out 10% of the samples (every tenth)
+    val = np.zeros(F.shape[0], dtype=bool)
+    val[::10] = True
+    params, hist = train(F[~val], T[~val], dev, steps=args.steps, seed=args.seed)
+    ev = evaluate(params, F[val], T[val], dev)
+    meta = dict(samples=int(F.shape[0]), shapes=args.shapes, runs_per_shape=args.runs, seed0=args.seed,
+                collect_s=round(t1 - t0, 1), train_s=round(time.perf_counter() - t1, 1), loss=hist,
+                heldout=ev)
+    save(params.cpu().numpy(), args.out, meta)
+    print(json.dumps(meta), flush=True)
+
+
+if __name__ == "__main__":
+    main()

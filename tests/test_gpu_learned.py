@@ -115,7 +115,7 @@ def test_learned_prox_matches_oracle_rsvd(tp, orc):
     kp = np.full(h, 5, dtype=np.int32)
     fb = torch.zeros(h, dtype=torch.int32, device="cuda:0")
     X = tp.tp_prox_tnn_learned(gpu(Y), tau, fixed_rank=5, oversample=4, power_iters=2, max_rank=16, seed=99,
-                               fallback=fb).cpu().numpy()
+                               accuracy=0.0, fallback=fb).cpu().numpy()
     ref, fbr, _ = orc.prox_tnn_rsvd(Y, np.float32(tau), kp, oversample=4, power=2, lfull=17, seed=99)
     err = rel_fro(X, ref)
     say(f"  vs oracle rsvd: rel.err {err:.2e}, fallback gpu {fb.cpu().numpy().tolist()} oracle {fbr.tolist()}")
@@ -165,3 +165,28 @@ def test_learned_prox_deterministic(tp, orc):
     a = tp.tp_prox_tnn_learned(Y, 1.0, fixed_rank=5, max_rank=24, seed=1)
     b = tp.tp_prox_tnn_learned(Y, 1.0, fixed_rank=5, max_rank=24, seed=1)
     assert torch.equal(a, b)
+
+
+def test_learned_prox_accuracy_check(tp, orc):
+    """Kept singular values close above a noise bulk: two power iterations do
+    not resolve the kept subspace to 1e-4; the a posteriori residual check
+    adds iterations (or falls back) until the result is within 1e-4 of the
+    exact prox."""
+    rng = np.random.default_rng(31)
+    n, n3, r = 120, 4, 5
+    P = rng.standard_normal((n, r, n3)) / np.sqrt(n)
+    Q = rng.standard_normal((r, n, n3)) / np.sqrt(n)
+    L = orc.tprod(P, Q) * 0.7
+    Y = (L + 0.35 * rng.standard_normal((n, n, n3)) / np.sqrt(n)).astype(np.float32)
+    sig = orc.slice_sigma(Y)[:3]
+    tau = float(np.sort(sig[:, r - 1])[0]) * 0.8
+    say(f"  sigma_r {sig[:, r - 1].round(3).tolist()} sigma_r+1 {sig[:, r].round(3).tolist()} tau {tau:.3f}")
+    exact = orc.prox_tnn(Y, np.float32(tau))
+    kw = dict(fixed_rank=r, oversample=3, power_iters=2, max_rank=16, seed=5)
+    loose = tp.tp_prox_tnn_learned(gpu(Y), tau, accuracy=0.0, **kw).cpu().numpy()
+    fb = torch.zeros(3, dtype=torch.int32, device="cuda:0")
+    tight = tp.tp_prox_tnn_learned(gpu(Y), tau, accuracy=2e-5, max_power_iters=60, fallback=fb, **kw).cpu().numpy()
+    e0, e1 = rel_fro(loose, exact), rel_fro(tight, exact)
+    say(f"  without check {e0:.2e}, with check {e1:.2e}, fallback {fb.cpu().numpy().tolist()}")
+    assert e1 <= 1e-4
+    assert e0 > e1
