@@ -118,7 +118,9 @@ int tp_prox_tnn(const float* Y, float* X, int n1, int n2, int n3, float tau, int
  * Q2 R2 (CholeskyQR2); one-sided Jacobi SVD of R2^* = U_r S V_r^*; and
  * W^(k) = Q U_r (S - tau)_+ V_r^* Q2^*.  A slice falls back to the full SVD
  * path of tp_prox_tnn when l > max_rank, or when the check sigma_(kpred+1) <
- * tau fails on the singular values of R2^*.  With accuracy > 0, the kept
+ * tau fails on the singular values of R2^* (with retry_wide, a slice failing
+ * the check below the widest sketch is first redone once with kpred =
+ * max_rank - oversample, and falls back if it fails there).  With accuracy > 0, the kept
  * Ritz triplets (u_j, sigma_j, v_j), sigma_j > tau, are checked a posteriori:
  * when sum_j ||Ybar v_j - sigma_j u_j||^2 > accuracy^2 sum_j (sigma_j - tau)^2
  * on some slice, all slices get one more power iteration, up to
@@ -132,40 +134,55 @@ int tp_prox_tnn(const float* Y, float* X, int n1, int n2, int n3, float tau, int
  * Unlike the other entry points this call waits for the stream (once, plus
  * once per accuracy check): it reads which slices fell back before enqueueing
  * their full SVD.
- * Features (TP_MLP_INPUTS = 8, FP32, per slice): log(tau / rms sigma) with
- * rms sigma = ||Ybar^(k)||_F / sqrt(min(n1,n2)); log(max column norm / tau);
- * prev_rank/min(n1,n2) and 1 when prev_rank is given (else 0, 0);
- * k/(n3/2); 1 for a real slice; log(min(n1,n2))/8; log(max(n1,n2)/min(n1,n2));
- * each clamped to [-30, 30].  The MLP maps them to y and
- * kpred = round(expm1(y * log1p(min(n1,n2)))) clipped to [0, min(n1,n2)].
+ * Features (TP_MLP_INPUTS = 12, FP32, per slice; p = min(n1,n2)):
+ *   0 log(tau / rms sigma), rms sigma = ||Ybar^(k)||_F / sqrt(p)
+ *   1 log(max column norm / tau)
+ *   2 prev_rank / p and 3 one when prev_rank is given (else 0, 0)
+ *   4 k/(n3/2)    5 one for a real slice    6 log(p)/8    7 log(max(n1,n2)/p)
+ *   with prev_sigma (the previous call's leading singular values s_1 >= s_2
+ *   >= ... of the slice, TP_SIGMA_KEEP per slice, zero-padded; c of them
+ *   nonzero), else zeros:
+ *   8 #{s_j > tau}/p   9 #{s_j > tau/1.25}/p   10 log(s_1/tau)
+ *   11 one when c > 0 and s_c > tau (the previous sketch saw no value below tau)
+ * the logarithms clamped to [-30, 30].  The MLP maps them to y and
+ * kpred = round(expm1(y * log1p(p))) clipped to [0, p].
+ * sigma_out (optional, device float[(floor(n3/2)+1) * TP_SIGMA_KEEP]) receives
+ * this call's leading singular values per slice in that layout (from the
+ * randomized SVD, or from the full SVD for fallback slices), to be passed as
+ * prev_sigma of the next call.
  */
-#define TP_MLP_INPUTS 8
+#define TP_MLP_INPUTS 12
+#define TP_SIGMA_KEEP 64
 #define TP_MLP_HIDDEN 64
 typedef struct tp_learned_opts {
     const float* mlp;          /* device MLP parameters (tp_mlp_param_count floats) or NULL */
     int fixed_rank;            /* kpred of every slice when mlp is NULL */
     const int* prev_rank;      /* device int[floor(n3/2)+1] or NULL (a feature) */
+    const float* prev_sigma;   /* device float[(floor(n3/2)+1) * TP_SIGMA_KEEP] or NULL */
     int oversample;            /* extra sketch columns (the paper setting: 10) */
     int power_iters;           /* subspace iterations (2) */
     int max_rank;              /* l_max <= 64: wider slices use the full SVD */
     unsigned long long seed;   /* sketch seed */
     float accuracy;            /* a posteriori residual tolerance, 0 = no check */
     int max_power_iters;       /* cap on power iterations with the check */
+    int retry_wide;            /* 1: retry count-check failures once at the widest sketch */
 } tp_learned_opts;
 size_t tp_prox_tnn_learned_workspace_size(int n1, int n2, int n3, int max_rank);
 int tp_prox_tnn_learned(const float* Y, float* X, int n1, int n2, int n3, float tau,
                         const tp_learned_opts* opts, int* rank, int* fallback, int* info,
-                        void* workspace, size_t workspace_bytes, void* stream);
-/* the per-slice features above, feats is device float[(floor(n3/2)+1) * 8] */
+                        float* sigma_out, void* workspace, size_t workspace_bytes, void* stream);
+/* the per-slice features above, feats is device float[(floor(n3/2)+1) * TP_MLP_INPUTS] */
 size_t tp_slice_features_workspace_size(int n1, int n2, int n3);
 int tp_slice_features(const float* Y, int n1, int n2, int n3, float tau, const int* prev_rank,
-                      float* feats, void* workspace, size_t workspace_bytes, void* stream);
+                      const float* prev_sigma, float* feats, void* workspace, size_t workspace_bytes,
+                      void* stream);
 
 /*
  * Rank-predicting MLP: TP_MLP_INPUTS -> 64 -> 64 -> 64 -> 1, ReLU hidden
  * layers.  Parameters (device float, tp_mlp_param_count() of them) are packed
- * W1 (64 x 8, row-major), b1 (64), W2 (64 x 64), b2, W3 (64 x 64), b3,
- * w4 (64), b4 (1).  x is batch x 8 row-major, y and t are batch floats.
+ * W1 (64 x TP_MLP_INPUTS, row-major), b1 (64), W2 (64 x 64), b2, W3 (64 x 64),
+ * b3, w4 (64), b4 (1).  x is batch x TP_MLP_INPUTS row-major, y and t are
+ * batch floats.
  * tp_mlp_loss_grad: loss = mean_s c(e_s) e_s^2 with e_s = y_s - t_s and
  * c(e) = 1 for e >= 0, `under` for e < 0 (under-prediction costs a fallback);
  * grad receives d loss / d params and loss (device float) its value; the sums

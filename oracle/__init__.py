@@ -58,7 +58,7 @@ def _load():
         "or_sketch_matrix": (None, [_I, _I, _I, _I, ctypes.c_ulonglong, _D]),
         "or_cholqr2": (_I, [_D, _I, _I, _I, _D]),
         "or_prox_tnn_rsvd": (_I, [_D, _I, _I, _I, ctypes.c_double, IP, _I, _I, _I, ctypes.c_ulonglong, _D, IP, IP]),
-        "or_slice_features": (None, [_D, _I, _I, _I, ctypes.c_double, IP, _D]),
+        "or_slice_features": (None, [_D, _I, _I, _I, ctypes.c_double, IP, _D, _D]),
         "or_mlp_param_count": (_I, [_I, _I]),
         "or_mlp_forward": (None, [_D, _I, _I, _D, _I, _D]),
         "or_mlp_loss_grad": (ctypes.c_double, [_D, _I, _I, _D, _D, _I, ctypes.c_double, _D]),
@@ -300,12 +300,14 @@ def mlp_loss_grad(params, X, t, d, h, under=4.0):
     return float(loss), g
 
 
-def slice_features(Y, tau, prev=None):
+def slice_features(Y, tau, prev=None, prev_sigma=None):
     Y = _real(Y)
     n1, n2, n3 = Y.shape
     h = n3 // 2 + 1
-    f = np.empty((h, 8))
+    f = np.empty((h, 12))
     IP = ctypes.POINTER(ctypes.c_int)
     pv = None if prev is None else np.ascontiguousarray(prev, dtype=np.int32)
-    _load().or_slice_features(_dp(Y), n1, n2, n3, float(tau), None if pv is None else pv.ctypes.data_as(IP), _dp(f))
+    ps = None if prev_sigma is None else _real(prev_sigma)
+    _load().or_slice_features(_dp(Y), n1, n2, n3, float(tau), None if pv is None else pv.ctypes.data_as(IP),
+                              None if ps is None else _dp(ps), _dp(f))
     return f

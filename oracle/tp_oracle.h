@@ -123,11 +123,15 @@ int or_prox_tnn_rsvd(const double* Y, int n1, int n2, int n3, double tau, const 
                      int power, int lfull, unsigned long long seed, double* X, int* fallback, int* rank);
 
 /* Per-slice features of the rank predictor, for the floor(n3/2)+1 leading
- * Fourier slices (row k of feats, 8 values): log(tau / (||Ybar^(k)||_F /
+ * Fourier slices (row k of feats, 12 values): log(tau / (||Ybar^(k)||_F /
  * sqrt(p))), log(max column norm / tau), prev[k]/p and 1 (0, 0 without prev),
- * k/(n3/2), 1 for a real slice, log(p)/8, log(max(n1,n2)/p); p = min(n1,n2);
- * the first two clamped to [-30, 30]. */
-void or_slice_features(const double* Y, int n1, int n2, int n3, double tau, const int* prev, double* feats);
+ * k/(n3/2), 1 for a real slice, log(p)/8, log(max(n1,n2)/p); from the
+ * previous leading singular values s (psig, 64 per slice, decreasing,
+ * zero-padded; zeros without psig): #{s > tau}/p, #{s > tau/1.25}/p,
+ * log(s_1/tau), [s_c > tau] with c the number of nonzero s; p = min(n1,n2);
+ * logarithms clamped to [-30, 30]. */
+void or_slice_features(const double* Y, int n1, int n2, int n3, double tau, const int* prev, const double* psig,
+                       double* feats);
 
 /* MLP with ReLU hidden layers: sizes d -> h -> h -> h -> 1.  Parameters packed
  * as W1 (h x d, row-major), b1 (h), W2 (h x h), b2, W3 (h x h), b3, w4 (h), b4.

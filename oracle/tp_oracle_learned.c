@@ -395,7 +395,8 @@ double or_mlp_loss_grad(const double* params, int d, int h, const double* X, con
 }
 
 /* ---------------------------------------------------------- features -- */
-void or_slice_features(const double* Y, int n1, int n2, int n3, double tau, const int* prev, double* feats)
+void or_slice_features(const double* Y, int n1, int n2, int n3, double tau, const int* prev, const double* psig,
+                       double* feats)
 {
     const int h = n3 / 2 + 1, p = n1 < n2 ? n1 : n2;
     const i64 tot = (i64)n1 * n2 * n3;
@@ -415,7 +416,7 @@ void or_slice_features(const double* Y, int n1, int n2, int n3, double tau, cons
             cmax = fmax(cmax, c);
         }
         const double t2 = tau * tau;
-        double* f = feats + (i64)k * 8;
+        double* f = feats + (i64)k * 12;
         f[0] = (nrm2 > 0.0 && t2 > 0.0) ? fmin(30.0, fmax(-30.0, 0.5 * log(t2 * p / nrm2))) : -30.0;
         f[1] = (cmax > 0.0 && t2 > 0.0) ? fmin(30.0, fmax(-30.0, 0.5 * log(cmax / t2))) : (cmax > 0.0 ? 30.0 : -30.0);
         f[2] = prev ? (double)prev[k] / p : 0.0;
@@ -424,6 +425,20 @@ void or_slice_features(const double* Y, int n1, int n2, int n3, double tau, cons
         f[5] = (k == 0 || (n3 % 2 == 0 && k == n3 / 2)) ? 1.0 : 0.0;
         f[6] = log((double)p) / 8.0;
         f[7] = log((double)(n1 > n2 ? n1 : n2) / (double)p);
+        f[8] = f[9] = f[10] = f[11] = 0.0;
+        if (psig) { /* previous leading singular values, 64 per slice, decreasing, zero-padded */
+            const double* sv = psig + (i64)k * 64;
+            int a = 0, b = 0, c = 0;
+            for (int j = 0; j < 64; ++j) {
+                c += sv[j] > 0.0 ? 1 : 0;
+                a += sv[j] > tau ? 1 : 0;
+                b += sv[j] > tau / 1.25 ? 1 : 0;
+            }
+            f[8] = (double)a / p;
+            f[9] = (double)b / p;
+            f[10] = (sv[0] > 0.0 && tau > 0.0) ? fmin(30.0, fmax(-30.0, log(sv[0] / tau))) : (sv[0] > 0.0 ? 30.0 : -30.0);
+            f[11] = (c > 0 && sv[c - 1] > tau) ? 1.0 : 0.0;
+        }
     }
     free(zy);
     free(Yb);

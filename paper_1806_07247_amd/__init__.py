@@ -16,6 +16,8 @@ from ._lib import TPError
 TP_PREC_FP32 = 0
 TP_PREC_BF16X3 = 1
 TP_PREC_BF16 = 2
+TP_MLP_INPUTS = 12
+TP_SIGMA_KEEP = 64
 _PREC = {"fp32": TP_PREC_FP32, "bf16x3": TP_PREC_BF16X3, "bf16": TP_PREC_BF16}
 
 __all__ = ["tp_tprod", "tp_tprod_workspace_size", "tp_tsvd", "tp_tsvd_workspace_size", "tp_prox_tnn", "tp_prox_tnn_workspace_size",
@@ -149,9 +151,9 @@ def tp_prox_tnn_learned_workspace_size(n1, n2, n3, max_rank=64):
     return int(_lib.load().tp_prox_tnn_learned_workspace_size(n1, n2, n3, max_rank))
 
 
-def tp_prox_tnn_learned(Y, tau, mlp=None, fixed_rank=0, prev_rank=None, oversample=10, power_iters=2,
-                        max_rank=64, seed=0, accuracy=2e-5, max_power_iters=8, out=None, rank=None, fallback=None,
-                        info=None, workspace=None):
+def tp_prox_tnn_learned(Y, tau, mlp=None, fixed_rank=0, prev_rank=None, prev_sigma=None, oversample=10,
+                        power_iters=2, max_rank=64, seed=0, accuracy=2e-5, max_power_iters=8, retry_wide=True,
+                        out=None, rank=None, fallback=None, info=None, sigma_out=None, workspace=None):
     """Learned-rank prox (see include/tp.h); mlp is a float32 device tensor of
     tp_mlp_param_count() parameters or None (then every slice uses fixed_rank).
     rank / fallback / info: optional int32 device tensors of half_slices(n3)."""
@@ -159,27 +161,29 @@ def tp_prox_tnn_learned(Y, tau, mlp=None, fixed_rank=0, prev_rank=None, oversamp
     Y = _dev_tensor(Y, "Y")
     n1, n2, n3 = Y.shape
     X = out if out is not None else torch.empty_like(Y)
-    opts = _lib.LearnedOpts(_ptr(mlp), int(fixed_rank), _ptr(prev_rank), int(oversample), int(power_iters),
-                            int(max_rank), int(seed) & 0xFFFFFFFFFFFFFFFF, float(accuracy), int(max_power_iters))
+    opts = _lib.LearnedOpts(_ptr(mlp), int(fixed_rank), _ptr(prev_rank), _ptr(prev_sigma), int(oversample),
+                            int(power_iters),
+                            int(max_rank), int(seed) & 0xFFFFFFFFFFFFFFFF, float(accuracy), int(max_power_iters),
+                            int(bool(retry_wide)))
     ws_bytes = lib.tp_prox_tnn_learned_workspace_size(n1, n2, n3, int(max_rank))
     ws = workspace if workspace is not None else _workspace(ws_bytes, Y.device)
     st = lib.tp_prox_tnn_learned(Y.data_ptr(), X.data_ptr(), n1, n2, n3, float(tau), ctypes.byref(opts),
-                                 _ptr(rank), _ptr(fallback), _ptr(info), ws.data_ptr(), ws.numel(),
-                                 _stream(Y.device))
+                                 _ptr(rank), _ptr(fallback), _ptr(info), _ptr(sigma_out), ws.data_ptr(),
+                                 ws.numel(), _stream(Y.device))
     _lib.check("tp_prox_tnn_learned", st)
     return X
 
 
-def tp_slice_features(Y, tau, prev_rank=None, workspace=None):
-    """Per-slice features of the rank predictor: (half_slices(n3), 8) float32 device tensor."""
+def tp_slice_features(Y, tau, prev_rank=None, prev_sigma=None, workspace=None):
+    """Per-slice features of the rank predictor: (half_slices(n3), TP_MLP_INPUTS) float32 device tensor."""
     lib = _lib.load()
     Y = _dev_tensor(Y, "Y")
     n1, n2, n3 = Y.shape
-    f = torch.empty((half_slices(n3), 8), dtype=torch.float32, device=Y.device)
+    f = torch.empty((half_slices(n3), TP_MLP_INPUTS), dtype=torch.float32, device=Y.device)
     ws_bytes = lib.tp_slice_features_workspace_size(n1, n2, n3)
     ws = workspace if workspace is not None else _workspace(ws_bytes, Y.device)
-    st = lib.tp_slice_features(Y.data_ptr(), n1, n2, n3, float(tau), _ptr(prev_rank), f.data_ptr(), ws.data_ptr(),
-                               ws.numel(), _stream(Y.device))
+    st = lib.tp_slice_features(Y.data_ptr(), n1, n2, n3, float(tau), _ptr(prev_rank), _ptr(prev_sigma),
+                               f.data_ptr(), ws.data_ptr(), ws.numel(), _stream(Y.device))
     _lib.check("tp_slice_features", st)
     return f
 

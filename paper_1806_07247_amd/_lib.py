@@ -40,16 +40,17 @@ _U64 = ctypes.c_ulonglong
 
 class LearnedOpts(ctypes.Structure):
     """tp_learned_opts of include/tp.h"""
-    _fields_ = [("mlp", _VP), ("fixed_rank", _I), ("prev_rank", _VP), ("oversample", _I),
-                ("power_iters", _I), ("max_rank", _I), ("seed", _U64), ("accuracy", _F), ("max_power_iters", _I)]
+    _fields_ = [("mlp", _VP), ("fixed_rank", _I), ("prev_rank", _VP), ("prev_sigma", _VP), ("oversample", _I),
+                ("power_iters", _I), ("max_rank", _I), ("seed", _U64), ("accuracy", _F), ("max_power_iters", _I),
+                ("retry_wide", _I)]
 
 
 SIGNATURES.update({
     "tp_prox_tnn_learned_workspace_size": (_SZ, [_I, _I, _I, _I]),
-    "tp_prox_tnn_learned": (_I, [_VP, _VP, _I, _I, _I, _F, ctypes.POINTER(LearnedOpts), _VP, _VP, _VP, _VP, _SZ,
-                                 _VP]),
+    "tp_prox_tnn_learned": (_I, [_VP, _VP, _I, _I, _I, _F, ctypes.POINTER(LearnedOpts), _VP, _VP, _VP, _VP, _VP,
+                                 _SZ, _VP]),
     "tp_slice_features_workspace_size": (_SZ, [_I, _I, _I]),
-    "tp_slice_features": (_I, [_VP, _I, _I, _I, _F, _VP, _VP, _VP, _SZ, _VP]),
+    "tp_slice_features": (_I, [_VP, _I, _I, _I, _F, _VP, _VP, _VP, _VP, _SZ, _VP]),
     "tp_mlp_param_count": (_I, []),
     "tp_mlp_forward": (_I, [_VP, _VP, _VP, _I, _VP]),
     "tp_mlp_train_workspace_size": (_SZ, [_I]),

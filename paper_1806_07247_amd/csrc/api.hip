@@ -467,7 +467,8 @@ size_t tp_prox_tnn_learned_workspace_size(int n1, int n2, int n3, int max_rank)
 }
 
 int tp_prox_tnn_learned(const float* Y, float* X, int n1, int n2, int n3, float tau, const tp_learned_opts* opts,
-                        int* rank, int* fallback, int* info, void* workspace, size_t workspace_bytes, void* stream)
+                        int* rank, int* fallback, int* info, float* sigma_out, void* workspace, size_t workspace_bytes,
+                        void* stream)
 {
     if (!Y || !X || !opts) return TP_ERR_ARG;
     if (!(tau >= 0.0f) || std::isinf(tau)) return TP_ERR_ARG;
@@ -491,22 +492,37 @@ int tp_prox_tnn_learned(const float* Y, float* X, int n1, int n2, int n3, float 
     TP_LAUNCH(tp::K_RFFT, s, tp::launch_rfft(Y, ybar.re, ybar.im, mn, n3, s));
     // predicted count per slice and sketch width
     TP_LAUNCH(tp::K_FEATURES, s,
-              tp::launch_features(ybar.re, ybar.im, n1, n2, n3, h, (double)tau, opts->prev_rank, W.feats, s));
+              tp::launch_features(ybar.re, ybar.im, n1, n2, n3, h, (double)tau, opts->prev_rank, opts->prev_sigma,
+                                  W.feats, s));
     TP_LAUNCH(tp::K_PREDICT, s,
               tp::launch_predict(opts->mlp, W.feats, h, p, opts->fixed_rank, opts->oversample, opts->max_rank,
                                  W.kpred, W.lact, W.prefb, rk, s));
     TP_TRY(hipMemsetAsync(W.status, 0, h * sizeof(int), s));
-    // sketch width of this call: the widest predicted l, rounded up to 8
-    std::vector<int> hl(h), hpre(h), hbad(h), hfb(h);
+    std::vector<int> hl(h), hpre(h), hbad(h), hfb(h), hk(h);
     TP_TRY(hipMemcpyAsync(hl.data(), W.lact, h * sizeof(int), hipMemcpyDeviceToHost, s));
     TP_TRY(hipMemcpyAsync(hpre.data(), W.prefb, h * sizeof(int), hipMemcpyDeviceToHost, s));
+    TP_TRY(hipMemcpyAsync(hk.data(), W.kpred, h * sizeof(int), hipMemcpyDeviceToHost, s));
     TP_TRY(hipStreamSynchronize(s));
+    int st = TP_OK;
+    for (int attempt = 0; attempt < 2; ++attempt) {
+    // sketch width of this attempt: the widest l, rounded up to 8
     int lmax = 0;
     for (int k = 0; k < h; ++k)
         if (!hpre[k] && hl[k] > lmax) lmax = hl[k];
     const int L = lmax > 0 ? std::min(((lmax + 7) / 8) * 8, opts->max_rank) : 0;
+    // every slice on the randomized path uses the call's common width L (the
+    // batched products run at that width anyway): l = min(L, p), and the
+    // count check allows up to l - oversample singular values above tau
+    if (L > 0) {
+        for (int k = 0; k < h; ++k)
+            if (!hpre[k]) {
+                hl[k] = std::min(L, p);
+                hk[k] = std::max(hk[k], hl[k] - opts->oversample);
+            }
+        TP_TRY(hipMemcpyAsync(W.kpred, hk.data(), h * sizeof(int), hipMemcpyHostToDevice, s));
+        TP_TRY(hipMemcpyAsync(W.lact, hl.data(), h * sizeof(int), hipMemcpyHostToDevice, s));
+    }
 
-    int st = TP_OK;
     if (L == 0) {  // every slice goes to the full SVD
         TP_TRY(hipMemcpyAsync(fb, W.prefb, h * sizeof(int), hipMemcpyDeviceToDevice, s));
     } else {
@@ -574,11 +590,30 @@ int tp_prox_tnn_learned(const float* Y, float* X, int n1, int n2, int n3, float 
             if (st != TP_OK) return st;
             ++q;
         }
+        if (sigma_out)  // singular values of the slices kept on the randomized path
+            TP_LAUNCH(tp::K_RSVD_CHECK, s, tp::launch_sigma_top(W.jsig, L, W.lact, nullptr, fb, h, sigma_out, s));
         // W = Q (T Q2^*)
         st = gemm(W.T, L, sl, tp::OP_N, W.za, L, sz, tp::OP_C, W.m1, n2, (long long)L * n2, L, n2, L, h, rl, s);
         if (st == TP_OK)
             st = gemm(W.ya, L, sy, tp::OP_N, W.m1, n2, (long long)L * n2, tp::OP_N, W.wbar, n2, mn, n1, n2, L, h, rl, s);
         if (st != TP_OK) return st;
+    }
+    if (attempt == 1 || !opts->retry_wide) break;
+    // slices whose count check failed below the widest sketch: one retry with
+    // kpred = max_rank - oversample (the whole call is recomputed, the other
+    // slices identically)
+    TP_TRY(hipMemcpyAsync(hfb.data(), fb, h * sizeof(int), hipMemcpyDeviceToHost, s));
+    TP_TRY(hipStreamSynchronize(s));
+    const int kwide = std::min(std::max(opts->max_rank - opts->oversample, 0), p);
+    const int lwide = std::min(kwide + opts->oversample, p);
+    bool retry = false;
+    for (int k = 0; k < h; ++k)
+        if (hfb[k] && !hpre[k] && hl[k] < lwide && hk[k] < kwide) {
+            hk[k] = kwide;
+            hl[k] = lwide;
+            retry = true;
+        }
+    if (!retry) break;
     }
     // fallback slices: full SVD on a compact batch
     std::vector<int> hidx;
@@ -595,6 +630,8 @@ int tp_prox_tnn_learned(const float* Y, float* X, int n1, int n2, int n3, float 
         st = run_svt(F, W.cy, n1, n2, cnt, 0, 0, (double)tau, info ? W.cinfo : nullptr, W.crank, s);
         if (st != TP_OK) return st;
         TP_LAUNCH(tp::K_GATHER, s, tp::launch_gather(W.cy.re, W.cy.im, W.wbar.re, W.wbar.im, W.idx, cnt, mn, true, s));
+        if (sigma_out)
+            TP_LAUNCH(tp::K_GATHER, s, tp::launch_sigma_top(F.sigma, p, nullptr, W.idx, nullptr, cnt, sigma_out, s));
         std::vector<int> crank(cnt), cinfo(cnt, 0), hrank(h);
         TP_TRY(hipMemcpyAsync(crank.data(), W.crank, cnt * sizeof(int), hipMemcpyDeviceToHost, s));
         if (info) TP_TRY(hipMemcpyAsync(cinfo.data(), W.cinfo, cnt * sizeof(int), hipMemcpyDeviceToHost, s));
@@ -618,8 +655,8 @@ size_t tp_slice_features_workspace_size(int n1, int n2, int n3)
     return 2 * tp::align_up(h * n1 * n2 * sizeof(float));
 }
 
-int tp_slice_features(const float* Y, int n1, int n2, int n3, float tau, const int* prev_rank, float* feats,
-                      void* workspace, size_t workspace_bytes, void* stream)
+int tp_slice_features(const float* Y, int n1, int n2, int n3, float tau, const int* prev_rank, const float* prev_sigma,
+                      float* feats, void* workspace, size_t workspace_bytes, void* stream)
 {
     if (!Y || !feats) return TP_ERR_ARG;
     if (!(tau >= 0.0f) || std::isinf(tau)) return TP_ERR_ARG;
@@ -631,7 +668,8 @@ int tp_slice_features(const float* Y, int n1, int n2, int n3, float tau, const i
     if (!ar.ok) return TP_ERR_WORKSPACE;
     hipStream_t s = as_stream(stream);
     TP_LAUNCH(tp::K_RFFT, s, tp::launch_rfft(Y, re, im, (long long)n1 * n2, n3, s));
-    TP_LAUNCH(tp::K_FEATURES, s, tp::launch_features(re, im, n1, n2, n3, (int)h, (double)tau, prev_rank, feats, s));
+    TP_LAUNCH(tp::K_FEATURES, s,
+              tp::launch_features(re, im, n1, n2, n3, (int)h, (double)tau, prev_rank, prev_sigma, feats, s));
     return TP_OK;
 }
 

@@ -337,10 +337,13 @@ __global__ __launch_bounds__(256) void k_accuracy(const float* __restrict__ t1r,
 
 // ---------------------------------------------------------------- features --
 // Per slice: f = [log(tau/rms sigma), log(max column norm / tau), prev/p,
-// has_prev, frequency, real, log(p)/8, log(max(m,n)/p)], clamped to [-30, 30].
+// has_prev, frequency, real, log(p)/8, log(max(m,n)/p), and from the previous
+// call's leading singular values s: #{s > tau}/p, #{s > tau/1.25}/p,
+// log(s_1/tau), [s_c > tau]], logarithms clamped to [-30, 30].
 __global__ __launch_bounds__(256) void k_features(const float* __restrict__ yr, const float* __restrict__ yi, int m,
                                                   int n, int n3, int nslices, double tau,
-                                                  const int* __restrict__ prev, float* __restrict__ feats)
+                                                  const int* __restrict__ prev, const float* __restrict__ psig,
+                                                  float* __restrict__ feats)
 {
     __shared__ double red[256];
     __shared__ double redm[256];
@@ -380,6 +383,47 @@ __global__ __launch_bounds__(256) void k_features(const float* __restrict__ yr, 
         f[5] = is_real_slice(s, n3) ? 1.0f : 0.0f;
         f[6] = (float)(log((double)p) / 8.0);
         f[7] = (float)log((double)(m > n ? m : n) / (double)p);
+        float f8 = 0.0f, f9 = 0.0f, f10 = 0.0f, f11 = 0.0f;
+        if (psig) {
+            const float* sv = psig + (long long)s * TP_SIGMA_KEEP;
+            int a = 0, b = 0, c = 0;
+            for (int j = 0; j < TP_SIGMA_KEEP; ++j) {
+                const double v = sv[j];
+                c += v > 0.0 ? 1 : 0;
+                a += v > tau ? 1 : 0;
+                b += v > tau / 1.25 ? 1 : 0;
+            }
+            f8 = (float)a / (float)p;
+            f9 = (float)b / (float)p;
+            f10 = (sv[0] > 0.0f && tau > 0.0) ? clampf(log((double)sv[0] / tau)) : (sv[0] > 0.0f ? 30.0f : -30.0f);
+            f11 = (c > 0 && (double)sv[c - 1] > tau) ? 1.0f : 0.0f;
+        }
+        f[8] = f8;
+        f[9] = f9;
+        f[10] = f10;
+        f[11] = f11;
+    }
+}
+
+// Leading singular values of each slice, sorted decreasing, TP_SIGMA_KEEP per
+// slice (zero-padded): row r of `out` (slice map[r], or r) from the P
+// unsorted values sig[r*P ..], of which the first lact[r] are valid (or all);
+// rows with skip[r] != 0 are left alone.
+__global__ __launch_bounds__(256) void k_sigma_top(const double* __restrict__ sig, int P, const int* __restrict__ lact,
+                                                   const int* __restrict__ map, const int* __restrict__ skip,
+                                                   float* __restrict__ out)
+{
+    const int r = blockIdx.x;
+    if (skip && skip[r]) return;
+    const int valid = lact ? min(lact[r], P) : P;
+    const double* sv = sig + (long long)r * P;
+    float* o = out + (long long)(map ? map[r] : r) * TP_SIGMA_KEEP;
+    for (int j = threadIdx.x; j < TP_SIGMA_KEEP; j += blockDim.x) o[j] = 0.0f;
+    __syncthreads();
+    for (int j = threadIdx.x; j < valid; j += blockDim.x) {
+        int rank = 0;
+        for (int i = 0; i < valid; ++i) rank += (sv[i] > sv[j] || (sv[i] == sv[j] && i < j)) ? 1 : 0;
+        if (rank < TP_SIGMA_KEEP) o[rank] = (float)sv[j];
     }
 }
 
@@ -643,9 +687,17 @@ hipError_t launch_accuracy(Planes t1, Planes t2, const double* sigma, const int*
 }
 
 hipError_t launch_features(const float* yr, const float* yi, int m, int n, int n3, int nslices, double tau,
-                           const int* prev, float* feats, hipStream_t st)
+                           const int* prev, const float* prev_sigma, float* feats, hipStream_t st)
 {
-    k_features<<<nslices, 256, 0, st>>>(yr, yi, m, n, n3, nslices, tau, prev, feats);
+    k_features<<<nslices, 256, 0, st>>>(yr, yi, m, n, n3, nslices, tau, prev, prev_sigma, feats);
+    return hipGetLastError();
+}
+
+hipError_t launch_sigma_top(const double* sig, int P, const int* lact, const int* map, const int* skip, int rows,
+                            float* out, hipStream_t st)
+{
+    if (rows <= 0) return hipSuccess;
+    k_sigma_top<<<rows, 256, 0, st>>>(sig, P, lact, map, skip, out);
     return hipGetLastError();
 }
 

@@ -124,7 +124,9 @@ hipError_t launch_cm_to_planar(const float2* src, Planes dst, int L, int nslices
 hipError_t launch_accuracy(Planes t1, Planes t2, const double* sigma, const int* lact, int m, int L, double tau,
                            double delta, int* bad, int nslices, hipStream_t s);
 hipError_t launch_features(const float* yr, const float* yi, int m, int n, int n3, int nslices, double tau,
-                           const int* prev, float* feats, hipStream_t s);
+                           const int* prev, const float* prev_sigma, float* feats, hipStream_t s);
+hipError_t launch_sigma_top(const double* sig, int P, const int* lact, const int* map, const int* skip, int rows,
+                            float* out, hipStream_t s);
 hipError_t launch_predict(const float* params, const float* feats, int nslices, int p, int fixed_rank, int oversample,
                           int L, int* kpred, int* lact, int* fallback, int* rank, hipStream_t s);
 hipError_t launch_mlp_forward(const float* params, const float* x, float* y, int batch, hipStream_t s);

@@ -2,8 +2,10 @@
 
 Training samples come from the method's own prox calls inside TRPCA-ADMM
 runs (trpca.py): for every call and every leading Fourier slice, the
-features of tp_slice_features (with the previous call's count of that slice)
-and the exact count k* of singular values above tau from the full-SVD prox.
+features of tp_slice_features (with the previous call's count and leading
+singular values of that slice) and the exact count k* of singular values
+above tau (from the widest randomized sketch with the a posteriori check, or
+the full SVD where that falls back).
 The target is t = log1p(k*) / log1p(min(n1, n2)); the network is trained on
 the GPU with the library's own kernels (tp_mlp_loss_grad, tp_mlp_adam) on the
 asymmetric squared loss (under-prediction weighted `under` times, since it
@@ -31,7 +33,7 @@ WEIGHTS = os.path.join(HERE, "rank_mlp_gfx950.npy")
 def init_params(seed=0):
     """He-uniform weights, zero biases, packed as in include/tp.h."""
     rng = np.random.default_rng(seed)
-    D, H = 8, 64
+    D, H = tp.TP_MLP_INPUTS, 64
     parts = []
     for fan_in, fan_out in ((D, H), (H, H), (H, H), (H, 1)):
         b = math.sqrt(6.0 / fan_in)
@@ -84,14 +86,15 @@ def collect(shapes, runs, seed0, device, max_iter=200, log=print):
             r = rank_for(n, rng)
             X, _, _ = trpca.make_problem(n, n3, r, 0.05, seed, device)
             prox = label_prox(shape, device)
-            prev = {"rank": None}
+            prev = {"rank": None, "sigma": None}
 
-            def record(Yin, tau, rank):
-                f = tp.tp_slice_features(Yin, tau, prev["rank"])
+            def record(Yin, tau, rank, sigma):
+                f = tp.tp_slice_features(Yin, tau, prev["rank"], prev["sigma"])
                 feats.append(f.cpu().numpy())
                 t = np.log1p(rank.cpu().numpy().astype(np.float64)) / np.log1p(min(shape[0], shape[1]))
                 targets.append(t)
                 prev["rank"] = rank.clone()
+                prev["sigma"] = sigma.clone()
 
             t0 = time.perf_counter()
             res = trpca.trpca(X, prox, max_iter=max_iter, record=record)
@@ -136,9 +139,67 @@ def evaluate(params, F, T, device):
     return dict(under_rate=under, mae=mae)
 
 
+class PrevRank(trpca.ProxLearned):
+    """No network: each slice's predicted count is the largest count of the
+    previous call (0 at the first call)."""
+
+    name = "prev"
+
+    def __call__(self, Y, tau, out):
+        self.fixed_rank = int(self.prev.max()) if self.have_prev else 0
+        return super().__call__(Y, tau, out)
+
+
+def gain(mlp, seeds, device, shape=(1024, 1024, 64), full_runs=1, log=print):
+    """TRPCA on held-out problems of the learned-rank workload, driven by the
+    prox with the trained network, without it (previous count; a constant
+    count), and with the full SVD (the paper's method).  Reports total prox
+    time, fallback slices, recovery error, and the error of sampled learned
+    prox calls against the full-SVD prox on the same inputs."""
+    n, _, n3 = shape
+    out = {"shape": list(shape), "runs": []}
+    for si, seed in enumerate(seeds):
+        rng = np.random.default_rng(seed)
+        r = int(rng.integers(5, 41))
+        X, L0, _ = trpca.make_problem(n, n3, r, 0.05, seed, device)
+        row = {"seed": seed, "r": r}
+        caps = []
+        mlp_prox = trpca.ProxLearned(shape, device, mlp=mlp)
+
+        def cap(k, Y, tau):  # inputs and the previous call's outputs of some mlp-driven calls
+            if k % 6 == 3 and mlp_prox.have_prev:
+                caps.append((k, Y.clone(), tau, mlp_prox.prev.clone(), mlp_prox.prev_sigma.clone()))
+
+        variants = [("mlp", mlp_prox),
+                    ("mlp_noretry", trpca.ProxLearned(shape, device, mlp=mlp, retry_wide=False)),
+                    ("prev", PrevRank(shape, device)),
+                    ("const30", trpca.ProxLearned(shape, device, fixed_rank=30, use_prev=False)),
+                    ("const54", trpca.ProxLearned(shape, device, fixed_rank=54, use_prev=False))]
+        if si < full_runs:
+            variants.append(("full", trpca.ProxFull(shape, device)))
+        for name, prox in variants:
+            res = trpca.trpca(X, prox, capture=cap if name == "mlp" else None, time_prox=True)
+            row[name] = dict(prox_ms=round(res["prox_ms"], 1), iters=res["iters"],
+                             fallback_slices=getattr(prox, "fallbacks", None),
+                             L_err=float((res["L"] - L0).norm() / L0.norm()))
+            log(f"  seed {seed} r {r} {name}: {row[name]}", file=sys.stderr, flush=True)
+        errs = []
+        for k, Y, tau, pr, ps in caps:
+            Xl = tp.tp_prox_tnn_learned(Y, tau, mlp=mlp, prev_rank=pr, prev_sigma=ps)
+            Xf = tp.tp_prox_tnn(Y, tau)
+            errs.append((k, float((Xl - Xf).norm() / max(float(Xf.norm()), 1e-30))))
+        row["sampled_call_rel_err"] = errs
+        out["runs"].append(row)
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
-    ap.add_argument("cmd", choices=["train"])
+    ap.add_argument("cmd", choices=["train", "evaluate"])
+    ap.add_argument("--under", type=float, default=32.0, help="weight of under-prediction in the loss")
+    ap.add_argument("--weights", default=WEIGHTS)
+    ap.add_argument("--eval-seeds", default="10000,10001")
+    ap.add_argument("--full-runs", type=int, default=1)
     ap.add_argument("--out", default=WEIGHTS)
     ap.add_argument("--shapes", default="1024x1024x64,512x512x32,256x256x32")
     ap.add_argument("--runs", type=int, default=12, help="ADMM runs per shape")
@@ -147,6 +208,10 @@ def main():
     ap.add_argument("--seed", type=int, default=0, help="first ADMM seed (the evaluation uses 10000 and up)")
     args = ap.parse_args()
     dev = torch.device("cuda:0")
+    if args.cmd == "evaluate":
+        seeds = [int(v) for v in args.eval_seeds.split(",")]
+        print(json.dumps(gain(load(args.weights, dev), seeds, dev, full_runs=args.full_runs)), flush=True)
+        return
     t0 = time.perf_counter()
     shapes = [tuple(int(v) for v in sh.split("x")) for sh in args.shapes.split(",")]
     F, T = collect(shapes, args.runs, args.seed, dev, max_iter=args.max_iter)
@@ -154,9 +219,10 @@ def main():
     # hold out 10% of the samples (every tenth)
     val = np.zeros(F.shape[0], dtype=bool)
     val[::10] = True
-    params, hist = train(F[~val], T[~val], dev, steps=args.steps, seed=args.seed)
+    params, hist = train(F[~val], T[~val], dev, steps=args.steps, seed=args.seed, under=args.under)
     ev = evaluate(params, F[val], T[val], dev)
     meta = dict(samples=int(F.shape[0]), shapes=args.shapes, runs_per_shape=args.runs, seed0=args.seed,
+                under=args.under, steps=args.steps,
                 collect_s=round(t1 - t0, 1), train_s=round(time.perf_counter() - t1, 1), loss=hist,
                 heldout=ev)
     save(params.cpu().numpy(), args.out, meta)

@@ -45,30 +45,35 @@ class ProxLearned:
     name = "learned"
 
     def __init__(self, shape, device, mlp=None, fixed_rank=0, oversample=10, power_iters=2, max_rank=64, seed=0,
-                 use_prev=True, accuracy=2e-5, max_power_iters=8):
+                 use_prev=True, accuracy=2e-5, max_power_iters=8, retry_wide=True):
         n1, n2, n3 = shape
         self.h = tp.half_slices(n3)
         self.mlp, self.fixed_rank = mlp, fixed_rank
         self.oversample, self.power_iters, self.max_rank, self.seed = oversample, power_iters, max_rank, seed
-        self.accuracy, self.max_power_iters = accuracy, max_power_iters
+        self.accuracy, self.max_power_iters, self.retry_wide = accuracy, max_power_iters, retry_wide
         self.ws = torch.empty(tp.tp_prox_tnn_learned_workspace_size(n1, n2, n3, max_rank), dtype=torch.uint8,
                               device=device)
         self.rank = torch.zeros(self.h, dtype=torch.int32, device=device)
         self.fallback = torch.zeros(self.h, dtype=torch.int32, device=device)
         self.prev = torch.zeros(self.h, dtype=torch.int32, device=device)
+        self.sigma = torch.zeros((self.h, tp.TP_SIGMA_KEEP), dtype=torch.float32, device=device)
+        self.prev_sigma = torch.zeros_like(self.sigma)
         self.have_prev = False
         self.use_prev = use_prev
         self.calls = 0
         self.fallbacks = 0
 
     def __call__(self, Y, tau, out):
+        use = self.use_prev and self.have_prev
         tp.tp_prox_tnn_learned(Y, tau, mlp=self.mlp, fixed_rank=self.fixed_rank,
-                               prev_rank=self.prev if (self.use_prev and self.have_prev) else None,
+                               prev_rank=self.prev if use else None, prev_sigma=self.prev_sigma if use else None,
                                oversample=self.oversample, power_iters=self.power_iters, max_rank=self.max_rank,
                                seed=self.seed + self.calls, accuracy=self.accuracy,
-                               max_power_iters=self.max_power_iters, out=out, rank=self.rank,
-                               fallback=self.fallback, workspace=self.ws)
+                               max_power_iters=self.max_power_iters, retry_wide=self.retry_wide, out=out,
+                               rank=self.rank,
+                               fallback=self.fallback, sigma_out=self.sigma, workspace=self.ws)
         self.prev.copy_(self.rank)
+        self.prev_sigma.copy_(self.sigma)
         self.have_prev = True
         self.calls += 1
         self.fallbacks += int(self.fallback.sum())
@@ -79,8 +84,8 @@ def trpca(X, prox, lam=None, mu=1e-3, rho=1.1, mu_max=1e10, tol=1e-5, max_iter=5
           time_prox=False):
     """Inexact ALM for TRPCA on the GPU tensor X.
 
-    record(Yin, tau, rank_tensor) is called after every prox call (for
-    training samples); capture(k, Yin, tau) lets a caller keep prox inputs.
+    record(Yin, tau, rank_tensor, sigma_tensor) is called after every prox
+    call (for training samples); capture(k, Yin, tau) lets a caller keep prox inputs.
     Returns dict(L, S, iters, prox_ms (if timed), converged)."""
     n1, n2, n3 = X.shape
     if lam is None:
@@ -109,7 +114,7 @@ def trpca(X, prox, lam=None, mu=1e-3, rho=1.1, mu_max=1e10, tol=1e-5, max_iter=5
             torch.cuda.synchronize()
             prox_ms += ev0.elapsed_time(ev1)
         if record is not None:
-            record(Yin, tau, getattr(prox, "rank", None))
+            record(Yin, tau, getattr(prox, "rank", None), getattr(prox, "sigma", None))
         R = X - Lnew - Lam / mu
         Snew = torch.sign(R) * torch.clamp(R.abs() - lam / mu, min=0.0)
         resid = Lnew + Snew - X

@@ -11,7 +11,7 @@ from helpers import rel_fro, say
 pytestmark = pytest.mark.gpu
 torch = pytest.importorskip("torch")
 
-D, H = 8, 64
+D, H = 12, 64
 
 
 @pytest.fixture(scope="module")
@@ -73,9 +73,15 @@ def test_features(tp, orc, shape):
     Y = inputs.random_tensor(shape, seed=3)
     h = shape[2] // 2 + 1
     prev = np.arange(h, dtype=np.int32) % 5
-    for pv in (None, prev):
-        f = tp.tp_slice_features(gpu(Y), 0.7, None if pv is None else gpu(pv, np.int32)).cpu().numpy()
-        ref = orc.slice_features(Y, np.float32(0.7), pv)
+    rng = np.random.default_rng(2)
+    ps = np.zeros((h, 64), dtype=np.float32)
+    for k in range(h):
+        c = int(rng.integers(0, 65))
+        ps[k, :c] = np.sort(rng.uniform(0.1, 3.0, size=c))[::-1]
+    for pv, sv in ((None, None), (prev, None), (prev, ps)):
+        f = tp.tp_slice_features(gpu(Y), 0.7, None if pv is None else gpu(pv, np.int32),
+                                 None if sv is None else gpu(sv)).cpu().numpy()
+        ref = orc.slice_features(Y, np.float32(0.7), pv, sv)
         assert np.abs(f - ref).max() < 1e-5
 
 
@@ -112,7 +118,9 @@ def test_learned_prox_matches_oracle_rsvd(tp, orc):
     Y = lowrank(orc, 96, 80, 6, 5, seed=11, noise=0.05)
     tau = 0.15 * orc.tsn(Y)
     h = 4
-    kp = np.full(h, 5, dtype=np.int32)
+    # k = 5, oversample 4: l = 9, rounded up to the call's common width 16,
+    # which every slice uses, so the count check allows 16 - 4 = 12
+    kp = np.full(h, 12, dtype=np.int32)
     fb = torch.zeros(h, dtype=torch.int32, device="cuda:0")
     X = tp.tp_prox_tnn_learned(gpu(Y), tau, fixed_rank=5, oversample=4, power_iters=2, max_rank=16, seed=99,
                                accuracy=0.0, fallback=fb).cpu().numpy()
@@ -145,6 +153,28 @@ def test_learned_prox_forced_fallback(tp, orc):
     assert rel_fro(X, orc.prox_tnn(Y, np.float32(tau))) <= 1e-4
 
 
+def test_learned_prox_wide_retry(tp, orc):
+    """Under-predicted counts (k = 2 on tubal rank 6): without the retry every
+    slice fails the count check and takes the full SVD; with it the slices are
+    redone once at the widest sketch (k = max_rank - oversample) and pass."""
+    Y = lowrank(orc, 90, 70, 6, 6, seed=17)
+    tau = 0.1 * orc.tsn(Y)
+    h = 4
+    sig = orc.slice_sigma(Y)[:h]
+    exact = orc.prox_tnn(Y, np.float32(tau))
+    assert (sig > np.float32(tau)).sum(axis=1).min() > 2
+    for retry in (False, True):
+        fb = torch.zeros(h, dtype=torch.int32, device="cuda:0")
+        rk = torch.zeros(h, dtype=torch.int32, device="cuda:0")
+        X = tp.tp_prox_tnn_learned(gpu(Y), tau, fixed_rank=2, oversample=4, max_rank=24, retry_wide=retry,
+                                   rank=rk, fallback=fb).cpu().numpy()
+        err = rel_fro(X, exact)
+        say(f"  retry={retry}: rel.err {err:.2e} fallback {fb.cpu().numpy().tolist()}")
+        assert int(fb.sum()) == (0 if retry else h)
+        assert err <= 1e-4
+        assert np.array_equal(rk.cpu().numpy(), (sig > np.float32(tau)).sum(axis=1))
+
+
 def test_learned_prox_with_mlp_runs(tp, orc):
     """An MLP whose output is the constant log1p(4)/log1p(p) predicts k = 4."""
     Y = lowrank(orc, 50, 50, 4, 4, seed=2)
@@ -158,6 +188,30 @@ def test_learned_prox_with_mlp_runs(tp, orc):
     X = tp.tp_prox_tnn_learned(gpu(Y), tau, mlp=gpu(p), oversample=5, max_rank=16, rank=rk, fallback=fb).cpu().numpy()
     assert int(fb.sum()) == 0
     assert rel_fro(X, orc.prox_tnn(Y, np.float32(tau))) <= 1e-4
+
+
+def test_learned_prox_sigma_out(tp, orc):
+    """sigma_out holds each slice's leading singular values (decreasing), from
+    the randomized SVD or, for fallback slices, the full SVD."""
+    Y = lowrank(orc, 60, 50, 6, 4, seed=8, noise=0.01)
+    h = 4
+    so = torch.zeros((h, 64), dtype=torch.float32, device="cuda:0")
+    fb = torch.zeros(h, dtype=torch.int32, device="cuda:0")
+    kp = torch.tensor([4, 0, 4, 4], dtype=torch.int32)
+    tau = 0.05 * orc.tsn(Y)
+    tp.tp_prox_tnn_learned(gpu(Y), tau, fixed_rank=4, oversample=6, max_rank=16, fallback=fb, sigma_out=so)
+    sig = orc.slice_sigma(Y)[:h]
+    out = so.cpu().numpy()
+    assert int(fb.sum()) == 0
+    for k in range(h):
+        c = int((out[k] > 0).sum())
+        assert c >= 4 and np.all(np.diff(out[k, :c]) <= 0)
+        assert np.allclose(out[k, :4], sig[k, :4], rtol=1e-4)
+    # every slice through the full SVD: sigma_out = leading 64 exact values
+    so.zero_()
+    tp.tp_prox_tnn_learned(gpu(Y), tau, fixed_rank=20, oversample=2, max_rank=16, fallback=fb, sigma_out=so)
+    assert int(fb.sum()) == h
+    assert np.allclose(so.cpu().numpy()[:, :50], sig[:, :50], rtol=1e-4, atol=1e-6)
 
 
 def test_learned_prox_deterministic(tp, orc):
