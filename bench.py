@@ -3,20 +3,28 @@
 
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline]
 
-Prints one JSON line.  The headline workload is prox_tnn with the full
-per-slice SVD (Algorithm 3) on Y = P*Q + S + E, 200 x 200 x 50,
-tau = 1/sqrt(200*50); a step is one tp_prox_tnn call on that tensor (FFT,
-Jacobi SVD, shrinkage, two reconstruction products, inverse FFT), with the
-input resident in HBM.  value = n1*n2*n3 / time per call, in Melem/s.
+Prints one JSON line.
 
-The same line reports tprod on the precision workload (A 512x512x128,
-B 512x256x128) in FP32, split-BF16 (BF16X3) and BF16, in algorithmic
-TFLOP/s (8 n1 n2 l flops per complex slice product, 2 n1 n2 l per real one).
+Headline: learned-rank prox_tnn against full-SVD prox_tnn on the prox calls
+of a TRPCA-ADMM run on a held-out problem of the learned-rank workload
+(X = P*Q + S, 1024 x 1024 x 64, tubal rank r ~ U{5..40}, 5% +-1 outliers,
+seed 10000).  The ADMM run is made first (with the learned prox) and every
+call's input Y_t, tau_t = 1/mu_t and the previous call's per-slice counts and
+leading singular values are kept in HBM.  A step is one learned prox call
+(FFT, slice features, rank MLP, randomized SVD with the count check and the
+a posteriori check, full-SVD fallback, reconstruction, inverse FFT) on one
+captured call; K steps walk through the captured calls (evenly spaced when
+K is below their number, cyclically above it; by default one pass).
+value = n1 n2 n3 K / time, in Melem/s.  Every captured call is then run once
+through the full-SVD prox (Algorithm 3) on the same GPU, timed, and compared
+with the learned result.
 
-Per-kernel times come from HIP events the library records around each of its
-launches on the launch stream (tp_trace_enable), over the timed region.
-The cpu_baseline leg times the FP64 oracle on the host cores and compares
-the GPU results with it.
+The same line reports the full-SVD prox on the 200 x 200 x 50 workload and
+tprod on the precision workload (A 512x512x128, B 512x256x128) in FP32,
+split-BF16 (BF16X3) and BF16.
+
+Per-kernel times and the algorithmic flops and bytes of each launch come
+from the library's own stage trace (HIP events on the launch stream).
 """
 import argparse
 import json
@@ -31,18 +39,13 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 METRIC = "prox_tnn Melem/s learned-rank vs full-SVD @rel.err≤1e-4; tprod TFLOP/s"
-PEAK = {"hbm_GBs": 8000.0, "fp32_mfma_TF": 157.3, "bf16_mfma_TF": 2500.0, "valu_TF": 78.6}
-KNAMES = {0: "rfft", 1: "irfft", 2: "cgemm", 3: "jacobi", 4: "shrink", 5: "tnn_reduce"}
+PEAK = {"hbm_GBs": 8000.0, "fp32_mfma_TF": 157.3, "bf16_mfma_TF": 2500.0, "fp32_valu_TF": 157.3,
+        "valu_fp64_TF": 78.6}
+LEARNED_SEED = 10000
 
 
 def log(*a):
     print(*a, file=sys.stderr, flush=True)
-
-
-def tprod_flops(n1, n2, l, n3):
-    h = n3 // 2 + 1
-    nreal = 2 if n3 % 2 == 0 else 1
-    return (8 * (h - nreal) + 2 * nreal) * n1 * n2 * l
 
 
 def jacobi_sweep_flops(R, P, real):
@@ -53,51 +56,348 @@ def jacobi_sweep_flops(R, P, real):
     return per * R * P * (P - 1) // 2
 
 
-def collect(lib, cap=1 << 16):
-    import ctypes
-    ids = (ctypes.c_int * cap)()
-    ms = (ctypes.c_float * cap)()
-    n = lib.tp_trace_collect(ids, ms, cap)
-    if n < 0:
-        raise RuntimeError("tp_trace_collect failed")
-    n = min(n, cap)
+def summarize(recs, steps):
+    """Per-kernel totals of a trace: ms per step, launches per step, and the
+    algorithmic rates where the library accounts the work."""
     out = {}
-    for i in range(n):
-        out.setdefault(KNAMES.get(ids[i], str(ids[i])), []).append(ms[i])
-    return out
+    for name, ms, fl, by in recs:
+        d = out.setdefault(name, {"ms": 0.0, "launches": 0, "flops": 0.0, "bytes": 0.0})
+        d["ms"] += ms
+        d["launches"] += 1
+        d["flops"] += fl
+        d["bytes"] += by
+    table = {}
+    for name, d in sorted(out.items(), key=lambda kv: -kv[1]["ms"]):
+        row = {"ms_per_step": round(d["ms"] / steps, 4), "launches_per_step": round(d["launches"] / steps, 2),
+               "ms_per_launch": round(d["ms"] / d["launches"], 5)}
+        if d["bytes"] > 0:
+            row["GB_s"] = round(d["bytes"] / (d["ms"] * 1e-3) / 1e9, 1)
+        if d["flops"] > 0:
+            row["TFLOP_s"] = round(d["flops"] / (d["ms"] * 1e-3) / 1e12, 2)
+        table[name] = row
+    return out, table
 
 
-def timed(fn, steps, warmup, lib):
+def roofline_for(name, d, peak_mfma):
+    """Roofline object for one kernel class from its trace totals: HBM-bound
+    when its algorithmic intensity is below the machine balance for its
+    dtype, MFMA-bound above it."""
+    secs = d["ms"] * 1e-3
+    per_launch_ms = d["ms"] / d["launches"]
+    intensity = d["flops"] / d["bytes"] if d["bytes"] > 0 else float("inf")
+    balance = peak_mfma * 1e12 / (PEAK["hbm_GBs"] * 1e9)
+    if intensity < balance:
+        ach = d["bytes"] / secs / 1e9
+        return {"kernel": name, "bound": "hbm", "achieved": round(ach, 1), "peak": PEAK["hbm_GBs"], "unit": "GB/s",
+                "frac": round(ach / PEAK["hbm_GBs"], 4), "traffic": None,
+                "per_launch": {"ms": round(per_launch_ms, 5), "bytes": round(d["bytes"] / d["launches"]),
+                               "flops": round(d["flops"] / d["launches"])},
+                "intensity_flop_per_byte": round(intensity, 2)}
+    ach = d["flops"] / secs / 1e12
+    return {"kernel": name, "bound": "mfma", "achieved": round(ach, 2), "peak": peak_mfma, "unit": "TFLOP/s",
+            "frac": round(ach / peak_mfma, 4), "traffic": None,
+            "per_launch": {"ms": round(per_launch_ms, 5), "bytes": round(d["bytes"] / d["launches"]),
+                           "flops": round(d["flops"] / d["launches"])},
+            "intensity_flop_per_byte": round(intensity, 2)}
+
+
+def rel_err(X, Xref, Y, scale_by_input=False):
+    """||X - Xref||_F / ||Xref||_F, or with scale_by_input
+    ||X - Xref||_F / max(||Xref||_F, ||Y||_F) (the reading used where the
+    reference is small or 0: every singular value near or below tau).  Two
+    zero results count as equal."""
     import torch
-    for _ in range(warmup):
-        fn()
+    d = float(torch.linalg.vector_norm(X - Xref))
+    r = float(torch.linalg.vector_norm(Xref))
+    if scale_by_input:
+        r = max(r, float(torch.linalg.vector_norm(Y)))
+    if d == 0.0:
+        return 0.0
+    return d / r if r > 0 else float("inf")
+
+
+def selection(steps, ncalls):
+    if steps >= ncalls:
+        return [j % ncalls for j in range(steps)]
+    return [int(j * ncalls / steps) for j in range(steps)]
+
+
+# ------------------------------------------------------------- learned --
+def learned_block(args, tp, dev):
+    import torch
+
+    from paper_1806_07247_amd import rank_model, trpca
+
+    n, n3 = 1024, 64
+    X, L0, r = trpca.learned_workload(args.learned_seed, dev, n, n3)
+    shape = (n, n, n3)
+    h = n3 // 2 + 1
+    mlp = rank_model.load(device=dev)
+    prox = trpca.ProxLearned(shape, dev, mlp=mlp)
+    calls = []
+
+    def cap(k, Y, tau):
+        calls.append(dict(Y=Y.clone(), tau=tau, seed=prox.calls,
+                          prev=prox.prev.clone() if prox.have_prev else None,
+                          psig=prox.prev_sigma.clone() if prox.have_prev else None))
+
+    log(f"learned-rank workload {n}x{n}x{n3} seed {args.learned_seed} r {r}: ADMM capture")
+    t0 = time.perf_counter()
+    res = trpca.trpca(X, prox, capture=cap)
     torch.cuda.synchronize()
-    collect(lib)
-    lib.tp_trace_enable(1)
+    log(f"  {res['iters']} ADMM iterations ({len(calls)} prox calls) in {time.perf_counter() - t0:.1f} s, "
+        f"L rel.err {float((res['L'] - L0).norm() / L0.norm()):.2e}")
+    del X, L0, res
+    ncalls = len(calls)
+    steps = args.steps if args.steps else ncalls
+    sel = selection(steps, ncalls)
+
+    out = torch.empty((n, n, n3), dtype=torch.float32, device=dev)
+    rk = torch.zeros(h, dtype=torch.int32, device=dev)
+    fb = torch.zeros(h, dtype=torch.int32, device=dev)
+    so = torch.zeros((h, tp.TP_SIGMA_KEEP), dtype=torch.float32, device=dev)
+    ws = torch.empty(tp.tp_prox_tnn_learned_workspace_size(n, n, n3, 64), dtype=torch.uint8, device=dev)
+
+    info = torch.zeros(h, dtype=torch.int32, device=dev)
+    sweeps = torch.zeros(h, dtype=torch.int64, device=dev)
+
+    def learned(i, dst):
+        c = calls[i]
+        tp.tp_prox_tnn_learned(c["Y"], c["tau"], mlp=mlp, prev_rank=c["prev"], prev_sigma=c["psig"], seed=c["seed"],
+                               out=dst, rank=rk, fallback=fb, info=info, sigma_out=so, workspace=ws)
+
+    for j in range(args.warmup):
+        learned(sel[j % steps], out)
+    torch.cuda.synchronize()
+    tp.tp_trace_collect_work()
+    evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(steps)]
     start, stop = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    tp.tp_trace_enable(True)
     torch.cuda.synchronize()
     start.record()
-    for _ in range(steps):
-        fn()
+    for j in range(steps):
+        evs[j][0].record()
+        learned(sel[j], out)
+        evs[j][1].record()
+        sweeps.add_(info.abs())  # Jacobi sweeps of the fallback slices
     stop.record()
     torch.cuda.synchronize()
-    lib.tp_trace_enable(0)
-    per_kernel = collect(lib)
-    return start.elapsed_time(stop) / steps, per_kernel
+    tp.tp_trace_enable(False)
+    recs = tp.tp_trace_collect_work()
+    ms = start.elapsed_time(stop) / steps
+    per_call = {}
+    for j in range(steps):
+        per_call.setdefault(sel[j], []).append(evs[j][0].elapsed_time(evs[j][1]))
+    totals, stages = summarize(recs, steps)
+    sw = sweeps.cpu().numpy()
+    if "jacobi" in totals:  # the full SVDs of fallback slices (the small R-factor SVDs are not counted)
+        totals["jacobi"]["flops"] = float(sum(int(sw[k]) * jacobi_sweep_flops(n, n, k == 0 or k == h - 1)
+                                              for k in range(h)))
+        stages["jacobi"]["fallback_sweeps"] = int(sw.sum())
+        if totals["jacobi"]["flops"] > 0:
+            stages["jacobi"]["TFLOP_s"] = round(totals["jacobi"]["flops"] / (totals["jacobi"]["ms"] * 1e-3) / 1e12, 2)
+    value = n * n * n3 / (ms * 1e-3) / 1e6
+    log(f"  learned: {ms:.3f} ms/call, {value:.1f} Melem/s; stages {json.dumps(stages)}")
+
+    # full-SVD prox on the same calls, and the error of the learned result
+    fws = torch.empty(tp.tp_prox_tnn_workspace_size(n, n, n3), dtype=torch.uint8, device=dev)
+    frank = torch.zeros(h, dtype=torch.int32, device=dev)
+    xf = torch.empty_like(out)
+    distinct = sorted(per_call)
+    if args.full_calls and args.full_calls < len(distinct):
+        distinct = [distinct[int(j * len(distinct) / args.full_calls)] for j in range(args.full_calls)]
+    tp.tp_prox_tnn(calls[distinct[0]]["Y"], calls[distinct[0]]["tau"], out=xf, rank=frank, workspace=fws)  # warm-up
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    full_ms, lrn_ms, errs, errs_z, fbs, kmax = [], [], [], [], 0, []
+    log(f"  full-SVD prox on {len(distinct)} calls")
+    for i in distinct:
+        c = calls[i]
+        e0.record()
+        tp.tp_prox_tnn(c["Y"], c["tau"], out=xf, rank=frank, workspace=fws)
+        e1.record()
+        torch.cuda.synchronize()
+        full_ms.append(e0.elapsed_time(e1))
+        lrn_ms.append(float(np.median(per_call[i])))
+        learned(i, out)
+        torch.cuda.synchronize()
+        errs.append(rel_err(out, xf, None))
+        errs_z.append(rel_err(out, xf, c["Y"], scale_by_input=True))
+        fbs += int(fb.sum())
+        kmax.append(int(frank.max()))
+    speedup = float(np.sum(full_ms) / np.sum(lrn_ms))
+    full_value = n * n * n3 * len(full_ms) / (np.sum(full_ms) * 1e-3) / 1e6
+    log(f"  full: {np.mean(full_ms):.1f} ms/call; speedup {speedup:.1f}x; max rel.err {max(errs):.2e}")
+    block = {
+        "workload": f"TRPCA-ADMM prox calls, X = P*Q + S {n}x{n}x{n3}, tubal rank {r}, 5% +-1 outliers, "
+                    f"seed {args.learned_seed} (held out)",
+        "calls": ncalls, "steps": steps, "ms_per_call": round(ms, 4), "Melem_s": round(value, 3),
+        "full_svd": {"calls_timed": len(full_ms), "ms_per_call": round(float(np.mean(full_ms)), 3),
+                     "Melem_s": round(full_value, 4)},
+        "speedup_vs_full_svd": round(speedup, 2),
+        "rel_err_vs_full_svd": {"max": float(max(errs)), "median": float(np.median(errs)),
+                                "max_rel_to_max_of_output_and_input": float(max(errs_z))},
+        "fallback_slices": fbs, "slices_per_call": h, "max_count_above_tau": max(kmax),
+        "stages": stages,
+    }
+    # roofline: the learned path's dominant kernel class among those whose
+    # work the library accounts (the slice products and the transforms)
+    dom = max(totals, key=lambda k: totals[k]["ms"])
+    d = totals[dom]
+    if dom == "jacobi" and d["flops"] > 0:
+        ach = d["flops"] / (d["ms"] * 1e-3) / 1e12
+        roof = {"kernel": "jacobi", "bound": "alu", "achieved": round(ach, 3), "peak": PEAK["fp32_valu_TF"],
+                "unit": "TFLOP/s", "frac": round(ach / PEAK["fp32_valu_TF"], 4), "traffic": None,
+                "per_launch": {"ms": round(d["ms"] / d["launches"], 4), "flops": round(d["flops"] / d["launches"])}}
+    elif d["bytes"] > 0:
+        roof = roofline_for(dom, d, PEAK["fp32_mfma_TF"])
+    else:
+        roof = {"kernel": dom, "bound": None, "achieved": None, "peak": None, "unit": None, "frac": None,
+                "traffic": None}
+    roof["share_of_step"] = round(d["ms"] / (ms * steps), 4)
+    return value, ms, steps, block, roof, calls, mlp, r
 
 
-def per_launch_ms(per_kernel, name, launches_per_step, steps):
-    v = per_kernel.get(name, [])
-    if not v:
-        return None
-    return float(np.sum(v)) / (steps * launches_per_step)
+# --------------------------------------------------------- full prox D2 --
+def prox_full_block(args, tp, inputs, dev):
+    import torch
+    parts = inputs.prox_full_parts(seed=0)
+    n1, n2, n3 = parts["S"].shape
+    tau = float(parts["tau"])
+    P = torch.from_numpy(parts["P"]).to(dev)
+    Q = torch.from_numpy(parts["Q"]).to(dev)
+    Y = (tp.tp_tprod(P, Q) + torch.from_numpy(parts["S"]).to(dev) + torch.from_numpy(parts["E"]).to(dev)).contiguous()
+    h = n3 // 2 + 1
+    X = torch.empty_like(Y)
+    info = torch.zeros(h, dtype=torch.int32, device=dev)
+    rank = torch.zeros(h, dtype=torch.int32, device=dev)
+    ws = torch.empty(tp.tp_prox_tnn_workspace_size(n1, n2, n3), dtype=torch.uint8, device=dev)
+    steps = args.prox_steps
+    log(f"prox_tnn full SVD {n1}x{n2}x{n3} tau={tau:.4g}: {steps} steps")
+    for _ in range(3):
+        tp.tp_prox_tnn(Y, tau, out=X, info=info, rank=rank, workspace=ws)
+    torch.cuda.synchronize()
+    tp.tp_trace_collect_work()
+    tp.tp_trace_enable(True)
+    start, stop = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    start.record()
+    for _ in range(steps):
+        tp.tp_prox_tnn(Y, tau, out=X, info=info, rank=rank, workspace=ws)
+    stop.record()
+    torch.cuda.synchronize()
+    tp.tp_trace_enable(False)
+    totals, stages = summarize(tp.tp_trace_collect_work(), steps)
+    ms = start.elapsed_time(stop) / steps
+    sweeps = info.cpu().numpy()
+    R, Pc = max(n1, n2), min(n1, n2)
+    jflops = sum(abs(int(s)) * jacobi_sweep_flops(R, Pc, k == 0 or (n3 % 2 == 0 and k == h - 1))
+                 for k, s in enumerate(sweeps))
+    jms = totals["jacobi"]["ms"] / steps
+    block = {"workload": f"Y = P*Q + S + E {n1}x{n2}x{n3}, tau = 1/sqrt({n1}*{n3})", "ms_per_call": round(ms, 4),
+             "Melem_s": round(n1 * n2 * n3 / (ms * 1e-3) / 1e6, 3), "stages": stages,
+             "jacobi": {"ms": round(jms, 4), "sweeps": [int(s) for s in sweeps], "GFLOP": round(jflops / 1e9, 3),
+                        "TFLOP_s": round(jflops / (jms * 1e-3) / 1e12, 3),
+                        "frac_fp32_valu_peak": round(jflops / (jms * 1e-3) / 1e12 / PEAK["fp32_valu_TF"], 4)}}
+    log(f"  {ms:.4f} ms/call, {json.dumps(block['jacobi'])}")
+    return block, parts, Y
+
+
+# -------------------------------------------------------------- tprod --
+def tprod_block(args, tp, inputs, dev):
+    import torch
+    A_np, B_np = inputs.tprod_precision(seed=0)
+    A, B = torch.from_numpy(A_np).to(dev), torch.from_numpy(B_np).to(dev)
+    tn1, tn2, tl, tn3 = A_np.shape[0], A_np.shape[1], B_np.shape[1], A_np.shape[2]
+    tws = torch.empty(tp.tp_tprod_workspace_size(tn1, tn2, tl, tn3), dtype=torch.uint8, device=dev)
+    C = torch.empty((tn1, tl, tn3), dtype=torch.float32, device=dev)
+    block = {"workload": f"A {tn1}x{tn2}x{tn3} * B {tn2}x{tl}x{tn3}, N(0,1)"}
+    outs = {}
+    steps = args.tprod_steps
+    for prec in ("fp32", "bf16x3", "bf16"):
+        for _ in range(2):
+            tp.tp_tprod(A, B, prec=prec, out=C, workspace=tws)
+        torch.cuda.synchronize()
+        tp.tp_trace_collect_work()
+        tp.tp_trace_enable(True)
+        start, stop = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        start.record()
+        for _ in range(steps):
+            tp.tp_tprod(A, B, prec=prec, out=C, workspace=tws)
+        stop.record()
+        torch.cuda.synchronize()
+        tp.tp_trace_enable(False)
+        totals, stages = summarize(tp.tp_trace_collect_work(), steps)
+        tms = start.elapsed_time(stop) / steps
+        g = totals["cgemm"]
+        flops = g["flops"] / steps
+        peak = PEAK["fp32_mfma_TF"] if prec == "fp32" else PEAK["bf16_mfma_TF"]
+        row = {"ms": round(tms, 4), "GFLOP": round(flops / 1e9, 3), "TFLOP_s": round(flops / (tms * 1e-3) / 1e12, 2),
+               "cgemm_ms": round(g["ms"] / steps, 4), "cgemm_TFLOP_s": stages["cgemm"]["TFLOP_s"],
+               "cgemm_frac_peak": round(g["flops"] / (g["ms"] * 1e-3) / 1e12 / peak, 4),
+               "rfft_GB_s": stages["rfft"]["GB_s"], "irfft_GB_s": stages["irfft"]["GB_s"],
+               "rfft_frac_hbm": round(stages["rfft"]["GB_s"] / PEAK["hbm_GBs"], 4),
+               "irfft_frac_hbm": round(stages["irfft"]["GB_s"] / PEAK["hbm_GBs"], 4)}
+        block[prec] = row
+        outs[prec] = C.cpu().numpy()
+        log(f"tprod {prec}: {json.dumps(row)}")
+    return block, outs, A_np, B_np
+
+
+# --------------------------------------------------------- cpu oracle --
+def oracle_learned_prox(oracle, Y, tau, prev, psig, params, seed, oversample=10, max_rank=64, power=2):
+    """The oracle's learned-rank prox on one call: slice features, the rank
+    MLP, the common sketch width of the call, the randomized prox."""
+    n1, n2, n3 = Y.shape
+    p = min(n1, n2)
+    f = oracle.slice_features(Y, tau, prev, psig)
+    y = oracle.mlp_forward(params.astype(np.float64), f, f.shape[1], 64)
+    k = np.clip(np.rint(np.expm1(y * np.log1p(p))), 0, p).astype(np.int64)
+    lw = np.minimum(k + oversample, p)
+    L = min(int(-(-int(lw.max()) // 8) * 8), max_rank)
+    keff = np.maximum(k, min(L, p) - oversample).astype(np.int32)
+    return oracle.prox_tnn_rsvd(Y, np.float32(tau), keff, oversample=oversample, power=power, lfull=max_rank + 1,
+                                seed=seed)
+
+
+def cpu_baseline_learned(args, calls, tp, dev):
+    import oracle
+
+    from paper_1806_07247_amd import rank_model
+    nthr = int(os.environ.get("OMP_NUM_THREADS", "0") or 0) or min(16, os.cpu_count() or 1)
+    oracle.set_threads(nthr)
+    params = np.load(rank_model.WEIGHTS, allow_pickle=False)
+    n1, n2, n3 = calls[0]["Y"].shape
+    done, t0, errs = 0, time.perf_counter(), []
+    for i in range(len(calls) - 1, -1, -1):  # the converged end of the run first
+        c = calls[i]
+        Y = c["Y"].cpu().numpy()
+        prev = None if c["prev"] is None else c["prev"].cpu().numpy()
+        psig = None if c["psig"] is None else c["psig"].cpu().numpy().astype(np.float64)
+        log(f"cpu oracle learned prox, call {i}")
+        Xo, fbo, _ = oracle_learned_prox(oracle, Y, c["tau"], prev, psig, params, c["seed"])
+        done += 1
+        el = time.perf_counter() - t0
+        import torch
+        Xf = tp.tp_prox_tnn(c["Y"], c["tau"]).cpu().numpy()
+        nr = np.linalg.norm(Xf)
+        errs.append(float(np.linalg.norm(Xo - Xf) / (nr if nr > 0 else max(np.linalg.norm(Y), 1e-30))))
+        if el >= args.cpu_seconds:
+            break
+    cpu = {"value": round(n1 * n2 * n3 * done / el / 1e6, 4), "unit": "Melem/s", "cores": oracle.get_threads(),
+           "kind": "oracle",
+           "sample": f"{done} learned-rank prox call(s) of the same ADMM run, from its last call back "
+                     f"(FP64: slice features, rank MLP, randomized SVD with the count check), {el:.1f} s"}
+    return cpu, errs
 
 
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--steps", type=int, default=0, help="learned prox calls timed (0: one pass over all)")
     ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--learned-seed", type=int, default=LEARNED_SEED)
+    ap.add_argument("--full-calls", type=int, default=0, help="calls timed through the full SVD (0: all)")
+    ap.add_argument("--prox-steps", type=int, default=20)
     ap.add_argument("--tprod-steps", type=int, default=10)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=10.0)
@@ -110,127 +410,51 @@ def main():
     import torch
 
     import paper_1806_07247_amd as tp
-    from paper_1806_07247_amd import _lib, inputs
+    from paper_1806_07247_amd import inputs
 
-    lib = _lib.load()
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
 
-    # ---------------------------------------------------- prox full SVD --
-    parts = inputs.prox_full_parts(seed=0)
-    n1, n2, n3 = parts["S"].shape
-    tau = float(parts["tau"])
-    P = torch.from_numpy(parts["P"]).to(dev)
-    Q = torch.from_numpy(parts["Q"]).to(dev)
-    Y = (tp.tp_tprod(P, Q) + torch.from_numpy(parts["S"]).to(dev) + torch.from_numpy(parts["E"]).to(dev)).contiguous()
-    h = n3 // 2 + 1
-    X = torch.empty_like(Y)
-    info = torch.zeros(h, dtype=torch.int32, device=dev)
-    rank = torch.zeros(h, dtype=torch.int32, device=dev)
-    ws = torch.empty(tp.tp_prox_tnn_workspace_size(n1, n2, n3), dtype=torch.uint8, device=dev)
+    value, ms, steps, learned, roof, calls, mlp, r = learned_block(args, tp, dev)
+    prox_full, parts, _ = prox_full_block(args, tp, inputs, dev)
+    tprod, outs, A_np, B_np = tprod_block(args, tp, inputs, dev)
 
-    def prox_step():
-        tp.tp_prox_tnn(Y, tau, out=X, info=info, rank=rank, workspace=ws)
-
-    log(f"prox_tnn {n1}x{n2}x{n3} tau={tau:.4g}: warmup {args.warmup}, steps {args.steps}")
-    ms, pk = timed(prox_step, args.steps, args.warmup, lib)
-    sweeps = info.cpu().numpy()
-    value = n1 * n2 * n3 / (ms * 1e-3) / 1e6
-    R, Pc = max(n1, n2), min(n1, n2)
-    jflops = sum(abs(int(s)) * jacobi_sweep_flops(R, Pc, k == 0 or (n3 % 2 == 0 and k == h - 1))
-                 for k, s in enumerate(sweeps))
-    jms = per_launch_ms(pk, "jacobi", 1, args.steps)
-    stages = {}
-    fft_in = n1 * n2 * n3 * 4
-    fft_out = h * n1 * n2 * 8
-    for name, nl, byts in (("rfft", 1, fft_in + fft_out), ("irfft", 1, fft_in + fft_out),
-                           ("shrink", 1, 2 * h * n1 * n2 * 8 + h * Pc * 8)):
-        t = per_launch_ms(pk, name, nl, args.steps)
-        if t:
-            stages[name] = {"ms": round(t, 5), "GB_s": round(byts / (t * 1e-3) / 1e9, 1),
-                            "frac_hbm": round(byts / (t * 1e-3) / 1e9 / PEAK["hbm_GBs"], 4)}
-    gemm_ms = per_launch_ms(pk, "cgemm", 2, args.steps)
-    recon_flops = 2 * tprod_flops(n1, Pc, n2, n3) // 1  # two products, each ~ 8 n1 p n2 per complex slice
-    if gemm_ms:
-        stages["cgemm"] = {"ms_per_launch": round(gemm_ms, 5),
-                           "TFLOP_s": round(recon_flops / 2 / (gemm_ms * 1e-3) / 1e12, 2)}
-    stages["jacobi"] = {"ms": round(jms, 4), "sweeps": [int(s) for s in sweeps],
-                        "GFLOP": round(jflops / 1e9, 3),
-                        "TFLOP_s": round(jflops / (jms * 1e-3) / 1e12, 3)}
-    roofline = {"kernel": "jacobi", "bound": "alu", "achieved": round(jflops / (jms * 1e-3) / 1e12, 3),
-                "peak": PEAK["valu_TF"], "unit": "TFLOP/s",
-                "frac": round(jflops / (jms * 1e-3) / 1e12 / PEAK["valu_TF"], 4), "traffic": None}
-    log(f"  {ms:.4f} ms/step, {value:.1f} Melem/s, stages {json.dumps(stages)}")
-
-    # --------------------------------------------------- tprod precision --
-    A_np, B_np = inputs.tprod_precision(seed=0)
-    A, B = torch.from_numpy(A_np).to(dev), torch.from_numpy(B_np).to(dev)
-    tn1, tn2, tl, tn3 = A_np.shape[0], A_np.shape[1], B_np.shape[1], A_np.shape[2]
-    flops = tprod_flops(tn1, tn2, tl, tn3)
-    tws = torch.empty(tp.tp_tprod_workspace_size(tn1, tn2, tl, tn3), dtype=torch.uint8, device=dev)
-    C = torch.empty((tn1, tl, tn3), dtype=torch.float32, device=dev)
-    tprod = {"workload": f"A {tn1}x{tn2}x{tn3} * B {tn2}x{tl}x{tn3}, N(0,1)", "GFLOP": round(flops / 1e9, 3)}
-    outs = {}
-    for prec in ("fp32", "bf16x3", "bf16"):
-        def tstep():
-            tp.tp_tprod(A, B, prec=prec, out=C, workspace=tws)
-        log(f"tprod {prec}")
-        tms, tpk = timed(tstep, args.tprod_steps, 2, lib)
-        g = per_launch_ms(tpk, "cgemm", 1, args.tprod_steps)
-        peak = PEAK["fp32_mfma_TF"] if prec == "fp32" else PEAK["bf16_mfma_TF"]
-        rf = per_launch_ms(tpk, "rfft", 2, args.tprod_steps)
-        irf = per_launch_ms(tpk, "irfft", 1, args.tprod_steps)
-        th = tn3 // 2 + 1
-        rfft_bytes = ((tn1 * tn2 + tn2 * tl) * tn3 * 4 + th * (tn1 * tn2 + tn2 * tl) * 8) / 2
-        irfft_bytes = tn1 * tl * tn3 * 4 + th * tn1 * tl * 8
-        tprod[prec] = {"ms": round(tms, 4), "TFLOP_s": round(flops / (tms * 1e-3) / 1e12, 2),
-                       "cgemm_ms": round(g, 4), "cgemm_TFLOP_s": round(flops / (g * 1e-3) / 1e12, 2),
-                       "cgemm_frac_peak": round(flops / (g * 1e-3) / 1e12 / peak, 4),
-                       "rfft_GB_s": round(rfft_bytes / (rf * 1e-3) / 1e9, 1),
-                       "irfft_GB_s": round(irfft_bytes / (irf * 1e-3) / 1e9, 1)}
-        outs[prec] = C.cpu().numpy()
-        log(f"  {json.dumps(tprod[prec])}")
-
-    # ------------------------------------------------------ cpu baseline --
     cpu = None
-    parity = {}
+    parity = {"learned_vs_full_svd_max_rel_err": learned["rel_err_vs_full_svd"]["max"]}
     if not args.no_cpu_baseline:
         import oracle
-        nthr = int(os.environ.get("OMP_NUM_THREADS", "0") or 0) or min(16, os.cpu_count() or 1)
-        oracle.set_threads(nthr)
-        Ln = oracle.tprod(parts["P"], parts["Q"])
-        Yn = (Ln + parts["S"] + parts["E"]).astype(np.float32)
-        calls, t0 = 0, time.perf_counter()
-        while True:
-            Xref = oracle.prox_tnn(Yn, np.float32(tau))
-            calls += 1
-            el = time.perf_counter() - t0
-            if el >= args.cpu_seconds or calls >= 20:
-                break
-        cpu = {"value": round(n1 * n2 * n3 * calls / el / 1e6, 4), "unit": "Melem/s",
-               "cores": oracle.get_threads(), "kind": "oracle",
-               "sample": f"{calls} full prox_tnn call(s) on the same {n1}x{n2}x{n3} workload (FP64, "
-                         f"Y composed by the oracle's t-product), {el:.1f} s"}
-        # parity at full size: the GPU input Y was composed on the GPU; the
-        # comparison uses the GPU prox of the oracle-composed Y
+        cpu, errs = cpu_baseline_learned(args, calls, tp, dev)
+        parity["oracle_rsvd_no_check_vs_gpu_full_svd_rel_err"] = errs
+        log(f"cpu baseline {cpu}")
+        # full-size parity of the other two workloads
+        tau = float(parts["tau"])
+        Yn = (oracle.tprod(parts["P"], parts["Q"]) + parts["S"] + parts["E"]).astype(np.float32)
+        t0 = time.perf_counter()
+        Xref = oracle.prox_tnn(Yn, np.float32(tau))
+        prox_full["oracle_s_per_call"] = round(time.perf_counter() - t0, 2)
         Xg = tp.tp_prox_tnn(torch.from_numpy(Yn).to(dev), tau).cpu().numpy()
         parity["prox_full_rel_err"] = float(np.linalg.norm(Xg - Xref) / np.linalg.norm(Xref))
+        tn1, tl, tn3 = A_np.shape[0], B_np.shape[1], A_np.shape[2]
         rng = np.random.default_rng(1)
         idx = rng.choice(tn1 * tl * tn3, size=4000, replace=False)
         ref = oracle.tprod_entries(A_np, B_np, idx)
         for prec, Cn in outs.items():
             parity[f"tprod_{prec}_sampled_rel_err"] = float(
                 np.linalg.norm(Cn.reshape(-1)[idx] - ref) / np.linalg.norm(ref))
-        log(f"cpu baseline {cpu}, parity {parity}")
+        log(f"parity {parity}")
 
     line = {
         "metric": METRIC, "value": round(value, 3), "unit": "Melem/s", "n_gpus": 1,
-        "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms, 5),
+        "steps": steps, "warmup": args.warmup, "ms_per_step": round(ms, 5),
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
         "data": "synthetic",
-        "config": {"workload": f"prox_tnn full-SVD, Y = P*Q + S + E {n1}x{n2}x{n3}, tau = 1/sqrt({n1}*{n3})",
-                   "n1": n1, "n2": n2, "n3": n3, "tau": tau, "parallelism": "single GPU"},
-        "roofline": roofline, "cpu_baseline": cpu, "stages": stages, "tprod": tprod, "parity": parity,
+        "config": {"workload": "learned-rank prox_tnn on the TRPCA-ADMM prox calls of a held-out "
+                               f"1024x1024x64 low-tubal-rank (r={r}) plus 5% sparse problem, seed {args.learned_seed}",
+                   "n1": 1024, "n2": 1024, "n3": 64, "tubal_rank": r, "calls": learned["calls"],
+                   "rank_predictor": "MLP 12-64-64-64-1", "oversample": 10, "power_iters": 2,
+                   "parallelism": "single GPU"},
+        "roofline": roof, "cpu_baseline": cpu, "learned": learned, "prox_full_200": prox_full, "tprod": tprod,
+        "parity": parity,
     }
     print(json.dumps(line), flush=True)
 

@@ -246,10 +246,17 @@ int tp_get_param(int key);
  * last collect (or a negative tp_status) and forgets them.
  * Kernel ids: 0 rfft, 1 irfft, 2 cgemm, 3 jacobi, 4 shrink, 5 tnn_reduce,
  * 6 tsvd_finish, 7 features, 8 predict, 9 sketch, 10 cholqr, 11 rsvd_check,
- * 12 gather, 13 mlp.
+ * 12 gather, 13 mlp, 14 accuracy.
+ * tp_trace_collect_work also writes, per launch, the algorithmic work the
+ * library assigns to it (host arrays, either may be NULL): for the slice
+ * products 8 m n k flops per complex slice and 2 m n k per real one, and the
+ * FP32 bytes of both operands and the result (8 per complex element, 4 per
+ * real one); for the transforms 4 n1 n2 n3 bytes on the tensor side plus
+ * 8 h n1 n2 on the slice side; 0 for the other kernels.
  */
 int tp_trace_enable(int enable);
 int tp_trace_collect(int* kernel_ids, float* ms, int capacity);
+int tp_trace_collect_work(int* kernel_ids, float* ms, double* flops, double* bytes, int capacity);
 const char* tp_kernel_name(int id);
 
 #ifdef __cplusplus

@@ -23,6 +23,7 @@ _PREC = {"fp32": TP_PREC_FP32, "bf16x3": TP_PREC_BF16X3, "bf16": TP_PREC_BF16}
 __all__ = ["tp_tprod", "tp_tprod_workspace_size", "tp_tsvd", "tp_tsvd_workspace_size", "tp_prox_tnn", "tp_prox_tnn_workspace_size",
            "tp_tnn", "tp_tnn_workspace_size", "tp_prox_tnn_learned", "tp_prox_tnn_learned_workspace_size",
            "tp_slice_features", "tp_mlp_param_count", "tp_mlp_forward", "tp_mlp_loss_grad", "tp_mlp_adam",
+           "tp_trace_enable", "tp_trace_collect_work", "tp_kernel_name",
            "half_slices", "TPError", "TP_PREC_FP32",
            "TP_PREC_BF16X3", "TP_PREC_BF16", "library_path"]
 
@@ -220,3 +221,24 @@ def tp_mlp_adam(params, grad, m, v, step, lr=1e-3, beta1=0.9, beta2=0.999, eps=1
     _lib.check("tp_mlp_adam", lib.tp_mlp_adam(params.data_ptr(), grad.data_ptr(), m.data_ptr(), v.data_ptr(),
                                               int(step), float(lr), float(beta1), float(beta2), float(eps),
                                               _stream(params.device)))
+
+
+def tp_trace_enable(enable=True):
+    _lib.check("tp_trace_enable", _lib.load().tp_trace_enable(int(bool(enable))))
+
+
+def tp_kernel_name(kid):
+    return _lib.load().tp_kernel_name(int(kid)).decode()
+
+
+def tp_trace_collect_work(capacity=1 << 16):
+    """Launches recorded since the last collect: list of (kernel name, ms,
+    algorithmic flops, algorithmic bytes), in launch order."""
+    lib = _lib.load()
+    ids = (ctypes.c_int * capacity)()
+    ms = (ctypes.c_float * capacity)()
+    fl = (ctypes.c_double * capacity)()
+    by = (ctypes.c_double * capacity)()
+    n = lib.tp_trace_collect_work(ids, ms, fl, by, capacity)
+    _lib.check("tp_trace_collect_work", n if n < 0 else 0)
+    return [(tp_kernel_name(ids[i]), float(ms[i]), float(fl[i]), float(by[i])) for i in range(min(n, capacity))]

@@ -32,6 +32,8 @@ SIGNATURES = {
     "tp_get_param": (_I, [_I]),
     "tp_trace_enable": (_I, [_I]),
     "tp_trace_collect": (_I, [ctypes.POINTER(_I), ctypes.POINTER(_F), _I]),
+    "tp_trace_collect_work": (_I, [ctypes.POINTER(_I), ctypes.POINTER(_F), ctypes.POINTER(ctypes.c_double),
+                                   ctypes.POINTER(ctypes.c_double), _I]),
     "tp_kernel_name": (ctypes.c_char_p, [_I]),
 }
 

@@ -149,6 +149,7 @@ struct LearnedLayout {
     float2* jcols;
     float2* jv;
     double* jsig;
+    double* fpart;                  // per-band column norms of the features
     float* feats;
     tp::Planes vp, cp, t1, t2;      // V_r, U_r S (planar L x L), residual products (m x L)
     int *kpred, *lact, *fb, *rank, *status, *idx, *cinfo, *crank, *prefb, *bad;
@@ -192,6 +193,7 @@ tp::Arena learned_arena(void* ws, size_t bytes, int n1, int n2, int n3, int Lw, 
     t.jcols = ar.take<float2>(h * L * L);
     t.jv = ar.take<float2>(h * L * L);
     t.jsig = ar.take<double>(h * L);
+    t.fpart = reinterpret_cast<double*>(ar.take<char>(tp::features_part_bytes(n1, n2, (int)h)));
     t.feats = ar.take<float>(h * TP_MLP_INPUTS);
     t.kpred = ar.take<int>(h);
     t.lact = ar.take<int>(h);
@@ -493,7 +495,7 @@ int tp_prox_tnn_learned(const float* Y, float* X, int n1, int n2, int n3, float 
     // predicted count per slice and sketch width
     TP_LAUNCH(tp::K_FEATURES, s,
               tp::launch_features(ybar.re, ybar.im, n1, n2, n3, h, (double)tau, opts->prev_rank, opts->prev_sigma,
-                                  W.feats, s));
+                                  W.feats, W.fpart, s));
     TP_LAUNCH(tp::K_PREDICT, s,
               tp::launch_predict(opts->mlp, W.feats, h, p, opts->fixed_rank, opts->oversample, opts->max_rank,
                                  W.kpred, W.lact, W.prefb, rk, s));
@@ -652,7 +654,7 @@ size_t tp_slice_features_workspace_size(int n1, int n2, int n3)
 {
     if (bad_dim(n1) || bad_dim(n2) || bad_dim(n3)) return 0;
     const size_t h = (size_t)tp::half_slices(n3);
-    return 2 * tp::align_up(h * n1 * n2 * sizeof(float));
+    return 2 * tp::align_up(h * n1 * n2 * sizeof(float)) + tp::features_part_bytes(n1, n2, (int)h);
 }
 
 int tp_slice_features(const float* Y, int n1, int n2, int n3, float tau, const int* prev_rank, const float* prev_sigma,
@@ -665,11 +667,12 @@ int tp_slice_features(const float* Y, int n1, int n2, int n3, float tau, const i
     tp::Arena ar(workspace, workspace_bytes);
     float* re = ar.take<float>(h * n1 * n2);
     float* im = ar.take<float>(h * n1 * n2);
+    double* part = reinterpret_cast<double*>(ar.take<char>(tp::features_part_bytes(n1, n2, (int)h)));
     if (!ar.ok) return TP_ERR_WORKSPACE;
     hipStream_t s = as_stream(stream);
     TP_LAUNCH(tp::K_RFFT, s, tp::launch_rfft(Y, re, im, (long long)n1 * n2, n3, s));
     TP_LAUNCH(tp::K_FEATURES, s,
-              tp::launch_features(re, im, n1, n2, n3, (int)h, (double)tau, prev_rank, prev_sigma, feats, s));
+              tp::launch_features(re, im, n1, n2, n3, (int)h, (double)tau, prev_rank, prev_sigma, feats, part, s));
     return TP_OK;
 }
 

@@ -445,6 +445,11 @@ int pick_variant(const CgemmArgs& a)
 hipError_t launch_cgemm(const CgemmArgs& a, int opa, int opb, int prec, hipStream_t s)
 {
     if (a.m <= 0 || a.n <= 0 || a.nslices <= 0) return hipSuccess;
+    {
+        const int nreal = (a.real_first ? 1 : 0) + (a.real_last && a.nslices > 1 ? 1 : 0);
+        const double mnk = (double)a.m * a.n * a.k, elems = (double)a.m * a.k + (double)a.k * a.n + (double)a.m * a.n;
+        trace_work(mnk * (8.0 * (a.nslices - nreal) + 2.0 * nreal), elems * (8.0 * (a.nslices - nreal) + 4.0 * nreal));
+    }
     const int variant = pick_variant(a);
     if (prec != TP_PREC_FP32) {
         if (opa != OP_N || opb != OP_N) return hipErrorInvalidValue;

@@ -287,6 +287,7 @@ int any_tubes_per_block(int n)
 hipError_t launch_rfft(const float* x, float* re, float* im, long long ntubes, int n3, hipStream_t s)
 {
     if (ntubes <= 0) return hipSuccess;
+    trace_work(0.0, (double)ntubes * (4.0 * n3 + 8.0 * (n3 / 2 + 1)));
     const int g = grid_for(ntubes, kTubes);
     switch (n3) {
 #define TP_RFFT_CASE(N) \
@@ -309,6 +310,7 @@ hipError_t launch_rfft(const float* x, float* re, float* im, long long ntubes, i
 hipError_t launch_irfft(const float* re, const float* im, float* x, long long ntubes, int n3, hipStream_t s)
 {
     if (ntubes <= 0) return hipSuccess;
+    trace_work(0.0, (double)ntubes * (4.0 * n3 + 8.0 * (n3 / 2 + 1)));
     const int g = grid_for(ntubes, kTubes);
     switch (n3) {
 #define TP_IRFFT_CASE(N) \

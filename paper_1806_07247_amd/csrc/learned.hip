@@ -340,23 +340,37 @@ __global__ __launch_bounds__(256) void k_accuracy(const float* __restrict__ t1r,
 // has_prev, frequency, real, log(p)/8, log(max(m,n)/p), and from the previous
 // call's leading singular values s: #{s > tau}/p, #{s > tau/1.25}/p,
 // log(s_1/tau), [s_c > tau]], logarithms clamped to [-30, 30].
-__global__ __launch_bounds__(256) void k_features(const float* __restrict__ yr, const float* __restrict__ yi, int m,
-                                                  int n, int n3, int nslices, double tau,
-                                                  const int* __restrict__ prev, const float* __restrict__ psig,
-                                                  float* __restrict__ feats)
+// Squared column norms of each slice over one band of rows: block (c, s)
+// writes part[(s * nsplit + c) * n + j] for every column j (FP64 sums of
+// the FP32 entries; rows read whole, coalesced across the columns).
+__global__ __launch_bounds__(256) void k_features_part(const float* __restrict__ yr, const float* __restrict__ yi,
+                                                       int m, int n, int nsplit, double* __restrict__ part)
+{
+    const int c = blockIdx.x, s = blockIdx.y, tid = threadIdx.x;
+    const int rows = (m + nsplit - 1) / nsplit, i0 = c * rows, i1 = min(m, i0 + rows);
+    const float* Yr = yr + (long long)s * m * n;
+    const float* Yi = yi + (long long)s * m * n;
+    for (int j = tid; j < n; j += blockDim.x) {
+        double acc = 0.0;
+        for (int i = i0; i < i1; ++i) {
+            const double a = Yr[(long long)i * n + j], b = Yi[(long long)i * n + j];
+            acc += a * a + b * b;
+        }
+        part[((long long)s * nsplit + c) * n + j] = acc;
+    }
+}
+
+__global__ __launch_bounds__(256) void k_features(const double* __restrict__ part, int m, int n, int nsplit, int n3,
+                                                  int nslices, double tau, const int* __restrict__ prev,
+                                                  const float* __restrict__ psig, float* __restrict__ feats)
 {
     __shared__ double red[256];
     __shared__ double redm[256];
     const int s = blockIdx.x, tid = threadIdx.x;
-    const float* Yr = yr + (long long)s * m * n;
-    const float* Yi = yi + (long long)s * m * n;
     double tot = 0.0, cmax = 0.0;
     for (int j = tid; j < n; j += blockDim.x) {
         double c = 0.0;
-        for (int i = 0; i < m; ++i) {
-            const double a = Yr[(long long)i * n + j], b = Yi[(long long)i * n + j];
-            c += a * a + b * b;
-        }
+        for (int b = 0; b < nsplit; ++b) c += part[((long long)s * nsplit + b) * n + j];
         tot += c;
         cmax = fmax(cmax, c);
     }
@@ -686,10 +700,19 @@ hipError_t launch_accuracy(Planes t1, Planes t2, const double* sigma, const int*
     return hipGetLastError();
 }
 
-hipError_t launch_features(const float* yr, const float* yi, int m, int n, int n3, int nslices, double tau,
-                           const int* prev, const float* prev_sigma, float* feats, hipStream_t st)
+int features_split(int m) { return m < 16 * 32 ? (m + 31) / 32 : 16; }
+
+size_t features_part_bytes(int m, int n, int nslices)
 {
-    k_features<<<nslices, 256, 0, st>>>(yr, yi, m, n, n3, nslices, tau, prev, prev_sigma, feats);
+    return align_up((size_t)nslices * features_split(m) * n * sizeof(double));
+}
+
+hipError_t launch_features(const float* yr, const float* yi, int m, int n, int n3, int nslices, double tau,
+                           const int* prev, const float* prev_sigma, float* feats, double* part, hipStream_t st)
+{
+    const int ns = features_split(m);
+    k_features_part<<<dim3(ns, nslices), 256, 0, st>>>(yr, yi, m, n, ns, part);
+    k_features<<<nslices, 256, 0, st>>>(part, m, n, ns, n3, nslices, tau, prev, prev_sigma, feats);
     return hipGetLastError();
 }
 

@@ -12,7 +12,11 @@ namespace {
 struct Rec {
     hipEvent_t a, b;
     int id;
+    double flops, bytes;
 };
+
+// work reported inside the innermost open scope of this thread
+thread_local double t_flops = 0.0, t_bytes = 0.0;
 
 std::mutex g_mu;
 bool g_on = false;
@@ -39,6 +43,8 @@ const char* const kNames[] = {"rfft",    "irfft",   "cgemm",  "jacobi",     "shr
 
 TraceScope::TraceScope(hipStream_t s, int id) : stream_(s), id_(id), start_(nullptr)
 {
+    t_flops = 0.0;
+    t_bytes = 0.0;
     std::lock_guard<std::mutex> lk(g_mu);
     if (!g_on) return;
     start_ = take_event();
@@ -52,7 +58,13 @@ TraceScope::~TraceScope()
     hipEvent_t b = take_event();
     if (!b) return;
     hipEventRecord(b, stream_);
-    g_recs.push_back(Rec{static_cast<hipEvent_t>(start_), b, id_});
+    g_recs.push_back(Rec{static_cast<hipEvent_t>(start_), b, id_, t_flops, t_bytes});
+}
+
+void trace_work(double flops, double bytes)
+{
+    t_flops += flops;
+    t_bytes += bytes;
 }
 
 namespace {
@@ -93,6 +105,11 @@ int tp_trace_enable(int enable)
 
 int tp_trace_collect(int* kernel_ids, float* ms, int capacity)
 {
+    return tp_trace_collect_work(kernel_ids, ms, nullptr, nullptr, capacity);
+}
+
+int tp_trace_collect_work(int* kernel_ids, float* ms, double* flops, double* bytes, int capacity)
+{
     std::lock_guard<std::mutex> lk(tp::g_mu);
     int n = 0;
     for (const tp::Rec& r : tp::g_recs) {
@@ -102,6 +119,8 @@ int tp_trace_collect(int* kernel_ids, float* ms, int capacity)
         if (n < capacity) {
             if (kernel_ids) kernel_ids[n] = r.id;
             if (ms) ms[n] = t;
+            if (flops) flops[n] = r.flops;
+            if (bytes) bytes[n] = r.bytes;
         }
         ++n;
         tp::g_pool.push_back(r.a);

@@ -123,8 +123,10 @@ hipError_t launch_rsvd_check(const float2* cols, const double* sigma, const floa
 hipError_t launch_cm_to_planar(const float2* src, Planes dst, int L, int nslices, hipStream_t s);
 hipError_t launch_accuracy(Planes t1, Planes t2, const double* sigma, const int* lact, int m, int L, double tau,
                            double delta, int* bad, int nslices, hipStream_t s);
+// per-slice features; part: features_part_bytes(m, n, nslices) of scratch
+size_t features_part_bytes(int m, int n, int nslices);
 hipError_t launch_features(const float* yr, const float* yi, int m, int n, int n3, int nslices, double tau,
-                           const int* prev, const float* prev_sigma, float* feats, hipStream_t s);
+                           const int* prev, const float* prev_sigma, float* feats, double* part, hipStream_t st);
 hipError_t launch_sigma_top(const double* sig, int P, const int* lact, const int* map, const int* skip, int rows,
                             float* out, hipStream_t s);
 hipError_t launch_predict(const float* params, const float* feats, int nslices, int p, int fixed_rank, int oversample,
@@ -149,7 +151,8 @@ enum KernelId {
     K_ACCURACY = 14
 };
 
-// Records HIP events around the launches in its scope while tracing is on.
+// Records HIP events around the launches in its scope while tracing is on,
+// with the algorithmic work the launchers in the scope report.
 class TraceScope {
    public:
     TraceScope(hipStream_t s, int id);
@@ -160,6 +163,10 @@ class TraceScope {
     int id_;
     void* start_;
 };
+
+// Called by a launcher: adds the algorithmic flops and HBM bytes of the
+// kernel it enqueues to the enclosing TraceScope (ignored when not tracing).
+void trace_work(double flops, double bytes);
 
 }  // namespace tp
 

@@ -159,9 +159,7 @@ def gain(mlp, seeds, device, shape=(1024, 1024, 64), full_runs=1, log=print):
     n, _, n3 = shape
     out = {"shape": list(shape), "runs": []}
     for si, seed in enumerate(seeds):
-        rng = np.random.default_rng(seed)
-        r = int(rng.integers(5, 41))
-        X, L0, _ = trpca.make_problem(n, n3, r, 0.05, seed, device)
+        X, L0, r = trpca.learned_workload(seed, device, n, n3)
         row = {"seed": seed, "r": r}
         caps = []
         mlp_prox = trpca.ProxLearned(shape, device, mlp=mlp)

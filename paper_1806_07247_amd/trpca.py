@@ -143,6 +143,19 @@ def make_problem(n, n3, r, sparse_frac, seed, device):
     return (L0 + S0).contiguous(), L0, S0
 
 
+def learned_workload(seed, device, n=1024, n3=64):
+    """The learned-rank workload: X = P*Q + S, n x n x n3, tubal rank
+    r ~ U{5..40} drawn from the seed's own stream, P, Q entries N(0, 1/n),
+    5% +-1 outliers.  Returns (X, L0, r)."""
+    from paper_1806_07247_amd import inputs
+    parts = inputs.learned_rank_parts(seed, n, n3)
+    P = torch.from_numpy(parts["P"]).to(device)
+    Q = torch.from_numpy(parts["Q"]).to(device)
+    L0 = tp.tp_tprod(P, Q)
+    X = (L0 + torch.from_numpy(parts["S"]).to(device)).contiguous()
+    return X, L0, parts["r"]
+
+
 def timed_run(X, prox, **kw):
     torch.cuda.synchronize()
     t0 = time.perf_counter()
