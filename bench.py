@@ -401,6 +401,9 @@ def main():
     ap.add_argument("--tprod-steps", type=int, default=10)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=10.0)
+    ap.add_argument("--only", choices=["learned", "prox200", "tprod", "copy"], default=None,
+                    help="run one block and print its JSON (a short driver for counter runs); "
+                         "copy: a plain 1 GiB device copy, the reference for the byte counters")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported "
@@ -415,7 +418,24 @@ def main():
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
 
+    if args.only == "copy":
+        x = torch.empty(1 << 28, dtype=torch.float32, device=dev).fill_(1.0)
+        y = torch.empty_like(x)
+        for _ in range(3):
+            y.copy_(x)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes_read": x.numel() * 4, "copy_bytes_written": y.numel() * 4, "dispatches": 3}))
+        return
+    if args.only == "tprod":
+        print(json.dumps(tprod_block(args, tp, inputs, dev)[0]), flush=True)
+        return
+    if args.only == "prox200":
+        print(json.dumps(prox_full_block(args, tp, inputs, dev)[0]), flush=True)
+        return
     value, ms, steps, learned, roof, calls, mlp, r = learned_block(args, tp, dev)
+    if args.only == "learned":
+        print(json.dumps({"value": value, "roofline": roof, "learned": learned}), flush=True)
+        return
     prox_full, parts, _ = prox_full_block(args, tp, inputs, dev)
     tprod, outs, A_np, B_np = tprod_block(args, tp, inputs, dev)
 

@@ -110,7 +110,10 @@ int tp_prox_tnn(const float* Y, float* X, int n1, int n2, int n3, float tau, int
  * each leading Fourier slice's SVT computed on a randomized range whose width
  * is predicted per slice.  Per slice k: features of the slice (below) go
  * through the MLP (or fixed_rank is used) to give kpred, the predicted number
- * of singular values above tau; l = min(kpred + oversample, min(n1, n2));
+ * of singular values above tau; l = min(kpred + oversample, min(n1, n2)).
+ * The call's sketch width L is the largest l, rounded up to a multiple of 8
+ * (at most max_rank); every slice uses l = min(L, min(n1, n2)) columns and
+ * kpred = max(kpred, l - oversample).
  * Y = Ybar^(k) Om with the Gaussian sketch Om (Philox4x32-10 on counter
  * {row, column, slice, 0}, key = seed; Box-Muller; real on the real slices);
  * power_iters times {Z = Ybar^* Q, Y = Ybar Z}, every product re-orthonormalised
@@ -122,8 +125,12 @@ int tp_prox_tnn(const float* Y, float* X, int n1, int n2, int n3, float tau, int
  * the check below the widest sketch is first redone once with kpred =
  * max_rank - oversample, and falls back if it fails there).  With accuracy > 0, the kept
  * Ritz triplets (u_j, sigma_j, v_j), sigma_j > tau, are checked a posteriori:
- * when sum_j ||Ybar v_j - sigma_j u_j||^2 > accuracy^2 sum_j (sigma_j - tau)^2
- * on some slice, all slices get one more power iteration, up to
+ * when sum_j ||Ybar v_j - sigma_j u_j||^2 > accuracy^2 D on some slice, with
+ * D = max(sum_j (sigma_j - tau)^2, ||Ybar^(k)||_F^2) (accuracy_ref = 0: the
+ * error relative to the larger of the result and the input, the scale at
+ * which FP32 data can resolve a result much smaller than its input) or
+ * D = sum_j (sigma_j - tau)^2 (accuracy_ref = 1: relative to the result),
+ * all slices get one more power iteration, up to
  * max_power_iters in total, and slices still failing then fall back.
  * With l = min(n1,n2) or an exact rank <= l the result equals tp_prox_tnn's
  * up to rounding.
@@ -166,6 +173,7 @@ typedef struct tp_learned_opts {
     float accuracy;            /* a posteriori residual tolerance, 0 = no check */
     int max_power_iters;       /* cap on power iterations with the check */
     int retry_wide;            /* 1: retry count-check failures once at the widest sketch */
+    int accuracy_ref;          /* 0: check relative to max(result, input), 1: to the result */
 } tp_learned_opts;
 size_t tp_prox_tnn_learned_workspace_size(int n1, int n2, int n3, int max_rank);
 int tp_prox_tnn_learned(const float* Y, float* X, int n1, int n2, int n3, float tau,

@@ -154,6 +154,7 @@ def tp_prox_tnn_learned_workspace_size(n1, n2, n3, max_rank=64):
 
 def tp_prox_tnn_learned(Y, tau, mlp=None, fixed_rank=0, prev_rank=None, prev_sigma=None, oversample=10,
                         power_iters=2, max_rank=64, seed=0, accuracy=2e-5, max_power_iters=8, retry_wide=True,
+                        accuracy_ref=0,
                         out=None, rank=None, fallback=None, info=None, sigma_out=None, workspace=None):
     """Learned-rank prox (see include/tp.h); mlp is a float32 device tensor of
     tp_mlp_param_count() parameters or None (then every slice uses fixed_rank).
@@ -165,7 +166,7 @@ def tp_prox_tnn_learned(Y, tau, mlp=None, fixed_rank=0, prev_rank=None, prev_sig
     opts = _lib.LearnedOpts(_ptr(mlp), int(fixed_rank), _ptr(prev_rank), _ptr(prev_sigma), int(oversample),
                             int(power_iters),
                             int(max_rank), int(seed) & 0xFFFFFFFFFFFFFFFF, float(accuracy), int(max_power_iters),
-                            int(bool(retry_wide)))
+                            int(bool(retry_wide)), int(accuracy_ref))
     ws_bytes = lib.tp_prox_tnn_learned_workspace_size(n1, n2, n3, int(max_rank))
     ws = workspace if workspace is not None else _workspace(ws_bytes, Y.device)
     st = lib.tp_prox_tnn_learned(Y.data_ptr(), X.data_ptr(), n1, n2, n3, float(tau), ctypes.byref(opts),

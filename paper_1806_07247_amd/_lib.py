@@ -44,7 +44,7 @@ class LearnedOpts(ctypes.Structure):
     """tp_learned_opts of include/tp.h"""
     _fields_ = [("mlp", _VP), ("fixed_rank", _I), ("prev_rank", _VP), ("prev_sigma", _VP), ("oversample", _I),
                 ("power_iters", _I), ("max_rank", _I), ("seed", _U64), ("accuracy", _F), ("max_power_iters", _I),
-                ("retry_wide", _I)]
+                ("retry_wide", _I), ("accuracy_ref", _I)]
 
 
 SIGNATURES.update({

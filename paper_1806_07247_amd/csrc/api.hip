@@ -150,6 +150,7 @@ struct LearnedLayout {
     float2* jv;
     double* jsig;
     double* fpart;                  // per-band column norms of the features
+    double* fro2;                   // ||Ybar^(k)||_F^2 per slice
     float* feats;
     tp::Planes vp, cp, t1, t2;      // V_r, U_r S (planar L x L), residual products (m x L)
     int *kpred, *lact, *fb, *rank, *status, *idx, *cinfo, *crank, *prefb, *bad;
@@ -194,6 +195,7 @@ tp::Arena learned_arena(void* ws, size_t bytes, int n1, int n2, int n3, int Lw, 
     t.jv = ar.take<float2>(h * L * L);
     t.jsig = ar.take<double>(h * L);
     t.fpart = reinterpret_cast<double*>(ar.take<char>(tp::features_part_bytes(n1, n2, (int)h)));
+    t.fro2 = ar.take<double>(h);
     t.feats = ar.take<float>(h * TP_MLP_INPUTS);
     t.kpred = ar.take<int>(h);
     t.lact = ar.take<int>(h);
@@ -476,7 +478,7 @@ int tp_prox_tnn_learned(const float* Y, float* X, int n1, int n2, int n3, float 
     if (!(tau >= 0.0f) || std::isinf(tau)) return TP_ERR_ARG;
     if (opts->max_rank < 1 || opts->max_rank > tp::kMaxL || opts->oversample < 0 || opts->power_iters < 0 ||
         opts->power_iters > 16 || opts->max_power_iters > 64 || !(opts->accuracy >= 0.0f) ||
-        (!opts->mlp && opts->fixed_rank < 0))
+        (!opts->mlp && opts->fixed_rank < 0) || opts->accuracy_ref < 0 || opts->accuracy_ref > 1)
         return TP_ERR_ARG;
     if (bad_dim(n1) || bad_dim(n2) || bad_dim(n3) || n3 > kMaxN3) return TP_ERR_SHAPE;
     if (bad_slice(n1, n2)) return TP_ERR_SHAPE;
@@ -495,7 +497,7 @@ int tp_prox_tnn_learned(const float* Y, float* X, int n1, int n2, int n3, float 
     // predicted count per slice and sketch width
     TP_LAUNCH(tp::K_FEATURES, s,
               tp::launch_features(ybar.re, ybar.im, n1, n2, n3, h, (double)tau, opts->prev_rank, opts->prev_sigma,
-                                  W.feats, W.fpart, s));
+                                  W.feats, W.fpart, W.fro2, s));
     TP_LAUNCH(tp::K_PREDICT, s,
               tp::launch_predict(opts->mlp, W.feats, h, p, opts->fixed_rank, opts->oversample, opts->max_rank,
                                  W.kpred, W.lact, W.prefb, rk, s));
@@ -575,7 +577,8 @@ int tp_prox_tnn_learned(const float* Y, float* X, int n1, int n2, int n3, float 
             if (st == TP_OK) st = gemm(W.ya, L, sy, tp::OP_N, W.cp, L, sl, tp::OP_N, W.t2, L, sy, n1, L, L, h, rl, s);
             if (st != TP_OK) return st;
             TP_LAUNCH(tp::K_ACCURACY, s,
-                      tp::launch_accuracy(W.t1, W.t2, W.jsig, W.lact, n1, L, (double)tau, (double)opts->accuracy,
+                      tp::launch_accuracy(W.t1, W.t2, W.jsig, W.lact, opts->accuracy_ref == 0 ? W.fro2 : nullptr,
+                                          n1, L, (double)tau, (double)opts->accuracy,
                                           W.bad, h, s));
             TP_TRY(hipMemcpyAsync(hbad.data(), W.bad, h * sizeof(int), hipMemcpyDeviceToHost, s));
             TP_TRY(hipMemcpyAsync(hfb.data(), fb, h * sizeof(int), hipMemcpyDeviceToHost, s));
@@ -672,7 +675,8 @@ int tp_slice_features(const float* Y, int n1, int n2, int n3, float tau, const i
     hipStream_t s = as_stream(stream);
     TP_LAUNCH(tp::K_RFFT, s, tp::launch_rfft(Y, re, im, (long long)n1 * n2, n3, s));
     TP_LAUNCH(tp::K_FEATURES, s,
-              tp::launch_features(re, im, n1, n2, n3, (int)h, (double)tau, prev_rank, prev_sigma, feats, part, s));
+              tp::launch_features(re, im, n1, n2, n3, (int)h, (double)tau, prev_rank, prev_sigma, feats, part, nullptr,
+                                  s));
     return TP_OK;
 }
 

@@ -308,7 +308,8 @@ __global__ __launch_bounds__(256) void k_cm_to_planar(const float2* __restrict__
 __global__ __launch_bounds__(256) void k_accuracy(const float* __restrict__ t1r, const float* __restrict__ t1i,
                                                   const float* __restrict__ t2r, const float* __restrict__ t2i,
                                                   const double* __restrict__ sigma, const int* __restrict__ lact,
-                                                  int m, int L, double tau, double delta, int* __restrict__ bad)
+                                                  const double* __restrict__ fro2, int m, int L, double tau,
+                                                  double delta, int* __restrict__ bad)
 {
     __shared__ double red[256];
     const int s = blockIdx.x, tid = threadIdx.x;
@@ -331,6 +332,7 @@ __global__ __launch_bounds__(256) void k_accuracy(const float* __restrict__ t1r,
         double den = 0.0;
         for (int j = 0; j < lact[s]; ++j)
             if (sg[j] > tau) den += (sg[j] - tau) * (sg[j] - tau);
+        if (fro2 && den > 0.0) den = fmax(den, fro2[s]);
         bad[s] = (den > 0.0 && red[0] > delta * delta * den) ? 1 : 0;
     }
 }
@@ -362,7 +364,8 @@ __global__ __launch_bounds__(256) void k_features_part(const float* __restrict__
 
 __global__ __launch_bounds__(256) void k_features(const double* __restrict__ part, int m, int n, int nsplit, int n3,
                                                   int nslices, double tau, const int* __restrict__ prev,
-                                                  const float* __restrict__ psig, float* __restrict__ feats)
+                                                  const float* __restrict__ psig, float* __restrict__ feats,
+                                                  double* __restrict__ fro2)
 {
     __shared__ double red[256];
     __shared__ double redm[256];
@@ -387,6 +390,7 @@ __global__ __launch_bounds__(256) void k_features(const double* __restrict__ par
     if (tid == 0) {
         const int p = m < n ? m : n;
         const double nrm2 = red[0], cm = redm[0], t2 = tau * tau;
+        if (fro2) fro2[s] = nrm2;
         auto clampf = [](double v) { return (float)fmin(30.0, fmax(-30.0, v)); };
         float* f = feats + (long long)s * TP_MLP_INPUTS;
         f[0] = (nrm2 > 0.0 && t2 > 0.0) ? clampf(0.5 * log(t2 * p / nrm2)) : -30.0f;
@@ -693,10 +697,10 @@ hipError_t launch_cm_to_planar(const float2* src, Planes dst, int L, int nslices
     return hipGetLastError();
 }
 
-hipError_t launch_accuracy(Planes t1, Planes t2, const double* sigma, const int* lact, int m, int L, double tau,
-                           double delta, int* bad, int nslices, hipStream_t st)
+hipError_t launch_accuracy(Planes t1, Planes t2, const double* sigma, const int* lact, const double* fro2, int m,
+                           int L, double tau, double delta, int* bad, int nslices, hipStream_t st)
 {
-    k_accuracy<<<nslices, 256, 0, st>>>(t1.re, t1.im, t2.re, t2.im, sigma, lact, m, L, tau, delta, bad);
+    k_accuracy<<<nslices, 256, 0, st>>>(t1.re, t1.im, t2.re, t2.im, sigma, lact, fro2, m, L, tau, delta, bad);
     return hipGetLastError();
 }
 
@@ -708,11 +712,12 @@ size_t features_part_bytes(int m, int n, int nslices)
 }
 
 hipError_t launch_features(const float* yr, const float* yi, int m, int n, int n3, int nslices, double tau,
-                           const int* prev, const float* prev_sigma, float* feats, double* part, hipStream_t st)
+                           const int* prev, const float* prev_sigma, float* feats, double* part, double* fro2,
+                           hipStream_t st)
 {
     const int ns = features_split(m);
     k_features_part<<<dim3(ns, nslices), 256, 0, st>>>(yr, yi, m, n, ns, part);
-    k_features<<<nslices, 256, 0, st>>>(part, m, n, ns, n3, nslices, tau, prev, prev_sigma, feats);
+    k_features<<<nslices, 256, 0, st>>>(part, m, n, ns, n3, nslices, tau, prev, prev_sigma, feats, fro2);
     return hipGetLastError();
 }
 

@@ -45,12 +45,13 @@ class ProxLearned:
     name = "learned"
 
     def __init__(self, shape, device, mlp=None, fixed_rank=0, oversample=10, power_iters=2, max_rank=64, seed=0,
-                 use_prev=True, accuracy=2e-5, max_power_iters=8, retry_wide=True):
+                 use_prev=True, accuracy=2e-5, max_power_iters=8, retry_wide=True, accuracy_ref=0):
         n1, n2, n3 = shape
         self.h = tp.half_slices(n3)
         self.mlp, self.fixed_rank = mlp, fixed_rank
         self.oversample, self.power_iters, self.max_rank, self.seed = oversample, power_iters, max_rank, seed
         self.accuracy, self.max_power_iters, self.retry_wide = accuracy, max_power_iters, retry_wide
+        self.accuracy_ref = accuracy_ref
         self.ws = torch.empty(tp.tp_prox_tnn_learned_workspace_size(n1, n2, n3, max_rank), dtype=torch.uint8,
                               device=device)
         self.rank = torch.zeros(self.h, dtype=torch.int32, device=device)
@@ -69,7 +70,8 @@ class ProxLearned:
                                prev_rank=self.prev if use else None, prev_sigma=self.prev_sigma if use else None,
                                oversample=self.oversample, power_iters=self.power_iters, max_rank=self.max_rank,
                                seed=self.seed + self.calls, accuracy=self.accuracy,
-                               max_power_iters=self.max_power_iters, retry_wide=self.retry_wide, out=out,
+                               max_power_iters=self.max_power_iters, retry_wide=self.retry_wide,
+                               accuracy_ref=self.accuracy_ref, out=out,
                                rank=self.rank,
                                fallback=self.fallback, sigma_out=self.sigma, workspace=self.ws)
         self.prev.copy_(self.rank)

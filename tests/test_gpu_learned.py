@@ -239,8 +239,14 @@ def test_learned_prox_accuracy_check(tp, orc):
     kw = dict(fixed_rank=r, oversample=3, power_iters=2, max_rank=16, seed=5)
     loose = tp.tp_prox_tnn_learned(gpu(Y), tau, accuracy=0.0, **kw).cpu().numpy()
     fb = torch.zeros(3, dtype=torch.int32, device="cuda:0")
-    tight = tp.tp_prox_tnn_learned(gpu(Y), tau, accuracy=2e-5, max_power_iters=60, fallback=fb, **kw).cpu().numpy()
+    tight = tp.tp_prox_tnn_learned(gpu(Y), tau, accuracy=2e-5, max_power_iters=60, accuracy_ref=1, fallback=fb,
+                                   **kw).cpu().numpy()
     e0, e1 = rel_fro(loose, exact), rel_fro(tight, exact)
     say(f"  without check {e0:.2e}, with check {e1:.2e}, fallback {fb.cpu().numpy().tolist()}")
     assert e1 <= 1e-4
     assert e0 > e1
+    # the default check: relative to the larger of the result and the input
+    dflt = tp.tp_prox_tnn_learned(gpu(Y), tau, accuracy=2e-5, max_power_iters=60, **kw).cpu().numpy()
+    e2 = float(np.linalg.norm(dflt - exact) / max(np.linalg.norm(exact), np.linalg.norm(Y)))
+    say(f"  default check: {e2:.2e} relative to max(|X*|, |Y|)")
+    assert e2 <= 1e-4
