@@ -72,57 +72,81 @@ __global__ __launch_bounds__(256) void k_sketch(float* __restrict__ omr, float* 
 
 // ------------------------------------------------------------ CholeskyQR --
 // Partial Gram G_w = Y_w^* Y_w (FP64) of the rows handled by workgroup w of
-// nsplit, for the lact leading columns; Y is m x L planar row-major.
+// nsplit, for the lact leading columns; Y is m x L planar row-major.  The 256
+// threads form a 16 x 16 grid of B x B blocks of G (B = 1, 2, 4 for L <= 16,
+// 32, 64); blocks below the diagonal are written as zeros (only the upper
+// triangle is used).  Rows are staged in LDS in chunks; every product of two
+// FP32 values is exact in FP64 and the sums are FP64.
+template <int B>
 __global__ __launch_bounds__(256) void k_gram(const float* __restrict__ yr, const float* __restrict__ yi, int m,
                                               int L, const int* __restrict__ lact, double2* __restrict__ part,
                                               int nsplit)
 {
     constexpr int CH = 32;  // rows per LDS chunk
-    __shared__ float2 tile[CH * 64];
+    constexpr int W = 16 * B;
+    __shared__ float2 tile[CH * W];
     const int s = blockIdx.y, w = blockIdx.x, tid = threadIdx.x;
     const int la = lact[s];
+    const int ta = tid / 16, tb = tid % 16;
+    const int a0 = ta * B, b0 = tb * B;
+    const bool work = ta <= tb && a0 < la && b0 < la;
     const int r0 = (int)((long long)m * w / nsplit), r1 = (int)((long long)m * (w + 1) / nsplit);
     const float* Yr = yr + (long long)s * m * L;
     const float* Yi = yi + (long long)s * m * L;
-    constexpr int PER = 64 * 64 / 256;
-    double ar[PER], ai[PER];
+    double gr[B][B], gi[B][B];
 #pragma unroll
-    for (int u = 0; u < PER; ++u) ar[u] = ai[u] = 0.0;
+    for (int u = 0; u < B; ++u)
+#pragma unroll
+        for (int v = 0; v < B; ++v) gr[u][v] = gi[u][v] = 0.0;
+    const int lc = min(la, W);
     for (int c0 = r0; c0 < r1; c0 += CH) {
         const int nr = min(CH, r1 - c0);
         __syncthreads();
-        for (int e = tid; e < nr * L; e += blockDim.x) {
-            const int i = e / L, j = e % L;
-            tile[i * 64 + j] = make_float2(Yr[(long long)(c0 + i) * L + j], Yi[(long long)(c0 + i) * L + j]);
+        for (int e = tid; e < CH * W; e += blockDim.x) {
+            const int i = e / W, j = e % W;
+            float2 v = make_float2(0.f, 0.f);
+            if (i < nr && j < lc) v = make_float2(Yr[(long long)(c0 + i) * L + j], Yi[(long long)(c0 + i) * L + j]);
+            tile[e] = v;
         }
         __syncthreads();
+        if (work) {
+            for (int i = 0; i < nr; ++i) {
+                double xr[B], xi[B], vr[B], vi[B];
 #pragma unroll
-        for (int u = 0; u < PER; ++u) {
-            const int e = tid + u * 256;
-            const int a = e / 64, b = e % 64;
-            if (a < la && b < la) {
-                for (int i = 0; i < nr; ++i) {
-                    const float2 x = tile[i * 64 + a], y = tile[i * 64 + b];
-                    // conj(x) y
-                    ar[u] = fma((double)x.x, (double)y.x, fma((double)x.y, (double)y.y, ar[u]));
-                    ai[u] = fma((double)x.x, (double)y.y, fma(-(double)x.y, (double)y.x, ai[u]));
+                for (int u = 0; u < B; ++u) {
+                    const float2 x = tile[i * W + a0 + u], y = tile[i * W + b0 + u];
+                    xr[u] = x.x;
+                    xi[u] = x.y;
+                    vr[u] = y.x;
+                    vi[u] = y.y;
                 }
+#pragma unroll
+                for (int u = 0; u < B; ++u)
+#pragma unroll
+                    for (int v = 0; v < B; ++v) {  // conj(x_a) y_b
+                        gr[u][v] = fma(xr[u], vr[v], fma(xi[u], vi[v], gr[u][v]));
+                        gi[u][v] = fma(xr[u], vi[v], fma(-xi[u], vr[v], gi[u][v]));
+                    }
             }
         }
     }
     double2* out = part + ((long long)s * nsplit + w) * L * L;
 #pragma unroll
-    for (int u = 0; u < PER; ++u) {
-        const int e = tid + u * 256;
-        const int a = e / 64, b = e % 64;
-        if (a < L && b < L) out[a * L + b] = make_double2(ar[u], ai[u]);
-    }
+    for (int u = 0; u < B; ++u)
+#pragma unroll
+        for (int v = 0; v < B; ++v) {
+            const int a = a0 + u, b = b0 + v;
+            if (a < L && b < L) out[a * L + b] = work ? make_double2(gr[u][v], gi[u][v]) : make_double2(0.0, 0.0);
+        }
 }
 
-// Per slice: G = sum of the partial Grams (fixed order); in pass 0 a diagonal
-// shift 1e-13 trace(G)/lact; Cholesky G = R^* R (FP64, in LDS); Rinv = R^{-1}
-// written as FP32 planar (identity on the inactive columns); optionally
-// Rtot <- R Rtot (FP64) and R2^* (FP32 planar, zero outside the active block).
+// Per slice: G = sum of the partial Grams (fixed order, upper triangle); in
+// pass 0 a diagonal shift 1e-13 trace(G)/lact; Cholesky G = R^* R (FP64, in
+// LDS, right-looking: one row of R and a rank-1 update of the trailing block
+// per step, all threads in parallel); Rinv = R^{-1} by back substitution row
+// by row (parallel over the columns and the rows above), written as FP32
+// planar (identity on the inactive columns); optionally Rtot <- R Rtot (FP64)
+// and R2^* (FP32 planar, zero outside the active block).
 __global__ __launch_bounds__(256) void k_chol(const double2* __restrict__ part, int nsplit, int L,
                                               const int* __restrict__ lact, int pass, float* __restrict__ rir,
                                               float* __restrict__ rii, double2* __restrict__ rtot,
@@ -131,18 +155,20 @@ __global__ __launch_bounds__(256) void k_chol(const double2* __restrict__ part, 
 {
     extern __shared__ double2 sh[];
     double2* R = sh;            // L x L
-    double2* X = sh + L * L;    // L x L (inverse, then R Rtot)
+    double2* X = sh + L * L;    // L x L (inverse, then Rtot)
     __shared__ double sd;
     const int s = blockIdx.x, tid = threadIdx.x, nt = blockDim.x;
     const int la = lact[s];
     const double2* P = part + (long long)s * nsplit * L * L;
     for (int e = tid; e < L * L; e += nt) {
+        const int a = e / L, b = e % L;
         double2 g = make_double2(0.0, 0.0);
-        for (int w = 0; w < nsplit; ++w) {
-            const double2 v = P[(long long)w * L * L + e];
-            g.x += v.x;
-            g.y += v.y;
-        }
+        if (b >= a)
+            for (int w = 0; w < nsplit; ++w) {
+                const double2 v = P[(long long)w * L * L + e];
+                g.x += v.x;
+                g.y += v.y;
+            }
         R[e] = g;
     }
     __syncthreads();
@@ -154,13 +180,11 @@ __global__ __launch_bounds__(256) void k_chol(const double2* __restrict__ part, 
     __syncthreads();
     for (int a = tid; a < la; a += nt) R[a * L + a].x += sd;
     __syncthreads();
-    // in-place Cholesky on the upper triangle: row j of R from rows k < j
     for (int j = 0; j < L; ++j) {
         if (tid == 0) {
             double d = 1.0;
             if (j < la) {
                 d = R[j * L + j].x;
-                for (int k = 0; k < j; ++k) d -= R[k * L + j].x * R[k * L + j].x + R[k * L + j].y * R[k * L + j].y;
                 if (!(d > 0.0)) {
                     if (status) status[s] = 1;
                     d = 1e-300;
@@ -174,35 +198,50 @@ __global__ __launch_bounds__(256) void k_chol(const double2* __restrict__ part, 
             double2 v = make_double2(0.0, 0.0);
             if (j < la && c < la) {
                 v = R[j * L + c];
-                for (int k = 0; k < j; ++k) {  // - conj(R_kj) R_kc
-                    const double2 a = R[k * L + j], b = R[k * L + c];
-                    v.x -= a.x * b.x + a.y * b.y;
-                    v.y -= a.x * b.y - a.y * b.x;
-                }
                 v.x *= inv;
                 v.y *= inv;
             }
             R[j * L + c] = v;
         }
-        for (int c = tid; c < j; c += nt) R[j * L + c] = make_double2(0.0, 0.0);  // lower part
+        __syncthreads();
+        // trailing update of the upper triangle: R_ab -= conj(R_ja) R_jb, j < a <= b
+        const int t = L - j - 1;
+        for (int e = tid; e < t * t; e += nt) {
+            const int a = j + 1 + e / t, b = j + 1 + e % t;
+            if (b < a) continue;
+            const double2 x = R[j * L + a], y = R[j * L + b];
+            double2 v = R[a * L + b];
+            v.x -= x.x * y.x + x.y * y.y;
+            v.y -= x.x * y.y - x.y * y.x;
+            R[a * L + b] = v;
+        }
         __syncthreads();
     }
-    // X = R^{-1}, row j by thread j: X_jj = 1/R_jj, X_jc = -(sum_{j<=k<c} X_jk R_kc)/R_cc
-    for (int j = tid; j < L; j += nt) {
-        for (int c = 0; c < j; ++c) X[j * L + c] = make_double2(0.0, 0.0);
-        X[j * L + j] = make_double2(1.0 / R[j * L + j].x, 0.0);
-        for (int c = j + 1; c < L; ++c) {
-            double vr = 0.0, vi = 0.0;
-            for (int k = j; k < c; ++k) {
-                const double2 a = X[j * L + k], b = R[k * L + c];
-                vr += a.x * b.x - a.y * b.y;
-                vi += a.x * b.y + a.y * b.x;
-            }
-            const double ic = 1.0 / R[c * L + c].x;
-            X[j * L + c] = make_double2(-vr * ic, -vi * ic);
-        }
+    for (int e = tid; e < L * L; e += nt) {
+        const int a = e / L, b = e % L;
+        if (b < a) R[e] = make_double2(0.0, 0.0);
+        X[e] = make_double2(a == b ? 1.0 : 0.0, 0.0);
     }
     __syncthreads();
+    // R X = I: for j = L-1 .. 0, X_j /= R_jj, then X_i -= R_ij X_j for i < j
+    for (int j = L - 1; j >= 0; --j) {
+        const double inv = 1.0 / R[j * L + j].x;
+        for (int c = j + tid; c < L; c += nt) {
+            X[j * L + c].x *= inv;
+            X[j * L + c].y *= inv;
+        }
+        __syncthreads();
+        const int w = L - j;
+        for (int e = tid; e < j * w; e += nt) {
+            const int i = e / w, c = j + e % w;
+            const double2 r = R[i * L + j], x = X[j * L + c];
+            double2 v = X[i * L + c];
+            v.x -= r.x * x.x - r.y * x.y;
+            v.y -= r.x * x.y + r.y * x.x;
+            X[i * L + c] = v;
+        }
+        __syncthreads();
+    }
     for (int e = tid; e < L * L; e += nt) {
         rir[(long long)s * L * L + e] = (float)X[e].x;
         rii[(long long)s * L * L + e] = (float)X[e].y;
@@ -213,15 +252,29 @@ __global__ __launch_bounds__(256) void k_chol(const double2* __restrict__ part, 
         if (pass == 0) {
             for (int e = tid; e < L * L; e += nt) X[e] = R[e];
         } else {
-            for (int e = tid; e < L * L; e += nt) {  // X = R Rtot
-                const int a = e / L, b = e % L;
-                double vr = 0.0, vi = 0.0;
-                for (int k = 0; k < L; ++k) {
-                    const double2 u = R[a * L + k], v = T[k * L + b];
-                    vr += u.x * v.x - u.y * v.y;
-                    vi += u.x * v.y + u.y * v.x;
+            for (int e = tid; e < L * L; e += nt) X[e] = T[e];
+            __syncthreads();
+            // R Rtot of two upper triangular factors, entries kept in registers
+            constexpr int MAXE = 64 * 64 / 256;
+            double2 acc[MAXE];
+#pragma unroll
+            for (int u = 0; u < MAXE; ++u) {
+                const int e = tid + u * nt;
+                acc[u] = make_double2(0.0, 0.0);
+                if (e < L * L) {
+                    const int a = e / L, b = e % L;
+                    for (int k = a; k <= b; ++k) {
+                        const double2 x = R[a * L + k], y = X[k * L + b];
+                        acc[u].x += x.x * y.x - x.y * y.y;
+                        acc[u].y += x.x * y.y + x.y * y.x;
+                    }
                 }
-                X[e] = make_double2(vr, vi);
+            }
+            __syncthreads();
+#pragma unroll
+            for (int u = 0; u < MAXE; ++u) {
+                const int e = tid + u * nt;
+                if (e < L * L) X[e] = acc[u];
             }
         }
         __syncthreads();
@@ -660,13 +713,25 @@ hipError_t launch_sketch(float* omr, float* omi, int n, int L, const int* lact, 
 
 int gram_split(int m) { return m >= 2048 ? 16 : (m >= 256 ? 8 : 1); }
 
+template <int B>
+void launch_gram(const float* yr, const float* yi, int m, int L, const int* lact, int nslices, double2* part, int ns,
+                 hipStream_t st)
+{
+    k_gram<B><<<dim3(ns, nslices), 256, 0, st>>>(yr, yi, m, L, lact, part, ns);
+}
+
 hipError_t launch_cholqr_pass(const float* yr, const float* yi, int m, int L, const int* lact, int nslices,
                               int pass, double2* part, float* rir, float* rii, double2* rtot, float* rhr,
                               float* rhi, int* status, hipStream_t st)
 {
     if (L > kMaxL) return hipErrorInvalidValue;
     const int ns = gram_split(m);
-    k_gram<<<dim3(ns, nslices), 256, 0, st>>>(yr, yi, m, L, lact, part, ns);
+    if (L <= 16)
+        launch_gram<1>(yr, yi, m, L, lact, nslices, part, ns, st);
+    else if (L <= 32)
+        launch_gram<2>(yr, yi, m, L, lact, nslices, part, ns, st);
+    else
+        launch_gram<4>(yr, yi, m, L, lact, nslices, part, ns, st);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     const size_t lds = 2 * (size_t)L * L * sizeof(double2);
