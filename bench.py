@@ -19,9 +19,11 @@ value = n1 n2 n3 K / time, in Melem/s.  Every captured call is then run once
 through the full-SVD prox (Algorithm 3) on the same GPU, timed, and compared
 with the learned result.
 
-The same line reports the full-SVD prox on the 200 x 200 x 50 workload and
+The same line reports the full-SVD prox on the 200 x 200 x 50 workload,
 tprod on the precision workload (A 512x512x128, B 512x256x128) in FP32,
-split-BF16 (BF16X3) and BF16.
+split-BF16 (BF16X3) and BF16, and the batching workload (256 uneven tensors,
+tprod and prox as one plan each: eager, as a replayed HIP graph, and as 256
+sequential calls).
 
 Per-kernel times and the algorithmic flops and bytes of each launch come
 from the library's own stage trace (HIP events on the launch stream).
@@ -343,6 +345,90 @@ def tprod_block(args, tp, inputs, dev):
     return block, outs, A_np, B_np
 
 
+# ------------------------------------------------------------- batch --
+def batch_block(args, tp, inputs, dev):
+    """The batching workload: 256 tensors (n1, n2, l ~ U{16..128}, n3 in
+    {8, 16, 32, 64}), tprod (A_i * B_i) and prox (tau_i = 0.1 tsn(A_i)) as one
+    plan each, timed eagerly, as a replayed HIP graph, and against 256
+    sequential per-tensor calls."""
+    import torch
+    shapes = inputs.batch_shapes(seed=0)
+    pairs = inputs.batch_tensors(shapes, seed=0)
+    As = [torch.from_numpy(a).to(dev) for a, _ in pairs]
+    Bs = [torch.from_numpy(b).to(dev) for _, b in pairs]
+    reps = args.batch_steps
+    out = {"workload": f"{len(pairs)} tensors, n1, n2, l ~ U{{16..128}}, n3 in {{8,16,32,64}}, N(0,1), seed 0"}
+    for op in ("tprod", "prox"):
+        b = (tp.TPBatch("tprod", As, Bs) if op == "tprod"
+             else tp.TPBatch("prox", As, taus=[0.1] * len(As), tau_rel=True))
+        st = b.stats()
+        for _ in range(2):
+            b.run()
+        torch.cuda.synchronize()
+        tp.tp_trace_collect_work()
+        tp.tp_trace_enable(True)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(reps):
+            b.run()
+        e1.record()
+        torch.cuda.synchronize()
+        tp.tp_trace_enable(False)
+        totals, stages = summarize(tp.tp_trace_collect_work(), reps)
+        eager = e0.elapsed_time(e1) / reps
+        # the same plan as a HIP graph
+        s = torch.cuda.Stream()
+        s.wait_stream(torch.cuda.current_stream())
+        with torch.cuda.stream(s):
+            g = torch.cuda.CUDAGraph()
+            with torch.cuda.graph(g, stream=s):
+                b.run()
+        torch.cuda.current_stream().wait_stream(s)
+        g.replay()
+        torch.cuda.synchronize()
+        e0.record()
+        for _ in range(reps):
+            g.replay()
+        e1.record()
+        torch.cuda.synchronize()
+        graph = e0.elapsed_time(e1) / reps
+        # sequential per-tensor calls (prox with the tau the batch computed)
+        if op == "tprod":
+            ws = [torch.empty(tp.tp_tprod_workspace_size(a.shape[0], a.shape[1], bb.shape[1], a.shape[2]),
+                              dtype=torch.uint8, device=dev) for a, bb in zip(As, Bs)]
+            seq_out = [torch.empty((a.shape[0], bb.shape[1], a.shape[2]), device=dev) for a, bb in zip(As, Bs)]
+
+            def seq():
+                for a, bb, o, w in zip(As, Bs, seq_out, ws):
+                    tp.tp_tprod(a, bb, out=o, workspace=w)
+        else:
+            taus = [float(t) for t in b.tau_used.cpu()]
+            ws = [torch.empty(tp.tp_prox_tnn_workspace_size(*a.shape), dtype=torch.uint8, device=dev) for a in As]
+            seq_out = [torch.empty_like(a) for a in As]
+
+            def seq():
+                for a, t, o, w in zip(As, taus, seq_out, ws):
+                    tp.tp_prox_tnn(a, t, out=o, workspace=w)
+        seq()
+        torch.cuda.synchronize()
+        e0.record()
+        seq()
+        e1.record()
+        torch.cuda.synchronize()
+        sequential = e0.elapsed_time(e1)
+        diff = max(float(torch.linalg.norm(x - y) / max(float(torch.linalg.norm(y)), 1e-30))
+                   for x, y in zip(b.outs, seq_out))
+        row = {"ms_eager": round(eager, 4), "ms_graph": round(graph, 4), "ms_sequential_calls": round(sequential, 4),
+               "speedup_graph_vs_sequential": round(sequential / graph, 2),
+               "gemm_GFLOP": round(st["gemm_flops"] / 1e9, 3), "fft_MB": round(st["fft_bytes"] / 1e6, 1),
+               "TFLOP_s_gemm_work_over_graph_time": round(st["gemm_flops"] / (graph * 1e-3) / 1e12, 2),
+               "max_rel_diff_vs_sequential": diff, "stats": st, "stages": stages}
+        out[op] = row
+        log(f"batch {op}: {json.dumps({k: v for k, v in row.items() if k != 'stages'})}")
+        del g
+    return out
+
+
 # --------------------------------------------------------- cpu oracle --
 def oracle_learned_prox(oracle, Y, tau, prev, psig, params, seed, oversample=10, max_rank=64, power=2):
     """The oracle's learned-rank prox on one call: slice features, the rank
@@ -401,7 +487,8 @@ def main():
     ap.add_argument("--tprod-steps", type=int, default=10)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=10.0)
-    ap.add_argument("--only", choices=["learned", "prox200", "tprod", "copy"], default=None,
+    ap.add_argument("--batch-steps", type=int, default=10)
+    ap.add_argument("--only", choices=["learned", "prox200", "tprod", "batch", "copy"], default=None,
                     help="run one block and print its JSON (a short driver for counter runs); "
                          "copy: a plain 1 GiB device copy, the reference for the byte counters")
     args = ap.parse_args()
@@ -432,12 +519,16 @@ def main():
     if args.only == "prox200":
         print(json.dumps(prox_full_block(args, tp, inputs, dev)[0]), flush=True)
         return
+    if args.only == "batch":
+        print(json.dumps(batch_block(args, tp, inputs, dev)), flush=True)
+        return
     value, ms, steps, learned, roof, calls, mlp, r = learned_block(args, tp, dev)
     if args.only == "learned":
         print(json.dumps({"value": value, "roofline": roof, "learned": learned}), flush=True)
         return
     prox_full, parts, _ = prox_full_block(args, tp, inputs, dev)
     tprod, outs, A_np, B_np = tprod_block(args, tp, inputs, dev)
+    batch = batch_block(args, tp, inputs, dev)
 
     cpu = None
     parity = {"learned_vs_full_svd_max_rel_err": learned["rel_err_vs_full_svd"]["max"]}
@@ -473,7 +564,7 @@ def main():
                    "n1": 1024, "n2": 1024, "n3": 64, "tubal_rank": r, "calls": learned["calls"],
                    "rank_predictor": "MLP 12-64-64-64-1", "oversample": 10, "power_iters": 2,
                    "parallelism": "single GPU"},
-        "roofline": roof, "cpu_baseline": cpu, "learned": learned, "prox_full_200": prox_full, "tprod": tprod,
+        "roofline": roof, "cpu_baseline": cpu, "learned": learned, "prox_full_200": prox_full, "tprod": tprod, "batch": batch,
         "parity": parity,
     }
     print(json.dumps(line), flush=True)

@@ -218,6 +218,66 @@ int tp_tnn(const float* A, int n1, int n2, int n3, double* out, int* info, void*
            size_t workspace_bytes, void* stream);
 
 /*
+ * Batched tprod and prox_tnn over many tensors of uneven sizes (the slice
+ * pipeline of Algorithms 1 and 3 applied to each tensor).  A plan lists the
+ * work of every tensor; each stage of the pipeline is then one launch of a
+ * persistent kernel over all tensors (transforms, slice products, Jacobi
+ * SVDs, shrinkage), so the cost of a batch does not grow with launches per
+ * tensor.
+ *   tp_batch_create  validates the items and sizes the plan (host only; the
+ *                    item array is copied; the tensors must stay allocated
+ *                    while the plan is used).  op is TP_BATCH_TPROD
+ *                    (C_i = A_i * B_i, n1 x l x n3) or TP_BATCH_PROX
+ *                    (C_i = prox of tau_i ||.||_* at A_i, n1 x n2 x n3; n1, n2
+ *                    <= 128).  With TP_BATCH_TAU_REL (prox only) tau_i =
+ *                    item.tau * tsn(A_i), tsn = max_k sigma_1(Abar^(k))
+ *                    (Definition 2.8), computed on the device between the SVD
+ *                    and the shrinkage.  n3 <= 128.  opts may be NULL (all
+ *                    zero = automatic): tile 1 = 32x32, 2 = 64x64 output tiles
+ *                    of the slice products; grid_* persistent workgroups per
+ *                    stage; max_sweeps the Jacobi cap.
+ *   tp_batch_workspace_size  device bytes for the tables and all planes.
+ *   tp_batch_bind    writes the plan's descriptor tables into the workspace
+ *                    (device memory, caller-owned, at least the size above) on
+ *                    `stream` and waits for the copy.
+ *   tp_batch_run     enqueues the stages on `stream`; no allocation, copy or
+ *                    synchronisation, so a HIP graph may capture it and
+ *                    replay it while the workspace and the tensors live.
+ *   tp_batch_stats   unit counts and the chosen launch shapes.
+ * Optional per-item outputs (device, prox only): rank int[floor(n3/2)+1]
+ * (#{sigma_j > tau_i} per slice) and tau_used float[1].
+ */
+#define TP_BATCH_TPROD 0
+#define TP_BATCH_PROX 1
+#define TP_BATCH_TAU_REL 1
+typedef struct tp_batch_item {
+    int n1, n2, l, n3;
+    const float* A;
+    const float* B;      /* tprod only */
+    float* C;
+    float tau;           /* prox: tau, or its factor of tsn(A) with TP_BATCH_TAU_REL */
+    int* rank;           /* optional, prox */
+    float* tau_used;     /* optional, prox */
+} tp_batch_item;
+typedef struct tp_batch_opts {
+    int tile;            /* 0 auto, 1 = 32x32, 2 = 64x64 */
+    int grid_fft, grid_gemm, grid_jacobi;  /* 0 auto */
+    int max_sweeps;      /* 0 = TP_PARAM_JACOBI_SWEEPS */
+} tp_batch_opts;
+typedef struct tp_batch_stats_t {
+    int fft_units, gemm_units, slice_units, tile, grid_fft, grid_gemm, grid_jacobi;
+    double gemm_flops, fft_bytes;
+} tp_batch_stats_t;
+typedef struct tp_batch tp_batch;
+int tp_batch_create(tp_batch** plan, int op, const tp_batch_item* items, int count, int flags,
+                    const tp_batch_opts* opts);
+size_t tp_batch_workspace_size(const tp_batch* plan);
+int tp_batch_bind(tp_batch* plan, void* workspace, size_t workspace_bytes, void* stream);
+int tp_batch_run(const tp_batch* plan, void* stream);
+int tp_batch_stats(const tp_batch* plan, tp_batch_stats_t* stats);
+int tp_batch_destroy(tp_batch* plan);
+
+/*
  * Tunable launch parameters (process-wide, host side).  They select among
  * equivalent kernel schedules: results stay within the documented
  * tolerances for every setting, but workspace sizes may change, so query them

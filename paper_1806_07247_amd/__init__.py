@@ -23,7 +23,8 @@ _PREC = {"fp32": TP_PREC_FP32, "bf16x3": TP_PREC_BF16X3, "bf16": TP_PREC_BF16}
 __all__ = ["tp_tprod", "tp_tprod_workspace_size", "tp_tsvd", "tp_tsvd_workspace_size", "tp_prox_tnn", "tp_prox_tnn_workspace_size",
            "tp_tnn", "tp_tnn_workspace_size", "tp_prox_tnn_learned", "tp_prox_tnn_learned_workspace_size",
            "tp_slice_features", "tp_mlp_param_count", "tp_mlp_forward", "tp_mlp_loss_grad", "tp_mlp_adam",
-           "tp_trace_enable", "tp_trace_collect_work", "tp_kernel_name",
+           "tp_trace_enable", "tp_trace_collect_work", "tp_kernel_name", "TPBatch", "tp_batch_tprod",
+           "tp_batch_prox",
            "half_slices", "TPError", "TP_PREC_FP32",
            "TP_PREC_BF16X3", "TP_PREC_BF16", "library_path"]
 
@@ -243,3 +244,96 @@ def tp_trace_collect_work(capacity=1 << 16):
     n = lib.tp_trace_collect_work(ids, ms, fl, by, capacity)
     _lib.check("tp_trace_collect_work", n if n < 0 else 0)
     return [(tp_kernel_name(ids[i]), float(ms[i]), float(fl[i]), float(by[i])) for i in range(min(n, capacity))]
+
+
+TP_BATCH_TPROD = 0
+TP_BATCH_PROX = 1
+TP_BATCH_TAU_REL = 1
+
+
+class TPBatch:
+    """A bound batch plan (tp_batch_create + tp_batch_bind): run() enqueues
+    the whole batch on the current stream (capturable in a HIP graph).
+
+    op "tprod": outputs C_i = A_i * B_i.  op "prox": outputs the prox of
+    tau_i ||.||_* at A_i, with tau_i = taus[i], or taus[i] * tsn(A_i) when
+    tau_rel.  The tensors (inputs and outputs) and the workspace are kept
+    alive by the plan."""
+
+    def __init__(self, op, As, Bs=None, taus=None, tau_rel=False, outs=None, ranks=False, tile=0, grid_fft=0,
+                 grid_gemm=0, grid_jacobi=0, max_sweeps=0, tuned=True):
+        lib = _lib.load()
+        if tuned and not (tile or grid_fft or grid_gemm or grid_jacobi):
+            from . import autotune
+            o = autotune.batch_opts(op, autotune.batch_shapes_of(As, Bs if op == "tprod" else None))
+            tile, grid_fft = o.get("tile", 0), o.get("grid_fft", 0)
+            grid_gemm, grid_jacobi = o.get("grid_gemm", 0), o.get("grid_jacobi", 0)
+        self._lib = lib
+        self.op = {"tprod": TP_BATCH_TPROD, "prox": TP_BATCH_PROX}[op]
+        self.As = [_dev_tensor(a, "A") for a in As]
+        dev = self.As[0].device
+        n = len(self.As)
+        if self.op == TP_BATCH_TPROD:
+            if Bs is None or len(Bs) != n:
+                raise ValueError("tprod needs one B per A")
+            self.Bs = [_dev_tensor(b, "B") for b in Bs]
+            shapes = [(a.shape[0], a.shape[1], b.shape[1], a.shape[2]) for a, b in zip(self.As, self.Bs)]
+            for a, b in zip(self.As, self.Bs):
+                if b.shape[0] != a.shape[1] or b.shape[2] != a.shape[2]:
+                    raise ValueError("B must be n2 x l x n3")
+            self.outs = outs or [torch.empty((s[0], s[2], s[3]), dtype=torch.float32, device=dev) for s in shapes]
+        else:
+            self.Bs = [None] * n
+            if taus is None or len(taus) != n:
+                raise ValueError("prox needs one tau per tensor")
+            shapes = [(a.shape[0], a.shape[1], 0, a.shape[2]) for a in self.As]
+            self.outs = outs or [torch.empty_like(a) for a in self.As]
+        self.ranks = ([torch.zeros(half_slices(s[3]), dtype=torch.int32, device=dev) for s in shapes]
+                      if (ranks and self.op == TP_BATCH_PROX) else [None] * n)
+        self.tau_used = (torch.zeros(n, dtype=torch.float32, device=dev) if self.op == TP_BATCH_PROX else None)
+        items = (_lib.BatchItem * n)()
+        for i, (sh, a, b, c) in enumerate(zip(shapes, self.As, self.Bs, self.outs)):
+            it = items[i]
+            it.n1, it.n2, it.l, it.n3 = int(sh[0]), int(sh[1]), int(sh[2]), int(sh[3])
+            it.A = a.data_ptr()
+            it.B = b.data_ptr() if b is not None else None
+            it.C = c.data_ptr()
+            it.tau = float(taus[i]) if taus is not None else 0.0
+            it.rank = self.ranks[i].data_ptr() if self.ranks[i] is not None else None
+            it.tau_used = (self.tau_used.data_ptr() + 4 * i) if self.tau_used is not None else None
+        opts = _lib.BatchOpts(int(tile), int(grid_fft), int(grid_gemm), int(grid_jacobi), int(max_sweeps))
+        plan = ctypes.c_void_p()
+        flags = TP_BATCH_TAU_REL if tau_rel else 0
+        _lib.check("tp_batch_create", lib.tp_batch_create(ctypes.byref(plan), self.op, items, n, flags,
+                                                           ctypes.byref(opts)))
+        self._plan = plan
+        self.workspace = _workspace(lib.tp_batch_workspace_size(plan), dev)
+        _lib.check("tp_batch_bind", lib.tp_batch_bind(plan, _ptr(self.workspace), self.workspace.numel(),
+                                                       _stream(dev)))
+
+    def run(self):
+        _lib.check("tp_batch_run", self._lib.tp_batch_run(self._plan, _stream(self.As[0].device)))
+        return self.outs
+
+    def stats(self):
+        st = _lib.BatchStats()
+        _lib.check("tp_batch_stats", self._lib.tp_batch_stats(self._plan, ctypes.byref(st)))
+        return {k: getattr(st, k) for k, _ in _lib.BatchStats._fields_}
+
+    def __del__(self):
+        plan = getattr(self, "_plan", None)
+        if plan is not None and plan.value:
+            self._lib.tp_batch_destroy(plan)
+            self._plan = None
+
+
+def tp_batch_tprod(As, Bs, **kw):
+    """C_i = A_i * B_i for every pair, as one batch."""
+    b = TPBatch("tprod", As, Bs, **kw)
+    return b.run()
+
+
+def tp_batch_prox(As, taus, tau_rel=False, **kw):
+    """prox of tau_i ||.||_* at every A_i, as one batch."""
+    b = TPBatch("prox", As, taus=taus, tau_rel=tau_rel, **kw)
+    return b.run()

@@ -60,6 +60,35 @@ SIGNATURES.update({
     "tp_mlp_adam": (_I, [_VP, _VP, _VP, _VP, _I, _F, _F, _F, _F, _VP]),
 })
 
+
+
+class BatchItem(ctypes.Structure):
+    """tp_batch_item of include/tp.h"""
+    _fields_ = [("n1", _I), ("n2", _I), ("l", _I), ("n3", _I), ("A", _VP), ("B", _VP), ("C", _VP), ("tau", _F),
+                ("rank", _VP), ("tau_used", _VP)]
+
+
+class BatchOpts(ctypes.Structure):
+    """tp_batch_opts of include/tp.h"""
+    _fields_ = [("tile", _I), ("grid_fft", _I), ("grid_gemm", _I), ("grid_jacobi", _I), ("max_sweeps", _I)]
+
+
+class BatchStats(ctypes.Structure):
+    """tp_batch_stats_t of include/tp.h"""
+    _fields_ = [("fft_units", _I), ("gemm_units", _I), ("slice_units", _I), ("tile", _I), ("grid_fft", _I),
+                ("grid_gemm", _I), ("grid_jacobi", _I), ("gemm_flops", ctypes.c_double),
+                ("fft_bytes", ctypes.c_double)]
+
+
+SIGNATURES.update({
+    "tp_batch_create": (_I, [ctypes.POINTER(_VP), _I, ctypes.POINTER(BatchItem), _I, _I, ctypes.POINTER(BatchOpts)]),
+    "tp_batch_workspace_size": (_SZ, [_VP]),
+    "tp_batch_bind": (_I, [_VP, _VP, _SZ, _VP]),
+    "tp_batch_run": (_I, [_VP, _VP]),
+    "tp_batch_stats": (_I, [_VP, ctypes.POINTER(BatchStats)]),
+    "tp_batch_destroy": (_I, [_VP]),
+})
+
 _lib = None
 
 

@@ -110,11 +110,87 @@ def tune_svd(lib, shape, seed=0, widths=(8, 10, 13, 17, 21, 25, 32, 40), tol=1e-
     return best, results
 
 
+def batch_shapes_of(As, Bs=None):
+    """Shapes that key a batch: A's (n1, n2, n3), plus l for a tprod."""
+    if Bs is None:
+        return [tuple(int(v) for v in a.shape) for a in As]
+    return [tuple(int(v) for v in a.shape) + (int(b.shape[1]),) for a, b in zip(As, Bs)]
+
+
+def batch_key(op, shapes):
+    """Exact key of a batch workload: the operation and a digest of its shapes."""
+    import hashlib
+    h = hashlib.sha1(repr([tuple(int(v) for v in s) for s in shapes]).encode()).hexdigest()[:16]
+    return f"batch:{op}:n{len(shapes)}:{h}"
+
+
+def batch_opts(op, shapes):
+    """Cached launch options of a batch workload ({} when untuned)."""
+    e = load_cache().get(batch_key(op, shapes), {})
+    return {k: int(e[k]) for k in ("tile", "grid_fft", "grid_gemm", "grid_jacobi") if k in e}
+
+
+def tune_batch(op, As, Bs=None, taus=None, tau_rel=False, reps=5, tol=1e-5):
+    """Times the batch plan over tile shapes and persistent grid sizes; a
+    candidate must reproduce the default plan's outputs (relative error <= tol
+    per tensor) to be chosen.  Returns (best ms, best options, all results)."""
+    import itertools
+
+    import torch
+
+    import paper_1806_07247_amd as tp
+    ref = [c.clone() for c in tp.TPBatch(op, As, Bs, taus=taus, tau_rel=tau_rel, tuned=False).run()]
+    cands = []
+    for tile, gg, gf in itertools.product((1, 2), (1024, 2048, 4096), (2048, 4096)):
+        c = {"tile": tile, "grid_gemm": gg, "grid_fft": gf}
+        if op == "prox":
+            for gj in (256, 512):
+                cands.append(dict(c, grid_jacobi=gj))
+        else:
+            cands.append(c)
+    results = []
+    for c in cands:
+        b = tp.TPBatch(op, As, Bs, taus=taus, tau_rel=tau_rel, tuned=False, **c)
+        outs = b.run()
+        bad = max(float(torch.linalg.norm(o - r) / max(float(torch.linalg.norm(r)), 1e-30))
+                  for o, r in zip(outs, ref))
+        if not bad <= tol:
+            results.append((float("inf"), c, f"mismatch {bad:.2e}"))
+            continue
+        ms = _time(b.run, reps=reps)
+        results.append((ms, c, ""))
+        print(f"  batch {op} {c}: {ms:.3f} ms", file=sys.stderr, flush=True)
+    best = min(results, key=lambda r: r[0])
+    return best[0], best[1], results
+
+
+def save_batch(op, shapes, opts, ms, path=CACHE):
+    cache = load_cache(path)
+    cache[batch_key(op, shapes)] = dict(opts, ms=round(ms, 4))
+    with open(path, "w") as f:
+        json.dump(cache, f, indent=1, sort_keys=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--out", default=CACHE)
     ap.add_argument("--shapes", default="200x200x50,128x128x16,64x64x64,1024x1024x8")
+    ap.add_argument("--batch", action="store_true", help="tune the 256-tensor batching workload instead")
     args = ap.parse_args()
+    if args.batch:
+        import torch
+
+        from paper_1806_07247_amd import inputs
+        pairs = inputs.batch_tensors(inputs.batch_shapes(seed=0), seed=0)
+        As = [torch.from_numpy(a).cuda() for a, _ in pairs]
+        Bs = [torch.from_numpy(b).cuda() for _, b in pairs]
+        for op in ("tprod", "prox"):
+            Bo = Bs if op == "tprod" else None
+            ms, opts, _ = tune_batch(op, As, Bo, taus=[0.1] * len(As) if op == "prox" else None,
+                                     tau_rel=op == "prox")
+            save_batch(op, batch_shapes_of(As, Bo), opts, ms, args.out)
+            print(f"batch {op}: {opts} {ms:.3f} ms", flush=True)
+        return
     import torch  # noqa: F401
 
     from paper_1806_07247_amd import _lib

@@ -44,6 +44,7 @@ using T128x128 = Tile<128, 128, 2, 2>;
 using T128x64 = Tile<128, 64, 2, 2>;
 using T128x32 = Tile<128, 32, 4, 1>;
 using T256x16 = Tile<256, 16, 4, 1>;
+using T32x32 = Tile<32, 32, 2, 2>;
 
 struct SliceView {
     const float *ar, *ai, *br, *bi;
@@ -182,18 +183,28 @@ struct StoreF32 {
     __device__ __forceinline__ void b(int i, float r, float im) const { br[i] = r; bi[i] = im; }
 };
 
+// FP32 LDS footprint of one workgroup tile: double-buffered re/im panels
+template <class T>
+constexpr int f32_smem_floats()
+{
+    return 2 * 2 * (T::BM + T::BN) * 20;
+}
+
+// One BM x BN output tile of slice s at (m0, n0); smem holds
+// f32_smem_floats<T>() floats.
 template <int OPA, int OPB, class T>
-__global__ __launch_bounds__(256) void k_cgemm_f32(CgemmArgs p)
+__device__ __forceinline__ void cgemm_f32_tile(const CgemmArgs& p, int slice, int m0, int n0, float* smem)
 {
     constexpr int BM = T::BM, BN = T::BN, TM = T::TM, TN = T::TN;
     constexpr int BK = 16, LDK = BK + 4;
-    __shared__ __attribute__((aligned(16))) float sAr[2][BM * LDK];
-    __shared__ __attribute__((aligned(16))) float sAi[2][BM * LDK];
-    __shared__ __attribute__((aligned(16))) float sBr[2][BN * LDK];
-    __shared__ __attribute__((aligned(16))) float sBi[2][BN * LDK];
+    typedef float PanelA[BM * LDK];
+    typedef float PanelB[BN * LDK];
+    PanelA* sAr = reinterpret_cast<PanelA*>(smem);
+    PanelA* sAi = sAr + 2;
+    PanelB* sBr = reinterpret_cast<PanelB*>(smem + 4 * BM * LDK);
+    PanelB* sBi = sBr + 2;
 
-    const SliceView v = slice_view(p, blockIdx.z);
-    const int m0 = blockIdx.y * BM, n0 = blockIdx.x * BN;
+    const SliceView v = slice_view(p, slice);
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int wr = (wave / T::WGN) * T::WM, wc = (wave % T::WGN) * T::WN;
     const int g = lane >> 4, r16 = lane & 15;
@@ -257,6 +268,33 @@ __global__ __launch_bounds__(256) void k_cgemm_f32(CgemmArgs p)
         __syncthreads();
     }
     write_tile<T>(v, p, m0, n0, wr, wc, lane, accr, acci);
+}
+
+template <int OPA, int OPB, class T>
+__global__ __launch_bounds__(256) void k_cgemm_f32(CgemmArgs p)
+{
+    __shared__ __attribute__((aligned(16))) float smem[f32_smem_floats<T>()];
+    cgemm_f32_tile<OPA, OPB, T>(p, blockIdx.z, blockIdx.y * T::BM, blockIdx.x * T::BN, smem);
+}
+
+// Batched products of uneven shapes: a persistent grid walks a list of
+// output tiles, each naming its product (items[unit.item]), slice, tile
+// origin and operand forms.
+template <class T>
+__global__ __launch_bounds__(256) void k_cgemm_batch(const CgemmArgs* __restrict__ items,
+                                                     const GemmUnit* __restrict__ units, int nunits)
+{
+    __shared__ __attribute__((aligned(16))) float smem[f32_smem_floats<T>()];
+    for (int u = blockIdx.x; u < nunits; u += gridDim.x) {
+        const GemmUnit w = units[u];
+        const CgemmArgs p = items[w.item];
+        __syncthreads();
+        switch (w.op) {
+            case GEMM_CN: cgemm_f32_tile<OP_C, OP_N, T>(p, w.slice, w.m0, w.n0, smem); break;
+            case GEMM_NC: cgemm_f32_tile<OP_N, OP_C, T>(p, w.slice, w.m0, w.n0, smem); break;
+            default: cgemm_f32_tile<OP_N, OP_N, T>(p, w.slice, w.m0, w.n0, smem); break;
+        }
+    }
 }
 
 // ------------------------------------------------------------- BF16 (x3) --
@@ -441,6 +479,21 @@ int pick_variant(const CgemmArgs& a)
 }
 
 }  // namespace
+
+int batch_tile(int tile) { return tile == 1 ? 64 : 32; }
+
+hipError_t launch_cgemm_batch(const CgemmArgs* items, const GemmUnit* units, int nunits, int tile, int grid,
+                              double flops, double bytes, hipStream_t s)
+{
+    if (nunits <= 0) return hipSuccess;
+    trace_work(flops, bytes);
+    const int g = grid < nunits ? grid : nunits;
+    if (tile == 1)
+        k_cgemm_batch<T64x64><<<g, 256, 0, s>>>(items, units, nunits);
+    else
+        k_cgemm_batch<T32x32><<<g, 256, 0, s>>>(items, units, nunits);
+    return hipGetLastError();
+}
 
 hipError_t launch_cgemm(const CgemmArgs& a, int opa, int opb, int prec, hipStream_t s)
 {

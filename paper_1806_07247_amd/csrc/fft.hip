@@ -107,164 +107,242 @@ __device__ __forceinline__ void store_tile(float* __restrict__ dst, const float*
     }
 }
 
+// Forward transform of the nt (<= 64) tubes starting at tube `base` of a
+// tensor with `ntubes` tubes; tw holds W_N^j, buf 64 x (N+1) floats.
+template <int N>
+__device__ __forceinline__ void rfft_tile(const float* __restrict__ x, float* __restrict__ re, float* __restrict__ im,
+                                          long long ntubes, long long base, int nt, const float2* tw, float* buf)
+{
+    constexpr int M = N / 2, LD = N + 1;
+    const int tid = threadIdx.x;
+    load_tile(x + base * N, buf, nt, N, LD);
+    __syncthreads();
+    if (tid < nt) {
+        float zr[M], zi[M];
+        const float* xt = buf + tid * LD;
+#pragma unroll
+        for (int t = 0; t < M; ++t) {
+            zr[bitrev<M>(t)] = xt[2 * t];
+            zi[bitrev<M>(t)] = xt[2 * t + 1];
+        }
+        cfft_half<N, false>(zr, zi, tw);
+        const long long q = base + tid;
+        // X_k = E_k + W_N^k O_k with E = (Z_k + conj Z_{M-k})/2, O = -i (Z_k - conj Z_{M-k})/2
+        re[q] = zr[0] + zi[0];
+        im[q] = 0.0f;
+        re[(long long)M * ntubes + q] = zr[0] - zi[0];
+        im[(long long)M * ntubes + q] = 0.0f;
+#pragma unroll
+        for (int k = 1; k < M; ++k) {
+            const float ar = zr[k], ai = zi[k], br = zr[M - k], bi = -zi[M - k];
+            const float er = 0.5f * (ar + br), ei = 0.5f * (ai + bi);
+            const float dr = 0.5f * (ar - br), di = 0.5f * (ai - bi);
+            const float orr = di, oi = -dr;
+            const float2 w = tw[k];
+            re[(long long)k * ntubes + q] = er + (w.x * orr - w.y * oi);
+            im[(long long)k * ntubes + q] = ei + (w.x * oi + w.y * orr);
+        }
+    }
+}
+
 template <int N>
 __global__ __launch_bounds__(kTubes) void k_rfft_pow2(const float* __restrict__ x, float* __restrict__ re,
                                                        float* __restrict__ im, long long ntubes)
 {
-    constexpr int M = N / 2, LD = N + 1;
     __shared__ float2 tw[N];
-    __shared__ float buf[kTubes * LD];
+    __shared__ float buf[kTubes * (N + 1)];
     fill_twiddles(tw, N);
-    const int tid = threadIdx.x;
     for (long long base = (long long)blockIdx.x * kTubes; base < ntubes; base += (long long)gridDim.x * kTubes) {
         const int nt = (int)min<long long>(kTubes, ntubes - base);
         __syncthreads();
-        load_tile(x + base * N, buf, nt, N, LD);
-        __syncthreads();
-        if (tid < nt) {
-            float zr[M], zi[M];
-            const float* xt = buf + tid * LD;
+        rfft_tile<N>(x, re, im, ntubes, base, nt, tw, buf);
+    }
+}
+
+// Inverse transform of the nt tubes starting at `base` (see rfft_tile).
+template <int N>
+__device__ __forceinline__ void irfft_tile(const float* __restrict__ re, const float* __restrict__ im,
+                                           float* __restrict__ x, long long ntubes, long long base, int nt,
+                                           const float2* tw, float* buf)
+{
+    constexpr int M = N / 2, LD = N + 1;
+    const int tid = threadIdx.x;
+    const float scale = 1.0f / (float)N;
+    if (tid < nt) {
+        const long long q = base + tid;
+        float xr[M + 1], xi[M + 1];
 #pragma unroll
-            for (int t = 0; t < M; ++t) {
-                zr[bitrev<M>(t)] = xt[2 * t];
-                zi[bitrev<M>(t)] = xt[2 * t + 1];
-            }
-            cfft_half<N, false>(zr, zi, tw);
-            const long long q = base + tid;
-            // X_k = E_k + W_N^k O_k with E = (Z_k + conj Z_{M-k})/2, O = -i (Z_k - conj Z_{M-k})/2
-            re[q] = zr[0] + zi[0];
-            im[q] = 0.0f;
-            re[(long long)M * ntubes + q] = zr[0] - zi[0];
-            im[(long long)M * ntubes + q] = 0.0f;
+        for (int k = 0; k <= M; ++k) {
+            xr[k] = re[(long long)k * ntubes + q];
+            xi[k] = (k == 0 || k == M) ? 0.0f : im[(long long)k * ntubes + q];
+        }
+        // 2 Z_k = (X_k + conj X_{M-k}) + i W_N^{-k} (X_k - conj X_{M-k})
+        float zr[M], zi[M];
 #pragma unroll
-            for (int k = 1; k < M; ++k) {
-                const float ar = zr[k], ai = zi[k], br = zr[M - k], bi = -zi[M - k];
-                const float er = 0.5f * (ar + br), ei = 0.5f * (ai + bi);
-                const float dr = 0.5f * (ar - br), di = 0.5f * (ai - bi);
-                const float orr = di, oi = -dr;
-                const float2 w = tw[k];
-                re[(long long)k * ntubes + q] = er + (w.x * orr - w.y * oi);
-                im[(long long)k * ntubes + q] = ei + (w.x * oi + w.y * orr);
-            }
+        for (int k = 0; k < M; ++k) {
+            const float ar = xr[k], ai = xi[k], br = xr[M - k], bi = -xi[M - k];
+            const float sr = ar + br, si = ai + bi, dr = ar - br, di = ai - bi;
+            const float2 w = tw[k];  // conj applied below
+            const float tr = w.x * dr + w.y * di;
+            const float ti = w.x * di - w.y * dr;
+            zr[bitrev<M>(k)] = sr - ti;
+            zi[bitrev<M>(k)] = si + tr;
+        }
+        cfft_half<N, true>(zr, zi, tw);
+        float* xt = buf + tid * LD;
+#pragma unroll
+        for (int t = 0; t < M; ++t) {
+            xt[2 * t] = zr[t] * scale;
+            xt[2 * t + 1] = zi[t] * scale;
         }
     }
+    __syncthreads();
+    store_tile(x + base * N, buf, nt, N, LD);
 }
 
 template <int N>
 __global__ __launch_bounds__(kTubes) void k_irfft_pow2(const float* __restrict__ re, const float* __restrict__ im,
                                                         float* __restrict__ x, long long ntubes)
 {
-    constexpr int M = N / 2, LD = N + 1;
     __shared__ float2 tw[N];
-    __shared__ float buf[kTubes * LD];
+    __shared__ float buf[kTubes * (N + 1)];
     fill_twiddles(tw, N);
-    const int tid = threadIdx.x;
-    const float scale = 1.0f / (float)N;
     for (long long base = (long long)blockIdx.x * kTubes; base < ntubes; base += (long long)gridDim.x * kTubes) {
         const int nt = (int)min<long long>(kTubes, ntubes - base);
         __syncthreads();
-        if (tid < nt) {
-            const long long q = base + tid;
-            float xr[M + 1], xi[M + 1];
-#pragma unroll
-            for (int k = 0; k <= M; ++k) {
-                xr[k] = re[(long long)k * ntubes + q];
-                xi[k] = (k == 0 || k == M) ? 0.0f : im[(long long)k * ntubes + q];
-            }
-            // 2 Z_k = (X_k + conj X_{M-k}) + i W_N^{-k} (X_k - conj X_{M-k})
-            float zr[M], zi[M];
-#pragma unroll
-            for (int k = 0; k < M; ++k) {
-                const float ar = xr[k], ai = xi[k], br = xr[M - k], bi = -xi[M - k];
-                const float sr = ar + br, si = ai + bi, dr = ar - br, di = ai - bi;
-                const float2 w = tw[k];  // conj applied below
-                const float tr = w.x * dr + w.y * di;
-                const float ti = w.x * di - w.y * dr;
-                zr[bitrev<M>(k)] = sr - ti;
-                zi[bitrev<M>(k)] = si + tr;
-            }
-            cfft_half<N, true>(zr, zi, tw);
-            float* xt = buf + tid * LD;
-#pragma unroll
-            for (int t = 0; t < M; ++t) {
-                xt[2 * t] = zr[t] * scale;
-                xt[2 * t + 1] = zi[t] * scale;
-            }
-        }
-        __syncthreads();
-        store_tile(x + base * N, buf, nt, N, LD);
+        irfft_tile<N>(re, im, x, ntubes, base, nt, tw, buf);
     }
 }
 
-// direct DFT of any length n: X_k = sum_t x_t W_n^(k t), k < n/2+1
+// direct DFT of any length n: X_k = sum_t x_t W_n^(k t), k < n/2+1, for the
+// nt (<= blockDim.x) tubes starting at `base`; buf holds blockDim.x x (n+1)
+__device__ __forceinline__ void rdft_tile(const float* __restrict__ x, float* __restrict__ re, float* __restrict__ im,
+                                          long long ntubes, long long base, int nt, int n, const float2* tw,
+                                          float* buf)
+{
+    const int ld = n + 1, h = n / 2 + 1, tid = threadIdx.x;
+    load_tile(x + base * n, buf, nt, n, ld);
+    __syncthreads();
+    if (tid < nt) {
+        const long long q = base + tid;
+        const float* xt = buf + tid * ld;
+        for (int k = 0; k < h; ++k) {
+            float sr = 0.0f, si = 0.0f;
+            int e = 0;
+            for (int t = 0; t < n; ++t) {
+                const float v = xt[t];
+                const float2 w = tw[e];
+                sr += v * w.x;
+                si += v * w.y;
+                e += k;
+                if (e >= n) e -= n;
+            }
+            re[(long long)k * ntubes + q] = sr;
+            im[(long long)k * ntubes + q] = (k == 0 || 2 * k == n) ? 0.0f : si;
+        }
+    }
+}
+
+// x_t = (1/n) [X_0 + (-1)^t X_{n/2} + 2 sum_{0<k<n/2} Re(X_k W_n^(-k t))]
+__device__ __forceinline__ void irdft_tile(const float* __restrict__ re, const float* __restrict__ im,
+                                           float* __restrict__ x, long long ntubes, long long base, int nt, int n,
+                                           const float2* tw, float* buf)
+{
+    const int ld = n + 1, kmax = (n - 1) / 2, tid = threadIdx.x;
+    const float scale = 1.0f / (float)n;
+    if (tid < nt) {
+        const long long q = base + tid;
+        float* xt = buf + tid * ld;
+        const float x0 = re[q];
+        const float xn = (n % 2 == 0) ? re[(long long)(n / 2) * ntubes + q] : 0.0f;
+        for (int t = 0; t < n; ++t) xt[t] = x0 + ((t & 1) ? -xn : xn);
+        for (int k = 1; k <= kmax; ++k) {
+            const float a = 2.0f * re[(long long)k * ntubes + q];
+            const float b = 2.0f * im[(long long)k * ntubes + q];
+            int e = 0;
+            for (int t = 0; t < n; ++t) {
+                const float2 w = tw[e];
+                xt[t] += a * w.x + b * w.y;
+                e += k;
+                if (e >= n) e -= n;
+            }
+        }
+        for (int t = 0; t < n; ++t) xt[t] *= scale;
+    }
+    __syncthreads();
+    store_tile(x + base * n, buf, nt, n, ld);
+}
+
 __global__ void k_rdft_any(const float* __restrict__ x, float* __restrict__ re, float* __restrict__ im,
                            long long ntubes, int n)
 {
     extern __shared__ float smem[];
     float2* tw = reinterpret_cast<float2*>(smem);
     float* buf = smem + 2 * n;
-    const int ld = n + 1, h = n / 2 + 1, tpb = blockDim.x, tid = threadIdx.x;
+    const int tpb = blockDim.x;
     fill_twiddles(tw, n);
     for (long long base = (long long)blockIdx.x * tpb; base < ntubes; base += (long long)gridDim.x * tpb) {
         const int nt = (int)min<long long>(tpb, ntubes - base);
         __syncthreads();
-        load_tile(x + base * n, buf, nt, n, ld);
-        __syncthreads();
-        if (tid < nt) {
-            const long long q = base + tid;
-            const float* xt = buf + tid * ld;
-            for (int k = 0; k < h; ++k) {
-                float sr = 0.0f, si = 0.0f;
-                int e = 0;
-                for (int t = 0; t < n; ++t) {
-                    const float v = xt[t];
-                    const float2 w = tw[e];
-                    sr += v * w.x;
-                    si += v * w.y;
-                    e += k;
-                    if (e >= n) e -= n;
-                }
-                re[(long long)k * ntubes + q] = sr;
-                im[(long long)k * ntubes + q] = (k == 0 || 2 * k == n) ? 0.0f : si;
-            }
-        }
+        rdft_tile(x, re, im, ntubes, base, nt, n, tw, buf);
     }
 }
 
-// x_t = (1/n) [X_0 + (-1)^t X_{n/2} + 2 sum_{0<k<n/2} Re(X_k W_n^(-k t))]
 __global__ void k_irdft_any(const float* __restrict__ re, const float* __restrict__ im, float* __restrict__ x,
                             long long ntubes, int n)
 {
     extern __shared__ float smem[];
     float2* tw = reinterpret_cast<float2*>(smem);
     float* buf = smem + 2 * n;
-    const int ld = n + 1, kmax = (n - 1) / 2, tpb = blockDim.x, tid = threadIdx.x;
-    const float scale = 1.0f / (float)n;
+    const int tpb = blockDim.x;
     fill_twiddles(tw, n);
     for (long long base = (long long)blockIdx.x * tpb; base < ntubes; base += (long long)gridDim.x * tpb) {
         const int nt = (int)min<long long>(tpb, ntubes - base);
         __syncthreads();
-        if (tid < nt) {
-            const long long q = base + tid;
-            float* xt = buf + tid * ld;
-            const float x0 = re[q];
-            const float xn = (n % 2 == 0) ? re[(long long)(n / 2) * ntubes + q] : 0.0f;
-            for (int t = 0; t < n; ++t) xt[t] = x0 + ((t & 1) ? -xn : xn);
-            for (int k = 1; k <= kmax; ++k) {
-                const float a = 2.0f * re[(long long)k * ntubes + q];
-                const float b = 2.0f * im[(long long)k * ntubes + q];
-                int e = 0;
-                for (int t = 0; t < n; ++t) {
-                    const float2 w = tw[e];
-                    xt[t] += a * w.x + b * w.y;
-                    e += k;
-                    if (e >= n) e -= n;
-                }
-            }
-            for (int t = 0; t < n; ++t) xt[t] *= scale;
-        }
+        irdft_tile(re, im, x, ntubes, base, nt, n, tw, buf);
+    }
+}
+
+// Batched transforms: one persistent grid walks a list of units (64 tubes
+// of one tensor each; tensors of any n3 <= kBatchMaxN3).  The twiddle table
+// is refilled when a workgroup moves to a unit of another length.
+template <int MAXN>
+__global__ __launch_bounds__(kTubes) void k_fft_batch(const FftUnit* __restrict__ units, int nunits, int inverse)
+{
+    __shared__ float2 tw[MAXN];
+    __shared__ float buf[kTubes * (MAXN + 1)];
+    int cur = 0;
+    for (int u = blockIdx.x; u < nunits; u += gridDim.x) {
+        const FftUnit w = units[u];
         __syncthreads();
-        store_tile(x + base * n, buf, nt, n, ld);
+        if (w.n3 != cur) {
+            fill_twiddles(tw, w.n3);
+            cur = w.n3;
+            __syncthreads();
+        }
+        if (!inverse) {
+            switch (w.n3) {
+#define TP_RB(N) \
+    case N: rfft_tile<N>(w.src, w.re, w.im, w.ntubes, w.base, w.nt, tw, buf); break;
+                TP_RB(4) TP_RB(8) TP_RB(16) TP_RB(32) TP_RB(64)
+                case 128:
+                    if constexpr (MAXN >= 128) rfft_tile<128>(w.src, w.re, w.im, w.ntubes, w.base, w.nt, tw, buf);
+                    break;
+#undef TP_RB
+                default: rdft_tile(w.src, w.re, w.im, w.ntubes, w.base, w.nt, w.n3, tw, buf); break;
+            }
+        } else {
+            switch (w.n3) {
+#define TP_IB(N) \
+    case N: irfft_tile<N>(w.re, w.im, w.dst, w.ntubes, w.base, w.nt, tw, buf); break;
+                TP_IB(4) TP_IB(8) TP_IB(16) TP_IB(32) TP_IB(64)
+                case 128:
+                    if constexpr (MAXN >= 128) irfft_tile<128>(w.re, w.im, w.dst, w.ntubes, w.base, w.nt, tw, buf);
+                    break;
+#undef TP_IB
+                default: irdft_tile(w.re, w.im, w.dst, w.ntubes, w.base, w.nt, w.n3, tw, buf); break;
+            }
+        }
     }
 }
 
@@ -331,5 +409,17 @@ hipError_t launch_irfft(const float* re, const float* im, float* x, long long nt
 }
 
 size_t max_fft_length() { return 1024; }
+
+hipError_t launch_fft_batch(const FftUnit* units, int nunits, int inverse, int max_n3, int grid, hipStream_t s)
+{
+    if (nunits <= 0) return hipSuccess;
+    if (max_n3 > kBatchMaxN3) return hipErrorInvalidValue;
+    const int g = grid < nunits ? grid : nunits;
+    if (max_n3 <= 64)
+        k_fft_batch<64><<<g, kTubes, 0, s>>>(units, nunits, inverse);
+    else
+        k_fft_batch<128><<<g, kTubes, 0, s>>>(units, nunits, inverse);
+    return hipGetLastError();
+}
 
 }  // namespace tp

@@ -203,16 +203,13 @@ __device__ __forceinline__ void store_q(const JacobiArgs& a, int s, const float2
 }
 
 // ---- whole slice in one workgroup (LDS when it fits, else workspace) ----
-template <int G, int RPL, bool LDS, bool WITHV>
-__global__ __launch_bounds__(256) void k_jacobi(JacobiArgs a, float2* __restrict__ gwork)
+// Slice s of a, held in `work` (R x P, then P x P rotations with WITHV);
+// `rotated` is a workgroup-shared flag.
+template <int G, int RPL, bool WITHV>
+__device__ __forceinline__ void jacobi_whole(const JacobiArgs& a, int s, float2* work, int& rotated)
 {
-    extern __shared__ float2 lwork[];
-    __shared__ int rotated;
-    const int s = blockIdx.x;
     const int R = a.transpose ? a.n : a.m;
     const int P = a.transpose ? a.m : a.n;
-    const long long per = (long long)R * P + (WITHV ? (long long)P * P : 0);
-    float2* work = LDS ? lwork : gwork + (long long)s * per;
     float2* vw = work + (long long)R * P;
     const int tid = threadIdx.x;
     load_work(a, s, work, R, P, tid, blockDim.x);
@@ -244,6 +241,44 @@ __global__ __launch_bounds__(256) void k_jacobi(JacobiArgs a, float2* __restrict
     store_result<G>(a, s, work, R, P, 0, 1);
     if (WITHV) store_q(a, s, vw, P, 0, 1);
     if (a.info && tid == 0) a.info[s] = converged ? (sweep > 0 ? sweep : 1) : -sweep;
+}
+
+// largest workgroup of the whole-slice kernel: 1024 threads, 512 when each
+// lane holds 32 rows per column (register budget)
+constexpr int whole_max_threads(int rpl) { return rpl >= 32 ? 512 : 1024; }
+
+template <int G, int RPL, bool LDS, bool WITHV>
+__global__ __launch_bounds__(whole_max_threads(RPL)) void k_jacobi(JacobiArgs a, float2* __restrict__ gwork)
+{
+    extern __shared__ float2 lwork[];
+    __shared__ int rotated;
+    const int s = blockIdx.x;
+    const int R = a.transpose ? a.n : a.m;
+    const int P = a.transpose ? a.m : a.n;
+    const long long per = (long long)R * P + (WITHV ? (long long)P * P : 0);
+    float2* work = LDS ? lwork : gwork + (long long)s * per;
+    jacobi_whole<G, RPL, WITHV>(a, s, work, rotated);
+}
+
+// Batched slices of uneven shapes (R <= 128, LDS-resident): a persistent
+// grid walks (item, slice) units; each item has its own JacobiArgs.
+__global__ __launch_bounds__(1024) void k_jacobi_batch(const JacobiArgs* __restrict__ items,
+                                                      const SliceUnit* __restrict__ units, int nunits)
+{
+    extern __shared__ float2 lwork[];
+    __shared__ int rotated;
+    for (int u = blockIdx.x; u < nunits; u += gridDim.x) {
+        const SliceUnit w = units[u];
+        const JacobiArgs a = items[w.item];
+        const int R = a.transpose ? a.n : a.m;
+        __syncthreads();
+        if (R <= 32)
+            jacobi_whole<16, 2, false>(a, w.slice, lwork, rotated);
+        else if (R <= 64)
+            jacobi_whole<16, 4, false>(a, w.slice, lwork, rotated);
+        else
+            jacobi_whole<16, 8, false>(a, w.slice, lwork, rotated);
+    }
 }
 
 // ---- block Jacobi: several workgroups per slice, one launch per block step ----
@@ -387,17 +422,25 @@ size_t whole_bytes(int R, int P, bool withv)
     return ((size_t)R * P + (withv ? (size_t)P * P : 0)) * sizeof(float2);
 }
 
+// one group of G lanes per column pair of a step (at most `cap` threads)
+int whole_threads(int G, int P, int cap = 1024)
+{
+    const int t = G * ((P + 1) / 2);
+    return t >= cap ? cap : (t <= 64 ? 64 : ((t + 63) / 64) * 64);
+}
+
 template <int G, int RPL, bool WITHV>
 hipError_t launch_whole(const JacobiArgs& a, void* scratch, int R, int P, hipStream_t st)
 {
     const size_t lds = whole_bytes(R, P, WITHV);
+    const int threads = whole_threads(G, P, whole_max_threads(RPL));
     if (lds <= kMaxLds) {
         auto kern = k_jacobi<G, RPL, true, WITHV>;
         hipError_t e = allow_lds(kern, lds);
         if (e != hipSuccess) return e;
-        kern<<<a.nslices, 256, lds, st>>>(a, nullptr);
+        kern<<<a.nslices, threads, lds, st>>>(a, nullptr);
     } else {
-        k_jacobi<G, RPL, false, WITHV><<<a.nslices, 256, 0, st>>>(a, static_cast<float2*>(scratch));
+        k_jacobi<G, RPL, false, WITHV><<<a.nslices, threads, 0, st>>>(a, static_cast<float2*>(scratch));
     }
     return hipGetLastError();
 }
@@ -505,6 +548,20 @@ size_t jacobi_scratch_bytes(int m, int n, int nslices, bool withv)
     return b <= kMaxLds ? 0 : b * nslices;
 }
 
+size_t jacobi_batch_lds(int max_r, int max_p) { return (size_t)max_r * max_p * sizeof(float2); }
+
+hipError_t launch_jacobi_batch(const JacobiArgs* items, const SliceUnit* units, int nunits, int max_r, int max_p,
+                               int grid, hipStream_t st)
+{
+    if (nunits <= 0) return hipSuccess;
+    if (max_r > 128) return hipErrorInvalidValue;
+    const size_t lds = jacobi_batch_lds(max_r, max_p);
+    hipError_t e = allow_lds(k_jacobi_batch, lds);
+    if (e != hipSuccess) return e;
+    k_jacobi_batch<<<grid < nunits ? grid : nunits, whole_threads(16, max_p), lds, st>>>(items, units, nunits);
+    return hipGetLastError();
+}
+
 hipError_t launch_jacobi(const JacobiArgs& a, void* scratch, size_t scratch_bytes, hipStream_t st)
 {
     if (a.nslices <= 0) return hipSuccess;
@@ -551,6 +608,51 @@ __global__ __launch_bounds__(256) void k_shrink(float* __restrict__ wr, float* _
     }
 }
 
+// Batched shrinkage: unit (item, slice) scales the slice's rotated columns
+// by sqrt(d_j)/sigma_j with the item's tau; with tau_rel the item's tau is
+// tau_rel * max over its slices of sigma_1 (= tau_rel * tsn), computed here
+// from the singular values of all its slices.
+__global__ __launch_bounds__(256) void k_shrink_batch(const ShrinkItem* __restrict__ items,
+                                                      const SliceUnit* __restrict__ units, int nunits)
+{
+    __shared__ double red[256];
+    for (int u = blockIdx.x; u < nunits; u += gridDim.x) {
+        const SliceUnit w = units[u];
+        const ShrinkItem it = items[w.item];
+        double tau = it.tau;
+        if (it.rel) {
+            double mx = 0.0;
+            for (int e = threadIdx.x; e < it.h * it.P; e += blockDim.x) mx = fmax(mx, it.sigma[e]);
+            __syncthreads();
+            red[threadIdx.x] = mx;
+            __syncthreads();
+            for (int st = blockDim.x / 2; st > 0; st >>= 1) {
+                if (threadIdx.x < st) red[threadIdx.x] = fmax(red[threadIdx.x], red[threadIdx.x + st]);
+                __syncthreads();
+            }
+            tau = it.tau * red[0];
+        }
+        const double* sg = it.sigma + (long long)w.slice * it.P;
+        const long long per = (long long)it.R * it.P;
+        float* wr = it.wr + w.slice * per;
+        float* wi = it.wi + w.slice * per;
+        for (long long e = threadIdx.x; e < per; e += blockDim.x) {
+            const double sv = sg[e % it.P];
+            const float f = sv > tau ? (float)(sqrt(1.0 - tau / sv) / sv) : 0.0f;
+            wr[e] *= f;
+            wi[e] *= f;
+        }
+        if (threadIdx.x == 0) {
+            if (it.keep) {
+                int k = 0;
+                for (int j = 0; j < it.P; ++j) k += sg[j] > tau ? 1 : 0;
+                it.keep[w.slice] = k;
+            }
+            if (it.tau_out && w.slice == 0) *it.tau_out = (float)tau;
+        }
+    }
+}
+
 // tnn = (1/n3) sum_k w_k sum_j sigma_kj, w_k = 1 for real slices, 2 otherwise
 // (Definition 2.9 with eq (14), using the conjugate symmetry of eq (8)).
 __global__ __launch_bounds__(256) void k_tnn_reduce(const double* __restrict__ sigma, int nslices, int P, int n3,
@@ -586,6 +688,14 @@ hipError_t launch_shrink(float* wr, float* wi, const double* sigma, int* keep, i
     k_shrink<<<(int)blocks, 256, 0, st>>>(wr, wi, sigma, keep, R, P, total, tau);
     return hipGetLastError();
 }
+
+hipError_t launch_shrink_batch(const ShrinkItem* items, const SliceUnit* units, int nunits, int grid, hipStream_t st)
+{
+    if (nunits <= 0) return hipSuccess;
+    k_shrink_batch<<<grid < nunits ? grid : nunits, 256, 0, st>>>(items, units, nunits);
+    return hipGetLastError();
+}
+
 
 hipError_t launch_tnn_reduce(const double* sigma, int nslices, int P, int n3, double* out, hipStream_t st)
 {

@@ -47,6 +47,22 @@ struct Planes {
 // Forward real DFT of every tube of the tube-major tensor x (ntubes x n3) into
 // the first floor(n3/2)+1 slices of planar (re, im), slice-major: element k of
 // tube q lands at re[k*ntubes + q].
+// Batched transforms: 64 tubes of one tensor per unit (kBatchMaxN3 >= n3).
+// Forward: src (tube-major) -> re/im (slice-major planes of that tensor);
+// inverse: re/im -> dst.
+constexpr int kBatchMaxN3 = 128;
+struct FftUnit {
+    const float* src;
+    float* re;
+    float* im;
+    float* dst;
+    long long ntubes;  // tubes of the tensor (n1 * n2)
+    long long base;    // first tube of the unit
+    int n3;
+    int nt;            // tubes in the unit (<= 64)
+};
+// max_n3: the largest n3 among the units (sizes the LDS tile)
+hipError_t launch_fft_batch(const FftUnit* units, int nunits, int inverse, int max_n3, int grid, hipStream_t s);
 hipError_t launch_rfft(const float* x, float* re, float* im, long long ntubes, int n3, hipStream_t s);
 // Inverse of the above: x = (1/n3) sum over the full conjugate-symmetric
 // spectrum; the imaginary parts of slice 0 (and n3/2 for even n3) are ignored.
@@ -72,6 +88,18 @@ struct CgemmArgs {
     const int* kdyn;     // optional per-slice inner dimension (<= k), device
 };
 
+// Batched slice products of uneven shapes (FP32): one unit per output tile.
+enum { GEMM_NN = 0, GEMM_CN = 1, GEMM_NC = 2 };
+struct GemmUnit {
+    int item;   // index into the CgemmArgs table
+    int slice;
+    int m0, n0; // tile origin
+    int op;     // GEMM_NN, GEMM_CN (op(A) = A^*), GEMM_NC (op(B) = B^*)
+};
+// tile: 0 = 32 x 32, 1 = 64 x 64 outputs per workgroup; batch_tile gives the edge
+int batch_tile(int tile);
+hipError_t launch_cgemm_batch(const CgemmArgs* items, const GemmUnit* units, int nunits, int tile, int grid,
+                              double flops, double bytes, hipStream_t s);
 hipError_t launch_cgemm(const CgemmArgs& a, int opa, int opb, int prec, hipStream_t s);
 
 // -------------------------------------------------------------- Jacobi ----
@@ -91,6 +119,26 @@ struct JacobiArgs {
     float2* qout;     // optional: accumulated rotations V, column-major P x P per slice
     int whole;        // 1: one workgroup per slice whenever the slice fits in LDS
 };
+// Batched per-slice SVDs (whole slice in LDS, R = max(m, n) <= 128) and
+// shrinkage over (item, slice) units.
+struct SliceUnit {
+    int item;
+    int slice;
+};
+struct ShrinkItem {
+    const double* sigma;  // h x P
+    float* wr;            // h x R x P rotated columns (planar)
+    float* wi;
+    int R, P, h;
+    int rel;              // 1: tau = tau_rel * max sigma of the item
+    double tau;           // absolute tau, or tau_rel
+    int* keep;            // optional: #{sigma_j > tau} per slice
+    float* tau_out;       // optional: the tau used
+};
+size_t jacobi_batch_lds(int max_r, int max_p);
+hipError_t launch_jacobi_batch(const JacobiArgs* items, const SliceUnit* units, int nunits, int max_r, int max_p,
+                               int grid, hipStream_t st);
+hipError_t launch_shrink_batch(const ShrinkItem* items, const SliceUnit* units, int nunits, int grid, hipStream_t st);
 hipError_t launch_jacobi(const JacobiArgs& a, void* scratch, size_t scratch_bytes, hipStream_t s);
 size_t jacobi_scratch_bytes(int m, int n, int nslices, bool withv);
 // Jacobi convergence threshold for an R-row work matrix of FP32 data

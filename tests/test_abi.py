@@ -67,3 +67,45 @@ def test_workspace_query(lib):
     need = sum(((2 * h * e * 4 + 255) // 256) * 256 for e in (4 * 3, 3 * 2, 4 * 2))
     assert lib.tp_tprod_workspace_size(4, 3, 2, 5, 0) >= need
     assert lib.tp_tprod_workspace_size(0, 3, 2, 5, 0) == 0
+
+
+def test_batch_plan_validation(lib):
+    """tp_batch_create validates items on the host; a valid plan is sized
+    without touching the (fake) device pointers."""
+    from paper_1806_07247_amd import _lib
+    items = (_lib.BatchItem * 2)()
+    for it, (n1, n2, l, n3) in zip(items, [(5, 7, 3, 4), (20, 9, 11, 6)]):
+        it.n1, it.n2, it.l, it.n3 = n1, n2, l, n3
+        it.A, it.B, it.C = 0x1000, 0x2000, 0x3000
+        it.tau = 0.5
+    plan = ctypes.c_void_p()
+    assert lib.tp_batch_create(ctypes.byref(plan), 0, items, 2, 0, None) == 0
+    ws = lib.tp_batch_workspace_size(plan)
+    assert ws > 0
+    st = _lib.BatchStats()
+    assert lib.tp_batch_stats(plan, ctypes.byref(st)) == 0
+    # units: 64 tubes per transform unit (A, B forward; C inverse), one tile per slice product
+    fft = sum(-(-n1 * n2 // 64) + -(-n2 * l // 64) + -(-n1 * l // 64)
+              for n1, n2, l, n3 in [(5, 7, 3, 4), (20, 9, 11, 6)])
+    assert st.fft_units == fft
+    assert st.gemm_units == 3 + 4  # one 32x32 tile per slice, h = 3 and 4
+    assert lib.tp_batch_bind(plan, ctypes.c_void_p(0x4000), ws - 1, None) == -3
+    assert lib.tp_batch_run(plan, None) == -1  # not bound
+    assert lib.tp_batch_destroy(plan) == 0
+    # errors: op, count, flags, shapes, prox limits, tau
+    assert lib.tp_batch_create(ctypes.byref(plan), 2, items, 2, 0, None) == -1
+    assert lib.tp_batch_create(ctypes.byref(plan), 0, items, 0, 0, None) == -1
+    assert lib.tp_batch_create(ctypes.byref(plan), 0, items, 2, 1, None) == -1  # relative tau is prox only
+    items[1].n3 = 129
+    assert lib.tp_batch_create(ctypes.byref(plan), 0, items, 2, 0, None) == -2
+    items[1].n3 = 6
+    items[1].n1 = 129
+    assert lib.tp_batch_create(ctypes.byref(plan), 1, items, 2, 0, None) == -2
+    items[1].n1 = 20
+    items[0].tau = -1.0
+    assert lib.tp_batch_create(ctypes.byref(plan), 1, items, 2, 0, None) == -1
+    items[0].tau = 0.5
+    items[0].B = None
+    assert lib.tp_batch_create(ctypes.byref(plan), 0, items, 2, 0, None) == -1
+    assert lib.tp_batch_create(ctypes.byref(plan), 1, items, 2, 1, None) == 0  # prox needs no B
+    assert lib.tp_batch_destroy(plan) == 0
