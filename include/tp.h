@@ -292,7 +292,9 @@ int tp_batch_destroy(tp_batch* plan);
  *                                 multi-workgroup when fewer than this many
  *                                 slices are processed (default 128)
  *   TP_PARAM_JACOBI_SWEEPS        sweep cap (default 30)
- *   TP_PARAM_GEMM_VARIANT         slice GEMM tile variant (0 = default)
+ *   TP_PARAM_GEMM_VARIANT         slice GEMM tile variant: 0 = by shape, 1 = 64x64,
+ *                                 2 = 128x128, 3 = 128x64, 4 = 128x32, 5 = 256x16,
+ *                                 6 = 64x48 (output rows x columns per workgroup)
  */
 enum {
     TP_PARAM_JACOBI_BLOCK = 0,

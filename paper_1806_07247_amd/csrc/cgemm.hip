@@ -45,6 +45,7 @@ using T128x64 = Tile<128, 64, 2, 2>;
 using T128x32 = Tile<128, 32, 4, 1>;
 using T256x16 = Tile<256, 16, 4, 1>;
 using T32x32 = Tile<32, 32, 2, 2>;
+using T64x48 = Tile<64, 48, 4, 1>;
 
 struct SliceView {
     const float *ar, *ai, *br, *bi;
@@ -183,6 +184,22 @@ struct StoreF32 {
     __device__ __forceinline__ void b(int i, float r, float im) const { br[i] = r; bi[i] = im; }
 };
 
+// Tile of workgroup blockIdx, XCD-aware: the hardware deals consecutive
+// workgroup ids round-robin to the 8 XCDs, each with its own L2; renumbering
+// gives every XCD one contiguous run of tiles (same slice, neighbouring
+// row/column blocks), so the panels those tiles share stay in one L2.
+__device__ __forceinline__ void xcd_tile(int& x, int& y, int& z)
+{
+    const int nx = gridDim.x, ny = gridDim.y, nz = gridDim.z;
+    const int total = nx * ny * nz;
+    const int i = blockIdx.x + nx * (blockIdx.y + ny * blockIdx.z);
+    int t = i;
+    if (total >= 64 && total % 8 == 0) t = (i % 8) * (total / 8) + i / 8;
+    x = t % nx;
+    y = (t / nx) % ny;
+    z = t / (nx * ny);
+}
+
 // FP32 LDS footprint of one workgroup tile: double-buffered re/im panels
 template <class T>
 constexpr int f32_smem_floats()
@@ -274,7 +291,9 @@ template <int OPA, int OPB, class T>
 __global__ __launch_bounds__(256) void k_cgemm_f32(CgemmArgs p)
 {
     __shared__ __attribute__((aligned(16))) float smem[f32_smem_floats<T>()];
-    cgemm_f32_tile<OPA, OPB, T>(p, blockIdx.z, blockIdx.y * T::BM, blockIdx.x * T::BN, smem);
+    int x, y, z;
+    xcd_tile(x, y, z);
+    cgemm_f32_tile<OPA, OPB, T>(p, z, y * T::BM, x * T::BN, smem);
 }
 
 // Batched products of uneven shapes: a persistent grid walks a list of
@@ -351,8 +370,10 @@ __global__ __launch_bounds__(256) void k_cgemm_bf16(CgemmArgs p)
     __shared__ __attribute__((aligned(16))) unsigned short sA[2][NP][2][BM * LDK];  // [buf][hi/lo][re/im]
     __shared__ __attribute__((aligned(16))) unsigned short sB[2][NP][2][BN * LDK];
 
-    const SliceView v = slice_view(p, blockIdx.z);
-    const int m0 = blockIdx.y * BM, n0 = blockIdx.x * BN;
+    int bx, by, bz;
+    xcd_tile(bx, by, bz);
+    const SliceView v = slice_view(p, bz);
+    const int m0 = by * BM, n0 = bx * BN;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int wr = (wave / T::WGN) * T::WM, wc = (wave % T::WGN) * T::WN;
     const int g = lane >> 4, r16 = lane & 15;
@@ -459,6 +480,7 @@ hipError_t launch_ops(const CgemmArgs& a, int variant, hipStream_t s)
         case 3: return launch_f32<OPA, OPB, T128x64>(a, s);
         case 4: return launch_f32<OPA, OPB, T128x32>(a, s);
         case 5: return launch_f32<OPA, OPB, T256x16>(a, s);
+        case 6: return launch_f32<OPA, OPB, T64x48>(a, s);
         default: return launch_f32<OPA, OPB, T64x64>(a, s);
     }
 }
@@ -470,9 +492,10 @@ long long tiles(long long m, long long n, int bm, int bn, int ns) { return ((m +
 int pick_variant(const CgemmArgs& a)
 {
     const int tuned = param(TP_PARAM_GEMM_VARIANT);
-    if (tuned >= 1 && tuned <= 5) return tuned;
+    if (tuned >= 1 && tuned <= 6) return tuned;
     if (a.n <= 16) return 5;
     if (a.n <= 32) return 4;
+    if (a.n <= 48) return 6;
     if (a.m >= 256 && a.n >= 256 && tiles(a.m, a.n, 128, 128, a.nslices) >= 2048) return 2;
     if (a.m >= 128 && tiles(a.m, a.n, 128, 64, a.nslices) >= 2048) return 3;
     return 1;
@@ -511,6 +534,7 @@ hipError_t launch_cgemm(const CgemmArgs& a, int opa, int opb, int prec, hipStrea
             case 3: return launch_bf16<T128x64>(a, prec, s);
             case 4:
             case 5: return launch_bf16<T128x32>(a, prec, s);  // the 256-row split tile exceeds LDS
+            case 6: return launch_bf16<T64x48>(a, prec, s);
             default: return launch_bf16<T64x64>(a, prec, s);
         }
     }

@@ -100,3 +100,22 @@ def test_tprod_precision_config_sampled(tp, orc):
         err = rel_fro(C[idx], ref)
         say(f"  sampled rel.err {err:.3e}")
         assert err <= TOL[prec]
+
+
+@pytest.mark.parametrize("variant", [1, 2, 3, 4, 5, 6])
+@pytest.mark.parametrize("prec", ["fp32", "bf16x3"])
+def test_tprod_every_tile_variant(tp, orc, variant, prec):
+    """Each slice-product tile shape (forced through TP_PARAM_GEMM_VARIANT) on
+    a shape with ragged edges in every dimension."""
+    from paper_1806_07247_amd import _lib, inputs
+    lib = _lib.load()
+    A, B = inputs.tprod_pair(131, 67, 75, 6, seed=variant)
+    ref = orc.tprod(A, B)
+    try:
+        assert lib.tp_set_param(4, variant) == 0
+        C = tp.tp_tprod(gpu(A), gpu(B), prec=prec).cpu().numpy()
+    finally:
+        lib.tp_set_param(4, 0)
+    err = rel_fro(C, ref)
+    say(f"  variant {variant} {prec}: rel.err {err:.2e}")
+    assert err <= TOL[prec]
