@@ -9,8 +9,9 @@ Headline: learned-rank prox_tnn against full-SVD prox_tnn on the prox calls
 of a TRPCA-ADMM run on a held-out problem of the learned-rank workload
 (X = P*Q + S, 1024 x 1024 x 64, tubal rank r ~ U{5..40}, 5% +-1 outliers,
 seed 10000).  The ADMM run is made first (with the learned prox) and every
-call's input Y_t, tau_t = 1/mu_t and the previous call's per-slice counts and
-leading singular values are kept in HBM.  A step is one learned prox call
+call's input Y_t, tau_t = 1/mu_t and the previous call's outputs it takes
+(per-slice counts, leading singular values, range basis for the warm start)
+are kept in HBM.  A step is one learned prox call
 (FFT, slice features, rank MLP, randomized SVD with the count check and the
 a posteriori check, full-SVD fallback, reconstruction, inverse FFT) on one
 captured call; K steps walk through the captured calls (evenly spaced when
@@ -139,9 +140,11 @@ def learned_block(args, tp, dev):
     calls = []
 
     def cap(k, Y, tau):
+        wb, wc = prox.warm_inputs()
         calls.append(dict(Y=Y.clone(), tau=tau, seed=prox.calls,
                           prev=prox.prev.clone() if prox.have_prev else None,
-                          psig=prox.prev_sigma.clone() if prox.have_prev else None))
+                          psig=prox.prev_sigma.clone() if prox.have_prev else None,
+                          wb=wb.clone() if wb is not None else None, wc=wc.clone() if wc is not None else None))
 
     log(f"learned-rank workload {n}x{n}x{n3} seed {args.learned_seed} r {r}: ADMM capture")
     t0 = time.perf_counter()
@@ -163,9 +166,13 @@ def learned_block(args, tp, dev):
     info = torch.zeros(h, dtype=torch.int32, device=dev)
     sweeps = torch.zeros(h, dtype=torch.int64, device=dev)
 
+    bout = torch.empty(tp.basis_shape(n, n3), dtype=torch.float32, device=dev)
+    bcols = torch.zeros(h, dtype=torch.int32, device=dev)
+
     def learned(i, dst):
         c = calls[i]
         tp.tp_prox_tnn_learned(c["Y"], c["tau"], mlp=mlp, prev_rank=c["prev"], prev_sigma=c["psig"], seed=c["seed"],
+                               warm_basis=c["wb"], warm_cols=c["wc"], basis_out=bout, basis_cols_out=bcols,
                                out=dst, rank=rk, fallback=fb, info=info, sigma_out=so, workspace=ws)
 
     for j in range(args.warmup):

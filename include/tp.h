@@ -153,6 +153,15 @@ int tp_prox_tnn(const float* Y, float* X, int n1, int n2, int n3, float tau, int
  *   11 one when c > 0 and s_c > tau (the previous sketch saw no value below tau)
  * the logarithms clamped to [-30, 30].  The MLP maps them to y and
  * kpred = round(expm1(y * log1p(p))) clipped to [0, p].
+ * Warm start (optional): basis_out receives this call's right range basis
+ * Q2 of every slice, planar complex float[2][floor(n3/2)+1][n2][max_rank]
+ * (re plane, then im plane; columns beyond basis_cols_out[k] zero;
+ * basis_cols_out[k] = 0 for a fallback slice).  Passed back as warm_basis /
+ * warm_cols of the next call (same n1, n2, n3, max_rank), its first
+ * warm_cols[k] columns replace the Gaussian columns of slice k's sketch, so a
+ * sequence of calls on slowly changing inputs (the prox calls of an ADMM
+ * run) continues one subspace iteration instead of restarting it.  The
+ * result is checked as without warm start.
  * sigma_out (optional, device float[(floor(n3/2)+1) * TP_SIGMA_KEEP]) receives
  * this call's leading singular values per slice in that layout (from the
  * randomized SVD, or from the full SVD for fallback slices), to be passed as
@@ -174,6 +183,10 @@ typedef struct tp_learned_opts {
     int max_power_iters;       /* cap on power iterations with the check */
     int retry_wide;            /* 1: retry count-check failures once at the widest sketch */
     int accuracy_ref;          /* 0: check relative to max(result, input), 1: to the result */
+    const float* warm_basis;   /* device, optional: a previous call's basis_out */
+    const int* warm_cols;      /* device int[floor(n3/2)+1]: its basis_cols_out */
+    float* basis_out;          /* device, optional: this call's range basis Q2 */
+    int* basis_cols_out;       /* device int[floor(n3/2)+1]: valid columns per slice */
 } tp_learned_opts;
 size_t tp_prox_tnn_learned_workspace_size(int n1, int n2, int n3, int max_rank);
 int tp_prox_tnn_learned(const float* Y, float* X, int n1, int n2, int n3, float tau,

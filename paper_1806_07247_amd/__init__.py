@@ -155,19 +155,29 @@ def tp_prox_tnn_learned_workspace_size(n1, n2, n3, max_rank=64):
 
 def tp_prox_tnn_learned(Y, tau, mlp=None, fixed_rank=0, prev_rank=None, prev_sigma=None, oversample=10,
                         power_iters=2, max_rank=64, seed=0, accuracy=2e-5, max_power_iters=8, retry_wide=True,
-                        accuracy_ref=0,
+                        accuracy_ref=0, warm_basis=None, warm_cols=None, basis_out=None, basis_cols_out=None,
                         out=None, rank=None, fallback=None, info=None, sigma_out=None, workspace=None):
     """Learned-rank prox (see include/tp.h); mlp is a float32 device tensor of
     tp_mlp_param_count() parameters or None (then every slice uses fixed_rank).
-    rank / fallback / info: optional int32 device tensors of half_slices(n3)."""
+    rank / fallback / info: optional int32 device tensors of half_slices(n3).
+    basis_out (float32, basis_shape(n2, n3, max_rank)) and basis_cols_out
+    (int32, half_slices(n3)) receive the range basis that warm_basis /
+    warm_cols of the next call take."""
     lib = _lib.load()
     Y = _dev_tensor(Y, "Y")
     n1, n2, n3 = Y.shape
     X = out if out is not None else torch.empty_like(Y)
+    for t, shape in ((warm_basis, basis_shape(n2, n3, max_rank)), (basis_out, basis_shape(n2, n3, max_rank))):
+        if t is not None and (tuple(t.shape) != shape or t.dtype != torch.float32 or not t.is_contiguous()):
+            raise ValueError(f"basis tensors must be contiguous float32 of shape {shape}")
+    for t in (warm_cols, basis_cols_out):
+        if t is not None and (t.numel() != half_slices(n3) or t.dtype != torch.int32):
+            raise ValueError("basis column counts must be int32 of half_slices(n3)")
     opts = _lib.LearnedOpts(_ptr(mlp), int(fixed_rank), _ptr(prev_rank), _ptr(prev_sigma), int(oversample),
                             int(power_iters),
                             int(max_rank), int(seed) & 0xFFFFFFFFFFFFFFFF, float(accuracy), int(max_power_iters),
-                            int(bool(retry_wide)), int(accuracy_ref))
+                            int(bool(retry_wide)), int(accuracy_ref), _ptr(warm_basis), _ptr(warm_cols),
+                            _ptr(basis_out), _ptr(basis_cols_out))
     ws_bytes = lib.tp_prox_tnn_learned_workspace_size(n1, n2, n3, int(max_rank))
     ws = workspace if workspace is not None else _workspace(ws_bytes, Y.device)
     st = lib.tp_prox_tnn_learned(Y.data_ptr(), X.data_ptr(), n1, n2, n3, float(tau), ctypes.byref(opts),
@@ -175,6 +185,11 @@ def tp_prox_tnn_learned(Y, tau, mlp=None, fixed_rank=0, prev_rank=None, prev_sig
                                  ws.numel(), _stream(Y.device))
     _lib.check("tp_prox_tnn_learned", st)
     return X
+
+
+def basis_shape(n2, n3, max_rank=64):
+    """Shape of a warm-start basis buffer: (2, half_slices(n3), n2, max_rank)."""
+    return (2, half_slices(n3), int(n2), int(max_rank))
 
 
 def tp_slice_features(Y, tau, prev_rank=None, prev_sigma=None, workspace=None):

@@ -44,7 +44,8 @@ class LearnedOpts(ctypes.Structure):
     """tp_learned_opts of include/tp.h"""
     _fields_ = [("mlp", _VP), ("fixed_rank", _I), ("prev_rank", _VP), ("prev_sigma", _VP), ("oversample", _I),
                 ("power_iters", _I), ("max_rank", _I), ("seed", _U64), ("accuracy", _F), ("max_power_iters", _I),
-                ("retry_wide", _I), ("accuracy_ref", _I)]
+                ("retry_wide", _I), ("accuracy_ref", _I), ("warm_basis", _VP), ("warm_cols", _VP),
+                ("basis_out", _VP), ("basis_cols_out", _VP)]
 
 
 SIGNATURES.update({

@@ -529,10 +529,23 @@ int tp_prox_tnn_learned(const float* Y, float* X, int n1, int n2, int n3, float 
 
     if (L == 0) {  // every slice goes to the full SVD
         TP_TRY(hipMemcpyAsync(fb, W.prefb, h * sizeof(int), hipMemcpyDeviceToDevice, s));
+        if (opts->basis_out && opts->basis_cols_out)  // no basis to pass on
+            TP_LAUNCH(tp::K_SKETCH, s,
+                      tp::launch_store_basis(W.za.re, W.za.im, n2, 1, W.lact, fb, h, opts->basis_out,
+                                             opts->basis_out + (long long)h * n2 * opts->max_rank, opts->max_rank,
+                                             opts->basis_cols_out, s));
     } else {
         const long long sy = (long long)n1 * L, sz = (long long)n2 * L, sl = (long long)L * L;
         // range finder: Y = Ybar Om, re-orthonormalised; power iterations
-        TP_LAUNCH(tp::K_SKETCH, s, tp::launch_sketch(W.om.re, W.om.im, n2, L, W.lact, h, n3, opts->seed, s));
+        tp::WarmBasis warm{};
+        if (opts->warm_basis && opts->warm_cols) {
+            warm.re = opts->warm_basis;
+            warm.im = opts->warm_basis + (long long)h * n2 * opts->max_rank;
+            warm.ld = opts->max_rank;
+            warm.cols = opts->warm_cols;
+        }
+        TP_LAUNCH(tp::K_SKETCH, s,
+                  tp::launch_sketch(W.om.re, W.om.im, n2, L, W.lact, h, n3, opts->seed, warm, s));
         st = gemm(ybar, n2, mn, tp::OP_N, W.om, L, sz, tp::OP_N, W.ya, L, sy, n1, L, n2, h, rl, s);
         if (st == TP_OK) st = cholqr2(W, W.ya, W.yb, n1, L, h, rl, false, s);
         auto power_iteration = [&]() {
@@ -595,6 +608,11 @@ int tp_prox_tnn_learned(const float* Y, float* X, int n1, int n2, int n3, float 
             if (st != TP_OK) return st;
             ++q;
         }
+        if (opts->basis_out && opts->basis_cols_out)  // Q2 for the next call's warm start
+            TP_LAUNCH(tp::K_SKETCH, s,
+                      tp::launch_store_basis(W.za.re, W.za.im, n2, L, W.lact, fb, h, opts->basis_out,
+                                             opts->basis_out + (long long)h * n2 * opts->max_rank, opts->max_rank,
+                                             opts->basis_cols_out, s));
         if (sigma_out)  // singular values of the slices kept on the randomized path
             TP_LAUNCH(tp::K_RSVD_CHECK, s, tp::launch_sigma_top(W.jsig, L, W.lact, nullptr, fb, h, sigma_out, s));
         // W = Q (T Q2^*)

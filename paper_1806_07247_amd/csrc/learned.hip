@@ -42,7 +42,7 @@ __device__ __forceinline__ bool is_real_slice(int s, int n3) { return s == 0 || 
 // zero for j >= lact[slice].
 __global__ __launch_bounds__(256) void k_sketch(float* __restrict__ omr, float* __restrict__ omi, int n, int L,
                                                 const int* __restrict__ lact, int nslices, int n3,
-                                                unsigned long long seed)
+                                                unsigned long long seed, WarmBasis warm)
 {
     const long long total = (long long)nslices * n * L;
     for (long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x; e < total;
@@ -51,7 +51,11 @@ __global__ __launch_bounds__(256) void k_sketch(float* __restrict__ omr, float* 
         const int rem = (int)(e % ((long long)n * L));
         const int i = rem / L, j = rem % L;
         float vr = 0.0f, vi = 0.0f;
-        if (j < lact[s]) {
+        if (j < lact[s] && warm.re && j < min(warm.cols[s], warm.ld)) {  // column j of the previous basis
+            const long long o = ((long long)s * n + i) * warm.ld + j;
+            vr = warm.re[o];
+            vi = warm.im[o];
+        } else if (j < lact[s]) {
             unsigned int c[4] = {(unsigned int)i, (unsigned int)j, (unsigned int)s, 0u};
             philox4x32_10(c, (unsigned int)seed, (unsigned int)(seed >> 32));
             const double u0 = ((double)c[0] + 0.5) * 0x1p-32, u1 = ((double)c[1] + 0.5) * 0x1p-32;
@@ -705,9 +709,45 @@ inline int blocks_for(long long n, int tpb, int cap = 8192)
 int mlp_param_count() { return MlpOffsets::COUNT; }
 
 hipError_t launch_sketch(float* omr, float* omi, int n, int L, const int* lact, int nslices, int n3,
-                         unsigned long long seed, hipStream_t st)
+                         unsigned long long seed, WarmBasis warm, hipStream_t st)
 {
-    k_sketch<<<blocks_for((long long)nslices * n * L, 256), 256, 0, st>>>(omr, omi, n, L, lact, nslices, n3, seed);
+    k_sketch<<<blocks_for((long long)nslices * n * L, 256), 256, 0, st>>>(omr, omi, n, L, lact, nslices, n3, seed,
+                                                                          warm);
+    return hipGetLastError();
+}
+
+// The range basis Q2 (n x L per slice, planar) into the caller's basis
+// buffer (n x ld per slice), zero beyond the slice's valid columns, and the
+// valid count per slice (0 for fallback slices, whose basis failed).
+__global__ __launch_bounds__(256) void k_store_basis(const float* __restrict__ zr, const float* __restrict__ zi, int n,
+                                                     int L, const int* __restrict__ lact, const int* __restrict__ fb,
+                                                     int nslices, float* __restrict__ outr, float* __restrict__ outi,
+                                                     int ld, int* __restrict__ cols)
+{
+    const long long total = (long long)nslices * n * ld;
+    for (long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x; e < total;
+         e += (long long)gridDim.x * blockDim.x) {
+        const int s = (int)(e / ((long long)n * ld));
+        const int rem = (int)(e % ((long long)n * ld));
+        const int i = rem / ld, j = rem % ld;
+        const int valid = fb[s] ? 0 : min(lact[s], L);
+        float vr = 0.0f, vi = 0.0f;
+        if (j < valid) {
+            const long long o = ((long long)s * n + i) * L + j;
+            vr = zr[o];
+            vi = zi[o];
+        }
+        outr[e] = vr;
+        outi[e] = vi;
+        if (rem == 0) cols[s] = valid;
+    }
+}
+
+hipError_t launch_store_basis(const float* zr, const float* zi, int n, int L, const int* lact, const int* fb,
+                              int nslices, float* outr, float* outi, int ld, int* cols, hipStream_t st)
+{
+    k_store_basis<<<blocks_for((long long)nslices * n * ld, 256), 256, 0, st>>>(zr, zi, n, L, lact, fb, nslices,
+                                                                                outr, outi, ld, cols);
     return hipGetLastError();
 }
 

@@ -157,8 +157,18 @@ hipError_t launch_tnn_reduce(const double* sigma, int nslices, int P, int n3, do
 // ------------------------------------------------------------- learned ----
 constexpr int kMaxL = 64;  // widest randomized sketch (l_max)
 int mlp_param_count();
+// A previous call's range basis (planar n x ld per slice, cols[s] valid columns)
+struct WarmBasis {
+    const float* re;  // null: no warm start
+    const float* im;
+    int ld;
+    const int* cols;
+};
+// Sketch Om (n x L per slice): the warm columns where given, else Gaussian
 hipError_t launch_sketch(float* omr, float* omi, int n, int L, const int* lact, int nslices, int n3,
-                         unsigned long long seed, hipStream_t s);
+                         unsigned long long seed, WarmBasis warm, hipStream_t s);
+hipError_t launch_store_basis(const float* zr, const float* zi, int n, int L, const int* lact, const int* fb,
+                              int nslices, float* outr, float* outi, int ld, int* cols, hipStream_t st);
 size_t cholqr_part_bytes(int m, int L, int nslices);
 // one CholeskyQR pass on Y (m x L per slice): Gram in FP64, Cholesky, Rinv (FP32 planar);
 // rtot/rhr/rhi optional (accumulated R and, after pass 1, R^* restricted to the active block)

@@ -45,7 +45,7 @@ class ProxLearned:
     name = "learned"
 
     def __init__(self, shape, device, mlp=None, fixed_rank=0, oversample=10, power_iters=2, max_rank=64, seed=0,
-                 use_prev=True, accuracy=2e-5, max_power_iters=8, retry_wide=True, accuracy_ref=0):
+                 use_prev=True, accuracy=2e-5, max_power_iters=8, retry_wide=True, accuracy_ref=0, warm=True):
         n1, n2, n3 = shape
         self.h = tp.half_slices(n3)
         self.mlp, self.fixed_rank = mlp, fixed_rank
@@ -61,12 +61,28 @@ class ProxLearned:
         self.prev_sigma = torch.zeros_like(self.sigma)
         self.have_prev = False
         self.use_prev = use_prev
+        # warm start: the previous call's range basis (two buffers, swapped per call)
+        self.warm = warm
+        if warm:
+            bs = tp.basis_shape(n2, n3, max_rank)
+            self.basis = [torch.zeros(bs, dtype=torch.float32, device=device) for _ in range(2)]
+            self.bcols = [torch.zeros(self.h, dtype=torch.int32, device=device) for _ in range(2)]
         self.calls = 0
         self.fallbacks = 0
 
+    def warm_inputs(self):
+        """(warm_basis, warm_cols) the next call takes (None without a previous call)."""
+        if not (self.warm and self.have_prev):
+            return None, None
+        return self.basis[self.calls % 2 ^ 1], self.bcols[self.calls % 2 ^ 1]
+
     def __call__(self, Y, tau, out):
         use = self.use_prev and self.have_prev
+        wb, wc = self.warm_inputs()
         tp.tp_prox_tnn_learned(Y, tau, mlp=self.mlp, fixed_rank=self.fixed_rank,
+                               warm_basis=wb, warm_cols=wc,
+                               basis_out=self.basis[self.calls % 2] if self.warm else None,
+                               basis_cols_out=self.bcols[self.calls % 2] if self.warm else None,
                                prev_rank=self.prev if use else None, prev_sigma=self.prev_sigma if use else None,
                                oversample=self.oversample, power_iters=self.power_iters, max_rank=self.max_rank,
                                seed=self.seed + self.calls, accuracy=self.accuracy,

@@ -51,8 +51,10 @@ def test_trained_network_gain(tp, n, n3, seed):
     calls = []
 
     def cap(k, Y, tau):
+        wb, wc = prox.warm_inputs()
         calls.append((Y.clone(), tau, prox.calls, prox.prev.clone() if prox.have_prev else None,
-                      prox.prev_sigma.clone() if prox.have_prev else None))
+                      prox.prev_sigma.clone() if prox.have_prev else None,
+                      wb.clone() if wb is not None else None, wc.clone() if wc is not None else None))
 
     res = trpca.trpca(X, prox, capture=cap)
     assert res["converged"]
@@ -71,10 +73,14 @@ def test_trained_network_gain(tp, n, n3, seed):
     tp.tp_prox_tnn_learned(calls[-1][0], calls[-1][1], mlp=mlp, out=out_l, workspace=ws)
     torch.cuda.synchronize()
     t_l, t_f, errs, errs_in, fbs = 0.0, 0.0, [], [], 0
-    for Y, tau, sd, pr, ps in calls:
+    bout = torch.empty(tp.basis_shape(n, n3), dtype=torch.float32, device=dev)
+    bcols = torch.zeros(h, dtype=torch.int32, device=dev)
+    for Y, tau, sd, pr, ps, wb, wc in calls:
         _, ms_f = _timed(lambda: full(Y, tau, out_f))
         _, ms_l = _timed(lambda: tp.tp_prox_tnn_learned(Y, tau, mlp=mlp, prev_rank=pr, prev_sigma=ps, seed=sd,
-                                                         out=out_l, rank=rk, fallback=fb, workspace=ws))
+                                                         warm_basis=wb, warm_cols=wc, basis_out=bout,
+                                                         basis_cols_out=bcols, out=out_l, rank=rk, fallback=fb,
+                                                         workspace=ws))
         t_f += ms_f
         t_l += ms_l
         fbs += int(fb.sum())

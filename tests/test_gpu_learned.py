@@ -250,3 +250,44 @@ def test_learned_prox_accuracy_check(tp, orc):
     e2 = float(np.linalg.norm(dflt - exact) / max(np.linalg.norm(exact), np.linalg.norm(Y)))
     say(f"  default check: {e2:.2e} relative to max(|X*|, |Y|)")
     assert e2 <= 1e-4
+
+
+def test_learned_prox_warm_start(tp, orc):
+    """A sequence of prox calls on slowly changing inputs: with the previous
+    call's range basis as the sketch, every result stays within 1e-4 of the
+    exact prox and the a posteriori check needs fewer power iterations in
+    total (fewer accuracy-check launches)."""
+    rng = np.random.default_rng(41)
+    n1, n2, n3, r = 120, 110, 6, 5
+    # kept values close above a noise bulk (slow subspace convergence from a
+    # random start, as in test_learned_prox_accuracy_check)
+    P = rng.standard_normal((n1, r, n3)) / np.sqrt(n1)
+    Q = rng.standard_normal((r, n2, n3)) / np.sqrt(n2)
+    base = orc.tprod(P, Q) * 0.7 + 0.35 * rng.standard_normal((n1, n2, n3)) / np.sqrt(n1)
+    h = n3 // 2 + 1
+    seq = [(base + 1e-3 * t * rng.standard_normal(base.shape) / np.sqrt(n1)).astype(np.float32) for t in range(5)]
+    tau = float(np.sort(orc.slice_sigma(seq[0])[:h, r - 1])[0]) * 0.8
+    launches = {}
+    for warm in (False, True):
+        bs = [torch.zeros(tp.basis_shape(n2, n3, 16), dtype=torch.float32, device="cuda:0") for _ in range(2)]
+        bc = [torch.zeros(h, dtype=torch.int32, device="cuda:0") for _ in range(2)]
+        tp.tp_trace_collect_work()
+        tp.tp_trace_enable(True)
+        errs = []
+        for t, Y in enumerate(seq):
+            kw = dict(fixed_rank=5, oversample=3, power_iters=1, max_rank=16, seed=t, accuracy=2e-5,
+                      max_power_iters=40, accuracy_ref=1)
+            if warm:
+                kw.update(basis_out=bs[t % 2], basis_cols_out=bc[t % 2])
+                if t > 0:
+                    kw.update(warm_basis=bs[(t - 1) % 2], warm_cols=bc[(t - 1) % 2])
+            X = tp.tp_prox_tnn_learned(gpu(Y), tau, **kw).cpu().numpy()
+            errs.append(rel_fro(X, orc.prox_tnn(Y, np.float32(tau))))
+        tp.tp_trace_enable(False)
+        launches[warm] = sum(1 for rec in tp.tp_trace_collect_work() if rec[0] == "accuracy")
+        say(f"  warm={warm}: max rel.err {max(errs):.2e}, accuracy launches {launches[warm]}")
+        assert max(errs) <= 1e-4
+        if warm:
+            cols = bc[(len(seq) - 1) % 2].cpu().numpy()
+            assert np.all(cols == 8)  # l = kpred + oversample, rounded to the call width 8
+    assert launches[True] < launches[False]
