@@ -137,6 +137,10 @@ int run_svt(const SvtLayout& L, tp::Planes yb, int n1, int n2, int nslices, int 
 }
 
 
+// split-K partial buffer of the learned path: up to kMaxSplit parts of an
+// (max(n1, n2) x l_max) product per slice
+constexpr int kMaxSplit = 4;
+
 // Workspace of the learned-rank prox.
 struct LearnedLayout {
     SvtLayout full;                 // full path, sized for any batch of up to h slices
@@ -150,6 +154,8 @@ struct LearnedLayout {
     float2* jv;
     double* jsig;
     double* fpart;                  // per-band column norms of the features
+    float* kpart;                   // split-K partial products
+    size_t kpart_bytes;
     double* fro2;                   // ||Ybar^(k)||_F^2 per slice
     float* feats;
     tp::Planes vp, cp, t1, t2;      // V_r, U_r S (planar L x L), residual products (m x L)
@@ -195,6 +201,8 @@ tp::Arena learned_arena(void* ws, size_t bytes, int n1, int n2, int n3, int Lw, 
     t.jv = ar.take<float2>(h * L * L);
     t.jsig = ar.take<double>(h * L);
     t.fpart = reinterpret_cast<double*>(ar.take<char>(tp::features_part_bytes(n1, n2, (int)h)));
+    t.kpart_bytes = tp::splitk_bytes(kMaxSplit, (int)h, mx, Lw);
+    t.kpart = reinterpret_cast<float*>(ar.take<char>(t.kpart_bytes));
     t.fro2 = ar.take<double>(h);
     t.feats = ar.take<float>(h * TP_MLP_INPUTS);
     t.kpred = ar.take<int>(h);
@@ -211,11 +219,27 @@ tp::Arena learned_arena(void* ws, size_t bytes, int n1, int n2, int n3, int Lw, 
     return ar;
 }
 
+// parts of the inner dimension for a product with few output tiles (so that
+// enough workgroups run), each part at least 128 long
+int pick_ksplit(int m, int n, int k, int nslices, size_t part_bytes)
+{
+    if (!part_bytes || k < 256) return 1;
+    const long long tiles = (long long)((m + 63) / 64) * ((n + 63) / 64) * nslices;
+    int ks = 1;
+    while (ks < kMaxSplit && tiles * ks * 2 <= 2048 && k / (ks * 2) >= 128) ks *= 2;
+    while (ks > 1 && tp::splitk_bytes(ks, nslices, m, n) > part_bytes) ks /= 2;
+    return ks;
+}
+
 // slice GEMM of planar stacks: C = op(A) op(B) with op(A) m x k, op(B) k x n
+// (part: optional split-K scratch of part_bytes)
 int gemm(tp::Planes a, long long lda, long long sa, int opa, tp::Planes b, long long ldb, long long sb, int opb,
-         tp::Planes c, long long ldc, long long sc, int m, int n, int k, int nslices, int real_last, hipStream_t s)
+         tp::Planes c, long long ldc, long long sc, int m, int n, int k, int nslices, int real_last, hipStream_t s,
+         float* part = nullptr, size_t part_bytes = 0)
 {
     tp::CgemmArgs g{};
+    g.ksplit = pick_ksplit(m, n, k, nslices, part ? part_bytes : 0);
+    g.part = part;
     g.ar = a.re; g.ai = a.im; g.lda = lda; g.sa = sa;
     g.br = b.re; g.bi = b.im; g.ldb = ldb; g.sb = sb;
     g.cr = c.re; g.ci = c.im; g.ldc = ldc; g.sc = sc;
@@ -546,12 +570,15 @@ int tp_prox_tnn_learned(const float* Y, float* X, int n1, int n2, int n3, float 
         }
         TP_LAUNCH(tp::K_SKETCH, s,
                   tp::launch_sketch(W.om.re, W.om.im, n2, L, W.lact, h, n3, opts->seed, warm, s));
-        st = gemm(ybar, n2, mn, tp::OP_N, W.om, L, sz, tp::OP_N, W.ya, L, sy, n1, L, n2, h, rl, s);
+        st = gemm(ybar, n2, mn, tp::OP_N, W.om, L, sz, tp::OP_N, W.ya, L, sy, n1, L, n2, h, rl, s,
+                W.kpart, W.kpart_bytes);
         if (st == TP_OK) st = cholqr2(W, W.ya, W.yb, n1, L, h, rl, false, s);
         auto power_iteration = [&]() {
-            int r = gemm(ybar, n2, mn, tp::OP_C, W.ya, L, sy, tp::OP_N, W.za, L, sz, n2, L, n1, h, rl, s);
+            int r = gemm(ybar, n2, mn, tp::OP_C, W.ya, L, sy, tp::OP_N, W.za, L, sz, n2, L, n1, h, rl, s,
+                    W.kpart, W.kpart_bytes);
             if (r == TP_OK) r = cholqr2(W, W.za, W.zb, n2, L, h, rl, false, s);
-            if (r == TP_OK) r = gemm(ybar, n2, mn, tp::OP_N, W.za, L, sz, tp::OP_N, W.ya, L, sy, n1, L, n2, h, rl, s);
+            if (r == TP_OK) r = gemm(ybar, n2, mn, tp::OP_N, W.za, L, sz, tp::OP_N, W.ya, L, sy, n1, L, n2, h, rl, s,
+                    W.kpart, W.kpart_bytes);
             if (r == TP_OK) r = cholqr2(W, W.ya, W.yb, n1, L, h, rl, false, s);
             return r;
         };
@@ -561,7 +588,8 @@ int tp_prox_tnn_learned(const float* Y, float* X, int n1, int n2, int n3, float 
         int q = opts->power_iters;
         while (true) {
             // Bh = Ybar^* Q = Q2 R2
-            st = gemm(ybar, n2, mn, tp::OP_C, W.ya, L, sy, tp::OP_N, W.za, L, sz, n2, L, n1, h, rl, s);
+            st = gemm(ybar, n2, mn, tp::OP_C, W.ya, L, sy, tp::OP_N, W.za, L, sz, n2, L, n1, h, rl, s,
+                    W.kpart, W.kpart_bytes);
             if (st == TP_OK) st = cholqr2(W, W.za, W.zb, n2, L, h, rl, true, s);
             if (st != TP_OK) return st;
             // SVD of R2^* (one workgroup per slice, LDS), count check, core T
@@ -585,7 +613,8 @@ int tp_prox_tnn_learned(const float* Y, float* X, int n1, int n2, int n3, float 
             // a posteriori check: residuals Ybar v_j - sigma_j u_j of the kept Ritz triplets
             TP_LAUNCH(tp::K_ACCURACY, s, tp::launch_cm_to_planar(W.jv, W.vp, L, h, s));
             TP_LAUNCH(tp::K_ACCURACY, s, tp::launch_cm_to_planar(W.jcols, W.cp, L, h, s));
-            st = gemm(ybar, n2, mn, tp::OP_N, W.za, L, sz, tp::OP_N, W.yb, L, sy, n1, L, n2, h, rl, s);  // Ybar Q2
+            st = gemm(ybar, n2, mn, tp::OP_N, W.za, L, sz, tp::OP_N, W.yb, L, sy, n1, L, n2, h, rl, s,
+                    W.kpart, W.kpart_bytes);  // Ybar Q2
             if (st == TP_OK) st = gemm(W.yb, L, sy, tp::OP_N, W.vp, L, sl, tp::OP_N, W.t1, L, sy, n1, L, L, h, rl, s);
             if (st == TP_OK) st = gemm(W.ya, L, sy, tp::OP_N, W.cp, L, sl, tp::OP_N, W.t2, L, sy, n1, L, L, h, rl, s);
             if (st != TP_OK) return st;

@@ -50,21 +50,37 @@ using T64x48 = Tile<64, 48, 4, 1>;
 struct SliceView {
     const float *ar, *ai, *br, *bi;
     float *cr, *ci;
-    int K;
+    long long ldc;
+    int K0, K;  // inner-dimension range [K0, K) of this workgroup
     bool real;
 };
 
-__device__ __forceinline__ SliceView slice_view(const CgemmArgs& p, int s)
+// Slice s, inner-dimension part kp of p.ksplit (output to the partial buffer
+// when the product is split).
+__device__ __forceinline__ SliceView slice_view(const CgemmArgs& p, int s, int kp = 0)
 {
     SliceView v;
     v.ar = p.ar + s * p.sa;
     v.ai = p.ai + s * p.sa;
     v.br = p.br + s * p.sb;
     v.bi = p.bi + s * p.sb;
-    v.cr = p.cr + s * p.sc;
-    v.ci = p.ci + s * p.sc;
-    v.K = p.kdyn ? min(p.kdyn[s], p.k) : p.k;
+    const int K = p.kdyn ? min(p.kdyn[s], p.k) : p.k;
     v.real = (p.real_first && s == 0) || (p.real_last && s == p.nslices - 1);
+    if (p.ksplit > 1) {
+        const long long mn = (long long)p.m * p.n;
+        const int chunk = ((p.k + p.ksplit - 1) / p.ksplit + 15) / 16 * 16;
+        v.K0 = min(K, kp * chunk);
+        v.K = min(K, v.K0 + chunk);
+        v.cr = p.part + ((long long)kp * p.nslices + s) * mn;
+        v.ci = v.cr + (long long)p.ksplit * p.nslices * mn;
+        v.ldc = p.n;
+    } else {
+        v.K0 = 0;
+        v.K = K;
+        v.cr = p.cr + s * p.sc;
+        v.ci = p.ci + s * p.sc;
+        v.ldc = p.ldc;
+    }
     return v;
 }
 
@@ -170,7 +186,7 @@ __device__ __forceinline__ void write_tile(const SliceView& v, const CgemmArgs& 
                 const int row = m0 + wr + 16 * ti + 4 * g + j;
                 const int col = n0 + wc + 16 * tj + c16;
                 if (row < p.m && col < p.n) {
-                    const long long off = (long long)row * p.ldc + col;
+                    const long long off = (long long)row * v.ldc + col;
                     v.cr[off] = accr[ti][tj][j];
                     v.ci[off] = v.real ? 0.0f : acci[ti][tj][j];
                 }
@@ -210,7 +226,7 @@ constexpr int f32_smem_floats()
 // One BM x BN output tile of slice s at (m0, n0); smem holds
 // f32_smem_floats<T>() floats.
 template <int OPA, int OPB, class T>
-__device__ __forceinline__ void cgemm_f32_tile(const CgemmArgs& p, int slice, int m0, int n0, float* smem)
+__device__ __forceinline__ void cgemm_f32_tile(const CgemmArgs& p, int slice, int m0, int n0, float* smem, int kp = 0)
 {
     constexpr int BM = T::BM, BN = T::BN, TM = T::TM, TN = T::TN;
     constexpr int BK = 16, LDK = BK + 4;
@@ -221,7 +237,7 @@ __device__ __forceinline__ void cgemm_f32_tile(const CgemmArgs& p, int slice, in
     PanelB* sBr = reinterpret_cast<PanelB*>(smem + 4 * BM * LDK);
     PanelB* sBi = sBr + 2;
 
-    const SliceView v = slice_view(p, slice);
+    const SliceView v = slice_view(p, slice, kp);
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int wr = (wave / T::WGN) * T::WM, wc = (wave % T::WGN) * T::WN;
     const int g = lane >> 4, r16 = lane & 15;
@@ -236,15 +252,15 @@ __device__ __forceinline__ void cgemm_f32_tile(const CgemmArgs& p, int slice, in
         }
 
     PanelLoader<OPA, OPB, BM, BN, BK> ld;
-    const int nk = (v.K + BK - 1) / BK;
+    const int nk = (v.K - v.K0 + BK - 1) / BK;
     if (nk > 0) {
-        ld.load(v, p, m0, n0, 0, tid);
+        ld.load(v, p, m0, n0, v.K0, tid);
         ld.template store<LDK>(tid, StoreF32{sAr[0], sAi[0], sBr[0], sBi[0]});
     }
     __syncthreads();
     for (int c = 0; c < nk; ++c) {
         const int cur = c & 1;
-        if (c + 1 < nk) ld.load(v, p, m0, n0, (c + 1) * BK, tid);
+        if (c + 1 < nk) ld.load(v, p, m0, n0, v.K0 + (c + 1) * BK, tid);
         // lane (g, r16) of MFMA step s uses k = 4g + s: one 16-byte LDS read per operand
         float4 fa_r[TM], fa_i[TM], fb_r[TN], fb_i[TN];
 #pragma unroll
@@ -292,8 +308,30 @@ __global__ __launch_bounds__(256) void k_cgemm_f32(CgemmArgs p)
 {
     __shared__ __attribute__((aligned(16))) float smem[f32_smem_floats<T>()];
     int x, y, z;
-    xcd_tile(x, y, z);
-    cgemm_f32_tile<OPA, OPB, T>(p, z, y * T::BM, x * T::BN, smem);
+    xcd_tile(x, y, z);  // z = kp * nslices + slice
+    cgemm_f32_tile<OPA, OPB, T>(p, z % p.nslices, y * T::BM, x * T::BN, smem, z / p.nslices);
+}
+
+// C = sum over the ksplit partial products, in a fixed order
+__global__ __launch_bounds__(256) void k_splitk_reduce(CgemmArgs p)
+{
+    const long long mn = (long long)p.m * p.n, total = (long long)p.nslices * mn;
+    const long long plane = (long long)p.ksplit * total;
+    for (long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x; e < total;
+         e += (long long)gridDim.x * blockDim.x) {
+        const int s = (int)(e / mn);
+        const long long r = e % mn;
+        const int i = (int)(r / p.n), j = (int)(r % p.n);
+        float vr = 0.0f, vi = 0.0f;
+        for (int kp = 0; kp < p.ksplit; ++kp) {
+            vr += p.part[kp * total + e];
+            vi += p.part[plane + kp * total + e];
+        }
+        const bool real = (p.real_first && s == 0) || (p.real_last && s == p.nslices - 1);
+        const long long off = s * p.sc + (long long)i * p.ldc + j;
+        p.cr[off] = vr;
+        p.ci[off] = real ? 0.0f : vi;
+    }
 }
 
 // Batched products of uneven shapes: a persistent grid walks a list of
@@ -458,6 +496,19 @@ dim3 grid_of(const CgemmArgs& a)
 template <int OPA, int OPB, class T>
 hipError_t launch_f32(const CgemmArgs& a, hipStream_t s)
 {
+    if (a.ksplit > 1) {
+        if (!a.part) return hipErrorInvalidValue;
+        dim3 g = grid_of<T>(a);
+        g.z *= a.ksplit;
+        k_cgemm_f32<OPA, OPB, T><<<g, 256, 0, s>>>(a);
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+        const long long total = (long long)a.nslices * a.m * a.n;
+        long long blocks = (total + 255) / 256;
+        if (blocks > 4096) blocks = 4096;
+        k_splitk_reduce<<<(int)blocks, 256, 0, s>>>(a);
+        return hipGetLastError();
+    }
     k_cgemm_f32<OPA, OPB, T><<<grid_of<T>(a), 256, 0, s>>>(a);
     return hipGetLastError();
 }
@@ -505,6 +556,11 @@ int pick_variant(const CgemmArgs& a)
 
 int batch_tile(int tile) { return tile == 1 ? 64 : 32; }
 
+size_t splitk_bytes(int ksplit, int nslices, int m, int n)
+{
+    return ksplit > 1 ? align_up((size_t)2 * ksplit * nslices * m * n * sizeof(float)) : 0;
+}
+
 hipError_t launch_cgemm_batch(const CgemmArgs* items, const GemmUnit* units, int nunits, int tile, int grid,
                               double flops, double bytes, hipStream_t s)
 {
@@ -528,7 +584,7 @@ hipError_t launch_cgemm(const CgemmArgs& a, int opa, int opb, int prec, hipStrea
     }
     const int variant = pick_variant(a);
     if (prec != TP_PREC_FP32) {
-        if (opa != OP_N || opb != OP_N) return hipErrorInvalidValue;
+        if (opa != OP_N || opb != OP_N || a.ksplit > 1) return hipErrorInvalidValue;
         switch (variant) {
             case 2: return launch_bf16<T128x128>(a, prec, s);
             case 3: return launch_bf16<T128x64>(a, prec, s);

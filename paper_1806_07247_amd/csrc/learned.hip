@@ -76,24 +76,32 @@ __global__ __launch_bounds__(256) void k_sketch(float* __restrict__ omr, float* 
 
 // ------------------------------------------------------------ CholeskyQR --
 // Partial Gram G_w = Y_w^* Y_w (FP64) of the rows handled by workgroup w of
-// nsplit, for the lact leading columns; Y is m x L planar row-major.  The 256
-// threads form a 16 x 16 grid of B x B blocks of G (B = 1, 2, 4 for L <= 16,
-// 32, 64); blocks below the diagonal are written as zeros (only the upper
-// triangle is used).  Rows are staged in LDS in chunks; every product of two
-// FP32 values is exact in FP64 and the sums are FP64.
+// nsplit, for the lact leading columns; Y is m x L planar row-major.  Only the
+// upper triangle is formed (the Cholesky reads nothing else): thread t owns
+// the B x B block (ta, tb), ta <= tb, the t-th block of the upper triangle
+// of the nb x nb block grid (nb = ceil(L / B), nb (nb + 1) / 2 <= 256).
+// Rows are staged in LDS in chunks; every product of two FP32 values is exact
+// in FP64 and the sums are FP64.
 template <int B>
 __global__ __launch_bounds__(256) void k_gram(const float* __restrict__ yr, const float* __restrict__ yi, int m,
                                               int L, const int* __restrict__ lact, double2* __restrict__ part,
                                               int nsplit)
 {
     constexpr int CH = 32;  // rows per LDS chunk
-    constexpr int W = 16 * B;
+    constexpr int W = kMaxL + B;
     __shared__ float2 tile[CH * W];
     const int s = blockIdx.y, w = blockIdx.x, tid = threadIdx.x;
     const int la = lact[s];
-    const int ta = tid / 16, tb = tid % 16;
+    const int nb = (L + B - 1) / B;
+    // block pair of this thread: row ta holds nb - ta blocks (tb = ta .. nb-1)
+    int ta = 0, t = tid;
+    while (ta < nb && t >= nb - ta) {
+        t -= nb - ta;
+        ++ta;
+    }
+    const int tb = ta + t;
     const int a0 = ta * B, b0 = tb * B;
-    const bool work = ta <= tb && a0 < la && b0 < la;
+    const bool work = ta < nb && a0 < la && b0 < la;
     const int r0 = (int)((long long)m * w / nsplit), r1 = (int)((long long)m * (w + 1) / nsplit);
     const float* Yr = yr + (long long)s * m * L;
     const float* Yi = yi + (long long)s * m * L;
@@ -102,7 +110,7 @@ __global__ __launch_bounds__(256) void k_gram(const float* __restrict__ yr, cons
     for (int u = 0; u < B; ++u)
 #pragma unroll
         for (int v = 0; v < B; ++v) gr[u][v] = gi[u][v] = 0.0;
-    const int lc = min(la, W);
+    const int lc = min(la, L);
     for (int c0 = r0; c0 < r1; c0 += CH) {
         const int nr = min(CH, r1 - c0);
         __syncthreads();
@@ -134,6 +142,7 @@ __global__ __launch_bounds__(256) void k_gram(const float* __restrict__ yr, cons
             }
         }
     }
+    if (ta >= nb) return;
     double2* out = part + ((long long)s * nsplit + w) * L * L;
 #pragma unroll
     for (int u = 0; u < B; ++u)
@@ -409,13 +418,32 @@ __global__ __launch_bounds__(256) void k_features_part(const float* __restrict__
     const int rows = (m + nsplit - 1) / nsplit, i0 = c * rows, i1 = min(m, i0 + rows);
     const float* Yr = yr + (long long)s * m * n;
     const float* Yi = yi + (long long)s * m * n;
+    double* out = part + ((long long)s * nsplit + c) * n;
+    if ((n & 3) == 0) {  // 16-byte loads of 4 neighbouring columns
+        for (int j = 4 * tid; j < n; j += 4 * blockDim.x) {
+            double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
+            for (int i = i0; i < i1; ++i) {
+                const float4 r = *reinterpret_cast<const float4*>(Yr + (long long)i * n + j);
+                const float4 q = *reinterpret_cast<const float4*>(Yi + (long long)i * n + j);
+                a0 += (double)r.x * r.x + (double)q.x * q.x;
+                a1 += (double)r.y * r.y + (double)q.y * q.y;
+                a2 += (double)r.z * r.z + (double)q.z * q.z;
+                a3 += (double)r.w * r.w + (double)q.w * q.w;
+            }
+            out[j] = a0;
+            out[j + 1] = a1;
+            out[j + 2] = a2;
+            out[j + 3] = a3;
+        }
+        return;
+    }
     for (int j = tid; j < n; j += blockDim.x) {
         double acc = 0.0;
         for (int i = i0; i < i1; ++i) {
             const double a = Yr[(long long)i * n + j], b = Yi[(long long)i * n + j];
             acc += a * a + b * b;
         }
-        part[((long long)s * nsplit + c) * n + j] = acc;
+        out[j] = acc;
     }
 }
 
@@ -548,22 +576,43 @@ __global__ __launch_bounds__(64) void k_mlp_forward(const float* __restrict__ pa
 
 // Rank prediction: kpred = round(expm1(y log1p(p))) clipped to [0, p] (or the
 // fixed rank), lact = min(kpred + oversample, p); slices with lact > L go to
-// the full SVD (fallback = 1, lact = 0).
-__global__ __launch_bounds__(64) void k_predict(const float* __restrict__ params, const float* __restrict__ feats,
-                                                int nslices, int p, int fixed_rank, int oversample, int L,
-                                                int* __restrict__ kpred, int* __restrict__ lact,
-                                                int* __restrict__ fallback, int* __restrict__ rank)
+// the full SVD (fallback = 1, lact = 0).  One wavefront per slice, lane i
+// computing hidden unit i of each layer (each unit's sum in the same order as
+// mlp_eval, so y is bit-identical to tp_mlp_forward).
+__global__ __launch_bounds__(H) void k_predict(const float* __restrict__ params, const float* __restrict__ feats,
+                                               int nslices, int p, int fixed_rank, int oversample, int L,
+                                               int* __restrict__ kpred, int* __restrict__ lact,
+                                               int* __restrict__ fallback, int* __restrict__ rank)
 {
-    __shared__ float w[MlpOffsets::COUNT];
-    if (params)
-        for (int e = threadIdx.x; e < MlpOffsets::COUNT; e += blockDim.x) w[e] = params[e];
-    __syncthreads();
-    const int s = blockIdx.x * blockDim.x + threadIdx.x;
-    if (s >= nslices) return;
+    using O = MlpOffsets;
+    __shared__ float x[D];
+    __shared__ float za[H], zb[H];
+    const int s = blockIdx.x, i = threadIdx.x;
+    float yv = 0.0f;
+    if (params) {
+        if (i < D) x[i] = feats[(long long)s * D + i];
+        __syncthreads();
+        float v = params[O::B1 + i];
+        for (int j = 0; j < D; ++j) v = fmaf(params[O::W1 + i * D + j], x[j], v);
+        za[i] = v;
+        __syncthreads();
+        v = params[O::B2 + i];
+        for (int j = 0; j < H; ++j) v = fmaf(params[O::W2 + i * H + j], fmaxf(za[j], 0.0f), v);
+        zb[i] = v;
+        __syncthreads();
+        v = params[O::B3 + i];
+        for (int j = 0; j < H; ++j) v = fmaf(params[O::W3 + i * H + j], fmaxf(zb[j], 0.0f), v);
+        __syncthreads();
+        za[i] = v;
+        __syncthreads();
+        if (i == 0) {
+            yv = params[O::B4];
+            for (int j = 0; j < H; ++j) yv = fmaf(params[O::W4 + j], fmaxf(za[j], 0.0f), yv);
+        }
+    }
+    if (i != 0) return;
     int k = fixed_rank;
     if (params) {
-        float z[3 * H];
-        const float yv = mlp_eval(w, feats + (long long)s * D, z, z + H, z + 2 * H);
         const double kk = expm1((double)yv * log1p((double)p));
         k = (int)fmin((double)p, fmax(0.0, rint(kk)));
     }
@@ -751,7 +800,7 @@ hipError_t launch_store_basis(const float* zr, const float* zi, int n, int L, co
     return hipGetLastError();
 }
 
-int gram_split(int m) { return m >= 2048 ? 16 : (m >= 256 ? 8 : 1); }
+int gram_split(int m) { return m >= 1024 ? 16 : (m >= 256 ? 8 : 1); }
 
 template <int B>
 void launch_gram(const float* yr, const float* yi, int m, int L, const int* lact, int nslices, double2* part, int ns,
@@ -766,12 +815,13 @@ hipError_t launch_cholqr_pass(const float* yr, const float* yi, int m, int L, co
 {
     if (L > kMaxL) return hipErrorInvalidValue;
     const int ns = gram_split(m);
-    if (L <= 16)
+    // block edge B: the upper triangle of ceil(L/B) blocks fits 256 threads
+    if (L <= 22)
         launch_gram<1>(yr, yi, m, L, lact, nslices, part, ns, st);
-    else if (L <= 32)
+    else if (L <= 44)
         launch_gram<2>(yr, yi, m, L, lact, nslices, part, ns, st);
     else
-        launch_gram<4>(yr, yi, m, L, lact, nslices, part, ns, st);
+        launch_gram<3>(yr, yi, m, L, lact, nslices, part, ns, st);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     const size_t lds = 2 * (size_t)L * L * sizeof(double2);
@@ -837,8 +887,8 @@ hipError_t launch_sigma_top(const double* sig, int P, const int* lact, const int
 hipError_t launch_predict(const float* params, const float* feats, int nslices, int p, int fixed_rank,
                           int oversample, int L, int* kpred, int* lact, int* fallback, int* rank, hipStream_t st)
 {
-    k_predict<<<(nslices + 63) / 64, 64, 0, st>>>(params, feats, nslices, p, fixed_rank, oversample, L, kpred, lact,
-                                                  fallback, rank);
+    k_predict<<<nslices, H, 0, st>>>(params, feats, nslices, p, fixed_rank, oversample, L, kpred, lact, fallback,
+                                     rank);
     return hipGetLastError();
 }
 

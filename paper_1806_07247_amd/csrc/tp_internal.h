@@ -86,7 +86,11 @@ struct CgemmArgs {
     int real_first;      // slice 0 is real (imaginary planes are zero)
     int real_last;       // slice nslices-1 is real
     const int* kdyn;     // optional per-slice inner dimension (<= k), device
+    int ksplit;          // > 1: the inner dimension is cut in ksplit parts (FP32 only) whose
+    float* part;         // products go to part (re: [ksplit][nslices][m][n], then im) and are summed
 };
+// bytes of the split-K partial buffer of a product
+size_t splitk_bytes(int ksplit, int nslices, int m, int n);
 
 // Batched slice products of uneven shapes (FP32): one unit per output tile.
 enum { GEMM_NN = 0, GEMM_CN = 1, GEMM_NC = 2 };

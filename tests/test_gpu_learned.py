@@ -93,7 +93,10 @@ def lowrank(orc, n1, n2, n3, r, seed, noise=0.0):
     return A.astype(np.float32)
 
 
-@pytest.mark.parametrize("n1,n2,n3,r", [(64, 48, 6, 3), (40, 70, 5, 4), (128, 128, 8, 6), (200, 160, 4, 10)])
+# (512, 300, 4, 6): inner dimensions >= 256 with few output tiles, so the
+# range-finder products are split along k (split-K partial sums)
+@pytest.mark.parametrize("n1,n2,n3,r", [(64, 48, 6, 3), (40, 70, 5, 4), (128, 128, 8, 6), (200, 160, 4, 10),
+                                        (512, 300, 4, 6)])
 def test_learned_prox_exact_on_low_rank(tp, orc, n1, n2, n3, r):
     Y = lowrank(orc, n1, n2, n3, r, seed=n1 + r)
     tau = 0.2 * orc.tsn(Y)
