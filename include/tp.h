@@ -308,6 +308,8 @@ int tp_batch_destroy(tp_batch* plan);
  *   TP_PARAM_GEMM_VARIANT         slice GEMM tile variant: 0 = by shape, 1 = 64x64,
  *                                 2 = 128x128, 3 = 128x64, 4 = 128x32, 5 = 256x16,
  *                                 6 = 64x48 (output rows x columns per workgroup)
+ *   TP_PARAM_FFT_GRID             persistent workgroups per compute unit of the
+ *                                 tube transforms (0 = default 16)
  */
 enum {
     TP_PARAM_JACOBI_BLOCK = 0,
@@ -315,7 +317,8 @@ enum {
     TP_PARAM_JACOBI_BLOCKED_BELOW = 2,
     TP_PARAM_JACOBI_SWEEPS = 3,
     TP_PARAM_GEMM_VARIANT = 4,
-    TP_PARAM_COUNT = 5
+    TP_PARAM_FFT_GRID = 5,
+    TP_PARAM_COUNT = 6
 };
 int tp_set_param(int key, int value);
 int tp_get_param(int key);

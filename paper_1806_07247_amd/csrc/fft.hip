@@ -349,7 +349,7 @@ __global__ __launch_bounds__(kTubes) void k_fft_batch(const FftUnit* __restrict_
 inline int grid_for(long long ntubes, int tpb)
 {
     long long g = (ntubes + tpb - 1) / tpb;
-    const long long cap = 256LL * 16;  // enough waves to fill 256 CUs; the rest loops
+    const long long cap = 256LL * param(TP_PARAM_FFT_GRID);  // persistent: the rest loops
     return (int)(g < cap ? (g > 0 ? g : 1) : cap);
 }
 
