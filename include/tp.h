@@ -309,7 +309,11 @@ int tp_batch_destroy(tp_batch* plan);
  *                                 2 = 128x128, 3 = 128x64, 4 = 128x32, 5 = 256x16,
  *                                 6 = 64x48 (output rows x columns per workgroup)
  *   TP_PARAM_FFT_GRID             persistent workgroups per compute unit of the
- *                                 tube transforms (0 = default 16)
+ *                                 tube transforms (0 = default 8)
+ *   TP_PARAM_FFT_DIRECT           loads of the power-of-two forward transform: 1 =
+ *                                 each lane reads its own tube with 16-byte loads
+ *                                 (default), 2 = staged through LDS (the inverse
+ *                                 always stores through LDS, coalesced)
  */
 enum {
     TP_PARAM_JACOBI_BLOCK = 0,
@@ -318,7 +322,8 @@ enum {
     TP_PARAM_JACOBI_SWEEPS = 3,
     TP_PARAM_GEMM_VARIANT = 4,
     TP_PARAM_FFT_GRID = 5,
-    TP_PARAM_COUNT = 6
+    TP_PARAM_FFT_DIRECT = 6,
+    TP_PARAM_COUNT = 7
 };
 int tp_set_param(int key, int value);
 int tp_get_param(int key);

@@ -159,6 +159,50 @@ __global__ __launch_bounds__(kTubes) void k_rfft_pow2(const float* __restrict__ 
     }
 }
 
+// The same transform with each lane loading its own tube straight from
+// global memory (16-byte loads, no LDS staging): less LDS per wavefront, so
+// more wavefronts per compute unit; the lines a wavefront touches are reused
+// from the L1 cache over its next loads.
+template <int N>
+__global__ __launch_bounds__(kTubes) void k_rfft_pow2_direct(const float* __restrict__ x, float* __restrict__ re,
+                                                              float* __restrict__ im, long long ntubes)
+{
+    constexpr int M = N / 2;
+    __shared__ float2 tw[N];
+    fill_twiddles(tw, N);
+    __syncthreads();
+    const int tid = threadIdx.x;
+    for (long long base = (long long)blockIdx.x * kTubes; base < ntubes; base += (long long)gridDim.x * kTubes) {
+        const long long q = base + tid;
+        if (q >= ntubes) continue;
+        float zr[M], zi[M];
+        const float4* xt = reinterpret_cast<const float4*>(x + q * N);
+#pragma unroll
+        for (int t = 0; t < M / 2; ++t) {
+            const float4 v = xt[t];
+            zr[bitrev<M>(2 * t)] = v.x;
+            zi[bitrev<M>(2 * t)] = v.y;
+            zr[bitrev<M>(2 * t + 1)] = v.z;
+            zi[bitrev<M>(2 * t + 1)] = v.w;
+        }
+        cfft_half<N, false>(zr, zi, tw);
+        re[q] = zr[0] + zi[0];
+        im[q] = 0.0f;
+        re[(long long)M * ntubes + q] = zr[0] - zi[0];
+        im[(long long)M * ntubes + q] = 0.0f;
+#pragma unroll
+        for (int k = 1; k < M; ++k) {
+            const float ar = zr[k], ai = zi[k], br = zr[M - k], bi = -zi[M - k];
+            const float er = 0.5f * (ar + br), ei = 0.5f * (ai + bi);
+            const float dr = 0.5f * (ar - br), di = 0.5f * (ai - bi);
+            const float orr = di, oi = -dr;
+            const float2 w = tw[k];
+            re[(long long)k * ntubes + q] = er + (w.x * orr - w.y * oi);
+            im[(long long)k * ntubes + q] = ei + (w.x * oi + w.y * orr);
+        }
+    }
+}
+
 // Inverse transform of the nt tubes starting at `base` (see rfft_tile).
 template <int N>
 __device__ __forceinline__ void irfft_tile(const float* __restrict__ re, const float* __restrict__ im,
@@ -367,9 +411,15 @@ hipError_t launch_rfft(const float* x, float* re, float* im, long long ntubes, i
     if (ntubes <= 0) return hipSuccess;
     trace_work(0.0, (double)ntubes * (4.0 * n3 + 8.0 * (n3 / 2 + 1)));
     const int g = grid_for(ntubes, kTubes);
+    const bool direct = param(TP_PARAM_FFT_DIRECT) == 1 && (reinterpret_cast<uintptr_t>(x) & 15) == 0;
     switch (n3) {
-#define TP_RFFT_CASE(N) \
-    case N: k_rfft_pow2<N><<<g, kTubes, 0, s>>>(x, re, im, ntubes); return hipGetLastError();
+#define TP_RFFT_CASE(N)                                                       \
+    case N:                                                                   \
+        if (direct && N >= 8)                                                 \
+            k_rfft_pow2_direct<N><<<g, kTubes, 0, s>>>(x, re, im, ntubes);    \
+        else                                                                  \
+            k_rfft_pow2<N><<<g, kTubes, 0, s>>>(x, re, im, ntubes);           \
+        return hipGetLastError();
         TP_RFFT_CASE(4)
         TP_RFFT_CASE(8)
         TP_RFFT_CASE(16)

@@ -119,3 +119,21 @@ def test_tprod_every_tile_variant(tp, orc, variant, prec):
     err = rel_fro(C, ref)
     say(f"  variant {variant} {prec}: rel.err {err:.2e}")
     assert err <= TOL[prec]
+
+
+@pytest.mark.parametrize("direct", [1, 2])
+@pytest.mark.parametrize("shape", [(33, 31, 29, 8), (70, 65, 80, 64), (40, 36, 33, 128), (17, 13, 11, 16)],
+                         ids=lambda s: "x".join(map(str, s)))
+def test_tprod_fft_load_variants(tp, orc, direct, shape):
+    """Forward transform with direct per-lane tube loads (1) and LDS-staged
+    loads (2), forced through TP_PARAM_FFT_DIRECT."""
+    from paper_1806_07247_amd import _lib, inputs
+    lib = _lib.load()
+    n1, n2, l, n3 = shape
+    A, B = inputs.tprod_pair(n1, n2, l, n3, seed=n3 + direct)
+    try:
+        assert lib.tp_set_param(6, direct) == 0
+        C = tp.tp_tprod(gpu(A), gpu(B)).cpu().numpy()
+    finally:
+        lib.tp_set_param(6, 0)
+    assert rel_fro(C, orc.tprod(A, B)) <= TOL["fp32"]
