@@ -45,6 +45,11 @@ METRIC = "prox_tnn Melem/s learned-rank vs full-SVD @rel.err≤1e-4; tprod TFLOP
 PEAK = {"hbm_GBs": 8000.0, "fp32_mfma_TF": 157.3, "bf16_mfma_TF": 2500.0, "fp32_valu_TF": 157.3,
         "valu_fp64_TF": 78.6}
 LEARNED_SEED = 10000
+# HBM bytes per launch of the learned path's dominant kernel class, from the
+# FETCH_SIZE / WRITE_SIZE counter runs (copy-calibrated) recorded in
+# profiles/learned_prox_1024x1024x64_hbm_counters.md, for the kernels as they
+# are now (set to None when the kernel changes before it is measured again)
+MEASURED_TRAFFIC = {"cgemm": 121.7e6}
 
 
 def log(*a):
@@ -208,6 +213,9 @@ def learned_block(args, tp, dev):
     value = n * n * n3 / (ms * 1e-3) / 1e6
     log(f"  learned: {ms:.3f} ms/call, {value:.1f} Melem/s; stages {json.dumps(stages)}")
 
+    if args.no_full:
+        return value, ms, steps, {"calls": ncalls, "steps": steps, "ms_per_call": round(ms, 4),
+                                  "Melem_s": round(value, 3), "stages": stages}, None, calls, mlp, r
     # full-SVD prox on the same calls, and the error of the learned result
     fws = torch.empty(tp.tp_prox_tnn_workspace_size(n, n, n3), dtype=torch.uint8, device=dev)
     frank = torch.zeros(h, dtype=torch.int32, device=dev)
@@ -260,6 +268,7 @@ def learned_block(args, tp, dev):
                 "per_launch": {"ms": round(d["ms"] / d["launches"], 4), "flops": round(d["flops"] / d["launches"])}}
     elif d["bytes"] > 0:
         roof = roofline_for(dom, d, PEAK["fp32_mfma_TF"])
+        roof["traffic"] = MEASURED_TRAFFIC.get(dom)
     else:
         roof = {"kernel": dom, "bound": None, "achieved": None, "peak": None, "unit": None, "frac": None,
                 "traffic": None}
@@ -490,6 +499,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--learned-seed", type=int, default=LEARNED_SEED)
     ap.add_argument("--full-calls", type=int, default=0, help="calls timed through the full SVD (0: all)")
+    ap.add_argument("--no-full", action="store_true", help="skip the full-SVD comparison (a counter-run driver)")
     ap.add_argument("--prox-steps", type=int, default=20)
     ap.add_argument("--tprod-steps", type=int, default=10)
     ap.add_argument("--no-cpu-baseline", action="store_true")

@@ -3,8 +3,12 @@
 //
 // Layout: the tensor is tube-major (n1, n2, n3), so a block of consecutive
 // tubes is one contiguous span of memory.  A workgroup of one wavefront takes
-// 64 tubes, reads their span fully coalesced into LDS, and each lane then
-// transforms one tube in registers.  The Fourier side is slice-major planar
+// 64 tubes and each lane transforms one tube in registers.  The forward
+// transform reads each lane's tube with 16-byte loads (the lines a wavefront
+// touches are consumed from L1 over its next loads; no LDS, so more
+// wavefronts fit a compute unit), or stages the 64-tube span through LDS with
+// coalesced loads; the inverse stages its output through LDS and writes the
+// span coalesced.  The Fourier side is slice-major planar
 // complex: bin k of tube q is re[k*ntubes + q], im[k*ntubes + q], so the
 // per-bin stores of a wavefront are 64 consecutive floats; the transpose from
 // tube-major to slice-major costs no extra pass.
