@@ -106,6 +106,37 @@ int tp_prox_tnn(const float* Y, float* X, int n1, int n2, int n3, float tau, int
                 void* workspace, size_t workspace_bytes, void* stream);
 
 /*
+ * Tensor spectral norm (Definition 2.8): ||A|| = ||bcirc(A)|| = the largest
+ * singular value over the Fourier slices, written as one device double.
+ * Workspace and info as tp_tnn.
+ */
+size_t tp_tsn_workspace_size(int n1, int n2, int n3);
+int tp_tsn(const float* A, int n1, int n2, int n3, double* out, int* info, void* workspace, size_t workspace_bytes,
+           void* stream);
+
+/*
+ * Tensor tubal rank (Definition 2.7): the number of nonzero singular tubes
+ * S(i,i,:) of the t-SVD, written as one device int.  In floating point a tube
+ * counts when S(i,i,1) > tol, with S(i,i,1) = (1/n3) sum_k sigma_i(Abar^(k))
+ * (the first frontal slice of S is the mean of the Fourier-domain S; each
+ * slice's singular values taken in decreasing order); tol < 0 selects
+ * max(n1, n2) * 2^-23 * S(1,1,1) (FP32 working precision).
+ */
+size_t tp_tubalrank_workspace_size(int n1, int n2, int n3);
+int tp_tubalrank(const float* A, int n1, int n2, int n3, double tol, int* out, int* info, void* workspace,
+                 size_t workspace_bytes, void* stream);
+
+/*
+ * Conjugate tensor transpose (Definition 2.2) of a real n1 x n2 x n3 tensor:
+ * out (n2 x n1 x n3, tube-major, not overlapping A) has frontal slice t equal
+ * to the transpose of A's slice (n3 - t) mod n3.  Identity tensor (Definition
+ * 2.3): out (n x n x n3) gets I_n in its first frontal slice and zeros
+ * elsewhere.  Neither needs a workspace.
+ */
+int tp_tran(const float* A, float* out, int n1, int n2, int n3, void* stream);
+int tp_teye(float* out, int n, int n3, void* stream);
+
+/*
  * Learned-rank prox_tnn: the same operator as tp_prox_tnn (Theorem 2.3), with
  * each leading Fourier slice's SVT computed on a randomized range whose width
  * is predicted per slice.  Per slice k: features of the slice (below) go
@@ -337,7 +368,7 @@ int tp_get_param(int key);
  * last collect (or a negative tp_status) and forgets them.
  * Kernel ids: 0 rfft, 1 irfft, 2 cgemm, 3 jacobi, 4 shrink, 5 tnn_reduce,
  * 6 tsvd_finish, 7 features, 8 predict, 9 sketch, 10 cholqr, 11 rsvd_check,
- * 12 gather, 13 mlp, 14 accuracy.
+ * 12 gather, 13 mlp, 14 accuracy, 15 tensor_op.
  * tp_trace_collect_work also writes, per launch, the algorithmic work the
  * library assigns to it (host arrays, either may be NULL): for the slice
  * products 8 m n k flops per complex slice and 2 m n k per real one, and the

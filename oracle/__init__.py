@@ -48,6 +48,7 @@ def _load():
         "or_slice_sigma": (_I, [_D, _I, _I, _I, _D]),
         "or_tnn": (ctypes.c_double, [_D, _I, _I, _I]),
         "or_tsn": (ctypes.c_double, [_D, _I, _I, _I]),
+        "or_tubalrank": (_I, [_D, _I, _I, _I, ctypes.c_double, ctypes.c_double]),
         "or_prox_tnn": (_I, [_D, _I, _I, _I, ctypes.c_double, _D]),
         "or_svt_real": (_I, [_D, _I, _I, ctypes.c_double, _D]),
     }
@@ -214,6 +215,13 @@ def tsn(A):
     A = _real(A)
     n1, n2, n3 = A.shape
     return float(_load().or_tsn(_dp(A), n1, n2, n3))
+
+
+def tubalrank(A, tol=-1.0, eps=2.0 ** -23):
+    """Definition 2.7 with the tolerance of tp_tubalrank (tol < 0: max(n1,n2) eps S(1,1,1))."""
+    A = _real(A)
+    n1, n2, n3 = A.shape
+    return int(_load().or_tubalrank(_dp(A), n1, n2, n3, float(tol), float(eps)))
 
 
 def prox_tnn(Y, tau):

@@ -526,6 +526,25 @@ double or_tsn(const double* A, int n1, int n2, int n3)
     return mx;
 }
 
+int or_tubalrank(const double* A, int n1, int n2, int n3, double tol, double eps)
+{
+    const int p = n1 < n2 ? n1 : n2;
+    double* sig = (double*)xmalloc(sizeof(double) * (size_t)n3 * p);
+    or_slice_sigma(A, n1, n2, n3, sig); /* each slice's values, decreasing */
+    double s0 = 0.0;
+    for (int k = 0; k < n3; ++k) s0 += sig[(i64)k * p];
+    s0 /= n3;
+    if (tol < 0.0) tol = (double)(n1 > n2 ? n1 : n2) * eps * s0;
+    int rank = 0;
+    for (int i = 0; i < p; ++i) {
+        double si = 0.0;
+        for (int k = 0; k < n3; ++k) si += sig[(i64)k * p + i];
+        if (si / n3 > tol) ++rank;
+    }
+    free(sig);
+    return rank;
+}
+
 /* U (S - tau)_+ V^* of a complex m x n matrix, written to out */
 static int svt_complex(const or_cplx* a, int m, int n, double tau, or_cplx* out)
 {

@@ -73,6 +73,14 @@ int or_slice_sigma(const double* A, int n1, int n2, int n3, double* sig);
 double or_tnn(const double* A, int n1, int n2, int n3);
 /* Definition 2.8 with eq (17): ||bcirc(A)|| = max_k sigma_1(Abar^(k)). */
 double or_tsn(const double* A, int n1, int n2, int n3);
+
+/* Definition 2.7: the number of nonzero singular tubes S(i,i,:) of the
+ * t-SVD.  In floating point a tube counts when S(i,i,1) > tol, where
+ * S(i,i,1) = (1/n3) sum_k sigma_i(Abar^(k)) (the first frontal slice of S is
+ * the mean of the Fourier-domain S, eq (2) inverted at t = 0) with each
+ * slice's singular values in decreasing order; tol < 0 selects
+ * max(n1, n2) * eps * S(1,1,1). */
+int or_tubalrank(const double* A, int n1, int n2, int n3, double tol, double eps);
 /* Theorem 2.3 / Algorithm 3: Prox of the TNN at tau. */
 int or_prox_tnn(const double* Y, int n1, int n2, int n3, double tau, double* X);
 /* matrix singular value thresholding U (S - tau)_+ V^* of a real m x n matrix */

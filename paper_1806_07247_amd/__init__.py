@@ -24,6 +24,7 @@ __all__ = ["tp_tprod", "tp_tprod_workspace_size", "tp_tsvd", "tp_tsvd_workspace_
            "tp_tnn", "tp_tnn_workspace_size", "tp_prox_tnn_learned", "tp_prox_tnn_learned_workspace_size",
            "tp_slice_features", "tp_mlp_param_count", "tp_mlp_forward", "tp_mlp_loss_grad", "tp_mlp_adam",
            "tp_trace_enable", "tp_trace_collect_work", "tp_kernel_name", "TPBatch", "tp_batch_tprod",
+           "tp_tsn", "tp_tubalrank", "tp_tran", "tp_teye",
            "tp_batch_prox",
            "half_slices", "TPError", "TP_PREC_FP32",
            "TP_PREC_BF16X3", "TP_PREC_BF16", "library_path"]
@@ -352,3 +353,46 @@ def tp_batch_prox(As, taus, tau_rel=False, **kw):
     """prox of tau_i ||.||_* at every A_i, as one batch."""
     b = TPBatch("prox", As, taus=taus, tau_rel=tau_rel, **kw)
     return b.run()
+
+
+def tp_tsn(A, info=None, workspace=None):
+    """Tensor spectral norm (Definition 2.8) as a float64 device scalar tensor."""
+    lib = _lib.load()
+    A = _dev_tensor(A, "A")
+    n1, n2, n3 = A.shape
+    out = torch.empty((), dtype=torch.float64, device=A.device)
+    ws = workspace if workspace is not None else _workspace(lib.tp_tsn_workspace_size(n1, n2, n3), A.device)
+    _lib.check("tp_tsn", lib.tp_tsn(A.data_ptr(), n1, n2, n3, out.data_ptr(), _ptr(info), ws.data_ptr(),
+                                    ws.numel(), _stream(A.device)))
+    return out
+
+
+def tp_tubalrank(A, tol=-1.0, info=None, workspace=None):
+    """Tensor tubal rank (Definition 2.7) as an int32 device scalar tensor
+    (tol < 0: max(n1, n2) 2^-23 S(1,1,1))."""
+    lib = _lib.load()
+    A = _dev_tensor(A, "A")
+    n1, n2, n3 = A.shape
+    out = torch.empty((), dtype=torch.int32, device=A.device)
+    ws = workspace if workspace is not None else _workspace(lib.tp_tubalrank_workspace_size(n1, n2, n3), A.device)
+    _lib.check("tp_tubalrank", lib.tp_tubalrank(A.data_ptr(), n1, n2, n3, float(tol), out.data_ptr(), _ptr(info),
+                                                ws.data_ptr(), ws.numel(), _stream(A.device)))
+    return out
+
+
+def tp_tran(A, out=None):
+    """Conjugate transpose (Definition 2.2) of a real tensor: n2 x n1 x n3."""
+    lib = _lib.load()
+    A = _dev_tensor(A, "A")
+    n1, n2, n3 = A.shape
+    out = out if out is not None else torch.empty((n2, n1, n3), dtype=torch.float32, device=A.device)
+    _lib.check("tp_tran", lib.tp_tran(A.data_ptr(), out.data_ptr(), n1, n2, n3, _stream(A.device)))
+    return out
+
+
+def tp_teye(n, n3, device="cuda:0"):
+    """Identity tensor (Definition 2.3), n x n x n3."""
+    lib = _lib.load()
+    out = torch.empty((n, n, n3), dtype=torch.float32, device=device)
+    _lib.check("tp_teye", lib.tp_teye(out.data_ptr(), int(n), int(n3), _stream(out.device)))
+    return out

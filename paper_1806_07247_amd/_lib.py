@@ -28,6 +28,12 @@ SIGNATURES = {
     "tp_prox_tnn": (_I, [_VP, _VP, _I, _I, _I, _F, _VP, _VP, _VP, _SZ, _VP]),
     "tp_tnn_workspace_size": (_SZ, [_I, _I, _I]),
     "tp_tnn": (_I, [_VP, _I, _I, _I, _VP, _VP, _VP, _SZ, _VP]),
+    "tp_tsn_workspace_size": (_SZ, [_I, _I, _I]),
+    "tp_tsn": (_I, [_VP, _I, _I, _I, _VP, _VP, _VP, _SZ, _VP]),
+    "tp_tubalrank_workspace_size": (_SZ, [_I, _I, _I]),
+    "tp_tubalrank": (_I, [_VP, _I, _I, _I, ctypes.c_double, _VP, _VP, _VP, _SZ, _VP]),
+    "tp_tran": (_I, [_VP, _VP, _I, _I, _I, _VP]),
+    "tp_teye": (_I, [_VP, _I, _I, _VP]),
     "tp_set_param": (_I, [_I, _I]),
     "tp_get_param": (_I, [_I]),
     "tp_trace_enable": (_I, [_I]),

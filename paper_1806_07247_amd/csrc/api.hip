@@ -439,6 +439,100 @@ int tp_tnn(const float* A, int n1, int n2, int n3, double* out, int* info, void*
     return TP_OK;
 }
 
+// singular values of the h leading slices into L.sigma (unsorted), for tsn and tubalrank
+int slice_sigmas(const float* A, int n1, int n2, int n3, const SvtLayout& L, int* info, hipStream_t s)
+{
+    const int h = tp::half_slices(n3);
+    const bool tr = n1 < n2;
+    TP_LAUNCH(tp::K_RFFT, s, tp::launch_rfft(A, L.ybar.re, L.ybar.im, (long long)n1 * n2, n3, s));
+    tp::JacobiArgs j{};
+    j.yr = L.ybar.re;
+    j.yi = L.ybar.im;
+    j.sigma = L.sigma;
+    j.info = info;
+    j.m = n1;
+    j.n = n2;
+    j.nslices = h;
+    j.max_sweeps = tp::param(TP_PARAM_JACOBI_SWEEPS);
+    j.transpose = tr ? 1 : 0;
+    j.tol = tp::jacobi_tol(tr ? n2 : n1);
+    TP_LAUNCH(tp::K_JACOBI, s, tp::launch_jacobi(j, L.jscratch, L.jscratch_bytes, s));
+    return TP_OK;
+}
+
+int check_sigma_call(const float* A, const void* out, int n1, int n2, int n3)
+{
+    if (!A || !out) return TP_ERR_ARG;
+    if (bad_dim(n1) || bad_dim(n2) || bad_dim(n3) || n3 > kMaxN3) return TP_ERR_SHAPE;
+    if (bad_slice(n1, n2)) return TP_ERR_SHAPE;
+    if ((n1 < n2 ? n2 : n1) > 2048) return TP_ERR_UNSUPPORTED;
+    return TP_OK;
+}
+
+size_t tp_tsn_workspace_size(int n1, int n2, int n3) { return tp_tnn_workspace_size(n1, n2, n3); }
+
+int tp_tsn(const float* A, int n1, int n2, int n3, double* out, int* info, void* workspace, size_t workspace_bytes,
+           void* stream)
+{
+    const int c = check_sigma_call(A, out, n1, n2, n3);
+    if (c != TP_OK) return c;
+    SvtLayout L;
+    tp::Arena ar = svt_arena(workspace, workspace_bytes, n1, n2, n3, false, &L);
+    if (!ar.ok) return TP_ERR_WORKSPACE;
+    hipStream_t s = as_stream(stream);
+    const int st = slice_sigmas(A, n1, n2, n3, L, info, s);
+    if (st != TP_OK) return st;
+    TP_LAUNCH(tp::K_TNN_REDUCE, s,
+              tp::launch_tsn_reduce(L.sigma, tp::half_slices(n3), n1 < n2 ? n1 : n2, out, s));
+    return TP_OK;
+}
+
+size_t tp_tubalrank_workspace_size(int n1, int n2, int n3)
+{
+    const size_t base = tp_tnn_workspace_size(n1, n2, n3);
+    if (!base) return 0;
+    return base + tp::align_up((size_t)tp::half_slices(n3) * (n1 < n2 ? n1 : n2) * sizeof(double));
+}
+
+int tp_tubalrank(const float* A, int n1, int n2, int n3, double tol, int* out, int* info, void* workspace,
+                 size_t workspace_bytes, void* stream)
+{
+    const int c = check_sigma_call(A, out, n1, n2, n3);
+    if (c != TP_OK) return c;
+    if (std::isnan(tol) || std::isinf(tol)) return TP_ERR_ARG;
+    SvtLayout L;
+    tp::Arena ar = svt_arena(workspace, workspace_bytes, n1, n2, n3, false, &L);
+    double* sorted = ar.take<double>((size_t)tp::half_slices(n3) * (n1 < n2 ? n1 : n2));
+    if (!ar.ok) return TP_ERR_WORKSPACE;
+    hipStream_t s = as_stream(stream);
+    const int st = slice_sigmas(A, n1, n2, n3, L, info, s);
+    if (st != TP_OK) return st;
+    const double scale = (double)(n1 > n2 ? n1 : n2) * 0x1p-23;  // max(n1, n2) * eps of FP32
+    TP_LAUNCH(tp::K_TNN_REDUCE, s,
+              tp::launch_tubal_rank(L.sigma, sorted, tp::half_slices(n3), n1 < n2 ? n1 : n2, n3, tol, scale, out,
+                                    s));
+    return TP_OK;
+}
+
+int tp_tran(const float* A, float* out, int n1, int n2, int n3, void* stream)
+{
+    if (!A || !out) return TP_ERR_ARG;
+    if (bad_dim(n1) || bad_dim(n2) || bad_dim(n3)) return TP_ERR_SHAPE;
+    if (A == out && !(n1 == 1 && n2 == 1 && n3 == 1)) return TP_ERR_ARG;  // not in place
+    hipStream_t s = as_stream(stream);
+    TP_LAUNCH(tp::K_TENSOR_OP, s, tp::launch_tran(A, out, n1, n2, n3, s));
+    return TP_OK;
+}
+
+int tp_teye(float* out, int n, int n3, void* stream)
+{
+    if (!out) return TP_ERR_ARG;
+    if (bad_dim(n) || bad_dim(n3)) return TP_ERR_SHAPE;
+    hipStream_t s = as_stream(stream);
+    TP_LAUNCH(tp::K_TENSOR_OP, s, tp::launch_teye(out, n, n3, s));
+    return TP_OK;
+}
+
 size_t tp_tsvd_workspace_size(int n1, int n2, int n3)
 {
     if (bad_dim(n1) || bad_dim(n2) || bad_dim(n3)) return 0;

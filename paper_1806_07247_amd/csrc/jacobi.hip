@@ -697,6 +697,89 @@ hipError_t launch_shrink_batch(const ShrinkItem* items, const SliceUnit* units, 
 }
 
 
+namespace {
+
+// max over all slices and columns (the column norms are the singular values)
+__global__ __launch_bounds__(256) void k_tsn_reduce(const double* __restrict__ sigma, long long total,
+                                                    double* __restrict__ out)
+{
+    __shared__ double part[256];
+    double m = 0.0;
+    for (long long e = threadIdx.x; e < total; e += blockDim.x) m = fmax(m, sigma[e]);
+    part[threadIdx.x] = m;
+    __syncthreads();
+    for (int w = blockDim.x / 2; w > 0; w >>= 1) {
+        if (threadIdx.x < w) part[threadIdx.x] = fmax(part[threadIdx.x], part[threadIdx.x + w]);
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) *out = part[0];
+}
+
+// per slice (one workgroup): the P values in decreasing order, ties by index
+__global__ __launch_bounds__(256) void k_sort_sigma(const double* __restrict__ sigma, double* __restrict__ sorted,
+                                                    int P)
+{
+    const double* sg = sigma + (long long)blockIdx.x * P;
+    double* out = sorted + (long long)blockIdx.x * P;
+    for (int j = threadIdx.x; j < P; j += blockDim.x) {
+        const double v = sg[j];
+        int r = 0;
+        for (int i = 0; i < P; ++i) {
+            const double u = sg[i];
+            r += (u > v || (u == v && i < j)) ? 1 : 0;
+        }
+        out[r] = v;
+    }
+}
+
+// S(i,i,1) = (1/n3) sum over all n3 slices of the i-th largest singular value
+// (the h leading slices, the non-real ones counted twice by conjugate
+// symmetry); rank = #{i : S(i,i,1) > tol}, tol < 0: tol_scale * S(1,1,1)
+__global__ __launch_bounds__(256) void k_tubal_rank(const double* __restrict__ sorted, int nslices, int P, int n3,
+                                                    double tol, double tol_scale, int* __restrict__ out)
+{
+    __shared__ int cnt[256];
+    __shared__ double s0;
+    auto mean_at = [&](int i) {
+        double acc = 0.0;
+        for (int s = 0; s < nslices; ++s) {
+            const bool real = (s == 0) || (n3 % 2 == 0 && s == n3 / 2);
+            acc += (real ? 1.0 : 2.0) * sorted[(long long)s * P + i];
+        }
+        return acc / n3;
+    };
+    if (threadIdx.x == 0) s0 = P > 0 ? mean_at(0) : 0.0;
+    __syncthreads();
+    const double t = tol >= 0.0 ? tol : tol_scale * s0;
+    int c = 0;
+    for (int i = threadIdx.x; i < P; i += blockDim.x) c += mean_at(i) > t ? 1 : 0;
+    cnt[threadIdx.x] = c;
+    __syncthreads();
+    for (int w = blockDim.x / 2; w > 0; w >>= 1) {
+        if (threadIdx.x < w) cnt[threadIdx.x] += cnt[threadIdx.x + w];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) *out = cnt[0];
+}
+
+}  // namespace
+
+hipError_t launch_tsn_reduce(const double* sigma, int nslices, int P, double* out, hipStream_t st)
+{
+    k_tsn_reduce<<<1, 256, 0, st>>>(sigma, (long long)nslices * P, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_tubal_rank(const double* sigma, double* sorted, int nslices, int P, int n3, double tol,
+                             double tol_scale, int* out, hipStream_t st)
+{
+    k_sort_sigma<<<nslices, 256, 0, st>>>(sigma, sorted, P);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    k_tubal_rank<<<1, 256, 0, st>>>(sorted, nslices, P, n3, tol, tol_scale, out);
+    return hipGetLastError();
+}
+
 hipError_t launch_tnn_reduce(const double* sigma, int nslices, int P, int n3, double* out, hipStream_t st)
 {
     k_tnn_reduce<<<1, 256, 0, st>>>(sigma, nslices, P, n3, out);

@@ -143,6 +143,15 @@ size_t jacobi_batch_lds(int max_r, int max_p);
 hipError_t launch_jacobi_batch(const JacobiArgs* items, const SliceUnit* units, int nunits, int max_r, int max_p,
                                int grid, hipStream_t st);
 hipError_t launch_shrink_batch(const ShrinkItem* items, const SliceUnit* units, int nunits, int grid, hipStream_t st);
+// Definition 2.2 (conjugate transpose of a real tensor) and 2.3 (identity)
+hipError_t launch_tran(const float* a, float* out, int n1, int n2, int n3, hipStream_t s);
+hipError_t launch_teye(float* out, int n, int n3, hipStream_t s);
+// tsn (Definition 2.8): the largest singular value over the slices
+hipError_t launch_tsn_reduce(const double* sigma, int nslices, int P, double* out, hipStream_t st);
+// tubal rank (Definition 2.7) from the unsorted singular values of the h
+// leading slices: sorted (h x P scratch) then counted against tol
+hipError_t launch_tubal_rank(const double* sigma, double* sorted, int nslices, int P, int n3, double tol,
+                             double tol_scale, int* out, hipStream_t st);
 hipError_t launch_jacobi(const JacobiArgs& a, void* scratch, size_t scratch_bytes, hipStream_t s);
 size_t jacobi_scratch_bytes(int m, int n, int nslices, bool withv);
 // Jacobi convergence threshold for an R-row work matrix of FP32 data
@@ -211,7 +220,7 @@ int param(int key);
 enum KernelId {
     K_RFFT = 0, K_IRFFT = 1, K_CGEMM = 2, K_JACOBI = 3, K_SHRINK = 4, K_TNN_REDUCE = 5, K_TSVD_FINISH = 6,
     K_FEATURES = 7, K_PREDICT = 8, K_SKETCH = 9, K_CHOLQR = 10, K_RSVD_CHECK = 11, K_GATHER = 12, K_MLP = 13,
-    K_ACCURACY = 14
+    K_ACCURACY = 14, K_TENSOR_OP = 15
 };
 
 // Records HIP events around the launches in its scope while tracing is on,

@@ -376,3 +376,35 @@ def test_prox_nonexpansive(orc):
 def test_prox_rejects_negative_tau(orc):
     with pytest.raises(ValueError):
         orc.prox_tnn(rand(2, 2, 2), -1.0)
+
+
+@pytest.mark.parametrize("n1,n2,n3,r", [(7, 6, 5, 3), (5, 9, 4, 2), (6, 6, 1, 4), (8, 5, 6, 5)])
+def test_tubalrank_of_product(orc, n1, n2, n3, r):
+    """Definition 2.7: P * Q with P n1 x r x n3, Q r x n2 x n3 generic has tubal
+    rank r (every Fourier slice has rank r)."""
+    rng = np.random.default_rng(n1 * 10 + r)
+    A = orc.tprod(rng.standard_normal((n1, r, n3)), rng.standard_normal((r, n2, n3)))
+    assert orc.tubalrank(A) == r
+
+
+def test_tubalrank_special_cases(orc):
+    """teye(n, n3) has tubal rank n, the zero tensor 0, and for n3 = 1 the
+    tubal rank is the matrix rank (numpy)."""
+    assert orc.tubalrank(orc.teye(4, 3)) == 4
+    assert orc.tubalrank(np.zeros((3, 4, 2))) == 0
+    rng = np.random.default_rng(2)
+    M = rng.standard_normal((6, 2)) @ rng.standard_normal((2, 5))
+    assert orc.tubalrank(M[:, :, None]) == np.linalg.matrix_rank(M) == 2
+    # singular tubes are formed per rank position across the Fourier slices
+    # (each slice's values sorted), so the tubal rank is the largest slice
+    # rank, not the number of nonzero tubes of A: here the DC slice holds one
+    # tube and the Nyquist slice the other, each slice has rank 1
+    A = np.zeros((3, 3, 4))
+    A[0, 0, :] = [1.0, -1.0, 1.0, -1.0]  # energy only at the Nyquist bin
+    A[1, 1, :] = 1.0                     # only at DC
+    assert orc.tubalrank(A) == 1
+    A[1, 1, :] = [1.0, 1.0, -1.0, -1.0]  # now bins 1 and 3: a second slice with rank 1
+    A[2, 2, :] = 1.0                     # and DC again: DC rank 1, Nyquist rank 1
+    assert orc.tubalrank(A) == 1
+    A[2, 2, :] = [1.0, -1.0, 1.0, -1.0]  # the Nyquist slice now has rank 2
+    assert orc.tubalrank(A) == 2
