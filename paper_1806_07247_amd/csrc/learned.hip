@@ -75,6 +75,8 @@ __global__ __launch_bounds__(256) void k_sketch(float* __restrict__ omr, float* 
 }
 
 // ------------------------------------------------------------ CholeskyQR --
+constexpr int kMaxGramSplit = 16;  // row bands of the Gram (partials summed by k_chol)
+
 // Partial Gram G_w = Y_w^* Y_w (FP64) of the rows handled by workgroup w of
 // nsplit, for the lact leading columns; Y is m x L planar row-major.  Only the
 // upper triangle is formed (the Cholesky reads nothing else): thread t owns
@@ -176,12 +178,20 @@ __global__ __launch_bounds__(256) void k_chol(const double2* __restrict__ part, 
     for (int e = tid; e < L * L; e += nt) {
         const int a = e / L, b = e % L;
         double2 g = make_double2(0.0, 0.0);
-        if (b >= a)
-            for (int w = 0; w < nsplit; ++w) {
-                const double2 v = P[(long long)w * L * L + e];
-                g.x += v.x;
-                g.y += v.y;
+        if (b >= a) {
+            // all partials in flight at once, then summed in the fixed order w = 0, 1, ...
+            double2 v[kMaxGramSplit];
+#pragma unroll
+            for (int w = 0; w < kMaxGramSplit; ++w)
+                v[w] = w < nsplit ? P[(long long)w * L * L + e] : make_double2(0.0, 0.0);
+#pragma unroll
+            for (int w = 0; w < kMaxGramSplit; ++w) {
+                if (w < nsplit) {
+                    g.x += v[w].x;
+                    g.y += v[w].y;
+                }
             }
+        }
         R[e] = g;
     }
     __syncthreads();
@@ -194,19 +204,14 @@ __global__ __launch_bounds__(256) void k_chol(const double2* __restrict__ part, 
     for (int a = tid; a < la; a += nt) R[a * L + a].x += sd;
     __syncthreads();
     for (int j = 0; j < L; ++j) {
-        if (tid == 0) {
-            double d = 1.0;
-            if (j < la) {
-                d = R[j * L + j].x;
-                if (!(d > 0.0)) {
-                    if (status) status[s] = 1;
-                    d = 1e-300;
-                }
-            }
-            R[j * L + j] = make_double2(sqrt(d), 0.0);
+        // every thread forms the pivot itself (same bits everywhere); the
+        // diagonal entry is rewritten after the barrier, once all have read it
+        double d = 1.0;
+        if (j < la) {
+            d = R[j * L + j].x;
+            if (!(d > 0.0)) d = 1e-300;
         }
-        __syncthreads();
-        const double inv = 1.0 / R[j * L + j].x;
+        const double rjj = sqrt(d), inv = 1.0 / rjj;
         for (int c = j + 1 + tid; c < L; c += nt) {
             double2 v = make_double2(0.0, 0.0);
             if (j < la && c < la) {
@@ -217,6 +222,10 @@ __global__ __launch_bounds__(256) void k_chol(const double2* __restrict__ part, 
             R[j * L + c] = v;
         }
         __syncthreads();
+        if (tid == 0) {
+            if (j < la && !(R[j * L + j].x > 0.0) && status) status[s] = 1;
+            R[j * L + j] = make_double2(rjj, 0.0);
+        }
         // trailing update of the upper triangle: R_ab -= conj(R_ja) R_jb, j < a <= b
         const int t = L - j - 1;
         for (int e = tid; e < t * t; e += nt) {
@@ -236,25 +245,29 @@ __global__ __launch_bounds__(256) void k_chol(const double2* __restrict__ part, 
         X[e] = make_double2(a == b ? 1.0 : 0.0, 0.0);
     }
     __syncthreads();
-    // R X = I: for j = L-1 .. 0, X_j /= R_jj, then X_i -= R_ij X_j for i < j
+    // R X = I: for j = L-1 .. 0, X_j /= R_jj, then X_i -= R_ij X_j for i < j.
+    // The rows above use X_j / R_jj formed on the fly from the unscaled row,
+    // which is scaled in place afterwards (nothing later reads it), so each
+    // step needs one barrier.
     for (int j = L - 1; j >= 0; --j) {
         const double inv = 1.0 / R[j * L + j].x;
-        for (int c = j + tid; c < L; c += nt) {
-            X[j * L + c].x *= inv;
-            X[j * L + c].y *= inv;
-        }
-        __syncthreads();
         const int w = L - j;
         for (int e = tid; e < j * w; e += nt) {
             const int i = e / w, c = j + e % w;
-            const double2 r = R[i * L + j], x = X[j * L + c];
+            const double2 r = R[i * L + j], x0 = X[j * L + c];
+            const double2 x = make_double2(x0.x * inv, x0.y * inv);
             double2 v = X[i * L + c];
             v.x -= r.x * x.x - r.y * x.y;
             v.y -= r.x * x.y + r.y * x.x;
             X[i * L + c] = v;
         }
         __syncthreads();
+        for (int c = j + tid; c < L; c += nt) {
+            X[j * L + c].x *= inv;
+            X[j * L + c].y *= inv;
+        }
     }
+    __syncthreads();
     for (int e = tid; e < L * L; e += nt) {
         rir[(long long)s * L * L + e] = (float)X[e].x;
         rii[(long long)s * L * L + e] = (float)X[e].y;
@@ -800,7 +813,7 @@ hipError_t launch_store_basis(const float* zr, const float* zi, int n, int L, co
     return hipGetLastError();
 }
 
-int gram_split(int m) { return m >= 1024 ? 16 : (m >= 256 ? 8 : 1); }
+int gram_split(int m) { return m >= 1024 ? kMaxGramSplit : (m >= 256 ? 8 : 1); }
 
 template <int B>
 void launch_gram(const float* yr, const float* yi, int m, int L, const int* lact, int nslices, double2* part, int ns,
