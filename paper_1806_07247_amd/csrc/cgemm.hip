@@ -216,20 +216,23 @@ __device__ __forceinline__ void xcd_tile(int& x, int& y, int& z)
     z = t / (nx * ny);
 }
 
-// FP32 LDS footprint of one workgroup tile: double-buffered re/im panels
-template <class T>
+// FP32 LDS footprint of one workgroup tile: double-buffered re/im panels of
+// BK columns of the inner dimension
+template <class T, int BK = 16>
 constexpr int f32_smem_floats()
 {
-    return 2 * 2 * (T::BM + T::BN) * 20;
+    return 2 * 2 * (T::BM + T::BN) * (BK + 4);
 }
 
 // One BM x BN output tile of slice s at (m0, n0); smem holds
-// f32_smem_floats<T>() floats.
-template <int OPA, int OPB, class T>
+// f32_smem_floats<T, BK>() floats.  BK (16 or 32) inner-dimension columns
+// per LDS stage.
+template <int OPA, int OPB, class T, int BK = 16>
 __device__ __forceinline__ void cgemm_f32_tile(const CgemmArgs& p, int slice, int m0, int n0, float* smem, int kp = 0)
 {
     constexpr int BM = T::BM, BN = T::BN, TM = T::TM, TN = T::TN;
-    constexpr int BK = 16, LDK = BK + 4;
+    constexpr int LDK = BK + 4;
+    static_assert(BK % 16 == 0, "16-column MFMA k groups");
     typedef float PanelA[BM * LDK];
     typedef float PanelB[BN * LDK];
     PanelA* sAr = reinterpret_cast<PanelA*>(smem);
@@ -261,17 +264,19 @@ __device__ __forceinline__ void cgemm_f32_tile(const CgemmArgs& p, int slice, in
     for (int c = 0; c < nk; ++c) {
         const int cur = c & 1;
         if (c + 1 < nk) ld.load(v, p, m0, n0, v.K0 + (c + 1) * BK, tid);
-        // lane (g, r16) of MFMA step s uses k = 4g + s: one 16-byte LDS read per operand
+#pragma unroll
+        for (int kh = 0; kh < BK / 16; ++kh) {
+        // lane (g, r16) of MFMA step s uses k = 16 kh + 4g + s: one 16-byte LDS read per operand
         float4 fa_r[TM], fa_i[TM], fb_r[TN], fb_i[TN];
 #pragma unroll
         for (int t = 0; t < TM; ++t) {
-            fa_r[t] = *reinterpret_cast<const float4*>(&sAr[cur][(wr + 16 * t + r16) * LDK + 4 * g]);
-            fa_i[t] = *reinterpret_cast<const float4*>(&sAi[cur][(wr + 16 * t + r16) * LDK + 4 * g]);
+            fa_r[t] = *reinterpret_cast<const float4*>(&sAr[cur][(wr + 16 * t + r16) * LDK + 16 * kh + 4 * g]);
+            fa_i[t] = *reinterpret_cast<const float4*>(&sAi[cur][(wr + 16 * t + r16) * LDK + 16 * kh + 4 * g]);
         }
 #pragma unroll
         for (int t = 0; t < TN; ++t) {
-            fb_r[t] = *reinterpret_cast<const float4*>(&sBr[cur][(wc + 16 * t + r16) * LDK + 4 * g]);
-            fb_i[t] = *reinterpret_cast<const float4*>(&sBi[cur][(wc + 16 * t + r16) * LDK + 4 * g]);
+            fb_r[t] = *reinterpret_cast<const float4*>(&sBr[cur][(wc + 16 * t + r16) * LDK + 16 * kh + 4 * g]);
+            fb_i[t] = *reinterpret_cast<const float4*>(&sBi[cur][(wc + 16 * t + r16) * LDK + 16 * kh + 4 * g]);
         }
         if (v.real) {
 #pragma unroll
@@ -297,19 +302,20 @@ __device__ __forceinline__ void cgemm_f32_tile(const CgemmArgs& p, int slice, in
                         acci[ti][tj] = __builtin_amdgcn_mfma_f32_16x16x4f32(ai, br, acci[ti][tj], 0, 0, 0);
                     }
         }
+        }
         if (c + 1 < nk) ld.template store<LDK>(tid, StoreF32{sAr[cur ^ 1], sAi[cur ^ 1], sBr[cur ^ 1], sBi[cur ^ 1]});
         __syncthreads();
     }
     write_tile<T>(v, p, m0, n0, wr, wc, lane, accr, acci);
 }
 
-template <int OPA, int OPB, class T>
+template <int OPA, int OPB, class T, int BK>
 __global__ __launch_bounds__(256) void k_cgemm_f32(CgemmArgs p)
 {
-    __shared__ __attribute__((aligned(16))) float smem[f32_smem_floats<T>()];
+    __shared__ __attribute__((aligned(16))) float smem[f32_smem_floats<T, BK>()];
     int x, y, z;
     xcd_tile(x, y, z);  // z = kp * nslices + slice
-    cgemm_f32_tile<OPA, OPB, T>(p, z % p.nslices, y * T::BM, x * T::BN, smem, z / p.nslices);
+    cgemm_f32_tile<OPA, OPB, T, BK>(p, z % p.nslices, y * T::BM, x * T::BN, smem, z / p.nslices);
 }
 
 // C = sum over the ksplit partial products, in a fixed order
@@ -496,11 +502,15 @@ dim3 grid_of(const CgemmArgs& a)
 template <int OPA, int OPB, class T>
 hipError_t launch_f32(const CgemmArgs& a, hipStream_t s)
 {
+    // inner-dimension stage: 32 columns for long inner dimensions (tunable)
+    const int bkp = param(TP_PARAM_GEMM_BK);
+    const bool bk32 = bkp == 32 || (bkp == 0 && a.k >= 256);
+    auto kern = bk32 ? k_cgemm_f32<OPA, OPB, T, 32> : k_cgemm_f32<OPA, OPB, T, 16>;
     if (a.ksplit > 1) {
         if (!a.part) return hipErrorInvalidValue;
         dim3 g = grid_of<T>(a);
         g.z *= a.ksplit;
-        k_cgemm_f32<OPA, OPB, T><<<g, 256, 0, s>>>(a);
+        kern<<<g, 256, 0, s>>>(a);
         hipError_t e = hipGetLastError();
         if (e != hipSuccess) return e;
         const long long total = (long long)a.nslices * a.m * a.n;
@@ -509,7 +519,7 @@ hipError_t launch_f32(const CgemmArgs& a, hipStream_t s)
         k_splitk_reduce<<<(int)blocks, 256, 0, s>>>(a);
         return hipGetLastError();
     }
-    k_cgemm_f32<OPA, OPB, T><<<grid_of<T>(a), 256, 0, s>>>(a);
+    kern<<<grid_of<T>(a), 256, 0, s>>>(a);
     return hipGetLastError();
 }
 
