@@ -31,6 +31,12 @@ struct tp_batch {
     std::vector<tp::JacobiArgs> jac;
     std::vector<tp::ShrinkItem> shr;
     std::vector<tp::SliceUnit> ju, su;
+    // Jacobi units in classes of LDS footprint (largest class first), each
+    // launched with its own LDS size, so that small slices share a CU
+    struct JClass {
+        int start, count, max_r, max_p, grid;
+    };
+    std::vector<JClass> jcls;
     // byte offsets of the tables and the planes in the workspace
     size_t off_fwd = 0, off_inv = 0, off_g1 = 0, off_g2 = 0, off_u1 = 0, off_u2 = 0, off_jac = 0, off_shr = 0,
            off_ju = 0, off_su = 0, tables_end = 0, total = 0;
@@ -217,11 +223,34 @@ int plan_layout(tp_batch* p, char* ws)
     };
     std::stable_sort(p->u1.begin(), p->u1.end(), gemm_cost(p->g1));
     std::stable_sort(p->u2.begin(), p->u2.end(), gemm_cost(p->g2));
+    // Jacobi units: by LDS class (largest first), then by cost within a class
+    auto jclass = [&](const tp::JacobiArgs& a) {
+        const size_t b = (size_t)a.m * a.n * sizeof(float2);
+        return b <= 16 * 1024 ? 0 : (b <= 32 * 1024 ? 1 : (b <= 64 * 1024 ? 2 : 3));
+    };
     std::stable_sort(p->ju.begin(), p->ju.end(), [&](const tp::SliceUnit& x, const tp::SliceUnit& y) {
         const tp::JacobiArgs &a = p->jac[x.item], &b = p->jac[y.item];
+        const int ka = jclass(a), kb = jclass(b);
+        if (ka != kb) return ka > kb;
         const double ca = (double)a.m * a.n * std::min(a.m, a.n), cb = (double)b.m * b.n * std::min(b.m, b.n);
         return ca > cb;
     });
+    p->jcls.clear();
+    for (int u = 0; u < (int)p->ju.size(); ++u) {
+        const tp::JacobiArgs& a = p->jac[p->ju[u].item];
+        const int k = jclass(a);
+        if (p->jcls.empty() || jclass(p->jac[p->ju[p->jcls.back().start].item]) != k)
+            p->jcls.push_back(tp_batch::JClass{u, 0, 0, 0, 0});
+        tp_batch::JClass& c = p->jcls.back();
+        ++c.count;
+        c.max_r = std::max(c.max_r, std::max(a.m, a.n));
+        c.max_p = std::max(c.max_p, std::min(a.m, a.n));
+    }
+    for (tp_batch::JClass& c : p->jcls) {
+        const size_t lds = tp::jacobi_batch_lds(c.max_r, c.max_p);
+        const int per_cu = std::max(1, std::min(8, (int)((160 * 1024 - 1024) / std::max<size_t>(lds, 1))));
+        c.grid = p->opts.grid_jacobi > 0 ? p->opts.grid_jacobi : 256 * per_cu;
+    }
     return (int)(cursor - p->tables_end);
 }
 
@@ -355,9 +384,11 @@ int tp_batch_run(const tp_batch* p, void* stream)
                   tp::launch_cgemm_batch(dev<tp::CgemmArgs>(p, p->off_g1), dev<tp::GemmUnit>(p, p->off_u1),
                                          (int)p->u1.size(), p->tile, p->grid_gemm, p->g1_flops, p->g1_bytes, s));
     } else {
-        TP_LAUNCH(tp::K_JACOBI, s,
-                  tp::launch_jacobi_batch(dev<tp::JacobiArgs>(p, p->off_jac), dev<tp::SliceUnit>(p, p->off_ju),
-                                          (int)p->ju.size(), p->max_r, p->max_p, p->grid_jac, s));
+        for (const tp_batch::JClass& c : p->jcls)
+            TP_LAUNCH(tp::K_JACOBI, s,
+                      tp::launch_jacobi_batch(dev<tp::JacobiArgs>(p, p->off_jac),
+                                              dev<tp::SliceUnit>(p, p->off_ju) + c.start, c.count, c.max_r, c.max_p,
+                                              c.grid, s));
         TP_LAUNCH(tp::K_SHRINK, s,
                   tp::launch_shrink_batch(dev<tp::ShrinkItem>(p, p->off_shr), dev<tp::SliceUnit>(p, p->off_su),
                                           (int)p->su.size(), p->grid_jac, s));

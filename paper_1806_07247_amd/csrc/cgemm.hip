@@ -361,28 +361,27 @@ __global__ __launch_bounds__(256) void k_cgemm_batch(const CgemmArgs* __restrict
 }
 
 // ------------------------------------------------------------- BF16 (x3) --
-__device__ __forceinline__ unsigned short bf16_rne(float x)
-{
-    unsigned int u = __float_as_uint(x);
-    if ((u & 0x7f800000u) == 0x7f800000u) return (unsigned short)((u >> 16) | ((u & 0xffffu) ? 0x40u : 0u));
-    u += 0x7fffu + ((u >> 16) & 1u);
-    return (unsigned short)(u >> 16);
-}
-__device__ __forceinline__ float bf16_to_f32(unsigned short h) { return __uint_as_float(((unsigned int)h) << 16); }
 
-// writes hi (and lo when splitting) bf16 planes: pointers [hi/lo][re/im]
+// writes hi (and lo when splitting) bf16 planes: pointers [hi/lo][re/im].
+// Each conversion is one hardware round-to-nearest-even conversion
+// (v_cvt_pk_bf16_f32, one value per instruction; the two-element vector form
+// of the conversion measured wrong lanes on this toolchain);
+// lo = bf16(x - hi) carries the next 8 bits.
 struct StoreBF16 {
     unsigned short* a[2][2];
     unsigned short* b[2][2];
     bool split;
     __device__ __forceinline__ void put(unsigned short* const (&d)[2][2], int i, float r, float im) const
     {
-        const unsigned short rh = bf16_rne(r), ih = bf16_rne(im);
-        d[0][0][i] = rh;
-        d[0][1][i] = ih;
+        const __bf16 hr = (__bf16)r;
+        const __bf16 hi = (__bf16)im;
+        d[0][0][i] = __builtin_bit_cast(unsigned short, hr);
+        d[0][1][i] = __builtin_bit_cast(unsigned short, hi);
         if (split) {
-            d[1][0][i] = bf16_rne(r - bf16_to_f32(rh));
-            d[1][1][i] = bf16_rne(im - bf16_to_f32(ih));
+            const __bf16 lr = (__bf16)(r - (float)hr);
+            const __bf16 li = (__bf16)(im - (float)hi);
+            d[1][0][i] = __builtin_bit_cast(unsigned short, lr);
+            d[1][1][i] = __builtin_bit_cast(unsigned short, li);
         }
     }
     __device__ __forceinline__ void a_(int i, float r, float im) const { put(a, i, r, im); }
