@@ -84,61 +84,88 @@ __device__ __forceinline__ SliceView slice_view(const CgemmArgs& p, int s, int k
     return v;
 }
 
+// Four source elements contiguous in memory at off (valid of them in bounds):
+// one 16-byte load per plane when all four are valid and the planes allow
+// it, else element by element with zero fill.  neg negates the imaginary
+// part (conjugated operands).
+struct Quad {
+    float4 r, i;
+};
+__device__ __forceinline__ Quad load4(const float* pr, const float* pi, long long off, int valid, bool vec, bool neg)
+{
+    Quad q;
+    if (vec && valid == 4) {
+        q.r = *reinterpret_cast<const float4*>(pr + off);
+        q.i = *reinterpret_cast<const float4*>(pi + off);
+    } else {
+        q.r.x = valid > 0 ? pr[off] : 0.0f;
+        q.r.y = valid > 1 ? pr[off + 1] : 0.0f;
+        q.r.z = valid > 2 ? pr[off + 2] : 0.0f;
+        q.r.w = valid > 3 ? pr[off + 3] : 0.0f;
+        q.i.x = valid > 0 ? pi[off] : 0.0f;
+        q.i.y = valid > 1 ? pi[off + 1] : 0.0f;
+        q.i.z = valid > 2 ? pi[off + 2] : 0.0f;
+        q.i.w = valid > 3 ? pi[off + 3] : 0.0f;
+    }
+    if (neg) q.i = -q.i;
+    return q;
+}
+
+// true when 16-byte loads of 4-aligned groups are aligned in both planes
+__device__ __forceinline__ bool vec_ok(const float* pr, const float* pi, long long ld)
+{
+    return ((reinterpret_cast<unsigned long long>(pr) | reinterpret_cast<unsigned long long>(pi)) & 15) == 0 &&
+           (ld & 3) == 0;
+}
+
 // Register staging of one BM x BK panel of op(A) and BN x BK panel of op(B):
 // the panels are cut in groups of 4 consecutive elements along the
 // contiguous direction of the source, groups spread over the 256 threads.
 //   A, OP_N: group -> (row, 4 k)    A, OP_C: group -> (k, 4 rows)
 //   B, OP_N: group -> (k, 4 cols)   B, OP_C: group -> (col, 4 k)
+// Tile origins and inner-dimension stages are multiples of 4, so every
+// group starts 4-aligned in its source.
 template <int OPA, int OPB, int BM, int BN, int BK>
 struct PanelLoader {
     static constexpr int KQ = BK / 4;
     static constexpr int GA = BM * BK / 4, GB = BN * BK / 4;
     static constexpr int NA = (GA + 255) / 256, NB = (GB + 255) / 256;
-    float a_r[NA][4], a_i[NA][4], b_r[NB][4], b_i[NB][4];
+    Quad a[NA], b[NB];
 
     __device__ __forceinline__ void load(const SliceView& v, const CgemmArgs& p, int m0, int n0, int k0, int tid)
     {
+        const bool va = vec_ok(v.ar, v.ai, p.lda), vb = vec_ok(v.br, v.bi, p.ldb);
 #pragma unroll
         for (int u = 0; u < NA; ++u) {
             const int g = tid + u * 256;
-#pragma unroll
-            for (int e = 0; e < 4; ++e) {
-                int row, kk;
-                long long off;
-                if (OPA == OP_N) {
-                    row = m0 + g / KQ;
-                    kk = k0 + (g % KQ) * 4 + e;
-                    off = (long long)row * p.lda + kk;
-                } else {
-                    kk = k0 + g / (BM / 4);
-                    row = m0 + (g % (BM / 4)) * 4 + e;
-                    off = (long long)kk * p.lda + row;
-                }
-                const bool in = g < GA && row < p.m && kk < v.K;
-                a_r[u][e] = in ? v.ar[off] : 0.0f;
-                a_i[u][e] = in ? (OPA == OP_C ? -v.ai[off] : v.ai[off]) : 0.0f;
+            int valid;
+            long long off;
+            if (OPA == OP_N) {
+                const int row = m0 + g / KQ, kk = k0 + (g % KQ) * 4;
+                valid = (g < GA && row < p.m) ? max(0, min(4, v.K - kk)) : 0;
+                off = (long long)row * p.lda + kk;
+            } else {
+                const int kk = k0 + g / (BM / 4), row = m0 + (g % (BM / 4)) * 4;
+                valid = (g < GA && kk < v.K) ? max(0, min(4, p.m - row)) : 0;
+                off = (long long)kk * p.lda + row;
             }
+            a[u] = load4(v.ar, v.ai, off, valid, va, OPA == OP_C);
         }
 #pragma unroll
         for (int u = 0; u < NB; ++u) {
             const int g = tid + u * 256;
-#pragma unroll
-            for (int e = 0; e < 4; ++e) {
-                int col, kk;
-                long long off;
-                if (OPB == OP_N) {
-                    kk = k0 + g / (BN / 4);
-                    col = n0 + (g % (BN / 4)) * 4 + e;
-                    off = (long long)kk * p.ldb + col;
-                } else {
-                    col = n0 + g / KQ;
-                    kk = k0 + (g % KQ) * 4 + e;
-                    off = (long long)col * p.ldb + kk;
-                }
-                const bool in = g < GB && col < p.n && kk < v.K;
-                b_r[u][e] = in ? v.br[off] : 0.0f;
-                b_i[u][e] = in ? (OPB == OP_C ? -v.bi[off] : v.bi[off]) : 0.0f;
+            int valid;
+            long long off;
+            if (OPB == OP_N) {
+                const int kk = k0 + g / (BN / 4), col = n0 + (g % (BN / 4)) * 4;
+                valid = (g < GB && kk < v.K) ? max(0, min(4, p.n - col)) : 0;
+                off = (long long)kk * p.ldb + col;
+            } else {
+                const int col = n0 + g / KQ, kk = k0 + (g % KQ) * 4;
+                valid = (g < GB && col < p.n) ? max(0, min(4, v.K - kk)) : 0;
+                off = (long long)col * p.ldb + kk;
             }
+            b[u] = load4(v.br, v.bi, off, valid, vb, OPB == OP_C);
         }
     }
 
@@ -154,7 +181,7 @@ struct PanelLoader {
             for (int e = 0; e < 4; ++e) {
                 const int idx = (OPA == OP_N) ? (g / KQ) * LDK + (g % KQ) * 4 + e
                                               : ((g % (BM / 4)) * 4 + e) * LDK + g / (BM / 4);
-                st.a(idx, a_r[u][e], a_i[u][e]);
+                st.a(idx, (&a[u].r.x)[e], (&a[u].i.x)[e]);
             }
         }
 #pragma unroll
@@ -165,7 +192,7 @@ struct PanelLoader {
             for (int e = 0; e < 4; ++e) {
                 const int idx = (OPB == OP_N) ? ((g % (BN / 4)) * 4 + e) * LDK + g / (BN / 4)
                                               : (g / KQ) * LDK + (g % KQ) * 4 + e;
-                st.b(idx, b_r[u][e], b_i[u][e]);
+                st.b(idx, (&b[u].r.x)[e], (&b[u].i.x)[e]);
             }
         }
     }
