@@ -342,7 +342,10 @@ int tp_batch_destroy(tp_batch* plan);
  *   TP_PARAM_FFT_GRID             persistent workgroups per compute unit of the
  *                                 tube transforms (0 = default 8)
  *   TP_PARAM_GEMM_BK              FP32 slice GEMM inner-dimension stage: 16 or 32
- *                                 columns (0 = 32 when the inner dimension is >= 256)
+ *                                 columns (0 = 32 when the inner dimension is >= 256
+ *                                 and the tile is at least 64 columns wide)
+ *   TP_PARAM_GEMM_KSPLIT          learned-rank prox: parts of the inner dimension of
+ *                                 its long products (0 = by shape, else 1 .. 4)
  *   TP_PARAM_FFT_DIRECT           loads of the power-of-two forward transform: 1 =
  *                                 each lane reads its own tube with 16-byte loads
  *                                 (default), 2 = staged through LDS (the inverse
@@ -357,7 +360,8 @@ enum {
     TP_PARAM_FFT_GRID = 5,
     TP_PARAM_FFT_DIRECT = 6,
     TP_PARAM_GEMM_BK = 7,
-    TP_PARAM_COUNT = 8
+    TP_PARAM_GEMM_KSPLIT = 8,
+    TP_PARAM_COUNT = 9
 };
 int tp_set_param(int key, int value);
 int tp_get_param(int key);

@@ -19,7 +19,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CACHE = os.path.join(HERE, "tune_gfx950.json")
 
 PARAM = {"jacobi_block": 0, "jacobi_mode": 1, "jacobi_blocked_below": 2, "jacobi_sweeps": 3,
-         "gemm_variant": 4, "fft_grid": 5, "fft_direct": 6, "gemm_bk": 7}
+         "gemm_variant": 4, "fft_grid": 5, "fft_direct": 6, "gemm_bk": 7, "gemm_ksplit": 8}
 
 
 def _bucket(v):

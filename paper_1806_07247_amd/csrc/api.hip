@@ -226,7 +226,11 @@ int pick_ksplit(int m, int n, int k, int nslices, size_t part_bytes)
     if (!part_bytes || k < 256) return 1;
     const long long tiles = (long long)((m + 63) / 64) * ((n + 63) / 64) * nslices;
     int ks = 1;
-    while (ks < kMaxSplit && tiles * ks * 2 <= 2048 && k / (ks * 2) >= 128) ks *= 2;
+    const int forced = tp::param(TP_PARAM_GEMM_KSPLIT);
+    if (forced > 0)
+        ks = std::min(forced, kMaxSplit);
+    else
+        while (ks < kMaxSplit && tiles * ks * 2 <= 4096 && k / (ks * 2) >= 128) ks *= 2;
     while (ks > 1 && tp::splitk_bytes(ks, nslices, m, n) > part_bytes) ks /= 2;
     return ks;
 }

@@ -315,19 +315,27 @@ __device__ __forceinline__ void cgemm_f32_tile(const CgemmArgs& p, int slice, in
                         accr[ti][tj] = __builtin_amdgcn_mfma_f32_16x16x4f32(
                             (&fa_r[ti].x)[s], (&fb_r[tj].x)[s], accr[ti][tj], 0, 0, 0);
         } else {
+            // two passes over the tiles, so that the two products into one
+            // accumulator are 2 TM TN independent MFMAs apart
 #pragma unroll
-            for (int s = 0; s < 4; ++s)
+            for (int s = 0; s < 4; ++s) {
 #pragma unroll
                 for (int ti = 0; ti < TM; ++ti)
 #pragma unroll
                     for (int tj = 0; tj < TN; ++tj) {
-                        const float ar = (&fa_r[ti].x)[s], ai = (&fa_i[ti].x)[s];
-                        const float br = (&fb_r[tj].x)[s], bi = (&fb_i[tj].x)[s];
-                        accr[ti][tj] = __builtin_amdgcn_mfma_f32_16x16x4f32(ar, br, accr[ti][tj], 0, 0, 0);
-                        acci[ti][tj] = __builtin_amdgcn_mfma_f32_16x16x4f32(ar, bi, acci[ti][tj], 0, 0, 0);
-                        accr[ti][tj] = __builtin_amdgcn_mfma_f32_16x16x4f32(-ai, bi, accr[ti][tj], 0, 0, 0);
-                        acci[ti][tj] = __builtin_amdgcn_mfma_f32_16x16x4f32(ai, br, acci[ti][tj], 0, 0, 0);
+                        const float ar = (&fa_r[ti].x)[s];
+                        accr[ti][tj] = __builtin_amdgcn_mfma_f32_16x16x4f32(ar, (&fb_r[tj].x)[s], accr[ti][tj], 0, 0, 0);
+                        acci[ti][tj] = __builtin_amdgcn_mfma_f32_16x16x4f32(ar, (&fb_i[tj].x)[s], acci[ti][tj], 0, 0, 0);
                     }
+#pragma unroll
+                for (int ti = 0; ti < TM; ++ti)
+#pragma unroll
+                    for (int tj = 0; tj < TN; ++tj) {
+                        const float ai = (&fa_i[ti].x)[s];
+                        accr[ti][tj] = __builtin_amdgcn_mfma_f32_16x16x4f32(-ai, (&fb_i[tj].x)[s], accr[ti][tj], 0, 0, 0);
+                        acci[ti][tj] = __builtin_amdgcn_mfma_f32_16x16x4f32(ai, (&fb_r[tj].x)[s], acci[ti][tj], 0, 0, 0);
+                    }
+            }
         }
         }
         if (c + 1 < nk) ld.template store<LDK>(tid, StoreF32{sAr[cur ^ 1], sAi[cur ^ 1], sBr[cur ^ 1], sBi[cur ^ 1]});
@@ -492,24 +500,29 @@ __global__ __launch_bounds__(256) void k_cgemm_bf16(CgemmArgs p)
                 for (int t = 0; t < TN; ++t)
                     fb[t][h][ri] = *reinterpret_cast<const shortx8*>(&sB[cur][h][ri][(wc + 16 * t + r16) * LDK + 8 * g]);
             }
+        // terms (a-part, b-part): hi*hi, then hi*lo and lo*hi when splitting;
+        // each term in two passes over the tiles (independent MFMAs between
+        // the two products into one accumulator)
 #pragma unroll
-        for (int ti = 0; ti < TM; ++ti)
+        for (int term = 0; term < (SPLIT ? 3 : 1); ++term) {
+            const int ha = (term == 2) ? 1 : 0, hb = (term == 1) ? 1 : 0;
 #pragma unroll
-            for (int tj = 0; tj < TN; ++tj) {
-                // terms (a-part, b-part): hi*hi, then hi*lo and lo*hi when splitting
+            for (int ti = 0; ti < TM; ++ti)
 #pragma unroll
-                for (int term = 0; term < (SPLIT ? 3 : 1); ++term) {
-                    const int ha = (term == 2) ? 1 : 0, hb = (term == 1) ? 1 : 0;
-                    const shortx8 ar = fa[ti][ha][0], ai = fa[ti][ha][1];
-                    const shortx8 br = fb[tj][hb][0], bi = fb[tj][hb][1];
-                    accr[ti][tj] = TP_MFMA_BF16(ar, br, accr[ti][tj]);
-                    if (!v.real) {
-                        acci[ti][tj] = TP_MFMA_BF16(ar, bi, acci[ti][tj]);
-                        accr[ti][tj] = TP_MFMA_BF16(neg_bf16x8(ai), bi, accr[ti][tj]);
-                        acci[ti][tj] = TP_MFMA_BF16(ai, br, acci[ti][tj]);
-                    }
+                for (int tj = 0; tj < TN; ++tj) {
+                    accr[ti][tj] = TP_MFMA_BF16(fa[ti][ha][0], fb[tj][hb][0], accr[ti][tj]);
+                    if (!v.real) acci[ti][tj] = TP_MFMA_BF16(fa[ti][ha][0], fb[tj][hb][1], acci[ti][tj]);
                 }
+            if (!v.real) {
+#pragma unroll
+                for (int ti = 0; ti < TM; ++ti)
+#pragma unroll
+                    for (int tj = 0; tj < TN; ++tj) {
+                        accr[ti][tj] = TP_MFMA_BF16(neg_bf16x8(fa[ti][ha][1]), fb[tj][hb][1], accr[ti][tj]);
+                        acci[ti][tj] = TP_MFMA_BF16(fa[ti][ha][1], fb[tj][hb][0], acci[ti][tj]);
+                    }
             }
+        }
         if (c + 1 < nk) {
             const StoreBF16 st = storer(cur ^ 1);
             ld.template store<LDK>(tid, StoreAdapter<StoreBF16>{st});
@@ -528,9 +541,12 @@ dim3 grid_of(const CgemmArgs& a)
 template <int OPA, int OPB, class T>
 hipError_t launch_f32(const CgemmArgs& a, hipStream_t s)
 {
-    // inner-dimension stage: 32 columns for long inner dimensions (tunable)
+    // inner-dimension stage (tunable): 32 columns for long inner dimensions on
+    // tiles at least 64 wide; narrow tiles keep 16, whose smaller LDS stage
+    // fits twice the workgroups per CU (measured faster on the skinny
+    // range-finder products)
     const int bkp = param(TP_PARAM_GEMM_BK);
-    const bool bk32 = bkp == 32 || (bkp == 0 && a.k >= 256);
+    const bool bk32 = bkp == 32 || (bkp == 0 && a.k >= 256 && T::BN >= 64);
     auto kern = bk32 ? k_cgemm_f32<OPA, OPB, T, 32> : k_cgemm_f32<OPA, OPB, T, 16>;
     if (a.ksplit > 1) {
         if (!a.part) return hipErrorInvalidValue;

@@ -156,152 +156,170 @@ __global__ __launch_bounds__(256) void k_gram(const float* __restrict__ yr, cons
 }
 
 // Per slice: G = sum of the partial Grams (fixed order, upper triangle); in
-// pass 0 a diagonal shift 1e-13 trace(G)/lact; Cholesky G = R^* R (FP64, in
-// LDS, right-looking: one row of R and a rank-1 update of the trailing block
-// per step, all threads in parallel); Rinv = R^{-1} by back substitution row
-// by row (parallel over the columns and the rows above), written as FP32
-// planar (identity on the inactive columns); optionally Rtot <- R Rtot (FP64)
-// and R2^* (FP32 planar, zero outside the active block).
-__global__ __launch_bounds__(256) void k_chol(const double2* __restrict__ part, int nsplit, int L,
-                                              const int* __restrict__ lact, int pass, float* __restrict__ rir,
-                                              float* __restrict__ rii, double2* __restrict__ rtot,
-                                              float* __restrict__ rhr, float* __restrict__ rhi,
-                                              int* __restrict__ status)
+// pass 0 a diagonal shift 1e-13 trace(G)/lact; then one elimination sweep on
+// the augmented pair [G | I] (FP64): step j scales row j by 1/sqrt(pivot) and
+// subtracts conj(R_ja) times it from every later row a.  On the G side this
+// is the right-looking Cholesky G = R^* R; the same row operations turn I
+// into M = R^{-*} (they are the E with E G = R), so Rinv = M^* is formed in
+// the same L steps.  Every thread keeps its own entries (a, b) of both sides
+// in registers; the owners of row j+1 publish it to LDS after their update
+// (two row buffers, one barrier per step).  Rinv is written as FP32 planar
+// (identity on the inactive columns); optionally Rtot <- R Rtot (FP64) and
+// R2^* (FP32 planar, zero outside the active block).
+constexpr int kCholThreads = 1024;
+constexpr int kCholEntries = kMaxL * kMaxL / kCholThreads;  // entries per thread
+
+__global__ __launch_bounds__(kCholThreads) void k_chol(const double2* __restrict__ part, int nsplit, int L,
+                                                       const int* __restrict__ lact, int pass, float* __restrict__ rir,
+                                                       float* __restrict__ rii, double2* __restrict__ rtot,
+                                                       float* __restrict__ rhr, float* __restrict__ rhi,
+                                                       int* __restrict__ status)
 {
     extern __shared__ double2 sh[];
-    double2* R = sh;            // L x L
-    double2* X = sh + L * L;    // L x L (inverse, then Rtot)
-    __shared__ double sd;
+    double2* R = sh;            // L x L (R, for the Rtot product)
+    double2* X = sh + L * L;    // L x L (Rtot)
+    __shared__ double2 rowG[2][kMaxL], rowM[2][kMaxL];
+    __shared__ double diag[kMaxL];
     const int s = blockIdx.x, tid = threadIdx.x, nt = blockDim.x;
     const int la = lact[s];
     const double2* P = part + (long long)s * nsplit * L * L;
-    for (int e = tid; e < L * L; e += nt) {
-        const int a = e / L, b = e % L;
-        double2 g = make_double2(0.0, 0.0);
-        if (b >= a) {
-            // all partials in flight at once, then summed in the fixed order w = 0, 1, ...
-            double2 v[kMaxGramSplit];
+
+    // own entries e = tid + u nt: G side (b >= a) in (gr, gi), M side (b <= a)
+    // in (mr, mi); plain doubles, so that they stay in registers
+    int ea[kCholEntries], eb[kCholEntries];
+    double gr[kCholEntries], gi[kCholEntries], mr[kCholEntries], mi[kCholEntries];
 #pragma unroll
-            for (int w = 0; w < kMaxGramSplit; ++w)
-                v[w] = w < nsplit ? P[(long long)w * L * L + e] : make_double2(0.0, 0.0);
+    for (int u = 0; u < kCholEntries; ++u) {
+        const int e = tid + u * nt;
+        ea[u] = e < L * L ? e / L : L;  // L: no entry
+        eb[u] = e < L * L ? e % L : 0;
+        gr[u] = gi[u] = 0.0;
+        mr[u] = ea[u] == eb[u] ? 1.0 : 0.0;
+        mi[u] = 0.0;
+        if (ea[u] < L && eb[u] >= ea[u]) {
+            // all partials in flight at once, then summed in the fixed order w = 0, 1, ...
+            double vr[kMaxGramSplit], vi[kMaxGramSplit];
+#pragma unroll
+            for (int w = 0; w < kMaxGramSplit; ++w) {
+                const double2 v = w < nsplit ? P[(long long)w * L * L + e] : make_double2(0.0, 0.0);
+                vr[w] = v.x;
+                vi[w] = v.y;
+            }
 #pragma unroll
             for (int w = 0; w < kMaxGramSplit; ++w) {
                 if (w < nsplit) {
-                    g.x += v[w].x;
-                    g.y += v[w].y;
+                    gr[u] += vr[w];
+                    gi[u] += vi[w];
+                }
+            }
+            if (ea[u] == eb[u]) diag[ea[u]] = gr[u];
+        }
+    }
+    __syncthreads();
+    // diagonal shift (pass 0): every thread sums the same values in the same order
+    double sd = 0.0;
+    if (pass == 0 && la > 0) {
+        double tr = 0.0;
+        for (int a = 0; a < la; ++a) tr += diag[a];
+        sd = 1e-13 * tr / la;
+    }
+#pragma unroll
+    for (int u = 0; u < kCholEntries; ++u) {
+        if (ea[u] == eb[u] && ea[u] < la) gr[u] += sd;
+        if (ea[u] == 0) {  // publish row 0
+            rowG[0][eb[u]] = make_double2(gr[u], gi[u]);
+            if (eb[u] == 0) rowM[0][0] = make_double2(mr[u], mi[u]);
+        }
+    }
+    __syncthreads();
+    bool broke = false;
+    for (int j = 0; j < L; ++j) {
+        const int cur = j & 1, nxt = cur ^ 1;
+        const bool act = j < la;
+        double p = act ? rowG[cur][j].x : 1.0;
+        if (!(p > 0.0)) {
+            p = 1e-300;
+            broke = true;
+        }
+        const double rjj = sqrt(p), inv = 1.0 / rjj;
+#pragma unroll
+        for (int u = 0; u < kCholEntries; ++u) {
+            const int a = ea[u], b = eb[u];
+            if (a < L && a >= j) {
+                // R_jb of the scaled row j (zero outside the active block)
+                const double2 rb = (act && b > j && b < la) ? rowG[cur][b] : make_double2(0.0, 0.0);
+                if (a == j) {
+                    if (b > j) {
+                        gr[u] = rb.x * inv;
+                        gi[u] = rb.y * inv;
+                    } else if (b == j) {
+                        gr[u] = rjj;
+                        gi[u] = 0.0;
+                    }
+                    if (b <= j) {
+                        const double2 mv = rowM[cur][b];
+                        mr[u] = mv.x * inv;
+                        mi[u] = mv.y * inv;
+                    }
+                } else {
+                    const double2 ra = (act && a < la) ? rowG[cur][a] : make_double2(0.0, 0.0);
+                    const double xr = ra.x * inv, xi = ra.y * inv;  // R_ja
+                    if (b >= a) {  // G_ab -= conj(R_ja) R_jb
+                        const double yr = rb.x * inv, yi = rb.y * inv;
+                        gr[u] -= xr * yr + xi * yi;
+                        gi[u] -= xr * yi - xi * yr;
+                    }
+                    if (b <= j) {  // M_ab -= conj(R_ja) M'_jb
+                        const double2 mv = rowM[cur][b];
+                        const double yr = mv.x * inv, yi = mv.y * inv;
+                        mr[u] -= xr * yr + xi * yi;
+                        mi[u] -= xr * yi - xi * yr;
+                    }
+                }
+                if (a == j + 1) {  // publish row j+1 for the next step
+                    if (b >= a) rowG[nxt][b] = make_double2(gr[u], gi[u]);
+                    if (b <= a) rowM[nxt][b] = make_double2(mr[u], mi[u]);
                 }
             }
         }
-        R[e] = g;
-    }
-    __syncthreads();
-    if (tid == 0) {
-        double tr = 0.0;
-        for (int a = 0; a < la; ++a) tr += R[a * L + a].x;
-        sd = (pass == 0 && la > 0) ? 1e-13 * tr / la : 0.0;
-    }
-    __syncthreads();
-    for (int a = tid; a < la; a += nt) R[a * L + a].x += sd;
-    __syncthreads();
-    for (int j = 0; j < L; ++j) {
-        // every thread forms the pivot itself (same bits everywhere); the
-        // diagonal entry is rewritten after the barrier, once all have read it
-        double d = 1.0;
-        if (j < la) {
-            d = R[j * L + j].x;
-            if (!(d > 0.0)) d = 1e-300;
-        }
-        const double rjj = sqrt(d), inv = 1.0 / rjj;
-        for (int c = j + 1 + tid; c < L; c += nt) {
-            double2 v = make_double2(0.0, 0.0);
-            if (j < la && c < la) {
-                v = R[j * L + c];
-                v.x *= inv;
-                v.y *= inv;
-            }
-            R[j * L + c] = v;
-        }
-        __syncthreads();
-        if (tid == 0) {
-            if (j < la && !(R[j * L + j].x > 0.0) && status) status[s] = 1;
-            R[j * L + j] = make_double2(rjj, 0.0);
-        }
-        // trailing update of the upper triangle: R_ab -= conj(R_ja) R_jb, j < a <= b
-        const int t = L - j - 1;
-        for (int e = tid; e < t * t; e += nt) {
-            const int a = j + 1 + e / t, b = j + 1 + e % t;
-            if (b < a) continue;
-            const double2 x = R[j * L + a], y = R[j * L + b];
-            double2 v = R[a * L + b];
-            v.x -= x.x * y.x + x.y * y.y;
-            v.y -= x.x * y.y - x.y * y.x;
-            R[a * L + b] = v;
-        }
         __syncthreads();
     }
-    for (int e = tid; e < L * L; e += nt) {
-        const int a = e / L, b = e % L;
-        if (b < a) R[e] = make_double2(0.0, 0.0);
-        X[e] = make_double2(a == b ? 1.0 : 0.0, 0.0);
-    }
-    __syncthreads();
-    // R X = I: for j = L-1 .. 0, X_j /= R_jj, then X_i -= R_ij X_j for i < j.
-    // The rows above use X_j / R_jj formed on the fly from the unscaled row,
-    // which is scaled in place afterwards (nothing later reads it), so each
-    // step needs one barrier.
-    for (int j = L - 1; j >= 0; --j) {
-        const double inv = 1.0 / R[j * L + j].x;
-        const int w = L - j;
-        for (int e = tid; e < j * w; e += nt) {
-            const int i = e / w, c = j + e % w;
-            const double2 r = R[i * L + j], x0 = X[j * L + c];
-            const double2 x = make_double2(x0.x * inv, x0.y * inv);
-            double2 v = X[i * L + c];
-            v.x -= r.x * x.x - r.y * x.y;
-            v.y -= r.x * x.y + r.y * x.x;
-            X[i * L + c] = v;
-        }
-        __syncthreads();
-        for (int c = j + tid; c < L; c += nt) {
-            X[j * L + c].x *= inv;
-            X[j * L + c].y *= inv;
+    if (broke && tid == 0 && status) status[s] = 1;
+    // Rinv = M^*: entry (a, b) of M gives Rinv(b, a); Rinv(b, a) = 0 for b > a
+#pragma unroll
+    for (int u = 0; u < kCholEntries; ++u) {
+        const int a = ea[u], b = eb[u];
+        if (a < L) {
+            const long long o = (long long)s * L * L + b * L + a;
+            rir[o] = b <= a ? (float)mr[u] : 0.0f;
+            rii[o] = b <= a ? (float)(-mi[u]) : 0.0f;
+            R[a * L + b] = b >= a ? make_double2(gr[u], gi[u]) : make_double2(0.0, 0.0);
         }
     }
-    __syncthreads();
-    for (int e = tid; e < L * L; e += nt) {
-        rir[(long long)s * L * L + e] = (float)X[e].x;
-        rii[(long long)s * L * L + e] = (float)X[e].y;
-    }
-    __syncthreads();
     if (rtot) {
         double2* T = rtot + (long long)s * L * L;
         if (pass == 0) {
-            for (int e = tid; e < L * L; e += nt) X[e] = R[e];
+            for (int e = tid; e < L * L; e += nt) X[e] = R[e];  // own entries, written above by this thread
         } else {
             for (int e = tid; e < L * L; e += nt) X[e] = T[e];
             __syncthreads();
-            // R Rtot of two upper triangular factors, entries kept in registers
-            constexpr int MAXE = 64 * 64 / 256;
-            double2 acc[MAXE];
+            // R Rtot of two upper triangular factors
+            double cr[kCholEntries], ci[kCholEntries];
 #pragma unroll
-            for (int u = 0; u < MAXE; ++u) {
-                const int e = tid + u * nt;
-                acc[u] = make_double2(0.0, 0.0);
-                if (e < L * L) {
-                    const int a = e / L, b = e % L;
+            for (int u = 0; u < kCholEntries; ++u) {
+                const int a = ea[u], b = eb[u];
+                cr[u] = ci[u] = 0.0;
+                if (a < L)
                     for (int k = a; k <= b; ++k) {
                         const double2 x = R[a * L + k], y = X[k * L + b];
-                        acc[u].x += x.x * y.x - x.y * y.y;
-                        acc[u].y += x.x * y.y + x.y * y.x;
+                        cr[u] += x.x * y.x - x.y * y.y;
+                        ci[u] += x.x * y.y + x.y * y.x;
                     }
-                }
             }
             __syncthreads();
 #pragma unroll
-            for (int u = 0; u < MAXE; ++u) {
-                const int e = tid + u * nt;
-                if (e < L * L) X[e] = acc[u];
-            }
+            for (int u = 0; u < kCholEntries; ++u)
+                if (ea[u] < L) X[ea[u] * L + eb[u]] = make_double2(cr[u], ci[u]);
         }
         __syncthreads();
         for (int e = tid; e < L * L; e += nt) T[e] = X[e];
@@ -838,11 +856,11 @@ hipError_t launch_cholqr_pass(const float* yr, const float* yi, int m, int L, co
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     const size_t lds = 2 * (size_t)L * L * sizeof(double2);
-    if (lds > 64 * 1024) {
-        e = hipFuncSetAttribute((const void*)k_chol, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024 - 1024);
+    if (lds + 8 * 1024 > 64 * 1024) {  // dynamic + the static row buffers
+        e = hipFuncSetAttribute((const void*)k_chol, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
         if (e != hipSuccess) return e;
     }
-    k_chol<<<nslices, 256, lds, st>>>(part, ns, L, lact, pass, rir, rii, rtot, rhr, rhi, status);
+    k_chol<<<nslices, kCholThreads, lds, st>>>(part, ns, L, lact, pass, rir, rii, rtot, rhr, rhi, status);
     return hipGetLastError();
 }
 
