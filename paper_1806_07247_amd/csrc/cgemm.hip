@@ -169,18 +169,27 @@ struct PanelLoader {
         }
     }
 
-    // writes the panels as sA[row][k], sB[col][k] (leading dimension LDK)
-    template <int LDK, class Store>
+    // writes the panels to LDS.  Row-major panels are sA[row][k], sB[col][k]
+    // (leading dimension LDK); with KA (KB) the A (B) panel is k-major,
+    // sA[k][row] (sB[k][col]) with leading dimension BM + 4 (BN + 4), chosen
+    // where the source groups run along rows (columns), so that every group
+    // is one contiguous 16-byte LDS write.
+    template <int LDK, bool KA, bool KB, class Store>
     __device__ __forceinline__ void store(int tid, Store&& st) const
     {
+        constexpr int LDM = BM + 4, LDN = BN + 4;
 #pragma unroll
         for (int u = 0; u < NA; ++u) {
             const int g = tid + u * 256;
             if (g >= GA) continue;
 #pragma unroll
             for (int e = 0; e < 4; ++e) {
-                const int idx = (OPA == OP_N) ? (g / KQ) * LDK + (g % KQ) * 4 + e
-                                              : ((g % (BM / 4)) * 4 + e) * LDK + g / (BM / 4);
+                int idx;
+                if (OPA == OP_N)
+                    idx = KA ? ((g % KQ) * 4 + e) * LDM + g / KQ : (g / KQ) * LDK + (g % KQ) * 4 + e;
+                else
+                    idx = KA ? (g / (BM / 4)) * LDM + (g % (BM / 4)) * 4 + e
+                             : ((g % (BM / 4)) * 4 + e) * LDK + g / (BM / 4);
                 st.a(idx, (&a[u].r.x)[e], (&a[u].i.x)[e]);
             }
         }
@@ -190,8 +199,12 @@ struct PanelLoader {
             if (g >= GB) continue;
 #pragma unroll
             for (int e = 0; e < 4; ++e) {
-                const int idx = (OPB == OP_N) ? ((g % (BN / 4)) * 4 + e) * LDK + g / (BN / 4)
-                                              : (g / KQ) * LDK + (g % KQ) * 4 + e;
+                int idx;
+                if (OPB == OP_N)
+                    idx = KB ? (g / (BN / 4)) * LDN + (g % (BN / 4)) * 4 + e
+                             : ((g % (BN / 4)) * 4 + e) * LDK + g / (BN / 4);
+                else
+                    idx = KB ? ((g % KQ) * 4 + e) * LDN + g / KQ : (g / KQ) * LDK + (g % KQ) * 4 + e;
                 st.b(idx, (&b[u].r.x)[e], (&b[u].i.x)[e]);
             }
         }
@@ -245,10 +258,15 @@ __device__ __forceinline__ void xcd_tile(int& x, int& y, int& z)
 
 // FP32 LDS footprint of one workgroup tile: double-buffered re/im panels of
 // BK columns of the inner dimension
+template <int R, int BK>
+constexpr int panel_floats()  // one plane of an R x BK panel, row-major or k-major
+{
+    return R * (BK + 4) > BK * (R + 4) ? R * (BK + 4) : BK * (R + 4);
+}
 template <class T, int BK = 16>
 constexpr int f32_smem_floats()
 {
-    return 2 * 2 * (T::BM + T::BN) * (BK + 4);
+    return 2 * 2 * (panel_floats<T::BM, BK>() + panel_floats<T::BN, BK>());
 }
 
 // One BM x BN output tile of slice s at (m0, n0); smem holds
@@ -259,12 +277,15 @@ __device__ __forceinline__ void cgemm_f32_tile(const CgemmArgs& p, int slice, in
 {
     constexpr int BM = T::BM, BN = T::BN, TM = T::TM, TN = T::TN;
     constexpr int LDK = BK + 4;
+    // k-major panels where the source runs along the output dimension
+    constexpr bool KA = OPA == OP_C, KB = OPB == OP_N;
+    constexpr int LDM = BM + 4, LDN = BN + 4;
     static_assert(BK % 16 == 0, "16-column MFMA k groups");
-    typedef float PanelA[BM * LDK];
-    typedef float PanelB[BN * LDK];
+    typedef float PanelA[panel_floats<BM, BK>()];
+    typedef float PanelB[panel_floats<BN, BK>()];
     PanelA* sAr = reinterpret_cast<PanelA*>(smem);
     PanelA* sAi = sAr + 2;
-    PanelB* sBr = reinterpret_cast<PanelB*>(smem + 4 * BM * LDK);
+    PanelB* sBr = reinterpret_cast<PanelB*>(smem + 4 * panel_floats<BM, BK>());
     PanelB* sBi = sBr + 2;
 
     const SliceView v = slice_view(p, slice, kp);
@@ -285,7 +306,7 @@ __device__ __forceinline__ void cgemm_f32_tile(const CgemmArgs& p, int slice, in
     const int nk = (v.K - v.K0 + BK - 1) / BK;
     if (nk > 0) {
         ld.load(v, p, m0, n0, v.K0, tid);
-        ld.template store<LDK>(tid, StoreF32{sAr[0], sAi[0], sBr[0], sBi[0]});
+        ld.template store<LDK, KA, KB>(tid, StoreF32{sAr[0], sAi[0], sBr[0], sBi[0]});
     }
     __syncthreads();
     for (int c = 0; c < nk; ++c) {
@@ -297,13 +318,25 @@ __device__ __forceinline__ void cgemm_f32_tile(const CgemmArgs& p, int slice, in
         float4 fa_r[TM], fa_i[TM], fb_r[TN], fb_i[TN];
 #pragma unroll
         for (int t = 0; t < TM; ++t) {
-            fa_r[t] = *reinterpret_cast<const float4*>(&sAr[cur][(wr + 16 * t + r16) * LDK + 16 * kh + 4 * g]);
-            fa_i[t] = *reinterpret_cast<const float4*>(&sAi[cur][(wr + 16 * t + r16) * LDK + 16 * kh + 4 * g]);
+            if (KA) {  // four reads of 16 consecutive rows each
+                const int o = (16 * kh + 4 * g) * LDM + wr + 16 * t + r16;
+                fa_r[t] = float4{sAr[cur][o], sAr[cur][o + LDM], sAr[cur][o + 2 * LDM], sAr[cur][o + 3 * LDM]};
+                fa_i[t] = float4{sAi[cur][o], sAi[cur][o + LDM], sAi[cur][o + 2 * LDM], sAi[cur][o + 3 * LDM]};
+            } else {
+                fa_r[t] = *reinterpret_cast<const float4*>(&sAr[cur][(wr + 16 * t + r16) * LDK + 16 * kh + 4 * g]);
+                fa_i[t] = *reinterpret_cast<const float4*>(&sAi[cur][(wr + 16 * t + r16) * LDK + 16 * kh + 4 * g]);
+            }
         }
 #pragma unroll
         for (int t = 0; t < TN; ++t) {
-            fb_r[t] = *reinterpret_cast<const float4*>(&sBr[cur][(wc + 16 * t + r16) * LDK + 16 * kh + 4 * g]);
-            fb_i[t] = *reinterpret_cast<const float4*>(&sBi[cur][(wc + 16 * t + r16) * LDK + 16 * kh + 4 * g]);
+            if (KB) {
+                const int o = (16 * kh + 4 * g) * LDN + wc + 16 * t + r16;
+                fb_r[t] = float4{sBr[cur][o], sBr[cur][o + LDN], sBr[cur][o + 2 * LDN], sBr[cur][o + 3 * LDN]};
+                fb_i[t] = float4{sBi[cur][o], sBi[cur][o + LDN], sBi[cur][o + 2 * LDN], sBi[cur][o + 3 * LDN]};
+            } else {
+                fb_r[t] = *reinterpret_cast<const float4*>(&sBr[cur][(wc + 16 * t + r16) * LDK + 16 * kh + 4 * g]);
+                fb_i[t] = *reinterpret_cast<const float4*>(&sBi[cur][(wc + 16 * t + r16) * LDK + 16 * kh + 4 * g]);
+            }
         }
         if (v.real) {
 #pragma unroll
@@ -338,7 +371,7 @@ __device__ __forceinline__ void cgemm_f32_tile(const CgemmArgs& p, int slice, in
             }
         }
         }
-        if (c + 1 < nk) ld.template store<LDK>(tid, StoreF32{sAr[cur ^ 1], sAi[cur ^ 1], sBr[cur ^ 1], sBi[cur ^ 1]});
+        if (c + 1 < nk) ld.template store<LDK, KA, KB>(tid, StoreF32{sAr[cur ^ 1], sAi[cur ^ 1], sBr[cur ^ 1], sBi[cur ^ 1]});
         __syncthreads();
     }
     write_tile<T>(v, p, m0, n0, wr, wc, lane, accr, acci);
@@ -481,7 +514,7 @@ __global__ __launch_bounds__(256) void k_cgemm_bf16(CgemmArgs p)
     if (nk > 0) {
         ld.load(v, p, m0, n0, 0, tid);
         const StoreBF16 st = storer(0);
-        ld.template store<LDK>(tid, StoreAdapter<StoreBF16>{st});
+        ld.template store<LDK, false, false>(tid, StoreAdapter<StoreBF16>{st});
     }
     __syncthreads();
     for (int c = 0; c < nk; ++c) {
@@ -525,7 +558,7 @@ __global__ __launch_bounds__(256) void k_cgemm_bf16(CgemmArgs p)
         }
         if (c + 1 < nk) {
             const StoreBF16 st = storer(cur ^ 1);
-            ld.template store<LDK>(tid, StoreAdapter<StoreBF16>{st});
+            ld.template store<LDK, false, false>(tid, StoreAdapter<StoreBF16>{st});
         }
         __syncthreads();
     }
