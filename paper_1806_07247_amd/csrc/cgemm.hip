@@ -293,13 +293,21 @@ __device__ __forceinline__ void cgemm_f32_tile(const CgemmArgs& p, int slice, in
     const int wr = (wave / T::WGN) * T::WM, wc = (wave % T::WGN) * T::WN;
     const int g = lane >> 4, r16 = lane & 15;
 
-    floatx4 accr[TM][TN], acci[TM][TN];
+    // Complex products: tiles with few MFMA sub-tiles per wavefront use the
+    // three-product form p1 = Ar Br, p2 = Ai Bi, p3 = (Ar + Ai)(Br + Bi),
+    // Cr = p1 - p2, Ci = p3 - p1 - p2 (3 real MFMAs per step instead of 4);
+    // larger tiles, whose accumulators would not fit the registers three
+    // times, keep the four-product form (p1 = Cr, p3 = Ci, p2 unused).
+    // Real slices: p1 only.
+    constexpr bool M3 = TM * TN <= 4;
+    floatx4 p1[TM][TN], p2[TM][TN], p3[TM][TN];
 #pragma unroll
     for (int ti = 0; ti < TM; ++ti)
 #pragma unroll
         for (int tj = 0; tj < TN; ++tj) {
-            accr[ti][tj] = floatx4{0.f, 0.f, 0.f, 0.f};
-            acci[ti][tj] = floatx4{0.f, 0.f, 0.f, 0.f};
+            p1[ti][tj] = floatx4{0.f, 0.f, 0.f, 0.f};
+            p2[ti][tj] = floatx4{0.f, 0.f, 0.f, 0.f};
+            p3[ti][tj] = floatx4{0.f, 0.f, 0.f, 0.f};
         }
 
     PanelLoader<OPA, OPB, BM, BN, BK> ld;
@@ -345,11 +353,37 @@ __device__ __forceinline__ void cgemm_f32_tile(const CgemmArgs& p, int slice, in
                 for (int ti = 0; ti < TM; ++ti)
 #pragma unroll
                     for (int tj = 0; tj < TN; ++tj)
-                        accr[ti][tj] = __builtin_amdgcn_mfma_f32_16x16x4f32(
-                            (&fa_r[ti].x)[s], (&fb_r[tj].x)[s], accr[ti][tj], 0, 0, 0);
+                        p1[ti][tj] = __builtin_amdgcn_mfma_f32_16x16x4f32(
+                            (&fa_r[ti].x)[s], (&fb_r[tj].x)[s], p1[ti][tj], 0, 0, 0);
+        } else if (M3) {
+            // three passes over the tiles: the products into one accumulator
+            // are TM TN independent MFMAs apart
+#pragma unroll
+            for (int s = 0; s < 4; ++s) {
+#pragma unroll
+                for (int ti = 0; ti < TM; ++ti)
+#pragma unroll
+                    for (int tj = 0; tj < TN; ++tj)
+                        p1[ti][tj] = __builtin_amdgcn_mfma_f32_16x16x4f32((&fa_r[ti].x)[s], (&fb_r[tj].x)[s],
+                                                                          p1[ti][tj], 0, 0, 0);
+#pragma unroll
+                for (int ti = 0; ti < TM; ++ti)
+#pragma unroll
+                    for (int tj = 0; tj < TN; ++tj)
+                        p2[ti][tj] = __builtin_amdgcn_mfma_f32_16x16x4f32((&fa_i[ti].x)[s], (&fb_i[tj].x)[s],
+                                                                          p2[ti][tj], 0, 0, 0);
+#pragma unroll
+                for (int ti = 0; ti < TM; ++ti) {
+                    const float as = (&fa_r[ti].x)[s] + (&fa_i[ti].x)[s];
+#pragma unroll
+                    for (int tj = 0; tj < TN; ++tj)
+                        p3[ti][tj] = __builtin_amdgcn_mfma_f32_16x16x4f32(
+                            as, (&fb_r[tj].x)[s] + (&fb_i[tj].x)[s], p3[ti][tj], 0, 0, 0);
+                }
+            }
         } else {
-            // two passes over the tiles, so that the two products into one
-            // accumulator are 2 TM TN independent MFMAs apart
+            // four-product form in two passes over the tiles (2 TM TN
+            // independent MFMAs between the products into one accumulator)
 #pragma unroll
             for (int s = 0; s < 4; ++s) {
 #pragma unroll
@@ -357,16 +391,16 @@ __device__ __forceinline__ void cgemm_f32_tile(const CgemmArgs& p, int slice, in
 #pragma unroll
                     for (int tj = 0; tj < TN; ++tj) {
                         const float ar = (&fa_r[ti].x)[s];
-                        accr[ti][tj] = __builtin_amdgcn_mfma_f32_16x16x4f32(ar, (&fb_r[tj].x)[s], accr[ti][tj], 0, 0, 0);
-                        acci[ti][tj] = __builtin_amdgcn_mfma_f32_16x16x4f32(ar, (&fb_i[tj].x)[s], acci[ti][tj], 0, 0, 0);
+                        p1[ti][tj] = __builtin_amdgcn_mfma_f32_16x16x4f32(ar, (&fb_r[tj].x)[s], p1[ti][tj], 0, 0, 0);
+                        p3[ti][tj] = __builtin_amdgcn_mfma_f32_16x16x4f32(ar, (&fb_i[tj].x)[s], p3[ti][tj], 0, 0, 0);
                     }
 #pragma unroll
                 for (int ti = 0; ti < TM; ++ti)
 #pragma unroll
                     for (int tj = 0; tj < TN; ++tj) {
                         const float ai = (&fa_i[ti].x)[s];
-                        accr[ti][tj] = __builtin_amdgcn_mfma_f32_16x16x4f32(-ai, (&fb_i[tj].x)[s], accr[ti][tj], 0, 0, 0);
-                        acci[ti][tj] = __builtin_amdgcn_mfma_f32_16x16x4f32(ai, (&fb_r[tj].x)[s], acci[ti][tj], 0, 0, 0);
+                        p1[ti][tj] = __builtin_amdgcn_mfma_f32_16x16x4f32(-ai, (&fb_i[tj].x)[s], p1[ti][tj], 0, 0, 0);
+                        p3[ti][tj] = __builtin_amdgcn_mfma_f32_16x16x4f32(ai, (&fb_r[tj].x)[s], p3[ti][tj], 0, 0, 0);
                     }
             }
         }
@@ -374,6 +408,14 @@ __device__ __forceinline__ void cgemm_f32_tile(const CgemmArgs& p, int slice, in
         if (c + 1 < nk) ld.template store<LDK, KA, KB>(tid, StoreF32{sAr[cur ^ 1], sAi[cur ^ 1], sBr[cur ^ 1], sBi[cur ^ 1]});
         __syncthreads();
     }
+    floatx4 accr[TM][TN], acci[TM][TN];
+#pragma unroll
+    for (int ti = 0; ti < TM; ++ti)
+#pragma unroll
+        for (int tj = 0; tj < TN; ++tj) {
+            accr[ti][tj] = M3 ? p1[ti][tj] - p2[ti][tj] : p1[ti][tj];
+            acci[ti][tj] = M3 ? p3[ti][tj] - p1[ti][tj] - p2[ti][tj] : p3[ti][tj];
+        }
     write_tile<T>(v, p, m0, n0, wr, wc, lane, accr, acci);
 }
 
