@@ -674,6 +674,9 @@ int pick_variant(const CgemmArgs& a)
     if (a.n <= 16) return 5;
     if (a.n <= 32) return 4;
     if (a.n <= 48) return 6;
+    // short inner dimensions (rank-L reconstructions) stay on 64 x 64, whose
+    // higher occupancy overlaps the output writes (measured faster)
+    if (a.k < 128) return 1;
     if (a.m >= 256 && a.n >= 256 && tiles(a.m, a.n, 128, 128, a.nslices) >= 2048) return 2;
     if (a.m >= 128 && tiles(a.m, a.n, 128, 64, a.nslices) >= 2048) return 3;
     return 1;

@@ -179,6 +179,7 @@ __global__ __launch_bounds__(kCholThreads) void k_chol(const double2* __restrict
     double2* R = sh;            // L x L (R, for the Rtot product)
     double2* X = sh + L * L;    // L x L (Rtot)
     __shared__ double2 rowG[2][kMaxL], rowM[2][kMaxL];
+    __shared__ double2 piv[2];  // (R_jj, 1 / R_jj) of the published row
     __shared__ double diag[kMaxL];
     const int s = blockIdx.x, tid = threadIdx.x, nt = blockDim.x;
     const int la = lact[s];
@@ -223,25 +224,35 @@ __global__ __launch_bounds__(kCholThreads) void k_chol(const double2* __restrict
         for (int a = 0; a < la; ++a) tr += diag[a];
         sd = 1e-13 * tr / la;
     }
+    // the owner of diagonal entry (j, j) forms the pivot of step j once, when
+    // it publishes row j (inactive rows: pivot 1)
+    bool broke = false;
+    auto pivot = [&](int j, double d, int buf) {
+        double p = j < la ? d : 1.0;
+        if (!(p > 0.0)) {
+            p = 1e-300;
+            broke = true;
+        }
+        const double r = sqrt(p);
+        piv[buf] = make_double2(r, 1.0 / r);
+    };
 #pragma unroll
     for (int u = 0; u < kCholEntries; ++u) {
         if (ea[u] == eb[u] && ea[u] < la) gr[u] += sd;
         if (ea[u] == 0) {  // publish row 0
             rowG[0][eb[u]] = make_double2(gr[u], gi[u]);
-            if (eb[u] == 0) rowM[0][0] = make_double2(mr[u], mi[u]);
+            if (eb[u] == 0) {
+                rowM[0][0] = make_double2(mr[u], mi[u]);
+                pivot(0, gr[u], 0);
+            }
         }
     }
     __syncthreads();
-    bool broke = false;
     for (int j = 0; j < L; ++j) {
         const int cur = j & 1, nxt = cur ^ 1;
         const bool act = j < la;
-        double p = act ? rowG[cur][j].x : 1.0;
-        if (!(p > 0.0)) {
-            p = 1e-300;
-            broke = true;
-        }
-        const double rjj = sqrt(p), inv = 1.0 / rjj;
+        const double2 pv = piv[cur];
+        const double rjj = pv.x, inv = pv.y;
 #pragma unroll
         for (int u = 0; u < kCholEntries; ++u) {
             const int a = ea[u], b = eb[u];
@@ -279,12 +290,13 @@ __global__ __launch_bounds__(kCholThreads) void k_chol(const double2* __restrict
                 if (a == j + 1) {  // publish row j+1 for the next step
                     if (b >= a) rowG[nxt][b] = make_double2(gr[u], gi[u]);
                     if (b <= a) rowM[nxt][b] = make_double2(mr[u], mi[u]);
+                    if (b == a) pivot(a, gr[u], nxt);
                 }
             }
         }
         __syncthreads();
     }
-    if (broke && tid == 0 && status) status[s] = 1;
+    if (broke && status) status[s] = 1;  // by the owners of the failed pivots
     // Rinv = M^*: entry (a, b) of M gives Rinv(b, a); Rinv(b, a) = 0 for b > a
 #pragma unroll
     for (int u = 0; u < kCholEntries; ++u) {
