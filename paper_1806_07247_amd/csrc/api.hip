@@ -205,15 +205,16 @@ tp::Arena learned_arena(void* ws, size_t bytes, int n1, int n2, int n3, int Lw, 
     t.kpart = reinterpret_cast<float*>(ar.take<char>(t.kpart_bytes));
     t.fro2 = ar.take<double>(h);
     t.feats = ar.take<float>(h * TP_MLP_INPUTS);
-    t.kpred = ar.take<int>(h);
-    t.lact = ar.take<int>(h);
+    // kpred, lact and prefb adjacent: the host reads them with one copy
+    t.kpred = ar.take<int>(3 * h);
+    t.lact = t.kpred + h;
+    t.prefb = t.kpred + 2 * h;
     t.fb = ar.take<int>(h);
     t.rank = ar.take<int>(h);
     t.status = ar.take<int>(h);
     t.idx = ar.take<int>(h);
     t.cinfo = ar.take<int>(h);
     t.crank = ar.take<int>(h);
-    t.prefb = ar.take<int>(h);
     t.bad = ar.take<int>(h);
     if (out) *out = t;
     return ar;
@@ -624,12 +625,13 @@ int tp_prox_tnn_learned(const float* Y, float* X, int n1, int n2, int n3, float 
               tp::launch_predict(opts->mlp, W.feats, h, p, opts->fixed_rank, opts->oversample, opts->max_rank,
                                  W.kpred, W.lact, W.prefb, rk, s));
     TP_TRY(hipMemsetAsync(W.status, 0, h * sizeof(int), s));
-    std::vector<int> hl(h), hpre(h), hbad(h), hfb(h), hk(h);
-    TP_TRY(hipMemcpyAsync(hl.data(), W.lact, h * sizeof(int), hipMemcpyDeviceToHost, s));
-    TP_TRY(hipMemcpyAsync(hpre.data(), W.prefb, h * sizeof(int), hipMemcpyDeviceToHost, s));
-    TP_TRY(hipMemcpyAsync(hk.data(), W.kpred, h * sizeof(int), hipMemcpyDeviceToHost, s));
+    std::vector<int> hbad(h), hfb(h), hkl(3 * h);
+    TP_TRY(hipMemcpyAsync(hkl.data(), W.kpred, 3 * h * sizeof(int), hipMemcpyDeviceToHost, s));
     TP_TRY(hipStreamSynchronize(s));
+    int *hk = hkl.data(), *hl = hk + h;
+    const int* hpre = hk + 2 * h;
     int st = TP_OK;
+    bool fb_known = false;  // hfb holds the current fallback flags
     for (int attempt = 0; attempt < 2; ++attempt) {
     // sketch width of this attempt: the widest l, rounded up to 8
     int lmax = 0;
@@ -645,8 +647,7 @@ int tp_prox_tnn_learned(const float* Y, float* X, int n1, int n2, int n3, float 
                 hl[k] = std::min(L, p);
                 hk[k] = std::max(hk[k], hl[k] - opts->oversample);
             }
-        TP_TRY(hipMemcpyAsync(W.kpred, hk.data(), h * sizeof(int), hipMemcpyHostToDevice, s));
-        TP_TRY(hipMemcpyAsync(W.lact, hl.data(), h * sizeof(int), hipMemcpyHostToDevice, s));
+        TP_TRY(hipMemcpyAsync(W.kpred, hk, 2 * h * sizeof(int), hipMemcpyHostToDevice, s));  // kpred, lact
     }
 
     if (L == 0) {  // every slice goes to the full SVD
@@ -754,6 +755,7 @@ int tp_prox_tnn_learned(const float* Y, float* X, int n1, int n2, int n3, float 
     // slices identically)
     TP_TRY(hipMemcpyAsync(hfb.data(), fb, h * sizeof(int), hipMemcpyDeviceToHost, s));
     TP_TRY(hipStreamSynchronize(s));
+    fb_known = true;
     const int kwide = std::min(std::max(opts->max_rank - opts->oversample, 0), p);
     const int lwide = std::min(kwide + opts->oversample, p);
     bool retry = false;
@@ -764,11 +766,14 @@ int tp_prox_tnn_learned(const float* Y, float* X, int n1, int n2, int n3, float 
             retry = true;
         }
     if (!retry) break;
+    fb_known = false;
     }
     // fallback slices: full SVD on a compact batch
     std::vector<int> hidx;
-    TP_TRY(hipMemcpyAsync(hfb.data(), fb, h * sizeof(int), hipMemcpyDeviceToHost, s));
-    TP_TRY(hipStreamSynchronize(s));
+    if (!fb_known) {
+        TP_TRY(hipMemcpyAsync(hfb.data(), fb, h * sizeof(int), hipMemcpyDeviceToHost, s));
+        TP_TRY(hipStreamSynchronize(s));
+    }
     for (int k = 0; k < h; ++k)
         if (hfb[k]) hidx.push_back(k);
     const int cnt = (int)hidx.size();
