@@ -51,6 +51,8 @@ def _load():
         "or_tubalrank": (_I, [_D, _I, _I, _I, ctypes.c_double, ctypes.c_double]),
         "or_prox_tnn": (_I, [_D, _I, _I, _I, ctypes.c_double, _D]),
         "or_svt_real": (_I, [_D, _I, _I, ctypes.c_double, _D]),
+        "or_trpca": (_I, [_D, _I, _I, _I, ctypes.c_double, ctypes.c_double, ctypes.c_double, ctypes.c_double,
+                          ctypes.c_double, _I, _D, _D, _D, ctypes.POINTER(ctypes.c_int)]),
     }
     U32 = ctypes.POINTER(ctypes.c_uint)
     IP = ctypes.POINTER(ctypes.c_int)
@@ -233,6 +235,23 @@ def prox_tnn(Y, tau):
     if rc < 0:
         raise ValueError("tau must be >= 0")
     return X
+
+
+def trpca(X, lam=None, mu=1e-3, rho=1.1, mu_max=1e10, tol=1e-5, max_iter=500):
+    """Tensor robust PCA by the inexact ALM around prox_tnn, in FP64.
+    lam defaults to 1/sqrt(max(n1, n2) n3).  Returns dict(L, S, Lam, iters,
+    converged)."""
+    X = _real(X)
+    n1, n2, n3 = X.shape
+    if lam is None:
+        lam = 1.0 / np.sqrt(max(n1, n2) * n3)
+    L, S, Lam = np.empty_like(X), np.empty_like(X), np.empty_like(X)
+    it = ctypes.c_int(0)
+    rc = _load().or_trpca(_dp(X), n1, n2, n3, float(lam), float(mu), float(rho), float(mu_max), float(tol),
+                          int(max_iter), _dp(L), _dp(S), _dp(Lam), ctypes.byref(it))
+    if rc < 0:
+        raise ValueError("bad TRPCA argument")
+    return dict(L=L, S=S, Lam=Lam, iters=it.value, converged=bool(rc))
 
 
 def svt_real(M, tau):

@@ -609,3 +609,60 @@ int or_svt_real(const double* M, int m, int n, double tau, double* out)
     free(w);
     return rc;
 }
+
+/* ------------------------------------------------------------------------ */
+/* Tensor robust PCA by the inexact augmented Lagrangian method             */
+/* ------------------------------------------------------------------------ */
+/*
+ * The problem the paper names as the use of the prox of Theorem 2.3:
+ *   min ||L||_* + lam ||S||_1  s.t.  L + S = X   (||.||_* the TNN, Def 2.9).
+ * The paper states no algorithm for it; this is the standard inexact ALM
+ * (alternating minimisation of the augmented Lagrangian
+ * ||L||_* + lam ||S||_1 + <Lam, L + S - X> + mu/2 ||L + S - X||_F^2, then a
+ * multiplier step), with the stopping test and the relative tolerance the
+ * GPU driver uses:
+ *   L' = prox_tnn(X - S - Lam/mu, 1/mu)           (eq (19), Theorem 2.3)
+ *   S' = soft(X - L' - Lam/mu, lam/mu)            (entrywise shrinkage)
+ *   R  = L' + S' - X;  Lam <- Lam + mu R;  mu <- min(rho mu, mu_max)
+ *   stop when max(max|L' - L|, max|S' - S|, max|R|) <= tol max(1, max|X|).
+ * Returns 1 when the test was met within max_iter iterations, 0 otherwise,
+ * negative on a bad argument; *iters receives the iterations run.
+ */
+int or_trpca(const double* X, int n1, int n2, int n3, double lam, double mu, double rho, double mu_max,
+             double tol, int max_iter, double* L, double* S, double* Lam, int* iters)
+{
+    if (n1 < 1 || n2 < 1 || n3 < 1 || !(lam > 0.0) || !(mu > 0.0) || !(rho >= 1.0) || max_iter < 1) return -1;
+    const i64 n = (i64)n1 * n2 * n3;
+    double* Y = (double*)xmalloc((size_t)n * sizeof(double));
+    double* Ln = (double*)xmalloc((size_t)n * sizeof(double));
+    double scale = 1.0;
+    for (i64 e = 0; e < n; ++e) {
+        L[e] = S[e] = Lam[e] = 0.0;
+        if (fabs(X[e]) > scale) scale = fabs(X[e]);
+    }
+    int converged = 0, it = 0;
+    while (it < max_iter && !converged) {
+        ++it;
+        for (i64 e = 0; e < n; ++e) Y[e] = X[e] - S[e] - Lam[e] / mu;
+        or_prox_tnn(Y, n1, n2, n3, 1.0 / mu, Ln);
+        double dl = 0.0, ds = 0.0, dr = 0.0;
+        const double thr = lam / mu;
+        for (i64 e = 0; e < n; ++e) {
+            const double r = X[e] - Ln[e] - Lam[e] / mu;
+            const double sn = r > thr ? r - thr : (r < -thr ? r + thr : 0.0);
+            const double res = Ln[e] + sn - X[e];
+            dl = fmax(dl, fabs(Ln[e] - L[e]));
+            ds = fmax(ds, fabs(sn - S[e]));
+            dr = fmax(dr, fabs(res));
+            Lam[e] += mu * res;
+            L[e] = Ln[e];
+            S[e] = sn;
+        }
+        mu = fmin(rho * mu, mu_max);
+        converged = fmax(dl, fmax(ds, dr)) <= tol * scale;
+    }
+    free(Y);
+    free(Ln);
+    if (iters) *iters = it;
+    return converged;
+}

@@ -83,6 +83,13 @@ double or_tsn(const double* A, int n1, int n2, int n3);
 int or_tubalrank(const double* A, int n1, int n2, int n3, double tol, double eps);
 /* Theorem 2.3 / Algorithm 3: Prox of the TNN at tau. */
 int or_prox_tnn(const double* Y, int n1, int n2, int n3, double tau, double* X);
+/* Tensor robust PCA, min ||L||_* + lam ||S||_1 s.t. L + S = X, by the inexact
+ * augmented Lagrangian method around or_prox_tnn (the paper names the problem
+ * but gives no algorithm; the steps are listed in tp_oracle.c).  L, S, Lam
+ * are outputs (n1*n2*n3 each); returns 1 if converged, 0 if not, < 0 on a bad
+ * argument; *iters = iterations run. */
+int or_trpca(const double* X, int n1, int n2, int n3, double lam, double mu, double rho, double mu_max,
+             double tol, int max_iter, double* L, double* S, double* Lam, int* iters);
 /* matrix singular value thresholding U (S - tau)_+ V^* of a real m x n matrix */
 int or_svt_real(const double* M, int m, int n, double tau, double* out);
 
