@@ -250,6 +250,51 @@ int tp_mlp_adam(float* params, const float* grad, float* m, float* v, int step, 
                 float beta2, float eps, void* stream);
 
 /*
+ * Tensor robust PCA, the recovery problem the paper names as the use of the
+ * TNN and its prox (Section 1; eq (19) and Theorem 2.3):
+ *   min ||L||_* + lambda ||S||_1   s.t.   L + S = X
+ * (||.||_* the TNN of Definition 2.9).  The paper gives no algorithm for it;
+ * this is the inexact augmented Lagrangian method, one prox per iteration:
+ *   L' = prox_tnn(X - S - Lam/mu, 1/mu)       (tp_prox_tnn, or the learned-rank
+ *                                               prox with `learned`)
+ *   S' = sign(r) max(|r| - lambda/mu, 0),  r = X - L' - Lam/mu
+ *   Lam <- Lam + mu (L' + S' - X);  mu <- min(rho mu, mu_max)
+ * until max(max|L' - L|, max|S' - S|, max|L' + S' - X|) <= tol max(1, max|X|)
+ * (a relative tolerance: FP32 data cannot reach the absolute 1e-8 customary
+ * in double precision) or max_iter iterations.  Everything but the prox is
+ * one fused pass over the entries per iteration.
+ *   X          device, n1 x n2 x n3 (read only)
+ *   L, S       device, n1 x n2 x n3 (outputs; overwritten from zero)
+ *   Lam        device n1 x n2 x n3 or NULL: the final multiplier (the
+ *              workspace holds it when NULL)
+ *   iters, converged   host ints or NULL: iterations run; 1 if the
+ *              stopping test was met
+ *   opts       required.  lambda <= 0 selects 1/sqrt(max(n1, n2) n3).
+ *              learned NULL: the full-SVD prox (Algorithm 3).  Otherwise the
+ *              learned-rank prox with those settings; the driver chains its
+ *              calls itself (the previous call's counts and singular values
+ *              as features, its range basis as warm start, seed + i for call
+ *              i), so learned->prev_rank, prev_sigma, warm_basis, warm_cols,
+ *              basis_out and basis_cols_out are ignored.
+ * Errors: TP_ERR_ARG (null pointers, mu <= 0, rho < 1, mu_max < mu or
+ * infinite, tol < 0, max_iter < 1, a learned max_rank outside 1..64, a NaN
+ * in X), TP_ERR_SHAPE, TP_ERR_WORKSPACE, or the prox's error.  The call waits
+ * for the stream once per iteration (the stopping test is read on the host).
+ */
+typedef struct tp_trpca_opts {
+    float lambda;                   /* <= 0: 1/sqrt(max(n1, n2) n3) */
+    float mu;                       /* initial penalty (1e-3) */
+    float rho;                      /* penalty growth per iteration (1.1) */
+    float mu_max;                   /* penalty cap (1e10) */
+    float tol;                      /* relative stopping tolerance (1e-5) */
+    int max_iter;                   /* iteration cap (500) */
+    const tp_learned_opts* learned; /* NULL: full-SVD prox; else learned-rank prox settings */
+} tp_trpca_opts;
+size_t tp_trpca_workspace_size(int n1, int n2, int n3, const tp_trpca_opts* opts);
+int tp_trpca(const float* X, float* L, float* S, int n1, int n2, int n3, const tp_trpca_opts* opts, float* Lam,
+             int* iters, int* converged, void* workspace, size_t workspace_bytes, void* stream);
+
+/*
  * Tensor nuclear norm (Definition 2.9 with eq (14)):
  *   ||A||_* = sum_i S(i,i,1) = (1/n3) sum_k sum_i sigma_i(Abar^(k)),
  * summed over all n3 slices through the conjugate symmetry of eq (8) (the
@@ -375,7 +420,7 @@ int tp_get_param(int key);
  * last collect (or a negative tp_status) and forgets them.
  * Kernel ids: 0 rfft, 1 irfft, 2 cgemm, 3 jacobi, 4 shrink, 5 tnn_reduce,
  * 6 tsvd_finish, 7 features, 8 predict, 9 sketch, 10 cholqr, 11 rsvd_check,
- * 12 gather, 13 mlp, 14 accuracy, 15 tensor_op.
+ * 12 gather, 13 mlp, 14 accuracy, 15 tensor_op, 16 trpca.
  * tp_trace_collect_work also writes, per launch, the algorithmic work the
  * library assigns to it (host arrays, either may be NULL): for the slice
  * products 8 m n k flops per complex slice and 2 m n k per real one, and the

@@ -188,6 +188,44 @@ def tp_prox_tnn_learned(Y, tau, mlp=None, fixed_rank=0, prev_rank=None, prev_sig
     return X
 
 
+def tp_trpca(X, lam=None, mu=1e-3, rho=1.1, mu_max=1e10, tol=1e-5, max_iter=500, learned=None, L=None, S=None,
+             Lam=None, workspace=None):
+    """Tensor robust PCA (include/tp.h): min ||L||_* + lam ||S||_1 s.t. L + S = X
+    by the inexact ALM, natively.  learned: None for the full-SVD prox, else a
+    dict of tp_prox_tnn_learned settings (mlp, fixed_rank, oversample,
+    power_iters, max_rank, seed, accuracy, max_power_iters, retry_wide,
+    accuracy_ref).  Returns dict(L, S, Lam (if given), iters, converged)."""
+    lib = _lib.load()
+    X = _dev_tensor(X, "X")
+    n1, n2, n3 = X.shape
+    for t, name in ((L, "L"), (S, "S"), (Lam, "Lam")):
+        if t is not None and (tuple(t.shape) != tuple(X.shape) or t.dtype != torch.float32 or not t.is_contiguous()
+                              or not t.is_cuda):
+            raise ValueError(f"{name} must be a contiguous float32 device tensor shaped like X")
+    Lo = L if L is not None else torch.empty_like(X)
+    So = S if S is not None else torch.empty_like(X)
+    lo = None
+    if learned is not None:
+        d = dict(mlp=None, fixed_rank=0, oversample=10, power_iters=2, max_rank=64, seed=0, accuracy=2e-5,
+                 max_power_iters=8, retry_wide=True, accuracy_ref=0)
+        d.update(learned)
+        lo = _lib.LearnedOpts(_ptr(d["mlp"]), int(d["fixed_rank"]), None, None, int(d["oversample"]),
+                              int(d["power_iters"]), int(d["max_rank"]), int(d["seed"]) & 0xFFFFFFFFFFFFFFFF,
+                              float(d["accuracy"]), int(d["max_power_iters"]), int(bool(d["retry_wide"])),
+                              int(d["accuracy_ref"]), None, None, None, None)
+    opts = _lib.TrpcaOpts(float(lam) if lam is not None else 0.0, float(mu), float(rho), float(mu_max), float(tol),
+                          int(max_iter), ctypes.pointer(lo) if lo is not None else None)
+    ws_bytes = lib.tp_trpca_workspace_size(n1, n2, n3, ctypes.byref(opts))
+    if ws_bytes == 0:
+        raise ValueError("bad TRPCA settings")
+    ws = workspace if workspace is not None else _workspace(ws_bytes, X.device)
+    it, conv = ctypes.c_int(0), ctypes.c_int(0)
+    st = lib.tp_trpca(X.data_ptr(), Lo.data_ptr(), So.data_ptr(), n1, n2, n3, ctypes.byref(opts), _ptr(Lam),
+                      ctypes.byref(it), ctypes.byref(conv), ws.data_ptr(), ws.numel(), _stream(X.device))
+    _lib.check("tp_trpca", st)
+    return dict(L=Lo, S=So, Lam=Lam, iters=it.value, converged=bool(conv.value))
+
+
 def basis_shape(n2, n3, max_rank=64):
     """Shape of a warm-start basis buffer: (2, half_slices(n3), n2, max_rank)."""
     return (2, half_slices(n3), int(n2), int(max_rank))

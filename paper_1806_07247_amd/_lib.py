@@ -54,6 +54,19 @@ class LearnedOpts(ctypes.Structure):
                 ("basis_out", _VP), ("basis_cols_out", _VP)]
 
 
+class TrpcaOpts(ctypes.Structure):
+    """tp_trpca_opts of include/tp.h"""
+    _fields_ = [("lam", _F), ("mu", _F), ("rho", _F), ("mu_max", _F), ("tol", _F), ("max_iter", _I),
+                ("learned", ctypes.POINTER(LearnedOpts))]
+
+
+SIGNATURES.update({
+    "tp_trpca_workspace_size": (_SZ, [_I, _I, _I, ctypes.POINTER(TrpcaOpts)]),
+    "tp_trpca": (_I, [_VP, _VP, _VP, _I, _I, _I, ctypes.POINTER(TrpcaOpts), _VP, ctypes.POINTER(_I),
+                      ctypes.POINTER(_I), _VP, _SZ, _VP]),
+})
+
+
 SIGNATURES.update({
     "tp_prox_tnn_learned_workspace_size": (_SZ, [_I, _I, _I, _I]),
     "tp_prox_tnn_learned": (_I, [_VP, _VP, _I, _I, _I, _F, ctypes.POINTER(LearnedOpts), _VP, _VP, _VP, _VP, _VP,

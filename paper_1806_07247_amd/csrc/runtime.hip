@@ -37,7 +37,7 @@ hipEvent_t take_event()
 
 const char* const kNames[] = {"rfft",    "irfft",   "cgemm",  "jacobi",     "shrink", "tnn_reduce", "tsvd_finish",
                               "features", "predict", "sketch", "cholqr", "rsvd_check", "gather",     "mlp",
-                              "accuracy", "tensor_op"};
+                              "accuracy", "tensor_op", "trpca"};
 
 }  // namespace
 

@@ -220,7 +220,7 @@ int param(int key);
 enum KernelId {
     K_RFFT = 0, K_IRFFT = 1, K_CGEMM = 2, K_JACOBI = 3, K_SHRINK = 4, K_TNN_REDUCE = 5, K_TSVD_FINISH = 6,
     K_FEATURES = 7, K_PREDICT = 8, K_SKETCH = 9, K_CHOLQR = 10, K_RSVD_CHECK = 11, K_GATHER = 12, K_MLP = 13,
-    K_ACCURACY = 14, K_TENSOR_OP = 15
+    K_ACCURACY = 14, K_TENSOR_OP = 15, K_TRPCA = 16
 };
 
 // Records HIP events around the launches in its scope while tracing is on,

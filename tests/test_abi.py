@@ -109,3 +109,33 @@ def test_batch_plan_validation(lib):
     assert lib.tp_batch_create(ctypes.byref(plan), 0, items, 2, 0, None) == -1
     assert lib.tp_batch_create(ctypes.byref(plan), 1, items, 2, 1, None) == 0  # prox needs no B
     assert lib.tp_batch_destroy(plan) == 0
+
+
+def test_trpca_argument_errors(lib):
+    from paper_1806_07247_amd import _lib
+    ok = _lib.TrpcaOpts(0.0, 1e-3, 1.1, 1e10, 1e-5, 500, None)
+    ws = lib.tp_trpca_workspace_size(6, 5, 4, ctypes.byref(ok))
+    assert ws >= 3 * 6 * 5 * 4 * 4
+    it, conv = ctypes.c_int(0), ctypes.c_int(0)
+
+    def call(opts, n1=6, ws_bytes=ws, x=FAKE):
+        return lib.tp_trpca(x, FAKE, FAKE, n1, 5, 4, opts, None, ctypes.byref(it), ctypes.byref(conv), FAKE,
+                            ws_bytes, None)
+
+    assert call(None) == -1
+    assert call(ctypes.byref(ok), x=None) == -1
+    for bad in (_lib.TrpcaOpts(0.0, 0.0, 1.1, 1e10, 1e-5, 500, None),       # mu <= 0
+                _lib.TrpcaOpts(0.0, 1e-3, 0.9, 1e10, 1e-5, 500, None),      # rho < 1
+                _lib.TrpcaOpts(0.0, 1e-3, 1.1, 1e-4, 1e-5, 500, None),      # mu_max < mu
+                _lib.TrpcaOpts(0.0, 1e-3, 1.1, 1e10, -1.0, 500, None),      # tol < 0
+                _lib.TrpcaOpts(0.0, 1e-3, 1.1, 1e10, 1e-5, 0, None)):       # max_iter < 1
+        assert call(ctypes.byref(bad)) == -1
+        assert lib.tp_trpca_workspace_size(6, 5, 4, ctypes.byref(bad)) == 0
+    lo = _lib.LearnedOpts(None, 5, None, None, 10, 2, 65, 0, 0.0, 8, 1, 0, None, None, None, None)
+    bad_l = _lib.TrpcaOpts(0.0, 1e-3, 1.1, 1e10, 1e-5, 500, ctypes.pointer(lo))  # max_rank > 64
+    assert call(ctypes.byref(bad_l)) == -1
+    assert call(ctypes.byref(ok), n1=0) == -2
+    assert call(ctypes.byref(ok), ws_bytes=ws - 1) == -3
+    lo.max_rank = 16
+    good_l = _lib.TrpcaOpts(0.0, 1e-3, 1.1, 1e10, 1e-5, 500, ctypes.pointer(lo))
+    assert lib.tp_trpca_workspace_size(6, 5, 4, ctypes.byref(good_l)) > ws
