@@ -446,6 +446,60 @@ def batch_block(args, tp, inputs, dev):
 
 
 # --------------------------------------------------------- cpu oracle --
+def trpca_block(args, tp, dev, mlp=None):
+    """Whole TRPCA solves on the learned-rank workload: the native driver
+    (tp_trpca, one fused update pass per iteration) against the Python driver
+    (torch elementwise updates), both with the learned-rank prox."""
+    import torch
+
+    from paper_1806_07247_amd import rank_model, trpca
+
+    n, n3 = 1024, 64
+    X, L0, r = trpca.learned_workload(args.learned_seed, dev, n, n3)
+    if mlp is None:
+        mlp = rank_model.load(device=dev)
+    settings = dict(mlp=mlp, max_rank=64)
+    ws = torch.empty(tp.tp_trpca_workspace_size_for(X.shape, learned=settings), dtype=torch.uint8, device=dev)
+    Lo, So = torch.empty_like(X), torch.empty_like(X)
+
+    def native():
+        return tp.tp_trpca(X, learned=settings, L=Lo, S=So, workspace=ws)
+
+    native()  # warm-up
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    res = native()
+    torch.cuda.synchronize()
+    t_nat = time.perf_counter() - t0
+    err_nat = float((Lo - L0).norm() / L0.norm())
+    # fused update pass: HIP events around each launch
+    tp.tp_trace_collect_work()
+    tp.tp_trace_enable(True)
+    native()
+    torch.cuda.synchronize()
+    tp.tp_trace_enable(False)
+    upd = [rec for rec in tp.tp_trace_collect_work() if rec[0] == "trpca" and rec[3] > 0]
+    upd_ms = sum(rec[1] for rec in upd) / max(len(upd), 1)
+    upd_gbs = (upd[0][3] / (upd_ms * 1e-3) / 1e9) if upd else None
+
+    trpca.timed_run(X, trpca.ProxLearned(X.shape, dev, mlp=mlp))  # warm-up
+    py = trpca.timed_run(X, trpca.ProxLearned(X.shape, dev, mlp=mlp))
+    err_py = float((py["L"] - L0).norm() / L0.norm())
+    out = {
+        "workload": f"TRPCA of X = P*Q + S, 1024x1024x64, tubal rank {r}, 5% +-1 outliers, seed {args.learned_seed}",
+        "native": {"iters": res["iters"], "converged": res["converged"], "ms": round(t_nat * 1e3, 2),
+                   "ms_per_iter": round(t_nat * 1e3 / max(res["iters"], 1), 3), "L_rel_err": err_nat},
+        "python_driver": {"iters": py["iters"], "converged": py["converged"], "ms": round(py["wall_s"] * 1e3, 2),
+                          "ms_per_iter": round(py["wall_s"] * 1e3 / max(py["iters"], 1), 3), "L_rel_err": err_py},
+        "speedup_native_vs_python": round(py["wall_s"] / t_nat, 2),
+        "update_pass": {"ms": round(upd_ms, 4), "bytes": upd[0][3] if upd else None,
+                        "GB_s": round(upd_gbs, 1) if upd_gbs else None,
+                        "frac_hbm": round(upd_gbs / 8000.0, 4) if upd_gbs else None},
+    }
+    log(f"trpca {out}")
+    return out
+
+
 def oracle_learned_prox(oracle, Y, tau, prev, psig, params, seed, oversample=10, max_rank=64, power=2):
     """The oracle's learned-rank prox on one call: slice features, the rank
     MLP, the common sketch width of the call, the randomized prox."""
@@ -505,7 +559,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=10.0)
     ap.add_argument("--batch-steps", type=int, default=10)
-    ap.add_argument("--only", choices=["learned", "prox200", "tprod", "batch", "copy"], default=None,
+    ap.add_argument("--only", choices=["learned", "prox200", "tprod", "batch", "trpca", "copy"], default=None,
                     help="run one block and print its JSON (a short driver for counter runs); "
                          "copy: a plain 1 GiB device copy, the reference for the byte counters")
     args = ap.parse_args()
@@ -539,6 +593,9 @@ def main():
     if args.only == "batch":
         print(json.dumps(batch_block(args, tp, inputs, dev)), flush=True)
         return
+    if args.only == "trpca":
+        print(json.dumps(trpca_block(args, tp, dev)), flush=True)
+        return
     value, ms, steps, learned, roof, calls, mlp, r = learned_block(args, tp, dev)
     if args.only == "learned":
         print(json.dumps({"value": value, "roofline": roof, "learned": learned}), flush=True)
@@ -546,6 +603,7 @@ def main():
     prox_full, parts, _ = prox_full_block(args, tp, inputs, dev)
     tprod, outs, A_np, B_np = tprod_block(args, tp, inputs, dev)
     batch = batch_block(args, tp, inputs, dev)
+    trpca_res = trpca_block(args, tp, dev, mlp)
 
     cpu = None
     parity = {"learned_vs_full_svd_max_rel_err": learned["rel_err_vs_full_svd"]["max"]}
@@ -582,7 +640,7 @@ def main():
                    "rank_predictor": "MLP 12-64-64-64-1", "oversample": 10, "power_iters": 2,
                    "parallelism": "single GPU"},
         "roofline": roof, "cpu_baseline": cpu, "learned": learned, "prox_full_200": prox_full, "tprod": tprod, "batch": batch,
-        "parity": parity,
+        "trpca": trpca_res, "parity": parity,
     }
     print(json.dumps(line), flush=True)
 

@@ -188,6 +188,19 @@ def tp_prox_tnn_learned(Y, tau, mlp=None, fixed_rank=0, prev_rank=None, prev_sig
     return X
 
 
+def tp_trpca_workspace_size_for(shape, learned=None, **kw):
+    """Workspace bytes of tp_trpca for an X of this shape and these settings."""
+    n1, n2, n3 = (int(v) for v in shape)
+    lo = None
+    if learned is not None:
+        lo = _lib.LearnedOpts(None, 0, None, None, 10, 2, int(learned.get("max_rank", 64)), 0, 0.0, 8, 1, 0,
+                              None, None, None, None)
+    opts = _lib.TrpcaOpts(0.0, float(kw.get("mu", 1e-3)), float(kw.get("rho", 1.1)), float(kw.get("mu_max", 1e10)),
+                          float(kw.get("tol", 1e-5)), int(kw.get("max_iter", 500)),
+                          ctypes.pointer(lo) if lo is not None else None)
+    return int(_lib.load().tp_trpca_workspace_size(n1, n2, n3, ctypes.byref(opts)))
+
+
 def tp_trpca(X, lam=None, mu=1e-3, rho=1.1, mu_max=1e10, tol=1e-5, max_iter=500, learned=None, L=None, S=None,
              Lam=None, workspace=None):
     """Tensor robust PCA (include/tp.h): min ||L||_* + lam ||S||_1 s.t. L + S = X
