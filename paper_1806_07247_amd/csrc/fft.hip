@@ -19,8 +19,9 @@
 //
 // Power-of-two n3 (4..128): a complex FFT of length n3/2 on the packed
 // sequence z_t = x_2t + i x_2t+1 (radix-2, fully unrolled in registers), then
-// the even/odd split.  Other n3: a direct DFT per lane.  Twiddles are
-// computed per workgroup in double precision (sincospi) and rounded once.
+// the even/odd split, with compile-time twiddles.  Other n3: a direct DFT
+// per lane, with twiddles computed per workgroup in double precision
+// (sincospi) and rounded once.
 #include "tp_internal.h"
 
 namespace tp {
@@ -37,6 +38,60 @@ __device__ void fill_twiddles(float2* tw, int n)
     }
 }
 
+// Twiddles of the power-of-two lengths as compile-time constants,
+// W_N^j = exp(-2 pi i j / N): cos and sin of 2 pi j / N in double (reduction
+// to an octant, Taylor series on [0, pi/4), exact octant rotations), rounded
+// once to float.  The fully unrolled transforms index them with constants,
+// so they become instruction literals and take no registers or LDS.
+constexpr double kCxPi = 3.14159265358979323846264338327950288;
+constexpr double cx_sin_small(double x)
+{
+    double t = x, s = x;
+    for (int k = 1; k < 14; ++k) {
+        t *= -x * x / ((2.0 * k) * (2.0 * k + 1.0));
+        s += t;
+    }
+    return s;
+}
+constexpr double cx_cos_small(double x)
+{
+    double t = 1.0, s = 1.0;
+    for (int k = 1; k < 14; ++k) {
+        t *= -x * x / ((2.0 * k - 1.0) * (2.0 * k));
+        s += t;
+    }
+    return s;
+}
+template <int N>
+struct TwTab {
+    float re[N], im[N];
+};
+template <int N>
+constexpr TwTab<N> make_twiddles()
+{
+    TwTab<N> t{};
+    for (int j = 0; j < N; ++j) {
+        const long o = (8L * j) / N, r = 8L * j - o * N;  // angle = (pi/4)(o + r/N)
+        const double x = (kCxPi / 4.0) * (double)r / (double)N;
+        double c = cx_cos_small(x), sn = cx_sin_small(x);
+        const double h = 0.70710678118654752440084436210484903;
+        for (long q = 0; q < o; ++q) {
+            const double nc = (c - sn) * h, ns = (sn + c) * h;
+            c = nc;
+            sn = ns;
+        }
+        t.re[j] = (float)c;
+        t.im[j] = (float)(-sn);
+    }
+    return t;
+}
+template <int N>
+__device__ __forceinline__ float2 twc(int j)
+{
+    constexpr TwTab<N> T = make_twiddles<N>();
+    return make_float2(T.re[j], T.im[j]);
+}
+
 template <int M>
 __device__ constexpr int bitrev(int t)
 {
@@ -51,7 +106,7 @@ __device__ constexpr int bitrev(int t)
 // In-place radix-2 DIT FFT of length M = N/2 on bit-reversed input.  The
 // twiddle W_len^j is W_N^(j*N/len) from the length-N table; INV conjugates it.
 template <int N, bool INV>
-__device__ __forceinline__ void cfft_half(float (&zr)[N / 2], float (&zi)[N / 2], const float2* tw)
+__device__ __forceinline__ void cfft_half(float (&zr)[N / 2], float (&zi)[N / 2])
 {
     constexpr int M = N / 2;
 #pragma unroll
@@ -66,7 +121,7 @@ __device__ __forceinline__ void cfft_half(float (&zr)[N / 2], float (&zi)[N / 2]
                     tr = zr[i1];
                     ti = zi[i1];
                 } else {
-                    float2 w = tw[j * (N / len)];
+                    float2 w = twc<N>(j * (N / len));
                     if (INV) w.y = -w.y;
                     tr = zr[i1] * w.x - zi[i1] * w.y;
                     ti = zr[i1] * w.y + zi[i1] * w.x;
@@ -129,7 +184,7 @@ __device__ __forceinline__ void rfft_tile(const float* __restrict__ x, float* __
             zr[bitrev<M>(t)] = xt[2 * t];
             zi[bitrev<M>(t)] = xt[2 * t + 1];
         }
-        cfft_half<N, false>(zr, zi, tw);
+        cfft_half<N, false>(zr, zi);
         const long long q = base + tid;
         // X_k = E_k + W_N^k O_k with E = (Z_k + conj Z_{M-k})/2, O = -i (Z_k - conj Z_{M-k})/2
         re[q] = zr[0] + zi[0];
@@ -142,7 +197,7 @@ __device__ __forceinline__ void rfft_tile(const float* __restrict__ x, float* __
             const float er = 0.5f * (ar + br), ei = 0.5f * (ai + bi);
             const float dr = 0.5f * (ar - br), di = 0.5f * (ai - bi);
             const float orr = di, oi = -dr;
-            const float2 w = tw[k];
+            const float2 w = twc<N>(k);
             re[(long long)k * ntubes + q] = er + (w.x * orr - w.y * oi);
             im[(long long)k * ntubes + q] = ei + (w.x * oi + w.y * orr);
         }
@@ -153,13 +208,11 @@ template <int N>
 __global__ __launch_bounds__(kTubes) void k_rfft_pow2(const float* __restrict__ x, float* __restrict__ re,
                                                        float* __restrict__ im, long long ntubes)
 {
-    __shared__ float2 tw[N];
     __shared__ float buf[kTubes * (N + 1)];
-    fill_twiddles(tw, N);
     for (long long base = (long long)blockIdx.x * kTubes; base < ntubes; base += (long long)gridDim.x * kTubes) {
         const int nt = (int)min<long long>(kTubes, ntubes - base);
         __syncthreads();
-        rfft_tile<N>(x, re, im, ntubes, base, nt, tw, buf);
+        rfft_tile<N>(x, re, im, ntubes, base, nt, nullptr, buf);
     }
 }
 
@@ -172,9 +225,6 @@ __global__ __launch_bounds__(kTubes) void k_rfft_pow2_direct(const float* __rest
                                                               float* __restrict__ im, long long ntubes)
 {
     constexpr int M = N / 2;
-    __shared__ float2 tw[N];
-    fill_twiddles(tw, N);
-    __syncthreads();
     const int tid = threadIdx.x;
     for (long long base = (long long)blockIdx.x * kTubes; base < ntubes; base += (long long)gridDim.x * kTubes) {
         const long long q = base + tid;
@@ -189,7 +239,7 @@ __global__ __launch_bounds__(kTubes) void k_rfft_pow2_direct(const float* __rest
             zr[bitrev<M>(2 * t + 1)] = v.z;
             zi[bitrev<M>(2 * t + 1)] = v.w;
         }
-        cfft_half<N, false>(zr, zi, tw);
+        cfft_half<N, false>(zr, zi);
         re[q] = zr[0] + zi[0];
         im[q] = 0.0f;
         re[(long long)M * ntubes + q] = zr[0] - zi[0];
@@ -200,7 +250,7 @@ __global__ __launch_bounds__(kTubes) void k_rfft_pow2_direct(const float* __rest
             const float er = 0.5f * (ar + br), ei = 0.5f * (ai + bi);
             const float dr = 0.5f * (ar - br), di = 0.5f * (ai - bi);
             const float orr = di, oi = -dr;
-            const float2 w = tw[k];
+            const float2 w = twc<N>(k);
             re[(long long)k * ntubes + q] = er + (w.x * orr - w.y * oi);
             im[(long long)k * ntubes + q] = ei + (w.x * oi + w.y * orr);
         }
@@ -230,13 +280,13 @@ __device__ __forceinline__ void irfft_tile(const float* __restrict__ re, const f
         for (int k = 0; k < M; ++k) {
             const float ar = xr[k], ai = xi[k], br = xr[M - k], bi = -xi[M - k];
             const float sr = ar + br, si = ai + bi, dr = ar - br, di = ai - bi;
-            const float2 w = tw[k];  // conj applied below
+            const float2 w = twc<N>(k);  // conj applied below
             const float tr = w.x * dr + w.y * di;
             const float ti = w.x * di - w.y * dr;
             zr[bitrev<M>(k)] = sr - ti;
             zi[bitrev<M>(k)] = si + tr;
         }
-        cfft_half<N, true>(zr, zi, tw);
+        cfft_half<N, true>(zr, zi);
         float* xt = buf + tid * LD;
 #pragma unroll
         for (int t = 0; t < M; ++t) {
@@ -252,13 +302,11 @@ template <int N>
 __global__ __launch_bounds__(kTubes) void k_irfft_pow2(const float* __restrict__ re, const float* __restrict__ im,
                                                         float* __restrict__ x, long long ntubes)
 {
-    __shared__ float2 tw[N];
     __shared__ float buf[kTubes * (N + 1)];
-    fill_twiddles(tw, N);
     for (long long base = (long long)blockIdx.x * kTubes; base < ntubes; base += (long long)gridDim.x * kTubes) {
         const int nt = (int)min<long long>(kTubes, ntubes - base);
         __syncthreads();
-        irfft_tile<N>(re, im, x, ntubes, base, nt, tw, buf);
+        irfft_tile<N>(re, im, x, ntubes, base, nt, nullptr, buf);
     }
 }
 
