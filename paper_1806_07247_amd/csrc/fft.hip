@@ -166,6 +166,24 @@ __device__ __forceinline__ void store_tile(float* __restrict__ dst, const float*
     }
 }
 
+// coalesced copy of the LDS tile (nt rows of `cols` floats, leading dimension
+// ld) to global rows `gstride` floats apart (a column block of nt tubes)
+__device__ __forceinline__ void store_tile_cols(float* __restrict__ dst, const float* buf, int nt, int cols, int ld,
+                                                int gstride)
+{
+    const int total = nt * cols;
+    if ((cols & 3) == 0 && (gstride & 3) == 0 && (reinterpret_cast<uintptr_t>(dst) & 15) == 0) {
+        for (int e = threadIdx.x * 4; e < total; e += blockDim.x * 4) {
+            const int r = e / cols, c = e % cols;
+            const float* sp = buf + r * ld + c;
+            *reinterpret_cast<float4*>(dst + (long long)r * gstride + c) = make_float4(sp[0], sp[1], sp[2], sp[3]);
+        }
+    } else {
+        for (int e = threadIdx.x; e < total; e += blockDim.x) dst[(long long)(e / cols) * gstride + e % cols] =
+            buf[(e / cols) * ld + e % cols];
+    }
+}
+
 // Forward transform of the nt (<= 64) tubes starting at tube `base` of a
 // tensor with `ntubes` tubes; tw holds W_N^j, buf 64 x (N+1) floats.
 template <int N>
@@ -258,55 +276,85 @@ __global__ __launch_bounds__(kTubes) void k_rfft_pow2_direct(const float* __rest
 }
 
 // Inverse transform of the nt tubes starting at `base` (see rfft_tile).
-template <int N>
+// HALF: the output goes through a half-width LDS tile (N/2 + 1 floats per
+// tube) in two passes, for more wavefronts per compute unit at large N.  All
+// barriers are reached by every lane.
+template <int N, bool HALF = false>
 __device__ __forceinline__ void irfft_tile(const float* __restrict__ re, const float* __restrict__ im,
                                            float* __restrict__ x, long long ntubes, long long base, int nt,
                                            const float2* tw, float* buf)
 {
     constexpr int M = N / 2, LD = N + 1;
     const int tid = threadIdx.x;
+    const bool act = tid < nt;
     const float scale = 1.0f / (float)N;
-    if (tid < nt) {
+    float zr[M], zi[M];
+    if (act) {
         const long long q = base + tid;
-        float xr[M + 1], xi[M + 1];
+        // 2 Z_k = (X_k + conj X_{M-k}) + i W_N^{-k} (X_k - conj X_{M-k}).  Bins k
+        // and M-k feed both Z_k and Z_{M-k}: they are loaded as a pair and
+        // consumed at once (a few pairs in flight), so the M+1 bins are never
+        // all live in registers.
 #pragma unroll
-        for (int k = 0; k <= M; ++k) {
-            xr[k] = re[(long long)k * ntubes + q];
-            xi[k] = (k == 0 || k == M) ? 0.0f : im[(long long)k * ntubes + q];
-        }
-        // 2 Z_k = (X_k + conj X_{M-k}) + i W_N^{-k} (X_k - conj X_{M-k})
-        float zr[M], zi[M];
-#pragma unroll
-        for (int k = 0; k < M; ++k) {
-            const float ar = xr[k], ai = xi[k], br = xr[M - k], bi = -xi[M - k];
-            const float sr = ar + br, si = ai + bi, dr = ar - br, di = ai - bi;
-            const float2 w = twc<N>(k);  // conj applied below
-            const float tr = w.x * dr + w.y * di;
-            const float ti = w.x * di - w.y * dr;
-            zr[bitrev<M>(k)] = sr - ti;
-            zi[bitrev<M>(k)] = si + tr;
+        for (int k = 0; k <= M / 2; ++k) {
+            const int k2 = M - k;  // partner bin (M for k = 0)
+            const float xr_a = re[(long long)k * ntubes + q];
+            const float xi_a = (k == 0) ? 0.0f : im[(long long)k * ntubes + q];
+            const float xr_b = (k2 == k) ? xr_a : re[(long long)k2 * ntubes + q];
+            const float xi_b = (k2 == M || k2 == k) ? ((k2 == k) ? xi_a : 0.0f) : im[(long long)k2 * ntubes + q];
+            auto zk = [&](int kk, float ar, float ai, float br, float bi) {
+                const float sr = ar + br, si = ai + bi, dr = ar - br, di = ai - bi;
+                const float2 w = twc<N>(kk);  // conj applied below
+                const float tr = w.x * dr + w.y * di;
+                const float ti = w.x * di - w.y * dr;
+                zr[bitrev<M>(kk)] = sr - ti;
+                zi[bitrev<M>(kk)] = si + tr;
+            };
+            zk(k, xr_a, xi_a, xr_b, -xi_b);
+            if (k > 0 && k2 != k) zk(k2, xr_b, xi_b, xr_a, -xi_a);
+            if ((k & 7) == 7) __builtin_amdgcn_sched_barrier(0);
         }
         cfft_half<N, true>(zr, zi);
-        float* xt = buf + tid * LD;
+    }
+    if (!HALF) {
+        if (act) {
+            float* xt = buf + tid * LD;
 #pragma unroll
-        for (int t = 0; t < M; ++t) {
-            xt[2 * t] = zr[t] * scale;
-            xt[2 * t + 1] = zi[t] * scale;
+            for (int t = 0; t < M; ++t) {
+                xt[2 * t] = zr[t] * scale;
+                xt[2 * t + 1] = zi[t] * scale;
+            }
+        }
+        __syncthreads();
+        store_tile(x + base * N, buf, nt, N, LD);
+    } else {
+        float* xt = buf + tid * (M + 1);
+#pragma unroll
+        for (int half = 0; half < 2; ++half) {
+            if (half) __syncthreads();  // the first half has been stored
+            if (act) {
+#pragma unroll
+                for (int t = 0; t < M / 2; ++t) {
+                    xt[2 * t] = zr[t + half * M / 2] * scale;
+                    xt[2 * t + 1] = zi[t + half * M / 2] * scale;
+                }
+            }
+            __syncthreads();
+            store_tile_cols(x + base * N + half * M, buf, nt, M, M + 1, N);
         }
     }
-    __syncthreads();
-    store_tile(x + base * N, buf, nt, N, LD);
 }
 
 template <int N>
 __global__ __launch_bounds__(kTubes) void k_irfft_pow2(const float* __restrict__ re, const float* __restrict__ im,
                                                         float* __restrict__ x, long long ntubes)
 {
-    __shared__ float buf[kTubes * (N + 1)];
+    constexpr bool HALF = N >= 64;  // half-width staging tile at the larger lengths
+    __shared__ float buf[kTubes * (HALF ? N / 2 + 1 : N + 1)];
     for (long long base = (long long)blockIdx.x * kTubes; base < ntubes; base += (long long)gridDim.x * kTubes) {
         const int nt = (int)min<long long>(kTubes, ntubes - base);
         __syncthreads();
-        irfft_tile<N>(re, im, x, ntubes, base, nt, nullptr, buf);
+        irfft_tile<N, HALF>(re, im, x, ntubes, base, nt, nullptr, buf);
     }
 }
 
