@@ -161,13 +161,15 @@ __global__ __launch_bounds__(256) void k_gram(const float* __restrict__ yr, cons
 // subtracts conj(R_ja) times it from every later row a.  On the G side this
 // is the right-looking Cholesky G = R^* R; the same row operations turn I
 // into M = R^{-*} (they are the E with E G = R), so Rinv = M^* is formed in
-// the same L steps.  Every thread keeps its own entries (a, b) of both sides
-// in registers; the owners of row j+1 publish it to LDS after their update
-// (two row buffers, one barrier per step).  Rinv is written as FP32 planar
+// the same L steps.  The entries stay in registers (the upper triangle of G
+// and the strict lower triangle of M share one slot per (a, b)); the owners
+// of row j+1 publish it to LDS after their update (two row buffers, one
+// barrier per step).  Rinv is written as FP32 planar
 // (identity on the inactive columns); optionally Rtot <- R Rtot (FP64) and
 // R2^* (FP32 planar, zero outside the active block).
 constexpr int kCholThreads = 1024;
-constexpr int kCholEntries = kMaxL * kMaxL / kCholThreads;  // entries per thread
+constexpr int kCholEntries = kMaxL * kMaxL / kCholThreads;  // entries per thread (rows per wavefront)
+static_assert(kMaxL == 64 && kCholThreads / 64 * kCholEntries == kMaxL, "one lane per column, 16 waves x 4 rows");
 
 __global__ __launch_bounds__(kCholThreads) void k_chol(const double2* __restrict__ part, int nsplit, int L,
                                                        const int* __restrict__ lact, int pass, float* __restrict__ rir,
@@ -178,42 +180,46 @@ __global__ __launch_bounds__(kCholThreads) void k_chol(const double2* __restrict
     extern __shared__ double2 sh[];
     double2* R = sh;            // L x L (R, for the Rtot product)
     double2* X = sh + L * L;    // L x L (Rtot)
-    __shared__ double2 rowG[2][kMaxL], rowM[2][kMaxL];
+    __shared__ double2 rowG[2][kMaxL];  // the published row (R and M' parts), two buffers
     __shared__ double2 piv[2];  // (R_jj, 1 / R_jj) of the published row
     __shared__ double diag[kMaxL];
     const int s = blockIdx.x, tid = threadIdx.x, nt = blockDim.x;
     const int la = lact[s];
     const double2* P = part + (long long)s * nsplit * L * L;
 
-    // own entries e = tid + u nt: G side (b >= a) in (gr, gi), M side (b <= a)
-    // in (mr, mi); plain doubles, so that they stay in registers
-    int ea[kCholEntries], eb[kCholEntries];
-    double gr[kCholEntries], gi[kCholEntries], mr[kCholEntries], mi[kCholEntries];
+    // One value per entry (a, b), held by lane b of wavefront w for the rows
+    // a = w + 16 u: the G side for b >= a, the M side for b < a (the two
+    // share a slot: M_ab is zero until column b is eliminated, and the slot is
+    // reset at that step); M_aa = 1 / R_aa is implicit.  A row is one
+    // wavefront's, so rows already eliminated are skipped as a whole.  Plain
+    // doubles, so that the values stay in registers.
+    const int lane = tid & 63, wave = tid >> 6;
+    int ea[kCholEntries];
+    double vr[kCholEntries], vi[kCholEntries];
+    const int b = lane;
 #pragma unroll
     for (int u = 0; u < kCholEntries; ++u) {
-        const int e = tid + u * nt;
-        ea[u] = e < L * L ? e / L : L;  // L: no entry
-        eb[u] = e < L * L ? e % L : 0;
-        gr[u] = gi[u] = 0.0;
-        mr[u] = ea[u] == eb[u] ? 1.0 : 0.0;
-        mi[u] = 0.0;
-        if (ea[u] < L && eb[u] >= ea[u]) {
+        const int a0 = wave + (kCholThreads / 64) * u;
+        ea[u] = (a0 < L && b < L) ? a0 : L;  // L: no entry
+        vr[u] = vi[u] = 0.0;
+        if (ea[u] < L && b >= ea[u]) {
             // all partials in flight at once, then summed in the fixed order w = 0, 1, ...
-            double vr[kMaxGramSplit], vi[kMaxGramSplit];
+            const int e = ea[u] * L + b;
+            double pr[kMaxGramSplit], pi[kMaxGramSplit];
 #pragma unroll
             for (int w = 0; w < kMaxGramSplit; ++w) {
                 const double2 v = w < nsplit ? P[(long long)w * L * L + e] : make_double2(0.0, 0.0);
-                vr[w] = v.x;
-                vi[w] = v.y;
+                pr[w] = v.x;
+                pi[w] = v.y;
             }
 #pragma unroll
             for (int w = 0; w < kMaxGramSplit; ++w) {
                 if (w < nsplit) {
-                    gr[u] += vr[w];
-                    gi[u] += vi[w];
+                    vr[u] += pr[w];
+                    vi[u] += pi[w];
                 }
             }
-            if (ea[u] == eb[u]) diag[ea[u]] = gr[u];
+            if (ea[u] == b) diag[b] = vr[u];
         }
     }
     __syncthreads();
@@ -221,7 +227,7 @@ __global__ __launch_bounds__(kCholThreads) void k_chol(const double2* __restrict
     double sd = 0.0;
     if (pass == 0 && la > 0) {
         double tr = 0.0;
-        for (int a = 0; a < la; ++a) tr += diag[a];
+        for (int k = 0; k < la; ++k) tr += diag[k];
         sd = 1e-13 * tr / la;
     }
     // the owner of diagonal entry (j, j) forms the pivot of step j once, when
@@ -238,13 +244,10 @@ __global__ __launch_bounds__(kCholThreads) void k_chol(const double2* __restrict
     };
 #pragma unroll
     for (int u = 0; u < kCholEntries; ++u) {
-        if (ea[u] == eb[u] && ea[u] < la) gr[u] += sd;
+        if (ea[u] == b && b < la) vr[u] += sd;
         if (ea[u] == 0) {  // publish row 0
-            rowG[0][eb[u]] = make_double2(gr[u], gi[u]);
-            if (eb[u] == 0) {
-                rowM[0][0] = make_double2(mr[u], mi[u]);
-                pivot(0, gr[u], 0);
-            }
+            rowG[0][b] = make_double2(vr[u], vi[u]);
+            if (b == 0) pivot(0, vr[u], 0);
         }
     }
     __syncthreads();
@@ -253,65 +256,58 @@ __global__ __launch_bounds__(kCholThreads) void k_chol(const double2* __restrict
         const bool act = j < la;
         const double2 pv = piv[cur];
         const double rjj = pv.x, inv = pv.y;
+        // y_b: R_jb (b > j; zero outside the active block), M'_jb (b < j), M'_jj = 1 / R_jj
+        double yr = inv, yi = 0.0;
+        if (b != j) {
+            const double2 t = (b < j || (act && b < la)) ? rowG[cur][b] : make_double2(0.0, 0.0);
+            yr = t.x * inv;
+            yi = t.y * inv;
+        }
 #pragma unroll
         for (int u = 0; u < kCholEntries; ++u) {
-            const int a = ea[u], b = eb[u];
+            const int a = ea[u];
             if (a < L && a >= j) {
-                // R_jb of the scaled row j (zero outside the active block)
-                const double2 rb = (act && b > j && b < la) ? rowG[cur][b] : make_double2(0.0, 0.0);
-                if (a == j) {
-                    if (b > j) {
-                        gr[u] = rb.x * inv;
-                        gi[u] = rb.y * inv;
-                    } else if (b == j) {
-                        gr[u] = rjj;
-                        gi[u] = 0.0;
-                    }
-                    if (b <= j) {
-                        const double2 mv = rowM[cur][b];
-                        mr[u] = mv.x * inv;
-                        mi[u] = mv.y * inv;
-                    }
+                if (a == j) {  // row j: R_jb, R_jj, M'_jb
+                    vr[u] = b == j ? rjj : yr;
+                    vi[u] = b == j ? 0.0 : yi;
                 } else {
                     const double2 ra = (act && a < la) ? rowG[cur][a] : make_double2(0.0, 0.0);
                     const double xr = ra.x * inv, xi = ra.y * inv;  // R_ja
-                    if (b >= a) {  // G_ab -= conj(R_ja) R_jb
-                        const double yr = rb.x * inv, yi = rb.y * inv;
-                        gr[u] -= xr * yr + xi * yi;
-                        gi[u] -= xr * yi - xi * yr;
-                    }
-                    if (b <= j) {  // M_ab -= conj(R_ja) M'_jb
-                        const double2 mv = rowM[cur][b];
-                        const double yr = mv.x * inv, yi = mv.y * inv;
-                        mr[u] -= xr * yr + xi * yi;
-                        mi[u] -= xr * yi - xi * yr;
-                    }
+                    // v_ab -= conj(R_ja) y_b; column j enters the M side from zero
+                    const double br = b == j ? 0.0 : vr[u], bi = b == j ? 0.0 : vi[u];
+                    vr[u] = br - (xr * yr + xi * yi);
+                    vi[u] = bi - (xr * yi - xi * yr);
                 }
                 if (a == j + 1) {  // publish row j+1 for the next step
-                    if (b >= a) rowG[nxt][b] = make_double2(gr[u], gi[u]);
-                    if (b <= a) rowM[nxt][b] = make_double2(mr[u], mi[u]);
-                    if (b == a) pivot(a, gr[u], nxt);
+                    rowG[nxt][b] = make_double2(vr[u], vi[u]);
+                    if (b == a) pivot(a, vr[u], nxt);
                 }
             }
         }
         __syncthreads();
     }
     if (broke && status) status[s] = 1;  // by the owners of the failed pivots
-    // Rinv = M^*: entry (a, b) of M gives Rinv(b, a); Rinv(b, a) = 0 for b > a
+    // Rinv = M^*: entry (a, b), b <= a, of M gives Rinv(b, a); Rinv(b, a) = 0 for b > a
 #pragma unroll
     for (int u = 0; u < kCholEntries; ++u) {
-        const int a = ea[u], b = eb[u];
+        const int a = ea[u];
         if (a < L) {
             const long long o = (long long)s * L * L + b * L + a;
-            rir[o] = b <= a ? (float)mr[u] : 0.0f;
-            rii[o] = b <= a ? (float)(-mi[u]) : 0.0f;
-            R[a * L + b] = b >= a ? make_double2(gr[u], gi[u]) : make_double2(0.0, 0.0);
+            double mr = vr[u], mi = vi[u];
+            if (b == a) {  // M_aa = 1 / R_aa (R_aa real)
+                mr = 1.0 / vr[u];
+                mi = 0.0;
+            }
+            rir[o] = b <= a ? (float)mr : 0.0f;
+            rii[o] = b <= a ? (float)(-mi) : 0.0f;
+            R[a * L + b] = b >= a ? make_double2(vr[u], vi[u]) : make_double2(0.0, 0.0);
         }
     }
     if (rtot) {
         double2* T = rtot + (long long)s * L * L;
+        __syncthreads();  // R complete
         if (pass == 0) {
-            for (int e = tid; e < L * L; e += nt) X[e] = R[e];  // own entries, written above by this thread
+            for (int e = tid; e < L * L; e += nt) X[e] = R[e];
         } else {
             for (int e = tid; e < L * L; e += nt) X[e] = T[e];
             __syncthreads();
@@ -319,7 +315,7 @@ __global__ __launch_bounds__(kCholThreads) void k_chol(const double2* __restrict
             double cr[kCholEntries], ci[kCholEntries];
 #pragma unroll
             for (int u = 0; u < kCholEntries; ++u) {
-                const int a = ea[u], b = eb[u];
+                const int a = ea[u];
                 cr[u] = ci[u] = 0.0;
                 if (a < L)
                     for (int k = a; k <= b; ++k) {
@@ -331,7 +327,7 @@ __global__ __launch_bounds__(kCholThreads) void k_chol(const double2* __restrict
             __syncthreads();
 #pragma unroll
             for (int u = 0; u < kCholEntries; ++u)
-                if (ea[u] < L) X[ea[u] * L + eb[u]] = make_double2(cr[u], ci[u]);
+                if (ea[u] < L) X[ea[u] * L + b] = make_double2(cr[u], ci[u]);
         }
         __syncthreads();
         for (int e = tid; e < L * L; e += nt) T[e] = X[e];
