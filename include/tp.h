@@ -184,8 +184,10 @@ int tp_teye(float* out, int n, int n3, void* stream);
  *   11 one when c > 0 and s_c > tau (the previous sketch saw no value below tau)
  * the logarithms clamped to [-30, 30].  The MLP maps them to y and
  * kpred = round(expm1(y * log1p(p))) clipped to [0, p].
- * Warm start (optional): basis_out receives this call's right range basis
- * Q2 of every slice, planar complex float[2][floor(n3/2)+1][n2][max_rank]
+ * Warm start (optional): basis_out receives this call's right Ritz vectors
+ * Q2 V of every slice (the right range basis rotated by the small SVD, so
+ * the next sketch starts from the singular basis and its small SVD needs few
+ * sweeps), planar complex float[2][floor(n3/2)+1][n2][max_rank]
  * (re plane, then im plane; columns beyond basis_cols_out[k] zero;
  * basis_cols_out[k] = 0 for a fallback slice).  Passed back as warm_basis /
  * warm_cols of the next call (same n1, n2, n3, max_rank), its first

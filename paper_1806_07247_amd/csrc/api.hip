@@ -736,11 +736,18 @@ int tp_prox_tnn_learned(const float* Y, float* X, int n1, int n2, int n3, float 
             if (st != TP_OK) return st;
             ++q;
         }
-        if (opts->basis_out && opts->basis_cols_out)  // Q2 for the next call's warm start
+        if (opts->basis_out && opts->basis_cols_out) {
+            // the right Ritz vectors Q2 V for the next call's warm start: its
+            // sketch then starts from the singular basis, so its R2^* comes out
+            // nearly diagonal and the small Jacobi SVD needs few sweeps
+            TP_LAUNCH(tp::K_ACCURACY, s, tp::launch_cm_to_planar(W.jv, W.vp, L, h, s));
+            st = gemm(W.za, L, sz, tp::OP_N, W.vp, L, sl, tp::OP_N, W.zb, L, sz, n2, L, L, h, rl, s);
+            if (st != TP_OK) return st;
             TP_LAUNCH(tp::K_SKETCH, s,
-                      tp::launch_store_basis(W.za.re, W.za.im, n2, L, W.lact, fb, h, opts->basis_out,
+                      tp::launch_store_basis(W.zb.re, W.zb.im, n2, L, W.lact, fb, h, opts->basis_out,
                                              opts->basis_out + (long long)h * n2 * opts->max_rank, opts->max_rank,
                                              opts->basis_cols_out, s));
+        }
         if (sigma_out)  // singular values of the slices kept on the randomized path
             TP_LAUNCH(tp::K_RSVD_CHECK, s, tp::launch_sigma_top(W.jsig, L, W.lact, nullptr, fb, h, sigma_out, s));
         // W = Q (T Q2^*)
