@@ -157,6 +157,7 @@ struct LearnedLayout {
     float* kpart;                   // split-K partial products
     size_t kpart_bytes;
     double* fro2;                   // ||Ybar^(k)||_F^2 per slice
+    double* accpart;                // per-band partial residual sums of the accuracy check
     float* feats;
     tp::Planes vp, cp, t1, t2;      // V_r, U_r S (planar L x L), residual products (m x L)
     int *kpred, *lact, *fb, *rank, *status, *idx, *cinfo, *crank, *prefb, *bad;
@@ -204,6 +205,7 @@ tp::Arena learned_arena(void* ws, size_t bytes, int n1, int n2, int n3, int Lw, 
     t.kpart_bytes = tp::splitk_bytes(kMaxSplit, (int)h, mx, Lw);
     t.kpart = reinterpret_cast<float*>(ar.take<char>(t.kpart_bytes));
     t.fro2 = ar.take<double>(h);
+    t.accpart = reinterpret_cast<double*>(ar.take<char>(tp::accuracy_part_bytes((int)h)));
     t.feats = ar.take<float>(h * TP_MLP_INPUTS);
     // kpred, lact and prefb adjacent: the host reads them with one copy
     t.kpred = ar.take<int>(3 * h);
@@ -720,7 +722,7 @@ int tp_prox_tnn_learned(const float* Y, float* X, int n1, int n2, int n3, float 
             TP_LAUNCH(tp::K_ACCURACY, s,
                       tp::launch_accuracy(W.t1, W.t2, W.jsig, W.lact, opts->accuracy_ref == 0 ? W.fro2 : nullptr,
                                           n1, L, (double)tau, (double)opts->accuracy,
-                                          W.bad, h, s));
+                                          W.bad, h, W.accpart, s));
             TP_TRY(hipMemcpyAsync(hbad.data(), W.bad, h * sizeof(int), hipMemcpyDeviceToHost, s));
             TP_TRY(hipMemcpyAsync(hfb.data(), fb, h * sizeof(int), hipMemcpyDeviceToHost, s));
             TP_TRY(hipStreamSynchronize(s));

@@ -372,14 +372,19 @@ __global__ __launch_bounds__(256) void k_rsvd_check(const float2* __restrict__ c
         scale[j] = (j < lact[s] && sg[j] > tau) ? (sg[j] - tau) / sg[j] : 0.0;
     __syncthreads();
     (void)above;
-    const float2* C = cols + (long long)s * L * L;
-    const float2* V = vr + (long long)s * L * L;
+    // C and V of the slice staged in LDS (column-major, L x L each)
+    __shared__ float2 sC[kMaxL * kMaxL], sV[kMaxL * kMaxL];
+    for (int e = tid; e < L * L; e += blockDim.x) {
+        sC[e] = cols[(long long)s * L * L + e];
+        sV[e] = vr[(long long)s * L * L + e];
+    }
+    __syncthreads();
     for (int e = tid; e < L * L; e += blockDim.x) {
         const int a = e / L, b = e % L;
         double vr_ = 0.0, vi_ = 0.0;
         for (int j = 0; j < L; ++j) {
             if (scale[j] == 0.0) continue;
-            const float2 c = C[(long long)j * L + a], v = V[(long long)j * L + b];  // C(a,j) conj(V(b,j))
+            const float2 c = sC[j * L + a], v = sV[j * L + b];  // C(a,j) conj(V(b,j))
             vr_ += scale[j] * ((double)c.x * v.x + (double)c.y * v.y);
             vi_ += scale[j] * ((double)c.y * v.x - (double)c.x * v.y);
         }
@@ -410,36 +415,61 @@ __global__ __launch_bounds__(256) void k_cm_to_planar(const float2* __restrict__
 // T2 = Q U_r S); the slice is inaccurate when
 //   sum_J ||r_j||^2 > delta^2 sum_J (sigma_j - tau)^2,
 // i.e. the residuals are not small against the thresholded part it keeps.
-__global__ __launch_bounds__(256) void k_accuracy(const float* __restrict__ t1r, const float* __restrict__ t1i,
-                                                  const float* __restrict__ t2r, const float* __restrict__ t2i,
-                                                  const double* __restrict__ sigma, const int* __restrict__ lact,
-                                                  const double* __restrict__ fro2, int m, int L, double tau,
-                                                  double delta, int* __restrict__ bad)
+constexpr int kAccSplit = 16;  // row bands of the residual sums (partials summed in order)
+
+// Partial residual sums over the rows of band w of kAccSplit:
+// sum over kept columns j (sigma_j > tau, j < lact) of |t1 - t2|^2, FP64
+__global__ __launch_bounds__(256) void k_accuracy_part(const float* __restrict__ t1r, const float* __restrict__ t1i,
+                                                       const float* __restrict__ t2r, const float* __restrict__ t2i,
+                                                       const double* __restrict__ sigma,
+                                                       const int* __restrict__ lact, int m, int L, double tau,
+                                                       double* __restrict__ part)
 {
     __shared__ double red[256];
-    const int s = blockIdx.x, tid = threadIdx.x;
+    __shared__ unsigned char keep[kMaxL];
+    const int w = blockIdx.x, s = blockIdx.y, tid = threadIdx.x;
     const double* sg = sigma + (long long)s * L;
+    if (tid < L) keep[tid] = (tid < lact[s] && sg[tid] > tau) ? 1 : 0;
+    __syncthreads();
+    const long long r0 = (long long)m * w / kAccSplit, r1 = (long long)m * (w + 1) / kAccSplit;
     const long long off = (long long)s * m * L;
+    const long long e0 = r0 * L, e1 = r1 * L;
+    const int step = (int)(blockDim.x % L);
+    int j = (int)((e0 + tid) % L);  // column of element e, advanced without a division
     double num = 0.0;
-    for (long long e = tid; e < (long long)m * L; e += blockDim.x) {
-        const int j = (int)(e % L);
-        if (j >= lact[s] || !(sg[j] > tau)) continue;
-        const double dr = (double)t1r[off + e] - t2r[off + e], di = (double)t1i[off + e] - t2i[off + e];
-        num += dr * dr + di * di;
+    for (long long e = e0 + tid; e < e1; e += blockDim.x) {
+        if (keep[j]) {
+            const double dr = (double)t1r[off + e] - t2r[off + e], di = (double)t1i[off + e] - t2i[off + e];
+            num += dr * dr + di * di;
+        }
+        j += step;
+        if (j >= L) j -= L;
     }
     red[tid] = num;
     __syncthreads();
-    for (int w = blockDim.x / 2; w > 0; w >>= 1) {
-        if (tid < w) red[tid] += red[tid + w];
+    for (int h = blockDim.x / 2; h > 0; h >>= 1) {
+        if (tid < h) red[tid] += red[tid + h];
         __syncthreads();
     }
-    if (tid == 0) {
-        double den = 0.0;
-        for (int j = 0; j < lact[s]; ++j)
-            if (sg[j] > tau) den += (sg[j] - tau) * (sg[j] - tau);
-        if (fro2 && den > 0.0) den = fmax(den, fro2[s]);
-        bad[s] = (den > 0.0 && red[0] > delta * delta * den) ? 1 : 0;
-    }
+    if (tid == 0) part[(long long)s * kAccSplit + w] = red[0];
+}
+
+// Per slice: the partial sums in band order, and the test against the kept
+// shrunk energy (or the slice's Frobenius norm squared with fro2)
+__global__ __launch_bounds__(64) void k_accuracy(const double* __restrict__ part, const double* __restrict__ sigma,
+                                                 const int* __restrict__ lact, const double* __restrict__ fro2, int L,
+                                                 double tau, double delta, int* __restrict__ bad, int nslices)
+{
+    const int s = blockIdx.x * blockDim.x + threadIdx.x;
+    if (s >= nslices) return;
+    double num = 0.0;
+    for (int w = 0; w < kAccSplit; ++w) num += part[(long long)s * kAccSplit + w];
+    const double* sg = sigma + (long long)s * L;
+    double den = 0.0;
+    for (int j = 0; j < lact[s]; ++j)
+        if (sg[j] > tau) den += (sg[j] - tau) * (sg[j] - tau);
+    if (fro2 && den > 0.0) den = fmax(den, fro2[s]);
+    bad[s] = (den > 0.0 && num > delta * delta * den) ? 1 : 0;
 }
 
 // ---------------------------------------------------------------- features --
@@ -891,10 +921,17 @@ hipError_t launch_cm_to_planar(const float2* src, Planes dst, int L, int nslices
     return hipGetLastError();
 }
 
+size_t accuracy_part_bytes(int nslices) { return align_up((size_t)nslices * kAccSplit * sizeof(double)); }
+
 hipError_t launch_accuracy(Planes t1, Planes t2, const double* sigma, const int* lact, const double* fro2, int m,
-                           int L, double tau, double delta, int* bad, int nslices, hipStream_t st)
+                           int L, double tau, double delta, int* bad, int nslices, double* part, hipStream_t st)
 {
-    k_accuracy<<<nslices, 256, 0, st>>>(t1.re, t1.im, t2.re, t2.im, sigma, lact, fro2, m, L, tau, delta, bad);
+    // part: nslices x kAccSplit doubles (accuracy_part_bytes)
+    k_accuracy_part<<<dim3(kAccSplit, nslices), 256, 0, st>>>(t1.re, t1.im, t2.re, t2.im, sigma, lact, m, L, tau,
+                                                              part);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    k_accuracy<<<(nslices + 63) / 64, 64, 0, st>>>(part, sigma, lact, fro2, L, tau, delta, bad, nslices);
     return hipGetLastError();
 }
 

@@ -192,8 +192,10 @@ hipError_t launch_rsvd_check(const float2* cols, const double* sigma, const floa
                              const int* lact, const int* prefb, int L, double tau, Planes T, int* fallback, int* rank,
                              int nslices, hipStream_t s);
 hipError_t launch_cm_to_planar(const float2* src, Planes dst, int L, int nslices, hipStream_t s);
+// part: accuracy_part_bytes(nslices) of workspace for the per-band partial sums
+size_t accuracy_part_bytes(int nslices);
 hipError_t launch_accuracy(Planes t1, Planes t2, const double* sigma, const int* lact, const double* fro2, int m,
-                           int L, double tau, double delta, int* bad, int nslices, hipStream_t st);
+                           int L, double tau, double delta, int* bad, int nslices, double* part, hipStream_t st);
 // per-slice features; part: features_part_bytes(m, n, nslices) of scratch
 size_t features_part_bytes(int m, int n, int nslices);
 hipError_t launch_features(const float* yr, const float* yi, int m, int n, int n3, int nslices, double tau,
