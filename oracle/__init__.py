@@ -51,6 +51,8 @@ def _load():
         "or_tubalrank": (_I, [_D, _I, _I, _I, ctypes.c_double, ctypes.c_double]),
         "or_prox_tnn": (_I, [_D, _I, _I, _I, ctypes.c_double, _D]),
         "or_svt_real": (_I, [_D, _I, _I, ctypes.c_double, _D]),
+        "or_tqr": (_I, [_D, _I, _I, _I, _D, _D]),
+        "or_tinv": (_I, [_D, _I, _I, _D]),
         "or_trpca": (_I, [_D, _I, _I, _I, ctypes.c_double, ctypes.c_double, ctypes.c_double, ctypes.c_double,
                           ctypes.c_double, _I, _D, _D, _D, ctypes.POINTER(ctypes.c_int)]),
     }
@@ -235,6 +237,29 @@ def prox_tnn(Y, tau):
     if rc < 0:
         raise ValueError("tau must be >= 0")
     return X
+
+
+def tqr(A):
+    """Theorem 2.4: A = Q * R (FP64), Q orthogonal, R f-upper triangular with
+    real non-negative diagonals of its Fourier slices.  Returns (Q, R)."""
+    A = _real(A)
+    n1, n2, n3 = A.shape
+    Q = np.empty((n1, n1, n3))
+    R = np.empty((n1, n2, n3))
+    _load().or_tqr(_dp(A), n1, n2, n3, _dp(Q), _dp(R))
+    return Q, R
+
+
+def tinv(A):
+    """Definition 2.4: the inverse of a square tensor (FP64).  Returns (B,
+    status) with status 0, or 1 + the first singular Fourier slice."""
+    A = _real(A)
+    n, n2, n3 = A.shape
+    if n != n2:
+        raise ValueError("tinv needs n x n x n3")
+    B = np.empty_like(A)
+    rc = _load().or_tinv(_dp(A), n, n3, _dp(B))
+    return B, int(rc)
 
 
 def trpca(X, lam=None, mu=1e-3, rho=1.1, mu_max=1e10, tol=1e-5, max_iter=500):

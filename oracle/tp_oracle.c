@@ -666,3 +666,187 @@ int or_trpca(const double* X, int n1, int n2, int n3, double lam, double mu, dou
     if (iters) *iters = it;
     return converged;
 }
+
+/* ------------------------------------------------------------------------ */
+/* Tensor QR (Theorem 2.4) and tensor inverse (Definition 2.4)              */
+/* ------------------------------------------------------------------------ */
+/*
+ * Householder QR of the m x n complex matrix a (FP64): a = q r with q m x m
+ * unitary and r m x n upper trapezoidal.  Reflector j makes column j zero
+ * below row j: H = I - 2 v v^* / (v^* v) with v = x + phi |x| e_1, x the part
+ * of column j from row j down and phi the phase of x_0 (so no cancellation),
+ * giving H x = -phi |x| e_1.  q = H_0 H_1 ... H_{k-1} is formed by applying
+ * the reflectors to the identity in reverse order.  Finally row i of r and
+ * column i of q are rephased so that r(i,i) is real and >= 0, which makes the
+ * factorisation unique for full-rank matrices (up to the complement columns
+ * of q when m > n).  On real data every step stays real.
+ */
+static void qr_householder(const or_cplx* a, int m, int n, or_cplx* q, or_cplx* r)
+{
+    const int k = m < n ? m : n;
+    or_cplx* w = (or_cplx*)xmalloc(sizeof(or_cplx) * (size_t)m * n);
+    or_cplx* v = (or_cplx*)xmalloc(sizeof(or_cplx) * (size_t)m * (k > 0 ? k : 1));
+    double* beta = (double*)xmalloc(sizeof(double) * (size_t)(k > 0 ? k : 1));
+    memcpy(w, a, sizeof(or_cplx) * (size_t)m * n);
+    for (int j = 0; j < k; ++j) {
+        double s2 = 0.0;
+        for (int i = j; i < m; ++i) s2 += abs2(w[(i64)i * n + j]);
+        for (int i = 0; i < m; ++i) v[(i64)i * k + j] = 0.0;
+        if (s2 == 0.0) {
+            beta[j] = 0.0;
+            continue;
+        }
+        const double s = sqrt(s2);
+        const or_cplx alpha = w[(i64)j * n + j];
+        const double aa = cabs(alpha);
+        const or_cplx phi = aa > 0.0 ? alpha / aa : 1.0;
+        double vv = 0.0;
+        for (int i = j; i < m; ++i) {
+            const or_cplx vi = (i == j) ? alpha + phi * s : w[(i64)i * n + j];
+            v[(i64)i * k + j] = vi;
+            vv += abs2(vi);
+        }
+        beta[j] = 2.0 / vv;
+        for (int c = j; c < n; ++c) { /* column c <- H column c */
+            or_cplx t = 0.0;
+            for (int i = j; i < m; ++i) t += conj(v[(i64)i * k + j]) * w[(i64)i * n + c];
+            t *= beta[j];
+            for (int i = j; i < m; ++i) w[(i64)i * n + c] -= v[(i64)i * k + j] * t;
+        }
+    }
+    for (int i = 0; i < m; ++i)
+        for (int c = 0; c < m; ++c) q[(i64)i * m + c] = (i == c) ? 1.0 : 0.0;
+    for (int j = k - 1; j >= 0; --j) {
+        if (beta[j] == 0.0) continue;
+        for (int c = j; c < m; ++c) {
+            or_cplx t = 0.0;
+            for (int i = j; i < m; ++i) t += conj(v[(i64)i * k + j]) * q[(i64)i * m + c];
+            t *= beta[j];
+            for (int i = j; i < m; ++i) q[(i64)i * m + c] -= v[(i64)i * k + j] * t;
+        }
+    }
+    for (int i = 0; i < m; ++i)
+        for (int c = 0; c < n; ++c) r[(i64)i * n + c] = (c >= i) ? w[(i64)i * n + c] : 0.0;
+    for (int i = 0; i < k; ++i) { /* r(i,i) real >= 0 */
+        const or_cplx d = r[(i64)i * n + i];
+        const double ad = cabs(d);
+        if (ad == 0.0) continue;
+        const or_cplx ph = conj(d) / ad;
+        for (int c = i; c < n; ++c) r[(i64)i * n + c] *= ph;
+        r[(i64)i * n + i] = ad;
+        for (int row = 0; row < m; ++row) q[(i64)row * m + i] *= conj(ph);
+    }
+    free(w);
+    free(v);
+    free(beta);
+}
+
+/* Theorem 2.4: A = Q * R with Q (n1 x n1 x n3) orthogonal and R (n1 x n2 x n3)
+ * f-upper triangular, by the pipeline of Algorithm 2 with a QR per Fourier
+ * slice (k < h; the rest by conjugate symmetry). */
+int or_tqr(const double* A, int n1, int n2, int n3, double* Q, double* R)
+{
+    if (n1 < 1 || n2 < 1 || n3 < 1) return -1;
+    const int h = n3 / 2 + 1;
+    or_cplx* za = real_to_complex(A, (i64)n1 * n2 * n3);
+    or_cplx* Ab = (or_cplx*)xmalloc(sizeof(or_cplx) * (size_t)n1 * n2 * n3);
+    or_dft3(za, n1, n2, n3, 0, Ab);
+    free(za);
+    or_cplx* Qb = (or_cplx*)xmalloc(sizeof(or_cplx) * (size_t)n1 * n1 * n3);
+    or_cplx* Rb = (or_cplx*)xmalloc(sizeof(or_cplx) * (size_t)n1 * n2 * n3);
+#pragma omp parallel for schedule(dynamic)
+    for (int k = 0; k < h; ++k) {
+        or_cplx* a = (or_cplx*)xmalloc(sizeof(or_cplx) * (size_t)n1 * n2);
+        or_cplx* q = (or_cplx*)xmalloc(sizeof(or_cplx) * (size_t)n1 * n1);
+        or_cplx* r = (or_cplx*)xmalloc(sizeof(or_cplx) * (size_t)n1 * n2);
+        get_slice(Ab, n1, n2, n3, k, a);
+        qr_householder(a, n1, n2, q, r);
+        put_slice(Qb, n1, n1, n3, k, q);
+        put_slice(Rb, n1, n2, n3, k, r);
+        free(a);
+        free(q);
+        free(r);
+    }
+    conj_fill(Qb, n1, n1, n3);
+    conj_fill(Rb, n1, n2, n3);
+    idft_real(Qb, n1, n1, n3, Q);
+    idft_real(Rb, n1, n2, n3, R);
+    free(Ab);
+    free(Qb);
+    free(Rb);
+    return 0;
+}
+
+/* Inverse of the n x n complex matrix a by Gauss-Jordan elimination with
+ * partial pivoting (largest modulus, first on ties) on [a | I].  Returns 0,
+ * or j + 1 when the pivot of step j is zero (singular). */
+static int inv_gauss_jordan(const or_cplx* a, int n, or_cplx* out)
+{
+    const int w2 = 2 * n;
+    or_cplx* w = (or_cplx*)xmalloc(sizeof(or_cplx) * (size_t)n * w2);
+    for (int i = 0; i < n; ++i)
+        for (int c = 0; c < w2; ++c) w[(i64)i * w2 + c] = c < n ? a[(i64)i * n + c] : (c - n == i ? 1.0 : 0.0);
+    int rc = 0;
+    for (int j = 0; j < n && !rc; ++j) {
+        int p = j;
+        double best = cabs(w[(i64)j * w2 + j]);
+        for (int i = j + 1; i < n; ++i) {
+            const double t = cabs(w[(i64)i * w2 + j]);
+            if (t > best) {
+                best = t;
+                p = i;
+            }
+        }
+        if (best == 0.0) {
+            rc = j + 1;
+            break;
+        }
+        if (p != j)
+            for (int c = 0; c < w2; ++c) {
+                const or_cplx t = w[(i64)j * w2 + c];
+                w[(i64)j * w2 + c] = w[(i64)p * w2 + c];
+                w[(i64)p * w2 + c] = t;
+            }
+        const or_cplx piv = w[(i64)j * w2 + j];
+        for (int c = 0; c < w2; ++c) w[(i64)j * w2 + c] /= piv;
+        for (int i = 0; i < n; ++i) {
+            if (i == j) continue;
+            const or_cplx f = w[(i64)i * w2 + j];
+            if (f == 0.0) continue;
+            for (int c = 0; c < w2; ++c) w[(i64)i * w2 + c] -= f * w[(i64)j * w2 + c];
+        }
+    }
+    for (int i = 0; i < n; ++i)
+        for (int c = 0; c < n; ++c) out[(i64)i * n + c] = w[(i64)i * w2 + n + c];
+    free(w);
+    return rc;
+}
+
+/* Definition 2.4: B with A * B = B * A = I, slice by slice in the Fourier
+ * domain (the Fourier slices of I are identities).  Returns 0, or 1 + the
+ * first Fourier slice (k < h) that is singular (B then undefined). */
+int or_tinv(const double* A, int n, int n3, double* B)
+{
+    if (n < 1 || n3 < 1) return -1;
+    const int h = n3 / 2 + 1;
+    or_cplx* za = real_to_complex(A, (i64)n * n * n3);
+    or_cplx* Ab = (or_cplx*)xmalloc(sizeof(or_cplx) * (size_t)n * n * n3);
+    or_dft3(za, n, n, n3, 0, Ab);
+    free(za);
+    or_cplx* Bb = (or_cplx*)xmalloc(sizeof(or_cplx) * (size_t)n * n * n3);
+    int bad = 0;
+    for (int k = 0; k < h; ++k) {
+        or_cplx* a = (or_cplx*)xmalloc(sizeof(or_cplx) * (size_t)n * n);
+        or_cplx* b = (or_cplx*)xmalloc(sizeof(or_cplx) * (size_t)n * n);
+        get_slice(Ab, n, n, n3, k, a);
+        if (inv_gauss_jordan(a, n, b) && !bad) bad = k + 1;
+        put_slice(Bb, n, n, n3, k, b);
+        free(a);
+        free(b);
+    }
+    conj_fill(Bb, n, n, n3);
+    idft_real(Bb, n, n, n3, B);
+    free(Ab);
+    free(Bb);
+    return bad;
+}

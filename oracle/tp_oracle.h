@@ -83,6 +83,14 @@ double or_tsn(const double* A, int n1, int n2, int n3);
 int or_tubalrank(const double* A, int n1, int n2, int n3, double tol, double eps);
 /* Theorem 2.3 / Algorithm 3: Prox of the TNN at tau. */
 int or_prox_tnn(const double* Y, int n1, int n2, int n3, double tau, double* X);
+/* Theorem 2.4 (T-QR): A = Q * R, Q n1 x n1 x n3 orthogonal, R n1 x n2 x n3
+ * f-upper triangular; per Fourier slice a Householder QR with diag(R) real
+ * and >= 0.  Returns 0 (< 0 on a bad argument). */
+int or_tqr(const double* A, int n1, int n2, int n3, double* Q, double* R);
+/* Definition 2.4: the inverse B of the n x n x n3 tensor A (Gauss-Jordan with
+ * partial pivoting per Fourier slice).  Returns 0, or 1 + the first singular
+ * Fourier slice (< 0 on a bad argument). */
+int or_tinv(const double* A, int n, int n3, double* B);
 /* Tensor robust PCA, min ||L||_* + lam ||S||_1 s.t. L + S = X, by the inexact
  * augmented Lagrangian method around or_prox_tnn (the paper names the problem
  * but gives no algorithm; the steps are listed in tp_oracle.c).  L, S, Lam
