@@ -252,6 +252,34 @@ int tp_mlp_adam(float* params, const float* grad, float* m, float* v, int step, 
                 float beta2, float eps, void* stream);
 
 /*
+ * Tensor inverse (Definition 2.4): B with A * B = B * A = I for a square
+ * n x n x n3 tensor A.  The Fourier slices of I are identities, so B's
+ * slices are the inverses of A's: real DFT, Gauss-Jordan with partial
+ * pivoting (largest modulus, first row on ties; FP32 data, FP64 moduli) on
+ * each of the floor(n3/2)+1 leading slices, inverse DFT.  n <= 1024.
+ *   A, B   device n x n x n3
+ *   info   device int[floor(n3/2)+1] or NULL: 0, or j+1 when slice k's pivot
+ *          of step j is zero (a singular slice; B is then undefined)
+ */
+size_t tp_tinv_workspace_size(int n, int n3);
+int tp_tinv(const float* A, float* B, int n, int n3, int* info, void* workspace, size_t workspace_bytes,
+            void* stream);
+
+/*
+ * T-QR (Theorem 2.4): A = Q * R with Q (n1 x n1 x n3) orthogonal
+ * (Definition 2.5) and R (n1 x n2 x n3) f-upper triangular.  Per Fourier
+ * slice a Householder QR (FP32 data, FP64 norms and dot products), with row i
+ * of R and column i of Q rephased so that the Fourier slices of R have real,
+ * non-negative diagonals: R is then unique for full-rank slices, and so are
+ * Q's first min(n1, n2) columns (the rest complete the basis).  The theorem
+ * names the orthogonal factor U; it is Q.
+ *   A      device n1 x n2 x n3;  Q  device n1 x n1 x n3;  R  device n1 x n2 x n3
+ */
+size_t tp_tqr_workspace_size(int n1, int n2, int n3);
+int tp_tqr(const float* A, float* Q, float* R, int n1, int n2, int n3, void* workspace, size_t workspace_bytes,
+           void* stream);
+
+/*
  * Tensor robust PCA, the recovery problem the paper names as the use of the
  * TNN and its prox (Section 1; eq (19) and Theorem 2.3):
  *   min ||L||_* + lambda ||S||_1   s.t.   L + S = X

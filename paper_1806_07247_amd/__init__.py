@@ -188,6 +188,36 @@ def tp_prox_tnn_learned(Y, tau, mlp=None, fixed_rank=0, prev_rank=None, prev_sig
     return X
 
 
+def tp_tinv(A, out=None, info=None, workspace=None):
+    """Tensor inverse (Definition 2.4) of a square n x n x n3 tensor; info:
+    optional int32 device tensor of half_slices(n3) (0, or j+1 for a singular
+    slice)."""
+    lib = _lib.load()
+    A = _dev_tensor(A, "A")
+    n, n2, n3 = A.shape
+    if n != n2:
+        raise ValueError("tp_tinv needs an n x n x n3 tensor")
+    B = out if out is not None else torch.empty_like(A)
+    ws = workspace if workspace is not None else _workspace(lib.tp_tinv_workspace_size(n, n3), A.device)
+    st = lib.tp_tinv(A.data_ptr(), B.data_ptr(), n, n3, _ptr(info), ws.data_ptr(), ws.numel(), _stream(A.device))
+    _lib.check("tp_tinv", st)
+    return B
+
+
+def tp_tqr(A, workspace=None):
+    """T-QR (Theorem 2.4): returns (Q, R) with A = Q * R."""
+    lib = _lib.load()
+    A = _dev_tensor(A, "A")
+    n1, n2, n3 = A.shape
+    Q = torch.empty((n1, n1, n3), dtype=torch.float32, device=A.device)
+    R = torch.empty_like(A)
+    ws = workspace if workspace is not None else _workspace(lib.tp_tqr_workspace_size(n1, n2, n3), A.device)
+    st = lib.tp_tqr(A.data_ptr(), Q.data_ptr(), R.data_ptr(), n1, n2, n3, ws.data_ptr(), ws.numel(),
+                    _stream(A.device))
+    _lib.check("tp_tqr", st)
+    return Q, R
+
+
 def tp_trpca_workspace_size_for(shape, learned=None, **kw):
     """Workspace bytes of tp_trpca for an X of this shape and these settings."""
     n1, n2, n3 = (int(v) for v in shape)

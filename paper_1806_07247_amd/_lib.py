@@ -54,6 +54,14 @@ class LearnedOpts(ctypes.Structure):
                 ("basis_out", _VP), ("basis_cols_out", _VP)]
 
 
+SIGNATURES.update({
+    "tp_tinv_workspace_size": (_SZ, [_I, _I]),
+    "tp_tinv": (_I, [_VP, _VP, _I, _I, _VP, _VP, _SZ, _VP]),
+    "tp_tqr_workspace_size": (_SZ, [_I, _I, _I]),
+    "tp_tqr": (_I, [_VP, _VP, _VP, _I, _I, _I, _VP, _SZ, _VP]),
+})
+
+
 class TrpcaOpts(ctypes.Structure):
     """tp_trpca_opts of include/tp.h"""
     _fields_ = [("lam", _F), ("mu", _F), ("rho", _F), ("mu_max", _F), ("tol", _F), ("max_iter", _I),

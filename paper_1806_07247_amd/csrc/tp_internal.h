@@ -218,6 +218,14 @@ hipError_t launch_gather(const float* sr, const float* si, float* dr, float* di,
 // current value of a TP_PARAM_* setting (tp_set_param), default if unset
 int param(int key);
 
+// per-slice inverse (Gauss-Jordan) and QR (Householder) of the tensor
+// inverse and T-QR: one workgroup per slice, planar complex slices
+hipError_t launch_slice_inv(const float* ar, const float* ai, float* wr, float* wi, float* br, float* bi, int n,
+                            int nslices, int* info, hipStream_t st);
+hipError_t launch_slice_qr(const float* ar, const float* ai, float* wr, float* wi, float* vr, float* vi,
+                           double* beta, float* qr, float* qi, float* rr, float* ri, int m, int n, int nslices,
+                           hipStream_t st);
+
 // ------------------------------------------------------------- tracing ----
 enum KernelId {
     K_RFFT = 0, K_IRFFT = 1, K_CGEMM = 2, K_JACOBI = 3, K_SHRINK = 4, K_TNN_REDUCE = 5, K_TSVD_FINISH = 6,
