@@ -162,14 +162,28 @@ __global__ __launch_bounds__(256) void k_gram(const float* __restrict__ yr, cons
 // is the right-looking Cholesky G = R^* R; the same row operations turn I
 // into M = R^{-*} (they are the E with E G = R), so Rinv = M^* is formed in
 // the same L steps.  The entries stay in registers (the upper triangle of G
-// and the strict lower triangle of M share one slot per (a, b)); the owners
-// of row j+1 publish it to LDS after their update (two row buffers, one
-// barrier per step).  Rinv is written as FP32 planar
-// (identity on the inactive columns); optionally Rtot <- R Rtot (FP64) and
-// R2^* (FP32 planar, zero outside the active block).
+// and the strict lower triangle of M share one slot per (a, b)).  The sweep
+// is blocked by panels of kPanel rows, one panel per wavefront: the owner
+// takes its panel's steps alone (the pivot row is broadcast across the
+// wavefront with readlane, no barrier), publishes the normalized panel rows
+// to LDS, and after one barrier every later wavefront applies those steps to
+// its rows in step order (the same operations, in the same order, as the
+// unblocked sweep).  Rinv is written as FP32 planar (identity on the
+// inactive columns); optionally Rtot <- R Rtot (FP64) and R2^* (FP32 planar,
+// zero outside the active block).
 constexpr int kCholThreads = 1024;
 constexpr int kCholEntries = kMaxL * kMaxL / kCholThreads;  // entries per thread (rows per wavefront)
+constexpr int kPanel = kCholEntries;                          // rows of one panel = rows of one wavefront
 static_assert(kMaxL == 64 && kCholThreads / 64 * kCholEntries == kMaxL, "one lane per column, 16 waves x 4 rows");
+
+// value of v in lane l (l wavefront-uniform; every lane computed v)
+__device__ __forceinline__ double read_lane(double v, int l)
+{
+    const unsigned long long u = (unsigned long long)__double_as_longlong(v);
+    const unsigned lo = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)u, l);
+    const unsigned hi = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)(u >> 32), l);
+    return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
+}
 
 __global__ __launch_bounds__(kCholThreads) void k_chol(const double2* __restrict__ part, int nsplit, int L,
                                                        const int* __restrict__ lact, int pass, float* __restrict__ rir,
@@ -180,26 +194,25 @@ __global__ __launch_bounds__(kCholThreads) void k_chol(const double2* __restrict
     extern __shared__ double2 sh[];
     double2* R = sh;            // L x L (R, for the Rtot product)
     double2* X = sh + L * L;    // L x L (Rtot)
-    __shared__ double2 rowG[2][kMaxL];  // the published row (R and M' parts), two buffers
-    __shared__ double2 piv[2];  // (R_jj, 1 / R_jj) of the published row
+    __shared__ double2 pan[2][kPanel][kMaxL];  // the published normalized panel rows, two buffers
     __shared__ double diag[kMaxL];
     const int s = blockIdx.x, tid = threadIdx.x, nt = blockDim.x;
     const int la = lact[s];
     const double2* P = part + (long long)s * nsplit * L * L;
 
     // One value per entry (a, b), held by lane b of wavefront w for the rows
-    // a = w + 16 u: the G side for b >= a, the M side for b < a (the two
+    // a = kPanel w + u: the G side for b >= a, the M side for b < a (the two
     // share a slot: M_ab is zero until column b is eliminated, and the slot is
-    // reset at that step); M_aa = 1 / R_aa is implicit.  A row is one
-    // wavefront's, so rows already eliminated are skipped as a whole.  Plain
-    // doubles, so that the values stay in registers.
+    // reset at that step); the slot of (a, a) holds R_aa once row a is
+    // eliminated (M_aa = 1 / R_aa).  Plain doubles, so that the values stay
+    // in registers.
     const int lane = tid & 63, wave = tid >> 6;
     int ea[kCholEntries];
     double vr[kCholEntries], vi[kCholEntries];
     const int b = lane;
 #pragma unroll
     for (int u = 0; u < kCholEntries; ++u) {
-        const int a0 = wave + (kCholThreads / 64) * u;
+        const int a0 = kPanel * wave + u;
         ea[u] = (a0 < L && b < L) ? a0 : L;  // L: no entry
         vr[u] = vi[u] = 0.0;
         if (ea[u] < L && b >= ea[u]) {
@@ -230,59 +243,73 @@ __global__ __launch_bounds__(kCholThreads) void k_chol(const double2* __restrict
         for (int k = 0; k < la; ++k) tr += diag[k];
         sd = 1e-13 * tr / la;
     }
-    // the owner of diagonal entry (j, j) forms the pivot of step j once, when
-    // it publishes row j (inactive rows: pivot 1)
-    bool broke = false;
-    auto pivot = [&](int j, double d, int buf) {
-        double p = j < la ? d : 1.0;
-        if (!(p > 0.0)) {
-            p = 1e-300;
-            broke = true;
-        }
-        const double r = sqrt(p);
-        piv[buf] = make_double2(r, 1.0 / r);
-    };
 #pragma unroll
-    for (int u = 0; u < kCholEntries; ++u) {
+    for (int u = 0; u < kCholEntries; ++u)
         if (ea[u] == b && b < la) vr[u] += sd;
-        if (ea[u] == 0) {  // publish row 0
-            rowG[0][b] = make_double2(vr[u], vi[u]);
-            if (b == 0) pivot(0, vr[u], 0);
-        }
-    }
-    __syncthreads();
-    for (int j = 0; j < L; ++j) {
-        const int cur = j & 1, nxt = cur ^ 1;
-        const bool act = j < la;
-        const double2 pv = piv[cur];
-        const double rjj = pv.x, inv = pv.y;
-        // y_b: R_jb (b > j; zero outside the active block), M'_jb (b < j), M'_jj = 1 / R_jj
-        double yr = inv, yi = 0.0;
-        if (b != j) {
-            const double2 t = (b < j || (act && b < la)) ? rowG[cur][b] : make_double2(0.0, 0.0);
-            yr = t.x * inv;
-            yi = t.y * inv;
-        }
+
+    bool broke = false;
+    // steps j = kPanel p .. of panel p by its owner (all 64 lanes take part,
+    // so that readlane sees computed values); writes pan[buf]
+    auto factor = [&](int p, int buf) {
 #pragma unroll
-        for (int u = 0; u < kCholEntries; ++u) {
-            const int a = ea[u];
-            if (a < L && a >= j) {
-                if (a == j) {  // row j: R_jb, R_jj, M'_jb
-                    vr[u] = b == j ? rjj : yr;
-                    vi[u] = b == j ? 0.0 : yi;
-                } else {
-                    const double2 ra = (act && a < la) ? rowG[cur][a] : make_double2(0.0, 0.0);
-                    const double xr = ra.x * inv, xi = ra.y * inv;  // R_ja
-                    // v_ab -= conj(R_ja) y_b; column j enters the M side from zero
-                    const double br = b == j ? 0.0 : vr[u], bi = b == j ? 0.0 : vi[u];
-                    vr[u] = br - (xr * yr + xi * yi);
-                    vi[u] = bi - (xr * yi - xi * yr);
-                }
-                if (a == j + 1) {  // publish row j+1 for the next step
-                    rowG[nxt][b] = make_double2(vr[u], vi[u]);
-                    if (b == a) pivot(a, vr[u], nxt);
-                }
+        for (int t = 0; t < kPanel; ++t) {
+            const int j = kPanel * p + t;
+            if (j >= L) break;
+            const bool act = j < la;
+            // pivot of step j (inactive rows: pivot 1)
+            double pv = act ? read_lane(vr[t], j) : 1.0;
+            if (!(pv > 0.0)) {
+                pv = 1e-300;
+                broke = true;
             }
+            const double rjj = sqrt(pv), inv = 1.0 / rjj;
+            // y_b: R_jb (b > j; zero outside the active block), M'_jb (b < j), M'_jj = 1 / R_jj
+            double yr = inv, yi = 0.0;
+            if (b != j) {
+                const bool keep = b < j || (act && b < la);
+                yr = keep ? vr[t] * inv : 0.0;
+                yi = keep ? vi[t] * inv : 0.0;
+            }
+            vr[t] = b == j ? rjj : yr;
+            vi[t] = b == j ? 0.0 : yi;
+            pan[buf][t][b] = make_double2(yr, yi);
+#pragma unroll
+            for (int u = t + 1; u < kPanel; ++u) {
+                const int a = kPanel * p + u;
+                if (a >= L) break;
+                const double xr = read_lane(yr, a), xi = read_lane(yi, a);  // R_ja (zero unless active)
+                // v_ab -= conj(R_ja) y_b; column j enters the M side from zero
+                const double br = b == j ? 0.0 : vr[u], bi = b == j ? 0.0 : vi[u];
+                vr[u] = br - (xr * yr + xi * yi);
+                vi[u] = bi - (xr * yi - xi * yr);
+            }
+        }
+    };
+    // the steps of panel p (published in pan[buf]) on this wavefront's rows
+    auto apply = [&](int p, int buf) {
+#pragma unroll
+        for (int t = 0; t < kPanel; ++t) {
+            const int j = kPanel * p + t;
+            if (j >= L) break;
+            const double2 y = pan[buf][t][b];
+#pragma unroll
+            for (int u = 0; u < kPanel; ++u) {
+                const int a = kPanel * wave + u;
+                if (a >= L) break;
+                const double2 x = pan[buf][t][a];  // R_ja
+                const double br = b == j ? 0.0 : vr[u], bi = b == j ? 0.0 : vi[u];
+                vr[u] = br - (x.x * y.x + x.y * y.y);
+                vi[u] = bi - (x.x * y.y - x.y * y.x);
+            }
+        }
+    };
+    const int npan = (L + kPanel - 1) / kPanel;
+    if (wave == 0) factor(0, 0);
+    __syncthreads();
+    for (int p = 0; p + 1 < npan; ++p) {
+        if (wave > p && wave < npan) {
+            apply(p, p & 1);
+            if (wave == p + 1) factor(p + 1, (p + 1) & 1);
         }
         __syncthreads();
     }
@@ -894,7 +921,7 @@ hipError_t launch_cholqr_pass(const float* yr, const float* yi, int m, int L, co
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     const size_t lds = 2 * (size_t)L * L * sizeof(double2);
-    if (lds + 8 * 1024 > 64 * 1024) {  // dynamic + the static row buffers
+    if (lds + 16 * 1024 > 64 * 1024) {  // dynamic + the static panel buffers
         e = hipFuncSetAttribute((const void*)k_chol, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
         if (e != hipSuccess) return e;
     }
