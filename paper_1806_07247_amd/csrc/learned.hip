@@ -176,6 +176,20 @@ constexpr int kCholEntries = kMaxL * kMaxL / kCholThreads;  // entries per threa
 constexpr int kPanel = kCholEntries;                          // rows of one panel = rows of one wavefront
 static_assert(kMaxL == 64 && kCholThreads / 64 * kCholEntries == kMaxL, "one lane per column, 16 waves x 4 rows");
 
+// sqrt(p) and 1/sqrt(p), p > 0 normal: the hardware reciprocal square root
+// refined by two Newton steps, then one Newton step on sqrt(p) = p / sqrt(p)
+__device__ __forceinline__ void sqrt_and_rsqrt(double p, double& r, double& inv)
+{
+    double y = __builtin_amdgcn_rsq(p);
+    double h = p * y;
+    y = fma(0.5 * y, fma(-h, y, 1.0), y);
+    h = p * y;
+    y = fma(0.5 * y, fma(-h, y, 1.0), y);
+    const double q = p * y;
+    r = fma(0.5 * y, fma(-q, q, p), q);
+    inv = y;
+}
+
 // value of v in lane l (l wavefront-uniform; every lane computed v)
 __device__ __forceinline__ double read_lane(double v, int l)
 {
@@ -195,7 +209,6 @@ __global__ __launch_bounds__(kCholThreads) void k_chol(const double2* __restrict
     double2* R = sh;            // L x L (R, for the Rtot product)
     double2* X = sh + L * L;    // L x L (Rtot)
     __shared__ double2 pan[2][kPanel][kMaxL];  // the published normalized panel rows, two buffers
-    __shared__ double diag[kMaxL];
     const int s = blockIdx.x, tid = threadIdx.x, nt = blockDim.x;
     const int la = lact[s];
     const double2* P = part + (long long)s * nsplit * L * L;
@@ -206,46 +219,57 @@ __global__ __launch_bounds__(kCholThreads) void k_chol(const double2* __restrict
     // reset at that step); the slot of (a, a) holds R_aa once row a is
     // eliminated (M_aa = 1 / R_aa).  Plain doubles, so that the values stay
     // in registers.
+    // G = the sum of the partials in the fixed order w = 0, 1, ... (upper
+    // triangle; one entry per thread with all of its partials in flight),
+    // staged in R
+    const int nup = L * (L + 1) / 2;
+    for (int e = tid; e < nup; e += nt) {
+        int a = 0, r = e;
+        while (r >= L - a) {
+            r -= L - a;
+            ++a;
+        }
+        const int o = a * L + a + r;
+        double pr[kMaxGramSplit], pi[kMaxGramSplit];
+#pragma unroll
+        for (int w = 0; w < kMaxGramSplit; ++w) {
+            const double2 v = w < nsplit ? P[(long long)w * L * L + o] : make_double2(0.0, 0.0);
+            pr[w] = v.x;
+            pi[w] = v.y;
+        }
+        double gr = 0.0, gi = 0.0;
+#pragma unroll
+        for (int w = 0; w < kMaxGramSplit; ++w) {
+            if (w < nsplit) {
+                gr += pr[w];
+                gi += pi[w];
+            }
+        }
+        R[o] = make_double2(gr, gi);
+    }
+    __syncthreads();
     const int lane = tid & 63, wave = tid >> 6;
     int ea[kCholEntries];
     double vr[kCholEntries], vi[kCholEntries];
     const int b = lane;
+    // diagonal shift (pass 0): every thread sums the same values in the same order
+    double sd = 0.0;
+    if (pass == 0 && la > 0) {
+        double tr = 0.0;
+        for (int k = 0; k < la; ++k) tr += R[k * L + k].x;
+        sd = 1e-13 * tr / la;
+    }
 #pragma unroll
     for (int u = 0; u < kCholEntries; ++u) {
         const int a0 = kPanel * wave + u;
         ea[u] = (a0 < L && b < L) ? a0 : L;  // L: no entry
         vr[u] = vi[u] = 0.0;
         if (ea[u] < L && b >= ea[u]) {
-            // all partials in flight at once, then summed in the fixed order w = 0, 1, ...
-            const int e = ea[u] * L + b;
-            double pr[kMaxGramSplit], pi[kMaxGramSplit];
-#pragma unroll
-            for (int w = 0; w < kMaxGramSplit; ++w) {
-                const double2 v = w < nsplit ? P[(long long)w * L * L + e] : make_double2(0.0, 0.0);
-                pr[w] = v.x;
-                pi[w] = v.y;
-            }
-#pragma unroll
-            for (int w = 0; w < kMaxGramSplit; ++w) {
-                if (w < nsplit) {
-                    vr[u] += pr[w];
-                    vi[u] += pi[w];
-                }
-            }
-            if (ea[u] == b) diag[b] = vr[u];
+            const double2 g = R[ea[u] * L + b];
+            vr[u] = g.x + (ea[u] == b && b < la ? sd : 0.0);
+            vi[u] = g.y;
         }
     }
-    __syncthreads();
-    // diagonal shift (pass 0): every thread sums the same values in the same order
-    double sd = 0.0;
-    if (pass == 0 && la > 0) {
-        double tr = 0.0;
-        for (int k = 0; k < la; ++k) tr += diag[k];
-        sd = 1e-13 * tr / la;
-    }
-#pragma unroll
-    for (int u = 0; u < kCholEntries; ++u)
-        if (ea[u] == b && b < la) vr[u] += sd;
 
     bool broke = false;
     // steps j = kPanel p .. of panel p by its owner (all 64 lanes take part,
@@ -262,7 +286,8 @@ __global__ __launch_bounds__(kCholThreads) void k_chol(const double2* __restrict
                 pv = 1e-300;
                 broke = true;
             }
-            const double rjj = sqrt(pv), inv = 1.0 / rjj;
+            double rjj, inv;
+            sqrt_and_rsqrt(pv, rjj, inv);
             // y_b: R_jb (b > j; zero outside the active block), M'_jb (b < j), M'_jj = 1 / R_jj
             double yr = inv, yi = 0.0;
             if (b != j) {
