@@ -413,7 +413,11 @@ int tp_batch_destroy(tp_batch* plan);
  *   TP_PARAM_JACOBI_SWEEPS        sweep cap (default 30)
  *   TP_PARAM_GEMM_VARIANT         slice GEMM tile variant: 0 = by shape, 1 = 64x64,
  *                                 2 = 128x128, 3 = 128x64, 4 = 128x32, 5 = 256x16,
- *                                 6 = 64x48 (output rows x columns per workgroup)
+ *                                 6 = 64x48 (output rows x columns per workgroup),
+ *                                 7 = narrow-output kernel (FP32, op(B) = B, at most
+ *                                 64 output columns and a multiple of 4, inner
+ *                                 dimension >= 64; by shape it takes every such
+ *                                 product, variants 1 .. 6 keep them on the tiles)
  *   TP_PARAM_FFT_GRID             persistent workgroups per compute unit of the
  *                                 tube transforms (0 = default 8)
  *   TP_PARAM_GEMM_BK              FP32 slice GEMM inner-dimension stage: 16 or 32

@@ -20,8 +20,9 @@
 // TM x TN MFMA tiles of 16 x 16.  Operand panels (BM x BK of op(A), BN x BK of
 // op(B)) are staged through LDS, double buffered, with k contiguous so that
 // each lane reads its MFMA operands with 16-byte LDS loads.  Tile shapes from
-// 64 x 64 to 256 x 16 cover square products and the skinny products of the
-// randomized SVD (a few dozen columns).
+// 64 x 64 to 256 x 16 cover square products; FP32 products with at most 64
+// output columns (the range-finder products of the randomized SVD) take a
+// dedicated kernel that streams op(A) straight into registers.
 #include "tp_internal.h"
 
 namespace tp {
@@ -450,6 +451,256 @@ __global__ __launch_bounds__(256) void k_splitk_reduce(CgemmArgs p)
     }
 }
 
+// ------------------------------------------------------------ skinny FP32 --
+// Narrow outputs with a long inner dimension: op(A) (m x k) B (k x n),
+// n <= 64 and a multiple of 4, B not transposed (the range-finder
+// products).  A workgroup of four wavefronts computes 64 output rows x all
+// n columns over one inner-dimension part.  Each wavefront loads its 16 rows
+// of op(A) straight from global memory into registers, already in the MFMA
+// operand layout, with the next two 32-deep stages in flight while one is
+// multiplied; B goes through LDS (one 32 x n stage, transposed, shared by
+// the four wavefronts, double-buffered).  3M complex form.  The MFMAs take
+// the B fragment as their first operand, so that they accumulate the
+// transposed 16 x 16 tile: lane (r, g) ends with output row r and the four
+// columns 4g .. 4g+3 (one 16-byte store per plane).
+//
+// Operand layout of one 32-deep stage at k0, for lane (r, g) = (lane % 16,
+// lane / 16): MFMA step (h, s), h = 0, 1 and s = 0 .. 3, takes inner index
+// k0 + 16 h + 4 g + s, which is op(A)(row r, .) and B(., column r of the
+// column tile); over the 8 steps each of the 32 inner indices enters once.
+constexpr int kSkBK = 32;
+constexpr int kSkLDK = kSkBK + 4;  // padded row of the transposed B stage
+constexpr int kSkRows = 64;
+
+struct AStage {
+    float4 r[2], i[2];
+};
+
+// FAST: the whole stage lies inside the part and the row exists, and (OP_N)
+// the planes allow 16-byte loads; no masks, so that no load sits behind a
+// branch (a divergent load would make the compiler wait for every load in
+// flight where the paths merge)
+template <int OPA, bool FAST>
+__device__ __forceinline__ void sk_load_a(AStage& a, const SliceView& v, const CgemmArgs& p, int row, int k0, int g,
+                                          bool vec)
+{
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+        const int kb = k0 + 16 * h + 4 * g;
+        if (OPA == OP_N) {
+            const long long off = (long long)row * p.lda + kb;
+            if (FAST) {
+                a.r[h] = *reinterpret_cast<const float4*>(v.ar + off);
+                a.i[h] = *reinterpret_cast<const float4*>(v.ai + off);
+            } else {
+                const int valid = row < p.m ? max(0, min(4, v.K - kb)) : 0;
+                const Quad q = load4(v.ar, v.ai, off, valid, vec, false);
+                a.r[h] = q.r;
+                a.i[h] = q.i;
+            }
+        } else {  // A(k, row), A stored k x m; the conjugation of op(A) enters the arithmetic
+            const int valid = FAST ? 4 : (row < p.m ? max(0, min(4, v.K - kb)) : 0);
+            float xr[4], xi[4];
+#pragma unroll
+            for (int s = 0; s < 4; ++s) {
+                const long long off = (long long)(kb + s) * p.lda + row;
+                xr[s] = FAST || s < valid ? v.ar[off] : 0.0f;
+                xi[s] = FAST || s < valid ? v.ai[off] : 0.0f;
+            }
+            a.r[h] = make_float4(xr[0], xr[1], xr[2], xr[3]);
+            a.i[h] = make_float4(xi[0], xi[1], xi[2], xi[3]);
+        }
+    }
+}
+
+template <int TN>
+constexpr int sk_plane()  // one plane of one B buffer: NC = 16 TN staged columns
+{
+    return 16 * TN * kSkLDK;
+}
+
+// the workgroup's tile (x = row tile) of slice view v; REAL: real slice
+// (only the real planes enter)
+template <int OPA, int TN, bool REAL, bool FAST>
+__device__ __forceinline__ void sk_tile(const CgemmArgs& p, const SliceView& v, int x, float* lds)
+{
+    constexpr int NC = 16 * TN;                   // B columns staged (n rounded up to the tile)
+    constexpr int GB = (kSkBK * NC / 4 + 255) / 256;  // 4-column groups of a B stage per thread
+    constexpr int PL = sk_plane<TN>();
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int r = lane & 15, g = lane >> 4;
+    const int row = x * kSkRows + 16 * wave + r;
+    const bool veca = OPA == OP_N && vec_ok(v.ar, v.ai, p.lda);
+    const bool vecb = vec_ok(v.br, v.bi, p.ldb);
+    const int nst = (v.K - v.K0 + kSkBK - 1) / kSkBK;
+
+    floatx4 p1[TN], p2[TN], p3[TN];
+#pragma unroll
+    for (int t = 0; t < TN; ++t) p1[t] = p2[t] = p3[t] = floatx4{0.f, 0.f, 0.f, 0.f};
+
+    Quad bq[GB];
+    bool bok[GB];  // FAST: the group lies in the stage and in the n columns (else stored as zeros)
+#pragma unroll
+    for (int u = 0; u < GB; ++u) {
+        const int e = tid + 256 * u;
+        bok[u] = e < kSkBK * NC / 4 && 4 * (e % (NC / 4)) < p.n;
+    }
+    // B stage at k0 into registers (zero outside k < K and columns < n)
+    auto load_b = [&](int k0) {
+#pragma unroll
+        for (int u = 0; u < GB; ++u) {
+            const int e = tid + 256 * u;
+            const int kr = e / (NC / 4), col = 4 * (e % (NC / 4));
+            const int k = k0 + kr;
+            if (FAST) {  // clamped in-range load; the mask is applied when it is stored
+                const long long off = (long long)(bok[u] ? k : k0) * p.ldb + (bok[u] ? col : 0);
+                bq[u].r = *reinterpret_cast<const float4*>(v.br + off);
+                bq[u].i = *reinterpret_cast<const float4*>(v.bi + off);
+            } else {
+                const int valid = (e < kSkBK * NC / 4 && k < v.K) ? max(0, min(4, p.n - col)) : 0;
+                bq[u] = load4(v.br, v.bi, (long long)k * p.ldb + col, valid, vecb, false);
+            }
+        }
+    };
+    // the staged registers into LDS buffer buf, transposed (column-major in k)
+    auto store_b = [&](int buf) {
+        float* br = lds + buf * 2 * PL;
+        float* bi = br + PL;
+#pragma unroll
+        for (int u = 0; u < GB; ++u) {
+            const int e = tid + 256 * u;
+            if (e < kSkBK * NC / 4) {
+                const int kr = e / (NC / 4), col = 4 * (e % (NC / 4));
+                if (FAST && !bok[u]) bq[u].r = bq[u].i = make_float4(0.f, 0.f, 0.f, 0.f);
+                br[(col + 0) * kSkLDK + kr] = bq[u].r.x;
+                br[(col + 1) * kSkLDK + kr] = bq[u].r.y;
+                br[(col + 2) * kSkLDK + kr] = bq[u].r.z;
+                br[(col + 3) * kSkLDK + kr] = bq[u].r.w;
+                bi[(col + 0) * kSkLDK + kr] = bq[u].i.x;
+                bi[(col + 1) * kSkLDK + kr] = bq[u].i.y;
+                bi[(col + 2) * kSkLDK + kr] = bq[u].i.z;
+                bi[(col + 3) * kSkLDK + kr] = bq[u].i.w;
+            }
+        }
+    };
+    auto compute = [&](const AStage& a, int buf) {
+        const float* br = lds + buf * 2 * PL;
+        const float* bi = br + PL;
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+            float4 fr[TN], fi[TN];
+#pragma unroll
+            for (int t = 0; t < TN; ++t) {
+                const int off = (16 * t + r) * kSkLDK + 16 * h + 4 * g;
+                fr[t] = *reinterpret_cast<const float4*>(br + off);
+                fi[t] = *reinterpret_cast<const float4*>(bi + off);
+            }
+#pragma unroll
+            for (int s = 0; s < 4; ++s) {
+                // OP_C: ai is Im A(k, row), op(A) has -ai; p2 then holds +sum b_i ai
+                const float ar = (&a.r[h].x)[s], ai = (&a.i[h].x)[s];
+                const float as = OPA == OP_C ? ar - ai : ar + ai;
+#pragma unroll
+                for (int t = 0; t < TN; ++t) {
+                    const float b_r = (&fr[t].x)[s], b_i = (&fi[t].x)[s];
+                    p1[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(b_r, ar, p1[t], 0, 0, 0);
+                    if (!REAL) {
+                        p2[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(b_i, ai, p2[t], 0, 0, 0);
+                        p3[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(b_r + b_i, as, p3[t], 0, 0, 0);
+                    }
+                }
+            }
+        }
+    };
+    // stage st: publish B stage st+1 (loaded during stage st-1), prefetch B
+    // stage st+2 (registers) and then A stage st+2 (into nxt2, the slot stage
+    // st-1 used), multiply stage st.  Loads complete in issue order, so the
+    // one wait (for B stage st+1, at the top) leaves A stage st+1 in flight;
+    // the scheduling barriers keep that order.  Prefetches past the end
+    // re-read the last stage (never used), so that no load sits behind a
+    // branch.
+    auto body = [&](int st, const AStage& cur, AStage& nxt2) {
+        store_b((st + 1) & 1);
+        const int nx = min(st + 2, nst - 1);
+        load_b(v.K0 + kSkBK * nx);
+        __builtin_amdgcn_sched_barrier(0);
+        sk_load_a<OPA, FAST>(nxt2, v, p, row, v.K0 + kSkBK * nx, g, veca);
+        __builtin_amdgcn_sched_barrier(0);
+        compute(cur, st & 1);
+        __syncthreads();
+    };
+
+    AStage a0, a1, a2;
+    if (nst > 0) {
+        load_b(v.K0);
+        __builtin_amdgcn_sched_barrier(0);
+        sk_load_a<OPA, FAST>(a0, v, p, row, v.K0, g, veca);
+        sk_load_a<OPA, FAST>(a1, v, p, row, v.K0 + kSkBK * min(1, nst - 1), g, veca);
+        __builtin_amdgcn_sched_barrier(0);
+        store_b(0);
+        load_b(v.K0 + kSkBK * min(1, nst - 1));
+    }
+    __syncthreads();
+    int st = 0;
+    for (; st + 3 <= nst; st += 3) {
+        body(st, a0, a2);
+        body(st + 1, a1, a0);
+        body(st + 2, a2, a1);
+    }
+    if (st < nst) body(st, a0, a2);
+    if (st + 1 < nst) body(st + 1, a1, a0);
+
+    // epilogue: lane (r, g) holds row `row`, columns 16 t + 4 g .. + 3
+    if (row < p.m) {
+        const bool vecc = ((reinterpret_cast<unsigned long long>(v.cr) | reinterpret_cast<unsigned long long>(v.ci)) &
+                           15) == 0 &&
+                          (v.ldc & 3) == 0;
+#pragma unroll
+        for (int t = 0; t < TN; ++t) {
+            const int col = 16 * t + 4 * g;
+            if (col < p.n) {  // n is a multiple of 4: all four columns in range
+                // 3M: Re = p1 - p2, Im = p3 - p1 - p2 (OP_C: p2 has the opposite sign)
+                const floatx4 q2 = OPA == OP_C ? -p2[t] : p2[t];
+                const floatx4 cre = REAL ? p1[t] : p1[t] - q2;
+                const floatx4 cim = REAL ? floatx4{0.f, 0.f, 0.f, 0.f} : p3[t] - p1[t] - q2;
+                const long long off = (long long)row * v.ldc + col;
+                if (vecc) {
+                    *reinterpret_cast<floatx4*>(v.cr + off) = cre;
+                    *reinterpret_cast<floatx4*>(v.ci + off) = cim;
+                } else {
+#pragma unroll
+                    for (int j = 0; j < 4; ++j) {
+                        v.cr[off + j] = cre[j];
+                        v.ci[off + j] = cim[j];
+                    }
+                }
+            }
+        }
+    }
+}
+
+template <int OPA, int TN>
+__global__ __launch_bounds__(256) void k_skinny(CgemmArgs p)
+{
+    __shared__ __attribute__((aligned(16))) float lds[2 * 2 * sk_plane<TN>()];
+    int x, y, z;
+    xcd_tile(x, y, z);  // x = row tile, z = kp * nslices + slice
+    const SliceView v = slice_view(p, z % p.nslices, z / p.nslices);
+    const bool fast = (x + 1) * kSkRows <= p.m && (v.K - v.K0) % kSkBK == 0 && vec_ok(v.br, v.bi, p.ldb) &&
+                      (OPA == OP_C || vec_ok(v.ar, v.ai, p.lda));
+    if (v.real) {
+        if (fast)
+            sk_tile<OPA, TN, true, true>(p, v, x, lds);
+        else
+            sk_tile<OPA, TN, true, false>(p, v, x, lds);
+    } else {
+        if (fast)
+            sk_tile<OPA, TN, false, true>(p, v, x, lds);
+        else
+            sk_tile<OPA, TN, false, false>(p, v, x, lds);
+    }
+}
+
 // Batched products of uneven shapes: a persistent grid walks a list of
 // output tiles, each naming its product (items[unit.item]), slice, tile
 // origin and operand forms.
@@ -640,6 +891,34 @@ hipError_t launch_f32(const CgemmArgs& a, hipStream_t s)
     return hipGetLastError();
 }
 
+template <int OPA, int TN>
+hipError_t launch_skinny_tn(const CgemmArgs& a, hipStream_t s)
+{
+    const dim3 g((a.m + kSkRows - 1) / kSkRows, 1, a.nslices * (a.ksplit > 1 ? a.ksplit : 1));
+    if (a.ksplit > 1 && !a.part) return hipErrorInvalidValue;
+    k_skinny<OPA, TN><<<g, 256, 0, s>>>(a);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess || a.ksplit <= 1) return e;
+    const long long total = (long long)a.nslices * a.m * a.n;
+    long long blocks = (total + 255) / 256;
+    if (blocks > 4096) blocks = 4096;
+    k_splitk_reduce<<<(int)blocks, 256, 0, s>>>(a);
+    return hipGetLastError();
+}
+
+template <int OPA>
+hipError_t launch_skinny(const CgemmArgs& a, hipStream_t s)
+{
+    if (a.n <= 16) return launch_skinny_tn<OPA, 1>(a, s);
+    if (a.n <= 32) return launch_skinny_tn<OPA, 2>(a, s);
+    if (a.n <= 48) return launch_skinny_tn<OPA, 3>(a, s);
+    return launch_skinny_tn<OPA, 4>(a, s);
+}
+
+// the skinny kernel takes FP32 products with op(B) = B, n <= 64 and a
+// multiple of 4, and an inner dimension long enough to stream
+bool skinny_ok(const CgemmArgs& a, int opb) { return opb == OP_N && a.n <= 64 && a.n % 4 == 0 && a.k >= 64; }
+
 template <class T>
 hipError_t launch_bf16(const CgemmArgs& a, int prec, hipStream_t s)
 {
@@ -670,7 +949,7 @@ long long tiles(long long m, long long n, int bm, int bn, int ns) { return ((m +
 int pick_variant(const CgemmArgs& a)
 {
     const int tuned = param(TP_PARAM_GEMM_VARIANT);
-    if (tuned >= 1 && tuned <= 6) return tuned;
+    if (tuned >= 1 && tuned <= 7) return tuned;
     if (a.n <= 16) return 5;
     if (a.n <= 32) return 4;
     if (a.n <= 48) return 6;
@@ -724,6 +1003,9 @@ hipError_t launch_cgemm(const CgemmArgs& a, int opa, int opb, int prec, hipStrea
             default: return launch_bf16<T64x64>(a, prec, s);
         }
     }
+    const int tuned = param(TP_PARAM_GEMM_VARIANT);
+    if ((tuned == 0 || tuned == 7) && skinny_ok(a, opb) && (opa == OP_N || opa == OP_C))
+        return opa == OP_N ? launch_skinny<OP_N>(a, s) : launch_skinny<OP_C>(a, s);
     if (opa == OP_N && opb == OP_N) return launch_ops<OP_N, OP_N>(a, variant, s);
     if (opa == OP_C && opb == OP_N) return launch_ops<OP_C, OP_N>(a, variant, s);
     if (opa == OP_N && opb == OP_C) return launch_ops<OP_N, OP_C>(a, variant, s);

@@ -102,11 +102,12 @@ def test_tprod_precision_config_sampled(tp, orc):
         assert err <= TOL[prec]
 
 
-@pytest.mark.parametrize("variant", [1, 2, 3, 4, 5, 6])
+@pytest.mark.parametrize("variant", [1, 2, 3, 4, 5, 6, 7])
 @pytest.mark.parametrize("prec", ["fp32", "bf16x3"])
 def test_tprod_every_tile_variant(tp, orc, variant, prec):
     """Each slice-product tile shape (forced through TP_PARAM_GEMM_VARIANT) on
-    a shape with ragged edges in every dimension."""
+    a shape with ragged edges in every dimension (75 output columns: variant 7
+    falls back to the 64 x 64 tile)."""
     from paper_1806_07247_amd import _lib, inputs
     lib = _lib.load()
     A, B = inputs.tprod_pair(131, 67, 75, 6, seed=variant)
@@ -119,6 +120,26 @@ def test_tprod_every_tile_variant(tp, orc, variant, prec):
     err = rel_fro(C, ref)
     say(f"  variant {variant} {prec}: rel.err {err:.2e}")
     assert err <= TOL[prec]
+
+
+NARROW = [(131, 67, 40, 6), (200, 333, 8, 5), (64, 64, 64, 4), (257, 1024, 16, 3), (70, 96, 4, 7),
+          (128, 256, 48, 4), (1, 64, 12, 2), (96, 100, 20, 9)]
+
+
+@pytest.mark.parametrize("shape", NARROW, ids=lambda s: "x".join(map(str, s)))
+def test_tprod_narrow_output_kernel(tp, orc, shape):
+    """FP32 slice products with at most 64 output columns (a multiple of 4)
+    and an inner dimension >= 64 take the narrow-output kernel: full 64-row
+    tiles with whole 32-deep stages (the unmasked loop) and ragged rows, inner
+    dimensions and widths (the masked loop); real first and last slices."""
+    from paper_1806_07247_amd import inputs
+    n1, n2, l, n3 = shape
+    say(f"tprod narrow {shape}")
+    A, B = inputs.tprod_pair(n1, n2, l, n3, seed=7 * sum(shape))
+    C = tp.tp_tprod(gpu(A), gpu(B), prec="fp32").cpu().numpy()
+    err = rel_fro(C, orc.tprod(A, B))
+    say(f"  rel.err {err:.3e}")
+    assert err <= TOL["fp32"]
 
 
 @pytest.mark.parametrize("direct", [1, 2])
