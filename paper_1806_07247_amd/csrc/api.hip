@@ -258,13 +258,16 @@ int gemm(tp::Planes a, long long lda, long long sa, int opa, tp::Planes b, long 
     return TP_OK;
 }
 
-// CholeskyQR2 of y (rows x L per slice) in place, tmp of the same size; with
-// want_r the combined R of both passes is kept and R^* written to Lw.rh
-int cholqr2(LearnedLayout& Lw, tp::Planes y, tp::Planes tmp, int rows, int L, int h, int real_last, bool want_r,
-            hipStream_t s)
+// CholeskyQR of y (rows x L per slice) with `passes` passes (2: CholeskyQR2),
+// tmp of the same size; the result ends in y (with one pass the two plane
+// pairs are swapped).  With want_r (two passes) the combined R of both
+// passes is kept and R^* written to Lw.rh.
+int cholqr(LearnedLayout& Lw, tp::Planes& y, tp::Planes& tmp, int rows, int L, int h, int real_last, int passes,
+           bool want_r, hipStream_t s)
 {
+    if (want_r && passes != 2) return TP_ERR_ARG;
     tp::Planes src = y, dst = tmp;
-    for (int pass = 0; pass < 2; ++pass) {
+    for (int pass = 0; pass < passes; ++pass) {
         TP_LAUNCH(tp::K_CHOLQR, s,
                   tp::launch_cholqr_pass(src.re, src.im, rows, L, Lw.lact, h, pass, Lw.part, Lw.rinv.re, Lw.rinv.im,
                                          want_r ? Lw.rtot : nullptr, want_r ? Lw.rh.re : nullptr,
@@ -274,6 +277,7 @@ int cholqr2(LearnedLayout& Lw, tp::Planes y, tp::Planes tmp, int rows, int L, in
         if (st != TP_OK) return st;
         std::swap(src, dst);
     }
+    if (passes % 2) std::swap(y, tmp);
     return TP_OK;
 }
 
@@ -673,14 +677,18 @@ int tp_prox_tnn_learned(const float* Y, float* X, int n1, int n2, int n3, float 
                   tp::launch_sketch(W.om.re, W.om.im, n2, L, W.lact, h, n3, opts->seed, warm, s));
         st = gemm(ybar, n2, mn, tp::OP_N, W.om, L, sz, tp::OP_N, W.ya, L, sy, n1, L, n2, h, rl, s,
                 W.kpart, W.kpart_bytes);
-        if (st == TP_OK) st = cholqr2(W, W.ya, W.yb, n1, L, h, rl, false, s);
+        // a basis that only feeds the next power-iteration product takes one
+        // (shifted, FP64 Gram) CholeskyQR pass: it needs to be well
+        // conditioned, not orthonormal to working precision; every Y that
+        // the projection Ybar^* Q may use takes CholeskyQR2
+        if (st == TP_OK) st = cholqr(W, W.ya, W.yb, n1, L, h, rl, opts->power_iters > 0 ? 1 : 2, false, s);
         auto power_iteration = [&]() {
             int r = gemm(ybar, n2, mn, tp::OP_C, W.ya, L, sy, tp::OP_N, W.za, L, sz, n2, L, n1, h, rl, s,
                     W.kpart, W.kpart_bytes);
-            if (r == TP_OK) r = cholqr2(W, W.za, W.zb, n2, L, h, rl, false, s);
+            if (r == TP_OK) r = cholqr(W, W.za, W.zb, n2, L, h, rl, 1, false, s);
             if (r == TP_OK) r = gemm(ybar, n2, mn, tp::OP_N, W.za, L, sz, tp::OP_N, W.ya, L, sy, n1, L, n2, h, rl, s,
                     W.kpart, W.kpart_bytes);
-            if (r == TP_OK) r = cholqr2(W, W.ya, W.yb, n1, L, h, rl, false, s);
+            if (r == TP_OK) r = cholqr(W, W.ya, W.yb, n1, L, h, rl, 2, false, s);
             return r;
         };
         for (int it = 0; st == TP_OK && it < opts->power_iters; ++it) st = power_iteration();
@@ -691,7 +699,7 @@ int tp_prox_tnn_learned(const float* Y, float* X, int n1, int n2, int n3, float 
             // Bh = Ybar^* Q = Q2 R2
             st = gemm(ybar, n2, mn, tp::OP_C, W.ya, L, sy, tp::OP_N, W.za, L, sz, n2, L, n1, h, rl, s,
                     W.kpart, W.kpart_bytes);
-            if (st == TP_OK) st = cholqr2(W, W.za, W.zb, n2, L, h, rl, true, s);
+            if (st == TP_OK) st = cholqr(W, W.za, W.zb, n2, L, h, rl, 2, true, s);
             if (st != TP_OK) return st;
             // SVD of R2^* (one workgroup per slice, LDS), count check, core T
             tp::JacobiArgs j{};

@@ -916,8 +916,8 @@ hipError_t launch_skinny(const CgemmArgs& a, hipStream_t s)
 }
 
 // the skinny kernel takes FP32 products with op(B) = B, n <= 64 and a
-// multiple of 4, and an inner dimension long enough to stream
-bool skinny_ok(const CgemmArgs& a, int opb) { return opb == OP_N && a.n <= 64 && a.n % 4 == 0 && a.k >= 64; }
+// multiple of 4, and (by shape) an inner dimension long enough to stream
+bool skinny_ok(const CgemmArgs& a, int opb, int kmin) { return opb == OP_N && a.n <= 64 && a.n % 4 == 0 && a.k >= kmin; }
 
 template <class T>
 hipError_t launch_bf16(const CgemmArgs& a, int prec, hipStream_t s)
@@ -1004,7 +1004,7 @@ hipError_t launch_cgemm(const CgemmArgs& a, int opa, int opb, int prec, hipStrea
         }
     }
     const int tuned = param(TP_PARAM_GEMM_VARIANT);
-    if ((tuned == 0 || tuned == 7) && skinny_ok(a, opb) && (opa == OP_N || opa == OP_C))
+    if ((tuned == 0 || tuned == 7) && skinny_ok(a, opb, tuned == 7 ? 1 : 64) && (opa == OP_N || opa == OP_C))
         return opa == OP_N ? launch_skinny<OP_N>(a, s) : launch_skinny<OP_C>(a, s);
     if (opa == OP_N && opb == OP_N) return launch_ops<OP_N, OP_N>(a, variant, s);
     if (opa == OP_C && opb == OP_N) return launch_ops<OP_C, OP_N>(a, variant, s);
