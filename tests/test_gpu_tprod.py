@@ -142,6 +142,25 @@ def test_tprod_narrow_output_kernel(tp, orc, shape):
     assert err <= TOL["fp32"]
 
 
+@pytest.mark.parametrize("shape", [(100, 40, 24, 5), (64, 16, 8, 4), (70, 3, 4, 2)],
+                         ids=lambda s: "x".join(map(str, s)))
+def test_tprod_narrow_output_kernel_short_inner(tp, orc, shape):
+    """The narrow-output kernel forced (variant 7) on inner dimensions below
+    its by-shape threshold: a single partial stage, masked."""
+    from paper_1806_07247_amd import _lib, inputs
+    lib = _lib.load()
+    n1, n2, l, n3 = shape
+    A, B = inputs.tprod_pair(n1, n2, l, n3, seed=3 * sum(shape))
+    try:
+        assert lib.tp_set_param(4, 7) == 0
+        C = tp.tp_tprod(gpu(A), gpu(B), prec="fp32").cpu().numpy()
+    finally:
+        lib.tp_set_param(4, 0)
+    err = rel_fro(C, orc.tprod(A, B))
+    say(f"  narrow forced {shape}: rel.err {err:.2e}")
+    assert err <= TOL["fp32"]
+
+
 @pytest.mark.parametrize("direct", [1, 2])
 @pytest.mark.parametrize("shape", [(33, 31, 29, 8), (70, 65, 80, 64), (40, 36, 33, 128), (17, 13, 11, 16)],
                          ids=lambda s: "x".join(map(str, s)))
