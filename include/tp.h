@@ -417,7 +417,11 @@ int tp_batch_destroy(tp_batch* plan);
  *                                 7 = narrow-output kernel (FP32, op(B) = B, at most
  *                                 64 output columns and a multiple of 4, inner
  *                                 dimension >= 64; by shape it takes every such
- *                                 product, variants 1 .. 6 keep them on the tiles)
+ *                                 product, variants 1 .. 6 keep them on the tiles),
+ *                                 8 = wide-output kernel (FP32, A B, inner dimension
+ *                                 1 .. 48, m a multiple of 64 and n of 256, 16-byte
+ *                                 aligned B and C; by shape it takes every such
+ *                                 product that the narrow kernel does not)
  *   TP_PARAM_FFT_GRID             persistent workgroups per compute unit of the
  *                                 tube transforms (0 = default 8)
  *   TP_PARAM_GEMM_BK              FP32 slice GEMM inner-dimension stage: 16 or 32

@@ -22,7 +22,10 @@
 // each lane reads its MFMA operands with 16-byte LDS loads.  Tile shapes from
 // 64 x 64 to 256 x 16 cover square products; FP32 products with at most 64
 // output columns (the range-finder products of the randomized SVD) take a
-// dedicated kernel that streams op(A) straight into registers.
+// dedicated kernel that streams op(A) straight into registers, and FP32
+// products with an inner dimension of at most 48 and whole 64 x 256 output
+// tiles (the reconstruction of the randomized SVT) one that keeps A in
+// registers and streams the output.
 #include "tp_internal.h"
 
 namespace tp {
@@ -706,6 +709,153 @@ k_skinny(CgemmArgs p)
     }
 }
 
+// -------------------------------------------------------------- wide FP32 --
+// Products with a short inner dimension and a wide output: A (m x k, k <= 48)
+// times B (k x n), neither transposed (the reconstruction W = Q M1 of the
+// randomized SVT).  A workgroup of four wavefronts covers 64 rows x 256
+// columns.  Each wavefront keeps its 16 rows of A in registers, in the MFMA
+// operand layout of k_skinny (loaded once), and walks the four 64-column
+// blocks; the k x 64 block of B goes through LDS (row-major, rows padded to
+// 68 floats, double-buffered: the next block's loads are in flight while
+// this one is multiplied), and the results leave as 16-byte stores while the
+// next block's MFMAs run.  Full tiles only (m a multiple of 64, n of 256,
+// 16-byte aligned planes and rows); 3M complex form.
+constexpr int kWideRows = 64, kWideCols = 256, kWideBlk = 64, kWideMaxK = 48;
+constexpr int kWideLDB = kWideBlk + 4;  // 4 x 68 = 16 mod 64 banks: a lane's four fragment reads hit distinct banks
+
+// KC: staged inner rows (k rounded up to 16; zero beyond k)
+template <bool REAL, int KC>
+__device__ __forceinline__ void wide_tile(const CgemmArgs& p, const SliceView& v, int x, int y, float* lds)
+{
+    constexpr int GB = KC * (kWideBlk / 4) / 256;  // 4-column groups of a B block per thread
+    constexpr int nh = KC / 16;
+    constexpr int PL = KC * kWideLDB;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int r = lane & 15, g = lane >> 4;
+    const int row = y * kWideRows + 16 * wave + r;
+    const int K = v.K;
+    const int n0 = x * kWideCols;
+
+    // A: chunk h holds A(row, 16 h + 4 g + s), s = 0..3
+    float fa_r[nh * 4], fa_i[nh * 4];
+    const bool veca = vec_ok(v.ar, v.ai, p.lda);
+#pragma unroll
+    for (int h = 0; h < nh; ++h) {
+        const int kb = 16 * h + 4 * g;
+        const int valid = max(0, min(4, K - kb));
+        const Quad q = load4(v.ar, v.ai, (long long)row * p.lda + kb, valid, veca, false);
+        fa_r[4 * h + 0] = q.r.x;
+        fa_r[4 * h + 1] = q.r.y;
+        fa_r[4 * h + 2] = q.r.z;
+        fa_r[4 * h + 3] = q.r.w;
+        fa_i[4 * h + 0] = q.i.x;
+        fa_i[4 * h + 1] = q.i.y;
+        fa_i[4 * h + 2] = q.i.z;
+        fa_i[4 * h + 3] = q.i.w;
+    }
+
+    float4 bq_r[GB], bq_i[GB];
+    // B block j into registers: rows beyond K read row K-1 (kept in range) and are zeroed when stored
+    auto load_b = [&](int j) __attribute__((always_inline)) {
+#pragma unroll
+        for (int u = 0; u < GB; ++u) {
+            const int e = tid + 256 * u;
+            {
+                const int kr = min(e / (kWideBlk / 4), K - 1), col = n0 + kWideBlk * j + 4 * (e % (kWideBlk / 4));
+                const long long off = (long long)kr * p.ldb + col;
+                bq_r[u] = *reinterpret_cast<const float4*>(v.br + off);
+                bq_i[u] = *reinterpret_cast<const float4*>(v.bi + off);
+            }
+        }
+    };
+    auto store_b = [&](int buf) __attribute__((always_inline)) {
+        float* br = lds + buf * 2 * PL;
+        float* bi = br + PL;
+#pragma unroll
+        for (int u = 0; u < GB; ++u) {
+            const int e = tid + 256 * u;
+            {
+                const int kr = e / (kWideBlk / 4), c = 4 * (e % (kWideBlk / 4));
+                float4 qr = bq_r[u], qi = bq_i[u];  // by value: a select of two lvalues would go through memory
+                if (kr >= K) qr = qi = make_float4(0.f, 0.f, 0.f, 0.f);
+                *reinterpret_cast<float4*>(br + kr * kWideLDB + c) = qr;
+                *reinterpret_cast<float4*>(bi + kr * kWideLDB + c) = qi;
+            }
+        }
+    };
+    const bool vecc = ((reinterpret_cast<unsigned long long>(v.cr) | reinterpret_cast<unsigned long long>(v.ci)) &
+                       15) == 0 &&
+                      (v.ldc & 3) == 0;
+
+    load_b(0);
+    store_b(0);
+    __syncthreads();
+    for (int j = 0; j < kWideCols / kWideBlk; ++j) {
+        const bool more = j + 1 < kWideCols / kWideBlk;
+        if (more) load_b(j + 1);
+        floatx4 p1[4], p2[4], p3[4];
+#pragma unroll
+        for (int t = 0; t < 4; ++t) p1[t] = p2[t] = p3[t] = floatx4{0.f, 0.f, 0.f, 0.f};
+        const float* br = lds + (j & 1) * 2 * PL;
+        const float* bi = br + PL;
+#pragma unroll
+        for (int h = 0; h < nh; ++h) {
+            {
+#pragma unroll
+                for (int s = 0; s < 4; ++s) {
+                    const float ar = fa_r[4 * h + s], ai = fa_i[4 * h + s];
+                    const float as = ar + ai;
+                    const int off = (16 * h + 4 * g + s) * kWideLDB + r;
+#pragma unroll
+                    for (int t = 0; t < 4; ++t) {
+                        const float b_r = br[off + 16 * t], b_i = bi[off + 16 * t];
+                        p1[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(b_r, ar, p1[t], 0, 0, 0);
+                        if (!REAL) {
+                            p2[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(b_i, ai, p2[t], 0, 0, 0);
+                            p3[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(b_r + b_i, as, p3[t], 0, 0, 0);
+                        }
+                    }
+                }
+            }
+            // one chunk's fragments live at a time (the scheduler would hoist them all)
+            __builtin_amdgcn_sched_barrier(0);
+        }
+        // lane (r, g) holds row `row`, columns 16 t + 4 g .. + 3 of the block
+#pragma unroll
+        for (int t = 0; t < 4; ++t) {
+            const floatx4 cre = REAL ? p1[t] : p1[t] - p2[t];
+            const floatx4 cim = REAL ? floatx4{0.f, 0.f, 0.f, 0.f} : p3[t] - p1[t] - p2[t];
+            const long long off = (long long)row * v.ldc + n0 + kWideBlk * j + 16 * t + 4 * g;
+            if (vecc) {
+                *reinterpret_cast<floatx4*>(v.cr + off) = cre;
+                *reinterpret_cast<floatx4*>(v.ci + off) = cim;
+            } else {
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    v.cr[off + q] = cre[q];
+                    v.ci[off + q] = cim[q];
+                }
+            }
+        }
+        if (more) store_b((j + 1) & 1);
+        __syncthreads();
+    }
+}
+
+// three wavefronts per SIMD (no spills; measured 7% faster than two)
+template <int KC>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3, 3))) void k_wide(CgemmArgs p)
+{
+    __shared__ __attribute__((aligned(16))) float wlds[2 * 2 * KC * kWideLDB];
+    int x, y, z;
+    xcd_tile(x, y, z);  // x = 256-column group, y = 64-row tile, z = slice
+    const SliceView v = slice_view(p, z, 0);
+    if (v.real)
+        wide_tile<true, KC>(p, v, x, y, wlds);
+    else
+        wide_tile<false, KC>(p, v, x, y, wlds);
+}
+
 // Batched products of uneven shapes: a persistent grid walks a list of
 // output tiles, each naming its product (items[unit.item]), slice, tile
 // origin and operand forms.
@@ -920,6 +1070,31 @@ hipError_t launch_skinny(const CgemmArgs& a, hipStream_t s)
     return launch_skinny_tn<OPA, 4>(a, s);
 }
 
+// the wide kernel takes FP32 products A B, 1 <= k <= 48 (the same for every
+// slice), whole 64 x 256 tiles, 16-byte aligned planes and rows (B and C), no
+// split
+bool wide_ok(const CgemmArgs& a, int opa, int opb)
+{
+    const unsigned long long al = reinterpret_cast<unsigned long long>(a.br) |
+                                  reinterpret_cast<unsigned long long>(a.bi) |
+                                  reinterpret_cast<unsigned long long>(a.cr) | reinterpret_cast<unsigned long long>(a.ci);
+    return opa == OP_N && opb == OP_N && !a.kdyn && a.k >= 1 && a.k <= kWideMaxK && a.m % kWideRows == 0 &&
+           a.n % kWideCols == 0 && a.ksplit <= 1 && (al & 15) == 0 && a.ldb % 4 == 0 && a.sb % 4 == 0 &&
+           a.ldc % 4 == 0 && a.sc % 4 == 0;
+}
+
+hipError_t launch_wide(const CgemmArgs& a, hipStream_t s)
+{
+    const dim3 g(a.n / kWideCols, a.m / kWideRows, a.nslices);
+    if (a.k <= 16)
+        k_wide<16><<<g, 256, 0, s>>>(a);
+    else if (a.k <= 32)
+        k_wide<32><<<g, 256, 0, s>>>(a);
+    else
+        k_wide<48><<<g, 256, 0, s>>>(a);
+    return hipGetLastError();
+}
+
 // the skinny kernel takes FP32 products with op(B) = B, n <= 64 and a
 // multiple of 4, and (by shape) an inner dimension long enough to stream
 bool skinny_ok(const CgemmArgs& a, int opb, int kmin) { return opb == OP_N && a.n <= 64 && a.n % 4 == 0 && a.k >= kmin; }
@@ -954,7 +1129,7 @@ long long tiles(long long m, long long n, int bm, int bn, int ns) { return ((m +
 int pick_variant(const CgemmArgs& a)
 {
     const int tuned = param(TP_PARAM_GEMM_VARIANT);
-    if (tuned >= 1 && tuned <= 7) return tuned;
+    if (tuned >= 1 && tuned <= 8) return tuned;
     if (a.n <= 16) return 5;
     if (a.n <= 32) return 4;
     if (a.n <= 48) return 6;
@@ -1011,6 +1186,7 @@ hipError_t launch_cgemm(const CgemmArgs& a, int opa, int opb, int prec, hipStrea
     const int tuned = param(TP_PARAM_GEMM_VARIANT);
     if ((tuned == 0 || tuned == 7) && skinny_ok(a, opb, tuned == 7 ? 1 : 64) && (opa == OP_N || opa == OP_C))
         return opa == OP_N ? launch_skinny<OP_N>(a, s) : launch_skinny<OP_C>(a, s);
+    if ((tuned == 0 || tuned == 8) && wide_ok(a, opa, opb)) return launch_wide(a, s);
     if (opa == OP_N && opb == OP_N) return launch_ops<OP_N, OP_N>(a, variant, s);
     if (opa == OP_C && opb == OP_N) return launch_ops<OP_C, OP_N>(a, variant, s);
     if (opa == OP_N && opb == OP_C) return launch_ops<OP_N, OP_C>(a, variant, s);

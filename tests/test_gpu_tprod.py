@@ -102,12 +102,12 @@ def test_tprod_precision_config_sampled(tp, orc):
         assert err <= TOL[prec]
 
 
-@pytest.mark.parametrize("variant", [1, 2, 3, 4, 5, 6, 7])
+@pytest.mark.parametrize("variant", [1, 2, 3, 4, 5, 6, 7, 8])
 @pytest.mark.parametrize("prec", ["fp32", "bf16x3"])
 def test_tprod_every_tile_variant(tp, orc, variant, prec):
     """Each slice-product tile shape (forced through TP_PARAM_GEMM_VARIANT) on
-    a shape with ragged edges in every dimension (75 output columns: variant 7
-    falls back to the 64 x 64 tile)."""
+    a shape with ragged edges in every dimension (75 output columns: variants
+    7 and 8 fall back to the 64 x 64 tile)."""
     from paper_1806_07247_amd import _lib, inputs
     lib = _lib.load()
     A, B = inputs.tprod_pair(131, 67, 75, 6, seed=variant)
@@ -158,6 +158,26 @@ def test_tprod_narrow_output_kernel_short_inner(tp, orc, shape):
         lib.tp_set_param(4, 0)
     err = rel_fro(C, orc.tprod(A, B))
     say(f"  narrow forced {shape}: rel.err {err:.2e}")
+    assert err <= TOL["fp32"]
+
+
+WIDE = [(64, 17, 256, 5), (128, 48, 512, 4), (192, 1, 256, 3), (64, 40, 768, 6), (128, 32, 256, 2),
+        (64, 8, 512, 9)]
+
+
+@pytest.mark.parametrize("shape", WIDE, ids=lambda s: "x".join(map(str, s)))
+def test_tprod_wide_output_kernel(tp, orc, shape):
+    """FP32 slice products with an inner dimension of at most 48 and whole
+    64 x 256 output tiles take the wide-output kernel (A in registers, the
+    output streamed): inner dimensions 1 .. 48 (ragged against its 16-deep
+    stages), real first and last slices."""
+    from paper_1806_07247_amd import inputs
+    n1, n2, l, n3 = shape
+    say(f"tprod wide {shape}")
+    A, B = inputs.tprod_pair(n1, n2, l, n3, seed=11 * sum(shape))
+    C = tp.tp_tprod(gpu(A), gpu(B), prec="fp32").cpu().numpy()
+    err = rel_fro(C, orc.tprod(A, B))
+    say(f"  rel.err {err:.3e}")
     assert err <= TOL["fp32"]
 
 
