@@ -240,9 +240,9 @@ int pick_ksplit(int m, int n, int k, int nslices, size_t part_bytes)
 
 // slice GEMM of planar stacks: C = op(A) op(B) with op(A) m x k, op(B) k x n
 // (part: optional split-K scratch of part_bytes)
-int gemm(tp::Planes a, long long lda, long long sa, int opa, tp::Planes b, long long ldb, long long sb, int opb,
-         tp::Planes c, long long ldc, long long sc, int m, int n, int k, int nslices, int real_last, hipStream_t s,
-         float* part = nullptr, size_t part_bytes = 0)
+tp::CgemmArgs gemm_args(tp::Planes a, long long lda, long long sa, tp::Planes b, long long ldb, long long sb,
+                        tp::Planes c, long long ldc, long long sc, int m, int n, int k, int nslices, int real_last,
+                        float* part, size_t part_bytes)
 {
     tp::CgemmArgs g{};
     g.ksplit = pick_ksplit(m, n, k, nslices, part ? part_bytes : 0);
@@ -254,6 +254,14 @@ int gemm(tp::Planes a, long long lda, long long sa, int opa, tp::Planes b, long 
     g.nslices = nslices;
     g.real_first = 1;
     g.real_last = real_last;
+    return g;
+}
+
+int gemm(tp::Planes a, long long lda, long long sa, int opa, tp::Planes b, long long ldb, long long sb, int opb,
+         tp::Planes c, long long ldc, long long sc, int m, int n, int k, int nslices, int real_last, hipStream_t s,
+         float* part = nullptr, size_t part_bytes = 0)
+{
+    const tp::CgemmArgs g = gemm_args(a, lda, sa, b, ldb, sb, c, ldc, sc, m, n, k, nslices, real_last, part, part_bytes);
     TP_LAUNCH(tp::K_CGEMM, s, tp::launch_cgemm(g, opa, opb, TP_PREC_FP32, s));
     return TP_OK;
 }
@@ -261,9 +269,10 @@ int gemm(tp::Planes a, long long lda, long long sa, int opa, tp::Planes b, long 
 // CholeskyQR of y (rows x L per slice) with `passes` passes (2: CholeskyQR2),
 // tmp of the same size; the result ends in y (with one pass the two plane
 // pairs are swapped).  With want_r (two passes) the combined R of both
-// passes is kept and R^* written to Lw.rh.
+// passes is kept and R^* written to Lw.rh.  gram_ready: the first pass's
+// Gram partials are already in Lw.part (gemm_gram).
 int cholqr(LearnedLayout& Lw, tp::Planes& y, tp::Planes& tmp, int rows, int L, int h, int real_last, int passes,
-           bool want_r, hipStream_t s)
+           bool want_r, hipStream_t s, bool gram_ready = false)
 {
     if (want_r && passes != 2) return TP_ERR_ARG;
     tp::Planes src = y, dst = tmp;
@@ -271,13 +280,36 @@ int cholqr(LearnedLayout& Lw, tp::Planes& y, tp::Planes& tmp, int rows, int L, i
         TP_LAUNCH(tp::K_CHOLQR, s,
                   tp::launch_cholqr_pass(src.re, src.im, rows, L, Lw.lact, h, pass, Lw.part, Lw.rinv.re, Lw.rinv.im,
                                          want_r ? Lw.rtot : nullptr, want_r ? Lw.rh.re : nullptr,
-                                         want_r ? Lw.rh.im : nullptr, Lw.status, s));
+                                         want_r ? Lw.rh.im : nullptr, Lw.status, s, gram_ready && pass == 0));
         const int st = gemm(src, L, (long long)rows * L, tp::OP_N, Lw.rinv, L, (long long)L * L, tp::OP_N, dst, L,
                             (long long)rows * L, rows, L, L, h, real_last, s);
         if (st != TP_OK) return st;
         std::swap(src, dst);
     }
     if (passes % 2) std::swap(y, tmp);
+    return TP_OK;
+}
+
+// The range-finder product C = op(A) B (m x n per slice, row-major, packed)
+// whose result a CholeskyQR takes next: a split narrow product leaves its
+// parts, and their sum is formed together with the first pass's Gram (one
+// pass over C instead of the reduction's write and the Gram's read).
+// *gram_ready tells the CholeskyQR whether that happened.
+int gemm_gram(LearnedLayout& Lw, tp::Planes a, long long lda, long long sa, int opa, tp::Planes b, long long ldb,
+              long long sb, tp::Planes c, int m, int n, int k, int nslices, int real_last, hipStream_t s,
+              bool* gram_ready)
+{
+    const long long sc = (long long)m * n;
+    const tp::CgemmArgs g = gemm_args(a, lda, sa, b, ldb, sb, c, n, sc, m, n, k, nslices, real_last, Lw.kpart,
+                                      Lw.kpart_bytes);
+    *gram_ready = false;
+    if (!tp::cgemm_parts_ok(g, opa, tp::OP_N))
+        return gemm(a, lda, sa, opa, b, ldb, sb, tp::OP_N, c, n, sc, m, n, k, nslices, real_last, s, Lw.kpart,
+                    Lw.kpart_bytes);
+    TP_LAUNCH(tp::K_CGEMM, s, tp::launch_cgemm_parts(g, opa, tp::OP_N, s));
+    TP_LAUNCH(tp::K_CHOLQR, s,
+              tp::launch_reduce_gram(Lw.kpart, g.ksplit, m, n, nslices, 1, real_last, c.re, c.im, Lw.lact, Lw.part, s));
+    *gram_ready = true;
     return TP_OK;
 }
 
@@ -675,20 +707,19 @@ int tp_prox_tnn_learned(const float* Y, float* X, int n1, int n2, int n3, float 
         }
         TP_LAUNCH(tp::K_SKETCH, s,
                   tp::launch_sketch(W.om.re, W.om.im, n2, L, W.lact, h, n3, opts->seed, warm, s));
-        st = gemm(ybar, n2, mn, tp::OP_N, W.om, L, sz, tp::OP_N, W.ya, L, sy, n1, L, n2, h, rl, s,
-                W.kpart, W.kpart_bytes);
+        bool gr = false;
+        st = gemm_gram(W, ybar, n2, mn, tp::OP_N, W.om, L, sz, W.ya, n1, L, n2, h, rl, s, &gr);
         // a basis that only feeds the next power-iteration product takes one
         // (shifted, FP64 Gram) CholeskyQR pass: it needs to be well
         // conditioned, not orthonormal to working precision; every Y that
         // the projection Ybar^* Q may use takes CholeskyQR2
-        if (st == TP_OK) st = cholqr(W, W.ya, W.yb, n1, L, h, rl, opts->power_iters > 0 ? 1 : 2, false, s);
+        if (st == TP_OK) st = cholqr(W, W.ya, W.yb, n1, L, h, rl, opts->power_iters > 0 ? 1 : 2, false, s, gr);
         auto power_iteration = [&]() {
-            int r = gemm(ybar, n2, mn, tp::OP_C, W.ya, L, sy, tp::OP_N, W.za, L, sz, n2, L, n1, h, rl, s,
-                    W.kpart, W.kpart_bytes);
-            if (r == TP_OK) r = cholqr(W, W.za, W.zb, n2, L, h, rl, 1, false, s);
-            if (r == TP_OK) r = gemm(ybar, n2, mn, tp::OP_N, W.za, L, sz, tp::OP_N, W.ya, L, sy, n1, L, n2, h, rl, s,
-                    W.kpart, W.kpart_bytes);
-            if (r == TP_OK) r = cholqr(W, W.ya, W.yb, n1, L, h, rl, 2, false, s);
+            bool g1 = false, g2 = false;
+            int r = gemm_gram(W, ybar, n2, mn, tp::OP_C, W.ya, L, sy, W.za, n2, L, n1, h, rl, s, &g1);
+            if (r == TP_OK) r = cholqr(W, W.za, W.zb, n2, L, h, rl, 1, false, s, g1);
+            if (r == TP_OK) r = gemm_gram(W, ybar, n2, mn, tp::OP_N, W.za, L, sz, W.ya, n1, L, n2, h, rl, s, &g2);
+            if (r == TP_OK) r = cholqr(W, W.ya, W.yb, n1, L, h, rl, 2, false, s, g2);
             return r;
         };
         for (int it = 0; st == TP_OK && it < opts->power_iters; ++it) st = power_iteration();
@@ -697,9 +728,9 @@ int tp_prox_tnn_learned(const float* Y, float* X, int n1, int n2, int n3, float 
         int q = opts->power_iters;
         while (true) {
             // Bh = Ybar^* Q = Q2 R2
-            st = gemm(ybar, n2, mn, tp::OP_C, W.ya, L, sy, tp::OP_N, W.za, L, sz, n2, L, n1, h, rl, s,
-                    W.kpart, W.kpart_bytes);
-            if (st == TP_OK) st = cholqr(W, W.za, W.zb, n2, L, h, rl, 2, true, s);
+            bool gz = false;
+            st = gemm_gram(W, ybar, n2, mn, tp::OP_C, W.ya, L, sy, W.za, n2, L, n1, h, rl, s, &gz);
+            if (st == TP_OK) st = cholqr(W, W.za, W.zb, n2, L, h, rl, 2, true, s, gz);
             if (st != TP_OK) return st;
             // SVD of R2^* (one workgroup per slice, LDS), count check, core T
             tp::JacobiArgs j{};

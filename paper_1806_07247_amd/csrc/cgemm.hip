@@ -1047,13 +1047,13 @@ hipError_t launch_f32(const CgemmArgs& a, hipStream_t s)
 }
 
 template <int OPA, int TN>
-hipError_t launch_skinny_tn(const CgemmArgs& a, hipStream_t s)
+hipError_t launch_skinny_tn(const CgemmArgs& a, hipStream_t s, bool reduce)
 {
     const dim3 g((a.m + kSkRows - 1) / kSkRows, 1, a.nslices * (a.ksplit > 1 ? a.ksplit : 1));
     if (a.ksplit > 1 && !a.part) return hipErrorInvalidValue;
     k_skinny<OPA, TN><<<g, 256, 0, s>>>(a);
     hipError_t e = hipGetLastError();
-    if (e != hipSuccess || a.ksplit <= 1) return e;
+    if (e != hipSuccess || a.ksplit <= 1 || !reduce) return e;
     const long long total = (long long)a.nslices * a.m * a.n;
     long long blocks = (total + 255) / 256;
     if (blocks > 4096) blocks = 4096;
@@ -1061,13 +1061,14 @@ hipError_t launch_skinny_tn(const CgemmArgs& a, hipStream_t s)
     return hipGetLastError();
 }
 
+// reduce = false: a split product leaves its parts in a.part (summed by the caller)
 template <int OPA>
-hipError_t launch_skinny(const CgemmArgs& a, hipStream_t s)
+hipError_t launch_skinny(const CgemmArgs& a, hipStream_t s, bool reduce = true)
 {
-    if (a.n <= 16) return launch_skinny_tn<OPA, 1>(a, s);
-    if (a.n <= 32) return launch_skinny_tn<OPA, 2>(a, s);
-    if (a.n <= 48) return launch_skinny_tn<OPA, 3>(a, s);
-    return launch_skinny_tn<OPA, 4>(a, s);
+    if (a.n <= 16) return launch_skinny_tn<OPA, 1>(a, s, reduce);
+    if (a.n <= 32) return launch_skinny_tn<OPA, 2>(a, s, reduce);
+    if (a.n <= 48) return launch_skinny_tn<OPA, 3>(a, s, reduce);
+    return launch_skinny_tn<OPA, 4>(a, s, reduce);
 }
 
 // the wide kernel takes FP32 products A B, 1 <= k <= 48 (the same for every
@@ -1163,14 +1164,33 @@ hipError_t launch_cgemm_batch(const CgemmArgs* items, const GemmUnit* units, int
     return hipGetLastError();
 }
 
+namespace {
+void trace_gemm_work(const CgemmArgs& a)
+{
+    const int nreal = (a.real_first ? 1 : 0) + (a.real_last && a.nslices > 1 ? 1 : 0);
+    const double mnk = (double)a.m * a.n * a.k, elems = (double)a.m * a.k + (double)a.k * a.n + (double)a.m * a.n;
+    trace_work(mnk * (8.0 * (a.nslices - nreal) + 2.0 * nreal), elems * (8.0 * (a.nslices - nreal) + 4.0 * nreal));
+}
+}  // namespace
+
+bool cgemm_parts_ok(const CgemmArgs& a, int opa, int opb)
+{
+    const int tuned = param(TP_PARAM_GEMM_VARIANT);
+    return a.m > 0 && a.n > 0 && a.nslices > 0 && a.ksplit > 1 && a.part && (tuned == 0 || tuned == 7) &&
+           skinny_ok(a, opb, 64) && (opa == OP_N || opa == OP_C);
+}
+
+hipError_t launch_cgemm_parts(const CgemmArgs& a, int opa, int opb, hipStream_t s)
+{
+    if (!cgemm_parts_ok(a, opa, opb)) return hipErrorInvalidValue;
+    trace_gemm_work(a);
+    return opa == OP_N ? launch_skinny<OP_N>(a, s, false) : launch_skinny<OP_C>(a, s, false);
+}
+
 hipError_t launch_cgemm(const CgemmArgs& a, int opa, int opb, int prec, hipStream_t s)
 {
     if (a.m <= 0 || a.n <= 0 || a.nslices <= 0) return hipSuccess;
-    {
-        const int nreal = (a.real_first ? 1 : 0) + (a.real_last && a.nslices > 1 ? 1 : 0);
-        const double mnk = (double)a.m * a.n * a.k, elems = (double)a.m * a.k + (double)a.k * a.n + (double)a.m * a.n;
-        trace_work(mnk * (8.0 * (a.nslices - nreal) + 2.0 * nreal), elems * (8.0 * (a.nslices - nreal) + 4.0 * nreal));
-    }
+    trace_gemm_work(a);
     const int variant = pick_variant(a);
     if (prec != TP_PREC_FP32) {
         if (opa != OP_N || opb != OP_N || a.ksplit > 1) return hipErrorInvalidValue;

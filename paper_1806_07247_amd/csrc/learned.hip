@@ -84,26 +84,84 @@ constexpr int kMaxGramSplit = 16;  // row bands of the Gram (partials summed by 
 // of the nb x nb block grid (nb = ceil(L / B), nb (nb + 1) / 2 <= 256).
 // Rows are staged in LDS in chunks; every product of two FP32 values is exact
 // in FP64 and the sums are FP64.
+constexpr int kGramChunk = 32;                        // rows per LDS chunk
+constexpr int kGramLoads = kGramChunk * kMaxL / 256;  // chunk elements per thread (at most)
+constexpr int kMaxParts = 4;                          // split parts summed by k_reduce_gram
+
+// the B x B block (ta, tb) of the Gram that thread tid of the workgroup owns
+struct GramBlock {
+    int a0, b0;
+    bool has, work;  // has: a block of the grid; work: inside the active columns
+};
 template <int B>
-__global__ __launch_bounds__(256) void k_gram(const float* __restrict__ yr, const float* __restrict__ yi, int m,
-                                              int L, const int* __restrict__ lact, double2* __restrict__ part,
-                                              int nsplit)
+__device__ __forceinline__ GramBlock gram_block(int tid, int L, int la)
 {
-    constexpr int CH = 32;  // rows per LDS chunk
-    constexpr int W = kMaxL + B;
-    __shared__ float2 tile[CH * W];
-    const int s = blockIdx.y, w = blockIdx.x, tid = threadIdx.x;
-    const int la = lact[s];
     const int nb = (L + B - 1) / B;
-    // block pair of this thread: row ta holds nb - ta blocks (tb = ta .. nb-1)
+    // row ta holds nb - ta blocks (tb = ta .. nb-1)
     int ta = 0, t = tid;
     while (ta < nb && t >= nb - ta) {
         t -= nb - ta;
         ++ta;
     }
-    const int tb = ta + t;
-    const int a0 = ta * B, b0 = tb * B;
-    const bool work = ta < nb && a0 < la && b0 < la;
+    GramBlock gb;
+    gb.a0 = ta * B;
+    gb.b0 = (ta + t) * B;
+    gb.has = ta < nb;
+    gb.work = gb.has && gb.a0 < la && gb.b0 < la;
+    return gb;
+}
+
+// accumulate conj(x_a) y_b over the nr staged rows of tile (row stride W)
+template <int B, int W>
+__device__ __forceinline__ void gram_rows(const float2* tile, int nr, int a0, int b0, double (&gr)[B][B],
+                                          double (&gi)[B][B])
+{
+    for (int i = 0; i < nr; ++i) {
+        double xr[B], xi[B], vr[B], vi[B];
+#pragma unroll
+        for (int u = 0; u < B; ++u) {
+            const float2 x = tile[i * W + a0 + u], y = tile[i * W + b0 + u];
+            xr[u] = x.x;
+            xi[u] = x.y;
+            vr[u] = y.x;
+            vi[u] = y.y;
+        }
+#pragma unroll
+        for (int u = 0; u < B; ++u)
+#pragma unroll
+            for (int v = 0; v < B; ++v) {  // conj(x_a) y_b
+                gr[u][v] = fma(xr[u], vr[v], fma(xi[u], vi[v], gr[u][v]));
+                gi[u][v] = fma(xr[u], vi[v], fma(-xi[u], vr[v], gi[u][v]));
+            }
+    }
+}
+
+// the thread's block of partial Gram w of slice s
+template <int B>
+__device__ __forceinline__ void gram_store(const GramBlock& gb, int L, int s, int w, int nsplit, double2* part,
+                                           const double (&gr)[B][B], const double (&gi)[B][B])
+{
+    if (!gb.has) return;
+    double2* out = part + ((long long)s * nsplit + w) * L * L;
+#pragma unroll
+    for (int u = 0; u < B; ++u)
+#pragma unroll
+        for (int v = 0; v < B; ++v) {
+            const int a = gb.a0 + u, b = gb.b0 + v;
+            if (a < L && b < L) out[a * L + b] = gb.work ? make_double2(gr[u][v], gi[u][v]) : make_double2(0.0, 0.0);
+        }
+}
+
+template <int B>
+__global__ __launch_bounds__(256) void k_gram(const float* __restrict__ yr, const float* __restrict__ yi, int m,
+                                              int L, const int* __restrict__ lact, double2* __restrict__ part,
+                                              int nsplit)
+{
+    constexpr int W = kMaxL + B;
+    __shared__ float2 tile[kGramChunk * W];
+    const int s = blockIdx.y, w = blockIdx.x, tid = threadIdx.x;
+    const int la = lact[s];
+    const GramBlock gb = gram_block<B>(tid, L, la);
     const int r0 = (int)((long long)m * w / nsplit), r1 = (int)((long long)m * (w + 1) / nsplit);
     const float* Yr = yr + (long long)s * m * L;
     const float* Yi = yi + (long long)s * m * L;
@@ -113,46 +171,99 @@ __global__ __launch_bounds__(256) void k_gram(const float* __restrict__ yr, cons
 #pragma unroll
         for (int v = 0; v < B; ++v) gr[u][v] = gi[u][v] = 0.0;
     const int lc = min(la, L);
-    for (int c0 = r0; c0 < r1; c0 += CH) {
-        const int nr = min(CH, r1 - c0);
-        __syncthreads();
-        for (int e = tid; e < CH * W; e += blockDim.x) {
-            const int i = e / W, j = e % W;
-            float2 v = make_float2(0.f, 0.f);
-            if (i < nr && j < lc) v = make_float2(Yr[(long long)(c0 + i) * L + j], Yi[(long long)(c0 + i) * L + j]);
-            tile[e] = v;
+    for (int c0 = r0; c0 < r1; c0 += kGramChunk) {
+        // the chunk is contiguous: every load of the thread is issued before any is used
+        const int nr = min(kGramChunk, r1 - c0), nf = nr * L;
+        const float* cr = Yr + (long long)c0 * L;
+        const float* ci = Yi + (long long)c0 * L;
+        float xr[kGramLoads], xi[kGramLoads];
+#pragma unroll
+        for (int q = 0; q < kGramLoads; ++q) {
+            const int f = tid + 256 * q;
+            xr[q] = f < nf ? cr[f] : 0.0f;
+            xi[q] = f < nf ? ci[f] : 0.0f;
         }
-        __syncthreads();
-        if (work) {
-            for (int i = 0; i < nr; ++i) {
-                double xr[B], xi[B], vr[B], vi[B];
+        __syncthreads();  // the previous chunk is read
 #pragma unroll
-                for (int u = 0; u < B; ++u) {
-                    const float2 x = tile[i * W + a0 + u], y = tile[i * W + b0 + u];
-                    xr[u] = x.x;
-                    xi[u] = x.y;
-                    vr[u] = y.x;
-                    vi[u] = y.y;
-                }
-#pragma unroll
-                for (int u = 0; u < B; ++u)
-#pragma unroll
-                    for (int v = 0; v < B; ++v) {  // conj(x_a) y_b
-                        gr[u][v] = fma(xr[u], vr[v], fma(xi[u], vi[v], gr[u][v]));
-                        gi[u][v] = fma(xr[u], vi[v], fma(-xi[u], vr[v], gi[u][v]));
-                    }
+        for (int q = 0; q < kGramLoads; ++q) {
+            const int f = tid + 256 * q;
+            if (f < nf) {
+                const int i = f / L, j = f % L;
+                tile[i * W + j] = j < lc ? make_float2(xr[q], xi[q]) : make_float2(0.f, 0.f);
             }
         }
+        __syncthreads();
+        if (gb.work) gram_rows<B, W>(tile, nr, gb.a0, gb.b0, gr, gi);
     }
-    if (ta >= nb) return;
-    double2* out = part + ((long long)s * nsplit + w) * L * L;
+    gram_store<B>(gb, L, s, w, nsplit, part, gr, gi);
+}
+
+// The split parts of a narrow slice product summed into Y (the fixed order
+// kp = 0, 1, ... of the plain reduction) and, from the same staged rows,
+// the partial Grams of k_gram: one pass over Y instead of a write and a
+// read back.
+template <int B>
+__global__ __launch_bounds__(256) void k_reduce_gram(const float* __restrict__ parts, int ksplit, int m, int L,
+                                                     int nslices, int real_first, int real_last,
+                                                     float* __restrict__ yr, float* __restrict__ yi,
+                                                     const int* __restrict__ lact, double2* __restrict__ part,
+                                                     int nsplit)
+{
+    constexpr int W = kMaxL + B;
+    __shared__ float2 tile[kGramChunk * W];
+    const int s = blockIdx.y, w = blockIdx.x, tid = threadIdx.x;
+    const int la = lact[s];
+    const GramBlock gb = gram_block<B>(tid, L, la);
+    const int r0 = (int)((long long)m * w / nsplit), r1 = (int)((long long)m * (w + 1) / nsplit);
+    const long long mn = (long long)m * L, total = (long long)nslices * mn, plane = (long long)ksplit * total;
+    const bool real = (real_first && s == 0) || (real_last && s == nslices - 1);
+    const float* P = parts + s * mn;
+    float* Yr = yr + s * mn;
+    float* Yi = yi + s * mn;
+    double gr[B][B], gi[B][B];
 #pragma unroll
     for (int u = 0; u < B; ++u)
 #pragma unroll
-        for (int v = 0; v < B; ++v) {
-            const int a = a0 + u, b = b0 + v;
-            if (a < L && b < L) out[a * L + b] = work ? make_double2(gr[u][v], gi[u][v]) : make_double2(0.0, 0.0);
+        for (int v = 0; v < B; ++v) gr[u][v] = gi[u][v] = 0.0;
+    const int lc = min(la, L);
+    for (int c0 = r0; c0 < r1; c0 += kGramChunk) {
+        // the chunk is contiguous in every part: all loads of the thread in flight at once
+        const int nr = min(kGramChunk, r1 - c0), nf = nr * L;
+        const long long o0 = (long long)c0 * L;
+        float pr[kGramLoads][kMaxParts], pim[kGramLoads][kMaxParts];
+#pragma unroll
+        for (int q = 0; q < kGramLoads; ++q) {
+            const int f = tid + 256 * q;
+#pragma unroll
+            for (int kp = 0; kp < kMaxParts; ++kp) {
+                const bool ok = f < nf && kp < ksplit;
+                pr[q][kp] = ok ? P[kp * total + o0 + f] : 0.0f;
+                pim[q][kp] = ok ? P[plane + kp * total + o0 + f] : 0.0f;
+            }
         }
+        __syncthreads();  // the previous chunk is read
+#pragma unroll
+        for (int q = 0; q < kGramLoads; ++q) {
+            const int f = tid + 256 * q;
+            if (f < nf) {
+                float sr = 0.0f, si = 0.0f;  // the parts in order, as the plain reduction
+#pragma unroll
+                for (int kp = 0; kp < kMaxParts; ++kp)
+                    if (kp < ksplit) {
+                        sr += pr[q][kp];
+                        si += pim[q][kp];
+                    }
+                if (real) si = 0.0f;
+                Yr[o0 + f] = sr;
+                Yi[o0 + f] = si;
+                const int i = f / L, j = f % L;
+                tile[i * W + j] = j < lc ? make_float2(sr, si) : make_float2(0.f, 0.f);
+            }
+        }
+        __syncthreads();
+        if (gb.work) gram_rows<B, W>(tile, nr, gb.a0, gb.b0, gr, gi);
+    }
+    gram_store<B>(gb, L, s, w, nsplit, part, gr, gi);
 }
 
 // Per slice: G = sum of the partial Grams (fixed order, upper triangle); in
@@ -930,19 +1041,36 @@ void launch_gram(const float* yr, const float* yi, int m, int L, const int* lact
     k_gram<B><<<dim3(ns, nslices), 256, 0, st>>>(yr, yi, m, L, lact, part, ns);
 }
 
+hipError_t launch_reduce_gram(const float* parts, int ksplit, int m, int L, int nslices, int real_first, int real_last,
+                              float* yr, float* yi, const int* lact, double2* part, hipStream_t st)
+{
+    if (L > kMaxL || ksplit < 1 || ksplit > kMaxParts) return hipErrorInvalidValue;
+    const int ns = gram_split(m);
+    const dim3 g(ns, nslices);
+    if (L <= 22)
+        k_reduce_gram<1><<<g, 256, 0, st>>>(parts, ksplit, m, L, nslices, real_first, real_last, yr, yi, lact, part, ns);
+    else if (L <= 44)
+        k_reduce_gram<2><<<g, 256, 0, st>>>(parts, ksplit, m, L, nslices, real_first, real_last, yr, yi, lact, part, ns);
+    else
+        k_reduce_gram<3><<<g, 256, 0, st>>>(parts, ksplit, m, L, nslices, real_first, real_last, yr, yi, lact, part, ns);
+    return hipGetLastError();
+}
+
 hipError_t launch_cholqr_pass(const float* yr, const float* yi, int m, int L, const int* lact, int nslices,
                               int pass, double2* part, float* rir, float* rii, double2* rtot, float* rhr,
-                              float* rhi, int* status, hipStream_t st)
+                              float* rhi, int* status, hipStream_t st, bool gram_ready)
 {
     if (L > kMaxL) return hipErrorInvalidValue;
     const int ns = gram_split(m);
     // block edge B: the upper triangle of ceil(L/B) blocks fits 256 threads
-    if (L <= 22)
-        launch_gram<1>(yr, yi, m, L, lact, nslices, part, ns, st);
-    else if (L <= 44)
-        launch_gram<2>(yr, yi, m, L, lact, nslices, part, ns, st);
-    else
-        launch_gram<3>(yr, yi, m, L, lact, nslices, part, ns, st);
+    if (!gram_ready) {
+        if (L <= 22)
+            launch_gram<1>(yr, yi, m, L, lact, nslices, part, ns, st);
+        else if (L <= 44)
+            launch_gram<2>(yr, yi, m, L, lact, nslices, part, ns, st);
+        else
+            launch_gram<3>(yr, yi, m, L, lact, nslices, part, ns, st);
+    }
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     const size_t lds = 2 * (size_t)L * L * sizeof(double2);

@@ -105,6 +105,12 @@ int batch_tile(int tile);
 hipError_t launch_cgemm_batch(const CgemmArgs* items, const GemmUnit* units, int nunits, int tile, int grid,
                               double flops, double bytes, hipStream_t s);
 hipError_t launch_cgemm(const CgemmArgs& a, int opa, int opb, int prec, hipStream_t s);
+// FP32 narrow-output products split along k (ksplit > 1, part given): the
+// parts only, left in a.part ([ksplit][nslices][m][n], re then im) for the
+// caller to sum (launch_reduce_gram); cgemm_parts_ok says whether a product
+// qualifies
+bool cgemm_parts_ok(const CgemmArgs& a, int opa, int opb);
+hipError_t launch_cgemm_parts(const CgemmArgs& a, int opa, int opb, hipStream_t s);
 
 // -------------------------------------------------------------- Jacobi ----
 struct JacobiArgs {
@@ -185,9 +191,16 @@ hipError_t launch_store_basis(const float* zr, const float* zi, int n, int L, co
 size_t cholqr_part_bytes(int m, int L, int nslices);
 // one CholeskyQR pass on Y (m x L per slice): Gram in FP64, Cholesky, Rinv (FP32 planar);
 // rtot/rhr/rhi optional (accumulated R and, after pass 1, R^* restricted to the active block)
+// gram_ready: the Gram partials of Y are already in part (launch_reduce_gram)
 hipError_t launch_cholqr_pass(const float* yr, const float* yi, int m, int L, const int* lact, int nslices, int pass,
                               double2* part, float* rir, float* rii, double2* rtot, float* rhr, float* rhi,
-                              int* status, hipStream_t s);
+                              int* status, hipStream_t s, bool gram_ready = false);
+// the split parts of a narrow product summed in the fixed order kp = 0, 1, ...
+// into Y = (yr, yi) (m x L per slice, row-major, slice stride m L; imaginary
+// plane zero on the real slices), and the FP64 Gram partials of Y that
+// launch_cholqr_pass would form, in its layout (part)
+hipError_t launch_reduce_gram(const float* parts, int ksplit, int m, int L, int nslices, int real_first, int real_last,
+                              float* yr, float* yi, const int* lact, double2* part, hipStream_t s);
 hipError_t launch_rsvd_check(const float2* cols, const double* sigma, const float2* vr, const int* kpred,
                              const int* lact, const int* prefb, int L, double tau, Planes T, int* fallback, int* rank,
                              int nslices, hipStream_t s);
