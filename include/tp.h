@@ -148,7 +148,8 @@ int tp_teye(float* out, int n, int n3, void* stream);
  * Y = Ybar^(k) Om with the Gaussian sketch Om (Philox4x32-10 on counter
  * {row, column, slice, 0}, key = seed; Box-Muller; real on the real slices);
  * power_iters times {Z = Ybar^* Q, Y = Ybar Z}, every product re-orthonormalised
- * by CholeskyQR2 (Gram, Cholesky and inverse in FP64); Bh = Ybar^* Q =
+ * by CholeskyQR (Gram, Cholesky and inverse in FP64; two passes on every Y,
+ * one on the bases that only feed the next product); Bh = Ybar^* Q =
  * Q2 R2 (CholeskyQR2); one-sided Jacobi SVD of R2^* = U_r S V_r^*; and
  * W^(k) = Q U_r (S - tau)_+ V_r^* Q2^*.  A slice falls back to the full SVD
  * path of tp_prox_tnn when l > max_rank, or when the check sigma_(kpred+1) <
@@ -162,7 +163,9 @@ int tp_teye(float* out, int n, int n3, void* stream);
  * which FP32 data can resolve a result much smaller than its input) or
  * D = sum_j (sigma_j - tau)^2 (accuracy_ref = 1: relative to the result),
  * all slices get one more power iteration, up to
- * max_power_iters in total, and slices still failing then fall back.
+ * max_power_iters in total, and slices still failing then fall back (the
+ * extra iteration reuses the projection's basis Q2 as its Z and the check's
+ * product Ybar Q2 as its Y, so it forms no new product with Ybar).
  * With l = min(n1,n2) or an exact rank <= l the result equals tp_prox_tnn's
  * up to rounding.
  *   opts       required (see tp_learned_opts); rank, fallback, info optional

@@ -773,7 +773,12 @@ int tp_prox_tnn_learned(const float* Y, float* X, int n1, int n2, int n3, float 
                 TP_TRY(hipMemcpy(fb, hfb.data(), h * sizeof(int), hipMemcpyHostToDevice));
                 break;
             }
-            st = power_iteration();
+            // the next subspace iteration needs no new product: Ybar^* Y is
+            // the projection just formed (its orthonormal basis Q2 is in W.za),
+            // and Ybar Q2, whose span is that of the iteration's Ybar Z, is the
+            // residual check's product in W.yb; Y = orth(Ybar Q2)
+            std::swap(W.ya, W.yb);
+            st = cholqr(W, W.ya, W.yb, n1, L, h, rl, 2, false, s);
             if (st != TP_OK) return st;
             ++q;
         }

@@ -115,6 +115,31 @@ def test_learned_prox_exact_on_low_rank(tp, orc, n1, n2, n3, r):
     assert np.array_equal(rk.cpu().numpy(), (sig > np.float32(tau)).sum(axis=1))
 
 
+def test_learned_prox_split_parts_with_gram(tp, orc):
+    """Range-finder products split along k leave their parts, summed together
+    with the first CholeskyQR pass's Gram (k_reduce_gram); the same call with
+    the split turned off (TP_PARAM_GEMM_KSPLIT = 1: one part, plain Gram)
+    agrees to FP32 rounding, and both match the full-SVD prox."""
+    from paper_1806_07247_amd import _lib
+    lib = _lib.load()
+    n1, n2, n3, r = 768, 320, 4, 6
+    Y = gpu(lowrank(orc, n1, n2, n3, r, seed=77))
+    tau = 0.2 * orc.tsn(Y.cpu().numpy())
+    kw = dict(fixed_rank=r, oversample=6, power_iters=2, max_rank=32, seed=9)
+    X_split = tp.tp_prox_tnn_learned(Y, tau, **kw).cpu().numpy()
+    try:
+        assert lib.tp_set_param(8, 1) == 0
+        X_one = tp.tp_prox_tnn_learned(Y, tau, **kw).cpu().numpy()
+    finally:
+        lib.tp_set_param(8, 0)
+    X_full = tp.tp_prox_tnn(Y, tau).cpu().numpy()
+    d = rel_fro(X_split, X_one)
+    e1, e2 = rel_fro(X_split, X_full), rel_fro(X_one, X_full)
+    say(f"  split vs one part {d:.2e}; vs full SVD {e1:.2e} / {e2:.2e}")
+    assert d <= 1e-5
+    assert e1 <= 1e-4 and e2 <= 1e-4
+
+
 def test_learned_prox_matches_oracle_rsvd(tp, orc):
     """Same Philox sketch, same predicted counts: GPU (FP32 data, FP64
     CholeskyQR and rotations) against the FP64 oracle of the randomized prox."""
