@@ -37,6 +37,23 @@ __device__ __forceinline__ int rr_col(int pos, int step, int np)
     return 1 + c;
 }
 
+// 1/sqrt(x) and 1/x for normal x > 0 (x != 0): the hardware estimate and two
+// Newton steps, each doubling the correct bits
+__device__ __forceinline__ double rsqrt_f64(double x)
+{
+    double y = __builtin_amdgcn_rsq(x);
+    double h = x * y;
+    y = fma(0.5 * y, fma(-h, y, 1.0), y);
+    h = x * y;
+    return fma(0.5 * y, fma(-h, y, 1.0), y);
+}
+__device__ __forceinline__ double rcp_f64(double x)
+{
+    double y = __builtin_amdgcn_rcp(x);
+    y = fma(y, fma(-x, y, 1.0), y);
+    return fma(y, fma(-x, y, 1.0), y);
+}
+
 // DPP move of a double within a row of 16 lanes
 template <int CTRL>
 __device__ __forceinline__ double dpp_f64(double v)
@@ -102,11 +119,14 @@ __device__ __forceinline__ bool jacobi_pair(float2* work, int ldr, int p, int q,
     if (!(g2 > 0.0 && g2 > tol2 * al * be)) return false;
     // x' = c x - s conj(e) y,  y' = s e x + c y,  e = gamma/|gamma|,
     // t = s/c the smaller root of t^2 + 2 zeta t - 1 = 0, zeta = (beta - alpha)/(2|gamma|)
-    const double g = sqrt(g2);
-    const double ig = 1.0 / g;
+    // the chain of square roots and reciprocals from the hardware estimates
+    // refined by Newton steps (relative error ~1e-15, far below the FP32
+    // columns' rounding; a fraction of the IEEE sequences' latency)
+    const double ig = rsqrt_f64(g2);
     const double zeta = 0.5 * (be - al) * ig;
-    const double t = copysign(1.0, zeta) / (fabs(zeta) + sqrt(fma(zeta, zeta, 1.0)));
-    const double c = 1.0 / sqrt(fma(t, t, 1.0));
+    const double z2 = fma(zeta, zeta, 1.0);
+    const double t = copysign(rcp_f64(fabs(zeta) + z2 * rsqrt_f64(z2)), zeta);
+    const double c = rsqrt_f64(fma(t, t, 1.0));
     const double sn = c * t;
     const float cf = (float)c;
     const float sr = (float)(sn * gr * ig), si = (float)(sn * gi * ig);  // s e
