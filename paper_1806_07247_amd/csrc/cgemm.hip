@@ -710,10 +710,11 @@ k_skinny(CgemmArgs p)
 }
 
 // -------------------------------------------------------------- wide FP32 --
-// Products with a short inner dimension and a wide output: A (m x k, k <= 48)
-// times B (k x n), neither transposed (the reconstruction W = Q M1 of the
-// randomized SVT).  A workgroup of four wavefronts covers 64 rows x 256
-// columns.  Each wavefront keeps its 16 rows of A in registers, in the MFMA
+// Products with a short inner dimension: A (m x k, k <= 48) times B (k x n),
+// neither transposed (the reconstruction W = Q M1 of the randomized SVT, and
+// with at most 64 output columns the products by R^-1 and the Ritz bases).
+// A workgroup of four wavefronts covers 64 rows x 256 columns (x 64 columns,
+// masked, for the narrow outputs).  Each wavefront keeps its 16 rows of A in registers, in the MFMA
 // operand layout of k_skinny (loaded once), and walks the four 64-column
 // blocks; the k x 64 block of B goes through LDS (row-major, rows padded to
 // 68 floats, double-buffered: the next block's loads are in flight while
@@ -724,9 +725,12 @@ constexpr int kWideRows = 64, kWideCols = 256, kWideBlk = 64, kWideMaxK = 48;
 constexpr int kWideLDB = kWideBlk + 4;  // 4 x 68 = 16 mod 64 banks: a lane's four fragment reads hit distinct banks
 
 // KC: staged inner rows (k rounded up to 16; zero beyond k)
-template <bool REAL, int KC>
+// NB: 64-column blocks per workgroup (4: the unmasked full tiles; 1: a
+// masked tile for narrow outputs, rows < m and columns < n, n a multiple of 4)
+template <bool REAL, int KC, int NB>
 __device__ __forceinline__ void wide_tile(const CgemmArgs& p, const SliceView& v, int x, int y, float* lds)
 {
+    constexpr bool MASK = NB == 1;
     constexpr int GB = KC * (kWideBlk / 4) / 256;  // 4-column groups of a B block per thread
     constexpr int nh = KC / 16;
     constexpr int PL = KC * kWideLDB;
@@ -734,7 +738,7 @@ __device__ __forceinline__ void wide_tile(const CgemmArgs& p, const SliceView& v
     const int r = lane & 15, g = lane >> 4;
     const int row = y * kWideRows + 16 * wave + r;
     const int K = v.K;
-    const int n0 = x * kWideCols;
+    const int n0 = x * kWideBlk * NB;
 
     // A: chunk h holds A(row, 16 h + 4 g + s), s = 0..3
     float fa_r[nh * 4], fa_i[nh * 4];
@@ -742,7 +746,7 @@ __device__ __forceinline__ void wide_tile(const CgemmArgs& p, const SliceView& v
 #pragma unroll
     for (int h = 0; h < nh; ++h) {
         const int kb = 16 * h + 4 * g;
-        const int valid = max(0, min(4, K - kb));
+        const int valid = MASK && row >= p.m ? 0 : max(0, min(4, K - kb));
         const Quad q = load4(v.ar, v.ai, (long long)row * p.lda + kb, valid, veca, false);
         fa_r[4 * h + 0] = q.r.x;
         fa_r[4 * h + 1] = q.r.y;
@@ -755,13 +759,17 @@ __device__ __forceinline__ void wide_tile(const CgemmArgs& p, const SliceView& v
     }
 
     float4 bq_r[GB], bq_i[GB];
+    bool bok[GB];  // MASK: the group's columns exist (else stored as zeros)
     // B block j into registers: rows beyond K read row K-1 (kept in range) and are zeroed when stored
     auto load_b = [&](int j) __attribute__((always_inline)) {
 #pragma unroll
         for (int u = 0; u < GB; ++u) {
             const int e = tid + 256 * u;
             {
-                const int kr = min(e / (kWideBlk / 4), K - 1), col = n0 + kWideBlk * j + 4 * (e % (kWideBlk / 4));
+                const int kr = min(e / (kWideBlk / 4), K - 1);
+                int col = n0 + kWideBlk * j + 4 * (e % (kWideBlk / 4));
+                bok[u] = !MASK || col < p.n;
+                if (MASK && !bok[u]) col = 0;  // an in-range group, zeroed when stored
                 const long long off = (long long)kr * p.ldb + col;
                 bq_r[u] = *reinterpret_cast<const float4*>(v.br + off);
                 bq_i[u] = *reinterpret_cast<const float4*>(v.bi + off);
@@ -777,7 +785,7 @@ __device__ __forceinline__ void wide_tile(const CgemmArgs& p, const SliceView& v
             {
                 const int kr = e / (kWideBlk / 4), c = 4 * (e % (kWideBlk / 4));
                 float4 qr = bq_r[u], qi = bq_i[u];  // by value: a select of two lvalues would go through memory
-                if (kr >= K) qr = qi = make_float4(0.f, 0.f, 0.f, 0.f);
+                if (kr >= K || !bok[u]) qr = qi = make_float4(0.f, 0.f, 0.f, 0.f);
                 *reinterpret_cast<float4*>(br + kr * kWideLDB + c) = qr;
                 *reinterpret_cast<float4*>(bi + kr * kWideLDB + c) = qi;
             }
@@ -790,8 +798,8 @@ __device__ __forceinline__ void wide_tile(const CgemmArgs& p, const SliceView& v
     load_b(0);
     store_b(0);
     __syncthreads();
-    for (int j = 0; j < kWideCols / kWideBlk; ++j) {
-        const bool more = j + 1 < kWideCols / kWideBlk;
+    for (int j = 0; j < NB; ++j) {
+        const bool more = j + 1 < NB;
         if (more) load_b(j + 1);
         floatx4 p1[4], p2[4], p3[4];
 #pragma unroll
@@ -825,7 +833,9 @@ __device__ __forceinline__ void wide_tile(const CgemmArgs& p, const SliceView& v
         for (int t = 0; t < 4; ++t) {
             const floatx4 cre = REAL ? p1[t] : p1[t] - p2[t];
             const floatx4 cim = REAL ? floatx4{0.f, 0.f, 0.f, 0.f} : p3[t] - p1[t] - p2[t];
-            const long long off = (long long)row * v.ldc + n0 + kWideBlk * j + 16 * t + 4 * g;
+            const int col = n0 + kWideBlk * j + 16 * t + 4 * g;
+            if (MASK && (row >= p.m || col >= p.n)) continue;  // n a multiple of 4: all four columns or none
+            const long long off = (long long)row * v.ldc + col;
             if (vecc) {
                 *reinterpret_cast<floatx4*>(v.cr + off) = cre;
                 *reinterpret_cast<floatx4*>(v.ci + off) = cim;
@@ -842,18 +852,20 @@ __device__ __forceinline__ void wide_tile(const CgemmArgs& p, const SliceView& v
     }
 }
 
-// three wavefronts per SIMD (no spills; measured 7% faster than two)
-template <int KC>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3, 3))) void k_wide(CgemmArgs p)
+// three wavefronts per SIMD for the four-block tile (no spills; measured 7%
+// faster than two)
+template <int KC, int NB>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(NB > 1 ? 3 : 1, NB > 1 ? 3 : 10))) void
+k_wide(CgemmArgs p)
 {
-    __shared__ __attribute__((aligned(16))) float wlds[2 * 2 * KC * kWideLDB];
+    __shared__ __attribute__((aligned(16))) float wlds[(NB > 1 ? 2 : 1) * 2 * KC * kWideLDB];
     int x, y, z;
-    xcd_tile(x, y, z);  // x = 256-column group, y = 64-row tile, z = slice
+    xcd_tile(x, y, z);  // x = column group (64 NB), y = 64-row tile, z = slice
     const SliceView v = slice_view(p, z, 0);
     if (v.real)
-        wide_tile<true, KC>(p, v, x, y, wlds);
+        wide_tile<true, KC, NB>(p, v, x, y, wlds);
     else
-        wide_tile<false, KC>(p, v, x, y, wlds);
+        wide_tile<false, KC, NB>(p, v, x, y, wlds);
 }
 
 // Batched products of uneven shapes: a persistent grid walks a list of
@@ -1074,26 +1086,37 @@ hipError_t launch_skinny(const CgemmArgs& a, hipStream_t s, bool reduce = true)
 // the wide kernel takes FP32 products A B, 1 <= k <= 48 (the same for every
 // slice), whole 64 x 256 tiles, 16-byte aligned planes and rows (B and C), no
 // split
-bool wide_ok(const CgemmArgs& a, int opa, int opb)
+// 0: no; 4: whole 64 x 256 tiles (unmasked); 1: outputs at most 64 columns
+// wide, a multiple of 4 (masked rows and columns)
+int wide_form(const CgemmArgs& a, int opa, int opb)
 {
     const unsigned long long al = reinterpret_cast<unsigned long long>(a.br) |
                                   reinterpret_cast<unsigned long long>(a.bi) |
                                   reinterpret_cast<unsigned long long>(a.cr) | reinterpret_cast<unsigned long long>(a.ci);
-    return opa == OP_N && opb == OP_N && !a.kdyn && a.k >= 1 && a.k <= kWideMaxK && a.m % kWideRows == 0 &&
-           a.n % kWideCols == 0 && a.ksplit <= 1 && (al & 15) == 0 && a.ldb % 4 == 0 && a.sb % 4 == 0 &&
-           a.ldc % 4 == 0 && a.sc % 4 == 0;
+    if (!(opa == OP_N && opb == OP_N && !a.kdyn && a.k >= 1 && a.k <= kWideMaxK && a.ksplit <= 1 && (al & 15) == 0 &&
+          a.ldb % 4 == 0 && a.sb % 4 == 0 && a.ldc % 4 == 0 && a.sc % 4 == 0))
+        return 0;
+    if (a.m % kWideRows == 0 && a.n % kWideCols == 0) return 4;
+    if (a.n <= kWideBlk && a.n % 4 == 0) return 1;
+    return 0;
 }
 
-hipError_t launch_wide(const CgemmArgs& a, hipStream_t s)
+template <int NB>
+hipError_t launch_wide_nb(const CgemmArgs& a, hipStream_t s)
 {
-    const dim3 g(a.n / kWideCols, a.m / kWideRows, a.nslices);
+    const dim3 g((a.n + kWideBlk * NB - 1) / (kWideBlk * NB), (a.m + kWideRows - 1) / kWideRows, a.nslices);
     if (a.k <= 16)
-        k_wide<16><<<g, 256, 0, s>>>(a);
+        k_wide<16, NB><<<g, 256, 0, s>>>(a);
     else if (a.k <= 32)
-        k_wide<32><<<g, 256, 0, s>>>(a);
+        k_wide<32, NB><<<g, 256, 0, s>>>(a);
     else
-        k_wide<48><<<g, 256, 0, s>>>(a);
+        k_wide<48, NB><<<g, 256, 0, s>>>(a);
     return hipGetLastError();
+}
+
+hipError_t launch_wide(const CgemmArgs& a, int form, hipStream_t s)
+{
+    return form == 4 ? launch_wide_nb<4>(a, s) : launch_wide_nb<1>(a, s);
 }
 
 // the skinny kernel takes FP32 products with op(B) = B, n <= 64 and a
@@ -1206,7 +1229,10 @@ hipError_t launch_cgemm(const CgemmArgs& a, int opa, int opb, int prec, hipStrea
     const int tuned = param(TP_PARAM_GEMM_VARIANT);
     if ((tuned == 0 || tuned == 7) && skinny_ok(a, opb, tuned == 7 ? 1 : 64) && (opa == OP_N || opa == OP_C))
         return opa == OP_N ? launch_skinny<OP_N>(a, s) : launch_skinny<OP_C>(a, s);
-    if ((tuned == 0 || tuned == 8) && wide_ok(a, opa, opb)) return launch_wide(a, s);
+    if (tuned == 0 || tuned == 8) {
+        const int form = wide_form(a, opa, opb);
+        if (form) return launch_wide(a, form, s);
+    }
     if (opa == OP_N && opb == OP_N) return launch_ops<OP_N, OP_N>(a, variant, s);
     if (opa == OP_C && opb == OP_N) return launch_ops<OP_C, OP_N>(a, variant, s);
     if (opa == OP_N && opb == OP_C) return launch_ops<OP_N, OP_C>(a, variant, s);

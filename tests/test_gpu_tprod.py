@@ -162,15 +162,16 @@ def test_tprod_narrow_output_kernel_short_inner(tp, orc, shape):
 
 
 WIDE = [(64, 17, 256, 5), (128, 48, 512, 4), (192, 1, 256, 3), (64, 40, 768, 6), (128, 32, 256, 2),
-        (64, 8, 512, 9)]
+        (64, 8, 512, 9), (130, 40, 40, 5), (64, 48, 64, 3), (1000, 8, 16, 4), (33, 12, 4, 6), (5, 3, 60, 2)]
 
 
 @pytest.mark.parametrize("shape", WIDE, ids=lambda s: "x".join(map(str, s)))
 def test_tprod_wide_output_kernel(tp, orc, shape):
-    """FP32 slice products with an inner dimension of at most 48 and whole
-    64 x 256 output tiles take the wide-output kernel (A in registers, the
-    output streamed): inner dimensions 1 .. 48 (ragged against its 16-deep
-    stages), real first and last slices."""
+    """FP32 slice products with an inner dimension of at most 48 take the
+    wide-output kernel (A in registers, the output streamed): whole 64 x 256
+    output tiles, and (masked) outputs at most 64 columns wide with ragged
+    rows; inner dimensions 1 .. 48 (ragged against its 16-deep stages), real
+    first and last slices."""
     from paper_1806_07247_amd import inputs
     n1, n2, l, n3 = shape
     say(f"tprod wide {shape}")
