@@ -679,34 +679,42 @@ __global__ __launch_bounds__(256) void k_features_part(const float* __restrict__
     }
 }
 
+constexpr int kFeatSplit = 16;  // row bands of the column norms (partials summed by k_features)
+
 __global__ __launch_bounds__(256) void k_features(const double* __restrict__ part, int m, int n, int nsplit, int n3,
                                                   int nslices, double tau, const int* __restrict__ prev,
                                                   const float* __restrict__ psig, float* __restrict__ feats,
                                                   double* __restrict__ fro2)
 {
-    __shared__ double red[256];
-    __shared__ double redm[256];
+    __shared__ double red[4], redm[4];
     const int s = blockIdx.x, tid = threadIdx.x;
     double tot = 0.0, cmax = 0.0;
     for (int j = tid; j < n; j += blockDim.x) {
+        // the column's partial sums all in flight, then added in the fixed order b = 0, 1, ...
+        double v[kFeatSplit];
+#pragma unroll
+        for (int b = 0; b < kFeatSplit; ++b) v[b] = b < nsplit ? part[((long long)s * nsplit + b) * n + j] : 0.0;
         double c = 0.0;
-        for (int b = 0; b < nsplit; ++b) c += part[((long long)s * nsplit + b) * n + j];
+#pragma unroll
+        for (int b = 0; b < kFeatSplit; ++b) c += v[b];
         tot += c;
         cmax = fmax(cmax, c);
     }
-    red[tid] = tot;
-    redm[tid] = cmax;
-    __syncthreads();
-    for (int w = blockDim.x / 2; w > 0; w >>= 1) {
-        if (tid < w) {
-            red[tid] += red[tid + w];
-            redm[tid] = fmax(redm[tid], redm[tid + w]);
-        }
-        __syncthreads();
+    // wavefront butterflies (every lane ends with the same bits), then the four wavefronts in order
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+        tot += __shfl_xor(tot, o);
+        cmax = fmax(cmax, __shfl_xor(cmax, o));
     }
+    if ((tid & 63) == 0) {
+        red[tid >> 6] = tot;
+        redm[tid >> 6] = cmax;
+    }
+    __syncthreads();
     if (tid == 0) {
         const int p = m < n ? m : n;
-        const double nrm2 = red[0], cm = redm[0], t2 = tau * tau;
+        const double nrm2 = ((red[0] + red[1]) + red[2]) + red[3], t2 = tau * tau;
+        const double cm = fmax(fmax(redm[0], redm[1]), fmax(redm[2], redm[3]));
         if (fro2) fro2[s] = nrm2;
         auto clampf = [](double v) { return (float)fmin(30.0, fmax(-30.0, v)); };
         float* f = feats + (long long)s * TP_MLP_INPUTS;
@@ -1115,7 +1123,7 @@ hipError_t launch_accuracy(Planes t1, Planes t2, const double* sigma, const int*
     return hipGetLastError();
 }
 
-int features_split(int m) { return m < 16 * 32 ? (m + 31) / 32 : 16; }
+int features_split(int m) { return m < kFeatSplit * 32 ? (m + 31) / 32 : kFeatSplit; }
 
 size_t features_part_bytes(int m, int n, int nslices)
 {
