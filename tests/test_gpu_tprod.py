@@ -182,6 +182,35 @@ def test_tprod_wide_output_kernel(tp, orc, shape):
     assert err <= TOL["fp32"]
 
 
+def _sweep_shapes(count=40, seed=2024):
+    """Seeded random shapes biased to the slice-product kernels' boundaries:
+    output widths multiples of 4 up to 64 (narrow / masked wide), inner
+    dimensions around 48 and 64, 64-row and 256-column multiples, and ragged
+    sizes that fall back to the tiles."""
+    rng = np.random.default_rng(seed)
+    out = []
+    for _ in range(count):
+        n1 = int(rng.choice([int(rng.integers(1, 200)), 64 * int(rng.integers(1, 4))]))
+        n2 = int(rng.choice([int(rng.integers(1, 130)), 48, 64, 65, 47, 256, 300]))
+        l = int(rng.choice([4 * int(rng.integers(1, 17)), int(rng.integers(1, 70)), 256]))
+        n3 = int(rng.integers(1, 9))
+        out.append((n1, n2, l, n3))
+    return out
+
+
+@pytest.mark.parametrize("shape", _sweep_shapes(), ids=lambda s: "x".join(map(str, s)))
+def test_tprod_shape_sweep(tp, orc, shape):
+    """FP32 tprod on seeded random shapes against the FP64 oracle (whichever
+    slice-product kernel each shape selects)."""
+    from paper_1806_07247_amd import inputs
+    n1, n2, l, n3 = shape
+    A, B = inputs.tprod_pair(n1, n2, l, n3, seed=n1 * 7 + n2 * 3 + l + n3)
+    C = tp.tp_tprod(gpu(A), gpu(B), prec="fp32").cpu().numpy()
+    err = rel_fro(C, orc.tprod(A, B))
+    say(f"  sweep {shape}: rel.err {err:.2e}")
+    assert err <= TOL["fp32"]
+
+
 @pytest.mark.parametrize("direct", [1, 2])
 @pytest.mark.parametrize("shape", [(33, 31, 29, 8), (70, 65, 80, 64), (40, 36, 33, 128), (17, 13, 11, 16)],
                          ids=lambda s: "x".join(map(str, s)))
