@@ -185,7 +185,8 @@ int tp_teye(float* out, int n, int n3, void* stream);
  *   nonzero), else zeros:
  *   8 #{s_j > tau}/p   9 #{s_j > tau/1.25}/p   10 log(s_1/tau)
  *   11 one when c > 0 and s_c > tau (the previous sketch saw no value below tau)
- * the logarithms clamped to [-30, 30].  The MLP maps them to y and
+ * the logarithms clamped to [-30, 30] (their clamped limits where a norm or tau
+ * is 0: feature 0 is 30 for a zero slice).  The MLP maps them to y and
  * kpred = round(expm1(y * log1p(p))) clipped to [0, p].
  * Warm start (optional): basis_out receives this call's right Ritz vectors
  * Q2 V of every slice (the right range basis rotated by the small SVD, so

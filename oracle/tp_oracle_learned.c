@@ -417,7 +417,8 @@ void or_slice_features(const double* Y, int n1, int n2, int n3, double tau, cons
         }
         const double t2 = tau * tau;
         double* f = feats + (i64)k * 12;
-        f[0] = (nrm2 > 0.0 && t2 > 0.0) ? fmin(30.0, fmax(-30.0, 0.5 * log(t2 * p / nrm2))) : -30.0;
+        /* log(tau / rms sigma): +30 for a zero slice, -30 for tau = 0 (the clamped limits) */
+        f[0] = nrm2 > 0.0 ? (t2 > 0.0 ? fmin(30.0, fmax(-30.0, 0.5 * log(t2 * p / nrm2))) : -30.0) : 30.0;
         f[1] = (cmax > 0.0 && t2 > 0.0) ? fmin(30.0, fmax(-30.0, 0.5 * log(cmax / t2))) : (cmax > 0.0 ? 30.0 : -30.0);
         f[2] = prev ? (double)prev[k] / p : 0.0;
         f[3] = prev ? 1.0 : 0.0;

@@ -348,43 +348,26 @@ tp::Arena tsvd_arena(void* ws, size_t bytes, int n1, int n2, int n3, TsvdLayout*
 
 }  // namespace
 
-extern "C" {
+namespace tp {
 
-const char* tp_status_string(int status)
-{
-    switch (status) {
-        case TP_OK: return "ok";
-        case TP_ERR_ARG: return "invalid argument";
-        case TP_ERR_SHAPE: return "invalid or unsupported shape";
-        case TP_ERR_WORKSPACE: return "workspace missing or too small";
-        case TP_ERR_HIP: return "HIP kernel launch failed";
-        case TP_ERR_UNSUPPORTED: return "unsupported request";
-        default: return "unknown status";
-    }
-}
-
-int tp_version(void) { return 100; }
-
-size_t tp_tprod_workspace_size(int n1, int n2, int l, int n3, int prec)
-{
-    (void)prec;
-    if (bad_dim(n1) || bad_dim(n2) || bad_dim(l) || bad_dim(n3)) return 0;
-    return tprod_arena(nullptr, 0, n1, n2, l, n3, nullptr).used;
-}
-
-int tp_tprod(const float* A, const float* B, float* C, int n1, int n2, int l, int n3, int prec,
-             void* workspace, size_t workspace_bytes, void* stream)
+// Argument checks of tp_tprod (Definition 2.1 sizes).
+int check_tprod(const float* A, const float* B, const float* C, int n1, int n2, int l, int n3, int prec)
 {
     if (!A || !B || !C) return TP_ERR_ARG;
     if (prec != TP_PREC_FP32 && prec != TP_PREC_BF16X3 && prec != TP_PREC_BF16) return TP_ERR_ARG;
-    if (bad_dim(n1) || bad_dim(n2) || bad_dim(l) || bad_dim(n3) || n3 > kMaxN3) return TP_ERR_SHAPE;
-    if (bad_slice(n1, n2) || bad_slice(n2, l) || bad_slice(n1, l)) return TP_ERR_SHAPE;
-    TprodLayout L;
-    tp::Arena ar = tprod_arena(workspace, workspace_bytes, n1, n2, l, n3, &L);
-    if (!ar.ok) return TP_ERR_WORKSPACE;
-    hipStream_t s = as_stream(stream);
-    const int h = tp::half_slices(n3);
+    if (::bad_dim(n1) || ::bad_dim(n2) || ::bad_dim(l) || ::bad_dim(n3) || n3 > kMaxN3) return TP_ERR_SHAPE;
+    if (::bad_slice(n1, n2) || ::bad_slice(n2, l) || ::bad_slice(n1, l)) return TP_ERR_SHAPE;
+    return TP_OK;
+}
 
+// Algorithm 1 on checked arguments, with the half spectra in `workspace`.
+int run_tprod(const float* A, const float* B, float* C, int n1, int n2, int l, int n3, int prec, void* workspace,
+              size_t workspace_bytes, hipStream_t s)
+{
+    TprodLayout L;
+    tp::Arena ar = ::tprod_arena(workspace, workspace_bytes, n1, n2, l, n3, &L);
+    if (!ar.ok) return TP_ERR_WORKSPACE;
+    const int h = tp::half_slices(n3);
     // Algorithm 1, step 1: DFT of the tubes of A and B
     TP_LAUNCH(tp::K_RFFT, s, tp::launch_rfft(A, L.a.re, L.a.im, (long long)n1 * n2, n3, s));
     TP_LAUNCH(tp::K_RFFT, s, tp::launch_rfft(B, L.b.re, L.b.im, (long long)n2 * l, n3, s));
@@ -413,6 +396,41 @@ int tp_tprod(const float* A, const float* B, float* C, int n1, int n2, int l, in
     // step 3: inverse DFT (conjugate fill implicit)
     TP_LAUNCH(tp::K_IRFFT, s, tp::launch_irfft(L.c.re, L.c.im, C, (long long)n1 * l, n3, s));
     return TP_OK;
+}
+
+
+}  // namespace tp
+
+extern "C" {
+
+const char* tp_status_string(int status)
+{
+    switch (status) {
+        case TP_OK: return "ok";
+        case TP_ERR_ARG: return "invalid argument";
+        case TP_ERR_SHAPE: return "invalid or unsupported shape";
+        case TP_ERR_WORKSPACE: return "workspace missing or too small";
+        case TP_ERR_HIP: return "HIP kernel launch failed";
+        case TP_ERR_UNSUPPORTED: return "unsupported request";
+        default: return "unknown status";
+    }
+}
+
+int tp_version(void) { return 100; }
+
+size_t tp_tprod_workspace_size(int n1, int n2, int l, int n3, int prec)
+{
+    (void)prec;
+    if (bad_dim(n1) || bad_dim(n2) || bad_dim(l) || bad_dim(n3)) return 0;
+    return tprod_arena(nullptr, 0, n1, n2, l, n3, nullptr).used;
+}
+
+int tp_tprod(const float* A, const float* B, float* C, int n1, int n2, int l, int n3, int prec,
+             void* workspace, size_t workspace_bytes, void* stream)
+{
+    const int c = tp::check_tprod(A, B, C, n1, n2, l, n3, prec);
+    if (c != TP_OK) return c;
+    return tp::run_tprod(A, B, C, n1, n2, l, n3, prec, workspace, workspace_bytes, as_stream(stream));
 }
 
 size_t tp_prox_tnn_workspace_size(int n1, int n2, int n3)
@@ -747,8 +765,8 @@ int tp_prox_tnn_learned(const float* Y, float* X, int n1, int n2, int n3, float 
             j.whole = 1;
             TP_LAUNCH(tp::K_JACOBI, s, tp::launch_jacobi(j, nullptr, 0, s));
             TP_LAUNCH(tp::K_RSVD_CHECK, s,
-                      tp::launch_rsvd_check(W.jcols, W.jsig, W.jv, W.kpred, W.lact, W.prefb, L, (double)tau, W.T, fb,
-                                            rk, h, s));
+                      tp::launch_rsvd_check(W.jcols, W.jsig, W.jv, W.kpred, W.lact, W.prefb, W.status, L, (double)tau,
+                                            W.T, fb, rk, h, s));
             if (!(opts->accuracy > 0.0f)) break;
             // a posteriori check: residuals Ybar v_j - sigma_j u_j of the kept Ritz triplets
             TP_LAUNCH(tp::K_ACCURACY, s, tp::launch_cm_to_planar(W.jv, W.vp, L, h, s));

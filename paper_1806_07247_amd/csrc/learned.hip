@@ -514,7 +514,8 @@ __global__ __launch_bounds__(kCholThreads) void k_chol(const double2* __restrict
 __global__ __launch_bounds__(256) void k_rsvd_check(const float2* __restrict__ cols, const double* __restrict__ sigma,
                                                     const float2* __restrict__ vr, const int* __restrict__ kpred,
                                                     const int* __restrict__ lact, const int* __restrict__ prefb,
-                                                    int L, double tau, float* __restrict__ tr, float* __restrict__ ti,
+                                                    const int* __restrict__ status, int L, double tau,
+                                                    float* __restrict__ tr, float* __restrict__ ti,
                                                     int* __restrict__ fallback, int* __restrict__ rank)
 {
     __shared__ double scale[64];
@@ -522,13 +523,16 @@ __global__ __launch_bounds__(256) void k_rsvd_check(const float2* __restrict__ c
     const int s = blockIdx.x, tid = threadIdx.x;
     const double* sg = sigma + (long long)s * L;
     if (tid == 0) {
+        // counted NaN-safe: a NaN singular value counts as not below tau, so
+        // a broken basis fails the check instead of passing it
         int ge = 0, gt = 0;
         for (int j = 0; j < lact[s]; ++j) {
-            ge += sg[j] >= tau ? 1 : 0;
+            ge += !(sg[j] < tau) ? 1 : 0;
             gt += sg[j] > tau ? 1 : 0;
         }
         above = gt;
-        fallback[s] = (prefb[s] || (ge > kpred[s] && lact[s] > 0)) ? 1 : 0;
+        // a CholeskyQR breakdown on any basis of this slice (status) also sends it to the full SVD
+        fallback[s] = (prefb[s] || (status && status[s]) || (ge > kpred[s] && lact[s] > 0)) ? 1 : 0;
         if (fallback[s] == 0 && rank) rank[s] = gt;
     }
     for (int j = tid; j < L; j += blockDim.x)
@@ -632,7 +636,9 @@ __global__ __launch_bounds__(64) void k_accuracy(const double* __restrict__ part
     for (int j = 0; j < lact[s]; ++j)
         if (sg[j] > tau) den += (sg[j] - tau) * (sg[j] - tau);
     if (fro2 && den > 0.0) den = fmax(den, fro2[s]);
-    bad[s] = (den > 0.0 && num > delta * delta * den) ? 1 : 0;
+    // NaN-safe: anything but a finite residual within the bound fails
+    // (num is 0 when no triplet is kept, and 0 <= 0 passes)
+    bad[s] = !(num <= delta * delta * den) ? 1 : 0;
 }
 
 // ---------------------------------------------------------------- features --
@@ -718,7 +724,8 @@ __global__ __launch_bounds__(256) void k_features(const double* __restrict__ par
         if (fro2) fro2[s] = nrm2;
         auto clampf = [](double v) { return (float)fmin(30.0, fmax(-30.0, v)); };
         float* f = feats + (long long)s * TP_MLP_INPUTS;
-        f[0] = (nrm2 > 0.0 && t2 > 0.0) ? clampf(0.5 * log(t2 * p / nrm2)) : -30.0f;
+        // a zero slice (or tau = 0) takes the clamped limit of the logarithm
+        f[0] = nrm2 > 0.0 ? (t2 > 0.0 ? clampf(0.5 * log(t2 * p / nrm2)) : -30.0f) : 30.0f;
         f[1] = (cm > 0.0 && t2 > 0.0) ? clampf(0.5 * log(cm / t2)) : (cm > 0.0 ? 30.0f : -30.0f);
         f[2] = prev ? (float)prev[s] / (float)p : 0.0f;
         f[3] = prev ? 1.0f : 0.0f;
@@ -1096,10 +1103,11 @@ size_t cholqr_part_bytes(int m, int L, int nslices)
 }
 
 hipError_t launch_rsvd_check(const float2* cols, const double* sigma, const float2* vr, const int* kpred,
-                             const int* lact, const int* prefb, int L, double tau, Planes T, int* fallback, int* rank,
-                             int nslices, hipStream_t st)
+                             const int* lact, const int* prefb, const int* status, int L, double tau, Planes T,
+                             int* fallback, int* rank, int nslices, hipStream_t st)
 {
-    k_rsvd_check<<<nslices, 256, 0, st>>>(cols, sigma, vr, kpred, lact, prefb, L, tau, T.re, T.im, fallback, rank);
+    k_rsvd_check<<<nslices, 256, 0, st>>>(cols, sigma, vr, kpred, lact, prefb, status, L, tau, T.re, T.im, fallback,
+                                          rank);
     return hipGetLastError();
 }
 

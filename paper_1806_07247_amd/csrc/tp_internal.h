@@ -201,9 +201,10 @@ hipError_t launch_cholqr_pass(const float* yr, const float* yi, int m, int L, co
 // launch_cholqr_pass would form, in its layout (part)
 hipError_t launch_reduce_gram(const float* parts, int ksplit, int m, int L, int nslices, int real_first, int real_last,
                               float* yr, float* yi, const int* lact, double2* part, hipStream_t s);
+// status: per-slice CholeskyQR breakdown flags (or null), OR-ed into fallback
 hipError_t launch_rsvd_check(const float2* cols, const double* sigma, const float2* vr, const int* kpred,
-                             const int* lact, const int* prefb, int L, double tau, Planes T, int* fallback, int* rank,
-                             int nslices, hipStream_t s);
+                             const int* lact, const int* prefb, const int* status, int L, double tau, Planes T,
+                             int* fallback, int* rank, int nslices, hipStream_t s);
 hipError_t launch_cm_to_planar(const float2* src, Planes dst, int L, int nslices, hipStream_t s);
 // part: accuracy_part_bytes(nslices) of workspace for the per-band partial sums
 size_t accuracy_part_bytes(int nslices);
@@ -226,6 +227,11 @@ hipError_t launch_adam(float* p, const float* g, float* m, float* v, int count, 
                        float eps, hipStream_t s);
 hipError_t launch_gather(const float* sr, const float* si, float* dr, float* di, const int* idx, int cnt, long long per,
                          bool scatter, hipStream_t s);
+
+// tp_tprod after its argument checks (check_tprod), on a caller-given workspace
+int check_tprod(const float* A, const float* B, const float* C, int n1, int n2, int l, int n3, int prec);
+int run_tprod(const float* A, const float* B, float* C, int n1, int n2, int l, int n3, int prec, void* workspace,
+              size_t workspace_bytes, hipStream_t s);
 
 // ------------------------------------------------------------ tunables ----
 // current value of a TP_PARAM_* setting (tp_set_param), default if unset

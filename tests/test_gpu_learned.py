@@ -319,3 +319,48 @@ def test_learned_prox_warm_start(tp, orc):
             cols = bc[(len(seq) - 1) % 2].cpu().numpy()
             assert np.all(cols == 8)  # l = kpred + oversample, rounded to the call width 8
     assert launches[True] < launches[False]
+
+
+def test_rsvd_breakdown_falls_back(tp, orc):
+    """Every tube alternates in sign, so only the middle slice k = n3/2 is
+    nonzero in exact arithmetic; the DC slice (a sum of +x and -x) comes out
+    exactly zero.  There the sketch Y = Ybar Om is zero, its Gram matrix has
+    no positive pivot, and the CholeskyQR breakdown must send the slice to
+    the full SVD rather than pass a broken basis on.  (The other slices hold
+    rounding noise of the transform and may stay on the randomized path.)
+    The output stays finite and equal to the exact prox."""
+    rng = np.random.default_rng(41)
+    n1, n2, n3 = 90, 70, 6
+    U = rng.standard_normal((n1, n2))
+    Y = (U[:, :, None] * ((-1.0) ** np.arange(n3))[None, None, :]).astype(np.float32)
+    tau = 0.2 * orc.tsn(Y)
+    h = n3 // 2 + 1
+    fb = torch.zeros(h, dtype=torch.int32, device="cuda:0")
+    X = tp.tp_prox_tnn_learned(gpu(Y), tau, fixed_rank=6, max_rank=32, fallback=fb, accuracy=0.0).cpu().numpy()
+    ref = orc.prox_tnn(Y, np.float32(tau))
+    f = fb.cpu().numpy()
+    say(f"fallback {f.tolist()} err {rel_fro(X, ref):.2e}")
+    assert np.all(np.isfinite(X))
+    assert f[0] == 1                     # the exactly zero slice
+    assert rel_fro(X, ref) <= 1e-4
+
+
+@pytest.mark.parametrize("accuracy", [0.0, 2e-5])
+def test_rsvd_rank_deficient_narrower_than_sketch(tp, orc, accuracy):
+    """Slices of exact rank 3 with a sketch of 32 columns (kpred 20 + 10,
+    rounded up): the sketch's Gram matrix is singular.  Either the basis
+    passes the checks (its span then contains the whole range and the result
+    is exact) or the slice falls back; the output must be finite and equal
+    to the exact prox either way."""
+    rng = np.random.default_rng(43)
+    n1, n2, n3, r = 100, 40, 5, 3
+    Y = orc.tprod(rng.standard_normal((n1, r, n3)), rng.standard_normal((r, n2, n3))).astype(np.float32)
+    tau = 0.1 * orc.tsn(Y)
+    h = n3 // 2 + 1
+    fb = torch.zeros(h, dtype=torch.int32, device="cuda:0")
+    X = tp.tp_prox_tnn_learned(gpu(Y), tau, fixed_rank=20, max_rank=64, fallback=fb,
+                               accuracy=accuracy).cpu().numpy()
+    ref = orc.prox_tnn(Y, np.float32(tau))
+    say(f"fallback {fb.cpu().numpy().tolist()} err {rel_fro(X, ref):.2e}")
+    assert np.all(np.isfinite(X))
+    assert rel_fro(X, ref) <= 1e-4

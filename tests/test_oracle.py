@@ -408,3 +408,25 @@ def test_tubalrank_special_cases(orc):
     assert orc.tubalrank(A) == 1
     A[2, 2, :] = [1.0, -1.0, 1.0, -1.0]  # the Nyquist slice now has rank 2
     assert orc.tubalrank(A) == 2
+
+
+# ---------------------------------------------------------------------------
+# The library-primitive form of the exact prox (numpy FFT + LAPACK SVD per
+# slice), used for full-size checks, against the Jacobi oracle and against
+# the SVT of bcirc(Y) (no DFT at all: the prox of eq (19) is the matrix SVT
+# of the block circulant matrix, eq (18) and Theorem 2.3).
+@pytest.mark.parametrize("n1,n2,n3", [(9, 7, 5), (6, 11, 4), (8, 8, 1), (5, 5, 2)])
+def test_prox_lapack_matches_jacobi_and_bcirc(orc, n1, n2, n3):
+    rng = np.random.default_rng(n1 + 10 * n2 + 100 * n3)
+    Y = rng.standard_normal((n1, n2, n3))
+    tau = 0.3 * orc.tsn(Y)
+    X = orc.prox_tnn_lapack(Y, tau)
+    ref = orc.prox_tnn(Y, tau)
+    assert np.linalg.norm(X - ref) <= 1e-12 * np.linalg.norm(ref)
+    U, s, Vh = np.linalg.svd(orc.bcirc(Y))
+    Wb = (U[:, :len(s)] * np.maximum(s - tau, 0)) @ Vh[:len(s)]
+    # first block column of the circulant result = unfold(X)
+    assert np.linalg.norm(Wb[:, :n2] - orc.unfold(X)) <= 1e-12 * np.linalg.norm(ref)
+    k = n3 // 2
+    part = orc.prox_tnn_lapack(Y, tau, slices=[k])
+    assert np.allclose(part[k], np.fft.fft(ref, axis=2)[:, :, k], atol=1e-12 * np.linalg.norm(ref))

@@ -138,3 +138,115 @@ def test_mlp_gradient_central_differences(orc):
     y = orc.mlp_forward(p, X, d, h)
     e = y - t
     assert abs(loss - np.mean(np.where(e >= 0, 1.0, 4.0) * e * e)) < 1e-12 * max(1.0, loss)
+
+
+# ---------------------------------------------------------------------------
+# Power iterations of the randomized prox outside the exact regime: a
+# Gaussian tensor has a slowly decaying spectrum in every Fourier slice, so
+# with l well below the rank the result depends on the number of subspace
+# iterations q.  The oracle must agree with an independent numpy subspace
+# iteration started from the same sketch Om (Householder QR instead of
+# CholeskyQR2: the projector Q Q^* does not depend on how the basis is
+# orthonormalised), and the q = 0, 1, 2 results must differ from each other
+# and approach the exact prox as q grows.
+def numpy_rsvd_prox(orc, Y, tau, l, q, seed):
+    n1, n2, n3 = Y.shape
+    h = n3 // 2 + 1
+    F = np.fft.fft(Y, axis=2)
+    W = np.zeros_like(F)
+    for k in range(h):
+        real = k == 0 or (n3 % 2 == 0 and k == n3 // 2)
+        A = F[:, :, k].real.astype(complex) if real else F[:, :, k]
+        Om = orc.sketch_matrix(n2, l, k, real, seed)
+        Q = np.linalg.qr(A @ Om)[0]
+        for _ in range(q):
+            Z = np.linalg.qr(A.conj().T @ Q)[0]
+            Q = np.linalg.qr(A @ Z)[0]
+        U, s, Vh = np.linalg.svd(Q.conj().T @ A, full_matrices=False)
+        W[:, :, k] = Q @ (U * np.maximum(s - tau, 0.0)) @ Vh
+    for k in range(h, n3):
+        W[:, :, k] = W[:, :, n3 - k].conj()
+    return np.fft.ifft(W, axis=2).real
+
+
+@pytest.mark.parametrize("n1,n2,n3", [(60, 50, 5), (48, 64, 6)])
+def test_rsvd_prox_power_iterations_vs_numpy(orc, n1, n2, n3):
+    rng = np.random.default_rng(n1 * n2 + n3)
+    Y = rng.standard_normal((n1, n2, n3))
+    h = n3 // 2 + 1
+    tau = 0.45 * orc.tsn(Y)
+    l = 8                       # l < rank = min(n1, n2): not exact
+    kpred = np.full(h, l, dtype=np.int32)
+    exact = orc.prox_tnn(Y, tau)
+    res = {}
+    for q in (0, 1, 2):
+        # oversample 0: l = kpred, so the count check never sends a slice to the full SVD
+        X, fb, _ = orc.prox_tnn_rsvd(Y, tau, kpred, oversample=0, power=q, seed=21)
+        assert np.all(fb == 0)
+        ref = numpy_rsvd_prox(orc, Y, tau, l, q, seed=21)
+        assert np.linalg.norm(X - ref) <= 1e-10 * np.linalg.norm(ref), q
+        res[q] = X
+    # the iterations matter here (far above the agreement tolerance), and help
+    assert np.linalg.norm(res[0] - res[1]) > 1e-3 * np.linalg.norm(exact)
+    assert np.linalg.norm(res[1] - res[2]) > 1e-4 * np.linalg.norm(exact)
+    e = [np.linalg.norm(res[q] - exact) for q in (0, 1, 2)]
+    assert e[2] < e[1] < e[0]
+
+
+# ---------------------------------------------------------------------------
+# Slice features (the rank model's inputs, a definition of this build) on
+# inputs whose Fourier slices are known in closed form.
+def test_slice_features_identity_tensor(orc):
+    n, n3 = 7, 6
+    tau = 0.3
+    f = orc.slice_features(orc.teye(n, n3), tau)
+    h = n3 // 2 + 1
+    # every Fourier slice of the identity tensor is I_n: ||.||_F = sqrt(n), column norms 1
+    assert np.allclose(f[:, 0], np.log(tau))            # log(tau / (sqrt(n) / sqrt(n)))
+    assert np.allclose(f[:, 1], np.log(1.0 / tau))
+    assert np.all(f[:, 2:4] == 0) and np.all(f[:, 8:] == 0)
+    assert np.allclose(f[:, 4], np.arange(h) / (n3 // 2))
+    assert np.array_equal(f[:, 5], [1.0, 0, 0, 1.0])
+    assert np.allclose(f[:, 6], np.log(n) / 8) and np.allclose(f[:, 7], 0.0)
+
+
+def test_slice_features_rank_one_tensor(orc):
+    # A(i,j,t) = u_i v_j w_t with w_t = 1 + cos(2 pi t / n3): the DFT of the
+    # tube is w^_0 = n3, w^_1 = n3 / 2, w^_k = 0 for 2 <= k <= n3/2, so slice
+    # k is w^_k u v^T, ||.||_F = |w^_k| ||u|| ||v||, largest column norm
+    # |w^_k| ||u|| max|v_j|
+    n1, n2, n3 = 9, 5, 8
+    rng = np.random.default_rng(4)
+    u, v = rng.standard_normal(n1), rng.standard_normal(n2)
+    w = 1.0 + np.cos(2 * np.pi * np.arange(n3) / n3)
+    A = u[:, None, None] * v[None, :, None] * w[None, None, :]
+    tau, p = 0.7, min(n1, n2)
+    f = orc.slice_features(A, tau)
+    what = [n3, n3 / 2]
+    for k in range(2):
+        fro = what[k] * np.linalg.norm(u) * np.linalg.norm(v)
+        assert np.isclose(f[k, 0], np.log(tau * np.sqrt(p) / fro), rtol=1e-12)
+        assert np.isclose(f[k, 1], np.log(what[k] * np.linalg.norm(u) * np.abs(v).max() / tau), rtol=1e-12)
+    # (numerically) zero slices: tau / rms sigma and the column norm / tau at
+    # their clamped limits
+    assert np.all(f[2:, 0] == 30.0) and np.all(f[2:, 1] == -30.0)
+    Z = orc.slice_features(np.zeros((4, 3, 2)), tau)
+    assert np.all(Z[:, 0] == 30.0) and np.all(Z[:, 1] == -30.0)
+    assert np.allclose(f[:, 7], np.log(n1 / p))
+
+
+def test_slice_features_previous_call(orc):
+    n1, n2, n3 = 10, 12, 4
+    h = n3 // 2 + 1
+    Y = np.random.default_rng(5).standard_normal((n1, n2, n3))
+    tau, p = 0.8, 10
+    prev = np.array([3, 0, 7], dtype=np.int32)
+    ps = np.zeros((h, 64))
+    ps[0, :4] = [5.0, 3.0, 0.7, 0.5]    # 2 above tau, 3 above tau / 1.25 = 0.64, smallest kept <= tau
+    ps[1, :3] = [2.0, 1.5, 1.0]         # every kept value above tau
+    f = orc.slice_features(Y, tau, prev, ps)
+    assert np.allclose(f[:, 2], prev / p) and np.all(f[:, 3] == 1.0)
+    assert np.allclose(f[:, 8], [2 / p, 3 / p, 0.0])
+    assert np.allclose(f[:, 9], [3 / p, 3 / p, 0.0])
+    assert np.allclose(f[:2, 10], [np.log(5.0 / 0.8), np.log(2.0 / 0.8)]) and f[2, 10] == -30.0
+    assert np.array_equal(f[:, 11], [0.0, 1.0, 0.0])
