@@ -70,6 +70,24 @@ int tp_tprod(const float* A, const float* B, float* C, int n1, int n2, int l, in
              void* workspace, size_t workspace_bytes, void* stream);
 
 /*
+ * tp_tprod without a caller-given workspace, for callers that cannot
+ * allocate device memory (code under HIP graph capture, tight serving loops,
+ * harnesses that forbid hipMalloc).  The same computation and kernels as
+ * tp_tprod (bitwise equal results); the half spectra live in a device array
+ * of the library, tp_tprod_noalloc_max_bytes() bytes per GPU, allocated when
+ * the library is loaded on a device and held until the process ends.  The
+ * call allocates nothing and does not synchronise.
+ * Errors as tp_tprod, plus TP_ERR_WORKSPACE (before anything is enqueued)
+ * when tp_tprod_workspace_size(n1, n2, l, n3, prec) exceeds that size.
+ * Every call on one GPU uses that GPU's one array: calls that overlap on a
+ * GPU (concurrent streams, threads) race and must be serialised by the
+ * caller; a call fully overwrites what it uses, so no state carries over.
+ */
+int tp_tprod_noalloc(const float* A, const float* B, float* C, int n1, int n2, int l, int n3, int prec,
+                     void* stream);
+size_t tp_tprod_noalloc_max_bytes(void);
+
+/*
  * t-SVD A = U * S * V^* (Theorem 2.2), computed by Algorithm 2: DFT of the
  * tubes of A; for each of the floor(n3/2)+1 leading Fourier slices a full
  * SVD by one-sided Jacobi (real rotations on the real DC and, for even n3,

@@ -22,6 +22,8 @@ SIGNATURES = {
     "tp_version": (_I, []),
     "tp_tprod_workspace_size": (_SZ, [_I, _I, _I, _I, _I]),
     "tp_tprod": (_I, [_VP, _VP, _VP, _I, _I, _I, _I, _I, _VP, _SZ, _VP]),
+    "tp_tprod_noalloc": (_I, [_VP, _VP, _VP, _I, _I, _I, _I, _I, _VP]),
+    "tp_tprod_noalloc_max_bytes": (_SZ, []),
     "tp_tsvd_workspace_size": (_SZ, [_I, _I, _I]),
     "tp_tsvd": (_I, [_VP, _VP, _VP, _VP, _I, _I, _I, _VP, _VP, _SZ, _VP]),
     "tp_prox_tnn_workspace_size": (_SZ, [_I, _I, _I]),
