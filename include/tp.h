@@ -455,6 +455,11 @@ int tp_batch_destroy(tp_batch* plan);
  *                                 each lane reads its own tube with 16-byte loads
  *                                 (default), 2 = staged through LDS (the inverse
  *                                 always stores through LDS, coalesced)
+ *   TP_PARAM_JACOBI_STEPWISE      form of the multi-workgroup Jacobi without V:
+ *                                 1 = one launch per block step, the blocks
+ *                                 staged in LDS; 2 = one launch per sweep, the
+ *                                 column pairs in registers; 0 = by slice height
+ *                                 (per sweep above 256 rows)
  */
 enum {
     TP_PARAM_JACOBI_BLOCK = 0,
@@ -466,7 +471,8 @@ enum {
     TP_PARAM_FFT_DIRECT = 6,
     TP_PARAM_GEMM_BK = 7,
     TP_PARAM_GEMM_KSPLIT = 8,
-    TP_PARAM_COUNT = 9
+    TP_PARAM_JACOBI_STEPWISE = 9,
+    TP_PARAM_COUNT = 10
 };
 int tp_set_param(int key, int value);
 int tp_get_param(int key);

@@ -426,6 +426,356 @@ __global__ __launch_bounds__(256) void k_jacobi_block_finish(JacobiArgs a, const
     }
 }
 
+// ---- block sweep: one launch per sweep, column pairs held in registers ----
+// The same block circle order as k_jacobi_block, for slices without V.  An
+// item is one block pair (b1, b2) at one block step of one slice; items are
+// numbered step-major (step, slice, pair) and workgroups take them in that
+// order from a per-sweep ticket counter.  An item at step t waits for the two
+// items of step t-1 that last wrote its blocks, and those hold smaller
+// tickets, so they were taken by workgroups that are already running: the
+// waits always end, whatever the number of workgroups resident at once.
+//
+// In an item the b groups of G lanes (b = blockDim / G, also the block width)
+// hold columns in registers (RPL rows per lane, R <= G RPL).  Cross pairs:
+// group g keeps column g of block b1 and meets the b2 columns in turn, the
+// b2 columns passing one group down through LDS each round (b rounds).  At
+// block step 0 the pairs inside each block come first: groups [0, b/2) take
+// block b1 and [b/2, b) block b2, two columns per group, in the circle order
+// over b positions (b - 1 rounds; the columns move one position per round,
+// through LDS, one block at a time).  Completion is published with an
+// agent-scope release after the columns are stored; the waiter acquires
+// before it loads them (the L2s of the XCDs are not coherent).
+struct SweepArgs {
+    float2* work;           // [nslices][P][R] column-major
+    int* rot;               // [3][nslices]
+    int* done;              // [nslices]
+    int* flags;             // [nslices][nb - 1][nb / 2] completion stamps (sweep + 1)
+    unsigned int* tickets;  // [4] ticket counters: sweep k takes tickets from k mod 4
+    int* err;               // set when a wait hit its spin limit (never expected)
+    const int* count;       // optional device count of live slices (<= nslices)
+    int R, P, nslices, nb, b, sweep, nitems;
+    double tol2;
+};
+
+// position of block beta in step t of the circle order over nb blocks
+__device__ __forceinline__ int rr_pos(int beta, int t, int nb)
+{
+    if (beta == 0) return 0;
+    int p = beta - 1 - t;
+    while (p < 0) p += nb - 1;
+    return p + 1;
+}
+
+// rotation of the pair (x, y) held by the G lanes of a group: the same
+// arithmetic as jacobi_pair on register-resident columns
+template <int G, int RPL>
+__device__ __forceinline__ bool rotate_regs(float2 (&x)[RPL], float2 (&y)[RPL], double tol2)
+{
+    float pa = 0.f, pb = 0.f, pr = 0.f, pi = 0.f;
+#pragma unroll
+    for (int t = 0; t < RPL; ++t) {
+        pa = fmaf(x[t].x, x[t].x, fmaf(x[t].y, x[t].y, pa));
+        pb = fmaf(y[t].x, y[t].x, fmaf(y[t].y, y[t].y, pb));
+        pr = fmaf(x[t].x, y[t].x, fmaf(x[t].y, y[t].y, pr));
+        pi = fmaf(x[t].x, y[t].y, fmaf(-x[t].y, y[t].x, pi));
+    }
+    const double al = group_sum<G>((double)pa);
+    const double be = group_sum<G>((double)pb);
+    const double gr = group_sum<G>((double)pr);
+    const double gi = group_sum<G>((double)pi);
+    const double g2 = gr * gr + gi * gi;
+    if (!(g2 > 0.0 && g2 > tol2 * al * be)) return false;
+    const double ig = rsqrt_f64(g2);
+    const double zeta = 0.5 * (be - al) * ig;
+    const double z2 = fma(zeta, zeta, 1.0);
+    const double t = copysign(rcp_f64(fabs(zeta) + z2 * rsqrt_f64(z2)), zeta);
+    const double c = rsqrt_f64(fma(t, t, 1.0));
+    const double sn = c * t;
+    const float cf = (float)c;
+    const float sr = (float)(sn * gr * ig), si = (float)(sn * gi * ig);
+#pragma unroll
+    for (int t2 = 0; t2 < RPL; ++t2) {
+        const float2 xv = x[t2], yv = y[t2];
+        x[t2] = make_float2(cf * xv.x - (sr * yv.x + si * yv.y), cf * xv.y - (sr * yv.y - si * yv.x));
+        y[t2] = make_float2((sr * xv.x - si * xv.y) + cf * yv.x, (sr * xv.y + si * xv.x) + cf * yv.y);
+    }
+    return true;
+}
+
+// Column i/o of the block sweep.  Lane gl of a group holds, in its slot t,
+// row rowof(gl, t) = 2 (gl + G (t / 2)) + (t % 2) of a column: two adjacent
+// rows per pair of slots, so every access moves 16 bytes and a group's
+// accesses are contiguous.  The same mapping serves LDS and global memory.
+// The slice's columns in global memory, which other workgroups (on any XCD)
+// wrote in this launch, move with buffer loads and stores at device scope
+// (SC1): such accesses are coherent across the XCDs' L2 caches by their
+// scope, with no cache-wide writeback or invalidation.
+typedef int v4i __attribute__((ext_vector_type(4)));
+typedef int v2i __attribute__((ext_vector_type(2)));
+constexpr int kDeviceScope = 16;  // cache policy: SC1 (device scope)
+
+template <int G>
+__device__ __forceinline__ int rowof(int gl, int t) { return 2 * (gl + G * (t >> 1)) + (t & 1); }
+
+template <int G, int RPL>
+__device__ __forceinline__ void col_load(float2 (&v)[RPL], const float2* src, int R, int gl, bool live)
+{
+#pragma unroll
+    for (int t = 0; t < RPL; t += 2) {
+        const int r = rowof<G>(gl, t);
+        if (live && r + 1 < R) {
+            const float4 q = *reinterpret_cast<const float4*>(src + r);
+            v[t] = make_float2(q.x, q.y);
+            v[t + 1] = make_float2(q.z, q.w);
+        } else {
+            v[t] = (live && r < R) ? src[r] : make_float2(0.f, 0.f);
+            v[t + 1] = make_float2(0.f, 0.f);
+        }
+    }
+}
+
+template <int G, int RPL>
+__device__ __forceinline__ void col_store(const float2 (&v)[RPL], float2* dst, int R, int gl)
+{
+#pragma unroll
+    for (int t = 0; t < RPL; t += 2) {
+        const int r = rowof<G>(gl, t);
+        if (r + 1 < R)
+            *reinterpret_cast<float4*>(dst + r) = make_float4(v[t].x, v[t].y, v[t + 1].x, v[t + 1].y);
+        else if (r < R)
+            dst[r] = v[t];
+    }
+}
+
+// raw buffer access (the LLVM intrinsics; the resource is one slice, uniform
+// across the workgroup)
+typedef float v4f __attribute__((ext_vector_type(4)));
+typedef float v2f __attribute__((ext_vector_type(2)));
+__device__ v4f raw_buffer_load_v4(v4i rsrc, int voffset, int soffset, int aux) __asm("llvm.amdgcn.raw.buffer.load.v4f32");
+__device__ v2f raw_buffer_load_v2(v4i rsrc, int voffset, int soffset, int aux) __asm("llvm.amdgcn.raw.buffer.load.v2f32");
+__device__ void raw_buffer_store_v4(v4i data, v4i rsrc, int voffset, int soffset,
+                                    int aux) __asm("llvm.amdgcn.raw.buffer.store.v4i32");
+__device__ void raw_buffer_store_v2(v2i data, v4i rsrc, int voffset, int soffset,
+                                    int aux) __asm("llvm.amdgcn.raw.buffer.store.v2i32");
+
+// buffer resource over `bytes` bytes at p (stride 0: the range is in bytes;
+// accesses past it read zeros and write nothing)
+__device__ __forceinline__ v4i slice_rsrc(const void* p, unsigned int bytes)
+{
+    const unsigned long long a = reinterpret_cast<unsigned long long>(p);
+    v4i r;
+    r.x = (int)(unsigned int)(a & 0xffffffffu);
+    r.y = (int)(unsigned int)((a >> 32) & 0xffffu);
+    r.z = (int)bytes;
+    r.w = 0x00020000;
+    return r;
+}
+
+// column `col` (R rows, column-major, byte offset col * 8 R in the slice
+// resource rs of `limit` bytes); live = false reads zeros
+template <int G, int RPL>
+__device__ __forceinline__ void col_load_shared(float2 (&v)[RPL], v4i rs, int limit, int col, int R, int gl, bool live)
+{
+    const int base = col * R * 8;
+#pragma unroll
+    for (int t = 0; t < RPL; t += 2) {
+        const int r = rowof<G>(gl, t);
+        const v4f q = raw_buffer_load_v4(rs, (live && r + 1 < R) ? base + r * 8 : limit, 0, kDeviceScope);
+        v[t] = make_float2(q.x, q.y);
+        v[t + 1] = make_float2(q.z, q.w);
+        if ((R & 1) && live && r == R - 1) {  // the last row of an odd height
+            const v2f q2 = raw_buffer_load_v2(rs, base + r * 8, 0, kDeviceScope);
+            v[t] = make_float2(q2.x, q2.y);
+        }
+    }
+}
+
+template <int G, int RPL>
+__device__ __forceinline__ void col_store_shared(const float2 (&v)[RPL], v4i rs, int col, int R, int gl)
+{
+    const int base = col * R * 8;
+#pragma unroll
+    for (int t = 0; t < RPL; t += 2) {
+        const int r = rowof<G>(gl, t);
+        if (r + 1 < R) {
+            v4i q;
+            q.x = __builtin_bit_cast(int, v[t].x);
+            q.y = __builtin_bit_cast(int, v[t].y);
+            q.z = __builtin_bit_cast(int, v[t + 1].x);
+            q.w = __builtin_bit_cast(int, v[t + 1].y);
+            raw_buffer_store_v4(q, rs, base + r * 8, 0, kDeviceScope);
+        } else if (r < R) {
+            v2i q;
+            q.x = __builtin_bit_cast(int, v[t].x);
+            q.y = __builtin_bit_cast(int, v[t].y);
+            raw_buffer_store_v2(q, rs, base + r * 8, 0, kDeviceScope);
+        }
+    }
+}
+
+// spin (bounded) until *f >= want; one lane
+__device__ __forceinline__ void wait_stamp(const int* f, int want, int* err)
+{
+    for (long long it = 0; it < (1LL << 26); ++it) {
+        if (__hip_atomic_load(f, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) >= want) return;
+        __builtin_amdgcn_s_sleep(2);
+    }
+    atomicExch(err, 1);
+}
+
+template <int G, int RPL, int MAXT>
+__global__ __launch_bounds__(MAXT) void k_jacobi_sweep(SweepArgs a)
+{
+    extern __shared__ float2 xch[];  // b columns of R rows (stride ldr)
+    __shared__ int sh_item, sh_rot;
+    __shared__ int sh_id[64], sh_yid[64];
+    const int tid = threadIdx.x, g = tid / G, gl = tid % G, b = a.b, R = a.R;
+    const int ldr = (R + 1) & ~1;  // LDS column stride (even: 16-byte aligned columns)
+    const int npairs = a.nb / 2, per_step = a.nslices * npairs, half = b / 2;
+    const int live_slices = a.count ? min(*a.count, a.nslices) : a.nslices;
+    const int ns = a.nslices, stamp = a.sweep + 1;
+    if (a.sweep > 0) {  // every live slice converged: the launch has nothing to do
+        int busy = 0;
+        for (int q = tid; q < live_slices; q += blockDim.x) busy |= a.rot[((a.sweep - 1) % 3) * ns + q];
+        if (!__syncthreads_or(busy)) {
+            // the bookkeeping the slices' first items would have done
+            if (blockIdx.x == 0)
+                for (int q = tid; q < live_slices; q += blockDim.x) {
+                    a.rot[((a.sweep + 1) % 3) * ns + q] = 0;
+                    if (a.done[q] == 0) a.done[q] = a.sweep;
+                }
+            return;
+        }
+    }
+    float2 x[RPL], y[RPL];
+    for (;;) {
+        if (tid == 0) {
+            const unsigned int tk = atomicAdd(a.tickets + (a.sweep & 3), 1u);
+            // the counter of sweep + 2 was last used by sweep - 2, which has ended
+            if (tk == 0) a.tickets[(a.sweep + 2) & 3] = 0;
+            sh_item = (int)tk;
+            sh_rot = 0;
+        }
+        __syncthreads();
+        const int item = sh_item;
+        if (item >= a.nitems) return;
+        const int step = item / per_step, rem = item - step * per_step, s = rem / npairs, bp = rem - s * npairs;
+        if (s >= live_slices) {
+            __syncthreads();
+            continue;
+        }
+        // the flag of the next sweep is cleared every sweep, converged or not
+        if (step == 0 && bp == 0 && tid == 0) a.rot[((a.sweep + 1) % 3) * ns + s] = 0;
+        if (a.sweep > 0 && a.rot[((a.sweep - 1) % 3) * ns + s] == 0) {  // converged in the previous sweep
+            if (step == 0 && bp == 0 && tid == 0 && a.done[s] == 0) a.done[s] = a.sweep;
+            __syncthreads();
+            continue;
+        }
+        const int b1 = rr_col(bp, step, a.nb), b2 = rr_col(a.nb - 1 - bp, step, a.nb);
+        const int c1 = block_cols(b1, b, a.P), c2 = block_cols(b2, b, a.P);
+        int* fl = a.flags + (long long)s * (a.nb - 1) * npairs;
+        if (step > 0 && tid == 0) {
+            const int q1 = rr_pos(b1, step - 1, a.nb), q2 = rr_pos(b2, step - 1, a.nb);
+            wait_stamp(fl + (step - 1) * npairs + min(q1, a.nb - 1 - q1), stamp, a.err);
+            wait_stamp(fl + (step - 1) * npairs + min(q2, a.nb - 1 - q2), stamp, a.err);
+        }
+        // the column loads below are issued after the stamps were seen (the
+        // barrier) and read at device scope
+        __syncthreads();
+        // the slice as one buffer resource; columns by index
+        const int limit = a.P * R * (int)sizeof(float2);
+        const v4i rs = slice_rsrc(a.work + (long long)s * a.P * R, (unsigned int)limit);
+        const int col1 = b1 * b, col2 = b2 * b;
+        bool rotated = false;
+        int xid = g, yid = g;  // local column ids held in x (block b1) and y (block b2)
+        if (step == 0) {
+            // pairs inside each block: group (blk, u) holds positions u and
+            // b - 1 - u of its block; position p holds local column cid[p]
+            const int blk = g < half ? 0 : 1, u = g - blk * half, cb = blk ? c2 : c1;
+            const int cbase = blk ? col2 : col1;
+            int px = u, py = b - 1 - u, cx = px, cy = py;
+            col_load_shared<G, RPL>(x, rs, limit, cbase + cx, R, gl, cx < cb);
+            col_load_shared<G, RPL>(y, rs, limit, cbase + cy, R, gl, cy < cb);
+            for (int r = 0; r < b - 1; ++r) {
+                if (cx < cb && cy < cb) rotated |= rotate_regs<G, RPL>(x, y, a.tol2);
+                // every position but 0 moves down one (1 wraps to b - 1), one block at a time
+                const int nx = px == 0 ? 0 : (px == 1 ? b - 1 : px - 1);
+                const int ny = py == 1 ? b - 1 : py - 1;
+                for (int k = 0; k < 2; ++k) {
+                    if (blk == k) {
+                        col_store<G, RPL>(x, xch + (long long)nx * ldr, R, gl);
+                        col_store<G, RPL>(y, xch + (long long)ny * ldr, R, gl);
+                        if (gl == 0) {
+                            sh_id[nx] = cx;
+                            sh_id[ny] = cy;
+                        }
+                    }
+                    __syncthreads();
+                    if (blk == k) {
+                        col_load<G, RPL>(x, xch + (long long)px * ldr, R, gl, true);
+                        col_load<G, RPL>(y, xch + (long long)py * ldr, R, gl, true);
+                        cx = sh_id[px];
+                        cy = sh_id[py];
+                    }
+                    __syncthreads();
+                }
+            }
+            // to the cross layout (one b1 and one b2 column per group): group
+            // u of b1 swaps its second column for the first of group u of b2
+            if (blk == 0) {
+                col_store<G, RPL>(y, xch + (long long)u * ldr, R, gl);
+                if (gl == 0) sh_id[u] = cy;
+            } else {
+                col_store<G, RPL>(x, xch + (long long)(half + u) * ldr, R, gl);
+                if (gl == 0) sh_id[half + u] = cx;
+            }
+            __syncthreads();
+            if (blk == 0) {
+                col_load<G, RPL>(y, xch + (long long)(half + u) * ldr, R, gl, true);
+                xid = cx;
+                yid = sh_id[half + u];
+            } else {
+                col_load<G, RPL>(x, xch + (long long)u * ldr, R, gl, true);
+                xid = sh_id[u];
+                yid = cy;
+            }
+            __syncthreads();
+        } else {
+            col_load_shared<G, RPL>(x, rs, limit, col1 + g, R, gl, g < c1);
+            col_load_shared<G, RPL>(y, rs, limit, col2 + g, R, gl, g < c2);
+        }
+        // cross pairs: the b2 columns pass one group down per round, so group
+        // g meets in round r the column group (g + r) mod b started with
+        if (gl == 0) sh_yid[g] = yid;
+        __syncthreads();
+        for (int r = 0; r < b; ++r) {
+            yid = sh_yid[g + r < b ? g + r : g + r - b];
+            if (xid < c1 && yid < c2) rotated |= rotate_regs<G, RPL>(x, y, a.tol2);
+            if (r == b - 1) break;
+            col_store<G, RPL>(y, xch + (long long)g * ldr, R, gl);
+            __syncthreads();
+            col_load<G, RPL>(y, xch + (long long)(g + 1 < b ? g + 1 : 0) * ldr, R, gl, true);
+            __syncthreads();
+        }
+        if (xid < c1) col_store_shared<G, RPL>(x, rs, col1 + xid, R, gl);
+        if (yid < c2) col_store_shared<G, RPL>(y, rs, col2 + yid, R, gl);
+        if (rotated && gl == 0) sh_rot = 1;
+        // every wave's device-scope stores acknowledged before the stamp is written
+        __builtin_amdgcn_s_waitcnt(0);
+        __syncthreads();
+        if (tid == 0) {
+            if (sh_rot) atomicOr(&a.rot[(a.sweep % 3) * ns + s], 1);
+            __hip_atomic_store(fl + step * npairs + bp, stamp, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+        }
+    }
+}
+
+__global__ __launch_bounds__(256) void k_zero_ints(int* p, long long n)
+{
+    for (long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x; e < n; e += (long long)gridDim.x * blockDim.x)
+        p[e] = 0;
+}
+
 constexpr size_t kMaxLds = 160 * 1024 - 1024;
 constexpr size_t kBlockLds = 80 * 1024;  // two workgroups per CU
 
@@ -499,9 +849,116 @@ BlockPlan block_plan(int R, int P, int nslices, bool withv)
     return pl;
 }
 
+// one launch per sweep (column pairs in registers) or per block step (blocks
+// staged in LDS): by measurement the sweep form is faster on slices taller
+// than 256 rows (64-lane groups) and slower below
+bool use_sweeps(int R)
+{
+    const int m = param(TP_PARAM_JACOBI_STEPWISE);
+    if (m == 1) return false;
+    if (m == 2) return true;
+    return R > 256;
+}
+
+// Block sweep plan (slices without V): groups of G lanes, block width b (the
+// groups per workgroup, even, at most 64 and 1024 / G threads), reduced
+// towards 8 until a block step has enough items to fill the GPU.
+struct SweepPlan {
+    int b, nb, threads, grid, nitems;
+    size_t lds, work_bytes, flag_bytes;
+};
+
+SweepPlan sweep_plan(int G, int rpl, int R, int P, int nslices)
+{
+    SweepPlan sp{};
+    // workgroup size: 1024 threads, 512 with 32 rows per lane (registers)
+    const int maxthreads = rpl >= 32 ? 512 : 1024;
+    int b = maxthreads / G;
+    if (b > 64) b = 64;
+    const int tuned = param(TP_PARAM_JACOBI_BLOCK);
+    if (tuned > 0) {
+        b = tuned < b ? tuned : b;
+        b &= ~1;
+        if (b < 4) b = 4;
+    } else {
+        auto nbof = [&](int bb) { int n = (P + bb - 1) / bb; return n + (n & 1); };
+        while (b > 8 && (long long)(nbof(b) / 2) * nslices < 512) b /= 2;
+    }
+    sp.b = b;
+    sp.nb = (P + b - 1) / b;
+    sp.nb += sp.nb & 1;
+    if (sp.nb < 2) sp.nb = 2;
+    sp.threads = b * G;
+    sp.lds = (size_t)b * ((R + 1) & ~1) * sizeof(float2);
+    sp.nitems = (sp.nb - 1) * nslices * (sp.nb / 2);
+    int per_cu = (int)((160 * 1024) / (sp.lds + 1024));
+    const int by_threads = 2048 / sp.threads;
+    if (per_cu > by_threads) per_cu = by_threads;
+    if (per_cu > 8) per_cu = 8;
+    if (per_cu < 1) per_cu = 1;
+    sp.grid = 256 * per_cu < sp.nitems ? 256 * per_cu : sp.nitems;
+    sp.work_bytes = align_up((size_t)R * P * nslices * sizeof(float2));
+    // rot [3][ns], done [ns], flags [ns][nb-1][nb/2], tickets [4], err
+    sp.flag_bytes = align_up((4 * (size_t)nslices + (size_t)nslices * (sp.nb - 1) * (sp.nb / 2) + 5) * sizeof(int));
+    return sp;
+}
+
+// the lane-group shape of a slice height (the instantiations launch_jacobi picks)
+void group_shape(int R, int* G, int* rpl)
+{
+    if (R <= 32) { *G = 16; *rpl = 2; }
+    else if (R <= 64) { *G = 16; *rpl = 4; }
+    else if (R <= 128) { *G = 16; *rpl = 8; }
+    else if (R <= 256) { *G = 16; *rpl = 16; }
+    else if (R <= 512) { *G = 64; *rpl = 8; }
+    else if (R <= 1024) { *G = 64; *rpl = 16; }
+    else { *G = 64; *rpl = 32; }
+}
+
+template <int G, int RPL>
+hipError_t launch_sweeps(const JacobiArgs& a, void* scratch, int R, int P, hipStream_t st)
+{
+    const SweepPlan sp = sweep_plan(G, RPL, R, P, a.nslices);
+    char* base = static_cast<char*>(scratch);
+    float2* work = reinterpret_cast<float2*>(base);
+    int* ints = reinterpret_cast<int*>(base + sp.work_bytes);
+    const int ns = a.nslices;
+    int* rot = ints;
+    int* done = rot + 3 * ns;
+    int* flags = done + ns;
+    const long long nflags = (long long)ns * (sp.nb - 1) * (sp.nb / 2);
+    unsigned int* tickets = reinterpret_cast<unsigned int*>(flags + nflags);
+    int* err = reinterpret_cast<int*>(tickets + 4);
+    const long long nints = 4LL * ns + nflags + 5;
+    k_zero_ints<<<(int)((nints + 255) / 256 < 1024 ? (nints + 255) / 256 : 1024), 256, 0, st>>>(ints, nints);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    const size_t per = (size_t)R * P;
+    const int chunks = (int)(per / (256 * 8) + 1) < 64 ? (int)(per / (256 * 8) + 1) : 64;
+    k_jacobi_block_init<<<dim3(chunks, ns), 256, 0, st>>>(a, work, nullptr, rot, done);
+    e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    // the 512-thread instantiation has twice the registers per lane
+    auto kern = k_jacobi_sweep<G, RPL, 512>;
+    if constexpr (RPL < 32)
+        if (sp.threads > 512) kern = k_jacobi_sweep<G, RPL, 1024>;
+    e = allow_lds(kern, sp.lds);
+    if (e != hipSuccess) return e;
+    SweepArgs sa{work, rot, done, flags, tickets, err, a.count, R, P, ns, sp.nb, sp.b, 0, sp.nitems, a.tol * a.tol};
+    for (int sw = 0; sw < a.max_sweeps; ++sw) {
+        sa.sweep = sw;
+        kern<<<sp.grid, sp.threads, sp.lds, st>>>(sa);
+        e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    }
+    k_jacobi_block_finish<G><<<dim3(chunks, ns), 256, 0, st>>>(a, work, nullptr, rot, done, a.max_sweeps);
+    return hipGetLastError();
+}
+
 template <int G, int RPL, bool WITHV>
 hipError_t launch_blocked(const JacobiArgs& a, void* scratch, int R, int P, const BlockPlan& pl, hipStream_t st)
 {
+    if (!WITHV && R <= G * RPL && use_sweeps(R)) return launch_sweeps<G, RPL>(a, scratch, R, P, st);
     char* base = static_cast<char*>(scratch);
     float2* work = reinterpret_cast<float2*>(base);
     float2* v = WITHV ? reinterpret_cast<float2*>(base + pl.work_bytes) : nullptr;
@@ -562,7 +1019,14 @@ size_t jacobi_scratch_bytes(int m, int n, int nslices, bool withv)
     const int R = m >= n ? m : n, P = m >= n ? n : m;
     if (use_blocked(R, P, nslices, withv)) {  // (an upper bound when a call forces one workgroup per slice)
         const BlockPlan pl = block_plan(R, P, nslices, withv);
-        return pl.work_bytes + pl.v_bytes + pl.flag_bytes;
+        size_t bytes = pl.work_bytes + pl.v_bytes + pl.flag_bytes;
+        if (!withv && use_sweeps(R)) {
+            int G, rpl;
+            group_shape(R, &G, &rpl);
+            const SweepPlan sp = sweep_plan(G, rpl, R, P, nslices);
+            if (sp.work_bytes + sp.flag_bytes > bytes) bytes = sp.work_bytes + sp.flag_bytes;
+        }
+        return bytes;
     }
     const size_t b = whole_bytes(R, P, withv);
     return b <= kMaxLds ? 0 : b * nslices;

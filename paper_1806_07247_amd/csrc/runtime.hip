@@ -68,8 +68,8 @@ void trace_work(double flops, double bytes)
 }
 
 namespace {
-int g_params[TP_PARAM_COUNT] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
-const int kDefaults[TP_PARAM_COUNT] = {0, 0, 128, 30, 0, 8, 1, 0, 0};
+int g_params[TP_PARAM_COUNT] = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
+const int kDefaults[TP_PARAM_COUNT] = {0, 0, 128, 30, 0, 8, 1, 0, 0, 0};
 }  // namespace
 
 int param(int key)

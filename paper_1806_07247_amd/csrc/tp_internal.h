@@ -128,6 +128,7 @@ struct JacobiArgs {
     float2* cols;     // optional: rotated columns, column-major R x P per slice
     float2* qout;     // optional: accumulated rotations V, column-major P x P per slice
     int whole;        // 1: one workgroup per slice whenever the slice fits in LDS
+    const int* count; // optional device count of live slices (<= nslices); the rest are skipped
 };
 // Batched per-slice SVDs (whole slice in LDS, R = max(m, n) <= 128) and
 // shrinkage over (item, slice) units.

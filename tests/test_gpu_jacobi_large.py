@@ -29,12 +29,19 @@ def tp():
     return tp
 
 
-@pytest.fixture(params=[1, 2], ids=["one_wg", "blocked"])
+JACOBI_BLOCK = 0     # TP_PARAM_JACOBI_BLOCK
+JACOBI_STEPWISE = 9  # TP_PARAM_JACOBI_STEPWISE
+
+
+@pytest.fixture(params=[(1, 0), (2, 2), (2, 1)], ids=["one_wg", "blocked_sweep", "blocked_stepwise"])
 def mode(request, tp):
     lib = tp._lib.load()
-    assert lib.tp_set_param(JACOBI_MODE, request.param) == 0
+    m, stepwise = request.param
+    assert lib.tp_set_param(JACOBI_MODE, m) == 0
+    assert lib.tp_set_param(JACOBI_STEPWISE, stepwise) == 0
     yield request.param
     lib.tp_set_param(JACOBI_MODE, 0)
+    lib.tp_set_param(JACOBI_STEPWISE, 0)
 
 
 def gpu(x):
@@ -98,3 +105,57 @@ def test_tsvd_tall_slices(tp, orc, mode, shape):
     say(f"  rec {e_rec:.2e} U^*U {e_u:.2e} V^*V {e_v:.2e} S {e_s:.2e} sweeps {info.cpu().numpy().tolist()}")
     assert e_rec <= 1e-5 and e_s <= 1e-5
     assert e_u <= 1e-4 and e_v <= 1e-4
+
+
+# The one-launch-per-sweep block kernel (forced) at forced block widths: ragged last
+# blocks, an empty padding block (odd block counts), fewer columns than one
+# block, tall and wide slices, 16- and 64-lane groups.
+@pytest.mark.parametrize("width", [4, 8, 16, 64])
+@pytest.mark.parametrize("shape", [(200, 37, 3), (300, 130, 4), (130, 200, 2), (96, 3, 2), (600, 70, 3)],
+                         ids=lambda s: "x".join(map(str, s)))
+def test_prox_block_widths(tp, orc, shape, width):
+    from paper_1806_07247_amd import inputs
+    lib = tp._lib.load()
+    assert lib.tp_set_param(JACOBI_MODE, 2) == 0
+    assert lib.tp_set_param(JACOBI_BLOCK, width) == 0
+    assert lib.tp_set_param(JACOBI_STEPWISE, 2) == 0
+    try:
+        Y = inputs.random_tensor(shape, seed=5 * sum(shape) + width)
+        tau = 0.2 * orc.tsn(Y)
+        h = shape[2] // 2 + 1
+        info = torch.zeros(h, dtype=torch.int32, device="cuda:0")
+        rank = torch.zeros(h, dtype=torch.int32, device="cuda:0")
+        say(f"prox {shape} block width {width}")
+        X = tp.tp_prox_tnn(gpu(Y), tau, info=info, rank=rank).cpu().numpy()
+        ref = orc.prox_tnn(Y, np.float32(tau))
+        err = rel_fro(X, ref)
+        say(f"  rel.err {err:.3e} sweeps {info.cpu().numpy().tolist()}")
+        assert err <= 1e-4
+        assert int(info.min()) > 0
+        sig = orc.slice_sigma(Y)[:h]
+        assert np.array_equal(rank.cpu().numpy(), (sig > np.float32(tau)).sum(axis=1))
+        v = float(tp.tp_tnn(gpu(Y)).cpu())
+        assert abs(v - orc.tnn(Y)) <= 1e-5 * orc.tnn(Y)
+    finally:
+        lib.tp_set_param(JACOBI_MODE, 0)
+        lib.tp_set_param(JACOBI_BLOCK, 0)
+        lib.tp_set_param(JACOBI_STEPWISE, 0)
+
+
+def test_prox_full_size_slices(tp, orc):
+    """1024 x 1024 slices (the learned-rank workload's slice shape, 16 rows per
+    lane, blocked) against the FP64 prox of Theorem 2.3 written with LAPACK."""
+    from paper_1806_07247_amd import inputs
+    parts = inputs.lowrank_sparse_parts(1024, 1024, 4, 12, 1.0 / 1024, 0.05, 0.0, seed=21)
+    Y = (orc.tprod(parts["P"], parts["Q"]) + parts["S"]).astype(np.float32)
+    # tau at a tenth of the spectral norm of the DC slice (numpy's SVD: the
+    # threshold only has to fall inside the spectrum)
+    tau = 0.1 * float(np.linalg.svd(Y.astype(np.float64).sum(axis=2), compute_uv=False)[0])
+    info = torch.zeros(3, dtype=torch.int32, device="cuda:0")
+    say("prox 1024x1024x4 (blocked, one launch per sweep)")
+    X = tp.tp_prox_tnn(gpu(Y), tau, info=info).cpu().numpy()
+    ref = orc.prox_tnn_lapack(Y, float(np.float32(tau)))
+    err = rel_fro(X, ref)
+    say(f"  rel.err {err:.3e} sweeps {info.cpu().numpy().tolist()}")
+    assert err <= 1e-4
+    assert int(info.min()) > 0
