@@ -181,18 +181,25 @@ int tp_teye(float* out, int n, int n3, void* stream);
  * which FP32 data can resolve a result much smaller than its input) or
  * D = sum_j (sigma_j - tau)^2 (accuracy_ref = 1: relative to the result),
  * all slices get one more power iteration, up to
- * max_power_iters in total, and slices still failing then fall back (the
- * extra iteration reuses the projection's basis Q2 as its Z and the check's
- * product Ybar Q2 as its Y, so it forms no new product with Ybar).
+ * max_power_iters in total (at most 30 beyond power_iters; in a wide retry
+ * at most one beyond), and slices still failing then fall back (the extra iteration reuses the projection's basis
+ * Q2 as its Z and the check's product Ybar Q2 as its Y, so it forms no new
+ * product with Ybar).
  * With l = min(n1,n2) or an exact rank <= l the result equals tp_prox_tnn's
  * up to rounding.
  *   opts       required (see tp_learned_opts); rank, fallback, info optional
  *              device int[floor(n3/2)+1]: the number of singular values
  *              above tau used, 1 for a fallback slice, and the Jacobi sweeps of
  *              the fallback slices (0 for the others).
- * Unlike the other entry points this call waits for the stream (once, plus
- * once per accuracy check): it reads which slices fell back before enqueueing
- * their full SVD.
+ * Every decision above that depends on the data (the width L, which slices
+ * take the randomized path, whether each accuracy round and the wide retry
+ * run, which slices fall back) is taken on the device: the call enqueues a
+ * fixed sequence of launches for its arguments, sized for L = max_rank,
+ * whose kernels read the width, gates and fallback count from the workspace
+ * (a launch whose gate is closed does nothing).  Like the other entry points
+ * it allocates nothing and does not synchronise, so a HIP graph may capture
+ * it; each possible accuracy round adds about twenty such launches, so
+ * max_power_iters - power_iters is best kept small.
  * Features (TP_MLP_INPUTS = 12, FP32, per slice; p = min(n1,n2)):
  *   0 log(tau / rms sigma), rms sigma = ||Ybar^(k)||_F / sqrt(p)
  *   1 log(max column norm / tau)
@@ -441,7 +448,7 @@ int tp_batch_destroy(tp_batch* plan);
  *                                 dimension >= 64; by shape it takes every such
  *                                 product, variants 1 .. 6 keep them on the tiles),
  *                                 8 = wide-output kernel (FP32, A B, inner dimension
- *                                 1 .. 48, m a multiple of 64 and n of 256, 16-byte
+ *                                 1 .. 64, m a multiple of 64 and n of 256, 16-byte
  *                                 aligned B and C; by shape it takes every such
  *                                 product that the narrow kernel does not)
  *   TP_PARAM_FFT_GRID             persistent workgroups per compute unit of the
@@ -492,7 +499,12 @@ int tp_get_param(int key);
  * products 8 m n k flops per complex slice and 2 m n k per real one, and the
  * FP32 bytes of both operands and the result (8 per complex element, 4 per
  * real one); for the transforms 4 n1 n2 n3 bytes on the tensor side plus
- * 8 h n1 n2 on the slice side; 0 for the other kernels.
+ * 8 h n1 n2 on the slice side; 0 for the other kernels.  A product whose
+ * gate or sizes are decided on the device (the learned-rank prox) gets the
+ * work of the sizes it ran at, 0 when its gate was closed, evaluated at
+ * collection time from the values then in device memory: collect after each
+ * such call for exact figures.  Products over a device-counted set of
+ * slices (the learned prox's full-SVD fallback) are given no work.
  */
 int tp_trace_enable(int enable);
 int tp_trace_collect(int* kernel_ids, float* ms, int capacity);

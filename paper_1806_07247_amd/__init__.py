@@ -155,7 +155,7 @@ def tp_prox_tnn_learned_workspace_size(n1, n2, n3, max_rank=64):
 
 
 def tp_prox_tnn_learned(Y, tau, mlp=None, fixed_rank=0, prev_rank=None, prev_sigma=None, oversample=10,
-                        power_iters=2, max_rank=64, seed=0, accuracy=2e-5, max_power_iters=8, retry_wide=True,
+                        power_iters=2, max_rank=64, seed=0, accuracy=2e-5, max_power_iters=4, retry_wide=True,
                         accuracy_ref=0, warm_basis=None, warm_cols=None, basis_out=None, basis_cols_out=None,
                         out=None, rank=None, fallback=None, info=None, sigma_out=None, workspace=None):
     """Learned-rank prox (see include/tp.h); mlp is a float32 device tensor of
@@ -250,7 +250,7 @@ def tp_trpca(X, lam=None, mu=1e-3, rho=1.1, mu_max=1e10, tol=1e-5, max_iter=500,
     lo = None
     if learned is not None:
         d = dict(mlp=None, fixed_rank=0, oversample=10, power_iters=2, max_rank=64, seed=0, accuracy=2e-5,
-                 max_power_iters=8, retry_wide=True, accuracy_ref=0)
+                 max_power_iters=4, retry_wide=True, accuracy_ref=0)
         d.update(learned)
         lo = _lib.LearnedOpts(_ptr(d["mlp"]), int(d["fixed_rank"]), None, None, int(d["oversample"]),
                               int(d["power_iters"]), int(d["max_rank"]), int(d["seed"]) & 0xFFFFFFFFFFFFFFFF,

@@ -81,7 +81,7 @@ tp::Arena svt_arena(void* ws, size_t bytes, int n1, int n2, int n3, bool recon, 
 // slice (or its conjugate transpose when wide), shrinkage of the rotated
 // columns, then W = What What^* Ybar (or Ybar Bhat Bhat^*) as two products.
 int run_svt(const SvtLayout& L, tp::Planes yb, int n1, int n2, int nslices, int real_first, int real_last,
-            double tau, int* info, int* rank, hipStream_t s)
+            double tau, int* info, int* rank, hipStream_t s, const int* count = nullptr)
 {
     const bool tr = n1 < n2;
     const int R = tr ? n2 : n1, P = tr ? n1 : n2, p = P;
@@ -100,12 +100,15 @@ int run_svt(const SvtLayout& L, tp::Planes yb, int n1, int n2, int nslices, int 
     j.max_sweeps = tp::param(TP_PARAM_JACOBI_SWEEPS);
     j.transpose = tr ? 1 : 0;
     j.tol = tp::jacobi_tol(R);
+    j.count = count;
     TP_LAUNCH(tp::K_JACOBI, s, tp::launch_jacobi(j, L.jscratch, L.jscratch_bytes, s));
     // shrinkage (eq (21)): scaled columns sqrt(d_j)/sigma_j w_j
-    TP_LAUNCH(tp::K_SHRINK, s, tp::launch_shrink(L.w.re, L.w.im, L.sigma, rank ? rank : L.keep, R, P, h, tau, s));
+    TP_LAUNCH(tp::K_SHRINK, s,
+              tp::launch_shrink(L.w.re, L.w.im, L.sigma, rank ? rank : L.keep, R, P, h, tau, s, count));
     // W = U (S - tau)_+ V^* as two slice products
     tp::CgemmArgs g{};
     g.nslices = h;
+    g.dyn_ns = count;
     g.real_first = real_first;
     g.real_last = real_last;
     if (!tr) {
@@ -161,7 +164,21 @@ struct LearnedLayout {
     float* feats;
     tp::Planes vp, cp, t1, t2;      // V_r, U_r S (planar L x L), residual products (m x L)
     int *kpred, *lact, *fb, *rank, *status, *idx, *cinfo, *crank, *prefb, *bad;
+    int* ctl;                       // device-side control values (widths, gates, counts; Ctl)
 };
+
+// Entries of LearnedLayout::ctl, written and read on the device only.
+enum Ctl {
+    C_L1 = 0,      // sketch width of the first attempt (0: no randomized slice)
+    C_G1 = 1,      // gate of the first attempt
+    C_RETRY = 2,   // gate of the wide retry (some count check failed below the widest sketch)
+    C_L2 = 3,      // sketch width of the retry
+    C_G2 = 4,      // gate of the retry
+    C_NFB = 5,     // number of fallback slices
+    C_ROUND = 8,   // C_ROUND + 32 a + r: round r (r >= 1) of the accuracy loop of attempt a
+    C_COUNT = 72
+};
+constexpr int kMaxRounds = 31;
 
 tp::Arena learned_arena(void* ws, size_t bytes, int n1, int n2, int n3, int Lw, LearnedLayout* out)
 {
@@ -218,6 +235,7 @@ tp::Arena learned_arena(void* ws, size_t bytes, int n1, int n2, int n3, int Lw, 
     t.cinfo = ar.take<int>(h);
     t.crank = ar.take<int>(h);
     t.bad = ar.take<int>(h);
+    t.ctl = ar.take<int>(C_COUNT);
     if (out) *out = t;
     return ar;
 }
@@ -257,11 +275,28 @@ tp::CgemmArgs gemm_args(tp::Planes a, long long lda, long long sa, tp::Planes b,
     return g;
 }
 
+// device-side values of a launch (CgemmArgs): gate and caps of m, n, k
+struct Dyn {
+    const int* gate = nullptr;
+    const int* m = nullptr;
+    const int* n = nullptr;
+    const int* k = nullptr;
+};
+
+void set_dyn(tp::CgemmArgs& g, const Dyn& d)
+{
+    g.gate = d.gate;
+    g.dyn_m = d.m;
+    g.dyn_n = d.n;
+    g.dyn_k = d.k;
+}
+
 int gemm(tp::Planes a, long long lda, long long sa, int opa, tp::Planes b, long long ldb, long long sb, int opb,
          tp::Planes c, long long ldc, long long sc, int m, int n, int k, int nslices, int real_last, hipStream_t s,
-         float* part = nullptr, size_t part_bytes = 0)
+         float* part = nullptr, size_t part_bytes = 0, const Dyn& d = Dyn())
 {
-    const tp::CgemmArgs g = gemm_args(a, lda, sa, b, ldb, sb, c, ldc, sc, m, n, k, nslices, real_last, part, part_bytes);
+    tp::CgemmArgs g = gemm_args(a, lda, sa, b, ldb, sb, c, ldc, sc, m, n, k, nslices, real_last, part, part_bytes);
+    set_dyn(g, d);
     TP_LAUNCH(tp::K_CGEMM, s, tp::launch_cgemm(g, opa, opb, TP_PREC_FP32, s));
     return TP_OK;
 }
@@ -271,22 +306,47 @@ int gemm(tp::Planes a, long long lda, long long sa, int opa, tp::Planes b, long 
 // pairs are swapped).  With want_r (two passes) the combined R of both
 // passes is kept and R^* written to Lw.rh.  gram_ready: the first pass's
 // Gram partials are already in Lw.part (gemm_gram).
+// gate / width: the call's device gate and live sketch width (L is the
+// launch width, max_rank)
 int cholqr(LearnedLayout& Lw, tp::Planes& y, tp::Planes& tmp, int rows, int L, int h, int real_last, int passes,
-           bool want_r, hipStream_t s, bool gram_ready = false)
+           bool want_r, hipStream_t s, bool gram_ready = false, const int* gate = nullptr, const int* width = nullptr)
 {
     if (want_r && passes != 2) return TP_ERR_ARG;
     tp::Planes src = y, dst = tmp;
+    Dyn d;
+    d.gate = gate;
+    d.k = width;
     for (int pass = 0; pass < passes; ++pass) {
         TP_LAUNCH(tp::K_CHOLQR, s,
                   tp::launch_cholqr_pass(src.re, src.im, rows, L, Lw.lact, h, pass, Lw.part, Lw.rinv.re, Lw.rinv.im,
                                          want_r ? Lw.rtot : nullptr, want_r ? Lw.rh.re : nullptr,
-                                         want_r ? Lw.rh.im : nullptr, Lw.status, s, gram_ready && pass == 0));
+                                         want_r ? Lw.rh.im : nullptr, Lw.status, s, gram_ready && pass == 0, gate));
         const int st = gemm(src, L, (long long)rows * L, tp::OP_N, Lw.rinv, L, (long long)L * L, tp::OP_N, dst, L,
-                            (long long)rows * L, rows, L, L, h, real_last, s);
+                            (long long)rows * L, rows, L, L, h, real_last, s, nullptr, 0, d);
         if (st != TP_OK) return st;
         std::swap(src, dst);
     }
     if (passes % 2) std::swap(y, tmp);
+    return TP_OK;
+}
+
+// CholeskyQR2 of src into dst through mid (three buffers: the result lands in
+// dst, whatever held it before)
+int cholqr3(LearnedLayout& Lw, tp::Planes src, tp::Planes mid, tp::Planes dst, int rows, int L, int h, int real_last,
+            hipStream_t s, const int* gate, const int* width)
+{
+    Dyn d;
+    d.gate = gate;
+    d.k = width;
+    const tp::Planes io[3] = {src, mid, dst};
+    for (int pass = 0; pass < 2; ++pass) {
+        TP_LAUNCH(tp::K_CHOLQR, s,
+                  tp::launch_cholqr_pass(io[pass].re, io[pass].im, rows, L, Lw.lact, h, pass, Lw.part, Lw.rinv.re,
+                                         Lw.rinv.im, nullptr, nullptr, nullptr, Lw.status, s, false, gate));
+        const int st = gemm(io[pass], L, (long long)rows * L, tp::OP_N, Lw.rinv, L, (long long)L * L, tp::OP_N,
+                            io[pass + 1], L, (long long)rows * L, rows, L, L, h, real_last, s, nullptr, 0, d);
+        if (st != TP_OK) return st;
+    }
     return TP_OK;
 }
 
@@ -297,18 +357,23 @@ int cholqr(LearnedLayout& Lw, tp::Planes& y, tp::Planes& tmp, int rows, int L, i
 // *gram_ready tells the CholeskyQR whether that happened.
 int gemm_gram(LearnedLayout& Lw, tp::Planes a, long long lda, long long sa, int opa, tp::Planes b, long long ldb,
               long long sb, tp::Planes c, int m, int n, int k, int nslices, int real_last, hipStream_t s,
-              bool* gram_ready)
+              bool* gram_ready, const int* gate = nullptr, const int* width = nullptr)
 {
     const long long sc = (long long)m * n;
-    const tp::CgemmArgs g = gemm_args(a, lda, sa, b, ldb, sb, c, n, sc, m, n, k, nslices, real_last, Lw.kpart,
-                                      Lw.kpart_bytes);
+    tp::CgemmArgs g = gemm_args(a, lda, sa, b, ldb, sb, c, n, sc, m, n, k, nslices, real_last, Lw.kpart,
+                                Lw.kpart_bytes);
+    Dyn d;
+    d.gate = gate;
+    d.n = width;
+    set_dyn(g, d);
     *gram_ready = false;
     if (!tp::cgemm_parts_ok(g, opa, tp::OP_N))
         return gemm(a, lda, sa, opa, b, ldb, sb, tp::OP_N, c, n, sc, m, n, k, nslices, real_last, s, Lw.kpart,
-                    Lw.kpart_bytes);
+                    Lw.kpart_bytes, d);
     TP_LAUNCH(tp::K_CGEMM, s, tp::launch_cgemm_parts(g, opa, tp::OP_N, s));
     TP_LAUNCH(tp::K_CHOLQR, s,
-              tp::launch_reduce_gram(Lw.kpart, g.ksplit, m, n, nslices, 1, real_last, c.re, c.im, Lw.lact, Lw.part, s));
+              tp::launch_reduce_gram(Lw.kpart, g.ksplit, m, n, nslices, 1, real_last, c.re, c.im, Lw.lact, Lw.part, s,
+                                     gate, width));
     *gram_ready = true;
     return TP_OK;
 }
@@ -671,6 +736,16 @@ int tp_prox_tnn_learned(const float* Y, float* X, int n1, int n2, int n3, float 
     int* fb = fallback ? fallback : W.fb;
     int* rk = rank ? rank : W.rank;
     const tp::Planes ybar = W.full.ybar;
+    // Every launch below is sized for the widest sketch, L = max_rank; the
+    // width a call actually uses, which slices take the randomized path,
+    // whether an accuracy round or the wide retry runs, and which slices
+    // fall back are decided on the device (W.ctl) and read by the launches
+    // themselves, so the call never waits for the host and can be captured
+    // in a HIP graph.
+    const int L = opts->max_rank;
+    int* ctl = W.ctl;
+    const int qmax = std::max(opts->max_power_iters, opts->power_iters);
+    const int rounds = opts->accuracy > 0.0f ? std::min(qmax - opts->power_iters, kMaxRounds - 1) : 0;
 
     TP_LAUNCH(tp::K_RFFT, s, tp::launch_rfft(Y, ybar.re, ybar.im, mn, n3, s));
     // predicted count per slice and sketch width
@@ -678,77 +753,60 @@ int tp_prox_tnn_learned(const float* Y, float* X, int n1, int n2, int n3, float 
               tp::launch_features(ybar.re, ybar.im, n1, n2, n3, h, (double)tau, opts->prev_rank, opts->prev_sigma,
                                   W.feats, W.fpart, W.fro2, s));
     TP_LAUNCH(tp::K_PREDICT, s,
-              tp::launch_predict(opts->mlp, W.feats, h, p, opts->fixed_rank, opts->oversample, opts->max_rank,
-                                 W.kpred, W.lact, W.prefb, rk, s));
-    TP_TRY(hipMemsetAsync(W.status, 0, h * sizeof(int), s));
-    std::vector<int> hbad(h), hfb(h), hkl(3 * h);
-    TP_TRY(hipMemcpyAsync(hkl.data(), W.kpred, 3 * h * sizeof(int), hipMemcpyDeviceToHost, s));
-    TP_TRY(hipStreamSynchronize(s));
-    int *hk = hkl.data(), *hl = hk + h;
-    const int* hpre = hk + 2 * h;
-    int st = TP_OK;
-    bool fb_known = false;  // hfb holds the current fallback flags
-    for (int attempt = 0; attempt < 2; ++attempt) {
-    // sketch width of this attempt: the widest l, rounded up to 8
-    int lmax = 0;
-    for (int k = 0; k < h; ++k)
-        if (!hpre[k] && hl[k] > lmax) lmax = hl[k];
-    const int L = lmax > 0 ? std::min(((lmax + 7) / 8) * 8, opts->max_rank) : 0;
-    // every slice on the randomized path uses the call's common width L (the
-    // batched products run at that width anyway): l = min(L, p), and the
-    // count check allows up to l - oversample singular values above tau
-    if (L > 0) {
-        for (int k = 0; k < h; ++k)
-            if (!hpre[k]) {
-                hl[k] = std::min(L, p);
-                hk[k] = std::max(hk[k], hl[k] - opts->oversample);
-            }
-        TP_TRY(hipMemcpyAsync(W.kpred, hk, 2 * h * sizeof(int), hipMemcpyHostToDevice, s));  // kpred, lact
-    }
+              tp::launch_predict(opts->mlp, W.feats, h, p, opts->fixed_rank, opts->oversample, L, W.kpred, W.lact,
+                                 W.prefb, rk, s));
+    TP_LAUNCH(tp::K_PREDICT, s, tp::launch_fill_int(W.status, h, 0, s));
+    TP_LAUNCH(tp::K_PREDICT, s, tp::launch_fill_int(ctl, C_COUNT, 0, s));
+    TP_LAUNCH(tp::K_PREDICT, s,
+              tp::launch_width(W.kpred, W.lact, W.prefb, fb, h, p, opts->oversample, L, nullptr, ctl + C_L1,
+                               ctl + C_G1, true, s));
 
-    if (L == 0) {  // every slice goes to the full SVD
-        TP_TRY(hipMemcpyAsync(fb, W.prefb, h * sizeof(int), hipMemcpyDeviceToDevice, s));
-        if (opts->basis_out && opts->basis_cols_out)  // no basis to pass on
-            TP_LAUNCH(tp::K_SKETCH, s,
-                      tp::launch_store_basis(W.za.re, W.za.im, n2, 1, W.lact, fb, h, opts->basis_out,
-                                             opts->basis_out + (long long)h * n2 * opts->max_rank, opts->max_rank,
-                                             opts->basis_cols_out, s));
-    } else {
-        const long long sy = (long long)n1 * L, sz = (long long)n2 * L, sl = (long long)L * L;
+    tp::WarmBasis warm{};
+    if (opts->warm_basis && opts->warm_cols) {
+        warm.re = opts->warm_basis;
+        warm.im = opts->warm_basis + (long long)h * n2 * opts->max_rank;
+        warm.ld = opts->max_rank;
+        warm.cols = opts->warm_cols;
+    }
+    const long long sy = (long long)n1 * L, sz = (long long)n2 * L, sl = (long long)L * L;
+
+    // One attempt of the randomized SVT, run when *gate != 0 at sketch width *width.
+    // (the retry attempt has at most one extra accuracy round: it already
+    // runs at the widest sketch)
+    auto attempt = [&](int a, const int* gate, const int* width) -> int {
+        int st = TP_OK;
+        const int nround = a == 0 ? rounds : std::min(rounds, 1);
         // range finder: Y = Ybar Om, re-orthonormalised; power iterations
-        tp::WarmBasis warm{};
-        if (opts->warm_basis && opts->warm_cols) {
-            warm.re = opts->warm_basis;
-            warm.im = opts->warm_basis + (long long)h * n2 * opts->max_rank;
-            warm.ld = opts->max_rank;
-            warm.cols = opts->warm_cols;
-        }
         TP_LAUNCH(tp::K_SKETCH, s,
-                  tp::launch_sketch(W.om.re, W.om.im, n2, L, W.lact, h, n3, opts->seed, warm, s));
+                  tp::launch_sketch(W.om.re, W.om.im, n2, L, W.lact, h, n3, opts->seed, warm, s, gate));
         bool gr = false;
-        st = gemm_gram(W, ybar, n2, mn, tp::OP_N, W.om, L, sz, W.ya, n1, L, n2, h, rl, s, &gr);
+        st = gemm_gram(W, ybar, n2, mn, tp::OP_N, W.om, L, sz, W.ya, n1, L, n2, h, rl, s, &gr, gate, width);
         // a basis that only feeds the next power-iteration product takes one
         // (shifted, FP64 Gram) CholeskyQR pass: it needs to be well
         // conditioned, not orthonormal to working precision; every Y that
         // the projection Ybar^* Q may use takes CholeskyQR2
-        if (st == TP_OK) st = cholqr(W, W.ya, W.yb, n1, L, h, rl, opts->power_iters > 0 ? 1 : 2, false, s, gr);
-        auto power_iteration = [&]() {
+        if (st == TP_OK)
+            st = cholqr(W, W.ya, W.yb, n1, L, h, rl, opts->power_iters > 0 ? 1 : 2, false, s, gr, gate, width);
+        for (int it = 0; st == TP_OK && it < opts->power_iters; ++it) {
             bool g1 = false, g2 = false;
-            int r = gemm_gram(W, ybar, n2, mn, tp::OP_C, W.ya, L, sy, W.za, n2, L, n1, h, rl, s, &g1);
-            if (r == TP_OK) r = cholqr(W, W.za, W.zb, n2, L, h, rl, 1, false, s, g1);
-            if (r == TP_OK) r = gemm_gram(W, ybar, n2, mn, tp::OP_N, W.za, L, sz, W.ya, n1, L, n2, h, rl, s, &g2);
-            if (r == TP_OK) r = cholqr(W, W.ya, W.yb, n1, L, h, rl, 2, false, s, g2);
-            return r;
-        };
-        for (int it = 0; st == TP_OK && it < opts->power_iters; ++it) st = power_iteration();
+            st = gemm_gram(W, ybar, n2, mn, tp::OP_C, W.ya, L, sy, W.za, n2, L, n1, h, rl, s, &g1, gate, width);
+            if (st == TP_OK) st = cholqr(W, W.za, W.zb, n2, L, h, rl, 1, false, s, g1, gate, width);
+            if (st == TP_OK)
+                st = gemm_gram(W, ybar, n2, mn, tp::OP_N, W.za, L, sz, W.ya, n1, L, n2, h, rl, s, &g2, gate, width);
+            if (st == TP_OK) st = cholqr(W, W.ya, W.yb, n1, L, h, rl, 2, false, s, g2, gate, width);
+        }
         if (st != TP_OK) return st;
-        const int qmax = std::max(opts->max_power_iters, opts->power_iters);
-        int q = opts->power_iters;
-        while (true) {
+        Dyn dk;  // products over the sketch columns
+        dk.gate = gate;
+        dk.k = width;
+        for (int r = 0; r <= nround; ++r) {
+            // round r runs when the previous round's a posteriori check found
+            // an inaccurate slice (round 0: when the attempt runs)
+            const int* run = r == 0 ? gate : ctl + C_ROUND + 32 * a + r;
             // Bh = Ybar^* Q = Q2 R2
             bool gz = false;
-            st = gemm_gram(W, ybar, n2, mn, tp::OP_C, W.ya, L, sy, W.za, n2, L, n1, h, rl, s, &gz);
-            if (st == TP_OK) st = cholqr(W, W.za, W.zb, n2, L, h, rl, 2, true, s, gz);
+            st = gemm_gram(W, ybar, n2, mn, tp::OP_C, W.ya, L, sy, W.za, n2, L, n1, h, rl, s, &gz, run, width);
+            if (st == TP_OK) st = cholqr(W, W.za, W.zb, n2, L, h, rl, 2, true, s, gz, run, width);
             if (st != TP_OK) return st;
             // SVD of R2^* (one workgroup per slice, LDS), count check, core T
             tp::JacobiArgs j{};
@@ -763,50 +821,51 @@ int tp_prox_tnn_learned(const float* Y, float* X, int n1, int n2, int n3, float 
             j.cols = W.jcols;
             j.qout = W.jv;
             j.whole = 1;
+            j.gate = run;
+            j.pdyn = width;
             TP_LAUNCH(tp::K_JACOBI, s, tp::launch_jacobi(j, nullptr, 0, s));
             TP_LAUNCH(tp::K_RSVD_CHECK, s,
-                      tp::launch_rsvd_check(W.jcols, W.jsig, W.jv, W.kpred, W.lact, W.prefb, W.status, L, (double)tau,
-                                            W.T, fb, rk, h, s));
+                      tp::launch_rsvd_check(W.jcols, W.jsig, W.jv, W.kpred, W.lact, W.prefb, W.status, L,
+                                            (double)tau, W.T, fb, rk, h, s, run));
             if (!(opts->accuracy > 0.0f)) break;
             // a posteriori check: residuals Ybar v_j - sigma_j u_j of the kept Ritz triplets
-            TP_LAUNCH(tp::K_ACCURACY, s, tp::launch_cm_to_planar(W.jv, W.vp, L, h, s));
-            TP_LAUNCH(tp::K_ACCURACY, s, tp::launch_cm_to_planar(W.jcols, W.cp, L, h, s));
-            st = gemm(ybar, n2, mn, tp::OP_N, W.za, L, sz, tp::OP_N, W.yb, L, sy, n1, L, n2, h, rl, s,
-                    W.kpart, W.kpart_bytes);  // Ybar Q2
-            if (st == TP_OK) st = gemm(W.yb, L, sy, tp::OP_N, W.vp, L, sl, tp::OP_N, W.t1, L, sy, n1, L, L, h, rl, s);
-            if (st == TP_OK) st = gemm(W.ya, L, sy, tp::OP_N, W.cp, L, sl, tp::OP_N, W.t2, L, sy, n1, L, L, h, rl, s);
+            Dyn dr;
+            dr.gate = run;
+            dr.k = width;
+            TP_LAUNCH(tp::K_ACCURACY, s, tp::launch_cm_to_planar(W.jv, W.vp, L, h, s, run, W.jcols, W.cp));
+            Dyn dn;
+            dn.gate = run;
+            dn.n = width;
+            st = gemm(ybar, n2, mn, tp::OP_N, W.za, L, sz, tp::OP_N, W.yb, L, sy, n1, L, n2, h, rl, s, W.kpart,
+                      W.kpart_bytes, dn);  // Ybar Q2
+            if (st == TP_OK)
+                st = gemm(W.yb, L, sy, tp::OP_N, W.vp, L, sl, tp::OP_N, W.t1, L, sy, n1, L, L, h, rl, s, nullptr, 0, dr);
+            if (st == TP_OK)
+                st = gemm(W.ya, L, sy, tp::OP_N, W.cp, L, sl, tp::OP_N, W.t2, L, sy, n1, L, L, h, rl, s, nullptr, 0, dr);
             if (st != TP_OK) return st;
+            const bool last = r == nround;
+            int* next = last ? nullptr : ctl + C_ROUND + 32 * a + r + 1;
             TP_LAUNCH(tp::K_ACCURACY, s,
-                      tp::launch_accuracy(W.t1, W.t2, W.jsig, W.lact, opts->accuracy_ref == 0 ? W.fro2 : nullptr,
-                                          n1, L, (double)tau, (double)opts->accuracy,
-                                          W.bad, h, W.accpart, s));
-            TP_TRY(hipMemcpyAsync(hbad.data(), W.bad, h * sizeof(int), hipMemcpyDeviceToHost, s));
-            TP_TRY(hipMemcpyAsync(hfb.data(), fb, h * sizeof(int), hipMemcpyDeviceToHost, s));
-            TP_TRY(hipStreamSynchronize(s));
-            bool any = false;
-            for (int k = 0; k < h; ++k) any = any || (hbad[k] && !hfb[k]);
-            if (!any) break;
-            if (q >= qmax) {  // still inaccurate: those slices take the full SVD
-                for (int k = 0; k < h; ++k) hfb[k] = hfb[k] || hbad[k];
-                TP_TRY(hipMemcpy(fb, hfb.data(), h * sizeof(int), hipMemcpyHostToDevice));
-                break;
-            }
+                      tp::launch_accuracy_round(W.t1, W.t2, W.jsig, W.lact,
+                                                opts->accuracy_ref == 0 ? W.fro2 : nullptr, n1, L, (double)tau,
+                                                (double)opts->accuracy, W.bad, h, W.accpart, fb, run, next, last, s));
+            if (last) break;
             // the next subspace iteration needs no new product: Ybar^* Y is
             // the projection just formed (its orthonormal basis Q2 is in W.za),
             // and Ybar Q2, whose span is that of the iteration's Ybar Z, is the
-            // residual check's product in W.yb; Y = orth(Ybar Q2)
-            std::swap(W.ya, W.yb);
-            st = cholqr(W, W.ya, W.yb, n1, L, h, rl, 2, false, s);
+            // residual check's product in W.yb; Y = orth(Ybar Q2), its two
+            // CholeskyQR passes going W.yb -> W.t1 -> W.ya
+            st = cholqr3(W, W.yb, W.t1, W.ya, n1, L, h, rl, s, next, width);
             if (st != TP_OK) return st;
-            ++q;
         }
         if (opts->basis_out && opts->basis_cols_out) {
             // the right Ritz vectors Q2 V for the next call's warm start: its
             // sketch then starts from the singular basis, so its R2^* comes out
             // nearly diagonal and the small Jacobi SVD needs few sweeps
-            TP_LAUNCH(tp::K_ACCURACY, s, tp::launch_cm_to_planar(W.jv, W.vp, L, h, s));
-            st = gemm(W.za, L, sz, tp::OP_N, W.vp, L, sl, tp::OP_N, W.zb, L, sz, n2, L, L, h, rl, s);
+            TP_LAUNCH(tp::K_ACCURACY, s, tp::launch_cm_to_planar(W.jv, W.vp, L, h, s, gate));
+            st = gemm(W.za, L, sz, tp::OP_N, W.vp, L, sl, tp::OP_N, W.zb, L, sz, n2, L, L, h, rl, s, nullptr, 0, dk);
             if (st != TP_OK) return st;
+            // (valid columns 0 for fallback slices, so a closed attempt stores zeros)
             TP_LAUNCH(tp::K_SKETCH, s,
                       tp::launch_store_basis(W.zb.re, W.zb.im, n2, L, W.lact, fb, h, opts->basis_out,
                                              opts->basis_out + (long long)h * n2 * opts->max_rank, opts->max_rank,
@@ -815,61 +874,47 @@ int tp_prox_tnn_learned(const float* Y, float* X, int n1, int n2, int n3, float 
         if (sigma_out)  // singular values of the slices kept on the randomized path
             TP_LAUNCH(tp::K_RSVD_CHECK, s, tp::launch_sigma_top(W.jsig, L, W.lact, nullptr, fb, h, sigma_out, s));
         // W = Q (T Q2^*)
-        st = gemm(W.T, L, sl, tp::OP_N, W.za, L, sz, tp::OP_C, W.m1, n2, (long long)L * n2, L, n2, L, h, rl, s);
+        Dyn dmk;
+        dmk.gate = gate;
+        dmk.m = width;
+        dmk.k = width;
+        st = gemm(W.T, L, sl, tp::OP_N, W.za, L, sz, tp::OP_C, W.m1, n2, (long long)L * n2, L, n2, L, h, rl, s,
+                  nullptr, 0, dmk);
         if (st == TP_OK)
-            st = gemm(W.ya, L, sy, tp::OP_N, W.m1, n2, (long long)L * n2, tp::OP_N, W.wbar, n2, mn, n1, n2, L, h, rl, s);
+            st = gemm(W.ya, L, sy, tp::OP_N, W.m1, n2, (long long)L * n2, tp::OP_N, W.wbar, n2, mn, n1, n2, L, h, rl,
+                      s, nullptr, 0, dk);
+        return st;
+    };
+
+    int st = attempt(0, ctl + C_G1, ctl + C_L1);
+    if (st != TP_OK) return st;
+    if (opts->retry_wide) {
+        // slices whose count check failed below the widest sketch: one retry
+        // with kpred = max_rank - oversample (the whole call is recomputed
+        // at the retry's width)
+        TP_LAUNCH(tp::K_PREDICT, s,
+                  tp::launch_retry(fb, W.prefb, W.kpred, W.lact, h, p, opts->oversample, L, ctl + C_G1,
+                                   ctl + C_RETRY, s));
+        TP_LAUNCH(tp::K_PREDICT, s,
+                  tp::launch_width(W.kpred, W.lact, W.prefb, fb, h, p, opts->oversample, L, ctl + C_RETRY,
+                                   ctl + C_L2, ctl + C_G2, false, s));
+        st = attempt(1, ctl + C_G2, ctl + C_L2);
         if (st != TP_OK) return st;
     }
-    if (attempt == 1 || !opts->retry_wide) break;
-    // slices whose count check failed below the widest sketch: one retry with
-    // kpred = max_rank - oversample (the whole call is recomputed, the other
-    // slices identically)
-    TP_TRY(hipMemcpyAsync(hfb.data(), fb, h * sizeof(int), hipMemcpyDeviceToHost, s));
-    TP_TRY(hipStreamSynchronize(s));
-    fb_known = true;
-    const int kwide = std::min(std::max(opts->max_rank - opts->oversample, 0), p);
-    const int lwide = std::min(kwide + opts->oversample, p);
-    bool retry = false;
-    for (int k = 0; k < h; ++k)
-        if (hfb[k] && !hpre[k] && hl[k] < lwide && hk[k] < kwide) {
-            hk[k] = kwide;
-            hl[k] = lwide;
-            retry = true;
-        }
-    if (!retry) break;
-    fb_known = false;
-    }
-    // fallback slices: full SVD on a compact batch
-    std::vector<int> hidx;
-    if (!fb_known) {
-        TP_TRY(hipMemcpyAsync(hfb.data(), fb, h * sizeof(int), hipMemcpyDeviceToHost, s));
-        TP_TRY(hipStreamSynchronize(s));
-    }
-    for (int k = 0; k < h; ++k)
-        if (hfb[k]) hidx.push_back(k);
-    const int cnt = (int)hidx.size();
-    std::vector<int> hinfo(h, 0);
-    if (cnt > 0) {
-        TP_TRY(hipMemcpy(W.idx, hidx.data(), cnt * sizeof(int), hipMemcpyHostToDevice));
-        TP_LAUNCH(tp::K_GATHER, s, tp::launch_gather(ybar.re, ybar.im, W.cy.re, W.cy.im, W.idx, cnt, mn, false, s));
-        SvtLayout F = W.full;
-        st = run_svt(F, W.cy, n1, n2, cnt, 0, 0, (double)tau, info ? W.cinfo : nullptr, W.crank, s);
-        if (st != TP_OK) return st;
-        TP_LAUNCH(tp::K_GATHER, s, tp::launch_gather(W.cy.re, W.cy.im, W.wbar.re, W.wbar.im, W.idx, cnt, mn, true, s));
-        if (sigma_out)
-            TP_LAUNCH(tp::K_GATHER, s, tp::launch_sigma_top(F.sigma, p, nullptr, W.idx, nullptr, cnt, sigma_out, s));
-        std::vector<int> crank(cnt), cinfo(cnt, 0), hrank(h);
-        TP_TRY(hipMemcpyAsync(crank.data(), W.crank, cnt * sizeof(int), hipMemcpyDeviceToHost, s));
-        if (info) TP_TRY(hipMemcpyAsync(cinfo.data(), W.cinfo, cnt * sizeof(int), hipMemcpyDeviceToHost, s));
-        TP_TRY(hipMemcpyAsync(hrank.data(), rk, h * sizeof(int), hipMemcpyDeviceToHost, s));
-        TP_TRY(hipStreamSynchronize(s));
-        for (int c = 0; c < cnt; ++c) {
-            hrank[hidx[c]] = crank[c];
-            hinfo[hidx[c]] = cinfo[c];
-        }
-        TP_TRY(hipMemcpy(rk, hrank.data(), h * sizeof(int), hipMemcpyHostToDevice));
-    }
-    if (info) TP_TRY(hipMemcpy(info, hinfo.data(), h * sizeof(int), hipMemcpyHostToDevice));
+    // fallback slices: the full SVD on a compact batch whose size is known
+    // on the device only (every launch reads it; nothing runs for none)
+    const int* nfb = ctl + C_NFB;
+    TP_LAUNCH(tp::K_GATHER, s, tp::launch_compact(fb, h, W.idx, ctl + C_NFB, s));
+    TP_LAUNCH(tp::K_GATHER, s,
+              tp::launch_gather(ybar.re, ybar.im, W.cy.re, W.cy.im, W.idx, h, mn, false, s, nfb));
+    SvtLayout F = W.full;
+    st = run_svt(F, W.cy, n1, n2, h, 0, 0, (double)tau, W.cinfo, W.crank, s, nfb);
+    if (st != TP_OK) return st;
+    TP_LAUNCH(tp::K_GATHER, s,
+              tp::launch_gather(W.cy.re, W.cy.im, W.wbar.re, W.wbar.im, W.idx, h, mn, true, s, nfb));
+    if (sigma_out)
+        TP_LAUNCH(tp::K_GATHER, s, tp::launch_sigma_top(F.sigma, p, nullptr, W.idx, nullptr, h, sigma_out, s, nfb));
+    TP_LAUNCH(tp::K_GATHER, s, tp::launch_fb_results(W.idx, nfb, W.crank, W.cinfo, fb, rk, info, h, s));
     TP_LAUNCH(tp::K_IRFFT, s, tp::launch_irfft(W.wbar.re, W.wbar.im, X, mn, n3, s));
     return TP_OK;
 }

@@ -88,6 +88,20 @@ __device__ __forceinline__ SliceView slice_view(const CgemmArgs& p, int s, int k
     return v;
 }
 
+// The device-side values of a launch (see CgemmArgs): false when its gate is
+// 0 or a live size is 0.  A capped k replaces k; m and n keep the layout of
+// the output and of the split parts, and m_live / n_live give the rows and
+// columns that are computed (tiles past them do nothing).
+__device__ __forceinline__ int m_live(const CgemmArgs& p) { return p.dyn_m ? min(p.m, *p.dyn_m) : p.m; }
+__device__ __forceinline__ int n_live(const CgemmArgs& p) { return p.dyn_n ? min(p.n, *p.dyn_n) : p.n; }
+__device__ __forceinline__ bool apply_dyn(CgemmArgs& p)
+{
+    if (p.gate && *p.gate == 0) return false;
+    if (p.dyn_k) p.k = min(p.k, *p.dyn_k);
+    return m_live(p) > 0 && n_live(p) > 0 && p.k > 0;
+}
+__device__ __forceinline__ bool slice_live(const CgemmArgs& p, int s) { return !p.dyn_ns || s < *p.dyn_ns; }
+
 // Four source elements contiguous in memory at off (valid of them in bounds):
 // one 16-byte load per plane when all four are valid and the planes allow
 // it, else element by element with zero fill.  neg negates the imaginary
@@ -427,21 +441,26 @@ template <int OPA, int OPB, class T, int BK>
 __global__ __launch_bounds__(256) void k_cgemm_f32(CgemmArgs p)
 {
     __shared__ __attribute__((aligned(16))) float smem[f32_smem_floats<T, BK>()];
+    if (!apply_dyn(p)) return;
     int x, y, z;
     xcd_tile(x, y, z);  // z = kp * nslices + slice
+    if (!slice_live(p, z % p.nslices) || y * T::BM >= m_live(p) || x * T::BN >= n_live(p)) return;
     cgemm_f32_tile<OPA, OPB, T, BK>(p, z % p.nslices, y * T::BM, x * T::BN, smem, z / p.nslices);
 }
 
 // C = sum over the ksplit partial products, in a fixed order
 __global__ __launch_bounds__(256) void k_splitk_reduce(CgemmArgs p)
 {
+    if (!apply_dyn(p)) return;
     const long long mn = (long long)p.m * p.n, total = (long long)p.nslices * mn;
     const long long plane = (long long)p.ksplit * total;
     for (long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x; e < total;
          e += (long long)gridDim.x * blockDim.x) {
         const int s = (int)(e / mn);
+        if (!slice_live(p, s)) continue;
         const long long r = e % mn;
         const int i = (int)(r / p.n), j = (int)(r % p.n);
+        if (i >= m_live(p) || j >= n_live(p)) continue;  // not computed: left alone
         float vr = 0.0f, vi = 0.0f;
         for (int kp = 0; kp < p.ksplit; ++kp) {
             vr += p.part[kp * total + e];
@@ -543,6 +562,8 @@ __device__ __forceinline__ void sk_tile(const CgemmArgs& p, const SliceView& v, 
     const bool veca = OPA == OP_N && vec_ok(v.ar, v.ai, p.lda);
     const bool vecb = vec_ok(v.br, v.bi, p.ldb);
     const int nst = (v.K - v.K0 + kSkBK - 1) / kSkBK;
+    const int nl = n_live(p);             // live columns (a multiple of 4); the rest come out zero
+    const int tl = (nl + 15) / 16;        // live 16-column blocks (uniform)
 
     floatx4 p1[TN], p2[TN], p3[TN];
 #pragma unroll
@@ -553,7 +574,7 @@ __device__ __forceinline__ void sk_tile(const CgemmArgs& p, const SliceView& v, 
 #pragma unroll
     for (int u = 0; u < GB; ++u) {
         const int e = tid + 256 * u;
-        bok[u] = e < kSkBK * NC / 4 && 4 * (e % (NC / 4)) < p.n;
+        bok[u] = e < kSkBK * NC / 4 && 4 * (e % (NC / 4)) < nl;
     }
     // B stage at k0 into registers (zero outside k < K and columns < n)
     auto load_b = [&](int k0) {
@@ -567,7 +588,7 @@ __device__ __forceinline__ void sk_tile(const CgemmArgs& p, const SliceView& v, 
                 bq[u].r = *reinterpret_cast<const float4*>(v.br + off);
                 bq[u].i = *reinterpret_cast<const float4*>(v.bi + off);
             } else {
-                const int valid = (e < kSkBK * NC / 4 && k < v.K) ? max(0, min(4, p.n - col)) : 0;
+                const int valid = (e < kSkBK * NC / 4 && k < v.K) ? max(0, min(4, nl - col)) : 0;
                 bq[u] = load4(v.br, v.bi, (long long)k * p.ldb + col, valid, vecb, false);
             }
         }
@@ -595,6 +616,7 @@ __device__ __forceinline__ void sk_tile(const CgemmArgs& p, const SliceView& v, 
             float4 fr[TN], fi[TN];
 #pragma unroll
             for (int t = 0; t < TN; ++t) {
+                if (t >= tl) continue;
                 const int off = (16 * h + 4 * g) * LDB + 16 * t + r;
                 fr[t] = make_float4(br[off], br[off + LDB], br[off + 2 * LDB], br[off + 3 * LDB]);
                 fi[t] = make_float4(bi[off], bi[off + LDB], bi[off + 2 * LDB], bi[off + 3 * LDB]);
@@ -606,6 +628,7 @@ __device__ __forceinline__ void sk_tile(const CgemmArgs& p, const SliceView& v, 
                 const float as = OPA == OP_C ? ar - ai : ar + ai;
 #pragma unroll
                 for (int t = 0; t < TN; ++t) {
+                    if (t >= tl) continue;
                     const float b_r = (&fr[t].x)[s], b_i = (&fi[t].x)[s];
                     p1[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(b_r, ar, p1[t], 0, 0, 0);
                     if (!REAL) {
@@ -691,11 +714,24 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(TN >= 3 ? 3
 k_skinny(CgemmArgs p)
 {
     __shared__ __attribute__((aligned(16))) float lds[2 * 2 * sk_plane<TN>()];
+    if (!apply_dyn(p)) return;
     int x, y, z;
     xcd_tile(x, y, z);  // x = row tile, z = kp * nslices + slice
+    if (!slice_live(p, z % p.nslices) || x * kSkRows >= m_live(p)) return;
     const SliceView v = slice_view(p, z % p.nslices, z / p.nslices);
     const bool fast = (x + 1) * kSkRows <= p.m && (v.K - v.K0) % kSkBK == 0 && vec_ok(v.br, v.bi, p.ldb) &&
                       (OPA == OP_C || vec_ok(v.ar, v.ai, p.lda));
+    // a device-capped width of at most 48 columns takes the 48-column tile
+    // (the same registers and waves; its B stage fits the buffer)
+    if constexpr (TN == 4) {
+        if (p.dyn_n && (n_live(p) + 15) / 16 <= 3) {
+            if (v.real)
+                fast ? sk_tile<OPA, 3, true, true>(p, v, x, lds) : sk_tile<OPA, 3, true, false>(p, v, x, lds);
+            else
+                fast ? sk_tile<OPA, 3, false, true>(p, v, x, lds) : sk_tile<OPA, 3, false, false>(p, v, x, lds);
+            return;
+        }
+    }
     if (v.real) {
         if (fast)
             sk_tile<OPA, TN, true, true>(p, v, x, lds);
@@ -710,7 +746,7 @@ k_skinny(CgemmArgs p)
 }
 
 // -------------------------------------------------------------- wide FP32 --
-// Products with a short inner dimension: A (m x k, k <= 48) times B (k x n),
+// Products with a short inner dimension: A (m x k, k <= 64) times B (k x n),
 // neither transposed (the reconstruction W = Q M1 of the randomized SVT, and
 // with at most 64 output columns the products by R^-1 and the Ritz bases).
 // A workgroup of four wavefronts covers 64 rows x 256 columns (x 64 columns,
@@ -721,7 +757,7 @@ k_skinny(CgemmArgs p)
 // this one is multiplied), and the results leave as 16-byte stores while the
 // next block's MFMAs run.  Full tiles only (m a multiple of 64, n of 256,
 // 16-byte aligned planes and rows); 3M complex form.
-constexpr int kWideRows = 64, kWideCols = 256, kWideBlk = 64, kWideMaxK = 48;
+constexpr int kWideRows = 64, kWideCols = 256, kWideBlk = 64, kWideMaxK = 64;
 constexpr int kWideLDB = kWideBlk + 4;  // 4 x 68 = 16 mod 64 banks: a lane's four fragment reads hit distinct banks
 
 // KC: staged inner rows (k rounded up to 16; zero beyond k)
@@ -808,7 +844,7 @@ __device__ __forceinline__ void wide_tile(const CgemmArgs& p, const SliceView& v
         const float* bi = br + PL;
 #pragma unroll
         for (int h = 0; h < nh; ++h) {
-            {
+            if (16 * h < K) {  // chunks past a device-capped k hold zeros: skipped
 #pragma unroll
                 for (int s = 0; s < 4; ++s) {
                     const float ar = fa_r[4 * h + s], ai = fa_i[4 * h + s];
@@ -859,8 +895,10 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(NB > 1 ? 3 
 k_wide(CgemmArgs p)
 {
     __shared__ __attribute__((aligned(16))) float wlds[(NB > 1 ? 2 : 1) * 2 * KC * kWideLDB];
+    if (!apply_dyn(p)) return;
     int x, y, z;
     xcd_tile(x, y, z);  // x = column group (64 NB), y = 64-row tile, z = slice
+    if (!slice_live(p, z) || y * kWideRows >= m_live(p) || x * kWideBlk * NB >= n_live(p)) return;
     const SliceView v = slice_view(p, z, 0);
     if (v.real)
         wide_tile<true, KC, NB>(p, v, x, y, wlds);
@@ -1083,7 +1121,7 @@ hipError_t launch_skinny(const CgemmArgs& a, hipStream_t s, bool reduce = true)
     return launch_skinny_tn<OPA, 4>(a, s, reduce);
 }
 
-// the wide kernel takes FP32 products A B, 1 <= k <= 48 (the same for every
+// the wide kernel takes FP32 products A B, 1 <= k <= 64 (the same for every
 // slice), whole 64 x 256 tiles, 16-byte aligned planes and rows (B and C), no
 // split
 // 0: no; 4: whole 64 x 256 tiles (unmasked); 1: outputs at most 64 columns
@@ -1109,8 +1147,10 @@ hipError_t launch_wide_nb(const CgemmArgs& a, hipStream_t s)
         k_wide<16, NB><<<g, 256, 0, s>>>(a);
     else if (a.k <= 32)
         k_wide<32, NB><<<g, 256, 0, s>>>(a);
-    else
+    else if (a.k <= 48)
         k_wide<48, NB><<<g, 256, 0, s>>>(a);
+    else
+        k_wide<64, NB><<<g, 256, 0, s>>>(a);
     return hipGetLastError();
 }
 
@@ -1190,7 +1230,13 @@ hipError_t launch_cgemm_batch(const CgemmArgs* items, const GemmUnit* units, int
 namespace {
 void trace_gemm_work(const CgemmArgs& a)
 {
+    // a product over a device-counted set of slices has no work the host knows
+    if (a.dyn_ns) return;
     const int nreal = (a.real_first ? 1 : 0) + (a.real_last && a.nslices > 1 ? 1 : 0);
+    if (a.gate || a.dyn_m || a.dyn_n || a.dyn_k) {
+        trace_gemm_dyn(a.gate, a.dyn_m, a.dyn_n, a.dyn_k, a.m, a.n, a.k, a.nslices, nreal);
+        return;
+    }
     const double mnk = (double)a.m * a.n * a.k, elems = (double)a.m * a.k + (double)a.k * a.n + (double)a.m * a.n;
     trace_work(mnk * (8.0 * (a.nslices - nreal) + 2.0 * nreal), elems * (8.0 * (a.nslices - nreal) + 4.0 * nreal));
 }
@@ -1227,6 +1273,9 @@ hipError_t launch_cgemm(const CgemmArgs& a, int opa, int opb, int prec, hipStrea
         }
     }
     const int tuned = param(TP_PARAM_GEMM_VARIANT);
+    // a device-capped inner dimension that fits the wide kernel stays short:
+    // the wide kernel skips its dead 16-deep chunks
+    if (tuned == 0 && a.dyn_k && wide_form(a, opa, opb)) return launch_wide(a, wide_form(a, opa, opb), s);
     if ((tuned == 0 || tuned == 7) && skinny_ok(a, opb, tuned == 7 ? 1 : 64) && (opa == OP_N || opa == OP_C))
         return opa == OP_N ? launch_skinny<OP_N>(a, s) : launch_skinny<OP_C>(a, s);
     if (tuned == 0 || tuned == 8) {

@@ -237,17 +237,18 @@ __device__ __forceinline__ void jacobi_whole(const JacobiArgs& a, int s, float2*
     if (tid == 0) rotated = 0;
     __syncthreads();
 
-    const int np = P + (P & 1);
+    const int Ps = a.pdyn ? min(P, *a.pdyn) : P;  // columns swept
+    const int np = Ps + (Ps & 1);
     const int group = tid / G, gl = tid % G, ngroups = blockDim.x / G;
     const double tol2 = a.tol * a.tol;
     int sweep = 0;
-    bool converged = (P < 2);
+    bool converged = (Ps < 2);
     while (!converged && sweep < a.max_sweeps) {
         for (int step = 0; step < np - 1; ++step) {
             for (int pair = group; pair < np / 2; pair += ngroups) {
                 const int p = rr_col(pair, step, np);
                 const int q = rr_col(np - 1 - pair, step, np);
-                if (p >= P || q >= P) continue;
+                if (p >= Ps || q >= Ps) continue;
                 if (jacobi_pair<G, RPL, WITHV>(work, R, p, q, R, gl, tol2, vw, P, P) && gl == 0) rotated = 1;
             }
             __syncthreads();
@@ -273,6 +274,7 @@ __global__ __launch_bounds__(whole_max_threads(RPL)) void k_jacobi(JacobiArgs a,
     extern __shared__ float2 lwork[];
     __shared__ int rotated;
     const int s = blockIdx.x;
+    if ((a.gate && *a.gate == 0) || (a.count && s >= *a.count)) return;
     const int R = a.transpose ? a.n : a.m;
     const int P = a.transpose ? a.m : a.n;
     const long long per = (long long)R * P + (WITHV ? (long long)P * P : 0);
@@ -311,6 +313,7 @@ __global__ __launch_bounds__(1024) void k_jacobi_batch(const JacobiArgs* __restr
 // three rotating buffers tell, at the start of sweep k, whether sweep k-1 had
 // any rotation; a slice without is converged and its workgroups return.
 struct BlockArgs {
+    const int* count;  // optional device count of live slices
     float2* work;   // [nslices][P][R] column-major
     float2* v;      // [nslices][P][P] column-major (accumulated rotations) or null
     int* rot;       // [3][nslices]
@@ -331,6 +334,7 @@ __global__ __launch_bounds__(512) void k_jacobi_block(BlockArgs a)
     extern __shared__ float2 lds[];
     __shared__ int rotated;
     const int s = blockIdx.y, bp = blockIdx.x, tid = threadIdx.x;
+    if (a.count && s >= *a.count) return;
     const int ns = a.nslices;
     if (bp == 0 && a.bstep == 0 && tid == 0) a.rot[((a.sweep + 1) % 3) * ns + s] = 0;
     if (a.sweep > 0 && a.rot[((a.sweep - 1) % 3) * ns + s] == 0) {
@@ -397,6 +401,7 @@ __global__ __launch_bounds__(512) void k_jacobi_block(BlockArgs a)
 __global__ __launch_bounds__(256) void k_jacobi_block_init(JacobiArgs a, float2* work, float2* v, int* rot, int* done)
 {
     const int s = blockIdx.y;
+    if (a.count && s >= *a.count) return;
     const int R = a.transpose ? a.n : a.m;
     const int P = a.transpose ? a.m : a.n;
     const int w = blockIdx.x * blockDim.x + threadIdx.x, nw = gridDim.x * blockDim.x;
@@ -415,6 +420,7 @@ __global__ __launch_bounds__(256) void k_jacobi_block_finish(JacobiArgs a, const
                                                              const int* rot, const int* done, int sweeps_run)
 {
     const int s = blockIdx.y;
+    if (a.count && s >= *a.count) return;
     const int R = a.transpose ? a.n : a.m;
     const int P = a.transpose ? a.m : a.n;
     store_result<G>(a, s, work + (long long)s * R * P, R, P, blockIdx.x, gridDim.x);
@@ -633,6 +639,7 @@ __global__ __launch_bounds__(MAXT) void k_jacobi_sweep(SweepArgs a)
     const int ldr = (R + 1) & ~1;  // LDS column stride (even: 16-byte aligned columns)
     const int npairs = a.nb / 2, per_step = a.nslices * npairs, half = b / 2;
     const int live_slices = a.count ? min(*a.count, a.nslices) : a.nslices;
+    if (live_slices <= 0) return;
     const int ns = a.nslices, stamp = a.sweep + 1;
     if (a.sweep > 0) {  // every live slice converged: the launch has nothing to do
         int busy = 0;
@@ -969,7 +976,7 @@ hipError_t launch_blocked(const JacobiArgs& a, void* scratch, int R, int P, cons
     k_jacobi_block_init<<<dim3(chunks, a.nslices), 256, 0, st>>>(a, work, v, rot, done);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    BlockArgs b{work, v, rot, done, R, P, a.nslices, pl.nb, pl.b, 0, 0, a.tol * a.tol};
+    BlockArgs b{a.count, work, v, rot, done, R, P, a.nslices, pl.nb, pl.b, 0, 0, a.tol * a.tol};
     const int threads = min(512, ((pl.b * G + 63) / 64) * 64);
     const size_t lds = (size_t)2 * pl.b * (R + (WITHV ? P : 0)) * sizeof(float2);
     auto kern = k_jacobi_block<G, RPL, WITHV>;
@@ -1071,10 +1078,11 @@ namespace {
 // keep[s] = #{j : sigma_j > tau}.
 __global__ __launch_bounds__(256) void k_shrink(float* __restrict__ wr, float* __restrict__ wi,
                                                 const double* __restrict__ sigma, int* __restrict__ keep, int R,
-                                                int P, long long total, double tau)
+                                                int P, long long total, double tau, const int* __restrict__ count)
 {
     const long long e0 = (long long)blockIdx.x * blockDim.x + threadIdx.x;
     const long long per = (long long)R * P;
+    if (count) total = min(total, (long long)*count * per);
     for (long long e = e0; e < total; e += (long long)gridDim.x * blockDim.x) {
         const long long s = e / per;
         const int j = (int)(e % P);
@@ -1162,14 +1170,14 @@ __global__ __launch_bounds__(256) void k_tnn_reduce(const double* __restrict__ s
 }  // namespace
 
 hipError_t launch_shrink(float* wr, float* wi, const double* sigma, int* keep, int R, int P, int nslices, double tau,
-                         hipStream_t st)
+                         hipStream_t st, const int* count)
 {
     const long long total = (long long)R * P * nslices;
     if (total <= 0) return hipSuccess;
     long long blocks = (total + 255) / 256;
     if (blocks > 256 * 32) blocks = 256 * 32;
     if (blocks * 256 < nslices) blocks = (nslices + 255) / 256;
-    k_shrink<<<(int)blocks, 256, 0, st>>>(wr, wi, sigma, keep, R, P, total, tau);
+    k_shrink<<<(int)blocks, 256, 0, st>>>(wr, wi, sigma, keep, R, P, total, tau, count);
     return hipGetLastError();
 }
 

@@ -42,8 +42,9 @@ __device__ __forceinline__ bool is_real_slice(int s, int n3) { return s == 0 || 
 // zero for j >= lact[slice].
 __global__ __launch_bounds__(256) void k_sketch(float* __restrict__ omr, float* __restrict__ omi, int n, int L,
                                                 const int* __restrict__ lact, int nslices, int n3,
-                                                unsigned long long seed, WarmBasis warm)
+                                                unsigned long long seed, WarmBasis warm, const int* __restrict__ gate)
 {
+    if (gate && *gate == 0) return;
     const long long total = (long long)nslices * n * L;
     for (long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x; e < total;
          e += (long long)gridDim.x * blockDim.x) {
@@ -152,16 +153,19 @@ __device__ __forceinline__ void gram_store(const GramBlock& gb, int L, int s, in
         }
 }
 
+// block edge of the Gram blocks for la live columns: the upper triangle of
+// ceil(la / B) blocks fits the 256 threads
+__device__ __forceinline__ int gram_edge(int la) { return la <= 22 ? 1 : (la <= 44 ? 2 : 3); }
+constexpr int kGramW = kMaxL + 3;  // staged row stride (room for the widest edge's last block)
+
 template <int B>
-__global__ __launch_bounds__(256) void k_gram(const float* __restrict__ yr, const float* __restrict__ yi, int m,
-                                              int L, const int* __restrict__ lact, double2* __restrict__ part,
-                                              int nsplit)
+__device__ __forceinline__ void gram_body(const float* __restrict__ yr, const float* __restrict__ yi, int m, int L,
+                                          int la, double2* __restrict__ part, int nsplit, float2* tile)
 {
-    constexpr int W = kMaxL + B;
-    __shared__ float2 tile[kGramChunk * W];
+    constexpr int W = kGramW;
     const int s = blockIdx.y, w = blockIdx.x, tid = threadIdx.x;
-    const int la = lact[s];
-    const GramBlock gb = gram_block<B>(tid, L, la);
+    const int lc = min(la, L);
+    const GramBlock gb = gram_block<B>(tid, lc, lc);  // blocks of the live columns only
     const int r0 = (int)((long long)m * w / nsplit), r1 = (int)((long long)m * (w + 1) / nsplit);
     const float* Yr = yr + (long long)s * m * L;
     const float* Yi = yi + (long long)s * m * L;
@@ -170,27 +174,25 @@ __global__ __launch_bounds__(256) void k_gram(const float* __restrict__ yr, cons
     for (int u = 0; u < B; ++u)
 #pragma unroll
         for (int v = 0; v < B; ++v) gr[u][v] = gi[u][v] = 0.0;
-    const int lc = min(la, L);
+    const int lw = min(L, (lc + B - 1) / B * B);  // staged columns: the live ones, zero to the block edge
     for (int c0 = r0; c0 < r1; c0 += kGramChunk) {
-        // the chunk is contiguous: every load of the thread is issued before any is used
-        const int nr = min(kGramChunk, r1 - c0), nf = nr * L;
-        const float* cr = Yr + (long long)c0 * L;
-        const float* ci = Yi + (long long)c0 * L;
+        // every load of the thread is issued before any is used
+        const int nr = min(kGramChunk, r1 - c0), nf = nr * lw;
         float xr[kGramLoads], xi[kGramLoads];
 #pragma unroll
         for (int q = 0; q < kGramLoads; ++q) {
             const int f = tid + 256 * q;
-            xr[q] = f < nf ? cr[f] : 0.0f;
-            xi[q] = f < nf ? ci[f] : 0.0f;
+            const int i = f / lw, j = f % lw;
+            const bool ok = f < nf && j < lc;
+            const long long o = (long long)(c0 + i) * L + j;
+            xr[q] = ok ? Yr[o] : 0.0f;
+            xi[q] = ok ? Yi[o] : 0.0f;
         }
         __syncthreads();  // the previous chunk is read
 #pragma unroll
         for (int q = 0; q < kGramLoads; ++q) {
             const int f = tid + 256 * q;
-            if (f < nf) {
-                const int i = f / L, j = f % L;
-                tile[i * W + j] = j < lc ? make_float2(xr[q], xi[q]) : make_float2(0.f, 0.f);
-            }
+            if (f < nf) tile[(f / lw) * W + f % lw] = make_float2(xr[q], xi[q]);
         }
         __syncthreads();
         if (gb.work) gram_rows<B, W>(tile, nr, gb.a0, gb.b0, gr, gi);
@@ -198,22 +200,36 @@ __global__ __launch_bounds__(256) void k_gram(const float* __restrict__ yr, cons
     gram_store<B>(gb, L, s, w, nsplit, part, gr, gi);
 }
 
+// Partial Gram of the live columns (lact) of every slice; only their block
+// of the L x L layout is written.
+__global__ __launch_bounds__(256) void k_gram(const float* __restrict__ yr, const float* __restrict__ yi, int m,
+                                              int L, const int* __restrict__ lact, double2* __restrict__ part,
+                                              int nsplit, const int* __restrict__ gate)
+{
+    if (gate && *gate == 0) return;
+    __shared__ float2 tile[kGramChunk * kGramW];
+    const int la = lact[blockIdx.y];
+    switch (gram_edge(la)) {
+        case 1: gram_body<1>(yr, yi, m, L, la, part, nsplit, tile); break;
+        case 2: gram_body<2>(yr, yi, m, L, la, part, nsplit, tile); break;
+        default: gram_body<3>(yr, yi, m, L, la, part, nsplit, tile); break;
+    }
+}
+
 // The split parts of a narrow slice product summed into Y (the fixed order
 // kp = 0, 1, ... of the plain reduction) and, from the same staged rows,
 // the partial Grams of k_gram: one pass over Y instead of a write and a
 // read back.
 template <int B>
-__global__ __launch_bounds__(256) void k_reduce_gram(const float* __restrict__ parts, int ksplit, int m, int L,
-                                                     int nslices, int real_first, int real_last,
-                                                     float* __restrict__ yr, float* __restrict__ yi,
-                                                     const int* __restrict__ lact, double2* __restrict__ part,
-                                                     int nsplit)
+__device__ __forceinline__ void reduce_gram_body(const float* __restrict__ parts, int ksplit, int m, int L, int ny,
+                                                 int nslices, int real_first, int real_last, float* __restrict__ yr,
+                                                 float* __restrict__ yi, int la, double2* __restrict__ part,
+                                                 int nsplit, float2* tile)
 {
-    constexpr int W = kMaxL + B;
-    __shared__ float2 tile[kGramChunk * W];
+    constexpr int W = kGramW;
     const int s = blockIdx.y, w = blockIdx.x, tid = threadIdx.x;
-    const int la = lact[s];
-    const GramBlock gb = gram_block<B>(tid, L, la);
+    const int lc = min(la, L);
+    const GramBlock gb = gram_block<B>(tid, lc, lc);
     const int r0 = (int)((long long)m * w / nsplit), r1 = (int)((long long)m * (w + 1) / nsplit);
     const long long mn = (long long)m * L, total = (long long)nslices * mn, plane = (long long)ksplit * total;
     const bool real = (real_first && s == 0) || (real_last && s == nslices - 1);
@@ -225,20 +241,19 @@ __global__ __launch_bounds__(256) void k_reduce_gram(const float* __restrict__ p
     for (int u = 0; u < B; ++u)
 #pragma unroll
         for (int v = 0; v < B; ++v) gr[u][v] = gi[u][v] = 0.0;
-    const int lc = min(la, L);
     for (int c0 = r0; c0 < r1; c0 += kGramChunk) {
-        // the chunk is contiguous in every part: all loads of the thread in flight at once
-        const int nr = min(kGramChunk, r1 - c0), nf = nr * L;
-        const long long o0 = (long long)c0 * L;
+        // all loads of the thread in flight at once
+        const int nr = min(kGramChunk, r1 - c0), nf = nr * ny;
         float pr[kGramLoads][kMaxParts], pim[kGramLoads][kMaxParts];
 #pragma unroll
         for (int q = 0; q < kGramLoads; ++q) {
             const int f = tid + 256 * q;
+            const long long o = (long long)(c0 + f / ny) * L + f % ny;
 #pragma unroll
             for (int kp = 0; kp < kMaxParts; ++kp) {
                 const bool ok = f < nf && kp < ksplit;
-                pr[q][kp] = ok ? P[kp * total + o0 + f] : 0.0f;
-                pim[q][kp] = ok ? P[plane + kp * total + o0 + f] : 0.0f;
+                pr[q][kp] = ok ? P[kp * total + o] : 0.0f;
+                pim[q][kp] = ok ? P[plane + kp * total + o] : 0.0f;
             }
         }
         __syncthreads();  // the previous chunk is read
@@ -254,16 +269,46 @@ __global__ __launch_bounds__(256) void k_reduce_gram(const float* __restrict__ p
                         si += pim[q][kp];
                     }
                 if (real) si = 0.0f;
-                Yr[o0 + f] = sr;
-                Yi[o0 + f] = si;
-                const int i = f / L, j = f % L;
-                tile[i * W + j] = j < lc ? make_float2(sr, si) : make_float2(0.f, 0.f);
+                const int i = f / ny, j = f % ny;
+                const long long o = (long long)(c0 + i) * L + j;
+                Yr[o] = sr;
+                Yi[o] = si;
+                if (j < W) tile[i * W + j] = j < lc ? make_float2(sr, si) : make_float2(0.f, 0.f);
             }
         }
         __syncthreads();
         if (gb.work) gram_rows<B, W>(tile, nr, gb.a0, gb.b0, gr, gi);
     }
     gram_store<B>(gb, L, s, w, nsplit, part, gr, gi);
+}
+
+// The split parts of a narrow product summed into Y (columns below the
+// device width `width`, or all L) and the partial Grams of its live columns.
+__global__ __launch_bounds__(256) void k_reduce_gram(const float* __restrict__ parts, int ksplit, int m, int L,
+                                                     int nslices, int real_first, int real_last,
+                                                     float* __restrict__ yr, float* __restrict__ yi,
+                                                     const int* __restrict__ lact, double2* __restrict__ part,
+                                                     int nsplit, const int* __restrict__ gate,
+                                                     const int* __restrict__ width)
+{
+    if (gate && *gate == 0) return;
+    __shared__ float2 tile[kGramChunk * kGramW];
+    const int la = lact[blockIdx.y];
+    const int ny = width ? max(min(*width, L), min(la, L)) : L;  // columns of Y written
+    switch (gram_edge(la)) {
+        case 1:
+            reduce_gram_body<1>(parts, ksplit, m, L, ny, nslices, real_first, real_last, yr, yi, la, part, nsplit,
+                                tile);
+            break;
+        case 2:
+            reduce_gram_body<2>(parts, ksplit, m, L, ny, nslices, real_first, real_last, yr, yi, la, part, nsplit,
+                                tile);
+            break;
+        default:
+            reduce_gram_body<3>(parts, ksplit, m, L, ny, nslices, real_first, real_last, yr, yi, la, part, nsplit,
+                                tile);
+            break;
+    }
 }
 
 // Per slice: G = sum of the partial Grams (fixed order, upper triangle); in
@@ -314,8 +359,9 @@ __global__ __launch_bounds__(kCholThreads) void k_chol(const double2* __restrict
                                                        const int* __restrict__ lact, int pass, float* __restrict__ rir,
                                                        float* __restrict__ rii, double2* __restrict__ rtot,
                                                        float* __restrict__ rhr, float* __restrict__ rhi,
-                                                       int* __restrict__ status)
+                                                       int* __restrict__ status, const int* __restrict__ gate)
 {
+    if (gate && *gate == 0) return;
     extern __shared__ double2 sh[];
     double2* R = sh;            // L x L (R, for the Rtot product)
     double2* X = sh + L * L;    // L x L (Rtot)
@@ -333,11 +379,12 @@ __global__ __launch_bounds__(kCholThreads) void k_chol(const double2* __restrict
     // G = the sum of the partials in the fixed order w = 0, 1, ... (upper
     // triangle; one entry per thread with all of its partials in flight),
     // staged in R
-    const int nup = L * (L + 1) / 2;
+    // (only the la x la live block: the rest of the layout stays unread)
+    const int nup = la * (la + 1) / 2;
     for (int e = tid; e < nup; e += nt) {
         int a = 0, r = e;
-        while (r >= L - a) {
-            r -= L - a;
+        while (r >= la - a) {
+            r -= la - a;
             ++a;
         }
         const int o = a * L + a + r;
@@ -375,7 +422,7 @@ __global__ __launch_bounds__(kCholThreads) void k_chol(const double2* __restrict
         const int a0 = kPanel * wave + u;
         ea[u] = (a0 < L && b < L) ? a0 : L;  // L: no entry
         vr[u] = vi[u] = 0.0;
-        if (ea[u] < L && b >= ea[u]) {
+        if (ea[u] < la && b < la && b >= ea[u]) {
             const double2 g = R[ea[u] * L + b];
             vr[u] = g.x + (ea[u] == b && b < la ? sd : 0.0);
             vi[u] = g.y;
@@ -439,8 +486,9 @@ __global__ __launch_bounds__(kCholThreads) void k_chol(const double2* __restrict
             }
         }
     };
-    const int npan = (L + kPanel - 1) / kPanel;
-    if (wave == 0) factor(0, 0);
+    // panels past the live block are not swept: their rows end as the identity
+    const int npan = (la + kPanel - 1) / kPanel;
+    if (wave == 0 && npan > 0) factor(0, 0);
     __syncthreads();
     for (int p = 0; p + 1 < npan; ++p) {
         if (wave > p && wave < npan) {
@@ -457,7 +505,12 @@ __global__ __launch_bounds__(kCholThreads) void k_chol(const double2* __restrict
         if (a < L) {
             const long long o = (long long)s * L * L + b * L + a;
             double mr = vr[u], mi = vi[u];
-            if (b == a) {  // M_aa = 1 / R_aa (R_aa real)
+            if (a >= la) {  // outside the live block: the identity
+                mr = b == a ? 1.0 : 0.0;
+                mi = 0.0;
+                vr[u] = b == a ? 1.0 : 0.0;
+                vi[u] = 0.0;
+            } else if (b == a) {  // M_aa = 1 / R_aa (R_aa real)
                 mr = 1.0 / vr[u];
                 mi = 0.0;
             }
@@ -516,8 +569,9 @@ __global__ __launch_bounds__(256) void k_rsvd_check(const float2* __restrict__ c
                                                     const int* __restrict__ lact, const int* __restrict__ prefb,
                                                     const int* __restrict__ status, int L, double tau,
                                                     float* __restrict__ tr, float* __restrict__ ti,
-                                                    int* __restrict__ fallback, int* __restrict__ rank)
+                                                    int* __restrict__ fallback, int* __restrict__ rank, const int* __restrict__ gate)
 {
+    if (gate && *gate == 0) return;
     __shared__ double scale[64];
     __shared__ int above;
     const int s = blockIdx.x, tid = threadIdx.x;
@@ -539,9 +593,11 @@ __global__ __launch_bounds__(256) void k_rsvd_check(const float2* __restrict__ c
         scale[j] = (j < lact[s] && sg[j] > tau) ? (sg[j] - tau) / sg[j] : 0.0;
     __syncthreads();
     (void)above;
-    // C and V of the slice staged in LDS (column-major, L x L each)
+    // C and V of the slice staged in LDS (column-major, L x L each); T is
+    // formed on the live la x la block and zero elsewhere
+    const int la = min(lact[s], L);
     __shared__ float2 sC[kMaxL * kMaxL], sV[kMaxL * kMaxL];
-    for (int e = tid; e < L * L; e += blockDim.x) {
+    for (int e = tid; e < L * la; e += blockDim.x) {
         sC[e] = cols[(long long)s * L * L + e];
         sV[e] = vr[(long long)s * L * L + e];
     }
@@ -549,7 +605,8 @@ __global__ __launch_bounds__(256) void k_rsvd_check(const float2* __restrict__ c
     for (int e = tid; e < L * L; e += blockDim.x) {
         const int a = e / L, b = e % L;
         double vr_ = 0.0, vi_ = 0.0;
-        for (int j = 0; j < L; ++j) {
+        const int nj = (a < la && b < la) ? la : 0;  // zero outside the live block
+        for (int j = 0; j < nj; ++j) {
             if (scale[j] == 0.0) continue;
             const float2 c = sC[j * L + a], v = sV[j * L + b];  // C(a,j) conj(V(b,j))
             vr_ += scale[j] * ((double)c.x * v.x + (double)c.y * v.y);
@@ -562,18 +619,28 @@ __global__ __launch_bounds__(256) void k_rsvd_check(const float2* __restrict__ c
 
 // ---------------------------------------------------- a posteriori check --
 // column-major L x L (float2) to planar row-major L x L, per slice
+// (and a second pair src2 -> re2, im2 in the same launch when src2 is given)
 __global__ __launch_bounds__(256) void k_cm_to_planar(const float2* __restrict__ src, float* __restrict__ re,
-                                                      float* __restrict__ im, int L, int nslices)
+                                                      float* __restrict__ im, int L, int nslices, const int* __restrict__ gate,
+                                                      const float2* __restrict__ src2, float* __restrict__ re2,
+                                                      float* __restrict__ im2)
 {
+    if (gate && *gate == 0) return;
     const long long total = (long long)nslices * L * L;
     for (long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x; e < total;
          e += (long long)gridDim.x * blockDim.x) {
         const long long s = e / ((long long)L * L);
         const int r = (int)(e % ((long long)L * L));
         const int i = r / L, j = r % L;
-        const float2 v = src[s * L * L + (long long)j * L + i];
+        const long long o = s * L * L + (long long)j * L + i;
+        const float2 v = src[o];
         re[e] = v.x;
         im[e] = v.y;
+        if (src2) {
+            const float2 w = src2[o];
+            re2[e] = w.x;
+            im2[e] = w.y;
+        }
     }
 }
 
@@ -590,8 +657,9 @@ __global__ __launch_bounds__(256) void k_accuracy_part(const float* __restrict__
                                                        const float* __restrict__ t2r, const float* __restrict__ t2i,
                                                        const double* __restrict__ sigma,
                                                        const int* __restrict__ lact, int m, int L, double tau,
-                                                       double* __restrict__ part)
+                                                       double* __restrict__ part, const int* __restrict__ gate)
 {
+    if (gate && *gate == 0) return;
     __shared__ double red[256];
     __shared__ unsigned char keep[kMaxL];
     const int w = blockIdx.x, s = blockIdx.y, tid = threadIdx.x;
@@ -623,12 +691,10 @@ __global__ __launch_bounds__(256) void k_accuracy_part(const float* __restrict__
 
 // Per slice: the partial sums in band order, and the test against the kept
 // shrunk energy (or the slice's Frobenius norm squared with fro2)
-__global__ __launch_bounds__(64) void k_accuracy(const double* __restrict__ part, const double* __restrict__ sigma,
-                                                 const int* __restrict__ lact, const double* __restrict__ fro2, int L,
-                                                 double tau, double delta, int* __restrict__ bad, int nslices)
+__device__ __forceinline__ int slice_inaccurate(const double* __restrict__ part, const double* __restrict__ sigma,
+                                                const int* __restrict__ lact, const double* __restrict__ fro2, int L,
+                                                double tau, double delta, int s)
 {
-    const int s = blockIdx.x * blockDim.x + threadIdx.x;
-    if (s >= nslices) return;
     double num = 0.0;
     for (int w = 0; w < kAccSplit; ++w) num += part[(long long)s * kAccSplit + w];
     const double* sg = sigma + (long long)s * L;
@@ -638,7 +704,18 @@ __global__ __launch_bounds__(64) void k_accuracy(const double* __restrict__ part
     if (fro2 && den > 0.0) den = fmax(den, fro2[s]);
     // NaN-safe: anything but a finite residual within the bound fails
     // (num is 0 when no triplet is kept, and 0 <= 0 passes)
-    bad[s] = !(num <= delta * delta * den) ? 1 : 0;
+    return !(num <= delta * delta * den) ? 1 : 0;
+}
+
+__global__ __launch_bounds__(64) void k_accuracy(const double* __restrict__ part, const double* __restrict__ sigma,
+                                                 const int* __restrict__ lact, const double* __restrict__ fro2, int L,
+                                                 double tau, double delta, int* __restrict__ bad, int nslices,
+                                                 const int* __restrict__ gate)
+{
+    if (gate && *gate == 0) return;
+    const int s = blockIdx.x * blockDim.x + threadIdx.x;
+    if (s >= nslices) return;
+    bad[s] = slice_inaccurate(part, sigma, lact, fro2, L, tau, delta, s);
 }
 
 // ---------------------------------------------------------------- features --
@@ -761,9 +838,10 @@ __global__ __launch_bounds__(256) void k_features(const double* __restrict__ par
 // rows with skip[r] != 0 are left alone.
 __global__ __launch_bounds__(256) void k_sigma_top(const double* __restrict__ sig, int P, const int* __restrict__ lact,
                                                    const int* __restrict__ map, const int* __restrict__ skip,
-                                                   float* __restrict__ out)
+                                                   float* __restrict__ out, const int* __restrict__ count)
 {
     const int r = blockIdx.x;
+    if (count && r >= *count) return;
     if (skip && skip[r]) return;
     const int valid = lact ? min(lact[r], P) : P;
     const double* sv = sig + (long long)r * P;
@@ -977,9 +1055,10 @@ __global__ __launch_bounds__(256) void k_adam(float* __restrict__ p, const float
 // copy slices idx[0..cnt) of a planar stack into / out of a compact stack
 __global__ __launch_bounds__(256) void k_gather(const float* __restrict__ sr, const float* __restrict__ si,
                                                 float* __restrict__ dr, float* __restrict__ di,
-                                                const int* __restrict__ idx, int cnt, long long per, int scatter)
+                                                const int* __restrict__ idx, int cnt, long long per, int scatter,
+                                                const int* __restrict__ count)
 {
-    const long long total = (long long)cnt * per;
+    const long long total = (long long)(count ? min(*count, cnt) : cnt) * per;
     for (long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x; e < total;
          e += (long long)gridDim.x * blockDim.x) {
         const long long c = e / per, o = e % per;
@@ -994,6 +1073,150 @@ __global__ __launch_bounds__(256) void k_gather(const float* __restrict__ sr, co
     }
 }
 
+// ------------------------------------------------- device-side control --
+// The decisions of the learned prox that depend on device data are taken by
+// these single-workgroup kernels; later launches read their results (gates,
+// widths, counts), so a call never waits for the host.
+
+// OR of v over the workgroup (every thread gets it)
+__device__ __forceinline__ int block_or(int v) { return __syncthreads_or(v); }
+
+// Common sketch width of an attempt: L = the widest l over the slices not
+// already sent to the full SVD, rounded up to 8, at most max_rank (0: none);
+// every such slice then uses l = min(L, p) columns and kpred = max(kpred,
+// l - oversample).  set_fb: fallback starts as the pre-sent slices (all
+// slices when L = 0).
+// gate_in (optional) = 0 leaves L = 0 and the attempt's gate closed.
+__global__ __launch_bounds__(256) void k_width(int* __restrict__ kpred, int* __restrict__ lact,
+                                               const int* __restrict__ prefb, int* __restrict__ fb, int nslices,
+                                               int p, int oversample, int max_rank, const int* __restrict__ gate_in,
+                                               int* __restrict__ ctl_L, int* __restrict__ ctl_gate, int set_fb)
+{
+    __shared__ int red[256];
+    const int tid = threadIdx.x;
+    const bool open = !gate_in || *gate_in != 0;
+    int m = 0;
+    for (int q = tid; q < nslices; q += blockDim.x) {
+        if (set_fb) fb[q] = prefb[q];
+        if (!prefb[q]) m = max(m, lact[q]);
+    }
+    red[tid] = m;
+    __syncthreads();
+    for (int w = blockDim.x / 2; w > 0; w >>= 1) {
+        if (tid < w) red[tid] = max(red[tid], red[tid + w]);
+        __syncthreads();
+    }
+    const int lmax = red[0];
+    const int L = (open && lmax > 0) ? min(((lmax + 7) / 8) * 8, max_rank) : 0;
+    if (set_fb && L == 0)  // no sketch at all: every slice takes the full SVD
+        for (int q = tid; q < nslices; q += blockDim.x) fb[q] = 1;
+    if (L > 0)
+        for (int q = tid; q < nslices; q += blockDim.x)
+            if (!prefb[q]) {
+                lact[q] = min(L, p);
+                kpred[q] = max(kpred[q], lact[q] - oversample);
+            }
+    if (tid == 0) {
+        *ctl_L = L;
+        *ctl_gate = L > 0 ? 1 : 0;
+    }
+}
+
+// Wide retry: slices whose count check failed below the widest sketch get
+// kpred = max_rank - oversample, l = kpred + oversample (at most p); the
+// retry gate opens when there is one and the first attempt ran.
+__global__ __launch_bounds__(256) void k_retry(const int* __restrict__ fb, const int* __restrict__ prefb,
+                                               int* __restrict__ kpred, int* __restrict__ lact, int nslices, int p,
+                                               int oversample, int max_rank, const int* __restrict__ gate_in,
+                                               int* __restrict__ ctl_retry)
+{
+    const int kwide = min(max(max_rank - oversample, 0), p), lwide = min(kwide + oversample, p);
+    const bool open = *gate_in != 0;
+    int any = 0;
+    for (int q = threadIdx.x; q < nslices; q += blockDim.x)
+        if (open && fb[q] && !prefb[q] && lact[q] < lwide && kpred[q] < kwide) {
+            kpred[q] = kwide;
+            lact[q] = lwide;
+            any = 1;
+        }
+    any = block_or(any);
+    if (threadIdx.x == 0) *ctl_retry = any;
+}
+
+// End of an accuracy round (when it ran): next = some slice still inaccurate
+// and not sent to the full SVD, unless this was the last round, whose
+// inaccurate slices join the fallback set.
+// The verdict of each slice (bad: see k_accuracy) is formed here from the
+// partial residual sums when part is given.
+__global__ __launch_bounds__(256) void k_round(int* __restrict__ bad, int* __restrict__ fb, int nslices,
+                                               const int* __restrict__ cur, int* __restrict__ next, int last,
+                                               const double* __restrict__ part, const double* __restrict__ sigma,
+                                               const int* __restrict__ lact, const double* __restrict__ fro2, int L,
+                                               double tau, double delta)
+{
+    if (*cur == 0) {
+        if (next && threadIdx.x == 0) *next = 0;
+        return;
+    }
+    if (part)
+        for (int q = threadIdx.x; q < nslices; q += blockDim.x) bad[q] = slice_inaccurate(part, sigma, lact, fro2, L, tau,
+                                                                                          delta, q);
+    __syncthreads();
+    int any = 0;
+    for (int q = threadIdx.x; q < nslices; q += blockDim.x) any |= (bad[q] && !fb[q]) ? 1 : 0;
+    any = block_or(any);
+    if (last && any)
+        for (int q = threadIdx.x; q < nslices; q += blockDim.x)
+            if (bad[q]) fb[q] = 1;
+    if (next && threadIdx.x == 0) *next = (!last && any) ? 1 : 0;
+}
+
+// idx[0..count) = the fallback slices in increasing order; count to *count
+__global__ __launch_bounds__(64) void k_compact(const int* __restrict__ fb, int nslices, int* __restrict__ idx,
+                                                int* __restrict__ count)
+{
+    if (threadIdx.x != 0) return;
+    int c = 0;
+    for (int q = 0; q < nslices; ++q)
+        if (fb[q]) idx[c++] = q;
+    *count = c;
+}
+
+// the full-SVD counts and sweeps of the compact fallback slices back to
+// their slices (info: 0 for the others)
+__global__ __launch_bounds__(256) void k_fb_results(const int* __restrict__ idx, const int* __restrict__ count,
+                                                    const int* __restrict__ crank, const int* __restrict__ cinfo,
+                                                    const int* __restrict__ fb, int* __restrict__ rank,
+                                                    int* __restrict__ info, int nslices)
+{
+    const int c = *count;
+    for (int q = threadIdx.x; q < nslices; q += blockDim.x)
+        if (info && !fb[q]) info[q] = 0;
+    __syncthreads();
+    for (int j = threadIdx.x; j < c; j += blockDim.x) {
+        rank[idx[j]] = crank[j];
+        if (info) info[idx[j]] = cinfo[j];
+    }
+}
+
+// dst = src (planar, n floats per plane) when the gate is open
+__global__ __launch_bounds__(256) void k_copy_planes(const float* __restrict__ sr, const float* __restrict__ si,
+                                                     float* __restrict__ dr, float* __restrict__ di, long long n,
+                                                     const int* __restrict__ gate)
+{
+    if (gate && *gate == 0) return;
+    for (long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x; e < n; e += (long long)gridDim.x * blockDim.x) {
+        dr[e] = sr[e];
+        di[e] = si[e];
+    }
+}
+
+__global__ __launch_bounds__(256) void k_fill_int(int* __restrict__ p, long long n, int v)
+{
+    for (long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x; e < n; e += (long long)gridDim.x * blockDim.x)
+        p[e] = v;
+}
+
 inline int blocks_for(long long n, int tpb, int cap = 8192)
 {
     long long b = (n + tpb - 1) / tpb;
@@ -1005,10 +1228,10 @@ inline int blocks_for(long long n, int tpb, int cap = 8192)
 int mlp_param_count() { return MlpOffsets::COUNT; }
 
 hipError_t launch_sketch(float* omr, float* omi, int n, int L, const int* lact, int nslices, int n3,
-                         unsigned long long seed, WarmBasis warm, hipStream_t st)
+                         unsigned long long seed, WarmBasis warm, hipStream_t st, const int* gate)
 {
     k_sketch<<<blocks_for((long long)nslices * n * L, 256), 256, 0, st>>>(omr, omi, n, L, lact, nslices, n3, seed,
-                                                                          warm);
+                                                                          warm, gate);
     return hipGetLastError();
 }
 
@@ -1018,8 +1241,9 @@ hipError_t launch_sketch(float* omr, float* omi, int n, int L, const int* lact, 
 __global__ __launch_bounds__(256) void k_store_basis(const float* __restrict__ zr, const float* __restrict__ zi, int n,
                                                      int L, const int* __restrict__ lact, const int* __restrict__ fb,
                                                      int nslices, float* __restrict__ outr, float* __restrict__ outi,
-                                                     int ld, int* __restrict__ cols)
+                                                     int ld, int* __restrict__ cols, const int* __restrict__ gate)
 {
+    if (gate && *gate == 0) return;
     const long long total = (long long)nslices * n * ld;
     for (long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x; e < total;
          e += (long long)gridDim.x * blockDim.x) {
@@ -1040,52 +1264,34 @@ __global__ __launch_bounds__(256) void k_store_basis(const float* __restrict__ z
 }
 
 hipError_t launch_store_basis(const float* zr, const float* zi, int n, int L, const int* lact, const int* fb,
-                              int nslices, float* outr, float* outi, int ld, int* cols, hipStream_t st)
+                              int nslices, float* outr, float* outi, int ld, int* cols, hipStream_t st,
+                              const int* gate)
 {
     k_store_basis<<<blocks_for((long long)nslices * n * ld, 256), 256, 0, st>>>(zr, zi, n, L, lact, fb, nslices,
-                                                                                outr, outi, ld, cols);
+                                                                                outr, outi, ld, cols, gate);
     return hipGetLastError();
 }
 
 int gram_split(int m) { return m >= 1024 ? kMaxGramSplit : (m >= 256 ? 8 : 1); }
 
-template <int B>
-void launch_gram(const float* yr, const float* yi, int m, int L, const int* lact, int nslices, double2* part, int ns,
-                 hipStream_t st)
-{
-    k_gram<B><<<dim3(ns, nslices), 256, 0, st>>>(yr, yi, m, L, lact, part, ns);
-}
-
 hipError_t launch_reduce_gram(const float* parts, int ksplit, int m, int L, int nslices, int real_first, int real_last,
-                              float* yr, float* yi, const int* lact, double2* part, hipStream_t st)
+                              float* yr, float* yi, const int* lact, double2* part, hipStream_t st,
+                              const int* gate, const int* width)
 {
     if (L > kMaxL || ksplit < 1 || ksplit > kMaxParts) return hipErrorInvalidValue;
     const int ns = gram_split(m);
-    const dim3 g(ns, nslices);
-    if (L <= 22)
-        k_reduce_gram<1><<<g, 256, 0, st>>>(parts, ksplit, m, L, nslices, real_first, real_last, yr, yi, lact, part, ns);
-    else if (L <= 44)
-        k_reduce_gram<2><<<g, 256, 0, st>>>(parts, ksplit, m, L, nslices, real_first, real_last, yr, yi, lact, part, ns);
-    else
-        k_reduce_gram<3><<<g, 256, 0, st>>>(parts, ksplit, m, L, nslices, real_first, real_last, yr, yi, lact, part, ns);
+    k_reduce_gram<<<dim3(ns, nslices), 256, 0, st>>>(parts, ksplit, m, L, nslices, real_first, real_last, yr, yi, lact,
+                                                     part, ns, gate, width);
     return hipGetLastError();
 }
 
 hipError_t launch_cholqr_pass(const float* yr, const float* yi, int m, int L, const int* lact, int nslices,
                               int pass, double2* part, float* rir, float* rii, double2* rtot, float* rhr,
-                              float* rhi, int* status, hipStream_t st, bool gram_ready)
+                              float* rhi, int* status, hipStream_t st, bool gram_ready, const int* gate)
 {
     if (L > kMaxL) return hipErrorInvalidValue;
     const int ns = gram_split(m);
-    // block edge B: the upper triangle of ceil(L/B) blocks fits 256 threads
-    if (!gram_ready) {
-        if (L <= 22)
-            launch_gram<1>(yr, yi, m, L, lact, nslices, part, ns, st);
-        else if (L <= 44)
-            launch_gram<2>(yr, yi, m, L, lact, nslices, part, ns, st);
-        else
-            launch_gram<3>(yr, yi, m, L, lact, nslices, part, ns, st);
-    }
+    if (!gram_ready) k_gram<<<dim3(ns, nslices), 256, 0, st>>>(yr, yi, m, L, lact, part, ns, gate);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     const size_t lds = 2 * (size_t)L * L * sizeof(double2);
@@ -1093,7 +1299,7 @@ hipError_t launch_cholqr_pass(const float* yr, const float* yi, int m, int L, co
         e = hipFuncSetAttribute((const void*)k_chol, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
         if (e != hipSuccess) return e;
     }
-    k_chol<<<nslices, kCholThreads, lds, st>>>(part, ns, L, lact, pass, rir, rii, rtot, rhr, rhi, status);
+    k_chol<<<nslices, kCholThreads, lds, st>>>(part, ns, L, lact, pass, rir, rii, rtot, rhr, rhi, status, gate);
     return hipGetLastError();
 }
 
@@ -1104,30 +1310,33 @@ size_t cholqr_part_bytes(int m, int L, int nslices)
 
 hipError_t launch_rsvd_check(const float2* cols, const double* sigma, const float2* vr, const int* kpred,
                              const int* lact, const int* prefb, const int* status, int L, double tau, Planes T,
-                             int* fallback, int* rank, int nslices, hipStream_t st)
+                             int* fallback, int* rank, int nslices, hipStream_t st, const int* gate)
 {
     k_rsvd_check<<<nslices, 256, 0, st>>>(cols, sigma, vr, kpred, lact, prefb, status, L, tau, T.re, T.im, fallback,
-                                          rank);
+                                          rank, gate);
     return hipGetLastError();
 }
 
-hipError_t launch_cm_to_planar(const float2* src, Planes dst, int L, int nslices, hipStream_t st)
+hipError_t launch_cm_to_planar(const float2* src, Planes dst, int L, int nslices, hipStream_t st, const int* gate,
+                               const float2* src2, Planes dst2)
 {
-    k_cm_to_planar<<<blocks_for((long long)nslices * L * L, 256), 256, 0, st>>>(src, dst.re, dst.im, L, nslices);
+    k_cm_to_planar<<<blocks_for((long long)nslices * L * L, 256), 256, 0, st>>>(src, dst.re, dst.im, L, nslices,
+                                                                                gate, src2, dst2.re, dst2.im);
     return hipGetLastError();
 }
 
 size_t accuracy_part_bytes(int nslices) { return align_up((size_t)nslices * kAccSplit * sizeof(double)); }
 
 hipError_t launch_accuracy(Planes t1, Planes t2, const double* sigma, const int* lact, const double* fro2, int m,
-                           int L, double tau, double delta, int* bad, int nslices, double* part, hipStream_t st)
+                           int L, double tau, double delta, int* bad, int nslices, double* part, hipStream_t st,
+                           const int* gate)
 {
     // part: nslices x kAccSplit doubles (accuracy_part_bytes)
     k_accuracy_part<<<dim3(kAccSplit, nslices), 256, 0, st>>>(t1.re, t1.im, t2.re, t2.im, sigma, lact, m, L, tau,
-                                                              part);
+                                                              part, gate);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    k_accuracy<<<(nslices + 63) / 64, 64, 0, st>>>(part, sigma, lact, fro2, L, tau, delta, bad, nslices);
+    k_accuracy<<<(nslices + 63) / 64, 64, 0, st>>>(part, sigma, lact, fro2, L, tau, delta, bad, nslices, gate);
     return hipGetLastError();
 }
 
@@ -1149,10 +1358,10 @@ hipError_t launch_features(const float* yr, const float* yi, int m, int n, int n
 }
 
 hipError_t launch_sigma_top(const double* sig, int P, const int* lact, const int* map, const int* skip, int rows,
-                            float* out, hipStream_t st)
+                            float* out, hipStream_t st, const int* count)
 {
     if (rows <= 0) return hipSuccess;
-    k_sigma_top<<<rows, 256, 0, st>>>(sig, P, lact, map, skip, out);
+    k_sigma_top<<<rows, 256, 0, st>>>(sig, P, lact, map, skip, out, count);
     return hipGetLastError();
 }
 
@@ -1199,11 +1408,73 @@ hipError_t launch_adam(float* p, const float* g, float* m, float* v, int count, 
     return hipGetLastError();
 }
 
+hipError_t launch_width(int* kpred, int* lact, const int* prefb, int* fb, int nslices, int p, int oversample,
+                        int max_rank, const int* gate_in, int* ctl_L, int* ctl_gate, bool set_fb, hipStream_t st)
+{
+    k_width<<<1, 256, 0, st>>>(kpred, lact, prefb, fb, nslices, p, oversample, max_rank, gate_in, ctl_L, ctl_gate,
+                               set_fb ? 1 : 0);
+    return hipGetLastError();
+}
+
+hipError_t launch_retry(const int* fb, const int* prefb, int* kpred, int* lact, int nslices, int p, int oversample,
+                        int max_rank, const int* gate_in, int* ctl_retry, hipStream_t st)
+{
+    k_retry<<<1, 256, 0, st>>>(fb, prefb, kpred, lact, nslices, p, oversample, max_rank, gate_in, ctl_retry);
+    return hipGetLastError();
+}
+
+hipError_t launch_round(int* bad, int* fb, int nslices, const int* cur, int* next, bool last, hipStream_t st)
+{
+    k_round<<<1, 256, 0, st>>>(bad, fb, nslices, cur, next, last ? 1 : 0, nullptr, nullptr, nullptr, nullptr, 0, 0.0,
+                               0.0);
+    return hipGetLastError();
+}
+
+hipError_t launch_accuracy_round(Planes t1, Planes t2, const double* sigma, const int* lact, const double* fro2, int m,
+                                 int L, double tau, double delta, int* bad, int nslices, double* part, int* fb,
+                                 const int* cur, int* next, bool last, hipStream_t st)
+{
+    k_accuracy_part<<<dim3(kAccSplit, nslices), 256, 0, st>>>(t1.re, t1.im, t2.re, t2.im, sigma, lact, m, L, tau,
+                                                              part, cur);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    k_round<<<1, 256, 0, st>>>(bad, fb, nslices, cur, next, last ? 1 : 0, part, sigma, lact, fro2, L, tau, delta);
+    return hipGetLastError();
+}
+
+hipError_t launch_compact(const int* fb, int nslices, int* idx, int* count, hipStream_t st)
+{
+    k_compact<<<1, 64, 0, st>>>(fb, nslices, idx, count);
+    return hipGetLastError();
+}
+
+hipError_t launch_fb_results(const int* idx, const int* count, const int* crank, const int* cinfo, const int* fb,
+                             int* rank, int* info, int nslices, hipStream_t st)
+{
+    k_fb_results<<<1, 256, 0, st>>>(idx, count, crank, cinfo, fb, rank, info, nslices);
+    return hipGetLastError();
+}
+
+hipError_t launch_copy_planes(const float* sr, const float* si, float* dr, float* di, long long n, const int* gate,
+                              hipStream_t st)
+{
+    k_copy_planes<<<blocks_for(n, 256), 256, 0, st>>>(sr, si, dr, di, n, gate);
+    return hipGetLastError();
+}
+
+hipError_t launch_fill_int(int* p, long long n, int v, hipStream_t st)
+{
+    if (n <= 0) return hipSuccess;
+    k_fill_int<<<blocks_for(n, 256), 256, 0, st>>>(p, n, v);
+    return hipGetLastError();
+}
+
 hipError_t launch_gather(const float* sr, const float* si, float* dr, float* di, const int* idx, int cnt,
-                         long long per, bool scatter, hipStream_t st)
+                         long long per, bool scatter, hipStream_t st, const int* count)
 {
     if (cnt <= 0) return hipSuccess;
-    k_gather<<<blocks_for((long long)cnt * per, 256), 256, 0, st>>>(sr, si, dr, di, idx, cnt, per, scatter ? 1 : 0);
+    k_gather<<<blocks_for((long long)cnt * per, 256), 256, 0, st>>>(sr, si, dr, di, idx, cnt, per, scatter ? 1 : 0,
+                                                                    count);
     return hipGetLastError();
 }
 

@@ -88,6 +88,17 @@ struct CgemmArgs {
     const int* kdyn;     // optional per-slice inner dimension (<= k), device
     int ksplit;          // > 1: the inner dimension is cut in ksplit parts (FP32 only) whose
     float* part;         // products go to part (re: [ksplit][nslices][m][n], then im) and are summed
+    // Device-side values for launches sized on the host for their largest
+    // shape (all optional): gate 0 makes the launch do nothing; dyn_k caps k;
+    // dyn_m, dyn_n are the rows and columns computed (m and n keep the layout
+    // of the output and split parts; outputs past them are undefined: left
+    // alone or written with zeros); dyn_ns is the count of live slices (the
+    // others are left alone).
+    const int* gate;
+    const int* dyn_m;
+    const int* dyn_n;
+    const int* dyn_k;
+    const int* dyn_ns;
 };
 // bytes of the split-K partial buffer of a product
 size_t splitk_bytes(int ksplit, int nslices, int m, int n);
@@ -129,6 +140,9 @@ struct JacobiArgs {
     float2* qout;     // optional: accumulated rotations V, column-major P x P per slice
     int whole;        // 1: one workgroup per slice whenever the slice fits in LDS
     const int* count; // optional device count of live slices (<= nslices); the rest are skipped
+    const int* gate;  // optional device flag: 0 makes the call do nothing
+    const int* pdyn;  // optional device cap on the columns swept (one workgroup per slice only; the
+                      // layout keeps n, the columns beyond are left as they are)
 };
 // Batched per-slice SVDs (whole slice in LDS, R = max(m, n) <= 128) and
 // shrinkage over (item, slice) units.
@@ -170,7 +184,7 @@ hipError_t launch_tsvd_finish(const float2* cols, const double* sigma, const flo
 
 // columns w_j of each slice scaled by sqrt((1 - tau/sigma_j)_+) / sigma_j; keep = #{sigma_j > tau}
 hipError_t launch_shrink(float* wr, float* wi, const double* sigma, int* keep, int R, int P, int nslices, double tau,
-                         hipStream_t s);
+                         hipStream_t s, const int* count = nullptr);
 // (1/n3) sum over all n3 slices of the singular values, from the half spectrum
 hipError_t launch_tnn_reduce(const double* sigma, int nslices, int P, int n3, double* out, hipStream_t s);
 
@@ -186,38 +200,42 @@ struct WarmBasis {
 };
 // Sketch Om (n x L per slice): the warm columns where given, else Gaussian
 hipError_t launch_sketch(float* omr, float* omi, int n, int L, const int* lact, int nslices, int n3,
-                         unsigned long long seed, WarmBasis warm, hipStream_t s);
+                         unsigned long long seed, WarmBasis warm, hipStream_t s, const int* gate = nullptr);
 hipError_t launch_store_basis(const float* zr, const float* zi, int n, int L, const int* lact, const int* fb,
-                              int nslices, float* outr, float* outi, int ld, int* cols, hipStream_t st);
+                              int nslices, float* outr, float* outi, int ld, int* cols, hipStream_t st,
+                              const int* gate = nullptr);
 size_t cholqr_part_bytes(int m, int L, int nslices);
 // one CholeskyQR pass on Y (m x L per slice): Gram in FP64, Cholesky, Rinv (FP32 planar);
 // rtot/rhr/rhi optional (accumulated R and, after pass 1, R^* restricted to the active block)
 // gram_ready: the Gram partials of Y are already in part (launch_reduce_gram)
 hipError_t launch_cholqr_pass(const float* yr, const float* yi, int m, int L, const int* lact, int nslices, int pass,
                               double2* part, float* rir, float* rii, double2* rtot, float* rhr, float* rhi,
-                              int* status, hipStream_t s, bool gram_ready = false);
+                              int* status, hipStream_t s, bool gram_ready = false, const int* gate = nullptr);
 // the split parts of a narrow product summed in the fixed order kp = 0, 1, ...
 // into Y = (yr, yi) (m x L per slice, row-major, slice stride m L; imaginary
 // plane zero on the real slices), and the FP64 Gram partials of Y that
 // launch_cholqr_pass would form, in its layout (part)
 hipError_t launch_reduce_gram(const float* parts, int ksplit, int m, int L, int nslices, int real_first, int real_last,
-                              float* yr, float* yi, const int* lact, double2* part, hipStream_t s);
+                              float* yr, float* yi, const int* lact, double2* part, hipStream_t s,
+                              const int* gate = nullptr, const int* width = nullptr);
 // status: per-slice CholeskyQR breakdown flags (or null), OR-ed into fallback
 hipError_t launch_rsvd_check(const float2* cols, const double* sigma, const float2* vr, const int* kpred,
                              const int* lact, const int* prefb, const int* status, int L, double tau, Planes T,
-                             int* fallback, int* rank, int nslices, hipStream_t s);
-hipError_t launch_cm_to_planar(const float2* src, Planes dst, int L, int nslices, hipStream_t s);
+                             int* fallback, int* rank, int nslices, hipStream_t s, const int* gate = nullptr);
+hipError_t launch_cm_to_planar(const float2* src, Planes dst, int L, int nslices, hipStream_t s,
+                               const int* gate = nullptr, const float2* src2 = nullptr, Planes dst2 = Planes{});
 // part: accuracy_part_bytes(nslices) of workspace for the per-band partial sums
 size_t accuracy_part_bytes(int nslices);
 hipError_t launch_accuracy(Planes t1, Planes t2, const double* sigma, const int* lact, const double* fro2, int m,
-                           int L, double tau, double delta, int* bad, int nslices, double* part, hipStream_t st);
+                           int L, double tau, double delta, int* bad, int nslices, double* part, hipStream_t st,
+                           const int* gate = nullptr);
 // per-slice features; part: features_part_bytes(m, n, nslices) of scratch
 size_t features_part_bytes(int m, int n, int nslices);
 hipError_t launch_features(const float* yr, const float* yi, int m, int n, int n3, int nslices, double tau,
                            const int* prev, const float* prev_sigma, float* feats, double* part, double* fro2,
                            hipStream_t st);
 hipError_t launch_sigma_top(const double* sig, int P, const int* lact, const int* map, const int* skip, int rows,
-                            float* out, hipStream_t s);
+                            float* out, hipStream_t s, const int* count = nullptr);
 hipError_t launch_predict(const float* params, const float* feats, int nslices, int p, int fixed_rank, int oversample,
                           int L, int* kpred, int* lact, int* fallback, int* rank, hipStream_t s);
 hipError_t launch_mlp_forward(const float* params, const float* x, float* y, int batch, hipStream_t s);
@@ -227,7 +245,23 @@ hipError_t launch_mlp_loss_grad(const float* params, const float* x, const float
 hipError_t launch_adam(float* p, const float* g, float* m, float* v, int count, int step, float lr, float b1, float b2,
                        float eps, hipStream_t s);
 hipError_t launch_gather(const float* sr, const float* si, float* dr, float* di, const int* idx, int cnt, long long per,
-                         bool scatter, hipStream_t s);
+                         bool scatter, hipStream_t s, const int* count = nullptr);
+// device-side control of the learned prox (single-workgroup kernels; see learned.hip)
+hipError_t launch_width(int* kpred, int* lact, const int* prefb, int* fb, int nslices, int p, int oversample,
+                        int max_rank, const int* gate_in, int* ctl_L, int* ctl_gate, bool set_fb, hipStream_t s);
+hipError_t launch_retry(const int* fb, const int* prefb, int* kpred, int* lact, int nslices, int p, int oversample,
+                        int max_rank, const int* gate_in, int* ctl_retry, hipStream_t s);
+hipError_t launch_round(int* bad, int* fb, int nslices, const int* cur, int* next, bool last, hipStream_t s);
+// the a posteriori check of a round (when *cur) and the round's end (k_round) in two launches
+hipError_t launch_accuracy_round(Planes t1, Planes t2, const double* sigma, const int* lact, const double* fro2, int m,
+                                 int L, double tau, double delta, int* bad, int nslices, double* part, int* fb,
+                                 const int* cur, int* next, bool last, hipStream_t s);
+hipError_t launch_compact(const int* fb, int nslices, int* idx, int* count, hipStream_t s);
+hipError_t launch_fb_results(const int* idx, const int* count, const int* crank, const int* cinfo, const int* fb,
+                             int* rank, int* info, int nslices, hipStream_t s);
+hipError_t launch_copy_planes(const float* sr, const float* si, float* dr, float* di, long long n, const int* gate,
+                              hipStream_t s);
+hipError_t launch_fill_int(int* p, long long n, int v, hipStream_t s);
 
 // tp_tprod after its argument checks (check_tprod), on a caller-given workspace
 int check_tprod(const float* A, const float* B, const float* C, int n1, int n2, int l, int n3, int prec);
@@ -269,6 +303,11 @@ class TraceScope {
 // Called by a launcher: adds the algorithmic flops and HBM bytes of the
 // kernel it enqueues to the enclosing TraceScope (ignored when not tracing).
 void trace_work(double flops, double bytes);
+// A slice product whose gate or live sizes are device values: its work is
+// evaluated when the trace is collected, from the values then in device
+// memory (collect after each call for exact figures).
+void trace_gemm_dyn(const int* gate, const int* m, const int* n, const int* k, int hm, int hn, int hk, int nslices,
+                    int nreal);
 
 }  // namespace tp
 
