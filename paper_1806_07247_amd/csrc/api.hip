@@ -17,20 +17,40 @@ bool bad_slice(long long a, long long b) { return a * b >= (1LL << 31); }
 
 inline hipStream_t as_stream(void* s) { return reinterpret_cast<hipStream_t>(s); }
 
-// Workspace of tprod: half spectra of A, B and C (planar complex).
+// Workspace of tprod: half spectra of A, B and C (planar complex).  With
+// bf16 slice products, A and B are bf16 planes instead (hi re, hi im, and for
+// BF16X3 lo re, lo im): A as n1 rows of the inner index, B as l columns of
+// it, k-blocked and zero-padded to ld = n2 rounded up to the block length
+// the product reads (tp::SplitOut).
 struct TprodLayout {
     tp::Planes a, b, c;
+    unsigned short *ah, *bh;
+    int ld, np, bkl, variant;
 };
 
-tp::Arena tprod_arena(void* ws, size_t bytes, int n1, int n2, int l, int n3, TprodLayout* L)
+int bf16_planes(int prec) { return prec == TP_PREC_BF16X3 ? 4 : 2; }
+
+// real slices of the half spectrum: 0, and n3/2 for even n3
+int real_slices(int n3) { return (n3 % 2 == 0) ? 2 : 1; }
+
+tp::Arena tprod_arena(void* ws, size_t bytes, int n1, int n2, int l, int n3, int prec, TprodLayout* L)
 {
     const size_t h = (size_t)tp::half_slices(n3);
     tp::Arena ar(ws, bytes);
-    TprodLayout t;
-    t.a.re = ar.take<float>(h * n1 * n2);
-    t.a.im = ar.take<float>(h * n1 * n2);
-    t.b.re = ar.take<float>(h * n2 * l);
-    t.b.im = ar.take<float>(h * n2 * l);
+    TprodLayout t{};
+    if (prec == TP_PREC_FP32) {
+        t.a.re = ar.take<float>(h * n1 * n2);
+        t.a.im = ar.take<float>(h * n1 * n2);
+        t.b.re = ar.take<float>(h * n2 * l);
+        t.b.im = ar.take<float>(h * n2 * l);
+    } else {
+        t.np = bf16_planes(prec);
+        const int nreal = real_slices(n3);
+        t.variant = tp::bf16_plan(n1, l, n2, (int)h - nreal, nreal, &t.bkl);
+        t.ld = (n2 + t.bkl - 1) / t.bkl * t.bkl;
+        t.ah = ar.take<unsigned short>((size_t)t.np * h * n1 * t.ld);
+        t.bh = ar.take<unsigned short>((size_t)t.np * h * l * t.ld);
+    }
     t.c.re = ar.take<float>(h * n1 * l);
     t.c.im = ar.take<float>(h * n1 * l);
     if (L) *L = t;
@@ -430,9 +450,45 @@ int run_tprod(const float* A, const float* B, float* C, int n1, int n2, int l, i
               size_t workspace_bytes, hipStream_t s)
 {
     TprodLayout L;
-    tp::Arena ar = ::tprod_arena(workspace, workspace_bytes, n1, n2, l, n3, &L);
+    tp::Arena ar = ::tprod_arena(workspace, workspace_bytes, n1, n2, l, n3, prec, &L);
     if (!ar.ok) return TP_ERR_WORKSPACE;
     const int h = tp::half_slices(n3);
+    if (prec != TP_PREC_FP32) {
+        // step 1 into bf16 planes: A row-major (n1 x n2), B transposed (l x n2)
+        const long long pa = (long long)h * n1 * L.ld, pb = (long long)h * l * L.ld;
+        const int split = prec == TP_PREC_BF16X3 ? 1 : 0;
+        const tp::SplitOut oa{L.ah, pa, (long long)n1 * L.ld, n1, n2, L.ld, L.bkl, n2, 1, split};
+        const tp::SplitOut ob{L.bh, pb, (long long)l * L.ld, l, n2, L.ld, L.bkl, 1, l, split};
+        TP_LAUNCH(tp::K_RFFT, s, tp::launch_rfft_split(A, oa, n3, s));
+        TP_LAUNCH(tp::K_RFFT, s, tp::launch_rfft_split(B, ob, n3, s));
+        // step 2: slices 0 and (even n3) h-1 are real
+        tp::Bf16Args g{};
+        g.a = L.ah;
+        g.b = L.bh;
+        g.a_plane = pa;
+        g.a_slice = (long long)n1 * L.ld;
+        g.b_plane = pb;
+        g.b_slice = (long long)l * L.ld;
+        g.ld = L.ld;
+        g.bkl = L.bkl;
+        g.variant = L.variant;
+        g.cr = L.c.re;
+        g.ci = L.c.im;
+        g.ldc = l;
+        g.sc = (long long)n1 * l;
+        g.m = n1;
+        g.n = l;
+        g.k = n2;
+        g.nreal = real_slices(n3);
+        g.real_s[0] = 0;
+        g.real_s[1] = h - 1;
+        g.cs0 = 1;
+        g.ncs = h - g.nreal;
+        g.split = split;
+        TP_LAUNCH(tp::K_CGEMM, s, tp::launch_cgemm_bf16(g, s));
+        TP_LAUNCH(tp::K_IRFFT, s, tp::launch_irfft(L.c.re, L.c.im, C, (long long)n1 * l, n3, s));
+        return TP_OK;
+    }
     // Algorithm 1, step 1: DFT of the tubes of A and B
     TP_LAUNCH(tp::K_RFFT, s, tp::launch_rfft(A, L.a.re, L.a.im, (long long)n1 * n2, n3, s));
     TP_LAUNCH(tp::K_RFFT, s, tp::launch_rfft(B, L.b.re, L.b.im, (long long)n2 * l, n3, s));
@@ -485,9 +541,9 @@ int tp_version(void) { return 100; }
 
 size_t tp_tprod_workspace_size(int n1, int n2, int l, int n3, int prec)
 {
-    (void)prec;
     if (bad_dim(n1) || bad_dim(n2) || bad_dim(l) || bad_dim(n3)) return 0;
-    return tprod_arena(nullptr, 0, n1, n2, l, n3, nullptr).used;
+    if (prec != TP_PREC_FP32 && prec != TP_PREC_BF16X3 && prec != TP_PREC_BF16) return 0;
+    return tprod_arena(nullptr, 0, n1, n2, l, n3, prec, nullptr).used;
 }
 
 int tp_tprod(const float* A, const float* B, float* C, int n1, int n2, int l, int n3, int prec,

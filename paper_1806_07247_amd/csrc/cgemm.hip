@@ -927,38 +927,89 @@ __global__ __launch_bounds__(256) void k_cgemm_batch(const CgemmArgs* __restrict
 }
 
 // ------------------------------------------------------------- BF16 (x3) --
+// Slice products on the bf16 planes of the forward transform (hi = bf16(x)
+// and, when splitting, lo = bf16(x - hi) of every real and imaginary part).
+// Rows of op(A) and columns of op(B) both hold the inner index contiguous,
+// k-blocked by the stage depth and padded with zeros to a whole block, so
+// one stage of a run of rows is one contiguous span and every operand moves
+// in 16-byte groups of 8 values straight from global memory into LDS
+// (global_load_lds, 1 KB per wavefront instruction, no registers, no
+// conversion) and from LDS into v_mfma_f32_16x16x32_bf16.
+// Per output, the products hi*hi, hi*lo, lo*hi of each real product
+// accumulate in FP32 in that order.
+//
+// Pipeline: S LDS stages of 32 inner-dimension values; the loads of stage
+// c+S-1 are in flight while stage c is multiplied, one barrier per stage.
+// LDS rows are 64 bytes (four 16-byte groups); group g of row R sits in slot
+// g ^ ((R >> 1) & 3).  The MFMA fragment read (lane = 16 g + r, 16 bytes of
+// row R0 + r at group g) then runs at the full 256 bytes per clock without
+// bank conflicts; unswizzled 64-byte rows, and rows padded to 80 bytes,
+// measured one conflict cycle per clock of the read on gfx950.
+//
+// Workgroups: one per tile of a complex slice, then groups of rpw tiles of
+// the real slices (a real tile issues a quarter of the products of a
+// complex one), so that the real DC and Nyquist slices of the t-product do
+// not take a round of the GPU of their own.  XCD-aware numbering: the
+// hardware deals workgroup ids round-robin to the 8 XCDs; XCD x takes one
+// contiguous run of tiles (neighbouring tiles of one slice share panels of
+// A or B in its L2).
 
-// writes hi (and lo when splitting) bf16 planes: pointers [hi/lo][re/im].
-// Each conversion is one hardware round-to-nearest-even conversion
-// (v_cvt_pk_bf16_f32, one value per instruction; the two-element vector form
-// of the conversion measured wrong lanes on this toolchain);
-// lo = bf16(x - hi) carries the next 8 bits.
-struct StoreBF16 {
-    unsigned short* a[2][2];
-    unsigned short* b[2][2];
-    bool split;
-    __device__ __forceinline__ void put(unsigned short* const (&d)[2][2], int i, float r, float im) const
-    {
-        const __bf16 hr = (__bf16)r;
-        const __bf16 hi = (__bf16)im;
-        d[0][0][i] = __builtin_bit_cast(unsigned short, hr);
-        d[0][1][i] = __builtin_bit_cast(unsigned short, hi);
-        if (split) {
-            const __bf16 lr = (__bf16)(r - (float)hr);
-            const __bf16 li = (__bf16)(im - (float)hi);
-            d[1][0][i] = __builtin_bit_cast(unsigned short, lr);
-            d[1][1][i] = __builtin_bit_cast(unsigned short, li);
-        }
-    }
-    __device__ __forceinline__ void a_(int i, float r, float im) const { put(a, i, r, im); }
+template <int BM_, int BN_, int WGM_, int WGN_>
+struct BTile {
+    static constexpr int BM = BM_, BN = BN_, WGM = WGM_, WGN = WGN_;
+    static constexpr int NW = WGM * WGN, NT = 64 * NW;
+    static constexpr int WM = BM / WGM, WN = BN / WGN, TM = WM / 16, TN = WN / 16;
+    static_assert(TM >= 1 && TN >= 1 && WM % 16 == 0 && WN % 16 == 0, "16 x 16 MFMA tiles");
 };
+using B64x64 = BTile<64, 64, 2, 2>;      // wavefront tile 32 x 32
+using B128x32 = BTile<128, 32, 4, 1>;    // 32 x 32
+using B128x128 = BTile<128, 128, 2, 4>;  // 64 x 32, eight wavefronts
 
-template <class S>
-struct StoreAdapter {
-    const S& s;
-    __device__ __forceinline__ void a(int i, float r, float im) const { s.put(s.a, i, r, im); }
-    __device__ __forceinline__ void b(int i, float r, float im) const { s.put(s.b, i, r, im); }
-};
+constexpr int kBK = 32;  // inner-dimension values per stage (one MFMA step), 64-byte LDS rows
+
+// stages: as many as fit kLdsBudget bytes (at most 4, at least 2)
+template <class T, bool SPLIT>
+constexpr int bf16_stage_elems()
+{
+    return (SPLIT ? 4 : 2) * (T::BM + T::BN) * kBK;
+}
+template <class T, bool SPLIT>
+constexpr int bf16_stages()
+{
+    constexpr int budget = T::NW == 8 ? 128 * 1024 : 80 * 1024;
+    constexpr int n = budget / (2 * bf16_stage_elems<T, SPLIT>());
+    return n > 4 ? 4 : (n < 2 ? 2 : n);
+}
+
+typedef __attribute__((address_space(3))) void* lds_ptr;
+
+__device__ __forceinline__ int swz(int r) { return (r >> 1) & 3; }
+
+// wait until at most n of this wavefront's global loads are outstanding
+// (gfx9 s_waitcnt encoding: vmcnt in bits 3:0 and 15:14, the other counters
+// left at their maxima)
+template <int N>
+__device__ __forceinline__ void wait_vm()
+{
+    static_assert(N >= 0 && N < 64, "vmcnt range");
+    __builtin_amdgcn_s_waitcnt((N & 15) | ((N >> 4) << 14) | (7 << 4) | (15 << 8));
+}
+
+// workgroup barrier without a memory fence: LDS written by the global loads
+// is covered by each wavefront's own wait_vm before it; the wavefront's LDS
+// reads have all returned (lgkmcnt 0) before it arrives, so no buffer is
+// refilled under a read in flight
+__device__ __forceinline__ void barrier_only()
+{
+    asm volatile("" ::: "memory");
+    __builtin_amdgcn_s_waitcnt((15) | (3 << 14) | (7 << 4) | (0 << 8));
+    __builtin_amdgcn_s_barrier();
+    asm volatile("" ::: "memory");
+}
+
+#define TP_MFMA_BF16(a, b, c)                                                                                  \
+    __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8, (a)), __builtin_bit_cast(bf16x8, (b)), \
+                                            (c), 0, 0, 0)
 
 __device__ __forceinline__ shortx8 neg_bf16x8(shortx8 v)
 {
@@ -966,26 +1017,49 @@ __device__ __forceinline__ shortx8 neg_bf16x8(shortx8 v)
                          (short)0x8000, (short)0x8000, (short)0x8000, (short)0x8000};
 }
 
-#define TP_MFMA_BF16(a, b, c)                                                                                  \
-    __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8, (a)), __builtin_bit_cast(bf16x8, (b)), \
-                                            (c), 0, 0, 0)
-
-template <int OPA, int OPB, class T, bool SPLIT>
-__global__ __launch_bounds__(256) void k_cgemm_bf16(CgemmArgs p)
+// One BM x BN output tile of slice s at (m0, n0).  Planes used: complex
+// (hi re, hi im[, lo re, lo im]); real (hi re[, lo re]).  A stage holds the
+// NPU planes of the A panel (BM rows each), then those of the B panel.
+template <class T, bool SPLIT, bool CPLX>
+__device__ __forceinline__ void bf16_tile(const Bf16Args& p, int s, int m0, int n0, unsigned short* lds)
 {
-    constexpr int BM = T::BM, BN = T::BN, TM = T::TM, TN = T::TN;
-    constexpr int BK = 32, LDK = BK + 8;  // 16-byte aligned rows, staggered banks
-    constexpr int NP = SPLIT ? 2 : 1;
-    __shared__ __attribute__((aligned(16))) unsigned short sA[2][NP][2][BM * LDK];  // [buf][hi/lo][re/im]
-    __shared__ __attribute__((aligned(16))) unsigned short sB[2][NP][2][BN * LDK];
-
-    int bx, by, bz;
-    xcd_tile(bx, by, bz);
-    const SliceView v = slice_view(p, bz);
-    const int m0 = by * BM, n0 = bx * BN;
+    constexpr int BM = T::BM, BN = T::BN, TM = T::TM, TN = T::TN, NW = T::NW;
+    constexpr int S = bf16_stages<T, SPLIT>(), STAGE = bf16_stage_elems<T, SPLIT>();
+    constexpr int NPU = (SPLIT ? 2 : 1) * (CPLX ? 2 : 1);
+    constexpr int RA = NPU * BM, RB = NPU * BN;  // LDS rows of a stage used by this tile
+    constexpr int NBLK = (RA + RB) / 16;          // 1 KB blocks (16 rows) per stage
+    constexpr int LPW = (NBLK + NW - 1) / NW;     // loads per wavefront per stage (at most)
+    constexpr int LPW_MIN = NBLK / NW;            // (at least)
+    static_assert(BM % 16 == 0 && BN % 16 == 0, "16-row blocks");
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int wr = (wave / T::WGN) * T::WM, wc = (wave % T::WGN) * T::WN;
     const int g = lane >> 4, r16 = lane & 15;
+    // used plane u -> stored plane
+    auto stored = [](int u) { return CPLX ? u : 2 * u; };
+
+    // this lane's part of a block: row lane/4, LDS slot lane%4, which holds
+    // the 16-byte group (lane%4) ^ swz(row) of the row
+    const int brow = lane >> 2, bgrp = (lane & 3) ^ swz(lane >> 2);
+    const unsigned short* A = p.a + (long long)s * p.a_slice + bgrp * 8;
+    const unsigned short* B = p.b + (long long)s * p.b_slice + bgrp * 8;
+    auto issue = [&](int buf, int k0) {
+#pragma unroll
+        for (int j = 0; j < LPW; ++j) {
+            const int b = wave + j * NW;
+            if (j < LPW_MIN || b < NBLK) {
+                const unsigned short* src;
+                if (b < RA / 16) {
+                    const int u = b / (BM / 16), r = min(m0 + (b % (BM / 16)) * 16 + brow, p.m - 1);
+                    src = A + stored(u) * p.a_plane + (long long)(k0 / kBK) * p.m * kBK + (long long)r * kBK;
+                } else {
+                    const int bb = b - RA / 16;
+                    const int u = bb / (BN / 16), r = min(n0 + (bb % (BN / 16)) * 16 + brow, p.n - 1);
+                    src = B + stored(u) * p.b_plane + (long long)(k0 / kBK) * p.n * kBK + (long long)r * kBK;
+                }
+                __builtin_amdgcn_global_load_lds((void*)src, (lds_ptr)(lds + buf * STAGE + b * 512), 16, 0, 0);
+            }
+        }
+    };
 
     floatx4 accr[TM][TN], acci[TM][TN];
 #pragma unroll
@@ -996,71 +1070,293 @@ __global__ __launch_bounds__(256) void k_cgemm_bf16(CgemmArgs p)
             acci[ti][tj] = floatx4{0.f, 0.f, 0.f, 0.f};
         }
 
-    auto storer = [&](int b) {
-        StoreBF16 st;
-        for (int h = 0; h < 2; ++h)
-            for (int ri = 0; ri < 2; ++ri) {
-                st.a[h][ri] = sA[b][h < NP ? h : 0][ri];
-                st.b[h][ri] = sB[b][h < NP ? h : 0][ri];
+    // fragment of row R (a multiple of 16 plus r16): 16 bytes at slot g ^ swz(r16)
+    const int foff = r16 * kBK + ((g ^ swz(r16)) * 8);
+    const int nk = (p.k + kBK - 1) / kBK;
+#pragma unroll
+    for (int st = 0; st < S - 1; ++st)
+        if (st < nk) issue(st, st * kBK);
+    for (int c = 0; c < nk; ++c) {
+        // stage c has landed once at most the later stages' loads are outstanding
+        if (c + S - 2 < nk)
+            wait_vm<LPW_MIN * (S - 2)>();
+        else
+            wait_vm<0>();
+        barrier_only();  // stage c complete everywhere; stage c-1 no longer read
+        if (c + S - 1 < nk) issue((c + S - 1) % S, (c + S - 1) * kBK);
+        const unsigned short* sA = lds + (c % S) * STAGE;
+        const unsigned short* sB = sA + RA * kBK;
+        // 16x16x32 operands: lane (g, r16) holds k = 8g .. 8g+7 of row (column) r16.
+        // Row tiles in pairs, so that four accumulators rotate between
+        // dependent products.
+        constexpr int TP = TM < 2 ? TM : 2;
+#pragma unroll
+        for (int t0 = 0; t0 < TM; t0 += TP) {
+            shortx8 fa[TP][NPU];
+#pragma unroll
+            for (int i = 0; i < TP; ++i)
+#pragma unroll
+                for (int u = 0; u < NPU; ++u)
+                    fa[i][u] = *reinterpret_cast<const shortx8*>(sA + (u * BM + wr + 16 * (t0 + i)) * kBK + foff);
+#pragma unroll
+            for (int tj = 0; tj < TN; ++tj) {
+                shortx8 fb[NPU];
+#pragma unroll
+                for (int u = 0; u < NPU; ++u)
+                    fb[u] = *reinterpret_cast<const shortx8*>(sB + (u * BN + wc + 16 * tj) * kBK + foff);
+                if constexpr (CPLX) {
+                    // Cr += Ar Br - Ai Bi, Ci += Ar Bi + Ai Br for each (a-part, b-part)
+                    const shortx8 nb1 = neg_bf16x8(fb[1]);
+#define TP_CTERM(ar, ai, br, bi, nbi)                                                                  \
+    _Pragma("unroll") for (int i = 0; i < TP; ++i) accr[t0 + i][tj] = TP_MFMA_BF16(ar, br, accr[t0 + i][tj]); \
+    _Pragma("unroll") for (int i = 0; i < TP; ++i) acci[t0 + i][tj] = TP_MFMA_BF16(ar, bi, acci[t0 + i][tj]); \
+    _Pragma("unroll") for (int i = 0; i < TP; ++i) accr[t0 + i][tj] = TP_MFMA_BF16(ai, nbi, accr[t0 + i][tj]); \
+    _Pragma("unroll") for (int i = 0; i < TP; ++i) acci[t0 + i][tj] = TP_MFMA_BF16(ai, br, acci[t0 + i][tj]);
+                    TP_CTERM(fa[i][0], fa[i][1], fb[0], fb[1], nb1)  // hi * hi
+                    if constexpr (SPLIT) {
+                        const shortx8 nb3 = neg_bf16x8(fb[3]);
+                        TP_CTERM(fa[i][0], fa[i][1], fb[2], fb[3], nb3)  // hi * lo
+                        TP_CTERM(fa[i][2], fa[i][3], fb[0], fb[1], nb1)  // lo * hi
+                    }
+#undef TP_CTERM
+                } else {
+#pragma unroll
+                    for (int i = 0; i < TP; ++i) accr[t0 + i][tj] = TP_MFMA_BF16(fa[i][0], fb[0], accr[t0 + i][tj]);
+                    if constexpr (SPLIT) {
+#pragma unroll
+                        for (int i = 0; i < TP; ++i)
+                            accr[t0 + i][tj] = TP_MFMA_BF16(fa[i][0], fb[1], accr[t0 + i][tj]);
+#pragma unroll
+                        for (int i = 0; i < TP; ++i)
+                            accr[t0 + i][tj] = TP_MFMA_BF16(fa[i][1], fb[0], accr[t0 + i][tj]);
+                    }
+                }
             }
-        st.split = SPLIT;
-        return st;
+        }
+    }
+    // every wavefront is done with the last stage before LDS is reused
+    __syncthreads();
+
+    float* cr = p.cr + (long long)s * p.sc;
+    float* ci = p.ci + (long long)s * p.sc;
+#pragma unroll
+    for (int ti = 0; ti < TM; ++ti)
+#pragma unroll
+        for (int tj = 0; tj < TN; ++tj)
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                const int row = m0 + wr + 16 * ti + 4 * g + j, col = n0 + wc + 16 * tj + r16;
+                if (row < p.m && col < p.n) {
+                    const long long off = (long long)row * p.ldc + col;
+                    cr[off] = accr[ti][tj][j];
+                    ci[off] = CPLX ? acci[ti][tj][j] : 0.0f;
+                }
+            }
+}
+
+template <class T, bool SPLIT>
+__global__ __launch_bounds__(T::NT) void k_cgemm_bf16(Bf16Args p)
+{
+    __shared__ __attribute__((aligned(1024))) unsigned short lds[bf16_stages<T, SPLIT>() * bf16_stage_elems<T, SPLIT>()];
+    const int ntn = (p.n + T::BN - 1) / T::BN, tps = ((p.m + T::BM - 1) / T::BM) * ntn;
+    const int nct = p.ncs * tps, nrt = p.nreal * tps;
+    const int total = gridDim.x, w = blockIdx.x, x = w & 7;
+    const int t = x * (total >> 3) + min(x, total & 7) + (w >> 3);
+    if (t < nct) {
+        const int rem = t % tps;
+        bf16_tile<T, SPLIT, true>(p, p.cs0 + t / tps, (rem / ntn) * T::BM, (rem % ntn) * T::BN, lds);
+        return;
+    }
+    const int r0 = (t - nct) * p.rpw, r1 = min(nrt, r0 + p.rpw);
+    for (int r = r0; r < r1; ++r) {
+        const int rem = r % tps;
+        bf16_tile<T, SPLIT, false>(p, p.real_s[r / tps], (rem / ntn) * T::BM, (rem % ntn) * T::BN, lds);
+    }
+}
+
+// The same products on v_mfma_f32_32x32x16_bf16 (32 x 32 outputs per
+// instruction, 16 inner-dimension values): stages of 16 values, so that
+// larger tiles (fewer operand bytes through L2 per product) still fit
+// several stages in LDS.  LDS rows are 32 bytes (two 16-byte halves); half h
+// of row R sits in slot h ^ ((R >> 3) & 1), which measured free of bank
+// conflicts for the fragment read (lane = 32 h + r, row R0 + r).
+template <int BM_, int BN_, int WGM_, int WGN_>
+struct BTile32 {
+    static constexpr int BM = BM_, BN = BN_, WGM = WGM_, WGN = WGN_;
+    static constexpr int NW = WGM * WGN, NT = 64 * NW;
+    static constexpr int WM = BM / WGM, WN = BN / WGN, TM = WM / 32, TN = WN / 32;
+    static_assert(TM >= 1 && TN >= 1 && WM % 32 == 0 && WN % 32 == 0, "32 x 32 MFMA tiles");
+};
+using C256x128 = BTile32<256, 128, 4, 2>;  // wavefront tile 64 x 64, eight wavefronts
+using C128x128 = BTile32<128, 128, 2, 2>;  // 64 x 64
+
+constexpr int kBK32 = 16;  // inner-dimension values per stage of the 32 x 32 kernel
+
+template <class T, bool SPLIT>
+constexpr int bf16w_stage_elems()
+{
+    return (SPLIT ? 4 : 2) * (T::BM + T::BN) * kBK32;
+}
+template <class T, bool SPLIT>
+constexpr int bf16w_stages()
+{
+    constexpr int budget = T::NW == 8 ? 144 * 1024 : 80 * 1024;
+    constexpr int n = budget / (2 * bf16w_stage_elems<T, SPLIT>());
+    return n > 4 ? 4 : (n < 2 ? 2 : n);
+}
+
+typedef float floatx16 __attribute__((ext_vector_type(16)));
+
+#define TP_MFMA32_BF16(a, b, c)                                                                                \
+    __builtin_amdgcn_mfma_f32_32x32x16_bf16(__builtin_bit_cast(bf16x8, (a)), __builtin_bit_cast(bf16x8, (b)), \
+                                            (c), 0, 0, 0)
+
+template <class T, bool SPLIT, bool CPLX>
+__device__ __forceinline__ void bf16w_tile(const Bf16Args& p, int s, int m0, int n0, unsigned short* lds)
+{
+    constexpr int BM = T::BM, BN = T::BN, TM = T::TM, TN = T::TN, NW = T::NW;
+    constexpr int S = bf16w_stages<T, SPLIT>(), STAGE = bf16w_stage_elems<T, SPLIT>();
+    constexpr int NPU = (SPLIT ? 2 : 1) * (CPLX ? 2 : 1);
+    constexpr int RA = NPU * BM, RB = NPU * BN;  // LDS rows of a stage used by this tile
+    constexpr int NBLK = (RA + RB) / 32;          // 1 KB blocks (32 rows) per stage
+    constexpr int LPW = (NBLK + NW - 1) / NW, LPW_MIN = NBLK / NW;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int wr = (wave / T::WGN) * T::WM, wc = (wave % T::WGN) * T::WN;
+    const int r32 = lane & 31, kh = lane >> 5;
+    auto stored = [](int u) { return CPLX ? u : 2 * u; };
+
+    // this lane's part of a block: row lane/2, slot lane%2 holding half (lane%2) ^ ((row >> 3) & 1)
+    const int brow = lane >> 1, bhalf = (lane & 1) ^ ((brow >> 3) & 1);
+    const unsigned short* A = p.a + (long long)s * p.a_slice + bhalf * 8;
+    const unsigned short* B = p.b + (long long)s * p.b_slice + bhalf * 8;
+    auto issue = [&](int buf, int k0) {
+#pragma unroll
+        for (int j = 0; j < LPW; ++j) {
+            const int b = wave + j * NW;
+            if (j < LPW_MIN || b < NBLK) {
+                const unsigned short* src;
+                if (b < RA / 32) {
+                    const int u = b / (BM / 32), r = min(m0 + (b % (BM / 32)) * 32 + brow, p.m - 1);
+                    src = A + stored(u) * p.a_plane + (long long)(k0 / kBK32) * p.m * kBK32 + (long long)r * kBK32;
+                } else {
+                    const int bb = b - RA / 32;
+                    const int u = bb / (BN / 32), r = min(n0 + (bb % (BN / 32)) * 32 + brow, p.n - 1);
+                    src = B + stored(u) * p.b_plane + (long long)(k0 / kBK32) * p.n * kBK32 + (long long)r * kBK32;
+                }
+                __builtin_amdgcn_global_load_lds((void*)src, (lds_ptr)(lds + buf * STAGE + b * 512), 16, 0, 0);
+            }
+        }
     };
 
-    PanelLoader<OPA, OPB, BM, BN, BK> ld;
-    const int nk = (v.K + BK - 1) / BK;
-    if (nk > 0) {
-        ld.load(v, p, m0, n0, 0, tid);
-        const StoreBF16 st = storer(0);
-        ld.template store<LDK, false, false>(tid, StoreAdapter<StoreBF16>{st});
-    }
-    __syncthreads();
-    for (int c = 0; c < nk; ++c) {
-        const int cur = c & 1;
-        if (c + 1 < nk) ld.load(v, p, m0, n0, (c + 1) * BK, tid);
-        // 16x16x32 operands: lane (g, r16) holds k = 8g .. 8g+7 of row (col) r16
-        shortx8 fa[TM][NP][2], fb[TN][NP][2];
+    floatx16 accr[TM][TN], acci[TM][TN];
 #pragma unroll
-        for (int h = 0; h < NP; ++h)
+    for (int ti = 0; ti < TM; ++ti)
 #pragma unroll
-            for (int ri = 0; ri < 2; ++ri) {
+        for (int tj = 0; tj < TN; ++tj)
 #pragma unroll
-                for (int t = 0; t < TM; ++t)
-                    fa[t][h][ri] = *reinterpret_cast<const shortx8*>(&sA[cur][h][ri][(wr + 16 * t + r16) * LDK + 8 * g]);
-#pragma unroll
-                for (int t = 0; t < TN; ++t)
-                    fb[t][h][ri] = *reinterpret_cast<const shortx8*>(&sB[cur][h][ri][(wc + 16 * t + r16) * LDK + 8 * g]);
+            for (int v = 0; v < 16; ++v) {
+                accr[ti][tj][v] = 0.0f;
+                acci[ti][tj][v] = 0.0f;
             }
-        // terms (a-part, b-part): hi*hi, then hi*lo and lo*hi when splitting;
-        // each term in two passes over the tiles (independent MFMAs between
-        // the two products into one accumulator)
+
+    // fragment of row R0 + r32 (R0 a multiple of 32), values 8 kh .. 8 kh + 7
+    const int foff = r32 * kBK32 + ((kh ^ ((r32 >> 3) & 1)) * 8);
+    const int nk = (p.k + kBK32 - 1) / kBK32;
 #pragma unroll
-        for (int term = 0; term < (SPLIT ? 3 : 1); ++term) {
-            const int ha = (term == 2) ? 1 : 0, hb = (term == 1) ? 1 : 0;
+    for (int st = 0; st < S - 1; ++st)
+        if (st < nk) issue(st, st * kBK32);
+    for (int c = 0; c < nk; ++c) {
+        if (c + S - 2 < nk)
+            wait_vm<LPW_MIN * (S - 2)>();
+        else
+            wait_vm<0>();
+        barrier_only();
+        if (c + S - 1 < nk) issue((c + S - 1) % S, (c + S - 1) * kBK32);
+        const unsigned short* sA = lds + (c % S) * STAGE;
+        const unsigned short* sB = sA + RA * kBK32;
+        shortx8 fa[TM][NPU], fb[TN][NPU];
+#pragma unroll
+        for (int u = 0; u < NPU; ++u) {
 #pragma unroll
             for (int ti = 0; ti < TM; ++ti)
+                fa[ti][u] = *reinterpret_cast<const shortx8*>(sA + (u * BM + wr + 32 * ti) * kBK32 + foff);
 #pragma unroll
-                for (int tj = 0; tj < TN; ++tj) {
-                    accr[ti][tj] = TP_MFMA_BF16(fa[ti][ha][0], fb[tj][hb][0], accr[ti][tj]);
-                    if (!v.real) acci[ti][tj] = TP_MFMA_BF16(fa[ti][ha][0], fb[tj][hb][1], acci[ti][tj]);
-                }
-            if (!v.real) {
+            for (int tj = 0; tj < TN; ++tj)
+                fb[tj][u] = *reinterpret_cast<const shortx8*>(sB + (u * BN + wc + 32 * tj) * kBK32 + foff);
+        }
+        if constexpr (CPLX) {
+            shortx8 nb1[TN], nb3[TN];
 #pragma unroll
-                for (int ti = 0; ti < TM; ++ti)
-#pragma unroll
-                    for (int tj = 0; tj < TN; ++tj) {
-                        accr[ti][tj] = TP_MFMA_BF16(neg_bf16x8(fa[ti][ha][1]), fb[tj][hb][1], accr[ti][tj]);
-                        acci[ti][tj] = TP_MFMA_BF16(fa[ti][ha][1], fb[tj][hb][0], acci[ti][tj]);
-                    }
+            for (int tj = 0; tj < TN; ++tj) {
+                nb1[tj] = neg_bf16x8(fb[tj][1]);
+                if constexpr (SPLIT) nb3[tj] = neg_bf16x8(fb[tj][3]);
             }
+            // Cr += Ar Br - Ai Bi, Ci += Ar Bi + Ai Br for each (a-part, b-part); each
+            // product over all (ti, tj) before the next, so dependent MFMAs are 2 TM TN apart
+#define TP_W4(acc, a, b)                                                    \
+    _Pragma("unroll") for (int ti = 0; ti < TM; ++ti)                       \
+    _Pragma("unroll") for (int tj = 0; tj < TN; ++tj) acc[ti][tj] = TP_MFMA32_BF16(a, b, acc[ti][tj]);
+            TP_W4(accr, fa[ti][0], fb[tj][0])
+            TP_W4(acci, fa[ti][0], fb[tj][1])
+            TP_W4(accr, fa[ti][1], nb1[tj])
+            TP_W4(acci, fa[ti][1], fb[tj][0])
+            if constexpr (SPLIT) {
+                TP_W4(accr, fa[ti][0], fb[tj][2])
+                TP_W4(acci, fa[ti][0], fb[tj][3])
+                TP_W4(accr, fa[ti][1], nb3[tj])
+                TP_W4(acci, fa[ti][1], fb[tj][2])
+                TP_W4(accr, fa[ti][2], fb[tj][0])
+                TP_W4(acci, fa[ti][2], fb[tj][1])
+                TP_W4(accr, fa[ti][3], nb1[tj])
+                TP_W4(acci, fa[ti][3], fb[tj][0])
+            }
+        } else {
+            TP_W4(accr, fa[ti][0], fb[tj][0])
+            if constexpr (SPLIT) {
+                TP_W4(accr, fa[ti][0], fb[tj][1])
+                TP_W4(accr, fa[ti][1], fb[tj][0])
+            }
+#undef TP_W4
         }
-        if (c + 1 < nk) {
-            const StoreBF16 st = storer(cur ^ 1);
-            ld.template store<LDK, false, false>(tid, StoreAdapter<StoreBF16>{st});
-        }
-        __syncthreads();
     }
-    write_tile<T>(v, p, m0, n0, wr, wc, lane, accr, acci);
+    __syncthreads();
+
+    float* cr = p.cr + (long long)s * p.sc;
+    float* ci = p.ci + (long long)s * p.sc;
+    // output value v of a lane: row 8 (v / 4) + 4 kh + v % 4, column r32 of the 32 x 32 block
+#pragma unroll
+    for (int ti = 0; ti < TM; ++ti)
+#pragma unroll
+        for (int tj = 0; tj < TN; ++tj)
+#pragma unroll
+            for (int v = 0; v < 16; ++v) {
+                const int row = m0 + wr + 32 * ti + 8 * (v >> 2) + 4 * kh + (v & 3), col = n0 + wc + 32 * tj + r32;
+                if (row < p.m && col < p.n) {
+                    const long long off = (long long)row * p.ldc + col;
+                    cr[off] = accr[ti][tj][v];
+                    ci[off] = CPLX ? acci[ti][tj][v] : 0.0f;
+                }
+            }
+}
+
+template <class T, bool SPLIT>
+__global__ __launch_bounds__(T::NT) void k_cgemm_bf16w(Bf16Args p)
+{
+    __shared__ __attribute__((aligned(1024))) unsigned short lds[bf16w_stages<T, SPLIT>() * bf16w_stage_elems<T, SPLIT>()];
+    const int ntn = (p.n + T::BN - 1) / T::BN, tps = ((p.m + T::BM - 1) / T::BM) * ntn;
+    const int nct = p.ncs * tps, nrt = p.nreal * tps;
+    const int total = gridDim.x, w = blockIdx.x, x = w & 7;
+    const int t = x * (total >> 3) + min(x, total & 7) + (w >> 3);
+    if (t < nct) {
+        const int rem = t % tps;
+        bf16w_tile<T, SPLIT, true>(p, p.cs0 + t / tps, (rem / ntn) * T::BM, (rem % ntn) * T::BN, lds);
+        return;
+    }
+    const int r0 = (t - nct) * p.rpw, r1 = min(nrt, r0 + p.rpw);
+    for (int r = r0; r < r1; ++r) {
+        const int rem = r % tps;
+        bf16w_tile<T, SPLIT, false>(p, p.real_s[r / tps], (rem / ntn) * T::BM, (rem % ntn) * T::BN, lds);
+    }
 }
 
 template <class T>
@@ -1163,16 +1459,66 @@ hipError_t launch_wide(const CgemmArgs& a, int form, hipStream_t s)
 // multiple of 4, and (by shape) an inner dimension long enough to stream
 bool skinny_ok(const CgemmArgs& a, int opb, int kmin) { return opb == OP_N && a.n <= 64 && a.n % 4 == 0 && a.k >= kmin; }
 
-template <class T>
-hipError_t launch_bf16(const CgemmArgs& a, int prec, hipStream_t s)
+template <class T, bool W = false>
+hipError_t launch_bf16(Bf16Args a, hipStream_t s)
 {
-    if (prec == TP_PREC_BF16X3)
-        k_cgemm_bf16<OP_N, OP_N, T, true><<<grid_of<T>(a), 256, 0, s>>>(a);
-    else
-        k_cgemm_bf16<OP_N, OP_N, T, false><<<grid_of<T>(a), 256, 0, s>>>(a);
+    const long long tps = (long long)((a.m + T::BM - 1) / T::BM) * ((a.n + T::BN - 1) / T::BN);
+    const long long nwg = a.ncs * tps + (a.nreal * tps + a.rpw - 1) / a.rpw;
+    if (nwg <= 0) return hipSuccess;
+    if constexpr (W) {
+        if (a.split)
+            k_cgemm_bf16w<T, true><<<(unsigned)nwg, T::NT, 0, s>>>(a);
+        else
+            k_cgemm_bf16w<T, false><<<(unsigned)nwg, T::NT, 0, s>>>(a);
+    } else {
+        if (a.split)
+            k_cgemm_bf16<T, true><<<(unsigned)nwg, T::NT, 0, s>>>(a);
+        else
+            k_cgemm_bf16<T, false><<<(unsigned)nwg, T::NT, 0, s>>>(a);
+    }
     return hipGetLastError();
 }
 
+int cu_count()
+{
+    static const int n = [] {
+        int d = 0, v = 0;
+        if (hipGetDevice(&d) != hipSuccess || hipDeviceGetAttribute(&v, hipDeviceAttributeMultiprocessorCount, d) !=
+                                                   hipSuccess)
+            return 256;
+        return v > 0 ? v : 256;
+    }();
+    return n;
+}
+
+// bf16 tile: the tuned one if set (1: 64 x 64, 2: 128 x 128, 3: 128 x 32,
+// 4: 256 x 128 and 5: 128 x 128 on 32 x 32 x 16 products, others 64 x 64),
+// else the one with the least estimated time: workgroups per compute unit
+// times the work of a tile over the fraction of peak such tiles sustain.
+int pick_bf16(int m, int n, int ncs, int nreal)
+{
+    const int tuned = param(TP_PARAM_GEMM_VARIANT);
+    if (tuned >= 1 && tuned <= 8) return tuned <= 5 ? tuned : 1;
+    struct Cand {
+        int id, bm, bn;
+        double eff;
+    };
+    const Cand cands[] = {{4, 256, 128, 1.0}, {2, 128, 128, 0.9}, {1, 64, 64, 0.5}, {3, 128, 32, 0.45}};
+    int best = 1;
+    double best_cost = 0.0;
+    for (const Cand& c : cands) {
+        const long long tps = (long long)((m + c.bm - 1) / c.bm) * ((n + c.bn - 1) / c.bn);
+        const long long nwg = ncs * tps + (nreal * tps + 1) / 2;
+        const double cost = (double)((nwg + cu_count() - 1) / cu_count()) * c.bm * c.bn / c.eff;
+        if (best_cost == 0.0 || cost < best_cost) {
+            best = c.id;
+            best_cost = cost;
+        }
+    }
+    return best;
+}
+
+bool bf16_wide(int variant) { return variant == 4 || variant == 5; }
 template <int OPA, int OPB>
 hipError_t launch_ops(const CgemmArgs& a, int variant, hipStream_t s)
 {
@@ -1260,18 +1606,8 @@ hipError_t launch_cgemm(const CgemmArgs& a, int opa, int opb, int prec, hipStrea
 {
     if (a.m <= 0 || a.n <= 0 || a.nslices <= 0) return hipSuccess;
     trace_gemm_work(a);
+    if (prec != TP_PREC_FP32) return hipErrorInvalidValue;
     const int variant = pick_variant(a);
-    if (prec != TP_PREC_FP32) {
-        if (opa != OP_N || opb != OP_N || a.ksplit > 1) return hipErrorInvalidValue;
-        switch (variant) {
-            case 2: return launch_bf16<T128x128>(a, prec, s);
-            case 3: return launch_bf16<T128x64>(a, prec, s);
-            case 4:
-            case 5: return launch_bf16<T128x32>(a, prec, s);  // the 256-row split tile exceeds LDS
-            case 6: return launch_bf16<T64x48>(a, prec, s);
-            default: return launch_bf16<T64x64>(a, prec, s);
-        }
-    }
     const int tuned = param(TP_PARAM_GEMM_VARIANT);
     // a device-capped inner dimension that fits the wide kernel stays short:
     // the wide kernel skips its dead 16-deep chunks
@@ -1286,6 +1622,38 @@ hipError_t launch_cgemm(const CgemmArgs& a, int opa, int opb, int prec, hipStrea
     if (opa == OP_C && opb == OP_N) return launch_ops<OP_C, OP_N>(a, variant, s);
     if (opa == OP_N && opb == OP_C) return launch_ops<OP_N, OP_C>(a, variant, s);
     return launch_ops<OP_C, OP_C>(a, variant, s);
+}
+
+int bf16_plan(int m, int n, int k, int ncs, int nreal, int* bkl)
+{
+    (void)k;
+    const int v = pick_bf16(m, n, ncs, nreal);
+    if (bkl) *bkl = bf16_wide(v) ? kBK32 : kBK;
+    return v;
+}
+
+hipError_t launch_cgemm_bf16(Bf16Args a, hipStream_t s)
+{
+    if (a.m <= 0 || a.n <= 0 || a.ncs + a.nreal <= 0) return hipSuccess;
+    const int v = a.variant;
+    if (v < 1 || v > 5 || a.bkl != (bf16_wide(v) ? kBK32 : kBK) || a.ld % a.bkl || a.ld < a.k || a.nreal < 0 ||
+        a.nreal > 2 || a.k <= 0)
+        return hipErrorInvalidValue;
+    {
+        const double mnk = (double)a.m * a.n * a.k;
+        const double np = a.split ? 4.0 : 2.0;  // bf16 planes per operand
+        const double ns = (double)a.ncs + a.nreal;
+        trace_work(mnk * (8.0 * a.ncs + 2.0 * a.nreal),
+                   ns * (2.0 * np * ((double)a.m * a.k + (double)a.k * a.n) + 8.0 * (double)a.m * a.n));
+    }
+    a.rpw = 2;
+    switch (v) {
+        case 2: return launch_bf16<B128x128>(a, s);
+        case 3: return launch_bf16<B128x32>(a, s);
+        case 4: return launch_bf16<C256x128, true>(a, s);
+        case 5: return launch_bf16<C128x128, true>(a, s);
+        default: return launch_bf16<B64x64>(a, s);
+    }
 }
 
 }  // namespace tp

@@ -184,6 +184,26 @@ __device__ __forceinline__ void store_tile_cols(float* __restrict__ dst, const f
     }
 }
 
+// Bins 0 .. N/2 of the real length-N input from the length-N/2 transform Z of
+// its packed pairs: X_k = E_k + W_N^k O_k with E = (Z_k + conj Z_{M-k})/2,
+// O = -i (Z_k - conj Z_{M-k})/2; put(k, re, im) takes each bin.
+template <int N, class Put>
+__device__ __forceinline__ void rfft_bins(const float (&zr)[N / 2], const float (&zi)[N / 2], Put&& put)
+{
+    constexpr int M = N / 2;
+    put(0, zr[0] + zi[0], 0.0f);
+    put(M, zr[0] - zi[0], 0.0f);
+#pragma unroll
+    for (int k = 1; k < M; ++k) {
+        const float ar = zr[k], ai = zi[k], br = zr[M - k], bi = -zi[M - k];
+        const float er = 0.5f * (ar + br), ei = 0.5f * (ai + bi);
+        const float dr = 0.5f * (ar - br), di = 0.5f * (ai - bi);
+        const float orr = di, oi = -dr;
+        const float2 w = twc<N>(k);
+        put(k, er + (w.x * orr - w.y * oi), ei + (w.x * oi + w.y * orr));
+    }
+}
+
 // Forward transform of the nt (<= 64) tubes starting at tube `base` of a
 // tensor with `ntubes` tubes; tw holds W_N^j, buf 64 x (N+1) floats.
 template <int N>
@@ -204,21 +224,10 @@ __device__ __forceinline__ void rfft_tile(const float* __restrict__ x, float* __
         }
         cfft_half<N, false>(zr, zi);
         const long long q = base + tid;
-        // X_k = E_k + W_N^k O_k with E = (Z_k + conj Z_{M-k})/2, O = -i (Z_k - conj Z_{M-k})/2
-        re[q] = zr[0] + zi[0];
-        im[q] = 0.0f;
-        re[(long long)M * ntubes + q] = zr[0] - zi[0];
-        im[(long long)M * ntubes + q] = 0.0f;
-#pragma unroll
-        for (int k = 1; k < M; ++k) {
-            const float ar = zr[k], ai = zi[k], br = zr[M - k], bi = -zi[M - k];
-            const float er = 0.5f * (ar + br), ei = 0.5f * (ai + bi);
-            const float dr = 0.5f * (ar - br), di = 0.5f * (ai - bi);
-            const float orr = di, oi = -dr;
-            const float2 w = twc<N>(k);
-            re[(long long)k * ntubes + q] = er + (w.x * orr - w.y * oi);
-            im[(long long)k * ntubes + q] = ei + (w.x * oi + w.y * orr);
-        }
+        rfft_bins<N>(zr, zi, [&](int k, float vr, float vi) {
+            re[(long long)k * ntubes + q] = vr;
+            im[(long long)k * ntubes + q] = vi;
+        });
     }
 }
 
@@ -258,19 +267,104 @@ __global__ __launch_bounds__(kTubes) void k_rfft_pow2_direct(const float* __rest
             zi[bitrev<M>(2 * t + 1)] = v.w;
         }
         cfft_half<N, false>(zr, zi);
-        re[q] = zr[0] + zi[0];
-        im[q] = 0.0f;
-        re[(long long)M * ntubes + q] = zr[0] - zi[0];
-        im[(long long)M * ntubes + q] = 0.0f;
+        rfft_bins<N>(zr, zi, [&](int k, float vr, float vi) {
+            re[(long long)k * ntubes + q] = vr;
+            im[(long long)k * ntubes + q] = vi;
+        });
+    }
+}
+
+// ------------------------------------------------- bf16 plane output --
+// Element t of a plane slice in storage order (k-blocked, see SplitOut):
+// its tube, or -1 for padding.  Consecutive lanes write consecutive
+// elements of a plane.
+__device__ __forceinline__ long long split_tube(const SplitOut& o, long long t)
+{
+    const long long panel = (long long)o.outer * o.bkl;
+    const long long kb = t / panel, rem = t - kb * panel;
+    const long long r = rem / o.bkl, i = kb * o.bkl + (rem - r * o.bkl);
+    return i < o.inner ? r * o.q_outer + i * o.q_inner : -1;
+}
+
+__device__ __forceinline__ unsigned short bf16_bits(float v) { return __builtin_bit_cast(unsigned short, (__bf16)v); }
+
+// bin k of one tube: hi = bf16(v) (round to nearest even), lo = bf16(v - hi)
+__device__ __forceinline__ void put_split(const SplitOut& o, long long pos, int k, float vr, float vi)
+{
+    unsigned short* d = o.p + (long long)k * o.slice + pos;
+    const __bf16 hr = (__bf16)vr, hi = (__bf16)vi;
+    d[0] = __builtin_bit_cast(unsigned short, hr);
+    d[o.plane] = __builtin_bit_cast(unsigned short, hi);
+    if (o.split) {
+        d[2 * o.plane] = bf16_bits(vr - (float)hr);
+        d[3 * o.plane] = bf16_bits(vi - (float)hi);
+    }
+}
+
+__device__ __forceinline__ void put_zero(const SplitOut& o, long long pos, int h)
+{
+    for (int k = 0; k < h; ++k) put_split(o, pos, k, 0.0f, 0.0f);
+}
+
+// Power-of-two N: each lane transforms one tube read with 16-byte loads (as
+// k_rfft_pow2_direct) and writes its bins to the planes.
+template <int N>
+__global__ __launch_bounds__(kTubes) void k_rfft_split(const float* __restrict__ x, SplitOut o)
+{
+    constexpr int M = N / 2;
+    const long long total = (long long)o.outer * o.ld;
+    for (long long t = (long long)blockIdx.x * kTubes + threadIdx.x; t < total; t += (long long)gridDim.x * kTubes) {
+        const long long q = split_tube(o, t);
+        if (q < 0) {
+            put_zero(o, t, M + 1);
+            continue;
+        }
+        float zr[M], zi[M];
+        const float4* xt = reinterpret_cast<const float4*>(x + q * N);
 #pragma unroll
-        for (int k = 1; k < M; ++k) {
-            const float ar = zr[k], ai = zi[k], br = zr[M - k], bi = -zi[M - k];
-            const float er = 0.5f * (ar + br), ei = 0.5f * (ai + bi);
-            const float dr = 0.5f * (ar - br), di = 0.5f * (ai - bi);
-            const float orr = di, oi = -dr;
-            const float2 w = twc<N>(k);
-            re[(long long)k * ntubes + q] = er + (w.x * orr - w.y * oi);
-            im[(long long)k * ntubes + q] = ei + (w.x * oi + w.y * orr);
+        for (int u = 0; u < M / 2; ++u) {
+            const float4 v = xt[u];
+            zr[bitrev<M>(2 * u)] = v.x;
+            zi[bitrev<M>(2 * u)] = v.y;
+            zr[bitrev<M>(2 * u + 1)] = v.z;
+            zi[bitrev<M>(2 * u + 1)] = v.w;
+        }
+        cfft_half<N, false>(zr, zi);
+        rfft_bins<N>(zr, zi, [&](int k, float vr, float vi) { put_split(o, t, k, vr, vi); });
+    }
+}
+
+// Any n: direct DFT per lane on its tube staged in LDS (blockDim.x x (n+1)
+// floats after the n twiddles), as rdft_tile.
+__global__ void k_rdft_split_any(const float* __restrict__ x, SplitOut o, int n)
+{
+    extern __shared__ float smem[];
+    float2* tw = reinterpret_cast<float2*>(smem);
+    float* xt = smem + 2 * n + threadIdx.x * (n + 1);
+    fill_twiddles(tw, n);
+    __syncthreads();
+    const int h = n / 2 + 1;
+    const long long total = (long long)o.outer * o.ld;
+    for (long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x; t < total;
+         t += (long long)gridDim.x * blockDim.x) {
+        const long long q = split_tube(o, t);
+        if (q < 0) {
+            put_zero(o, t, h);
+            continue;
+        }
+        for (int u = 0; u < n; ++u) xt[u] = x[q * n + u];
+        for (int k = 0; k < h; ++k) {
+            float sr = 0.0f, si = 0.0f;
+            int e = 0;
+            for (int u = 0; u < n; ++u) {
+                const float v = xt[u];
+                const float2 w = tw[e];
+                sr += v * w.x;
+                si += v * w.y;
+                e += k;
+                if (e >= n) e -= n;
+            }
+            put_split(o, t, k, sr, (k == 0 || 2 * k == n) ? 0.0f : si);
         }
     }
 }
@@ -555,6 +649,35 @@ hipError_t launch_irfft(const float* re, const float* im, float* x, long long nt
     const int tpb = any_tubes_per_block(n3);
     const size_t lds = (size_t)(4 * tpb * (n3 + 1) + 8 * n3);
     k_irdft_any<<<grid_for(ntubes, tpb), tpb, lds, s>>>(re, im, x, ntubes, n3);
+    return hipGetLastError();
+}
+
+hipError_t launch_rfft_split(const float* x, const SplitOut& o, int n3, hipStream_t s)
+{
+    const long long total = (long long)o.outer * o.ld;
+    if (total <= 0) return hipSuccess;
+    if (o.inner > o.ld || o.bkl <= 0 || o.ld % o.bkl) return hipErrorInvalidValue;
+    const int h = n3 / 2 + 1;
+    trace_work(0.0, (double)o.outer * o.inner * 4.0 * n3 + (double)total * (o.split ? 8.0 : 4.0) * h);
+    const bool vec = (reinterpret_cast<uintptr_t>(x) & 15) == 0;
+    if (vec) {
+        const int g = grid_for(total, kTubes);
+        switch (n3) {
+#define TP_RSPLIT_CASE(N) \
+    case N: k_rfft_split<N><<<g, kTubes, 0, s>>>(x, o); return hipGetLastError();
+            TP_RSPLIT_CASE(4)
+            TP_RSPLIT_CASE(8)
+            TP_RSPLIT_CASE(16)
+            TP_RSPLIT_CASE(32)
+            TP_RSPLIT_CASE(64)
+            TP_RSPLIT_CASE(128)
+#undef TP_RSPLIT_CASE
+            default: break;
+        }
+    }
+    const int tpb = any_tubes_per_block(n3);
+    const size_t lds = (size_t)(4 * tpb * (n3 + 1) + 8 * n3);
+    k_rdft_split_any<<<grid_for(total, tpb), tpb, lds, s>>>(x, o, n3);
     return hipGetLastError();
 }
 

@@ -68,6 +68,24 @@ hipError_t launch_rfft(const float* x, float* re, float* im, long long ntubes, i
 // spectrum; the imaginary parts of slice 0 (and n3/2 for even n3) are ignored.
 hipError_t launch_irfft(const float* re, const float* im, float* x, long long ntubes, int n3, hipStream_t s);
 
+// Forward transform written as bf16 planes for the bf16 slice products.
+// Per bin k the planes hold an outer x ld matrix (element (o, i) is bin k of
+// tube q = o*q_outer + i*q_inner of x for i < inner, and 0 for
+// inner <= i < ld), stored k-blocked: blocks of bkl consecutive i, each
+// block an outer x bkl row-major panel, at k*slice + (i / bkl)*outer*bkl +
+// o*bkl + i % bkl (ld a multiple of bkl).  A run of rows of one block is
+// then contiguous.  Planes, plane elements apart: hi re, hi im, and with
+// split lo re, lo im, where hi = bf16(v) and lo = bf16(v - hi) (round to
+// nearest even).
+struct SplitOut {
+    unsigned short* p;
+    long long plane, slice;
+    int outer, inner, ld, bkl;
+    long long q_outer, q_inner;
+    int split;
+};
+hipError_t launch_rfft_split(const float* x, const SplitOut& o, int n3, hipStream_t s);
+
 // ---------------------------------------------------------- slice GEMM ----
 enum Op { OP_N = 0, OP_C = 1 };  // op(X) = X or X^* (conjugate transpose)
 
@@ -115,7 +133,37 @@ struct GemmUnit {
 int batch_tile(int tile);
 hipError_t launch_cgemm_batch(const CgemmArgs* items, const GemmUnit* units, int nunits, int tile, int grid,
                               double flops, double bytes, hipStream_t s);
+// FP32 slice products (prec must be TP_PREC_FP32; the bf16 products take
+// their operands as bf16 planes, launch_cgemm_bf16)
 hipError_t launch_cgemm(const CgemmArgs& a, int opa, int opb, int prec, hipStream_t s);
+
+// C^(s) = A^(s) B^(s) on bf16 planes (see SplitOut): A as m rows of the
+// inner index (outer = m), B as n columns of it (outer = n), both k-blocked
+// with the block length bf16_plan gives for the product, zero past k.
+// Planes hi re, hi im, then (split) lo re, lo im; strides in elements.
+// Slices cs0 .. cs0+ncs-1 are complex; real_s[0 .. nreal-1] are real
+// (imaginary planes ignored, Ci written as 0).  Output planar FP32 as
+// CgemmArgs.
+struct Bf16Args {
+    const unsigned short* a;
+    const unsigned short* b;
+    long long a_plane, a_slice, b_plane, b_slice;
+    int ld;       // k rounded up to the block length
+    int bkl;      // block length of the planes (from bf16_plan)
+    int variant;  // tile (from bf16_plan)
+    float* cr;
+    float* ci;
+    long long ldc, sc;
+    int m, n, k;
+    int cs0, ncs;
+    int nreal;
+    int real_s[2];
+    int split;  // 1: hi*hi + hi*lo + lo*hi, 0: hi*hi
+    int rpw;    // real-slice tiles per workgroup (set by the launcher)
+};
+// tile variant of a bf16 product and the plane block length it reads
+int bf16_plan(int m, int n, int k, int ncs, int nreal, int* bkl);
+hipError_t launch_cgemm_bf16(Bf16Args a, hipStream_t s);
 // FP32 narrow-output products split along k (ksplit > 1, part given): the
 // parts only, left in a.part ([ksplit][nslices][m][n], re then im) for the
 // caller to sum (launch_reduce_gram); cgemm_parts_ok says whether a product

@@ -103,11 +103,12 @@ def test_tprod_precision_config_sampled(tp, orc):
 
 
 @pytest.mark.parametrize("variant", [1, 2, 3, 4, 5, 6, 7, 8])
-@pytest.mark.parametrize("prec", ["fp32", "bf16x3"])
+@pytest.mark.parametrize("prec", ["fp32", "bf16x3", "bf16"])
 def test_tprod_every_tile_variant(tp, orc, variant, prec):
     """Each slice-product tile shape (forced through TP_PARAM_GEMM_VARIANT) on
-    a shape with ragged edges in every dimension (75 output columns: variants
-    7 and 8 fall back to the 64 x 64 tile)."""
+    a shape with ragged edges in every dimension (75 output columns: FP32
+    variants 7 and 8 fall back to the 64 x 64 tile; bf16 variants 1-5 are
+    its five tiles, 6-8 the 64 x 64 one)."""
     from paper_1806_07247_amd import _lib, inputs
     lib = _lib.load()
     A, B = inputs.tprod_pair(131, 67, 75, 6, seed=variant)
