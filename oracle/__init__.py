@@ -396,3 +396,7 @@ def slice_features(Y, tau, prev=None, prev_sigma=None):
     _load().or_slice_features(_dp(Y), n1, n2, n3, float(tau), None if pv is None else pv.ctypes.data_as(IP),
                               None if ps is None else _dp(ps), _dp(f))
     return f
+
+
+# order-p tensors (numpy; see nd.py)
+from .nd import prox_tnn_nd, teye_nd, tnn_nd, tprod_nd, tprod_nd_conv, tprod_nd_fft, tran_nd  # noqa: E402,F401
