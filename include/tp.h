@@ -366,6 +366,42 @@ int tp_tnn(const float* A, int n1, int n2, int n3, double* out, int* info, void*
            size_t workspace_bytes, void* stream);
 
 /*
+ * Order-p tensors, p = 2 + nd (the p-way extension the introduction of the
+ * paper defers to its reference [6]).  A tensor n1 x n2 x n3 x ... x np is
+ * C-ordered with np fastest (for nd = 1 exactly the 3-way layout above);
+ * dims[0 .. nd-1] = n3 .. np is a HOST int array, 1 <= nd <= 8, every
+ * dims[a] in 1..1024, and the number of Fourier slices
+ * h = n3 ... n_(p-1) * (floor(np/2)+1) at most 65535 (TP_ERR_SHAPE
+ * otherwise).  The t-product is defined recursively on the last mode (a
+ * block circulant of order-(p-1) tensors, Definition 2.1 at p = 3), which a
+ * DFT along each of modes 3..p diagonalises: the library transforms modes
+ * 3..p (a real DFT along mode p, keeping floor(np/2)+1 bins as in eq (8),
+ * complex DFTs along modes 3..p-1), works on the h kept Fourier slices as
+ * Algorithms 1 and 3 do, and transforms back.  FP32 arithmetic only.
+ *
+ * tp_tprod_nd: C = A * B, A n1 x n2 x dims, B n2 x l x dims, C n1 x l x dims.
+ * tp_prox_tnn_nd: X = Prox_tau(Y) for ||X||_* = (1/rho) sum over all
+ *   rho = n3 ... np Fourier slices of the matrix nuclear norms (eq (14) over
+ *   modes 3..p): the matrix SVT with threshold tau on every slice (Theorem
+ *   2.3; Parseval over modes 3..p carries its proof over).  info and rank as
+ *   for tp_prox_tnn, device int[h] each, slice s = kp * (n3 ... n_(p-1)) +
+ *   (k3, ..., k_(p-1)) in row-major order, kp the mode-p bin.
+ * tp_tnn_nd: that nuclear norm into the device double out (the slices with
+ *   mode-p bin 0 or, for even np, np/2 once, the others twice), FP64 sums.
+ * Errors as the 3-way calls.  nd = 1 computes exactly what tp_tprod (FP32),
+ * tp_prox_tnn and tp_tnn compute.
+ */
+size_t tp_tprod_nd_workspace_size(int n1, int n2, int l, int nd, const int* dims);
+int tp_tprod_nd(const float* A, const float* B, float* C, int n1, int n2, int l, int nd, const int* dims,
+                void* workspace, size_t workspace_bytes, void* stream);
+size_t tp_prox_tnn_nd_workspace_size(int n1, int n2, int nd, const int* dims);
+int tp_prox_tnn_nd(const float* Y, float* X, int n1, int n2, int nd, const int* dims, float tau, int* info,
+                   int* rank, void* workspace, size_t workspace_bytes, void* stream);
+size_t tp_tnn_nd_workspace_size(int n1, int n2, int nd, const int* dims);
+int tp_tnn_nd(const float* A, int n1, int n2, int nd, const int* dims, double* out, int* info, void* workspace,
+              size_t workspace_bytes, void* stream);
+
+/*
  * Batched tprod and prox_tnn over many tensors of uneven sizes (the slice
  * pipeline of Algorithms 1 and 3 applied to each tensor).  A plan lists the
  * work of every tensor; each stage of the pipeline is then one launch of a

@@ -24,6 +24,8 @@ __all__ = ["tp_tprod", "tp_tprod_workspace_size", "tp_tsvd", "tp_tsvd_workspace_
            "tp_tnn", "tp_tnn_workspace_size", "tp_prox_tnn_learned", "tp_prox_tnn_learned_workspace_size",
            "tp_slice_features", "tp_mlp_param_count", "tp_mlp_forward", "tp_mlp_loss_grad", "tp_mlp_adam",
            "tp_trace_enable", "tp_trace_collect_work", "tp_kernel_name", "TPBatch", "tp_batch_tprod",
+           "tp_tprod_nd", "tp_tprod_nd_workspace_size", "tp_prox_tnn_nd", "tp_prox_tnn_nd_workspace_size",
+           "tp_tnn_nd", "tp_tnn_nd_workspace_size", "tp_half_slices_nd",
            "tp_tsn", "tp_tubalrank", "tp_tran", "tp_teye",
            "tp_batch_prox",
            "half_slices", "TPError", "TP_PREC_FP32",
@@ -127,6 +129,87 @@ def tp_tnn(A, out=None, info=None, workspace=None):
     st = lib.tp_tnn(A.data_ptr(), n1, n2, n3, res.data_ptr(), _ptr(info), ws.data_ptr(), ws.numel(),
                     _stream(A.device))
     _lib.check("tp_tnn", st)
+    return res
+
+
+# ------------------------------------------------------------ order-p --
+def _dims(shape):
+    """Host int array of modes 3..p for the *_nd calls."""
+    d = (ctypes.c_int * len(shape))(*[int(v) for v in shape])
+    return len(shape), d
+
+
+def _nd_tensor(x, name):
+    if not isinstance(x, torch.Tensor) or not x.is_cuda:
+        raise TypeError(f"{name} must be a torch tensor on a GPU device")
+    if x.dtype != torch.float32:
+        raise TypeError(f"{name} must be float32")
+    if x.dim() < 3:
+        raise ValueError(f"{name} must have at least 3 dimensions")
+    return x.contiguous()
+
+
+def tp_half_slices_nd(dims):
+    """Fourier slices kept for modes 3..p of sizes dims: n3 ... n_(p-1) * (floor(np/2)+1)."""
+    r = 1
+    for v in dims[:-1]:
+        r *= int(v)
+    return r * (int(dims[-1]) // 2 + 1)
+
+
+def tp_tprod_nd_workspace_size(n1, n2, l, dims):
+    nd, d = _dims(dims)
+    return int(_lib.load().tp_tprod_nd_workspace_size(n1, n2, l, nd, d))
+
+
+def tp_tprod_nd(A, B, out=None, workspace=None):
+    """C = A * B for order-p tensors (A n1 x n2 x dims, B n2 x l x dims)."""
+    lib = _lib.load()
+    A = _nd_tensor(A, "A")
+    B = _nd_tensor(B, "B")
+    if B.dim() != A.dim() or B.shape[0] != A.shape[1] or B.shape[2:] != A.shape[2:]:
+        raise ValueError(f"shape mismatch: A {tuple(A.shape)}, B {tuple(B.shape)}")
+    n1, n2 = A.shape[:2]
+    l = B.shape[1]
+    nd, d = _dims(A.shape[2:])
+    C = out if out is not None else torch.empty((n1, l) + tuple(A.shape[2:]), dtype=torch.float32, device=A.device)
+    ws_bytes = lib.tp_tprod_nd_workspace_size(n1, n2, l, nd, d)
+    ws = workspace if workspace is not None else _workspace(ws_bytes, A.device)
+    st = lib.tp_tprod_nd(A.data_ptr(), B.data_ptr(), C.data_ptr(), n1, n2, l, nd, d, ws.data_ptr(), ws.numel(),
+                         _stream(A.device))
+    _lib.check("tp_tprod_nd", st)
+    return C
+
+
+def tp_prox_tnn_nd(Y, tau, out=None, info=None, rank=None, workspace=None):
+    """X = Prox_tau(Y) for an order-p tensor (SVT of every Fourier slice).
+
+    info / rank: optional int32 device tensors of tp_half_slices_nd(Y.shape[2:]) entries."""
+    lib = _lib.load()
+    Y = _nd_tensor(Y, "Y")
+    n1, n2 = Y.shape[:2]
+    nd, d = _dims(Y.shape[2:])
+    X = out if out is not None else torch.empty_like(Y)
+    ws_bytes = lib.tp_prox_tnn_nd_workspace_size(n1, n2, nd, d)
+    ws = workspace if workspace is not None else _workspace(ws_bytes, Y.device)
+    st = lib.tp_prox_tnn_nd(Y.data_ptr(), X.data_ptr(), n1, n2, nd, d, float(tau), _ptr(info), _ptr(rank),
+                            ws.data_ptr(), ws.numel(), _stream(Y.device))
+    _lib.check("tp_prox_tnn_nd", st)
+    return X
+
+
+def tp_tnn_nd(A, out=None, info=None, workspace=None):
+    """Nuclear norm of an order-p tensor; returns a 0-d float64 device tensor."""
+    lib = _lib.load()
+    A = _nd_tensor(A, "A")
+    n1, n2 = A.shape[:2]
+    nd, d = _dims(A.shape[2:])
+    res = out if out is not None else torch.empty((), dtype=torch.float64, device=A.device)
+    ws_bytes = lib.tp_tnn_nd_workspace_size(n1, n2, nd, d)
+    ws = workspace if workspace is not None else _workspace(ws_bytes, A.device)
+    st = lib.tp_tnn_nd(A.data_ptr(), n1, n2, nd, d, res.data_ptr(), _ptr(info), ws.data_ptr(), ws.numel(),
+                       _stream(A.device))
+    _lib.check("tp_tnn_nd", st)
     return res
 
 

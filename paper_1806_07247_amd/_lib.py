@@ -30,6 +30,12 @@ SIGNATURES = {
     "tp_prox_tnn": (_I, [_VP, _VP, _I, _I, _I, _F, _VP, _VP, _VP, _SZ, _VP]),
     "tp_tnn_workspace_size": (_SZ, [_I, _I, _I]),
     "tp_tnn": (_I, [_VP, _I, _I, _I, _VP, _VP, _VP, _SZ, _VP]),
+    "tp_tprod_nd_workspace_size": (_SZ, [_I, _I, _I, _I, _VP]),
+    "tp_tprod_nd": (_I, [_VP, _VP, _VP, _I, _I, _I, _I, _VP, _VP, _SZ, _VP]),
+    "tp_prox_tnn_nd_workspace_size": (_SZ, [_I, _I, _I, _VP]),
+    "tp_prox_tnn_nd": (_I, [_VP, _VP, _I, _I, _I, _VP, _F, _VP, _VP, _VP, _SZ, _VP]),
+    "tp_tnn_nd_workspace_size": (_SZ, [_I, _I, _I, _VP]),
+    "tp_tnn_nd": (_I, [_VP, _I, _I, _I, _VP, _VP, _VP, _VP, _SZ, _VP]),
     "tp_tsn_workspace_size": (_SZ, [_I, _I, _I]),
     "tp_tsn": (_I, [_VP, _I, _I, _I, _VP, _VP, _VP, _SZ, _VP]),
     "tp_tubalrank_workspace_size": (_SZ, [_I, _I, _I]),

@@ -66,11 +66,14 @@ struct SvtLayout {
     int* keep;         // per slice
     void* jscratch;    // Jacobi work matrices when a slice does not fit in LDS
     size_t jscratch_bytes;
+    tp::Planes tmp;    // transform scratch of order-p tensors (when asked for)
 };
 
-tp::Arena svt_arena(void* ws, size_t bytes, int n1, int n2, int n3, bool recon, SvtLayout* L, bool any_count = false)
+// the layout for h Fourier slices; tmp: scratch planes of h slices for the
+// transforms of order-p tensors when no reconstruction planes can serve
+tp::Arena svt_arena_h(void* ws, size_t bytes, int n1, int n2, size_t h, bool recon, SvtLayout* L,
+                      bool any_count = false, bool tmp = false)
 {
-    const size_t h = (size_t)tp::half_slices(n3);
     const size_t mn = (size_t)n1 * n2, p = (size_t)(n1 < n2 ? n1 : n2), P = p;
     tp::Arena ar(ws, bytes);
     SvtLayout t{};
@@ -90,11 +93,18 @@ tp::Arena svt_arena(void* ws, size_t bytes, int n1, int n2, int n3, bool recon, 
         if (one * h + 4096 > t.jscratch_bytes) t.jscratch_bytes = one * h + 4096;
     }
     t.jscratch = t.jscratch_bytes ? ar.take<char>(t.jscratch_bytes) : nullptr;
+    if (tmp) {
+        t.tmp.re = ar.take<float>(h * mn);
+        t.tmp.im = ar.take<float>(h * mn);
+    }
     if (L) *L = t;
     return ar;
 }
 
-
+tp::Arena svt_arena(void* ws, size_t bytes, int n1, int n2, int n3, bool recon, SvtLayout* L, bool any_count = false)
+{
+    return svt_arena_h(ws, bytes, n1, n2, (size_t)tp::half_slices(n3), recon, L, any_count);
+}
 
 // Matrix SVT W^(k) = U (S - tau)_+ V^* of `nslices` slices held in yb (planar
 // row-major n1 x n2 per slice), written back to yb: one-sided Jacobi on each
@@ -431,6 +441,51 @@ tp::Arena tsvd_arena(void* ws, size_t bytes, int n1, int n2, int n3, TsvdLayout*
     return ar;
 }
 
+// Order-p tensors: dims[0 .. nd-1] = n3 .. np (host array).  Shape check and
+// the slice counts: h = r * (floor(np/2)+1) Fourier slices, r = n3 ... n_(p-1).
+constexpr int kMaxNd = 8;
+constexpr long long kMaxSlicesNd = 65535;  // slice counts index a grid dimension
+
+int check_nd(int nd, const int* dims, long long* h, long long* r)
+{
+    if (nd < 1 || nd > kMaxNd) return TP_ERR_SHAPE;
+    if (!dims) return TP_ERR_ARG;
+    long long rr = 1;
+    for (int a = 0; a < nd; ++a) {
+        if (dims[a] <= 0 || dims[a] > kMaxN3) return TP_ERR_SHAPE;
+        if (a < nd - 1) rr *= dims[a];
+        if (rr > kMaxSlicesNd) return TP_ERR_SHAPE;
+    }
+    const long long hh = rr * (dims[nd - 1] / 2 + 1);
+    if (hh > kMaxSlicesNd) return TP_ERR_SHAPE;
+    *h = hh;
+    *r = rr;
+    return TP_OK;
+}
+
+// Workspace of tprod_nd: the A, B, C slices and one scratch set for the transforms.
+struct TprodNdLayout {
+    tp::Planes a, b, c, tmp;
+};
+
+tp::Arena tprod_nd_arena(void* ws, size_t bytes, int n1, int n2, int l, size_t h, TprodNdLayout* L)
+{
+    tp::Arena ar(ws, bytes);
+    TprodNdLayout t{};
+    const size_t sa = h * n1 * n2, sb = h * n2 * l, sc = h * n1 * l;
+    t.a.re = ar.take<float>(sa);
+    t.a.im = ar.take<float>(sa);
+    t.b.re = ar.take<float>(sb);
+    t.b.im = ar.take<float>(sb);
+    t.c.re = ar.take<float>(sc);
+    t.c.im = ar.take<float>(sc);
+    const size_t st = std::max(sa, std::max(sb, sc));
+    t.tmp.re = ar.take<float>(st);
+    t.tmp.im = ar.take<float>(st);
+    if (L) *L = t;
+    return ar;
+}
+
 }  // namespace
 
 namespace tp {
@@ -618,6 +673,125 @@ int tp_tnn(const float* A, int n1, int n2, int n3, double* out, int* info, void*
     j.tol = tp::jacobi_tol(tr ? n2 : n1);
     TP_LAUNCH(tp::K_JACOBI, s, tp::launch_jacobi(j, L.jscratch, L.jscratch_bytes, s));
     TP_LAUNCH(tp::K_TNN_REDUCE, s, tp::launch_tnn_reduce(L.sigma, h, tr ? n1 : n2, n3, out, s));
+    return TP_OK;
+}
+
+// ------------------------------------------------------ order-p tensors --
+size_t tp_tprod_nd_workspace_size(int n1, int n2, int l, int nd, const int* dims)
+{
+    long long h = 0, r = 0;
+    if (bad_dim(n1) || bad_dim(n2) || bad_dim(l) || check_nd(nd, dims, &h, &r) != TP_OK) return 0;
+    return tprod_nd_arena(nullptr, 0, n1, n2, l, (size_t)h, nullptr).used;
+}
+
+int tp_tprod_nd(const float* A, const float* B, float* C, int n1, int n2, int l, int nd, const int* dims,
+                void* workspace, size_t workspace_bytes, void* stream)
+{
+    if (!A || !B || !C) return TP_ERR_ARG;
+    long long h = 0, r = 0;
+    const int c = check_nd(nd, dims, &h, &r);
+    if (c != TP_OK) return c;
+    if (bad_dim(n1) || bad_dim(n2) || bad_dim(l)) return TP_ERR_SHAPE;
+    if (bad_slice(n1, n2) || bad_slice(n2, l) || bad_slice(n1, l)) return TP_ERR_SHAPE;
+    TprodNdLayout L;
+    tp::Arena ar = tprod_nd_arena(workspace, workspace_bytes, n1, n2, l, (size_t)h, &L);
+    if (!ar.ok) return TP_ERR_WORKSPACE;
+    hipStream_t s = as_stream(stream);
+    // DFT over modes 3..p of the frontal elements of A and B
+    TP_LAUNCH(tp::K_RFFT, s, tp::launch_rfft_nd(A, (long long)n1 * n2, nd, dims, L.a, L.tmp, s));
+    TP_LAUNCH(tp::K_RFFT, s, tp::launch_rfft_nd(B, (long long)n2 * l, nd, dims, L.b, L.tmp, s));
+    // the order-p form of eq (10): Cbar = Abar Bbar on every kept slice
+    tp::CgemmArgs g{};
+    g.ar = L.a.re;
+    g.ai = L.a.im;
+    g.lda = n2;
+    g.sa = (long long)n1 * n2;
+    g.br = L.b.re;
+    g.bi = L.b.im;
+    g.ldb = l;
+    g.sb = (long long)n2 * l;
+    g.cr = L.c.re;
+    g.ci = L.c.im;
+    g.ldc = l;
+    g.sc = (long long)n1 * l;
+    g.m = n1;
+    g.n = l;
+    g.k = n2;
+    g.nslices = (int)h;
+    g.real_first = 1;  // all bins 0
+    g.real_last = (nd == 1 && dims[0] % 2 == 0) ? 1 : 0;
+    TP_LAUNCH(tp::K_CGEMM, s, tp::launch_cgemm(g, tp::OP_N, tp::OP_N, TP_PREC_FP32, s));
+    TP_LAUNCH(tp::K_IRFFT, s, tp::launch_irfft_nd(L.c, L.tmp, C, (long long)n1 * l, nd, dims, s));
+    return TP_OK;
+}
+
+size_t tp_prox_tnn_nd_workspace_size(int n1, int n2, int nd, const int* dims)
+{
+    long long h = 0, r = 0;
+    if (bad_dim(n1) || bad_dim(n2) || check_nd(nd, dims, &h, &r) != TP_OK) return 0;
+    return svt_arena_h(nullptr, 0, n1, n2, (size_t)h, true, nullptr).used;
+}
+
+int tp_prox_tnn_nd(const float* Y, float* X, int n1, int n2, int nd, const int* dims, float tau, int* info,
+                   int* rank, void* workspace, size_t workspace_bytes, void* stream)
+{
+    if (!Y || !X) return TP_ERR_ARG;
+    if (!(tau >= 0.0f) || std::isinf(tau)) return TP_ERR_ARG;
+    long long h = 0, r = 0;
+    const int c = check_nd(nd, dims, &h, &r);
+    if (c != TP_OK) return c;
+    if (bad_dim(n1) || bad_dim(n2) || bad_slice(n1, n2)) return TP_ERR_SHAPE;
+    if ((n1 < n2 ? n2 : n1) > 2048) return TP_ERR_UNSUPPORTED;
+    SvtLayout L;
+    tp::Arena ar = svt_arena_h(workspace, workspace_bytes, n1, n2, (size_t)h, true, &L);
+    if (!ar.ok) return TP_ERR_WORKSPACE;
+    hipStream_t s = as_stream(stream);
+    const long long mn = (long long)n1 * n2;
+    // the rotated-column planes are free until the SVT and after it: transform scratch
+    TP_LAUNCH(tp::K_RFFT, s, tp::launch_rfft_nd(Y, mn, nd, dims, L.ybar, L.w, s));
+    const int st = run_svt(L, L.ybar, n1, n2, (int)h, 1, (nd == 1 && dims[0] % 2 == 0) ? 1 : 0, (double)tau,
+                           info, rank, s);
+    if (st != TP_OK) return st;
+    TP_LAUNCH(tp::K_IRFFT, s, tp::launch_irfft_nd(L.ybar, L.w, X, mn, nd, dims, s));
+    return TP_OK;
+}
+
+size_t tp_tnn_nd_workspace_size(int n1, int n2, int nd, const int* dims)
+{
+    long long h = 0, r = 0;
+    if (bad_dim(n1) || bad_dim(n2) || check_nd(nd, dims, &h, &r) != TP_OK) return 0;
+    return svt_arena_h(nullptr, 0, n1, n2, (size_t)h, false, nullptr, false, true).used;
+}
+
+int tp_tnn_nd(const float* A, int n1, int n2, int nd, const int* dims, double* out, int* info, void* workspace,
+              size_t workspace_bytes, void* stream)
+{
+    if (!A || !out) return TP_ERR_ARG;
+    long long h = 0, r = 0;
+    const int c = check_nd(nd, dims, &h, &r);
+    if (c != TP_OK) return c;
+    if (bad_dim(n1) || bad_dim(n2) || bad_slice(n1, n2)) return TP_ERR_SHAPE;
+    if ((n1 < n2 ? n2 : n1) > 2048) return TP_ERR_UNSUPPORTED;
+    SvtLayout L;
+    tp::Arena ar = svt_arena_h(workspace, workspace_bytes, n1, n2, (size_t)h, false, &L, false, true);
+    if (!ar.ok) return TP_ERR_WORKSPACE;
+    hipStream_t s = as_stream(stream);
+    const bool tr = n1 < n2;
+    TP_LAUNCH(tp::K_RFFT, s, tp::launch_rfft_nd(A, (long long)n1 * n2, nd, dims, L.ybar, L.tmp, s));
+    tp::JacobiArgs j{};
+    j.yr = L.ybar.re;
+    j.yi = L.ybar.im;
+    j.sigma = L.sigma;
+    j.info = info;
+    j.m = n1;
+    j.n = n2;
+    j.nslices = (int)h;
+    j.max_sweeps = tp::param(TP_PARAM_JACOBI_SWEEPS);
+    j.transpose = tr ? 1 : 0;
+    j.tol = tp::jacobi_tol(tr ? n2 : n1);
+    TP_LAUNCH(tp::K_JACOBI, s, tp::launch_jacobi(j, L.jscratch, L.jscratch_bytes, s));
+    TP_LAUNCH(tp::K_TNN_REDUCE, s,
+              tp::launch_tnn_reduce(L.sigma, (int)h, tr ? n1 : n2, dims[nd - 1], out, s, (int)r));
     return TP_OK;
 }
 

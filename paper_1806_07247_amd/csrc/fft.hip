@@ -584,6 +584,76 @@ __global__ __launch_bounds__(kTubes) void k_fft_batch(const FftUnit* __restrict_
     }
 }
 
+// ------------------------------------------------------ order-p tensors --
+// Complex DFT along one axis of planar complex data laid out [outer][n][inner]:
+// y[o][k][i] = scale * sum_t x[o][t][i] W_n^(+-k t) (direct, twiddles computed
+// per workgroup in double precision and rounded once, as k_rdft_any).  One
+// output per thread, inner index fastest, so reads of a row are shared by
+// neighbouring threads.
+__global__ __launch_bounds__(256) void k_cdft_axis(const float* __restrict__ xr, const float* __restrict__ xi,
+                                                   float* __restrict__ yr, float* __restrict__ yi, long long outer,
+                                                   int n, long long inner, int inverse)
+{
+    extern __shared__ float2 tws[];
+    fill_twiddles(tws, n);
+    __syncthreads();
+    const float sgn = inverse ? -1.0f : 1.0f, scale = inverse ? 1.0f / (float)n : 1.0f;
+    const long long total = outer * n * inner;
+    for (long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x; e < total;
+         e += (long long)gridDim.x * blockDim.x) {
+        const long long i = e % inner, ok = e / inner;
+        const int k = (int)(ok % n);
+        const long long base = (ok / n) * n * inner + i;
+        float sr = 0.0f, si = 0.0f;
+        int idx = 0;
+        for (int t = 0; t < n; ++t) {
+            const float a = xr[base + (long long)t * inner], b = xi[base + (long long)t * inner];
+            const float2 w = tws[idx];
+            const float wi = sgn * w.y;
+            sr += a * w.x - b * wi;
+            si += a * wi + b * w.x;
+            idx += k;
+            if (idx >= n) idx -= n;
+        }
+        yr[e] = sr * scale;
+        yi[e] = si * scale;
+    }
+}
+
+// Planar complex batched transpose [P][M][R] -> [P][R][M] through 32 x 32
+// LDS tiles (coalesced on both sides); tiles walked by a persistent grid.
+__global__ __launch_bounds__(256) void k_transpose_planes(const float* __restrict__ xr, const float* __restrict__ xi,
+                                                          float* __restrict__ yr, float* __restrict__ yi, long long P,
+                                                          long long M, long long R)
+{
+    __shared__ float tr[32][33], ti[32][33];
+    const long long tm = (M + 31) / 32, tn = (R + 31) / 32, ntiles = P * tm * tn;
+    const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;
+    for (long long t = blockIdx.x; t < ntiles; t += gridDim.x) {
+        const long long p = t / (tm * tn), rem = t % (tm * tn), m0 = (rem / tn) * 32, r0 = (rem % tn) * 32;
+        const float* sr = xr + p * M * R;
+        const float* si = xi + p * M * R;
+        __syncthreads();
+        for (int yy = ty; yy < 32; yy += 8) {
+            const long long m = m0 + yy, r = r0 + tx;
+            if (m < M && r < R) {
+                tr[yy][tx] = sr[m * R + r];
+                ti[yy][tx] = si[m * R + r];
+            }
+        }
+        __syncthreads();
+        float* dr = yr + p * M * R;
+        float* di = yi + p * M * R;
+        for (int yy = ty; yy < 32; yy += 8) {
+            const long long r = r0 + yy, m = m0 + tx;
+            if (m < M && r < R) {
+                dr[r * M + m] = tr[tx][yy];
+                di[r * M + m] = ti[tx][yy];
+            }
+        }
+    }
+}
+
 inline int grid_for(long long ntubes, int tpb)
 {
     long long g = (ntubes + tpb - 1) / tpb;
@@ -679,6 +749,74 @@ hipError_t launch_rfft_split(const float* x, const SplitOut& o, int n3, hipStrea
     const size_t lds = (size_t)(4 * tpb * (n3 + 1) + 8 * n3);
     k_rdft_split_any<<<grid_for(total, tpb), tpb, lds, s>>>(x, o, n3);
     return hipGetLastError();
+}
+
+namespace {
+hipError_t launch_cdft(Planes x, Planes y, long long outer, int n, long long inner, int inverse, hipStream_t s)
+{
+    const long long total = outer * n * inner;
+    if (total <= 0) return hipSuccess;
+    trace_work(8.0 * total * n, 16.0 * total);
+    const long long g = (total + 255) / 256, cap = 256LL * 64;
+    k_cdft_axis<<<(unsigned)(g < cap ? g : cap), 256, (size_t)n * sizeof(float2), s>>>(x.re, x.im, y.re, y.im,
+                                                                                      outer, n, inner, inverse);
+    return hipGetLastError();
+}
+
+hipError_t launch_transpose(Planes x, Planes y, long long P, long long M, long long R, hipStream_t s)
+{
+    const long long tiles = P * ((M + 31) / 32) * ((R + 31) / 32);
+    if (tiles <= 0) return hipSuccess;
+    trace_work(0.0, 16.0 * P * M * R);
+    const long long cap = 256LL * 32;
+    k_transpose_planes<<<(unsigned)(tiles < cap ? tiles : cap), 256, 0, s>>>(x.re, x.im, y.re, y.im, P, M, R);
+    return hipGetLastError();
+}
+
+long long prod_dims(const int* dims, int from, int to)
+{
+    long long p = 1;
+    for (int a = from; a < to; ++a) p *= dims[a];
+    return p;
+}
+}  // namespace
+
+hipError_t launch_rfft_nd(const float* x, long long mrow, int nd, const int* dims, Planes dst, Planes tmp,
+                          hipStream_t s)
+{
+    const int N = dims[nd - 1], hp = N / 2 + 1;
+    const long long r = prod_dims(dims, 0, nd - 1);
+    if (nd == 1) return launch_rfft(x, dst.re, dst.im, mrow, N, s);
+    // nd passes follow the real transform (nd - 1 complex DFTs, one transpose)
+    Planes cur = (nd % 2 == 0) ? dst : tmp, oth = (nd % 2 == 0) ? tmp : dst;
+    hipError_t e = launch_rfft(x, cur.re, cur.im, mrow * r, N, s);  // [kp][e][rest]
+    if (e != hipSuccess) return e;
+    for (int a = 0; a < nd - 1; ++a) {
+        const long long outer = (long long)hp * mrow * prod_dims(dims, 0, a), inner = prod_dims(dims, a + 1, nd - 1);
+        if ((e = launch_cdft(cur, oth, outer, dims[a], inner, 0, s)) != hipSuccess) return e;
+        const Planes t = cur;
+        cur = oth;
+        oth = t;
+    }
+    return launch_transpose(cur, oth, hp, mrow, r, s);  // [kp][rest][e] in dst
+}
+
+hipError_t launch_irfft_nd(Planes src, Planes tmp, float* x, long long mrow, int nd, const int* dims, hipStream_t s)
+{
+    const int N = dims[nd - 1], hp = N / 2 + 1;
+    const long long r = prod_dims(dims, 0, nd - 1);
+    if (nd == 1) return launch_irfft(src.re, src.im, x, mrow, N, s);
+    hipError_t e = launch_transpose(src, tmp, hp, r, mrow, s);  // [kp][e][rest]
+    if (e != hipSuccess) return e;
+    Planes cur = tmp, oth = src;
+    for (int a = nd - 2; a >= 0; --a) {
+        const long long outer = (long long)hp * mrow * prod_dims(dims, 0, a), inner = prod_dims(dims, a + 1, nd - 1);
+        if ((e = launch_cdft(cur, oth, outer, dims[a], inner, 1, s)) != hipSuccess) return e;
+        const Planes t = cur;
+        cur = oth;
+        oth = t;
+    }
+    return launch_irfft(cur.re, cur.im, x, mrow * r, N, s);
 }
 
 size_t max_fft_length() { return 1024; }

@@ -1147,13 +1147,16 @@ __global__ __launch_bounds__(256) void k_shrink_batch(const ShrinkItem* __restri
 
 // tnn = (1/n3) sum_k w_k sum_j sigma_kj, w_k = 1 for real slices, 2 otherwise
 // (Definition 2.9 with eq (14), using the conjugate symmetry of eq (8)).
+// slice s has last-mode bin s / period (period = 1 for p = 3); the bins 0 and,
+// for even n3, n3/2 are their own conjugates, the others stand for two
 __global__ __launch_bounds__(256) void k_tnn_reduce(const double* __restrict__ sigma, int nslices, int P, int n3,
-                                                    double* __restrict__ out)
+                                                    int period, double* __restrict__ out)
 {
     __shared__ double part[256];
     double acc = 0.0;
     for (int s = 0; s < nslices; ++s) {  // fixed order: deterministic
-        const bool real = (s == 0) || (n3 % 2 == 0 && s == n3 / 2);
+        const int kp = s / period;
+        const bool real = (kp == 0) || (n3 % 2 == 0 && kp == n3 / 2);
         double v = 0.0;
         for (int j = threadIdx.x; j < P; j += blockDim.x) v += sigma[(long long)s * P + j];
         acc += real ? v : 2.0 * v;
@@ -1164,7 +1167,7 @@ __global__ __launch_bounds__(256) void k_tnn_reduce(const double* __restrict__ s
         if (threadIdx.x < w) part[threadIdx.x] += part[threadIdx.x + w];
         __syncthreads();
     }
-    if (threadIdx.x == 0) *out = part[0] / (double)n3;
+    if (threadIdx.x == 0) *out = part[0] / ((double)n3 * period);
 }
 
 }  // namespace
@@ -1272,9 +1275,10 @@ hipError_t launch_tubal_rank(const double* sigma, double* sorted, int nslices, i
     return hipGetLastError();
 }
 
-hipError_t launch_tnn_reduce(const double* sigma, int nslices, int P, int n3, double* out, hipStream_t st)
+hipError_t launch_tnn_reduce(const double* sigma, int nslices, int P, int n3, double* out, hipStream_t st,
+                             int period)
 {
-    k_tnn_reduce<<<1, 256, 0, st>>>(sigma, nslices, P, n3, out);
+    k_tnn_reduce<<<1, 256, 0, st>>>(sigma, nslices, P, n3, period, out);
     return hipGetLastError();
 }
 

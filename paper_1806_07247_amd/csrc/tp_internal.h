@@ -68,6 +68,18 @@ hipError_t launch_rfft(const float* x, float* re, float* im, long long ntubes, i
 // spectrum; the imaginary parts of slice 0 (and n3/2 for even n3) are ignored.
 hipError_t launch_irfft(const float* re, const float* im, float* x, long long ntubes, int n3, hipStream_t s);
 
+// Order-p tensors (p = 2 + nd; dims[0 .. nd-1] = n3 .. np, host array): the
+// DFT over modes 3..p of every frontal element.  x is C-ordered
+// (mrow = n1*n2 frontal elements, then modes 3..p, np fastest).  The output
+// dst holds h = n3 ... n_(p-1) * (floor(np/2)+1) slices of mrow elements,
+// slice s = kp * (n3 ... n_(p-1)) + (k3, ..., k_(p-1)) (row-major), kp the
+// bin of the last mode (the others' conjugates implicit, as for p = 3).
+// tmp is scratch planes of the same size.  nd = 1 is launch_rfft.
+hipError_t launch_rfft_nd(const float* x, long long mrow, int nd, const int* dims, Planes dst, Planes tmp,
+                          hipStream_t s);
+// Inverse of launch_rfft_nd; src and tmp are both overwritten.
+hipError_t launch_irfft_nd(Planes src, Planes tmp, float* x, long long mrow, int nd, const int* dims, hipStream_t s);
+
 // Forward transform written as bf16 planes for the bf16 slice products.
 // Per bin k the planes hold an outer x ld matrix (element (o, i) is bin k of
 // tube q = o*q_outer + i*q_inner of x for i < inner, and 0 for
@@ -234,7 +246,10 @@ hipError_t launch_tsvd_finish(const float2* cols, const double* sigma, const flo
 hipError_t launch_shrink(float* wr, float* wi, const double* sigma, int* keep, int R, int P, int nslices, double tau,
                          hipStream_t s, const int* count = nullptr);
 // (1/n3) sum over all n3 slices of the singular values, from the half spectrum
-hipError_t launch_tnn_reduce(const double* sigma, int nslices, int P, int n3, double* out, hipStream_t s);
+// (1/(n3*period)) sum of sigma over the slices, weighted 1 for self-conjugate
+// last-mode bins (slice / period = 0 or n3/2) and 2 for the others
+hipError_t launch_tnn_reduce(const double* sigma, int nslices, int P, int n3, double* out, hipStream_t s,
+                             int period = 1);
 
 // ------------------------------------------------------------- learned ----
 constexpr int kMaxL = 64;  // widest randomized sketch (l_max)

@@ -110,3 +110,16 @@ def batch_tensors(shapes, seed=0):
 
 def random_tensor(shape, seed=0, var=1.0):
     return gaussian(_streams(seed, 6)[0], shape, var)
+
+
+def tensor_nd(shape, seed=0, var=1.0):
+    """An order-p tensor of the given shape, i.i.d. N(0, var), float32."""
+    return gaussian(_streams(seed, 7)[0], tuple(shape), var)
+
+
+def lowrank_nd(n1, n2, dims, r, seed=0):
+    """P * Q of order p (P n1 x r x dims, Q r x n2 x dims, i.i.d. N(0, 1/n1)),
+    returned as the two factors; the product is formed by the caller."""
+    rp, rq = _streams(seed, 8)[:2]
+    return gaussian(rp, (n1, r) + tuple(dims), 1.0 / n1), gaussian(rq, (r, n2) + tuple(dims), 1.0 / n1)
+

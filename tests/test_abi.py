@@ -139,3 +139,35 @@ def test_trpca_argument_errors(lib):
     lo.max_rank = 16
     good_l = _lib.TrpcaOpts(0.0, 1e-3, 1.1, 1e10, 1e-5, 500, ctypes.pointer(lo))
     assert lib.tp_trpca_workspace_size(6, 5, 4, ctypes.byref(good_l)) > ws
+
+
+def test_nd_argument_errors(lib):
+    """Order-p calls: shapes and the host dims array are checked before
+    anything is enqueued (the fake device pointers are never touched)."""
+    D = ctypes.c_int * 4
+    dims = D(3, 4, 5, 6)
+    ws = lib.tp_tprod_nd_workspace_size(4, 3, 2, 3, dims)
+    assert ws > 0
+    assert lib.tp_tprod_nd(FAKE, FAKE, FAKE, 4, 3, 2, 0, dims, FAKE, ws, None) == -2
+    assert lib.tp_tprod_nd(FAKE, FAKE, FAKE, 4, 3, 2, 9, dims, FAKE, ws, None) == -2
+    assert lib.tp_tprod_nd(FAKE, FAKE, FAKE, 4, 3, 2, 2, None, FAKE, ws, None) == -1
+    assert lib.tp_tprod_nd(None, FAKE, FAKE, 4, 3, 2, 2, dims, FAKE, ws, None) == -1
+    assert lib.tp_tprod_nd(FAKE, FAKE, FAKE, 4, 3, 2, 2, D(3, 0), FAKE, ws, None) == -2
+    assert lib.tp_tprod_nd(FAKE, FAKE, FAKE, 4, 3, 2, 2, D(3, 1025), FAKE, ws, None) == -2
+    # more than 65535 kept slices: 300 * 300 * (2/2 + 1)
+    assert lib.tp_tprod_nd(FAKE, FAKE, FAKE, 4, 3, 2, 3, D(300, 300, 2), FAKE, ws, None) == -2
+    assert lib.tp_tprod_nd_workspace_size(4, 3, 2, 3, D(300, 300, 2)) == 0
+    assert lib.tp_tprod_nd(FAKE, FAKE, FAKE, 4, 3, 2, 3, dims, FAKE, ws - 1, None) == -3
+    # the workspace holds three slice stacks and a scratch stack; nd = 3 reads
+    # dims 3, 4, 5: 3 * 4 * (5/2 + 1) = 36 slices
+    need = sum(2 * 36 * e * 4 for e in (4 * 3, 3 * 2, 4 * 2, 4 * 3))
+    assert ws >= need
+    pw = lib.tp_prox_tnn_nd_workspace_size(6, 5, 2, dims)
+    assert pw > 0
+    assert lib.tp_prox_tnn_nd(FAKE, FAKE, 6, 5, 2, dims, ctypes.c_float(-1.0), None, None, FAKE, pw, None) == -1
+    assert lib.tp_prox_tnn_nd(FAKE, FAKE, 6, 5, 2, dims, ctypes.c_float(0.5), None, None, FAKE, pw - 1, None) == -3
+    assert lib.tp_prox_tnn_nd(FAKE, FAKE, 6, 3000, 2, dims, ctypes.c_float(0.5), None, None, FAKE, pw, None) == -5
+    tw = lib.tp_tnn_nd_workspace_size(6, 5, 2, dims)
+    assert tw > 0
+    assert lib.tp_tnn_nd(FAKE, 6, 5, 2, dims, None, None, FAKE, tw, None) == -1
+    assert lib.tp_tnn_nd(FAKE, 6, 5, 2, dims, FAKE, None, FAKE, tw - 1, None) == -3
