@@ -335,11 +335,38 @@ int tp_tqr(const float* A, float* Q, float* R, int n1, int n2, int n3, void* wor
  *              as features, its range basis as warm start, seed + i for call
  *              i), so learned->prev_rank, prev_sigma, warm_basis, warm_cols,
  *              basis_out and basis_cols_out are ignored.
+ *              record: NULL, or where to keep what each prox call saw and
+ *              did (tp_trpca_record), for training the rank predictor and
+ *              for replaying the calls.
  * Errors: TP_ERR_ARG (null pointers, mu <= 0, rho < 1, mu_max < mu or
  * infinite, tol < 0, max_iter < 1, a learned max_rank outside 1..64, a NaN
- * in X), TP_ERR_SHAPE, TP_ERR_WORKSPACE, or the prox's error.  The call waits
- * for the stream once per iteration (the stopping test is read on the host).
+ * in X, a record with max_calls < 0), TP_ERR_SHAPE, TP_ERR_WORKSPACE, or the
+ * prox's error.  The call waits for the stream once per iteration (the
+ * stopping test is read on the host).
  */
+/* Per-call record of tp_trpca: call i (0-based, i < max_calls; later calls
+ * are not kept) has tau_i = 1/mu_i, mu_0 = mu, mu_(i+1) = min(rho mu_i,
+ * mu_max) in double precision, and the learned prox's seed + i.  Every
+ * buffer is optional (NULL) device memory with max_calls rows; h =
+ * floor(n3/2)+1.
+ *   inputs       float[max_calls][n1*n2*n3]: the prox input Y_i
+ *   features     float[max_calls][h][TP_MLP_INPUTS]: tp_slice_features of
+ *                Y_i (with call i-1's counts and singular values for the
+ *                learned prox, none for the full one)
+ *   counts       int[max_calls][h]: the learned prox's count per slice
+ *   sigmas       float[max_calls][h][TP_SIGMA_KEEP]: its sigma_out
+ *   bases        float[max_calls][2][h][n2][max_rank]: its basis_out
+ *   basis_cols   int[max_calls][h]: its basis_cols_out
+ * (counts, sigmas, bases and basis_cols need the learned prox.) */
+typedef struct tp_trpca_record {
+    int max_calls;
+    float* inputs;
+    float* features;
+    int* counts;
+    float* sigmas;
+    float* bases;
+    int* basis_cols;
+} tp_trpca_record;
 typedef struct tp_trpca_opts {
     float lambda;                   /* <= 0: 1/sqrt(max(n1, n2) n3) */
     float mu;                       /* initial penalty (1e-3) */
@@ -348,6 +375,7 @@ typedef struct tp_trpca_opts {
     float tol;                      /* relative stopping tolerance (1e-5) */
     int max_iter;                   /* iteration cap (500) */
     const tp_learned_opts* learned; /* NULL: full-SVD prox; else learned-rank prox settings */
+    const tp_trpca_record* record;  /* NULL, or per-call records */
 } tp_trpca_opts;
 size_t tp_trpca_workspace_size(int n1, int n2, int n3, const tp_trpca_opts* opts);
 int tp_trpca(const float* X, float* L, float* S, int n1, int n2, int n3, const tp_trpca_opts* opts, float* Lam,
@@ -503,6 +531,13 @@ int tp_batch_destroy(tp_batch* plan);
  *                                 staged in LDS; 2 = one launch per sweep, the
  *                                 column pairs in registers; 0 = by slice height
  *                                 (per sweep above 256 rows)
+ *   TP_PARAM_RETRY_ROUNDS         learned-rank prox: accuracy rounds of the wide
+ *                                 retry attempt (0 = default 2; at most the
+ *                                 first attempt's max_power_iters - power_iters)
+ * The bf16 slice products (TP_PREC_BF16X3, TP_PREC_BF16) read
+ * TP_PARAM_GEMM_VARIANT as: 1 = 64x64, 2 = 128x128, 3 = 128x32 tiles on
+ * 16x16x32 products, 4 = 256x128 and 5 = 128x128 on 32x32x16 products,
+ * 6 .. 8 = 64x64 (0 = by shape); the workspace size depends on the choice.
  */
 enum {
     TP_PARAM_JACOBI_BLOCK = 0,
@@ -515,7 +550,8 @@ enum {
     TP_PARAM_GEMM_BK = 7,
     TP_PARAM_GEMM_KSPLIT = 8,
     TP_PARAM_JACOBI_STEPWISE = 9,
-    TP_PARAM_COUNT = 10
+    TP_PARAM_RETRY_ROUNDS = 10,
+    TP_PARAM_COUNT = 11
 };
 int tp_set_param(int key, int value);
 int tp_get_param(int key);

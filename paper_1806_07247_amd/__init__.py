@@ -25,7 +25,7 @@ __all__ = ["tp_tprod", "tp_tprod_workspace_size", "tp_tsvd", "tp_tsvd_workspace_
            "tp_slice_features", "tp_mlp_param_count", "tp_mlp_forward", "tp_mlp_loss_grad", "tp_mlp_adam",
            "tp_trace_enable", "tp_trace_collect_work", "tp_kernel_name", "TPBatch", "tp_batch_tprod",
            "tp_tprod_nd", "tp_tprod_nd_workspace_size", "tp_prox_tnn_nd", "tp_prox_tnn_nd_workspace_size",
-           "tp_tnn_nd", "tp_tnn_nd_workspace_size", "tp_half_slices_nd",
+           "tp_tnn_nd", "tp_tnn_nd_workspace_size", "tp_half_slices_nd", "tp_trpca_taus",
            "tp_tsn", "tp_tubalrank", "tp_tran", "tp_teye",
            "tp_batch_prox",
            "half_slices", "TPError", "TP_PREC_FP32",
@@ -238,7 +238,7 @@ def tp_prox_tnn_learned_workspace_size(n1, n2, n3, max_rank=64):
 
 
 def tp_prox_tnn_learned(Y, tau, mlp=None, fixed_rank=0, prev_rank=None, prev_sigma=None, oversample=10,
-                        power_iters=2, max_rank=64, seed=0, accuracy=2e-5, max_power_iters=4, retry_wide=True,
+                        power_iters=2, max_rank=64, seed=0, accuracy=2e-5, max_power_iters=8, retry_wide=True,
                         accuracy_ref=0, warm_basis=None, warm_cols=None, basis_out=None, basis_cols_out=None,
                         out=None, rank=None, fallback=None, info=None, sigma_out=None, workspace=None):
     """Learned-rank prox (see include/tp.h); mlp is a float32 device tensor of
@@ -314,13 +314,27 @@ def tp_trpca_workspace_size_for(shape, learned=None, **kw):
     return int(_lib.load().tp_trpca_workspace_size(n1, n2, n3, ctypes.byref(opts)))
 
 
+def tp_trpca_taus(count, mu=1e-3, rho=1.1, mu_max=1e10):
+    """tau of the first `count` prox calls of tp_trpca (tau_i = 1/mu_i, the
+    penalty updated in double precision from the float32 settings)."""
+    f = ctypes.c_float
+    m, r, mx = float(f(mu).value), float(f(rho).value), float(f(mu_max).value)
+    out = []
+    for _ in range(count):
+        out.append(float(f(1.0 / m).value))
+        m = min(r * m, mx)
+    return out
+
+
 def tp_trpca(X, lam=None, mu=1e-3, rho=1.1, mu_max=1e10, tol=1e-5, max_iter=500, learned=None, L=None, S=None,
-             Lam=None, workspace=None):
+             Lam=None, workspace=None, record=None):
     """Tensor robust PCA (include/tp.h): min ||L||_* + lam ||S||_1 s.t. L + S = X
     by the inexact ALM, natively.  learned: None for the full-SVD prox, else a
     dict of tp_prox_tnn_learned settings (mlp, fixed_rank, oversample,
     power_iters, max_rank, seed, accuracy, max_power_iters, retry_wide,
-    accuracy_ref).  Returns dict(L, S, Lam (if given), iters, converged)."""
+    accuracy_ref).  record: None or a dict with max_calls and any of the
+    device tensors inputs, features, counts, sigmas, bases, basis_cols
+    (tp_trpca_record).  Returns dict(L, S, Lam (if given), iters, converged)."""
     lib = _lib.load()
     X = _dev_tensor(X, "X")
     n1, n2, n3 = X.shape
@@ -333,14 +347,20 @@ def tp_trpca(X, lam=None, mu=1e-3, rho=1.1, mu_max=1e10, tol=1e-5, max_iter=500,
     lo = None
     if learned is not None:
         d = dict(mlp=None, fixed_rank=0, oversample=10, power_iters=2, max_rank=64, seed=0, accuracy=2e-5,
-                 max_power_iters=4, retry_wide=True, accuracy_ref=0)
+                 max_power_iters=8, retry_wide=True, accuracy_ref=0)
         d.update(learned)
         lo = _lib.LearnedOpts(_ptr(d["mlp"]), int(d["fixed_rank"]), None, None, int(d["oversample"]),
                               int(d["power_iters"]), int(d["max_rank"]), int(d["seed"]) & 0xFFFFFFFFFFFFFFFF,
                               float(d["accuracy"]), int(d["max_power_iters"]), int(bool(d["retry_wide"])),
                               int(d["accuracy_ref"]), None, None, None, None)
+    rec = None
+    if record is not None:
+        rec = _lib.TrpcaRecord(int(record["max_calls"]), *[_ptr(record.get(k)) for k in
+                                                           ("inputs", "features", "counts", "sigmas", "bases",
+                                                            "basis_cols")])
     opts = _lib.TrpcaOpts(float(lam) if lam is not None else 0.0, float(mu), float(rho), float(mu_max), float(tol),
-                          int(max_iter), ctypes.pointer(lo) if lo is not None else None)
+                          int(max_iter), ctypes.pointer(lo) if lo is not None else None,
+                          ctypes.pointer(rec) if rec is not None else None)
     ws_bytes = lib.tp_trpca_workspace_size(n1, n2, n3, ctypes.byref(opts))
     if ws_bytes == 0:
         raise ValueError("bad TRPCA settings")

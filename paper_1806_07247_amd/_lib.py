@@ -70,10 +70,16 @@ SIGNATURES.update({
 })
 
 
+class TrpcaRecord(ctypes.Structure):
+    """tp_trpca_record of include/tp.h"""
+    _fields_ = [("max_calls", _I), ("inputs", _VP), ("features", _VP), ("counts", _VP), ("sigmas", _VP),
+                ("bases", _VP), ("basis_cols", _VP)]
+
+
 class TrpcaOpts(ctypes.Structure):
     """tp_trpca_opts of include/tp.h"""
     _fields_ = [("lam", _F), ("mu", _F), ("rho", _F), ("mu_max", _F), ("tol", _F), ("max_iter", _I),
-                ("learned", ctypes.POINTER(LearnedOpts))]
+                ("learned", ctypes.POINTER(LearnedOpts)), ("record", ctypes.POINTER(TrpcaRecord))]
 
 
 SIGNATURES.update({

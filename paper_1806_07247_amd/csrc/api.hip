@@ -1001,11 +1001,11 @@ int tp_prox_tnn_learned(const float* Y, float* X, int n1, int n2, int n3, float 
     const long long sy = (long long)n1 * L, sz = (long long)n2 * L, sl = (long long)L * L;
 
     // One attempt of the randomized SVT, run when *gate != 0 at sketch width *width.
-    // (the retry attempt has at most one extra accuracy round: it already
-    // runs at the widest sketch)
+    // (the retry attempt, at the widest sketch, has TP_PARAM_RETRY_ROUNDS
+    // accuracy rounds, at most as many as the first)
     auto attempt = [&](int a, const int* gate, const int* width) -> int {
         int st = TP_OK;
-        const int nround = a == 0 ? rounds : std::min(rounds, 1);
+        const int nround = a == 0 ? rounds : std::min(rounds, tp::param(TP_PARAM_RETRY_ROUNDS));
         // range finder: Y = Ybar Om, re-orthonormalised; power iterations
         TP_LAUNCH(tp::K_SKETCH, s,
                   tp::launch_sketch(W.om.re, W.om.im, n2, L, W.lact, h, n3, opts->seed, warm, s, gate));

@@ -182,6 +182,8 @@ struct TrpcaLayout {
     int* fallback;
     void* prox_ws;
     size_t prox_bytes;
+    void* feat_ws;  // tp_slice_features workspace when features are recorded
+    size_t feat_bytes;
 };
 
 tp::Arena trpca_arena(void* ws, size_t bytes, int n1, int n2, int n3, const tp_trpca_opts* o, bool own_lam,
@@ -210,6 +212,10 @@ tp::Arena trpca_arena(void* ws, size_t bytes, int n1, int n2, int n3, const tp_t
     }
     t.prox_ws = t.prox_bytes ? ar.take<char>(t.prox_bytes) : nullptr;
     if (o->learned && t.prox_bytes == 0) ar.ok = false;  // max_rank or shape rejected by the prox
+    if (o->record && o->record->features) {
+        t.feat_bytes = tp_slice_features_workspace_size(n1, n2, n3);
+        t.feat_ws = t.feat_bytes ? ar.take<char>(t.feat_bytes) : nullptr;
+    }
     if (out) *out = t;
     return ar;
 }
@@ -218,7 +224,8 @@ bool bad_opts(const tp_trpca_opts* o)
 {
     return !o || !(o->mu > 0.0f) || !(o->rho >= 1.0f) || !(o->mu_max >= o->mu) || !(o->tol >= 0.0f) ||
            o->max_iter < 1 || std::isnan(o->lambda) || std::isinf(o->mu_max) ||
-           (o->learned && (o->learned->max_rank < 1 || o->learned->max_rank > tp::kMaxL));
+           (o->learned && (o->learned->max_rank < 1 || o->learned->max_rank > tp::kMaxL)) ||
+           (o->record && o->record->max_calls < 0);
 }
 
 }  // namespace
@@ -241,7 +248,7 @@ int tp_trpca(const float* X, float* L, float* S, int n1, int n2, int n3, const t
     if (!ar.ok) return TP_ERR_WORKSPACE;
     if (Lam) W.lam = Lam;
     hipStream_t s = reinterpret_cast<hipStream_t>(stream);
-    const long long n = (long long)n1 * n2 * n3;
+    const long long n = (long long)n1 * n2 * n3, h = tp::half_slices(n3);
     const double lam = opts->lambda > 0.0f ? (double)opts->lambda : 1.0 / std::sqrt((double)std::max(n1, n2) * n3);
 
     TP_TRY(hipMemsetAsync(L, 0, n * sizeof(float), s));
@@ -261,10 +268,21 @@ int tp_trpca(const float* X, float* L, float* S, int n1, int n2, int n3, const t
     bool done = false;
     while (it < opts->max_iter && !done) {
         const float* yin = it == 0 ? X : W.yin;  // X - S - Lam/mu = X while S = Lam = 0
+        const tp_trpca_record* rec = (opts->record && it < opts->record->max_calls) ? opts->record : nullptr;
+        const int cur = it & 1, prv = cur ^ 1;
+        if (rec && rec->inputs)
+            TP_TRY(hipMemcpyAsync(rec->inputs + (long long)it * n, yin, n * sizeof(float), hipMemcpyDeviceToDevice, s));
+        if (rec && rec->features) {
+            const bool chain = opts->learned && it > 0;
+            const int fs = tp_slice_features(yin, n1, n2, n3, (float)(1.0 / mu), chain ? W.rank[prv] : nullptr,
+                                             chain ? W.sigma[prv] : nullptr,
+                                             rec->features + (long long)it * h * TP_MLP_INPUTS, W.feat_ws, W.feat_bytes,
+                                             stream);
+            if (fs != TP_OK) return fs;
+        }
         int st;
         if (opts->learned) {
             tp_learned_opts lo = *opts->learned;
-            const int cur = it & 1, prv = cur ^ 1;
             lo.prev_rank = it > 0 ? W.rank[prv] : nullptr;
             lo.prev_sigma = it > 0 ? W.sigma[prv] : nullptr;
             lo.warm_basis = it > 0 ? W.basis[prv] : nullptr;
@@ -279,6 +297,21 @@ int tp_trpca(const float* X, float* L, float* S, int n1, int n2, int n3, const t
                              stream);
         }
         if (st != TP_OK) return st;
+        if (rec && opts->learned) {
+            const long long mr = opts->learned->max_rank;
+            if (rec->counts)
+                TP_TRY(hipMemcpyAsync(rec->counts + (long long)it * h, W.rank[cur], h * sizeof(int),
+                                      hipMemcpyDeviceToDevice, s));
+            if (rec->sigmas)
+                TP_TRY(hipMemcpyAsync(rec->sigmas + (long long)it * h * TP_SIGMA_KEEP, W.sigma[cur],
+                                      h * TP_SIGMA_KEEP * sizeof(float), hipMemcpyDeviceToDevice, s));
+            if (rec->bases)
+                TP_TRY(hipMemcpyAsync(rec->bases + (long long)it * 2 * h * n2 * mr, W.basis[cur],
+                                      2 * h * n2 * mr * sizeof(float), hipMemcpyDeviceToDevice, s));
+            if (rec->basis_cols)
+                TP_TRY(hipMemcpyAsync(rec->basis_cols + (long long)it * h, W.bcols[cur], h * sizeof(int),
+                                      hipMemcpyDeviceToDevice, s));
+        }
         const double mu_next = std::min(opts->rho * mu, (double)opts->mu_max);
         TP_LAUNCH(tp::K_TRPCA, s,
                   tp::launch_trpca_update(X, lold, lnew, S, W.lam, W.yin, n, (float)mu, (float)(lam / mu),

@@ -12,6 +12,7 @@ asymmetric squared loss (under-prediction weighted `under` times, since it
 costs a fallback to the full SVD).
 
     python -m paper_1806_07247_amd.rank_model train [--out FILE] [--runs N] ...
+    python -m paper_1806_07247_amd.rank_model train --native --shapes 1024x1024x64 --runs 2000
 """
 import argparse
 import json
@@ -103,12 +104,64 @@ def collect(shapes, runs, seed0, device, max_iter=200, log=print):
     return np.concatenate(feats).astype(np.float32), np.concatenate(targets).astype(np.float32)
 
 
+def problem_gpu(n, n3, seed, device, frac=0.05):
+    """A training problem of the learned-rank workload's recipe, drawn on the
+    device from torch's seeded generator (host generation of 1024^2 x 64
+    problems costs seconds each): tubal rank r ~ U{5..40} scaled to n as in
+    rank_for, P (n x r x n3) and Q (r x n x n3) entries N(0, 1/n), X = P*Q + S
+    with +-1 outliers at Bernoulli(frac) positions.  Returns (X, r)."""
+    g = torch.Generator(device=device)
+    g.manual_seed(int(seed))
+    r = int(torch.randint(5, 41, (1,), generator=g, device=device).item())
+    r = max(2, int(round(r * n / 1024.0)))
+    P = torch.randn((n, r, n3), generator=g, device=device) / math.sqrt(n)
+    Q = torch.randn((r, n, n3), generator=g, device=device) / math.sqrt(n)
+    pos = torch.rand((n, n, n3), generator=g, device=device) < frac
+    sgn = torch.rand((n, n, n3), generator=g, device=device) < 0.5
+    S = torch.where(pos, torch.where(sgn, -1.0, 1.0), 0.0).to(torch.float32)
+    X = tp.tp_tprod(P.contiguous(), Q.contiguous())
+    X.add_(S)
+    return X, r
+
+
+def collect_native(shape, runs, seed0, device, labeller=None, max_iter=100, log=print):
+    """Training samples from native TRPCA runs (tp_trpca with its per-call
+    record): the features of every prox input (with the previous call's count
+    and singular values) and the exact count of every slice, from the
+    learned prox with the count check, the accuracy rounds, the wide retry and
+    the full-SVD fallback (so the count is exact whatever the labeller's
+    network predicts; labeller None uses the widest sketch).  Samples stay on
+    the device.  Returns (F, T) torch tensors."""
+    n1, n2, n3 = shape
+    h = n3 // 2 + 1
+    p = min(n1, n2)
+    rec = dict(max_calls=max_iter,
+               features=torch.zeros((max_iter, h, tp.TP_MLP_INPUTS), dtype=torch.float32, device=device),
+               counts=torch.zeros((max_iter, h), dtype=torch.int32, device=device))
+    lo = dict(mlp=labeller, fixed_rank=0 if labeller is not None else 54, accuracy=2e-5)
+    feats, targets = [], []
+    t0 = time.perf_counter()
+    for i in range(runs):
+        seed = seed0 + i
+        X, r = problem_gpu(n1, n3, seed, device)
+        lo["seed"] = seed * 1000
+        res = tp.tp_trpca(X, learned=lo, max_iter=max_iter, record=rec)
+        k = min(res["iters"], max_iter)
+        feats.append(rec["features"][:k].reshape(-1, tp.TP_MLP_INPUTS).clone())
+        c = rec["counts"][:k].reshape(-1).to(torch.float64)
+        targets.append((torch.log1p(c) / math.log1p(p)).to(torch.float32))
+        if i % 100 == 0 or i == runs - 1:
+            log(f"  run {i + 1}/{runs} seed {seed} r {r}: {res['iters']} iterations, converged {res['converged']}, "
+                f"{time.perf_counter() - t0:.1f} s", file=sys.stderr, flush=True)
+    return torch.cat(feats), torch.cat(targets)
+
+
 def train(F, T, device, steps=3000, batch=4096, lr=2e-3, under=4.0, seed=0, log=print):
     params = torch.from_numpy(init_params(seed)).to(device)
     m = torch.zeros_like(params)
     v = torch.zeros_like(params)
-    Fd = torch.from_numpy(F).to(device)
-    Td = torch.from_numpy(T).to(device)
+    Fd = F.to(device) if isinstance(F, torch.Tensor) else torch.from_numpy(F).to(device)
+    Td = T.to(device) if isinstance(T, torch.Tensor) else torch.from_numpy(T).to(device)
     n = F.shape[0]
     rng = np.random.default_rng(seed + 1)
     ws = torch.empty(tp._lib.load().tp_mlp_train_workspace_size(min(batch, n)), dtype=torch.uint8, device=device)
@@ -116,7 +169,7 @@ def train(F, T, device, steps=3000, batch=4096, lr=2e-3, under=4.0, seed=0, log=
     loss = torch.empty((), dtype=torch.float32, device=device)
     hist = []
     for step in range(1, steps + 1):
-        idx = torch.from_numpy(rng.choice(n, size=min(batch, n), replace=False)).to(device)
+        idx = torch.from_numpy(rng.integers(0, n, size=min(batch, n))).to(device)
         tp.tp_mlp_loss_grad(params, Fd[idx].contiguous(), Td[idx].contiguous(), under=under, grad=grad, loss=loss,
                             workspace=ws)
         lr_t = lr * (0.5 * (1 + math.cos(math.pi * step / steps)) * 0.9 + 0.1)
@@ -130,6 +183,8 @@ def train(F, T, device, steps=3000, batch=4096, lr=2e-3, under=4.0, seed=0, log=
 def evaluate(params, F, T, device):
     """Under-prediction rate and mean absolute error of the predicted counts;
     p is recovered from the feature log(p)/8."""
+    if isinstance(F, torch.Tensor):
+        F, T = F.cpu().numpy(), T.cpu().numpy()
     y = tp.tp_mlp_forward(params, torch.from_numpy(F).to(device)).cpu().numpy()
     p = np.rint(np.exp(F[:, 6].astype(np.float64) * 8.0))
     kpred = np.clip(np.rint(np.expm1(y * np.log1p(p))), 0, p)
@@ -150,7 +205,7 @@ class PrevRank(trpca.ProxLearned):
         return super().__call__(Y, tau, out)
 
 
-def gain(mlp, seeds, device, shape=(1024, 1024, 64), full_runs=1, log=print):
+def gain(mlp, seeds, device, shape=(1024, 1024, 64), full_runs=1, log=print, extra=None):
     """TRPCA on held-out problems of the learned-rank workload, driven by the
     prox with the trained network, without it (previous count; a constant
     count), and with the full SVD (the paper's method).  Reports total prox
@@ -173,6 +228,8 @@ def gain(mlp, seeds, device, shape=(1024, 1024, 64), full_runs=1, log=print):
                     ("prev", PrevRank(shape, device)),
                     ("const30", trpca.ProxLearned(shape, device, fixed_rank=30, use_prev=False)),
                     ("const54", trpca.ProxLearned(shape, device, fixed_rank=54, use_prev=False))]
+        for name, params in (extra or {}).items():
+            variants.append((name, trpca.ProxLearned(shape, device, mlp=params)))
         if si < full_runs:
             variants.append(("full", trpca.ProxFull(shape, device)))
         for name, prox in variants:
@@ -204,6 +261,9 @@ def main():
     ap.add_argument("--max-iter", type=int, default=200)
     ap.add_argument("--steps", type=int, default=3000)
     ap.add_argument("--seed", type=int, default=0, help="first ADMM seed (the evaluation uses 10000 and up)")
+    ap.add_argument("--native", action="store_true",
+                    help="collect from native TRPCA runs at the first shape on device-drawn problems")
+    ap.add_argument("--labeller", default=None, help="weights of the network that drives the labelling prox")
     args = ap.parse_args()
     dev = torch.device("cuda:0")
     if args.cmd == "evaluate":
@@ -212,14 +272,22 @@ def main():
         return
     t0 = time.perf_counter()
     shapes = [tuple(int(v) for v in sh.split("x")) for sh in args.shapes.split(",")]
-    F, T = collect(shapes, args.runs, args.seed, dev, max_iter=args.max_iter)
+    if args.native:
+        lab = load(args.labeller, dev) if args.labeller else None
+        F, T = collect_native(shapes[0], args.runs, args.seed, dev, labeller=lab,
+                              max_iter=min(args.max_iter, 100))
+        val = torch.zeros(F.shape[0], dtype=torch.bool, device=F.device)
+    else:
+        F, T = collect(shapes, args.runs, args.seed, dev, max_iter=args.max_iter)
+        val = np.zeros(F.shape[0], dtype=bool)
     t1 = time.perf_counter()
     # hold out 10% of the samples (every tenth)
-    val = np.zeros(F.shape[0], dtype=bool)
     val[::10] = True
     params, hist = train(F[~val], T[~val], dev, steps=args.steps, seed=args.seed, under=args.under)
     ev = evaluate(params, F[val], T[val], dev)
-    meta = dict(samples=int(F.shape[0]), shapes=args.shapes, runs_per_shape=args.runs, seed0=args.seed,
+    meta = dict(samples=int(F.shape[0]), shapes=args.shapes if not args.native else args.shapes.split(",")[0],
+                runs_per_shape=args.runs, seed0=args.seed, native=bool(args.native),
+                labeller=os.path.basename(args.labeller) if args.labeller else None,
                 under=args.under, steps=args.steps,
                 collect_s=round(t1 - t0, 1), train_s=round(time.perf_counter() - t1, 1), loss=hist,
                 heldout=ev)

@@ -45,7 +45,7 @@ class ProxLearned:
     name = "learned"
 
     def __init__(self, shape, device, mlp=None, fixed_rank=0, oversample=10, power_iters=2, max_rank=64, seed=0,
-                 use_prev=True, accuracy=2e-5, max_power_iters=4, retry_wide=True, accuracy_ref=0, warm=True):
+                 use_prev=True, accuracy=2e-5, max_power_iters=8, retry_wide=True, accuracy_ref=0, warm=True):
         n1, n2, n3 = shape
         self.h = tp.half_slices(n3)
         self.mlp, self.fixed_rank = mlp, fixed_rank

@@ -1,14 +1,21 @@
 """What the trained rank network gains over the method without it.
 
-On a held-out problem of the learned-rank workload (not among the training
+On a held-out problem of the learned-rank workload at the size the network
+was trained for (1024 x 1024 x 64; the seed is not among the training
 seeds), a TRPCA-ADMM run is driven by the learned prox; every prox call's
 input is kept and run through the learned prox and through the paper's
 full-SVD prox (Algorithm 3) on the same GPU.  The test requires the learned
 calls to be at least 3x faster in total and each within 1e-4 of the
 full-SVD result, relative to the larger of that result and the input.  It
-also reports the error relative to the result alone, and the same totals for
-two settings without the network (the previous call's count, and a constant
-count).
+also reports the error relative to the result alone.
+
+Against the method without the network, whole ADMM runs are timed with the
+network, with the previous call's largest count and with a constant count of
+30: the network must not be slower than the constant count.  Over the
+previous-count setting its gain is nil on this workload (measured on the 16
+held-out seeds 10000..10015 at 1024x1024x64: 1557 ms against 1554 ms of
+prox time): the counts settle within a few ADMM calls, and the wide retry
+makes the few under-predicted calls cheap, so the test only reports it.
 """
 import json
 
@@ -39,7 +46,7 @@ def _timed(fn):
     return out, a.elapsed_time(b)
 
 
-@pytest.mark.parametrize("n,n3,seed", [(512, 32, 10002)])
+@pytest.mark.parametrize("n,n3,seed", [(1024, 64, 10002)])
 def test_trained_network_gain(tp, n, n3, seed):
     from paper_1806_07247_amd import rank_model, trpca
     dev = torch.device("cuda:0")
@@ -91,16 +98,18 @@ def test_trained_network_gain(tp, n, n3, seed):
 
     # the method without the network: ADMM driven by heuristic counts
     others = {}
-    for name, p in (("previous_count", rank_model.PrevRank(shape, dev)),
+    for name, p in (("network", trpca.ProxLearned(shape, dev, mlp=mlp)),
+                    ("previous_count", rank_model.PrevRank(shape, dev)),
                     ("constant_30", trpca.ProxLearned(shape, dev, fixed_rank=30, use_prev=False))):
         rr = trpca.trpca(X, p, time_prox=True)
         others[name] = {"prox_ms": round(rr["prox_ms"], 1), "iters": rr["iters"], "fallback_slices": p.fallbacks}
     report = {"calls": len(calls), "full_svd_ms": round(t_f, 1), "learned_ms": round(t_l, 1),
               "speedup": round(t_f / t_l, 2), "max_rel_err": max(errs), "median_rel_err": float(np.median(errs)),
               "max_err_rel_to_max_of_result_and_input": max(errs_in),
-              "fallback_slices": fbs, "without_network": others}
+              "fallback_slices": fbs, "admm_runs": others}
     say("  " + json.dumps(report))
     assert t_f / t_l >= 3.0
+    assert others["network"]["prox_ms"] <= 1.05 * others["constant_30"]["prox_ms"]
     # error relative to the larger of the result and the input (the learned
     # prox checks its Ritz residuals at that scale)
     assert max(errs_in) <= 1e-4

@@ -110,3 +110,57 @@ def test_trpca_edges(tp):
     Xn[0, 0, 0] = float("nan")
     with pytest.raises(Exception):
         tp.tp_trpca(Xn)
+
+
+def test_trpca_record_replays_bitwise(tp):
+    """The per-call record of the native TRPCA driver: call 0's input is X, and
+    every recorded call replays bitwise through tp_slice_features and
+    tp_prox_tnn_learned from the recorded inputs, the tau sequence of
+    tp_trpca_taus, seed + i, and call i-1's counts, singular values and basis."""
+    import numpy as np
+    from paper_1806_07247_amd import rank_model, trpca
+    dev = torch.device("cuda:0")
+    n, n3, mr = 48, 6, 16
+    X, _, _ = trpca.make_problem(n, n3, 3, 0.05, 5, dev)
+    h = n3 // 2 + 1
+    K = 6
+    rec = dict(max_calls=K,
+               inputs=torch.zeros((K, n, n, n3), device=dev),
+               features=torch.zeros((K, h, tp.TP_MLP_INPUTS), device=dev),
+               counts=torch.zeros((K, h), dtype=torch.int32, device=dev),
+               sigmas=torch.zeros((K, h, tp.TP_SIGMA_KEEP), device=dev),
+               bases=torch.zeros((K,) + tp.basis_shape(n, n3, mr), device=dev),
+               basis_cols=torch.zeros((K, h), dtype=torch.int32, device=dev))
+    mlp = rank_model.load(device=dev)
+    lo = dict(mlp=mlp, max_rank=mr, seed=77, accuracy=2e-5)
+    res = tp.tp_trpca(X, learned=lo, record=rec, max_iter=200)
+    assert res["iters"] > K
+    assert torch.equal(rec["inputs"][0], X)
+    taus = tp.tp_trpca_taus(K)
+    ws = torch.empty(tp.tp_prox_tnn_learned_workspace_size(n, n, n3, mr), dtype=torch.uint8, device=dev)
+    out = torch.empty_like(X)
+    rk = torch.zeros(h, dtype=torch.int32, device=dev)
+    so = torch.zeros((h, tp.TP_SIGMA_KEEP), device=dev)
+    bo = torch.zeros(tp.basis_shape(n, n3, mr), device=dev)
+    bc = torch.zeros(h, dtype=torch.int32, device=dev)
+    for i in range(K):
+        Y = rec["inputs"][i].contiguous()
+        pr = rec["counts"][i - 1].contiguous() if i else None
+        ps = rec["sigmas"][i - 1].contiguous() if i else None
+        f = tp.tp_slice_features(Y, taus[i], pr, ps)
+        assert torch.equal(f, rec["features"][i]), i
+        tp.tp_prox_tnn_learned(Y, taus[i], mlp=mlp, max_rank=mr, seed=77 + i, accuracy=2e-5, prev_rank=pr,
+                               prev_sigma=ps, warm_basis=rec["bases"][i - 1].contiguous() if i else None,
+                               warm_cols=rec["basis_cols"][i - 1].contiguous() if i else None, basis_out=bo,
+                               basis_cols_out=bc, out=out, rank=rk, sigma_out=so, workspace=ws)
+        assert torch.equal(rk, rec["counts"][i]), i
+        assert torch.equal(so, rec["sigmas"][i]), i
+        assert torch.equal(bc, rec["basis_cols"][i]), i
+    # the full-SVD driver records inputs and unchained features
+    rec2 = dict(max_calls=2, inputs=torch.zeros((2, n, n, n3), device=dev),
+                features=torch.zeros((2, h, tp.TP_MLP_INPUTS), device=dev))
+    tp.tp_trpca(X, record=rec2, max_iter=200)
+    assert torch.equal(rec2["inputs"][0], X)
+    f1 = tp.tp_slice_features(rec2["inputs"][1].contiguous(), taus[1])
+    assert torch.equal(f1, rec2["features"][1])
+    assert np.isfinite(rec2["features"].cpu().numpy()).all()
