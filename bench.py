@@ -45,11 +45,37 @@ METRIC = "prox_tnn Melem/s learned-rank vs full-SVD @rel.err≤1e-4; tprod TFLOP
 PEAK = {"hbm_GBs": 8000.0, "fp32_mfma_TF": 157.3, "bf16_mfma_TF": 2500.0, "fp32_valu_TF": 157.3,
         "valu_fp64_TF": 78.6}
 LEARNED_SEED = 10000
-# HBM bytes per launch of the learned path's dominant kernel class, from the
-# FETCH_SIZE / WRITE_SIZE counter runs (copy-calibrated) recorded in
-# profiles/learned_prox_1024x1024x64_hbm_counters.md, for the kernels as they
-# are now (set to None when the kernel changes before it is measured again)
-MEASURED_TRAFFIC = {"cgemm": 129.0e6}  # bytes per slice-product launch, profiles/learned_prox_1024x1024x64_hbm_counters.md
+TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "learned_prox_1024x1024x64_hbm_counters.md")
+
+
+def sources_digest():
+    """sha256 over the library's kernel sources (the counters below stay
+    valid only for the code they were taken on)."""
+    import glob
+    import hashlib
+    h = hashlib.sha256()
+    csrc = os.path.join(ROOT, "paper_1806_07247_amd", "csrc")
+    for f in sorted(glob.glob(os.path.join(csrc, "*.hip")) + glob.glob(os.path.join(csrc, "*.h"))):
+        with open(f, "rb") as fh:
+            h.update(os.path.basename(f).encode() + b"\0" + fh.read())
+    return h.hexdigest()
+
+
+def measured_traffic(kernel):
+    """HBM bytes per launch of a kernel class from the FETCH_SIZE / WRITE_SIZE
+    counter runs (copy-calibrated) summarised in profiles/: its line
+    `bench-traffic: <class> <bytes per launch> sources <sha256>`, used only
+    while sources_digest() still matches (else None: the kernels changed
+    since the counters were taken)."""
+    try:
+        with open(TRAFFIC_PROFILE) as f:
+            for line in f:
+                parts = line.strip().strip("`").split()
+                if len(parts) == 5 and parts[0] == "bench-traffic:" and parts[1] == kernel and parts[3] == "sources":
+                    return float(parts[2]) if parts[4] == sources_digest() else None
+    except OSError:
+        pass
+    return None
 
 
 def log(*a):
@@ -296,6 +322,18 @@ def learned_block(args, tp, dev):
         fbs += int(fb.sum())
         kmax.append(int(frank.max()))
         kmax_by_call[i] = kmax[-1]
+    # stage breakdown of the full-SVD prox at this size (two traced calls):
+    # the shrinkage of 1024 x 1024 rotated columns per slice is bandwidth-bound
+    tp.tp_trace_collect_work()
+    tp.tp_trace_enable(True)
+    for i in distinct[-2:]:
+        tp.tp_prox_tnn(calls[i]["Y"], calls[i]["tau"], out=xf, rank=frank, workspace=fws)
+    torch.cuda.synchronize()
+    tp.tp_trace_enable(False)
+    ftot, fstages = summarize(tp.tp_trace_collect_work(), len(distinct[-2:]))
+    shrink_frac = None
+    if "shrink" in ftot and ftot["shrink"]["bytes"] > 0:
+        shrink_frac = round(ftot["shrink"]["bytes"] / (ftot["shrink"]["ms"] * 1e-3) / 1e9 / PEAK["hbm_GBs"], 4)
     speedup = float(np.sum(full_ms) / np.sum(lrn_ms))
     full_value = n * n * n3 * len(full_ms) / (np.sum(full_ms) * 1e-3) / 1e6
     log(f"  full: {np.mean(full_ms):.1f} ms/call; speedup {speedup:.1f}x; max rel.err {max(errs):.2e}")
@@ -304,7 +342,7 @@ def learned_block(args, tp, dev):
                     f"seed {args.learned_seed} (held out)",
         "calls": ncalls, "steps": steps, "ms_per_call": round(ms, 4), "Melem_s": round(value, 3), **timing,
         "full_svd": {"calls_timed": len(full_ms), "ms_per_call": round(float(np.mean(full_ms)), 3),
-                     "Melem_s": round(full_value, 4)},
+                     "Melem_s": round(full_value, 4), "stages": fstages, "shrink_frac_hbm": shrink_frac},
         "speedup_vs_full_svd": round(speedup, 2),
         "rel_err_vs_full_svd": {"max": float(max(errs)), "median": float(np.median(errs)),
                                 "max_rel_to_max_of_output_and_input": float(max(errs_z))},
@@ -322,7 +360,7 @@ def learned_block(args, tp, dev):
                 "per_launch": {"ms": round(d["ms"] / d["launches"], 4), "flops": round(d["flops"] / d["launches"])}}
     elif d["bytes"] > 0:
         roof = roofline_for(dom, d, PEAK["fp32_mfma_TF"])
-        roof["traffic"] = MEASURED_TRAFFIC.get(dom)
+        roof["traffic"] = measured_traffic(dom)
     else:
         roof = {"kernel": dom, "bound": None, "achieved": None, "peak": None, "unit": None, "frac": None,
                 "traffic": None}
@@ -643,6 +681,70 @@ def oracle_config5(args, ctx, calls, tp):
             "learned_meets_1e-4": bool(lmax <= 1e-4), "per_call": rows}
 
 
+def tprod_small_block(tp, inputs, oracle, dev, reps=50):
+    """The small t-product (A 64x48x32, B 48x40x32, seed 0): GPU time per
+    call, the oracle's time (bcirc(A) unfold(B), eq (9), no FFT) and the
+    relative Frobenius error."""
+    import torch
+    A, B = inputs.tprod_parity(seed=0)
+    a, b = torch.from_numpy(A).to(dev), torch.from_numpy(B).to(dev)
+    C = tp.tp_tprod(a, b)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        tp.tp_tprod(a, b, out=C)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    t0 = time.perf_counter()
+    ref = oracle.tprod(A.astype(np.float64), B.astype(np.float64))
+    t_or = time.perf_counter() - t0
+    err = float(np.linalg.norm(C.cpu().numpy() - ref) / np.linalg.norm(ref))
+    out = {"workload": "A 64x48x32 * B 48x40x32, N(0,1), seed 0", "ms_per_call": round(ms, 4),
+           "oracle": {"kind": "bcirc(A) unfold(B) (eq (9), no FFT)", "seconds": round(t_or, 4),
+                      "threads": oracle.get_threads()},
+           "rel_err": err}
+    log(f"tprod 64x48x40x32: {json.dumps(out)}")
+    return out
+
+
+def batch_oracle_sample(inputs, oracle, count, sample=8):
+    """The oracle on the first `sample` tensors of the batching workload (the
+    t-product by its definition and the prox by FFT + LAPACK SVD per slice),
+    and an estimate for all of them by each operation's arithmetic (the
+    definition: n1 n3 x n2 n3 times n2 n3 x l products; the prox: slices x
+    n1 n2 min(n1, n2))."""
+    shapes = inputs.batch_shapes(count, seed=0)
+    tensors = inputs.batch_tensors(shapes[:sample], seed=0)
+    t_def = t_prox = 0.0
+    for (A, B) in tensors:
+        t0 = time.perf_counter()
+        oracle.tprod(A.astype(np.float64), B.astype(np.float64))
+        t_def += time.perf_counter() - t0
+        Y = A.astype(np.float64)
+        sig = np.linalg.svd(np.fft.fft(Y, axis=2)[:, :, 0], compute_uv=False)
+        t0 = time.perf_counter()
+        oracle.prox_tnn_lapack(Y, 0.1 * float(sig[0]))
+        t_prox += time.perf_counter() - t0
+
+    def w_def(sh):
+        n1, n2, l, n3 = sh
+        return float(n1 * n3) * (n2 * n3) * l
+
+    def w_prox(sh):
+        n1, n2, _, n3 = sh
+        return float(n3 // 2 + 1) * n1 * n2 * min(n1, n2)
+
+    f_def = sum(w_def(sh) for sh in shapes) / sum(w_def(sh) for sh in shapes[:sample])
+    f_prox = sum(w_prox(sh) for sh in shapes) / sum(w_prox(sh) for sh in shapes[:sample])
+    out = {"sample_tensors": sample, "threads": oracle.get_threads(),
+           "tprod_definition_seconds": round(t_def, 3), "tprod_seconds_all_estimate": round(t_def * f_def, 1),
+           "prox_lapack_seconds": round(t_prox, 3), "prox_seconds_all_estimate": round(t_prox * f_prox, 1)}
+    log(f"batch oracle sample: {json.dumps(out)}")
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -706,6 +808,7 @@ def main():
     trpca_res = trpca_block(args, tp, dev, mlp)
 
     cpu = None
+    small = None
     parity = {"learned_vs_full_svd_max_rel_err": learned["rel_err_vs_full_svd"]["max"]}
     if not args.no_cpu_baseline:
         import oracle
@@ -726,10 +829,19 @@ def main():
         tn1, tl, tn3 = A_np.shape[0], B_np.shape[1], A_np.shape[2]
         rng = np.random.default_rng(1)
         idx = rng.choice(tn1 * tl * tn3, size=4000, replace=False)
+        t0 = time.perf_counter()
         ref = oracle.tprod_entries(A_np, B_np, idx)
+        t_ent = time.perf_counter() - t0
+        tprod["oracle"] = {"kind": "eq (9) by definition at sampled entries", "entries": int(idx.size),
+                           "seconds": round(t_ent, 3),
+                           "seconds_whole_tensor_estimate": round(t_ent * tn1 * tl * tn3 / idx.size, 1),
+                           "threads": oracle.get_threads()}
         for prec, Cn in outs.items():
             parity[f"tprod_{prec}_sampled_rel_err"] = float(
                 np.linalg.norm(Cn.reshape(-1)[idx] - ref) / np.linalg.norm(ref))
+        small = tprod_small_block(tp, inputs, oracle, dev)
+        parity["tprod_64x48x40x32_rel_err"] = small["rel_err"]
+        batch["oracle"] = batch_oracle_sample(inputs, oracle, batch.get("count", 256))
         log(f"parity {parity}")
 
     line = {
@@ -742,7 +854,8 @@ def main():
                    "n1": 1024, "n2": 1024, "n3": 64, "tubal_rank": r, "calls": learned["calls"],
                    "rank_predictor": "MLP 12-64-64-64-1", "oversample": 10, "power_iters": 2,
                    "parallelism": "single GPU"},
-        "roofline": roof, "cpu_baseline": cpu, "learned": learned, "prox_full_200": prox_full, "tprod": tprod, "batch": batch,
+        "roofline": roof, "cpu_baseline": cpu, "learned": learned, "prox_full_200": prox_full, "tprod": tprod,
+        "tprod_64x48x40x32": small, "batch": batch,
         "trpca": trpca_res, "parity": parity,
     }
     acc = parity.get("learned_workload_vs_fp64_oracle")

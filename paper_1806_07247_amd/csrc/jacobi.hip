@@ -1076,27 +1076,60 @@ namespace {
 
 // w_j <- w_j * sqrt(d_j) / sigma_j with d_j = (1 - tau/sigma_j)_+ (eq (21));
 // keep[s] = #{j : sigma_j > tau}.
+// Shrinkage of the rotated columns (eq (21)): column j of slice s is scaled
+// by sqrt(1 - tau/sigma_j)/sigma_j where sigma_j > tau, else 0.  A
+// workgroup takes a block of rows of one slice: the P column scales of the
+// slice go to LDS once, then the rows stream through with 16-byte accesses
+// (P a multiple of 4 and 16-byte aligned planes) or element by element.
+// keep[s] = #{sigma_j > tau}.  Only the first *count slices when count is
+// given.
 __global__ __launch_bounds__(256) void k_shrink(float* __restrict__ wr, float* __restrict__ wi,
                                                 const double* __restrict__ sigma, int* __restrict__ keep, int R,
-                                                int P, long long total, double tau, const int* __restrict__ count)
+                                                int P, int nslices, int rows, double tau,
+                                                const int* __restrict__ count, int vec)
 {
-    const long long e0 = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-    const long long per = (long long)R * P;
-    if (count) total = min(total, (long long)*count * per);
-    for (long long e = e0; e < total; e += (long long)gridDim.x * blockDim.x) {
-        const long long s = e / per;
-        const int j = (int)(e % P);
-        const double sg = sigma[s * P + j];
-        float f = 0.0f;
-        if (sg > tau) f = (float)(sqrt(1.0 - tau / sg) / sg);
-        wr[e] *= f;
-        wi[e] *= f;
-    }
-    if (keep && e0 < total / per) {
-        const long long s = e0;
-        int k = 0;
-        for (int j = 0; j < P; ++j) k += sigma[s * P + j] > tau ? 1 : 0;
-        keep[s] = k;
+    extern __shared__ float fsc[];
+    const int nb = (R + rows - 1) / rows;
+    const int ns = count ? min(nslices, *count) : nslices;
+    for (long long b = blockIdx.x; b < (long long)ns * nb; b += gridDim.x) {
+        const int s = (int)(b / nb), rb = (int)(b % nb);
+        __syncthreads();  // the previous block's scales are no longer read
+        int kept = 0;     // #{sigma_j > tau}, counted across the workgroup
+        for (int j0 = 0; j0 < P; j0 += blockDim.x) {
+            const int j = j0 + threadIdx.x;
+            bool above = false;
+            if (j < P) {
+                const double sg = sigma[(long long)s * P + j];
+                above = sg > tau;
+                fsc[j] = above ? (float)(sqrt(1.0 - tau / sg) / sg) : 0.0f;
+            }
+            kept += __syncthreads_count(above);
+        }
+        if (keep && rb == 0 && threadIdx.x == 0) keep[s] = kept;
+        __syncthreads();
+        const int r0 = rb * rows, nr = min(rows, R - r0);
+        const long long base = ((long long)s * R + r0) * P;
+        if (vec) {
+            float4* pr = reinterpret_cast<float4*>(wr + base);
+            float4* pi = reinterpret_cast<float4*>(wi + base);
+            const int q4 = P / 4, n4 = nr * q4;
+#pragma unroll 4
+            for (int q = threadIdx.x; q < n4; q += blockDim.x) {
+                const int j = (q % q4) * 4;
+                float4 a = pr[q], c = pi[q];
+                a.x *= fsc[j]; a.y *= fsc[j + 1]; a.z *= fsc[j + 2]; a.w *= fsc[j + 3];
+                c.x *= fsc[j]; c.y *= fsc[j + 1]; c.z *= fsc[j + 2]; c.w *= fsc[j + 3];
+                pr[q] = a;
+                pi[q] = c;
+            }
+        } else {
+            const int n1 = nr * P;
+            for (int q = threadIdx.x; q < n1; q += blockDim.x) {
+                const float f = fsc[q % P];
+                wr[base + q] *= f;
+                wi[base + q] *= f;
+            }
+        }
     }
 }
 
@@ -1177,10 +1210,15 @@ hipError_t launch_shrink(float* wr, float* wi, const double* sigma, int* keep, i
 {
     const long long total = (long long)R * P * nslices;
     if (total <= 0) return hipSuccess;
-    long long blocks = (total + 255) / 256;
-    if (blocks > 256 * 32) blocks = 256 * 32;
-    if (blocks * 256 < nslices) blocks = (nslices + 255) / 256;
-    k_shrink<<<(int)blocks, 256, 0, st>>>(wr, wi, sigma, keep, R, P, total, tau, count);
+    // read and write both planes, read the singular values (slices the
+    // device-side count excludes are not known here)
+    if (!count) trace_work(0.0, 16.0 * total + 8.0 * (double)P * nslices);
+    const int rows = std::max(1, std::min(R, 8192 / P));  // about 32 KB of each plane per block
+    const long long blocks = (long long)nslices * ((R + rows - 1) / rows);
+    const int grid = (int)std::min<long long>(blocks, 256LL * 16);
+    const int vec = (P % 4 == 0 && ((reinterpret_cast<uintptr_t>(wr) | reinterpret_cast<uintptr_t>(wi)) & 15) == 0)
+                        ? 1 : 0;
+    k_shrink<<<grid, 256, (size_t)P * sizeof(float), st>>>(wr, wi, sigma, keep, R, P, nslices, rows, tau, count, vec);
     return hipGetLastError();
 }
 
