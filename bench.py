@@ -529,7 +529,10 @@ def batch_block(args, tp, inputs, dev):
         sequential = e0.elapsed_time(e1)
         diff = max(float(torch.linalg.norm(x - y) / max(float(torch.linalg.norm(y)), 1e-30))
                    for x, y in zip(b.outs, seq_out))
-        row = {"ms_eager": round(eager, 4), "ms_graph": round(graph, 4), "ms_sequential_calls": round(sequential, 4),
+        from paper_1806_07247_amd import autotune
+        tuned = autotune.batch_opts(op, autotune.batch_shapes_of(As, Bs if op == "tprod" else None))
+        row = {"launch_options": tuned or "defaults (no cache entry)",
+               "ms_eager": round(eager, 4), "ms_graph": round(graph, 4), "ms_sequential_calls": round(sequential, 4),
                "speedup_graph_vs_sequential": round(sequential / graph, 2),
                "gemm_GFLOP": round(st["gemm_flops"] / 1e9, 3), "fft_MB": round(st["fft_bytes"] / 1e6, 1),
                "TFLOP_s_gemm_work_over_graph_time": round(st["gemm_flops"] / (graph * 1e-3) / 1e12, 2),
