@@ -534,6 +534,13 @@ int tp_batch_destroy(tp_batch* plan);
  *   TP_PARAM_RETRY_ROUNDS         learned-rank prox: accuracy rounds of the wide
  *                                 retry attempt (0 = default 2; at most the
  *                                 first attempt's max_power_iters - power_iters)
+ *   TP_PARAM_JACOBI_GRAM          multi-workgroup Jacobi without V: block pairs
+ *                                 through their Gram matrices (MFMA products,
+ *                                 FP64 rotations of the Gram matrix, one MFMA
+ *                                 update of the columns per block pair): 0 = on,
+ *                                 16-column block pairs up to 256 rows and 32
+ *                                 above; 1 = off (the column-rotation forms);
+ *                                 2 = 16 columns; 3 = 32 columns
  * The bf16 slice products (TP_PREC_BF16X3, TP_PREC_BF16) read
  * TP_PARAM_GEMM_VARIANT as: 1 = 64x64, 2 = 128x128, 3 = 128x32 tiles on
  * 16x16x32 products, 4 = 256x128 and 5 = 128x128 on 32x32x16 products,
@@ -551,7 +558,8 @@ enum {
     TP_PARAM_GEMM_KSPLIT = 8,
     TP_PARAM_JACOBI_STEPWISE = 9,
     TP_PARAM_RETRY_ROUNDS = 10,
-    TP_PARAM_COUNT = 11
+    TP_PARAM_JACOBI_GRAM = 11,
+    TP_PARAM_COUNT = 12
 };
 int tp_set_param(int key, int value);
 int tp_get_param(int key);

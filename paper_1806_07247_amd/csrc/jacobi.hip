@@ -777,6 +777,410 @@ __global__ __launch_bounds__(MAXT) void k_jacobi_sweep(SweepArgs a)
     }
 }
 
+// ---- Gram block sweep: block pairs through MFMA Gram matrices ----
+// The item order, stamps and flags of k_jacobi_sweep (one launch per sweep),
+// with blocks of b = 8 NT columns, so that an item holds W = 16 NT columns X
+// (R x W).  An item
+//  1. forms G = X^* X with FP32 MFMA (16x16x4) over groups of 8 rows, two
+//     accumulator sets per wave (one per row of a row pair), the partial sums
+//     added in FP64 in LDS;
+//  2. takes the scalar sweep's pair rotations (all W(W-1)/2 pairs in the
+//     circle order at block step 0, the b x b cross pairs later) on G instead
+//     of on the columns: a rotation J of positions (p, q) chosen from G_pp,
+//     G_qq and G_pq turns G into J^* G J and the accumulated V into V J, in
+//     FP64 (J^* G J is the Gram matrix of X J, so each decision is the one the
+//     column rotations would take up to the rounding of G);
+//  3. when anything rotated, replaces X by X V with FP32 MFMA (V rounded to
+//     FP32), rows in tiles of 16.
+// The columns are read from memory once when they fit in LDS (copied there by
+// step 1, read back by step 3), else twice; loads run one batch ahead.
+// The R-long column work of the W(W-1)/2 (or b^2) rotations becomes two
+// R x W x W complex products on the matrix cores; the dependent chain of an
+// item is W - 1 (or b) steps on W x W matrices in LDS.
+template <int NT>
+struct GramSmem {
+    static constexpr int W = 16 * NT, B = 8 * NT;
+    double2 ga[W][W + 1];  // G
+    double2 gb[W][W + 1];  // G J within a step
+    union {
+        double part[2][2][W][W];  // [half][re, T][i][j]: per-wave-pair partial sums
+        double2 v[W][W + 1];      // accumulated rotations V
+    } u;
+    double rc[B], rsr[B], rsi[B];  // rotation of each pair of the current step
+    int item;
+};
+
+// the rotation of the scalar sweep from alpha = ||x||^2, beta = ||y||^2 and
+// gamma = x^* y (FP64): x' = c x - s conj(e) y, y' = s e x + c y, e =
+// gamma/|gamma|; (sr, si) = s e.  False (and the identity) below the threshold.
+__device__ __forceinline__ bool pair_rotation(double al, double be, double gr, double gi, double tol2, double& c,
+                                              double& sr, double& si)
+{
+    c = 1.0;
+    sr = 0.0;
+    si = 0.0;
+    const double g2 = gr * gr + gi * gi;
+    if (!(g2 > 0.0 && g2 > tol2 * al * be)) return false;
+    const double ig = rsqrt_f64(g2);
+    const double zeta = 0.5 * (be - al) * ig;
+    const double z2 = fma(zeta, zeta, 1.0);
+    const double t = copysign(rcp_f64(fabs(zeta) + z2 * rsqrt_f64(z2)), zeta);
+    c = rsqrt_f64(fma(t, t, 1.0));
+    const double sn = c * t;
+    sr = sn * gr * ig;
+    si = sn * gi * ig;
+    return true;
+}
+
+// positions of pair k at inner step st: the circle order over all W positions
+// at block step 0, else position k of the first block against position
+// (k + st) mod b of the second
+template <int W>
+__device__ __forceinline__ void gram_pair(bool all, int k, int st, int& p, int& q)
+{
+    constexpr int B = W / 2;
+    if (all) {
+        p = rr_col(k, st, W);
+        q = rr_col(W - 1 - k, st, W);
+    } else {
+        p = k;
+        q = B + (k + st < B ? k + st : k + st - B);
+    }
+}
+
+// the bits of a float taken by value: a bit cast applied directly to an
+// element of an ext_vector_type value reads element 0 with this compiler
+__device__ __forceinline__ int f32_bits(float f) { return __builtin_bit_cast(int, f); }
+
+// rows r and r + 1 of a column (16 bytes), zeros where absent
+__device__ __forceinline__ v4f gram_rows2(v4i rs, int limit, int base, int r, int R, bool live)
+{
+    if (live && r + 1 < R) return raw_buffer_load_v4(rs, base + r * 8, 0, kDeviceScope);
+    v4f z = {0.f, 0.f, 0.f, 0.f};
+    if (live && r < R) {
+        const v2f q = raw_buffer_load_v2(rs, base + r * 8, 0, kDeviceScope);
+        z.x = q.x;
+        z.y = q.y;
+    }
+    return z;
+}
+
+// column stride (float2) of the item's columns staged in LDS: even, and 16 mod
+// 32, so that the two columns a half-wave reads in the update fall in
+// different halves of the banks
+__host__ __device__ constexpr int gram_ldx(int R) { return R + ((16 - R) % 32 + 32) % 32; }
+
+// whether the W columns of an item are staged in LDS (read once from memory)
+constexpr bool gram_stage_fits(int nt, int R)
+{
+    return (size_t)gram_ldx(R) * 16 * nt * sizeof(float2) <= (nt == 1 ? 64 : 90) * 1024;
+}
+
+template <int NT, bool STAGE>
+__global__ __launch_bounds__(256) void k_gram_sweep(SweepArgs a)
+{
+    constexpr int W = 16 * NT, B = 8 * NT;
+    constexpr int PF = 4;  // row groups per load batch
+    extern __shared__ __align__(16) char gram_raw[];
+    GramSmem<NT>& sm = *reinterpret_cast<GramSmem<NT>*>(gram_raw);
+    float2* xs = reinterpret_cast<float2*>(gram_raw + ((sizeof(GramSmem<NT>) + 15) & ~(size_t)15));
+    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+    const int j16 = lane & 15, k4 = lane >> 4;
+    const int R = a.R, ldx = gram_ldx(R);
+    const int npairs = a.nb / 2, per_step = a.nslices * npairs;
+    const int live_slices = a.count ? min(*a.count, a.nslices) : a.nslices;
+    if (live_slices <= 0) return;
+    const int ns = a.nslices, stamp = a.sweep + 1;
+    if (a.sweep > 0) {  // every live slice converged: the launch has nothing to do
+        int busy = 0;
+        for (int q = tid; q < live_slices; q += blockDim.x) busy |= a.rot[((a.sweep - 1) % 3) * ns + q];
+        if (!__syncthreads_or(busy)) {
+            if (blockIdx.x == 0)
+                for (int q = tid; q < live_slices; q += blockDim.x) {
+                    a.rot[((a.sweep + 1) % 3) * ns + q] = 0;
+                    if (a.done[q] == 0) a.done[q] = a.sweep;
+                }
+            return;
+        }
+    }
+    for (;;) {
+        if (tid == 0) {
+            const unsigned int tk = atomicAdd(a.tickets + (a.sweep & 3), 1u);
+            if (tk == 0) a.tickets[(a.sweep + 2) & 3] = 0;
+            sm.item = (int)tk;
+        }
+        __syncthreads();
+        const int item = sm.item;
+        if (item >= a.nitems) return;
+        const int step = item / per_step, rem = item - step * per_step, s = rem / npairs, bp = rem - s * npairs;
+        if (s >= live_slices) {
+            __syncthreads();
+            continue;
+        }
+        if (step == 0 && bp == 0 && tid == 0) a.rot[((a.sweep + 1) % 3) * ns + s] = 0;
+        if (a.sweep > 0 && a.rot[((a.sweep - 1) % 3) * ns + s] == 0) {
+            if (step == 0 && bp == 0 && tid == 0 && a.done[s] == 0) a.done[s] = a.sweep;
+            __syncthreads();
+            continue;
+        }
+        const int b1 = rr_col(bp, step, a.nb), b2 = rr_col(a.nb - 1 - bp, step, a.nb);
+        const int c1 = block_cols(b1, B, a.P), c2 = block_cols(b2, B, a.P);
+        int* fl = a.flags + (long long)s * (a.nb - 1) * npairs;
+        if (step > 0 && tid == 0) {
+            const int q1 = rr_pos(b1, step - 1, a.nb), q2 = rr_pos(b2, step - 1, a.nb);
+            wait_stamp(fl + (step - 1) * npairs + min(q1, a.nb - 1 - q1), stamp, a.err);
+            wait_stamp(fl + (step - 1) * npairs + min(q2, a.nb - 1 - q2), stamp, a.err);
+        }
+        __syncthreads();
+        const int limit = a.P * R * (int)sizeof(float2);
+        const v4i rs = slice_rsrc(a.work + (long long)s * a.P * R, (unsigned int)limit);
+        // local column i of the item: block b1 for i < b, else block b2
+        auto col_base = [&](int i) { return (i < B ? b1 * B + i : b2 * B + i - B) * R * 8; };
+        auto col_live = [&](int i) { return i < B ? i < c1 : i - B < c2; };
+
+        // 1. Gram matrix: lane (j16, k4) feeds rows 8t + 2 k4 (set 0) and + 1
+        // (set 1) of column 16 g + j16 as both MFMA operands
+        {
+            v4f accR[NT][NT][2], accT[NT][NT][2];
+#pragma unroll
+            for (int ti = 0; ti < NT; ++ti)
+#pragma unroll
+                for (int tj = 0; tj < NT; ++tj)
+#pragma unroll
+                    for (int h = 0; h < 2; ++h) {
+                        accR[ti][tj][h] = v4f{0.f, 0.f, 0.f, 0.f};
+                        accT[ti][tj][h] = v4f{0.f, 0.f, 0.f, 0.f};
+                    }
+            int base[NT];
+            bool live[NT];
+#pragma unroll
+            for (int g = 0; g < NT; ++g) {
+                base[g] = col_base(16 * g + j16);
+                live[g] = col_live(16 * g + j16);
+            }
+            // wave wv takes the row groups wv + 4 i, i < nw, in batches of PF
+            // whose loads are issued one batch ahead
+            const int ngroups = (R + 7) / 8;
+            const int nw = wv < ngroups ? (ngroups - wv + 3) / 4 : 0;
+            v4f cur[PF][NT], nxt[PF][NT];
+            auto load_batch = [&](int i0, v4f (&dst)[PF][NT]) {
+#pragma unroll
+                for (int b = 0; b < PF; ++b) {
+                    const int r = 8 * (wv + 4 * (i0 + b)) + 2 * k4;
+#pragma unroll
+                    for (int g = 0; g < NT; ++g) dst[b][g] = gram_rows2(rs, limit, base[g], r, R, live[g]);
+                }
+            };
+            if (nw > 0) load_batch(0, cur);
+            for (int i0 = 0; i0 < nw; i0 += PF) {
+                if (i0 + PF < nw) load_batch(i0 + PF, nxt);
+#pragma unroll
+                for (int b = 0; b < PF; ++b) {
+                    const v4f* x = cur[b];
+                    if (STAGE) {
+                        const int r = 8 * (wv + 4 * (i0 + b)) + 2 * k4;
+                        if (r < R)
+#pragma unroll
+                            for (int g = 0; g < NT; ++g)
+                                *reinterpret_cast<v4f*>(xs + (16 * g + j16) * ldx + r) = x[g];
+                    }
+#pragma unroll
+                    for (int ti = 0; ti < NT; ++ti)
+#pragma unroll
+                        for (int tj = 0; tj < NT; ++tj) {
+                            v4f& r0 = accR[ti][tj][0];
+                            v4f& r1 = accR[ti][tj][1];
+                            r0 = __builtin_amdgcn_mfma_f32_16x16x4f32(x[ti].x, x[tj].x, r0, 0, 0, 0);
+                            r0 = __builtin_amdgcn_mfma_f32_16x16x4f32(x[ti].y, x[tj].y, r0, 0, 0, 0);
+                            accT[ti][tj][0] =
+                                __builtin_amdgcn_mfma_f32_16x16x4f32(x[ti].x, x[tj].y, accT[ti][tj][0], 0, 0, 0);
+                            r1 = __builtin_amdgcn_mfma_f32_16x16x4f32(x[ti].z, x[tj].z, r1, 0, 0, 0);
+                            r1 = __builtin_amdgcn_mfma_f32_16x16x4f32(x[ti].w, x[tj].w, r1, 0, 0, 0);
+                            accT[ti][tj][1] =
+                                __builtin_amdgcn_mfma_f32_16x16x4f32(x[ti].z, x[tj].w, accT[ti][tj][1], 0, 0, 0);
+                        }
+                }
+#pragma unroll
+                for (int b = 0; b < PF; ++b)
+#pragma unroll
+                    for (int g = 0; g < NT; ++g) cur[b][g] = nxt[b][g];
+            }
+            // partial sums: waves 0, 1 store, waves 2, 3 add theirs (fixed order)
+            for (int pass = 0; pass < 2; ++pass) {
+                if ((wv >> 1) == pass) {
+                    double (*pr)[W] = sm.u.part[wv & 1][0];
+                    double (*pt)[W] = sm.u.part[wv & 1][1];
+#pragma unroll
+                    for (int ti = 0; ti < NT; ++ti)
+#pragma unroll
+                        for (int tj = 0; tj < NT; ++tj)
+#pragma unroll
+                            for (int e = 0; e < 4; ++e) {
+                                const int i = 16 * ti + 4 * k4 + e, jj = 16 * tj + j16;
+                                const double dr = (double)accR[ti][tj][0][e] + (double)accR[ti][tj][1][e];
+                                const double dt = (double)accT[ti][tj][0][e] + (double)accT[ti][tj][1][e];
+                                if (pass == 0) {
+                                    pr[i][jj] = dr;
+                                    pt[i][jj] = dt;
+                                } else {
+                                    pr[i][jj] += dr;
+                                    pt[i][jj] += dt;
+                                }
+                            }
+                }
+                __syncthreads();
+            }
+        }
+        // G = (Xr^T Xr + Xi^T Xi) + i (T - T^T), T = Xr^T Xi; the real part
+        // symmetrised so that G is exactly Hermitian
+        for (int e = tid; e < W * W; e += 256) {
+            const int i = e / W, jj = e - i * W;
+            const double rij = sm.u.part[0][0][i][jj] + sm.u.part[1][0][i][jj];
+            const double rji = sm.u.part[0][0][jj][i] + sm.u.part[1][0][jj][i];
+            const double tij = sm.u.part[0][1][i][jj] + sm.u.part[1][1][i][jj];
+            const double tji = sm.u.part[0][1][jj][i] + sm.u.part[1][1][jj][i];
+            sm.ga[i][jj] = make_double2(0.5 * (rij + rji), tij - tji);
+        }
+        __syncthreads();
+        const bool all = step == 0;
+        int need = 0;
+        for (int e = tid; e < W * W; e += 256) {
+            const int i = e / W, jj = e - i * W;
+            sm.u.v[i][jj] = make_double2(i == jj ? 1.0 : 0.0, 0.0);
+            if (i < jj && (all || (i < B && jj >= B))) {
+                const double2 g = sm.ga[i][jj];
+                const double g2 = g.x * g.x + g.y * g.y;
+                need |= (g2 > 0.0 && g2 > a.tol2 * sm.ga[i][i].x * sm.ga[jj][jj].x) ? 1 : 0;
+            }
+        }
+        // 2. the pair rotations on G (none when no visited pair is above the
+        // threshold: then none would ever rotate)
+        bool rotated = false;
+        if (__syncthreads_or(need)) {
+            const int nsteps = all ? W - 1 : B;
+            const int k = tid % B;  // this thread's pair in the first half of a step
+            for (int st = 0; st < nsteps; ++st) {
+                int p, q;
+                gram_pair<W>(all, k, st, p, q);
+                double c, sr, si;
+                const bool r = pair_rotation(sm.ga[p][p].x, sm.ga[q][q].x, sm.ga[p][q].x, sm.ga[p][q].y, a.tol2, c,
+                                             sr, si);
+                if (tid < B) {
+                    sm.rc[k] = c;
+                    sm.rsr[k] = sr;
+                    sm.rsi[k] = si;
+                }
+                // G J into gb, V J in place: rows (tid / B) + m 256 / B of G, then of V
+                for (int u = tid / B; u < 2 * W; u += 256 / B) {
+                    double2* row = u < W ? &sm.ga[u][0] : &sm.u.v[u - W][0];
+                    double2* out = u < W ? &sm.gb[u][0] : row;
+                    const double2 x = row[p], y = row[q];
+                    out[p] = make_double2(c * x.x - (sr * y.x + si * y.y), c * x.y - (sr * y.y - si * y.x));
+                    out[q] = make_double2((sr * x.x - si * x.y) + c * y.x, (sr * x.y + si * x.x) + c * y.y);
+                }
+                if (!__syncthreads_or(r ? 1 : 0)) continue;  // no rotation: G (ga) unchanged
+                rotated = true;
+                // J^* (G J) back into ga: rows p, q of every column
+                for (int u = tid; u < B * W; u += 256) {
+                    const int kk = u / W, cc = u - kk * W;
+                    int pp, qq;
+                    gram_pair<W>(all, kk, st, pp, qq);
+                    const double c2 = sm.rc[kk], sr2 = sm.rsr[kk], si2 = sm.rsi[kk];
+                    const double2 x = sm.gb[pp][cc], y = sm.gb[qq][cc];
+                    sm.ga[pp][cc] = make_double2(c2 * x.x - (sr2 * y.x - si2 * y.y), c2 * x.y - (sr2 * y.y + si2 * y.x));
+                    sm.ga[qq][cc] = make_double2((sr2 * x.x + si2 * x.y) + c2 * y.x, (sr2 * x.y - si2 * x.x) + c2 * y.y);
+                }
+                __syncthreads();
+            }
+        }
+        // 3. X <- X V: lane (j16, k4) feeds row 16 rt + j16 of column 4 kq + k4
+        // (A) and V(4 kq + k4, 16 gn + j16) (B); the output tile holds rows
+        // 16 rt + 4 k4 + e of column 16 gn + j16
+        if (rotated) {
+            float vr[W / 4][NT], vi[W / 4][NT];
+#pragma unroll
+            for (int kq = 0; kq < W / 4; ++kq)
+#pragma unroll
+                for (int gn = 0; gn < NT; ++gn) {
+                    const double2 v = sm.u.v[4 * kq + k4][16 * gn + j16];
+                    vr[kq][gn] = (float)v.x;
+                    vi[kq][gn] = (float)v.y;
+                }
+            // the A operand of a row tile: from the LDS stage, or from memory
+            // one tile ahead
+            auto load_tile = [&](int rt, v2f (&dst)[W / 4]) {
+                const int row = 16 * rt + j16;
+#pragma unroll
+                for (int kq = 0; kq < W / 4; ++kq) {
+                    const int lc = 4 * kq + k4;
+                    const bool lv = col_live(lc) && row < R;
+                    if (STAGE) {
+                        const float2 v = lv ? xs[lc * ldx + row] : make_float2(0.f, 0.f);
+                        dst[kq] = v2f{v.x, v.y};
+                    } else {
+                        dst[kq] = raw_buffer_load_v2(rs, lv ? col_base(lc) + row * 8 : limit, 0, kDeviceScope);
+                    }
+                }
+            };
+            v2f xc[W / 4], xn[W / 4];
+            if (wv * 16 < R) load_tile(wv, xc);
+            for (int rt = wv; 16 * rt < R; rt += 4) {
+                if (16 * (rt + 4) < R) load_tile(rt + 4, xn);
+                v4f ar[NT], ai[NT];
+#pragma unroll
+                for (int gn = 0; gn < NT; ++gn) {
+                    ar[gn] = v4f{0.f, 0.f, 0.f, 0.f};
+                    ai[gn] = v4f{0.f, 0.f, 0.f, 0.f};
+                }
+#pragma unroll
+                for (int kq = 0; kq < W / 4; ++kq) {
+                    const v2f x = xc[kq];
+#pragma unroll
+                    for (int gn = 0; gn < NT; ++gn) {
+                        ar[gn] = __builtin_amdgcn_mfma_f32_16x16x4f32(x.x, vr[kq][gn], ar[gn], 0, 0, 0);
+                        ar[gn] = __builtin_amdgcn_mfma_f32_16x16x4f32(-x.y, vi[kq][gn], ar[gn], 0, 0, 0);
+                        ai[gn] = __builtin_amdgcn_mfma_f32_16x16x4f32(x.x, vi[kq][gn], ai[gn], 0, 0, 0);
+                        ai[gn] = __builtin_amdgcn_mfma_f32_16x16x4f32(x.y, vr[kq][gn], ai[gn], 0, 0, 0);
+                    }
+                }
+                const int r0 = 16 * rt + 4 * k4;
+#pragma unroll
+                for (int gn = 0; gn < NT; ++gn) {
+                    const int lc = 16 * gn + j16;
+                    if (!col_live(lc)) continue;
+                    const int base = col_base(lc);
+#pragma unroll
+                    for (int e = 0; e < 4; e += 2) {
+                        const int r = r0 + e;
+                        if (r + 1 < R) {
+                            v4i q;
+                            q.x = f32_bits(ar[gn][e]);
+                            q.y = f32_bits(ai[gn][e]);
+                            q.z = f32_bits(ar[gn][e + 1]);
+                            q.w = f32_bits(ai[gn][e + 1]);
+                            raw_buffer_store_v4(q, rs, base + r * 8, 0, kDeviceScope);
+                        } else if (r < R) {
+                            v2i q;
+                            q.x = f32_bits(ar[gn][e]);
+                            q.y = f32_bits(ai[gn][e]);
+                            raw_buffer_store_v2(q, rs, base + r * 8, 0, kDeviceScope);
+                        }
+                    }
+                }
+#pragma unroll
+                for (int kq = 0; kq < W / 4; ++kq) xc[kq] = xn[kq];
+            }
+        }
+        // every wave's device-scope stores acknowledged before the stamp
+        __builtin_amdgcn_s_waitcnt(0);
+        __syncthreads();
+        if (tid == 0) {
+            if (rotated) atomicOr(&a.rot[(a.sweep % 3) * ns + s], 1);
+            __hip_atomic_store(fl + step * npairs + bp, stamp, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+        }
+    }
+}
+
 __global__ __launch_bounds__(256) void k_zero_ints(int* p, long long n)
 {
     for (long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x; e < n; e += (long long)gridDim.x * blockDim.x)
@@ -962,9 +1366,83 @@ hipError_t launch_sweeps(const JacobiArgs& a, void* scratch, int R, int P, hipSt
     return hipGetLastError();
 }
 
+// Gram block sweep: items of 16 NT columns (NT = 1 up to 256 rows, else 2;
+// TP_PARAM_JACOBI_GRAM 2 / 3 force 1 / 2, 1 turns the form off)
+int gram_nt(int R, int P)
+{
+    const int m = param(TP_PARAM_JACOBI_GRAM);
+    if (m == 1 || P < 16) return 0;
+    if (m == 2) return 1;
+    if (m == 3) return 2;
+    return R <= 256 ? 1 : 2;
+}
+
+SweepPlan gram_plan(int nt, int R, int P, int nslices)
+{
+    SweepPlan sp{};
+    sp.b = 8 * nt;
+    sp.nb = (P + sp.b - 1) / sp.b;
+    sp.nb += sp.nb & 1;
+    if (sp.nb < 2) sp.nb = 2;
+    sp.threads = 256;
+    sp.lds = nt == 1 ? sizeof(GramSmem<1>) : sizeof(GramSmem<2>);
+    sp.lds = (sp.lds + 15) & ~(size_t)15;
+    if (gram_stage_fits(nt, R)) sp.lds += (size_t)gram_ldx(R) * 16 * nt * sizeof(float2);
+    sp.nitems = (sp.nb - 1) * nslices * (sp.nb / 2);
+    int per_cu = (int)((160 * 1024) / (sp.lds + 1024));
+    if (per_cu > 8) per_cu = 8;
+    if (per_cu < 1) per_cu = 1;
+    sp.grid = 256 * per_cu < sp.nitems ? 256 * per_cu : sp.nitems;
+    sp.work_bytes = align_up((size_t)R * P * nslices * sizeof(float2));
+    sp.flag_bytes = align_up((4 * (size_t)nslices + (size_t)nslices * (sp.nb - 1) * (sp.nb / 2) + 5) * sizeof(int));
+    return sp;
+}
+
+template <int NT>
+hipError_t launch_gram_sweeps(const JacobiArgs& a, void* scratch, int R, int P, hipStream_t st)
+{
+    const SweepPlan sp = gram_plan(NT, R, P, a.nslices);
+    char* base = static_cast<char*>(scratch);
+    float2* work = reinterpret_cast<float2*>(base);
+    int* ints = reinterpret_cast<int*>(base + sp.work_bytes);
+    const int ns = a.nslices;
+    int* rot = ints;
+    int* done = rot + 3 * ns;
+    int* flags = done + ns;
+    const long long nflags = (long long)ns * (sp.nb - 1) * (sp.nb / 2);
+    unsigned int* tickets = reinterpret_cast<unsigned int*>(flags + nflags);
+    int* err = reinterpret_cast<int*>(tickets + 4);
+    const long long nints = 4LL * ns + nflags + 5;
+    k_zero_ints<<<(int)((nints + 255) / 256 < 1024 ? (nints + 255) / 256 : 1024), 256, 0, st>>>(ints, nints);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    const size_t per = (size_t)R * P;
+    const int chunks = (int)(per / (256 * 8) + 1) < 64 ? (int)(per / (256 * 8) + 1) : 64;
+    k_jacobi_block_init<<<dim3(chunks, ns), 256, 0, st>>>(a, work, nullptr, rot, done);
+    e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    auto kern = gram_stage_fits(NT, R) ? k_gram_sweep<NT, true> : k_gram_sweep<NT, false>;
+    e = allow_lds(kern, sp.lds);
+    if (e != hipSuccess) return e;
+    SweepArgs sa{work, rot, done, flags, tickets, err, a.count, R, P, ns, sp.nb, sp.b, 0, sp.nitems, a.tol * a.tol};
+    for (int sw = 0; sw < a.max_sweeps; ++sw) {
+        sa.sweep = sw;
+        kern<<<sp.grid, sp.threads, sp.lds, st>>>(sa);
+        e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    }
+    k_jacobi_block_finish<16><<<dim3(chunks, ns), 256, 0, st>>>(a, work, nullptr, rot, done, a.max_sweeps);
+    return hipGetLastError();
+}
+
 template <int G, int RPL, bool WITHV>
 hipError_t launch_blocked(const JacobiArgs& a, void* scratch, int R, int P, const BlockPlan& pl, hipStream_t st)
 {
+    if (!WITHV) {
+        const int nt = gram_nt(R, P);
+        if (nt == 1) return launch_gram_sweeps<1>(a, scratch, R, P, st);
+        if (nt == 2) return launch_gram_sweeps<2>(a, scratch, R, P, st);
+    }
     if (!WITHV && R <= G * RPL && use_sweeps(R)) return launch_sweeps<G, RPL>(a, scratch, R, P, st);
     char* base = static_cast<char*>(scratch);
     float2* work = reinterpret_cast<float2*>(base);
@@ -1031,6 +1509,10 @@ size_t jacobi_scratch_bytes(int m, int n, int nslices, bool withv)
             int G, rpl;
             group_shape(R, &G, &rpl);
             const SweepPlan sp = sweep_plan(G, rpl, R, P, nslices);
+            if (sp.work_bytes + sp.flag_bytes > bytes) bytes = sp.work_bytes + sp.flag_bytes;
+        }
+        if (!withv && gram_nt(R, P) > 0) {
+            const SweepPlan sp = gram_plan(gram_nt(R, P), R, P, nslices);
             if (sp.work_bytes + sp.flag_bytes > bytes) bytes = sp.work_bytes + sp.flag_bytes;
         }
         return bytes;

@@ -1,10 +1,11 @@
 """GPU parity of the per-slice Jacobi SVD on tall slices (more than 256
 rows, the instantiations with 64-lane pair groups) through tp_prox_tnn
 (Algorithm 3), tp_tnn (Definition 2.9) and tp_tsvd (Algorithm 2), against
-the FP64 oracle, in both forms of the kernel: one workgroup per slice with
+the FP64 oracle, in every form of the kernel: one workgroup per slice with
 the slice in LDS (TP_PARAM_JACOBI_MODE 1, where it fits) and the
-multi-workgroup block form (mode 2; always taken when the slice does not fit
-in LDS).
+multi-workgroup block forms (mode 2; always taken when the slice does not fit
+in LDS): block pairs through MFMA Gram matrices (the default without V), and
+the column-rotation forms, one launch per sweep or per block step.
 
 Tolerances as in the other prox / tnn / tsvd tests: prox 1e-4, tnn 1e-5,
 tsvd 1e-5 (relative Frobenius).
@@ -31,17 +32,23 @@ def tp():
 
 JACOBI_BLOCK = 0     # TP_PARAM_JACOBI_BLOCK
 JACOBI_STEPWISE = 9  # TP_PARAM_JACOBI_STEPWISE
+JACOBI_GRAM = 11     # TP_PARAM_JACOBI_GRAM: 1 off, 2 / 3 block pairs of 16 / 32 columns
 
 
-@pytest.fixture(params=[(1, 0), (2, 2), (2, 1)], ids=["one_wg", "blocked_sweep", "blocked_stepwise"])
+# (mode, stepwise, gram): the Gram form applies to the blocked form without V
+# (prox, tnn); tsvd (with V) takes the column-rotation block kernel in all
+@pytest.fixture(params=[(1, 0, 0), (2, 0, 2), (2, 0, 3), (2, 2, 1), (2, 1, 1)],
+                ids=["one_wg", "blocked_gram16", "blocked_gram32", "blocked_sweep", "blocked_stepwise"])
 def mode(request, tp):
     lib = tp._lib.load()
-    m, stepwise = request.param
+    m, stepwise, gram = request.param
     assert lib.tp_set_param(JACOBI_MODE, m) == 0
     assert lib.tp_set_param(JACOBI_STEPWISE, stepwise) == 0
+    assert lib.tp_set_param(JACOBI_GRAM, gram) == 0
     yield request.param
     lib.tp_set_param(JACOBI_MODE, 0)
     lib.tp_set_param(JACOBI_STEPWISE, 0)
+    lib.tp_set_param(JACOBI_GRAM, 0)
 
 
 def gpu(x):
@@ -119,6 +126,7 @@ def test_prox_block_widths(tp, orc, shape, width):
     assert lib.tp_set_param(JACOBI_MODE, 2) == 0
     assert lib.tp_set_param(JACOBI_BLOCK, width) == 0
     assert lib.tp_set_param(JACOBI_STEPWISE, 2) == 0
+    assert lib.tp_set_param(JACOBI_GRAM, 1) == 0
     try:
         Y = inputs.random_tensor(shape, seed=5 * sum(shape) + width)
         tau = 0.2 * orc.tsn(Y)
@@ -140,6 +148,42 @@ def test_prox_block_widths(tp, orc, shape, width):
         lib.tp_set_param(JACOBI_MODE, 0)
         lib.tp_set_param(JACOBI_BLOCK, 0)
         lib.tp_set_param(JACOBI_STEPWISE, 0)
+        lib.tp_set_param(JACOBI_GRAM, 0)
+
+
+# The Gram block sweep (forced, both block-pair widths): ragged last blocks, an
+# empty padding block, odd heights (a last row without its pair), heights below
+# one MFMA row group, conjugate-transposed wide slices, real DC / Nyquist
+# slices (even n3), slices a little above one block pair.
+@pytest.mark.parametrize("gram", [2, 3], ids=["gram16", "gram32"])
+@pytest.mark.parametrize("shape", [(200, 37, 3), (201, 45, 4), (300, 130, 4), (130, 200, 2), (96, 17, 2),
+                                   (600, 70, 3), (200, 200, 5), (7, 40, 3), (1030, 33, 2), (64, 64, 6)],
+                         ids=lambda s: "x".join(map(str, s)))
+def test_prox_gram_sweep(tp, orc, shape, gram):
+    from paper_1806_07247_amd import inputs
+    lib = tp._lib.load()
+    assert lib.tp_set_param(JACOBI_MODE, 2) == 0
+    assert lib.tp_set_param(JACOBI_GRAM, gram) == 0
+    try:
+        Y = inputs.random_tensor(shape, seed=7 * sum(shape) + gram)
+        tau = 0.2 * orc.tsn(Y)
+        h = shape[2] // 2 + 1
+        info = torch.zeros(h, dtype=torch.int32, device="cuda:0")
+        rank = torch.zeros(h, dtype=torch.int32, device="cuda:0")
+        say(f"prox {shape} gram {gram}")
+        X = tp.tp_prox_tnn(gpu(Y), tau, info=info, rank=rank).cpu().numpy()
+        ref = orc.prox_tnn(Y, np.float32(tau))
+        err = rel_fro(X, ref)
+        say(f"  rel.err {err:.3e} sweeps {info.cpu().numpy().tolist()}")
+        assert err <= 1e-4
+        assert int(info.min()) > 0
+        sig = orc.slice_sigma(Y)[:h]
+        assert np.array_equal(rank.cpu().numpy(), (sig > np.float32(tau)).sum(axis=1))
+        v = float(tp.tp_tnn(gpu(Y)).cpu())
+        assert abs(v - orc.tnn(Y)) <= 1e-5 * orc.tnn(Y)
+    finally:
+        lib.tp_set_param(JACOBI_MODE, 0)
+        lib.tp_set_param(JACOBI_GRAM, 0)
 
 
 def test_prox_full_size_slices(tp, orc):
