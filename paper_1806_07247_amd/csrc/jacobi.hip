@@ -800,13 +800,13 @@ __global__ __launch_bounds__(MAXT) void k_jacobi_sweep(SweepArgs a)
 template <int NT>
 struct GramSmem {
     static constexpr int W = 16 * NT, B = 8 * NT;
-    double2 ga[W][W + 1];  // G
-    double2 gb[W][W + 1];  // G J within a step
+    static constexpr int NREG = NT == 1 ? 4 : 2;  // partial-sum regions (one per wave, or per wave pair)
+    double2 g[2][W][W + 1];  // G, double-buffered across the steps of the rotation chain
     union {
-        double part[2][2][W][W];  // [half][re, T][i][j]: per-wave-pair partial sums
-        double2 v[W][W + 1];      // accumulated rotations V
+        double part[NREG][2][W][W];  // [region][re, T][i][j]: partial sums of the waves
+        double2 v[W][W + 1];         // accumulated rotations V
     } u;
-    double rc[B], rsr[B], rsi[B];  // rotation of each pair of the current step
+    double rc[B], rsr[B], rsi[B];  // rotations of the current step (two-pass chain)
     int item;
 };
 
@@ -821,10 +821,15 @@ __device__ __forceinline__ bool pair_rotation(double al, double be, double gr, d
     si = 0.0;
     const double g2 = gr * gr + gi * gi;
     if (!(g2 > 0.0 && g2 > tol2 * al * be)) return false;
+    // e = gamma / |gamma| and c = 1/sqrt(1 + t^2) to FP64 accuracy keep J
+    // unitary to FP64 rounding for any t; t itself (which only sets how
+    // closely gamma is annihilated) comes from the FP32 hardware estimates
     const double ig = rsqrt_f64(g2);
-    const double zeta = 0.5 * (be - al) * ig;
-    const double z2 = fma(zeta, zeta, 1.0);
-    const double t = copysign(rcp_f64(fabs(zeta) + z2 * rsqrt_f64(z2)), zeta);
+    const float zeta = (float)(0.5 * (be - al) * ig);
+    const float az = fabsf(zeta);
+    const float tf = az < 1e18f ? copysignf(__builtin_amdgcn_rcpf(az + __builtin_amdgcn_sqrtf(fmaf(az, az, 1.0f))), zeta)
+                                : 0.5f * __builtin_amdgcn_rcpf(zeta);
+    const double t = (double)tf;
     c = rsqrt_f64(fma(t, t, 1.0));
     const double sn = c * t;
     sr = sn * gr * ig;
@@ -880,7 +885,7 @@ template <int NT, bool STAGE>
 __global__ __launch_bounds__(256) void k_gram_sweep(SweepArgs a)
 {
     constexpr int W = 16 * NT, B = 8 * NT;
-    constexpr int PF = 4;  // row groups per load batch
+    constexpr int PF = NT == 1 ? 8 : 4;  // row groups per load batch
     extern __shared__ __align__(16) char gram_raw[];
     GramSmem<NT>& sm = *reinterpret_cast<GramSmem<NT>*>(gram_raw);
     float2* xs = reinterpret_cast<float2*>(gram_raw + ((sizeof(GramSmem<NT>) + 15) & ~(size_t)15));
@@ -958,11 +963,11 @@ __global__ __launch_bounds__(256) void k_gram_sweep(SweepArgs a)
                 base[g] = col_base(16 * g + j16);
                 live[g] = col_live(16 * g + j16);
             }
-            // wave wv takes the row groups wv + 4 i, i < nw, in batches of PF
-            // whose loads are issued one batch ahead
+            // wave wv takes the row groups wv + 4 i, i < nw, in batches of PF:
+            // 16 columns load a whole batch at once (8 groups, every group of
+            // a 256-row slice), 32 columns issue the loads one batch ahead
             const int ngroups = (R + 7) / 8;
             const int nw = wv < ngroups ? (ngroups - wv + 3) / 4 : 0;
-            v4f cur[PF][NT], nxt[PF][NT];
             auto load_batch = [&](int i0, v4f (&dst)[PF][NT]) {
 #pragma unroll
                 for (int b = 0; b < PF; ++b) {
@@ -971,9 +976,7 @@ __global__ __launch_bounds__(256) void k_gram_sweep(SweepArgs a)
                     for (int g = 0; g < NT; ++g) dst[b][g] = gram_rows2(rs, limit, base[g], r, R, live[g]);
                 }
             };
-            if (nw > 0) load_batch(0, cur);
-            for (int i0 = 0; i0 < nw; i0 += PF) {
-                if (i0 + PF < nw) load_batch(i0 + PF, nxt);
+            auto use_batch = [&](int i0, const v4f (&cur)[PF][NT]) {
 #pragma unroll
                 for (int b = 0; b < PF; ++b) {
                     const v4f* x = cur[b];
@@ -1000,16 +1003,32 @@ __global__ __launch_bounds__(256) void k_gram_sweep(SweepArgs a)
                                 __builtin_amdgcn_mfma_f32_16x16x4f32(x[ti].z, x[tj].w, accT[ti][tj][1], 0, 0, 0);
                         }
                 }
+            };
+            if constexpr (NT == 1) {
+                for (int i0 = 0; i0 < nw; i0 += PF) {
+                    v4f cur[PF][NT];
+                    load_batch(i0, cur);
+                    use_batch(i0, cur);
+                }
+            } else {
+                v4f cur[PF][NT], nxt[PF][NT];
+                if (nw > 0) load_batch(0, cur);
+                for (int i0 = 0; i0 < nw; i0 += PF) {
+                    if (i0 + PF < nw) load_batch(i0 + PF, nxt);
+                    use_batch(i0, cur);
 #pragma unroll
-                for (int b = 0; b < PF; ++b)
+                    for (int b = 0; b < PF; ++b)
 #pragma unroll
-                    for (int g = 0; g < NT; ++g) cur[b][g] = nxt[b][g];
+                        for (int g = 0; g < NT; ++g) cur[b][g] = nxt[b][g];
+                }
             }
-            // partial sums: waves 0, 1 store, waves 2, 3 add theirs (fixed order)
-            for (int pass = 0; pass < 2; ++pass) {
-                if ((wv >> 1) == pass) {
-                    double (*pr)[W] = sm.u.part[wv & 1][0];
-                    double (*pt)[W] = sm.u.part[wv & 1][1];
+            // partial sums: one region per wave (16 columns), or waves 0, 1
+            // store and waves 2, 3 add theirs (32 columns); fixed order
+            constexpr int NREG = GramSmem<NT>::NREG;
+            for (int pass = 0; pass < 4 / NREG; ++pass) {
+                if (wv / NREG == pass) {
+                    double (*pr)[W] = sm.u.part[wv % NREG][0];
+                    double (*pt)[W] = sm.u.part[wv % NREG][1];
 #pragma unroll
                     for (int ti = 0; ti < NT; ++ti)
 #pragma unroll
@@ -1035,11 +1054,15 @@ __global__ __launch_bounds__(256) void k_gram_sweep(SweepArgs a)
         // symmetrised so that G is exactly Hermitian
         for (int e = tid; e < W * W; e += 256) {
             const int i = e / W, jj = e - i * W;
-            const double rij = sm.u.part[0][0][i][jj] + sm.u.part[1][0][i][jj];
-            const double rji = sm.u.part[0][0][jj][i] + sm.u.part[1][0][jj][i];
-            const double tij = sm.u.part[0][1][i][jj] + sm.u.part[1][1][i][jj];
-            const double tji = sm.u.part[0][1][jj][i] + sm.u.part[1][1][jj][i];
-            sm.ga[i][jj] = make_double2(0.5 * (rij + rji), tij - tji);
+            double rij = 0.0, rji = 0.0, tij = 0.0, tji = 0.0;
+#pragma unroll
+            for (int q = 0; q < GramSmem<NT>::NREG; ++q) {
+                rij += sm.u.part[q][0][i][jj];
+                rji += sm.u.part[q][0][jj][i];
+                tij += sm.u.part[q][1][i][jj];
+                tji += sm.u.part[q][1][jj][i];
+            }
+            sm.g[0][i][jj] = make_double2(0.5 * (rij + rji), tij - tji);
         }
         __syncthreads();
         const bool all = step == 0;
@@ -1048,9 +1071,9 @@ __global__ __launch_bounds__(256) void k_gram_sweep(SweepArgs a)
             const int i = e / W, jj = e - i * W;
             sm.u.v[i][jj] = make_double2(i == jj ? 1.0 : 0.0, 0.0);
             if (i < jj && (all || (i < B && jj >= B))) {
-                const double2 g = sm.ga[i][jj];
+                const double2 g = sm.g[0][i][jj];
                 const double g2 = g.x * g.x + g.y * g.y;
-                need |= (g2 > 0.0 && g2 > a.tol2 * sm.ga[i][i].x * sm.ga[jj][jj].x) ? 1 : 0;
+                need |= (g2 > 0.0 && g2 > a.tol2 * sm.g[0][i][i].x * sm.g[0][jj][jj].x) ? 1 : 0;
             }
         }
         // 2. the pair rotations on G (none when no visited pair is above the
@@ -1058,39 +1081,95 @@ __global__ __launch_bounds__(256) void k_gram_sweep(SweepArgs a)
         bool rotated = false;
         if (__syncthreads_or(need)) {
             const int nsteps = all ? W - 1 : B;
-            const int k = tid % B;  // this thread's pair in the first half of a step
-            for (int st = 0; st < nsteps; ++st) {
-                int p, q;
-                gram_pair<W>(all, k, st, p, q);
-                double c, sr, si;
-                const bool r = pair_rotation(sm.ga[p][p].x, sm.ga[q][q].x, sm.ga[p][q].x, sm.ga[p][q].y, a.tol2, c,
-                                             sr, si);
-                if (tid < B) {
-                    sm.rc[k] = c;
-                    sm.rsr[k] = sr;
-                    sm.rsi[k] = si;
+            if constexpr (NT == 1) {
+                // 16 columns, two passes per step over all threads: thread k =
+                // tid mod b takes pair k's rotation; G J into the second
+                // buffer and V J in place, then J^* (G J) back (rows p, q)
+                const int k = tid % B;
+                double2 (*ga)[W + 1] = sm.g[0];
+                double2 (*gb)[W + 1] = sm.g[1];
+                for (int st = 0; st < nsteps; ++st) {
+                    int p, q;
+                    gram_pair<W>(all, k, st, p, q);
+                    double c, sr, si;
+                    const bool r = pair_rotation(ga[p][p].x, ga[q][q].x, ga[p][q].x, ga[p][q].y, a.tol2, c, sr, si);
+                    if (tid < B) {
+                        sm.rc[k] = c;
+                        sm.rsr[k] = sr;
+                        sm.rsi[k] = si;
+                    }
+                    for (int u = tid / B; u < 2 * W; u += 256 / B) {
+                        double2* row = u < W ? &ga[u][0] : &sm.u.v[u - W][0];
+                        double2* out = u < W ? &gb[u][0] : row;
+                        const double2 x = row[p], y = row[q];
+                        out[p] = make_double2(c * x.x - (sr * y.x + si * y.y), c * x.y - (sr * y.y - si * y.x));
+                        out[q] = make_double2((sr * x.x - si * x.y) + c * y.x, (sr * x.y + si * x.x) + c * y.y);
+                    }
+                    if (!__syncthreads_or(r ? 1 : 0)) continue;  // no rotation: G (ga) unchanged
+                    rotated = true;
+                    for (int u = tid; u < B * W; u += 256) {
+                        const int kk = u / W, cc = u - kk * W;
+                        int pp, qq;
+                        gram_pair<W>(all, kk, st, pp, qq);
+                        const double c2 = sm.rc[kk], sr2 = sm.rsr[kk], si2 = sm.rsi[kk];
+                        const double2 x = gb[pp][cc], y = gb[qq][cc];
+                        ga[pp][cc] = make_double2(c2 * x.x - (sr2 * y.x - si2 * y.y), c2 * x.y - (sr2 * y.y + si2 * y.x));
+                        ga[qq][cc] = make_double2((sr2 * x.x + si2 * x.y) + c2 * y.x, (sr2 * x.y - si2 * x.x) + c2 * y.y);
+                    }
+                    __syncthreads();
                 }
-                // G J into gb, V J in place: rows (tid / B) + m 256 / B of G, then of V
-                for (int u = tid / B; u < 2 * W; u += 256 / B) {
-                    double2* row = u < W ? &sm.ga[u][0] : &sm.u.v[u - W][0];
-                    double2* out = u < W ? &sm.gb[u][0] : row;
-                    const double2 x = row[p], y = row[q];
-                    out[p] = make_double2(c * x.x - (sr * y.x + si * y.y), c * x.y - (sr * y.y - si * y.x));
-                    out[q] = make_double2((sr * x.x - si * x.y) + c * y.x, (sr * x.y + si * x.x) + c * y.y);
+            } else {
+                // 32 columns, one pass per step: thread (kr, kc) owns the 2 x 2
+                // block of G in the rows of pair kr and the columns of pair kc,
+                // and rows 2 kr, 2 kr + 1 of V in the columns of pair kc; it
+                // takes both rotations itself, so that a step reads G from one
+                // buffer, writes the other and ends with one barrier: block <-
+                // J_kr^* block J_kc, V <- V J_kc, with J_k = [c, z; -conj(z), c]
+                // on positions (p_k, q_k), z = s e
+                const int kr = tid / B, kc = tid % B;
+                for (int st = 0; st < nsteps; ++st) {
+                    const double2 (*g0)[W + 1] = sm.g[st & 1];
+                    double2 (*g1)[W + 1] = sm.g[(st & 1) ^ 1];
+                    int pr, qr, pc, qc;
+                    gram_pair<W>(all, kr, st, pr, qr);
+                    gram_pair<W>(all, kc, st, pc, qc);
+                    double cr, zr, wr, cc, zc, wc;  // c, Re z, Im z of pairs kr, kc
+                    const bool rr = pair_rotation(g0[pr][pr].x, g0[qr][qr].x, g0[pr][qr].x, g0[pr][qr].y, a.tol2, cr,
+                                                  zr, wr);
+                    const bool rcb = pair_rotation(g0[pc][pc].x, g0[qc][qc].x, g0[pc][qc].x, g0[pc][qc].y, a.tol2,
+                                                   cc, zc, wc);
+                    const double2 a00 = g0[pr][pc], a01 = g0[pr][qc], a10 = g0[qr][pc], a11 = g0[qr][qc];
+                    // M = block J_kc: M0 = c a0 - conj(z) a1, M1 = z a0 + c a1 (per row)
+                    auto col_rot = [&](double2 x, double2 y, double2& o0, double2& o1) {
+                        o0 = make_double2(cc * x.x - (zc * y.x + wc * y.y), cc * x.y - (zc * y.y - wc * y.x));
+                        o1 = make_double2((zc * x.x - wc * x.y) + cc * y.x, (zc * x.y + wc * x.x) + cc * y.y);
+                    };
+                    // J_kr^* M: row p = c M_p - z M_q, row q = conj(z) M_p + c M_q
+                    auto row_rot = [&](double2 x, double2 y, double2& o0, double2& o1) {
+                        o0 = make_double2(cr * x.x - (zr * y.x - wr * y.y), cr * x.y - (zr * y.y + wr * y.x));
+                        o1 = make_double2((zr * x.x + wr * x.y) + cr * y.x, (zr * x.y - wr * x.x) + cr * y.y);
+                    };
+                    double2 m00, m01, m10, m11, n00, n01, n10, n11;
+                    col_rot(a00, a01, m00, m01);
+                    col_rot(a10, a11, m10, m11);
+                    row_rot(m00, m10, n00, n10);
+                    row_rot(m01, m11, n01, n11);
+                    g1[pr][pc] = n00;
+                    g1[pr][qc] = n01;
+                    g1[qr][pc] = n10;
+                    g1[qr][qc] = n11;
+                    if (rcb) {
+#pragma unroll
+                        for (int h = 0; h < 2; ++h) {
+                            double2* vrow = &sm.u.v[2 * kr + h][0];
+                            double2 o0, o1;
+                            col_rot(vrow[pc], vrow[qc], o0, o1);
+                            vrow[pc] = o0;
+                            vrow[qc] = o1;
+                        }
+                    }
+                    if (__syncthreads_or((rr || rcb) ? 1 : 0)) rotated = true;
                 }
-                if (!__syncthreads_or(r ? 1 : 0)) continue;  // no rotation: G (ga) unchanged
-                rotated = true;
-                // J^* (G J) back into ga: rows p, q of every column
-                for (int u = tid; u < B * W; u += 256) {
-                    const int kk = u / W, cc = u - kk * W;
-                    int pp, qq;
-                    gram_pair<W>(all, kk, st, pp, qq);
-                    const double c2 = sm.rc[kk], sr2 = sm.rsr[kk], si2 = sm.rsi[kk];
-                    const double2 x = sm.gb[pp][cc], y = sm.gb[qq][cc];
-                    sm.ga[pp][cc] = make_double2(c2 * x.x - (sr2 * y.x - si2 * y.y), c2 * x.y - (sr2 * y.y + si2 * y.x));
-                    sm.ga[qq][cc] = make_double2((sr2 * x.x + si2 * x.y) + c2 * y.x, (sr2 * x.y - si2 * x.x) + c2 * y.y);
-                }
-                __syncthreads();
             }
         }
         // 3. X <- X V: lane (j16, k4) feeds row 16 rt + j16 of column 4 kq + k4
