@@ -8,10 +8,10 @@ Prints one JSON line.
 Headline: learned-rank prox_tnn against full-SVD prox_tnn on the prox calls
 of a TRPCA-ADMM run on a held-out problem of the learned-rank workload
 (X = P*Q + S, 1024 x 1024 x 64, tubal rank r ~ U{5..40}, 5% +-1 outliers,
-seed 10000).  The ADMM run is made first (with the learned prox) and every
-call's input Y_t, tau_t = 1/mu_t and the previous call's outputs it takes
-(per-slice counts, leading singular values, range basis for the warm start)
-are kept in HBM.  A step is one learned prox call
+seed 10000).  The ADMM run is made first, by the native tp_trpca with the
+learned prox, which records per iteration the call's input Y_t and the
+outputs the next call takes (per-slice counts, leading singular values,
+range basis for the warm start); with tau_t = 1/mu_t they stay in HBM.  A step is one learned prox call
 (FFT, slice features, rank MLP, randomized SVD with the count check and the
 a posteriori check, full-SVD fallback, reconstruction, inverse FFT) on one
 captured call; K steps walk through the captured calls (evenly spaced when
@@ -164,27 +164,34 @@ def learned_block(args, tp, dev):
 
     n, n3 = 1024, 64
     X, L0, r = trpca.learned_workload(args.learned_seed, dev, n, n3)
-    shape = (n, n, n3)
     h = n3 // 2 + 1
     mlp = rank_model.load(device=dev)
-    prox = trpca.ProxLearned(shape, dev, mlp=mlp)
-    calls = []
-
-    def cap(k, Y, tau):
-        wb, wc = prox.warm_inputs()
-        calls.append(dict(Y=Y.clone(), tau=tau, seed=prox.calls,
-                          prev=prox.prev.clone() if prox.have_prev else None,
-                          psig=prox.prev_sigma.clone() if prox.have_prev else None,
-                          wb=wb.clone() if wb is not None else None, wc=wc.clone() if wc is not None else None))
-
-    log(f"learned-rank workload {n}x{n}x{n3} seed {args.learned_seed} r {r}: ADMM capture")
+    # the prox calls of one native TRPCA-ADMM run (tp_trpca with the learned
+    # prox at its default settings), recorded per iteration: the input, and
+    # the counts, singular values and warm-start basis that the next call
+    # takes; tau_t = 1/mu_t with mu_t = mu_0 rho^t (the driver's schedule)
+    max_calls, mu0, rho, mu_max = 64, 1e-3, 1.1, 1e10
+    rec = dict(max_calls=max_calls,
+               inputs=torch.empty((max_calls, n, n, n3), dtype=torch.float32, device=dev),
+               counts=torch.zeros((max_calls, h), dtype=torch.int32, device=dev),
+               sigmas=torch.zeros((max_calls, h, tp.TP_SIGMA_KEEP), dtype=torch.float32, device=dev),
+               bases=torch.zeros((max_calls,) + tuple(tp.basis_shape(n, n3)), dtype=torch.float32, device=dev),
+               basis_cols=torch.zeros((max_calls, h), dtype=torch.int32, device=dev))
+    log(f"learned-rank workload {n}x{n}x{n3} seed {args.learned_seed} r {r}: ADMM capture (native tp_trpca)")
     t0 = time.perf_counter()
-    res = trpca.trpca(X, prox, capture=cap)
+    res = tp.tp_trpca(X, mu=mu0, rho=rho, mu_max=mu_max, learned=dict(mlp=mlp), record=rec)
     torch.cuda.synchronize()
-    log(f"  {res['iters']} ADMM iterations ({len(calls)} prox calls) in {time.perf_counter() - t0:.1f} s, "
+    ncalls = min(res["iters"], max_calls)
+    calls, mu = [], mu0
+    for it in range(ncalls):
+        prev = it - 1
+        calls.append(dict(Y=rec["inputs"][it], tau=float(np.float32(1.0 / mu)), seed=it,
+                          prev=rec["counts"][prev] if it else None, psig=rec["sigmas"][prev] if it else None,
+                          wb=rec["bases"][prev] if it else None, wc=rec["basis_cols"][prev] if it else None))
+        mu = min(rho * mu, mu_max)
+    log(f"  {res['iters']} ADMM iterations ({ncalls} prox calls) in {time.perf_counter() - t0:.1f} s, "
         f"L rel.err {float((res['L'] - L0).norm() / L0.norm()):.2e}")
     del X, L0, res
-    ncalls = len(calls)
     steps = args.steps if args.steps else ncalls
     sel = selection(steps, ncalls)
 
