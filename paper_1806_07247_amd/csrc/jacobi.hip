@@ -417,7 +417,8 @@ __global__ __launch_bounds__(256) void k_jacobi_block_init(JacobiArgs a, float2*
 
 template <int G>
 __global__ __launch_bounds__(256) void k_jacobi_block_finish(JacobiArgs a, const float2* work, const float2* v,
-                                                             const int* rot, const int* done, int sweeps_run)
+                                                             const int* rot, const int* done, int sweeps_run,
+                                                             int ring = 3)
 {
     const int s = blockIdx.y;
     if (a.count && s >= *a.count) return;
@@ -427,7 +428,7 @@ __global__ __launch_bounds__(256) void k_jacobi_block_finish(JacobiArgs a, const
     if (v) store_q(a, s, v + (long long)s * P * P, P, blockIdx.x, gridDim.x);
     if (a.info && blockIdx.x == 0 && threadIdx.x == 0) {
         int d = done[s];
-        if (d == 0 && sweeps_run > 0 && rot[((sweeps_run - 1) % 3) * a.nslices + s] == 0) d = sweeps_run;
+        if (d == 0 && sweeps_run > 0 && rot[((sweeps_run - 1) % ring) * a.nslices + s] == 0) d = sweeps_run;
         a.info[s] = d > 0 ? d : -sweeps_run;
     }
 }
@@ -461,7 +462,12 @@ struct SweepArgs {
     const int* count;       // optional device count of live slices (<= nslices)
     int R, P, nslices, nb, b, sweep, nitems;
     double tol2;
+    int nsw;                // Gram sweep: sweeps per launch (sweep .. sweep + nsw - 1; nitems covers them)
 };
+
+// Gram sweep: sweeps per launch.  Its rotation flags have one row per sweep
+// (max_sweeps rows, zeroed once), so no row is reused within a call.
+constexpr int kGramSweepsPerLaunch = 3;
 
 // position of block beta in step t of the circle order over nb blocks
 __device__ __forceinline__ int rr_pos(int beta, int t, int nb)
@@ -895,46 +901,56 @@ __global__ __launch_bounds__(256) void k_gram_sweep(SweepArgs a)
     const int npairs = a.nb / 2, per_step = a.nslices * npairs;
     const int live_slices = a.count ? min(*a.count, a.nslices) : a.nslices;
     if (live_slices <= 0) return;
-    const int ns = a.nslices, stamp = a.sweep + 1;
+    // The launch covers sweeps a.sweep .. a.sweep + nsw - 1, items numbered
+    // sweep-major (sweep, step, slice, pair).  A slice whose previous sweep
+    // (the last of the previous launch) rotated nothing is converged and its
+    // items return; within a launch every sweep runs (one that rotates
+    // nothing stores nothing), and the next launch sees the last one's flag.
+    // Rotation flags: rot[sweep * ns + slice].
+    const int ns = a.nslices, per_sweep = (a.nb - 1) * per_step, launch = a.sweep / max(a.nsw, 1);
     if (a.sweep > 0) {  // every live slice converged: the launch has nothing to do
         int busy = 0;
-        for (int q = tid; q < live_slices; q += blockDim.x) busy |= a.rot[((a.sweep - 1) % 3) * ns + q];
+        for (int q = tid; q < live_slices; q += blockDim.x) busy |= a.rot[(a.sweep - 1) * ns + q];
         if (!__syncthreads_or(busy)) {
             if (blockIdx.x == 0)
-                for (int q = tid; q < live_slices; q += blockDim.x) {
-                    a.rot[((a.sweep + 1) % 3) * ns + q] = 0;
+                for (int q = tid; q < live_slices; q += blockDim.x)
                     if (a.done[q] == 0) a.done[q] = a.sweep;
-                }
             return;
         }
     }
     for (;;) {
         if (tid == 0) {
-            const unsigned int tk = atomicAdd(a.tickets + (a.sweep & 3), 1u);
-            if (tk == 0) a.tickets[(a.sweep + 2) & 3] = 0;
+            const unsigned int tk = atomicAdd(a.tickets + (launch & 3), 1u);
+            // the counter of launch + 2 was last used by launch - 2, which has ended
+            if (tk == 0) a.tickets[(launch + 2) & 3] = 0;
             sm.item = (int)tk;
         }
         __syncthreads();
         const int item = sm.item;
         if (item >= a.nitems) return;
-        const int step = item / per_step, rem = item - step * per_step, s = rem / npairs, bp = rem - s * npairs;
+        const int ls = item / per_sweep, irem = item - ls * per_sweep;
+        const int sweep = a.sweep + ls, stamp = sweep + 1;
+        const int step = irem / per_step, rem = irem - step * per_step, s = rem / npairs, bp = rem - s * npairs;
         if (s >= live_slices) {
             __syncthreads();
             continue;
         }
-        if (step == 0 && bp == 0 && tid == 0) a.rot[((a.sweep + 1) % 3) * ns + s] = 0;
-        if (a.sweep > 0 && a.rot[((a.sweep - 1) % 3) * ns + s] == 0) {
-            if (step == 0 && bp == 0 && tid == 0 && a.done[s] == 0) a.done[s] = a.sweep;
+        if (a.sweep > 0 && a.rot[(a.sweep - 1) * ns + s] == 0) {  // converged before this launch
+            if (ls == 0 && step == 0 && bp == 0 && tid == 0 && a.done[s] == 0) a.done[s] = a.sweep;
             __syncthreads();
             continue;
         }
         const int b1 = rr_col(bp, step, a.nb), b2 = rr_col(a.nb - 1 - bp, step, a.nb);
         const int c1 = block_cols(b1, B, a.P), c2 = block_cols(b2, B, a.P);
         int* fl = a.flags + (long long)s * (a.nb - 1) * npairs;
-        if (step > 0 && tid == 0) {
-            const int q1 = rr_pos(b1, step - 1, a.nb), q2 = rr_pos(b2, step - 1, a.nb);
-            wait_stamp(fl + (step - 1) * npairs + min(q1, a.nb - 1 - q1), stamp, a.err);
-            wait_stamp(fl + (step - 1) * npairs + min(q2, a.nb - 1 - q2), stamp, a.err);
+        // wait for the items that last wrote the two blocks: at the previous
+        // step, or at the last step of the previous sweep when it ran in this
+        // launch (smaller tickets: workgroups already running)
+        if (tid == 0 && (step > 0 || ls > 0)) {
+            const int ps = step > 0 ? step - 1 : a.nb - 2, want = step > 0 ? stamp : stamp - 1;
+            const int q1 = rr_pos(b1, ps, a.nb), q2 = rr_pos(b2, ps, a.nb);
+            wait_stamp(fl + ps * npairs + min(q1, a.nb - 1 - q1), want, a.err);
+            wait_stamp(fl + ps * npairs + min(q2, a.nb - 1 - q2), want, a.err);
         }
         __syncthreads();
         const int limit = a.P * R * (int)sizeof(float2);
@@ -1254,7 +1270,7 @@ __global__ __launch_bounds__(256) void k_gram_sweep(SweepArgs a)
         __builtin_amdgcn_s_waitcnt(0);
         __syncthreads();
         if (tid == 0) {
-            if (rotated) atomicOr(&a.rot[(a.sweep % 3) * ns + s], 1);
+            if (rotated) atomicOr(&a.rot[sweep * ns + s], 1);
             __hip_atomic_store(fl + step * npairs + bp, stamp, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
         }
     }
@@ -1456,6 +1472,10 @@ int gram_nt(int R, int P)
     return R <= 256 ? 1 : 2;
 }
 
+// rows of the Gram sweep's rotation flags: one per sweep of the cap (at least
+// the three rows the shared initialisation kernel clears)
+int gram_flag_rows() { return std::max(3, param(TP_PARAM_JACOBI_SWEEPS)); }
+
 SweepPlan gram_plan(int nt, int R, int P, int nslices)
 {
     SweepPlan sp{};
@@ -1473,7 +1493,9 @@ SweepPlan gram_plan(int nt, int R, int P, int nslices)
     if (per_cu < 1) per_cu = 1;
     sp.grid = 256 * per_cu < sp.nitems ? 256 * per_cu : sp.nitems;
     sp.work_bytes = align_up((size_t)R * P * nslices * sizeof(float2));
-    sp.flag_bytes = align_up((4 * (size_t)nslices + (size_t)nslices * (sp.nb - 1) * (sp.nb / 2) + 5) * sizeof(int));
+    // rot [max_sweeps][ns] (one row per sweep), done [ns], flags, tickets [4], err
+    const size_t rows = (size_t)gram_flag_rows();
+    sp.flag_bytes = align_up(((rows + 1) * nslices + (size_t)nslices * (sp.nb - 1) * (sp.nb / 2) + 5) * sizeof(int));
     return sp;
 }
 
@@ -1481,17 +1503,19 @@ template <int NT>
 hipError_t launch_gram_sweeps(const JacobiArgs& a, void* scratch, int R, int P, hipStream_t st)
 {
     const SweepPlan sp = gram_plan(NT, R, P, a.nslices);
+    const int rows = gram_flag_rows();
+    if (a.max_sweeps > rows) return hipErrorInvalidValue;  // the flags are sized for the sweep cap
     char* base = static_cast<char*>(scratch);
     float2* work = reinterpret_cast<float2*>(base);
     int* ints = reinterpret_cast<int*>(base + sp.work_bytes);
     const int ns = a.nslices;
     int* rot = ints;
-    int* done = rot + 3 * ns;
+    int* done = rot + (long long)rows * ns;
     int* flags = done + ns;
     const long long nflags = (long long)ns * (sp.nb - 1) * (sp.nb / 2);
     unsigned int* tickets = reinterpret_cast<unsigned int*>(flags + nflags);
     int* err = reinterpret_cast<int*>(tickets + 4);
-    const long long nints = 4LL * ns + nflags + 5;
+    const long long nints = (long long)(rows + 1) * ns + nflags + 5;
     k_zero_ints<<<(int)((nints + 255) / 256 < 1024 ? (nints + 255) / 256 : 1024), 256, 0, st>>>(ints, nints);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
@@ -1503,14 +1527,17 @@ hipError_t launch_gram_sweeps(const JacobiArgs& a, void* scratch, int R, int P, 
     auto kern = gram_stage_fits(NT, R) ? k_gram_sweep<NT, true> : k_gram_sweep<NT, false>;
     e = allow_lds(kern, sp.lds);
     if (e != hipSuccess) return e;
-    SweepArgs sa{work, rot, done, flags, tickets, err, a.count, R, P, ns, sp.nb, sp.b, 0, sp.nitems, a.tol * a.tol};
-    for (int sw = 0; sw < a.max_sweeps; ++sw) {
+    SweepArgs sa{work, rot, done, flags, tickets, err, a.count, R, P, ns, sp.nb, sp.b, 0, 0, a.tol * a.tol,
+                 kGramSweepsPerLaunch};
+    const int per_sweep = sp.nitems;  // (nb - 1) steps x slices x pairs
+    for (int sw = 0; sw < a.max_sweeps; sw += kGramSweepsPerLaunch) {
         sa.sweep = sw;
+        sa.nitems = std::min(kGramSweepsPerLaunch, a.max_sweeps - sw) * per_sweep;
         kern<<<sp.grid, sp.threads, sp.lds, st>>>(sa);
         e = hipGetLastError();
         if (e != hipSuccess) return e;
     }
-    k_jacobi_block_finish<16><<<dim3(chunks, ns), 256, 0, st>>>(a, work, nullptr, rot, done, a.max_sweeps);
+    k_jacobi_block_finish<16><<<dim3(chunks, ns), 256, 0, st>>>(a, work, nullptr, rot, done, a.max_sweeps, rows);
     return hipGetLastError();
 }
 
