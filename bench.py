@@ -238,10 +238,12 @@ def learned_block(args, tp, dev):
     # launch of the call)
     distinct_calls = sorted(set(sel))
     graphs = {}
+    if args.no_graph:  # counter runs: rocprofv3's counter collection does not take stream capture
+        distinct_calls = []
     side = torch.cuda.Stream()
     side.wait_stream(torch.cuda.current_stream())
     with torch.cuda.stream(side):
-        learned(distinct_calls[0], out)
+        learned(sel[0], out)
     torch.cuda.current_stream().wait_stream(side)
     torch.cuda.synchronize()
     for i in distinct_calls:
@@ -249,15 +251,17 @@ def learned_block(args, tp, dev):
         with torch.cuda.graph(g):
             learned(i, out)
         graphs[i] = g
-    for j in range(args.warmup):
-        graphs[sel[j % steps]].replay()
-    torch.cuda.synchronize()
-    start.record()
-    for j in range(steps):
-        graphs[sel[j]].replay()
-    stop.record()
-    torch.cuda.synchronize()
-    ms_graph = start.elapsed_time(stop) / steps
+    ms_graph = float("inf")
+    if graphs:
+        for j in range(args.warmup):
+            graphs[sel[j % steps]].replay()
+        torch.cuda.synchronize()
+        start.record()
+        for j in range(steps):
+            graphs[sel[j]].replay()
+        stop.record()
+        torch.cuda.synchronize()
+        ms_graph = start.elapsed_time(stop) / steps
     del graphs
     ms = min(ms_eager, ms_graph)
     # traced pass over the same calls: HIP events around every launch on its
@@ -294,7 +298,8 @@ def learned_block(args, tp, dev):
     value = n * n * n3 / (ms * 1e-3) / 1e6
     log(f"  learned: {ms:.3f} ms/call (eager {ms_eager:.3f}, graph replay {ms_graph:.3f}; "
         f"{ms_traced:.3f} traced), {value:.1f} Melem/s; stages {json.dumps(stages)}")
-    timing = {"ms_per_call_eager": round(ms_eager, 4), "ms_per_call_graph_replay": round(ms_graph, 4),
+    timing = {"ms_per_call_eager": round(ms_eager, 4),
+              "ms_per_call_graph_replay": round(ms_graph, 4) if ms_graph != float("inf") else None,
               "value_from": "graph replay" if ms_graph <= ms_eager else "eager",
               "ms_per_call_traced_pass": round(ms_traced, 4)}
 
@@ -763,6 +768,8 @@ def main():
     ap.add_argument("--learned-seed", type=int, default=LEARNED_SEED)
     ap.add_argument("--full-calls", type=int, default=0, help="calls timed through the full SVD (0: all)")
     ap.add_argument("--no-full", action="store_true", help="skip the full-SVD comparison (a counter-run driver)")
+    ap.add_argument("--no-graph", action="store_true", help="skip the graph-replay pass of the learned calls "
+                    "(counter runs: the profiler's counter collection does not take stream capture)")
     ap.add_argument("--prox-steps", type=int, default=20)
     ap.add_argument("--tprod-steps", type=int, default=10)
     ap.add_argument("--no-cpu-baseline", action="store_true")
