@@ -46,6 +46,16 @@ struct tp_batch {
     double fwd_bytes = 0, inv_bytes = 0, g1_flops = 0, g1_bytes = 0, g2_flops = 0, g2_bytes = 0;
     char* ws = nullptr;  // bound workspace
     bool bound = false;
+    // the Jacobi classes after the first run on side streams, forked from and
+    // joined back to the run's stream with events (graph-capturable); made
+    // by bind, default priority
+    std::vector<hipStream_t> side;
+    std::vector<hipEvent_t> ev;  // [0]: fork, [1 + i]: join of side stream i
+    ~tp_batch()
+    {
+        for (hipEvent_t e : ev) (void)hipEventDestroy(e);
+        for (hipStream_t x : side) (void)hipStreamDestroy(x);
+    }
 };
 
 namespace {
@@ -366,6 +376,18 @@ int tp_batch_bind(tp_batch* p, void* workspace, size_t workspace_bytes, void* st
     TP_UP(p->off_ju, p->ju);
     TP_UP(p->off_su, p->su);
 #undef TP_UP
+    if (p->op != TP_BATCH_TPROD && p->jcls.size() > 1 && p->side.empty()) {
+        for (size_t i = 1; i < p->jcls.size(); ++i) {
+            hipStream_t x;
+            TP_TRY(hipStreamCreateWithFlags(&x, hipStreamNonBlocking));
+            p->side.push_back(x);
+        }
+        for (size_t i = 0; i < p->jcls.size(); ++i) {
+            hipEvent_t e;
+            TP_TRY(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+            p->ev.push_back(e);
+        }
+    }
     TP_TRY(hipStreamSynchronize(s));
     p->bound = true;
     return TP_OK;
@@ -384,11 +406,21 @@ int tp_batch_run(const tp_batch* p, void* stream)
                   tp::launch_cgemm_batch(dev<tp::CgemmArgs>(p, p->off_g1), dev<tp::GemmUnit>(p, p->off_u1),
                                          (int)p->u1.size(), p->tile, p->grid_gemm, p->g1_flops, p->g1_bytes, s));
     } else {
-        for (const tp_batch::JClass& c : p->jcls)
-            TP_LAUNCH(tp::K_JACOBI, s,
+        // the classes touch disjoint slices: the first on the run's stream,
+        // the others at the same time on the side streams
+        const size_t nside = p->side.size();
+        if (nside) TP_TRY(hipEventRecord(p->ev[0], s));
+        for (size_t i = 0; i < p->jcls.size(); ++i) {
+            const tp_batch::JClass& c = p->jcls[i];
+            hipStream_t cs = (i == 0 || nside == 0) ? s : p->side[i - 1];
+            if (cs != s) TP_TRY(hipStreamWaitEvent(cs, p->ev[0], 0));
+            TP_LAUNCH(tp::K_JACOBI, cs,
                       tp::launch_jacobi_batch(dev<tp::JacobiArgs>(p, p->off_jac),
                                               dev<tp::SliceUnit>(p, p->off_ju) + c.start, c.count, c.max_r, c.max_p,
-                                              c.grid, s));
+                                              c.grid, cs));
+            if (cs != s) TP_TRY(hipEventRecord(p->ev[i], cs));
+        }
+        for (size_t i = 1; nside && i < p->jcls.size(); ++i) TP_TRY(hipStreamWaitEvent(s, p->ev[i], 0));
         TP_LAUNCH(tp::K_SHRINK, s,
                   tp::launch_shrink_batch(dev<tp::ShrinkItem>(p, p->off_shr), dev<tp::SliceUnit>(p, p->off_su),
                                           (int)p->su.size(), p->grid_jac, s));
