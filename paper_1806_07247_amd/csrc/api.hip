@@ -1054,15 +1054,18 @@ int tp_prox_tnn_learned(const float* Y, float* X, int n1, int n2, int n3, float 
             j.gate = run;
             j.pdyn = width;
             TP_LAUNCH(tp::K_JACOBI, s, tp::launch_jacobi(j, nullptr, 0, s));
+            // (with the a posteriori check, V_r and C_r also go to the planar
+            // operands of its products in the same launch)
+            const bool acc = opts->accuracy > 0.0f;
             TP_LAUNCH(tp::K_RSVD_CHECK, s,
                       tp::launch_rsvd_check(W.jcols, W.jsig, W.jv, W.kpred, W.lact, W.prefb, W.status, L,
-                                            (double)tau, W.T, fb, rk, h, s, run));
-            if (!(opts->accuracy > 0.0f)) break;
+                                            (double)tau, W.T, fb, rk, h, s, run, acc ? W.vp : tp::Planes{},
+                                            acc ? W.cp : tp::Planes{}));
+            if (!acc) break;
             // a posteriori check: residuals Ybar v_j - sigma_j u_j of the kept Ritz triplets
             Dyn dr;
             dr.gate = run;
             dr.k = width;
-            TP_LAUNCH(tp::K_ACCURACY, s, tp::launch_cm_to_planar(W.jv, W.vp, L, h, s, run, W.jcols, W.cp));
             Dyn dn;
             dn.gate = run;
             dn.n = width;

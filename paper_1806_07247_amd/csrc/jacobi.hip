@@ -223,8 +223,40 @@ __device__ __forceinline__ void store_q(const JacobiArgs& a, int s, const float2
 }
 
 // ---- whole slice in one workgroup (LDS when it fits, else workspace) ----
+// Sweeps over the first Ps columns, touching the first Rs rows of the work
+// matrix (stride R) and the first Pv rows of V (stride P): RPL rows per lane
+// cover Rs and Pv.
+template <int G, int RPL, bool WITHV>
+__device__ __forceinline__ void sweeps_whole(const JacobiArgs& a, float2* work, float2* vw, int R, int P, int Ps,
+                                             int Rs, int Pv, int& rotated, int& sweep, bool& converged)
+{
+    const int np = Ps + (Ps & 1);
+    const int tid = threadIdx.x, group = tid / G, gl = tid % G, ngroups = blockDim.x / G;
+    const double tol2 = a.tol * a.tol;
+    while (!converged && sweep < a.max_sweeps) {
+        for (int step = 0; step < np - 1; ++step) {
+            for (int pair = group; pair < np / 2; pair += ngroups) {
+                const int p = rr_col(pair, step, np);
+                const int q = rr_col(np - 1 - pair, step, np);
+                if (p >= Ps || q >= Ps) continue;
+                if (jacobi_pair<G, RPL, WITHV>(work, R, p, q, Rs, gl, tol2, vw, P, Pv) && gl == 0)
+                    rotated = 1;
+            }
+            __syncthreads();
+        }
+        ++sweep;
+        converged = (rotated == 0);
+        __syncthreads();
+        if (tid == 0) rotated = 0;
+        __syncthreads();
+    }
+}
+
 // Slice s of a, held in `work` (R x P, then P x P rotations with WITHV);
-// `rotated` is a workgroup-shared flag.
+// `rotated` is a workgroup-shared flag.  With a.pdyn the first *pdyn columns
+// are swept and the rows from *pdyn on are zero (the caller's contract), so
+// the rotations touch the first *pdyn rows only (of the work matrix and of
+// V), with 2 or 3 rows per lane when that covers them.
 template <int G, int RPL, bool WITHV>
 __device__ __forceinline__ void jacobi_whole(const JacobiArgs& a, int s, float2* work, int& rotated)
 {
@@ -238,27 +270,16 @@ __device__ __forceinline__ void jacobi_whole(const JacobiArgs& a, int s, float2*
     __syncthreads();
 
     const int Ps = a.pdyn ? min(P, *a.pdyn) : P;  // columns swept
-    const int np = Ps + (Ps & 1);
-    const int group = tid / G, gl = tid % G, ngroups = blockDim.x / G;
-    const double tol2 = a.tol * a.tol;
+    const int Rs = a.pdyn ? min(R, Ps) : R;       // rows of the work matrix touched
+    const int Pv = a.pdyn ? Ps : P;               // rows of V touched (Ps <= P <= R)
     int sweep = 0;
     bool converged = (Ps < 2);
-    while (!converged && sweep < a.max_sweeps) {
-        for (int step = 0; step < np - 1; ++step) {
-            for (int pair = group; pair < np / 2; pair += ngroups) {
-                const int p = rr_col(pair, step, np);
-                const int q = rr_col(np - 1 - pair, step, np);
-                if (p >= Ps || q >= Ps) continue;
-                if (jacobi_pair<G, RPL, WITHV>(work, R, p, q, R, gl, tol2, vw, P, P) && gl == 0) rotated = 1;
-            }
-            __syncthreads();
-        }
-        ++sweep;
-        converged = (rotated == 0);
-        __syncthreads();
-        if (tid == 0) rotated = 0;
-        __syncthreads();
-    }
+    if (RPL > 2 && Rs <= 2 * G)
+        sweeps_whole<G, (RPL > 2 ? 2 : RPL), WITHV>(a, work, vw, R, P, Ps, Rs, Pv, rotated, sweep, converged);
+    else if (RPL > 3 && Rs <= 3 * G)
+        sweeps_whole<G, (RPL > 3 ? 3 : RPL), WITHV>(a, work, vw, R, P, Ps, Rs, Pv, rotated, sweep, converged);
+    else
+        sweeps_whole<G, RPL, WITHV>(a, work, vw, R, P, Ps, Rs, Pv, rotated, sweep, converged);
     store_result<G>(a, s, work, R, P, 0, 1);
     if (WITHV) store_q(a, s, vw, P, 0, 1);
     if (a.info && tid == 0) a.info[s] = converged ? (sweep > 0 ? sweep : 1) : -sweep;

@@ -564,12 +564,16 @@ __global__ __launch_bounds__(kCholThreads) void k_chol(const double2* __restrict
 // Jacobi SVD of R2^*.  fallback[s] = 1 when #{sigma_j >= tau} > kpred[s]
 // (the check sigma_(k+1) < tau fails) or when the slice was already sent to
 // the full SVD; T = C_r diag((sigma - tau)_+ / sigma) V_r^* (planar, L x L).
+// With vp / cp given, V_r and C_r are also written planar row-major (L x L,
+// the operands of the a posteriori check's products).
 __global__ __launch_bounds__(256) void k_rsvd_check(const float2* __restrict__ cols, const double* __restrict__ sigma,
                                                     const float2* __restrict__ vr, const int* __restrict__ kpred,
                                                     const int* __restrict__ lact, const int* __restrict__ prefb,
                                                     const int* __restrict__ status, int L, double tau,
                                                     float* __restrict__ tr, float* __restrict__ ti,
-                                                    int* __restrict__ fallback, int* __restrict__ rank, const int* __restrict__ gate)
+                                                    int* __restrict__ fallback, int* __restrict__ rank, const int* __restrict__ gate,
+                                                    float* __restrict__ vpr, float* __restrict__ vpi,
+                                                    float* __restrict__ cpr, float* __restrict__ cpi)
 {
     if (gate && *gate == 0) return;
     __shared__ double scale[64];
@@ -615,6 +619,16 @@ __global__ __launch_bounds__(256) void k_rsvd_check(const float2* __restrict__ c
         tr[(long long)s * L * L + e] = (float)vr_;
         ti[(long long)s * L * L + e] = (float)vi_;
     }
+    if (vpr)  // column-major to planar row-major, as k_cm_to_planar
+        for (int e = tid; e < L * L; e += blockDim.x) {
+            const int i = e / L, j = e % L;
+            const long long o = (long long)s * L * L + (long long)j * L + i, d = (long long)s * L * L + e;
+            const float2 v = vr[o], c = cols[o];
+            vpr[d] = v.x;
+            vpi[d] = v.y;
+            cpr[d] = c.x;
+            cpi[d] = c.y;
+        }
 }
 
 // ---------------------------------------------------- a posteriori check --
@@ -1310,10 +1324,11 @@ size_t cholqr_part_bytes(int m, int L, int nslices)
 
 hipError_t launch_rsvd_check(const float2* cols, const double* sigma, const float2* vr, const int* kpred,
                              const int* lact, const int* prefb, const int* status, int L, double tau, Planes T,
-                             int* fallback, int* rank, int nslices, hipStream_t st, const int* gate)
+                             int* fallback, int* rank, int nslices, hipStream_t st, const int* gate, Planes vp,
+                             Planes cp)
 {
     k_rsvd_check<<<nslices, 256, 0, st>>>(cols, sigma, vr, kpred, lact, prefb, status, L, tau, T.re, T.im, fallback,
-                                          rank, gate);
+                                          rank, gate, vp.re, vp.im, cp.re, cp.im);
     return hipGetLastError();
 }
 

@@ -202,7 +202,8 @@ struct JacobiArgs {
     const int* count; // optional device count of live slices (<= nslices); the rest are skipped
     const int* gate;  // optional device flag: 0 makes the call do nothing
     const int* pdyn;  // optional device cap on the columns swept (one workgroup per slice only; the
-                      // layout keeps n, the columns beyond are left as they are)
+                      // layout keeps n, the columns beyond are left as they are).  The rows from
+                      // *pdyn on must be zero: the rotations touch the first *pdyn rows only
 };
 // Batched per-slice SVDs (whole slice in LDS, R = max(m, n) <= 128) and
 // shrinkage over (item, slice) units.
@@ -281,10 +282,12 @@ hipError_t launch_cholqr_pass(const float* yr, const float* yi, int m, int L, co
 hipError_t launch_reduce_gram(const float* parts, int ksplit, int m, int L, int nslices, int real_first, int real_last,
                               float* yr, float* yi, const int* lact, double2* part, hipStream_t s,
                               const int* gate = nullptr, const int* width = nullptr);
-// status: per-slice CholeskyQR breakdown flags (or null), OR-ed into fallback
+// status: per-slice CholeskyQR breakdown flags (or null), OR-ed into fallback;
+// vp / cp (optional): V_r and C_r also written planar row-major
 hipError_t launch_rsvd_check(const float2* cols, const double* sigma, const float2* vr, const int* kpred,
                              const int* lact, const int* prefb, const int* status, int L, double tau, Planes T,
-                             int* fallback, int* rank, int nslices, hipStream_t s, const int* gate = nullptr);
+                             int* fallback, int* rank, int nslices, hipStream_t s, const int* gate = nullptr,
+                             Planes vp = Planes{}, Planes cp = Planes{});
 hipError_t launch_cm_to_planar(const float2* src, Planes dst, int L, int nslices, hipStream_t s,
                                const int* gate = nullptr, const float2* src2 = nullptr, Planes dst2 = Planes{});
 // part: accuracy_part_bytes(nslices) of workspace for the per-band partial sums
