@@ -805,9 +805,9 @@ __global__ __launch_bounds__(MAXT) void k_jacobi_sweep(SweepArgs a)
 }
 
 // ---- Gram block sweep: block pairs through MFMA Gram matrices ----
-// The item order, stamps and flags of k_jacobi_sweep (one launch per sweep),
-// with blocks of b = 8 NT columns, so that an item holds W = 16 NT columns X
-// (R x W).  An item
+// The item order and stamps of k_jacobi_sweep (here three sweeps per launch,
+// with one row of rotation flags per sweep), with blocks of b = 8 NT columns,
+// so that an item holds W = 16 NT columns X (R x W).  An item
 //  1. forms G = X^* X with FP32 MFMA (16x16x4) over groups of 8 rows, two
 //     accumulator sets per wave (one per row of a row pair), the partial sums
 //     added in FP64 in LDS;
@@ -856,6 +856,9 @@ __device__ __forceinline__ bool pair_rotation(double al, double be, double gr, d
     const float az = fabsf(zeta);
     const float tf = az < 1e18f ? copysignf(__builtin_amdgcn_rcpf(az + __builtin_amdgcn_sqrtf(fmaf(az, az, 1.0f))), zeta)
                                 : 0.5f * __builtin_amdgcn_rcpf(zeta);
+    // an angle that underflows (norms some 10^12 apart) is no rotation: the
+    // pair counts as converged rather than as rotated without change
+    if (tf == 0.0f) return false;
     const double t = (double)tf;
     c = rsqrt_f64(fma(t, t, 1.0));
     const double sn = c * t;
