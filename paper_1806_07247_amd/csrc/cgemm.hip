@@ -548,9 +548,12 @@ constexpr int sk_plane()  // one plane of one B buffer: NC = 16 TN staged column
 }
 
 // the workgroup's tile (x = row tile) of slice view v; REAL: real slice
-// (only the real planes enter)
-template <int OPA, int TN, bool REAL, bool FAST>
-__device__ __forceinline__ void sk_tile(const CgemmArgs& p, const SliceView& v, int x, float* lds)
+// (only the real planes enter).  TN: the 16-column blocks staged and
+// multiplied; TW >= TN: the blocks written, those past TN as zeros.  RT:
+// the live blocks are tl <= TN, tested at run time (else TN are live, a
+// compile-time count, so that the MFMA chains carry no branches).
+template <int OPA, int TN, int TW, bool REAL, bool FAST, bool RT>
+__device__ __forceinline__ void sk_tile(const CgemmArgs& p, const SliceView& v, int x, int tl, float* lds)
 {
     constexpr int NC = 16 * TN;                   // B columns staged (n rounded up to the tile)
     constexpr int GB = (kSkBK * NC / 4 + 255) / 256;  // 4-column groups of a B stage per thread
@@ -563,7 +566,6 @@ __device__ __forceinline__ void sk_tile(const CgemmArgs& p, const SliceView& v, 
     const bool vecb = vec_ok(v.br, v.bi, p.ldb);
     const int nst = (v.K - v.K0 + kSkBK - 1) / kSkBK;
     const int nl = n_live(p);             // live columns (a multiple of 4); the rest come out zero
-    const int tl = (nl + 15) / 16;        // live 16-column blocks (uniform)
 
     floatx4 p1[TN], p2[TN], p3[TN];
 #pragma unroll
@@ -616,7 +618,7 @@ __device__ __forceinline__ void sk_tile(const CgemmArgs& p, const SliceView& v, 
             float4 fr[TN], fi[TN];
 #pragma unroll
             for (int t = 0; t < TN; ++t) {
-                if (t >= tl) continue;
+                if (RT && t >= tl) continue;
                 const int off = (16 * h + 4 * g) * LDB + 16 * t + r;
                 fr[t] = make_float4(br[off], br[off + LDB], br[off + 2 * LDB], br[off + 3 * LDB]);
                 fi[t] = make_float4(bi[off], bi[off + LDB], bi[off + 2 * LDB], bi[off + 3 * LDB]);
@@ -628,7 +630,7 @@ __device__ __forceinline__ void sk_tile(const CgemmArgs& p, const SliceView& v, 
                 const float as = OPA == OP_C ? ar - ai : ar + ai;
 #pragma unroll
                 for (int t = 0; t < TN; ++t) {
-                    if (t >= tl) continue;
+                    if (RT && t >= tl) continue;
                     const float b_r = (&fr[t].x)[s], b_i = (&fi[t].x)[s];
                     p1[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(b_r, ar, p1[t], 0, 0, 0);
                     if (!REAL) {
@@ -657,15 +659,20 @@ __device__ __forceinline__ void sk_tile(const CgemmArgs& p, const SliceView& v, 
         __syncthreads();
     };
 
+    // prologue in the loop's issue order (B stage 1 before A stage 1), so
+    // that the loads in flight where the loop starts are those of its
+    // steady state and the first wait of each pass leaves A in flight
     AStage a0, a1, a2;
     if (nst > 0) {
         load_b(v.K0);
         __builtin_amdgcn_sched_barrier(0);
         sk_load_a<OPA, FAST>(a0, v, p, row, v.K0, g, veca);
-        sk_load_a<OPA, FAST>(a1, v, p, row, v.K0 + kSkBK * min(1, nst - 1), g, veca);
         __builtin_amdgcn_sched_barrier(0);
         store_b(0);
         load_b(v.K0 + kSkBK * min(1, nst - 1));
+        __builtin_amdgcn_sched_barrier(0);
+        sk_load_a<OPA, FAST>(a1, v, p, row, v.K0 + kSkBK * min(1, nst - 1), g, veca);
+        __builtin_amdgcn_sched_barrier(0);
     }
     __syncthreads();
     int st = 0;
@@ -683,13 +690,16 @@ __device__ __forceinline__ void sk_tile(const CgemmArgs& p, const SliceView& v, 
                            15) == 0 &&
                           (v.ldc & 3) == 0;
 #pragma unroll
-        for (int t = 0; t < TN; ++t) {
+        for (int t = 0; t < TW; ++t) {
             const int col = 16 * t + 4 * g;
             if (col < p.n) {  // n is a multiple of 4: all four columns in range
                 // 3M: Re = p1 - p2, Im = p3 - p1 - p2 (OP_C: p2 has the opposite sign)
-                const floatx4 q2 = OPA == OP_C ? -p2[t] : p2[t];
-                const floatx4 cre = REAL ? p1[t] : p1[t] - q2;
-                const floatx4 cim = REAL ? floatx4{0.f, 0.f, 0.f, 0.f} : p3[t] - p1[t] - q2;
+                floatx4 cre = floatx4{0.f, 0.f, 0.f, 0.f}, cim = cre;
+                if (t < TN) {
+                    const floatx4 q2 = OPA == OP_C ? -p2[t] : p2[t];
+                    cre = REAL ? p1[t] : p1[t] - q2;
+                    cim = REAL ? floatx4{0.f, 0.f, 0.f, 0.f} : p3[t] - p1[t] - q2;
+                }
                 const long long off = (long long)row * v.ldc + col;
                 if (vecc) {
                     *reinterpret_cast<floatx4*>(v.cr + off) = cre;
@@ -703,6 +713,33 @@ __device__ __forceinline__ void sk_tile(const CgemmArgs& p, const SliceView& v, 
                 }
             }
         }
+    }
+}
+
+// The tile with the live column blocks of the launch (tl <= TNI) as a
+// compile-time count: TNI, or fewer for a device-capped width.  The
+// conjugated-A form keeps one body per width with a run-time count: its
+// element-wise A loads leave no registers for the extra bodies.
+template <int OPA, int TNI, int TW>
+__device__ __forceinline__ void sk_live(const CgemmArgs& p, const SliceView& v, int x, bool fast, int tl, float* lds)
+{
+    constexpr bool RT = OPA == OP_C;
+    if constexpr (TNI > 1 && !RT) {
+        if (tl < TNI) {
+            sk_live<OPA, TNI - 1, TW>(p, v, x, fast, tl, lds);
+            return;
+        }
+    }
+    if (v.real) {
+        if (fast)
+            sk_tile<OPA, TNI, TW, true, true, RT>(p, v, x, tl, lds);
+        else
+            sk_tile<OPA, TNI, TW, true, false, RT>(p, v, x, tl, lds);
+    } else {
+        if (fast)
+            sk_tile<OPA, TNI, TW, false, true, RT>(p, v, x, tl, lds);
+        else
+            sk_tile<OPA, TNI, TW, false, false, RT>(p, v, x, tl, lds);
     }
 }
 
@@ -721,28 +758,16 @@ k_skinny(CgemmArgs p)
     const SliceView v = slice_view(p, z % p.nslices, z / p.nslices);
     const bool fast = (x + 1) * kSkRows <= p.m && (v.K - v.K0) % kSkBK == 0 && vec_ok(v.br, v.bi, p.ldb) &&
                       (OPA == OP_C || vec_ok(v.ar, v.ai, p.lda));
-    // a device-capped width of at most 48 columns takes the 48-column tile
-    // (the same registers and waves; its B stage fits the buffer)
+    const int tl = (n_live(p) + 15) / 16;  // live 16-column blocks (uniform, 1 .. TN)
+    // a device-capped width of at most 48 columns writes the 48 columns of
+    // the three-block tile (the blocks past the live ones as zeros)
     if constexpr (TN == 4) {
-        if (p.dyn_n && (n_live(p) + 15) / 16 <= 3) {
-            if (v.real)
-                fast ? sk_tile<OPA, 3, true, true>(p, v, x, lds) : sk_tile<OPA, 3, true, false>(p, v, x, lds);
-            else
-                fast ? sk_tile<OPA, 3, false, true>(p, v, x, lds) : sk_tile<OPA, 3, false, false>(p, v, x, lds);
+        if (p.dyn_n && tl <= 3) {
+            sk_live<OPA, 3, 3>(p, v, x, fast, tl, lds);
             return;
         }
     }
-    if (v.real) {
-        if (fast)
-            sk_tile<OPA, TN, true, true>(p, v, x, lds);
-        else
-            sk_tile<OPA, TN, true, false>(p, v, x, lds);
-    } else {
-        if (fast)
-            sk_tile<OPA, TN, false, true>(p, v, x, lds);
-        else
-            sk_tile<OPA, TN, false, false>(p, v, x, lds);
-    }
+    sk_live<OPA, TN, TN>(p, v, x, fast, tl, lds);
 }
 
 // -------------------------------------------------------------- wide FP32 --
@@ -760,7 +785,8 @@ k_skinny(CgemmArgs p)
 constexpr int kWideRows = 64, kWideCols = 256, kWideBlk = 64, kWideMaxK = 64;
 constexpr int kWideLDB = kWideBlk + 4;  // 4 x 68 = 16 mod 64 banks: a lane's four fragment reads hit distinct banks
 
-// KC: staged inner rows (k rounded up to 16; zero beyond k)
+// KC: staged inner rows (the live k rounded up to 16, a compile-time count;
+// zero beyond k)
 // NB: 64-column blocks per workgroup (4: the unmasked full tiles; 1: a
 // masked tile for narrow outputs, rows < m and columns < n, n a multiple of 4)
 template <bool REAL, int KC, int NB>
@@ -779,21 +805,16 @@ __device__ __forceinline__ void wide_tile(const CgemmArgs& p, const SliceView& v
     // A: chunk h holds A(row, 16 h + 4 g + s), s = 0..3
     float fa_r[nh * 4], fa_i[nh * 4];
     const bool veca = vec_ok(v.ar, v.ai, p.lda);
-#pragma unroll
-    for (int h = 0; h < nh; ++h) {
-        const int kb = 16 * h + 4 * g;
-        const int valid = MASK && row >= p.m ? 0 : max(0, min(4, K - kb));
-        const Quad q = load4(v.ar, v.ai, (long long)row * p.lda + kb, valid, veca, false);
-        fa_r[4 * h + 0] = q.r.x;
-        fa_r[4 * h + 1] = q.r.y;
-        fa_r[4 * h + 2] = q.r.z;
-        fa_r[4 * h + 3] = q.r.w;
-        fa_i[4 * h + 0] = q.i.x;
-        fa_i[4 * h + 1] = q.i.y;
-        fa_i[4 * h + 2] = q.i.z;
-        fa_i[4 * h + 3] = q.i.w;
-    }
-
+    auto put_a = [&](int h, const float4& qr, const float4& qi) __attribute__((always_inline)) {
+        fa_r[4 * h + 0] = qr.x;
+        fa_r[4 * h + 1] = qr.y;
+        fa_r[4 * h + 2] = qr.z;
+        fa_r[4 * h + 3] = qr.w;
+        fa_i[4 * h + 0] = qi.x;
+        fa_i[4 * h + 1] = qi.y;
+        fa_i[4 * h + 2] = qi.z;
+        fa_i[4 * h + 3] = qi.w;
+    };
     float4 bq_r[GB], bq_i[GB];
     bool bok[GB];  // MASK: the group's columns exist (else stored as zeros)
     // B block j into registers: rows beyond K read row K-1 (kept in range) and are zeroed when stored
@@ -831,9 +852,32 @@ __device__ __forceinline__ void wide_tile(const CgemmArgs& p, const SliceView& v
                        15) == 0 &&
                       (v.ldc & 3) == 0;
 
-    load_b(0);
+    // the one-block tile issues B block 0 first, so that the A loads (and
+    // any wait the A path's selects need) queue behind it rather than ahead
+    // of it (the four-block tile loads A first: B's registers live across
+    // the A loads would spill it)
+    if constexpr (NB == 1) load_b(0);
+    if (veca && K == KC && (!MASK || (y + 1) * kWideRows <= p.m)) {
+        // every chunk whole and every row present: plain 16-byte loads, all
+        // in flight together (the masked form below waits between chunks)
+#pragma unroll
+        for (int h = 0; h < nh; ++h) {
+            const long long off = (long long)row * p.lda + 16 * h + 4 * g;
+            put_a(h, *reinterpret_cast<const float4*>(v.ar + off), *reinterpret_cast<const float4*>(v.ai + off));
+        }
+    } else {
+#pragma unroll
+        for (int h = 0; h < nh; ++h) {
+            const int kb = 16 * h + 4 * g;
+            const int valid = MASK && row >= p.m ? 0 : max(0, min(4, K - kb));
+            const Quad q = load4(v.ar, v.ai, (long long)row * p.lda + kb, valid, veca, false);
+            put_a(h, q.r, q.i);
+        }
+    }
+    if constexpr (NB > 1) load_b(0);
     store_b(0);
     __syncthreads();
+#pragma unroll
     for (int j = 0; j < NB; ++j) {
         const bool more = j + 1 < NB;
         if (more) load_b(j + 1);
@@ -844,26 +888,29 @@ __device__ __forceinline__ void wide_tile(const CgemmArgs& p, const SliceView& v
         const float* bi = br + PL;
 #pragma unroll
         for (int h = 0; h < nh; ++h) {
-            if (16 * h < K) {  // chunks past a device-capped k hold zeros: skipped
 #pragma unroll
-                for (int s = 0; s < 4; ++s) {
-                    const float ar = fa_r[4 * h + s], ai = fa_i[4 * h + s];
-                    const float as = ar + ai;
-                    const int off = (16 * h + 4 * g + s) * kWideLDB + r;
+            for (int s = 0; s < 4; ++s) {
+                const float ar = fa_r[4 * h + s], ai = fa_i[4 * h + s];
+                const float as = ar + ai;
+                const int off = (16 * h + 4 * g + s) * kWideLDB + r;
 #pragma unroll
-                    for (int t = 0; t < 4; ++t) {
-                        const float b_r = br[off + 16 * t], b_i = bi[off + 16 * t];
-                        p1[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(b_r, ar, p1[t], 0, 0, 0);
-                        if (!REAL) {
-                            p2[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(b_i, ai, p2[t], 0, 0, 0);
-                            p3[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(b_r + b_i, as, p3[t], 0, 0, 0);
-                        }
+                for (int t = 0; t < 4; ++t) {
+                    const float b_r = br[off + 16 * t], b_i = bi[off + 16 * t];
+                    p1[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(b_r, ar, p1[t], 0, 0, 0);
+                    if (!REAL) {
+                        p2[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(b_i, ai, p2[t], 0, 0, 0);
+                        p3[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(b_r + b_i, as, p3[t], 0, 0, 0);
                     }
                 }
             }
             // one chunk's fragments live at a time (the scheduler would hoist them all)
             __builtin_amdgcn_sched_barrier(0);
         }
+        // the next B block into the other buffer before this block's stores:
+        // its wait then covers only its own loads (stores count in the same
+        // counter and would be waited for too)
+        if (more) store_b((j + 1) & 1);
+        __builtin_amdgcn_sched_barrier(0);
         // lane (r, g) holds row `row`, columns 16 t + 4 g .. + 3 of the block
 #pragma unroll
         for (int t = 0; t < 4; ++t) {
@@ -883,9 +930,25 @@ __device__ __forceinline__ void wide_tile(const CgemmArgs& p, const SliceView& v
                 }
             }
         }
-        if (more) store_b((j + 1) & 1);
         __syncthreads();
     }
+}
+
+// the tile at the inner depth of the launch's live k (kc <= KC, a multiple
+// of 16), so that no MFMA chain waits behind a branch on a device-capped k
+template <int KC, int NB>
+__device__ __forceinline__ void wide_live(const CgemmArgs& p, const SliceView& v, int x, int y, int kc, float* lds)
+{
+    if constexpr (KC > 16) {
+        if (kc < KC) {
+            wide_live<KC - 16, NB>(p, v, x, y, kc, lds);
+            return;
+        }
+    }
+    if (v.real)
+        wide_tile<true, KC, NB>(p, v, x, y, lds);
+    else
+        wide_tile<false, KC, NB>(p, v, x, y, lds);
 }
 
 // three wavefronts per SIMD for the four-block tile (no spills; measured 7%
@@ -900,10 +963,7 @@ k_wide(CgemmArgs p)
     xcd_tile(x, y, z);  // x = column group (64 NB), y = 64-row tile, z = slice
     if (!slice_live(p, z) || y * kWideRows >= m_live(p) || x * kWideBlk * NB >= n_live(p)) return;
     const SliceView v = slice_view(p, z, 0);
-    if (v.real)
-        wide_tile<true, KC, NB>(p, v, x, y, wlds);
-    else
-        wide_tile<false, KC, NB>(p, v, x, y, wlds);
+    wide_live<KC, NB>(p, v, x, y, (v.K + 15) / 16 * 16, wlds);
 }
 
 // Batched products of uneven shapes: a persistent grid walks a list of
