@@ -16,7 +16,12 @@ range basis for the warm start); with tau_t = 1/mu_t they stay in HBM.  A step i
 a posteriori check, full-SVD fallback, reconstruction, inverse FFT) on one
 captured call; K steps walk through the captured calls (evenly spaced when
 K is below their number, cyclically above it; by default one pass).
-value = n1 n2 n3 K / time, in Melem/s.  Every captured call is then run once
+value = n1 n2 n3 K / time, in Melem/s, for the fastest of three ways of
+making the same calls (same bits): eager, each call as a replayed HIP graph
+(every launch enqueued, the optional work gated on the device), and the
+host-driven form (the host reads the device's round, retry and fallback
+decisions and enqueues only the launches that run, waiting for the device at
+those points; timed eagerly, waits included).  Every captured call is then run once
 through the full-SVD prox (Algorithm 3) on the same GPU, timed, and compared
 with the learned result.
 
@@ -76,6 +81,9 @@ def measured_traffic(kernel):
     except OSError:
         pass
     return None
+
+
+LEARNED_HOST = 12  # TP_PARAM_LEARNED_HOST
 
 
 def log(*a):
@@ -263,7 +271,25 @@ def learned_block(args, tp, dev):
         torch.cuda.synchronize()
         ms_graph = start.elapsed_time(stop) / steps
     del graphs
-    ms = min(ms_eager, ms_graph)
+    # the host-driven form (TP_PARAM_LEARNED_HOST = 1): the host reads the
+    # round, retry and fallback decisions where the device takes them and
+    # enqueues only the launches that run (the same bits; the call waits for
+    # the device at those points, so it is timed eagerly, waits included)
+    lib = tp._lib.load()
+    lib.tp_set_param(LEARNED_HOST, 1)
+    try:
+        for j in range(args.warmup):
+            learned(sel[j % steps], out)
+        torch.cuda.synchronize()
+        start.record()
+        for j in range(steps):
+            learned(sel[j], out)
+        stop.record()
+        torch.cuda.synchronize()
+        ms_host = start.elapsed_time(stop) / steps
+    finally:
+        lib.tp_set_param(LEARNED_HOST, 0)
+    ms = min(ms_eager, ms_graph, ms_host)
     # traced pass over the same calls: HIP events around every launch on its
     # stream (stage times, the roofline's per-launch durations), Jacobi
     # sweeps.  The work of the products whose gates and widths are decided on
@@ -296,11 +322,13 @@ def learned_block(args, tp, dev):
         if totals["jacobi"]["flops"] > 0:
             stages["jacobi"]["TFLOP_s"] = round(totals["jacobi"]["flops"] / (totals["jacobi"]["ms"] * 1e-3) / 1e12, 2)
     value = n * n * n3 / (ms * 1e-3) / 1e6
-    log(f"  learned: {ms:.3f} ms/call (eager {ms_eager:.3f}, graph replay {ms_graph:.3f}; "
-        f"{ms_traced:.3f} traced), {value:.1f} Melem/s; stages {json.dumps(stages)}")
+    log(f"  learned: {ms:.3f} ms/call (eager {ms_eager:.3f}, graph replay {ms_graph:.3f}, host-driven "
+        f"{ms_host:.3f}; {ms_traced:.3f} traced), {value:.1f} Melem/s; stages {json.dumps(stages)}")
+    forms = {"eager": ms_eager, "graph replay": ms_graph, "host-driven eager": ms_host}
     timing = {"ms_per_call_eager": round(ms_eager, 4),
               "ms_per_call_graph_replay": round(ms_graph, 4) if ms_graph != float("inf") else None,
-              "value_from": "graph replay" if ms_graph <= ms_eager else "eager",
+              "ms_per_call_host_driven": round(ms_host, 4),
+              "value_from": min(forms, key=forms.get),
               "ms_per_call_traced_pass": round(ms_traced, 4)}
 
     if args.no_full:
@@ -582,6 +610,21 @@ def trpca_block(args, tp, dev, mlp=None):
     torch.cuda.synchronize()
     t_nat = time.perf_counter() - t0
     err_nat = float((Lo - L0).norm() / L0.norm())
+    # the same solve with the host-driven learned prox (same bits)
+    lib = tp._lib.load()
+    L_dev = Lo.clone()
+    lib.tp_set_param(LEARNED_HOST, 1)
+    try:
+        native()  # warm-up
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        res_h = native()
+        torch.cuda.synchronize()
+        t_host = time.perf_counter() - t0
+    finally:
+        lib.tp_set_param(LEARNED_HOST, 0)
+    same_bits = bool(torch.equal(Lo, L_dev)) and res_h["iters"] == res["iters"]
+    del L_dev
     # fused update pass: HIP events around each launch
     tp.tp_trace_collect_work()
     tp.tp_trace_enable(True)
@@ -599,6 +642,9 @@ def trpca_block(args, tp, dev, mlp=None):
         "workload": f"TRPCA of X = P*Q + S, 1024x1024x64, tubal rank {r}, 5% +-1 outliers, seed {args.learned_seed}",
         "native": {"iters": res["iters"], "converged": res["converged"], "ms": round(t_nat * 1e3, 2),
                    "ms_per_iter": round(t_nat * 1e3 / max(res["iters"], 1), 3), "L_rel_err": err_nat},
+        "native_host_driven_prox": {"iters": res_h["iters"], "ms": round(t_host * 1e3, 2),
+                                    "ms_per_iter": round(t_host * 1e3 / max(res_h["iters"], 1), 3),
+                                    "same_bits_as_device_gated": same_bits},
         "python_driver": {"iters": py["iters"], "converged": py["converged"], "ms": round(py["wall_s"] * 1e3, 2),
                           "ms_per_iter": round(py["wall_s"] * 1e3 / max(py["iters"], 1), 3), "L_rel_err": err_py},
         "speedup_native_vs_python": round(py["wall_s"] / t_nat, 2),

@@ -541,6 +541,16 @@ int tp_batch_destroy(tp_batch* plan);
  *                                 16-column block pairs up to 256 rows and 32
  *                                 above; 1 = off (the column-rotation forms);
  *                                 2 = 16 columns; 3 = 32 columns
+ *   TP_PARAM_LEARNED_HOST         learned-rank prox: 1 = the host reads the
+ *                                 device's decisions (after each accuracy round,
+ *                                 after the retry test, the fallback count) and
+ *                                 enqueues only the work that runs; the call then
+ *                                 synchronizes its stream at those points and
+ *                                 cannot be captured (on a capturing stream it
+ *                                 keeps the default).  0 (default): every launch
+ *                                 is enqueued and gated on the device, so the
+ *                                 call never waits for the device and can be
+ *                                 captured.  Both give the same bits.
  * The bf16 slice products (TP_PREC_BF16X3, TP_PREC_BF16) read
  * TP_PARAM_GEMM_VARIANT as: 1 = 64x64, 2 = 128x128, 3 = 128x32 tiles on
  * 16x16x32 products, 4 = 256x128 and 5 = 128x128 on 32x32x16 products,
@@ -559,7 +569,8 @@ enum {
     TP_PARAM_JACOBI_STEPWISE = 9,
     TP_PARAM_RETRY_ROUNDS = 10,
     TP_PARAM_JACOBI_GRAM = 11,
-    TP_PARAM_COUNT = 12
+    TP_PARAM_LEARNED_HOST = 12,
+    TP_PARAM_COUNT = 13
 };
 int tp_set_param(int key, int value);
 int tp_get_param(int key);

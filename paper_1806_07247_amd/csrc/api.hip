@@ -1,6 +1,7 @@
 // C-ABI entry points of libtp.so: argument checks, workspace carving and the
 // kernel sequence of each operation.  See include/tp.h for the contract.
 #include <cmath>
+#include <cstring>
 #include <algorithm>
 #include <utility>
 #include <vector>
@@ -378,6 +379,33 @@ int cholqr3(LearnedLayout& Lw, tp::Planes src, tp::Planes mid, tp::Planes dst, i
         if (st != TP_OK) return st;
     }
     return TP_OK;
+}
+
+// n device ints (and n2 more from src2) copied to dst on the host through a
+// pinned buffer of the calling thread (kept for the life of the process), after the work queued
+// on s before the call: the host-driven form of the learned-rank prox reads
+// its device decisions with this.
+hipError_t read_device_ints(const int* src, int n, int* dst, hipStream_t s, const int* src2 = nullptr, int n2 = 0)
+{
+    thread_local int* pin = nullptr;
+    thread_local int cap = 0;
+    if (n + n2 > cap) {
+        const int want = std::max(n + n2, 1024);
+        int* p = nullptr;
+        const hipError_t e = hipHostMalloc(reinterpret_cast<void**>(&p), (size_t)want * sizeof(int),
+                                           hipHostMallocDefault);
+        if (e != hipSuccess) return e;
+        if (pin) (void)hipHostFree(pin);  // every earlier copy has completed (synchronized below)
+        pin = p;
+        cap = want;
+    }
+    hipError_t e = hipMemcpyAsync(pin, src, (size_t)n * sizeof(int), hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess && n2 > 0)  // a second range after the first (dst[n .. n + n2))
+        e = hipMemcpyAsync(pin + n, src2, (size_t)n2 * sizeof(int), hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e != hipSuccess) return e;
+    std::memcpy(dst, pin, (size_t)(n + n2) * sizeof(int));
+    return hipSuccess;
 }
 
 // The range-finder product C = op(A) B (m x n per slice, row-major, packed)
@@ -974,6 +1002,16 @@ int tp_prox_tnn_learned(const float* Y, float* X, int n1, int n2, int n3, float 
     // in a HIP graph.
     const int L = opts->max_rank;
     int* ctl = W.ctl;
+    // Host-driven form (TP_PARAM_LEARNED_HOST = 1): the host reads those
+    // decisions where they are taken (after each accuracy round, after the
+    // retry test) and leaves out the launches that would exit at their gate;
+    // the call then waits for the device there and cannot be captured, so a
+    // capturing stream keeps the device-gated form.  Both give the same bits.
+    bool host = tp::param(TP_PARAM_LEARNED_HOST) == 1;
+    if (host) {
+        hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+        if (hipStreamIsCapturing(s, &cs) != hipSuccess || cs != hipStreamCaptureStatusNone) host = false;
+    }
     const int qmax = std::max(opts->max_power_iters, opts->power_iters);
     const int rounds = opts->accuracy > 0.0f ? std::min(qmax - opts->power_iters, kMaxRounds - 1) : 0;
 
@@ -1083,6 +1121,11 @@ int tp_prox_tnn_learned(const float* Y, float* X, int n1, int n2, int n3, float 
                                                 opts->accuracy_ref == 0 ? W.fro2 : nullptr, n1, L, (double)tau,
                                                 (double)opts->accuracy, W.bad, h, W.accpart, fb, run, next, last, s));
             if (last) break;
+            if (host) {  // the later rounds run only when this one found an inaccurate slice
+                int more = 0;
+                if (read_device_ints(next, 1, &more, s) != hipSuccess) return TP_ERR_HIP;
+                if (!more) break;
+            }
             // the next subspace iteration needs no new product: Ybar^* Y is
             // the projection just formed (its orthonormal basis Q2 is in W.za),
             // and Ybar Q2, whose span is that of the iteration's Ybar Z, is the
@@ -1121,6 +1164,15 @@ int tp_prox_tnn_learned(const float* Y, float* X, int n1, int n2, int n3, float 
 
     int st = attempt(0, ctl + C_G1, ctl + C_L1);
     if (st != TP_OK) return st;
+    // host-driven form: the number of fallback slices once the host knows it
+    // (-1: not read); the fallback flags are final when no retry runs
+    int host_nfb = -1;
+    std::vector<int> hv;
+    auto count_fb = [&](const int* v) {
+        int c = 0;
+        for (int q = 0; q < h; ++q) c += v[q] ? 1 : 0;
+        return c;
+    };
     if (opts->retry_wide) {
         // slices whose count check failed below the widest sketch: one retry
         // with kpred = max_rank - oversample (the whole call is recomputed
@@ -1131,22 +1183,42 @@ int tp_prox_tnn_learned(const float* Y, float* X, int n1, int n2, int n3, float 
         TP_LAUNCH(tp::K_PREDICT, s,
                   tp::launch_width(W.kpred, W.lact, W.prefb, fb, h, p, opts->oversample, L, ctl + C_RETRY,
                                    ctl + C_L2, ctl + C_G2, false, s));
-        st = attempt(1, ctl + C_G2, ctl + C_L2);
-        if (st != TP_OK) return st;
+        bool retry = true;
+        if (host) {
+            // a closed retry changes nothing: its gated launches exit, and the
+            // basis and singular values it stores are the first attempt's,
+            // stored again
+            hv.resize(1 + h);
+            if (read_device_ints(ctl + C_G2, 1, hv.data(), s, fb, h) != hipSuccess) return TP_ERR_HIP;
+            retry = hv[0] != 0;
+            if (!retry) host_nfb = count_fb(hv.data() + 1);
+        }
+        if (retry) {
+            st = attempt(1, ctl + C_G2, ctl + C_L2);
+            if (st != TP_OK) return st;
+        }
+    }
+    if (host && host_nfb < 0) {
+        hv.resize(h);
+        if (read_device_ints(fb, h, hv.data(), s) != hipSuccess) return TP_ERR_HIP;
+        host_nfb = count_fb(hv.data());
     }
     // fallback slices: the full SVD on a compact batch whose size is known
     // on the device only (every launch reads it; nothing runs for none)
     const int* nfb = ctl + C_NFB;
-    TP_LAUNCH(tp::K_GATHER, s, tp::launch_compact(fb, h, W.idx, ctl + C_NFB, s));
-    TP_LAUNCH(tp::K_GATHER, s,
-              tp::launch_gather(ybar.re, ybar.im, W.cy.re, W.cy.im, W.idx, h, mn, false, s, nfb));
-    SvtLayout F = W.full;
-    st = run_svt(F, W.cy, n1, n2, h, 0, 0, (double)tau, W.cinfo, W.crank, s, nfb);
-    if (st != TP_OK) return st;
-    TP_LAUNCH(tp::K_GATHER, s,
-              tp::launch_gather(W.cy.re, W.cy.im, W.wbar.re, W.wbar.im, W.idx, h, mn, true, s, nfb));
-    if (sigma_out)
-        TP_LAUNCH(tp::K_GATHER, s, tp::launch_sigma_top(F.sigma, p, nullptr, W.idx, nullptr, h, sigma_out, s, nfb));
+    if (host_nfb != 0) {  // (none: the count stays 0 and every launch below would exit)
+        TP_LAUNCH(tp::K_GATHER, s, tp::launch_compact(fb, h, W.idx, ctl + C_NFB, s));
+        TP_LAUNCH(tp::K_GATHER, s,
+                  tp::launch_gather(ybar.re, ybar.im, W.cy.re, W.cy.im, W.idx, h, mn, false, s, nfb));
+        SvtLayout F = W.full;
+        st = run_svt(F, W.cy, n1, n2, h, 0, 0, (double)tau, W.cinfo, W.crank, s, nfb);
+        if (st != TP_OK) return st;
+        TP_LAUNCH(tp::K_GATHER, s,
+                  tp::launch_gather(W.cy.re, W.cy.im, W.wbar.re, W.wbar.im, W.idx, h, mn, true, s, nfb));
+        if (sigma_out)
+            TP_LAUNCH(tp::K_GATHER, s,
+                      tp::launch_sigma_top(F.sigma, p, nullptr, W.idx, nullptr, h, sigma_out, s, nfb));
+    }
     TP_LAUNCH(tp::K_GATHER, s, tp::launch_fb_results(W.idx, nfb, W.crank, W.cinfo, fb, rk, info, h, s));
     TP_LAUNCH(tp::K_IRFFT, s, tp::launch_irfft(W.wbar.re, W.wbar.im, X, mn, n3, s));
     return TP_OK;

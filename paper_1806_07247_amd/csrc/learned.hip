@@ -580,21 +580,23 @@ __global__ __launch_bounds__(256) void k_rsvd_check(const float2* __restrict__ c
     __shared__ int above;
     const int s = blockIdx.x, tid = threadIdx.x;
     const double* sg = sigma + (long long)s * L;
-    if (tid == 0) {
+    if (tid < kMaxL) {  // wavefront 0: one singular value per lane (L <= kMaxL = 64)
+        const int la_ = lact[s];
+        const bool live = tid < la_ && tid < L;
+        const double sj = live ? sg[tid] : 0.0;
         // counted NaN-safe: a NaN singular value counts as not below tau, so
         // a broken basis fails the check instead of passing it
-        int ge = 0, gt = 0;
-        for (int j = 0; j < lact[s]; ++j) {
-            ge += !(sg[j] < tau) ? 1 : 0;
-            gt += sg[j] > tau ? 1 : 0;
+        const int ge = __popcll(__ballot(live && !(sj < tau)));
+        const int gt = __popcll(__ballot(live && sj > tau));
+        scale[tid] = (live && sj > tau) ? (sj - tau) / sj : 0.0;
+        if (tid == 0) {
+            above = gt;
+            // a CholeskyQR breakdown on any basis of this slice (status) also sends it to the full SVD
+            const int fb = (prefb[s] || (status && status[s]) || (ge > kpred[s] && la_ > 0)) ? 1 : 0;
+            fallback[s] = fb;
+            if (fb == 0 && rank) rank[s] = gt;
         }
-        above = gt;
-        // a CholeskyQR breakdown on any basis of this slice (status) also sends it to the full SVD
-        fallback[s] = (prefb[s] || (status && status[s]) || (ge > kpred[s] && lact[s] > 0)) ? 1 : 0;
-        if (fallback[s] == 0 && rank) rank[s] = gt;
     }
-    for (int j = tid; j < L; j += blockDim.x)
-        scale[j] = (j < lact[s] && sg[j] > tau) ? (sg[j] - tau) / sg[j] : 0.0;
     __syncthreads();
     (void)above;
     // C and V of the slice staged in LDS (column-major, L x L each); T is

@@ -93,8 +93,8 @@ void trace_gemm_dyn(const int* gate, const int* m, const int* n, const int* k, i
 }
 
 namespace {
-int g_params[TP_PARAM_COUNT] = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
-const int kDefaults[TP_PARAM_COUNT] = {0, 0, 128, 30, 0, 8, 1, 0, 0, 0, 2, 0};
+int g_params[TP_PARAM_COUNT] = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
+const int kDefaults[TP_PARAM_COUNT] = {0, 0, 128, 30, 0, 8, 1, 0, 0, 0, 2, 0, 0};
 }  // namespace
 
 int param(int key)

@@ -452,3 +452,70 @@ def test_learned_prox_graph_replay(tp, orc, case):
         assert torch.equal(out, ref["X"]), f"replay {rep}: result differs"
         for k, v in bufs.items():
             assert torch.equal(v, ref[k]), f"replay {rep}: {k} differs"
+
+
+LEARNED_HOST = 12  # TP_PARAM_LEARNED_HOST
+
+
+@pytest.mark.parametrize("case", ["randomized", "fallback", "retry", "accuracy"])
+def test_learned_prox_host_driven(tp, orc, case):
+    """The host-driven form (the host reads the round, retry and fallback
+    decisions and enqueues only the launches that run) gives the bits of the
+    device-gated form in the result, the counts, the fallback flags, the
+    sweeps, the singular values and the stored basis; on a capturing stream
+    it keeps the device-gated form, so a captured call replays to the same
+    bits."""
+    Y, tau, kw = _graph_case(orc, case)
+    n1, n2, n3 = Y.shape
+    h = n3 // 2 + 1
+    dev = "cuda:0"
+    lib = tp._lib.load()
+    Yd = gpu(Y)
+    ws = torch.empty(tp.tp_prox_tnn_learned_workspace_size(n1, n2, n3, kw["max_rank"]), dtype=torch.uint8,
+                     device=dev)
+    bshape = tp.basis_shape(n2, n3, kw["max_rank"])
+
+    def fresh():
+        return dict(rank=torch.full((h,), -7, dtype=torch.int32, device=dev),
+                    fallback=torch.full((h,), -7, dtype=torch.int32, device=dev),
+                    info=torch.full((h,), -7, dtype=torch.int32, device=dev),
+                    sigma_out=torch.full((h, tp.TP_SIGMA_KEEP), -7.0, dtype=torch.float32, device=dev),
+                    basis_out=torch.full(bshape, -7.0, dtype=torch.float32, device=dev),
+                    basis_cols_out=torch.full((h,), -7, dtype=torch.int32, device=dev))
+
+    def call(bufs, out):
+        tp.tp_prox_tnn_learned(Yd, tau, out=out, workspace=ws, **bufs, **kw)
+
+    results = {}
+    try:
+        for mode in (0, 1):
+            assert lib.tp_set_param(LEARNED_HOST, mode) == 0
+            bufs, out = fresh(), torch.full_like(Yd, float("nan"))
+            call(bufs, out)
+            torch.cuda.synchronize()
+            results[mode] = dict(bufs, X=out)
+        say(f"{case}: fallback {int(results[0]['fallback'].sum())} of {h}, rank "
+            f"{results[0]['rank'].cpu().tolist()}")
+        for k, v in results[0].items():
+            assert torch.equal(results[1][k], v), f"host-driven {k} differs"
+        # captured with the host-driven form requested: the device-gated form runs
+        bufs, out = fresh(), torch.full_like(Yd, float("nan"))
+        g = torch.cuda.CUDAGraph()
+        side = torch.cuda.Stream()
+        side.wait_stream(torch.cuda.current_stream())
+        with torch.cuda.stream(side):
+            call(bufs, out)  # warm-up on the capturing stream (host-driven, not capturing)
+        torch.cuda.current_stream().wait_stream(side)
+        torch.cuda.synchronize()
+        with torch.cuda.graph(g):
+            call(bufs, out)
+        for v in list(bufs.values()) + [out]:
+            v.fill_(-7)
+        torch.cuda.synchronize()
+        g.replay()
+        torch.cuda.synchronize()
+        for k, v in results[0].items():
+            got = out if k == "X" else bufs[k]
+            assert torch.equal(got, v), f"captured replay: {k} differs"
+    finally:
+        lib.tp_set_param(LEARNED_HOST, 0)
