@@ -242,18 +242,22 @@ __device__ __forceinline__ void reduce_gram_body(const float* __restrict__ parts
 #pragma unroll
         for (int v = 0; v < B; ++v) gr[u][v] = gi[u][v] = 0.0;
     for (int c0 = r0; c0 < r1; c0 += kGramChunk) {
-        // all loads of the thread in flight at once
+        // all loads of the thread in flight at once: unconditional loads of
+        // in-range addresses (an element past the chunk reads the chunk's
+        // first, a part past ksplit the last part), the unused values
+        // dropped where they are summed (a load under a condition would make
+        // the merge wait for it before the next one is issued)
         const int nr = min(kGramChunk, r1 - c0), nf = nr * ny;
         float pr[kGramLoads][kMaxParts], pim[kGramLoads][kMaxParts];
 #pragma unroll
         for (int q = 0; q < kGramLoads; ++q) {
             const int f = tid + 256 * q;
-            const long long o = (long long)(c0 + f / ny) * L + f % ny;
+            const long long o = f < nf ? (long long)(c0 + f / ny) * L + f % ny : (long long)c0 * L;
 #pragma unroll
             for (int kp = 0; kp < kMaxParts; ++kp) {
-                const bool ok = f < nf && kp < ksplit;
-                pr[q][kp] = ok ? P[kp * total + o] : 0.0f;
-                pim[q][kp] = ok ? P[plane + kp * total + o] : 0.0f;
+                const long long kc = min(kp, ksplit - 1);
+                pr[q][kp] = P[kc * total + o];
+                pim[q][kp] = P[plane + kc * total + o];
             }
         }
         __syncthreads();  // the previous chunk is read
@@ -751,15 +755,26 @@ __global__ __launch_bounds__(256) void k_features_part(const float* __restrict__
     const float* Yi = yi + (long long)s * m * n;
     double* out = part + ((long long)s * nsplit + c) * n;
     if ((n & 3) == 0) {  // 16-byte loads of 4 neighbouring columns
+        constexpr int U = 8;  // rows in flight per thread (loaded before any is summed)
         for (int j = 4 * tid; j < n; j += 4 * blockDim.x) {
             double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
-            for (int i = i0; i < i1; ++i) {
-                const float4 r = *reinterpret_cast<const float4*>(Yr + (long long)i * n + j);
-                const float4 q = *reinterpret_cast<const float4*>(Yi + (long long)i * n + j);
-                a0 += (double)r.x * r.x + (double)q.x * q.x;
-                a1 += (double)r.y * r.y + (double)q.y * q.y;
-                a2 += (double)r.z * r.z + (double)q.z * q.z;
-                a3 += (double)r.w * r.w + (double)q.w * q.w;
+            for (int i = i0; i < i1; i += U) {
+                float4 r[U], q[U];
+#pragma unroll
+                for (int u = 0; u < U; ++u) {  // rows past the band re-read its last row (not summed)
+                    const long long o = (long long)min(i + u, i1 - 1) * n + j;
+                    r[u] = *reinterpret_cast<const float4*>(Yr + o);
+                    q[u] = *reinterpret_cast<const float4*>(Yi + o);
+                }
+#pragma unroll
+                for (int u = 0; u < U; ++u) {  // rows in order, as one row at a time
+                    if (i + u < i1) {
+                        a0 += (double)r[u].x * r[u].x + (double)q[u].x * q[u].x;
+                        a1 += (double)r[u].y * r[u].y + (double)q[u].y * q[u].y;
+                        a2 += (double)r[u].z * r[u].z + (double)q[u].z * q[u].z;
+                        a3 += (double)r[u].w * r[u].w + (double)q[u].w * q[u].w;
+                    }
+                }
             }
             out[j] = a0;
             out[j + 1] = a1;
