@@ -344,9 +344,11 @@ int cholqr(LearnedLayout& Lw, tp::Planes& y, tp::Planes& tmp, int rows, int L, i
 {
     if (want_r && passes != 2) return TP_ERR_ARG;
     tp::Planes src = y, dst = tmp;
+    // (columns past the live width: no later product, Gram or store reads them)
     Dyn d;
     d.gate = gate;
     d.k = width;
+    d.n = width;
     for (int pass = 0; pass < passes; ++pass) {
         TP_LAUNCH(tp::K_CHOLQR, s,
                   tp::launch_cholqr_pass(src.re, src.im, rows, L, Lw.lact, h, pass, Lw.part, Lw.rinv.re, Lw.rinv.im,
@@ -369,6 +371,7 @@ int cholqr3(LearnedLayout& Lw, tp::Planes src, tp::Planes mid, tp::Planes dst, i
     Dyn d;
     d.gate = gate;
     d.k = width;
+    d.n = width;
     const tp::Planes io[3] = {src, mid, dst};
     for (int pass = 0; pass < 2; ++pass) {
         TP_LAUNCH(tp::K_CHOLQR, s,

@@ -789,10 +789,13 @@ constexpr int kWideLDB = kWideBlk + 4;  // 4 x 68 = 16 mod 64 banks: a lane's fo
 // zero beyond k)
 // NB: 64-column blocks per workgroup (4: the unmasked full tiles; 1: a
 // masked tile for narrow outputs, rows < m and columns < n, n a multiple of 4)
-template <bool REAL, int KC, int NB>
+// TW: the 16-column groups of a block that are computed and stored (4, or
+// fewer in the masked tile for a device-capped n; the rest are left alone)
+template <bool REAL, int KC, int NB, int TW = 4>
 __device__ __forceinline__ void wide_tile(const CgemmArgs& p, const SliceView& v, int x, int y, float* lds)
 {
     constexpr bool MASK = NB == 1;
+    static_assert(TW >= 1 && TW <= 4 && (MASK || TW == 4), "column groups");
     constexpr int GB = KC * (kWideBlk / 4) / 256;  // 4-column groups of a B block per thread
     constexpr int nh = KC / 16;
     constexpr int PL = KC * kWideLDB;
@@ -894,7 +897,7 @@ __device__ __forceinline__ void wide_tile(const CgemmArgs& p, const SliceView& v
                 const float as = ar + ai;
                 const int off = (16 * h + 4 * g + s) * kWideLDB + r;
 #pragma unroll
-                for (int t = 0; t < 4; ++t) {
+                for (int t = 0; t < TW; ++t) {
                     const float b_r = br[off + 16 * t], b_i = bi[off + 16 * t];
                     p1[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(b_r, ar, p1[t], 0, 0, 0);
                     if (!REAL) {
@@ -913,7 +916,7 @@ __device__ __forceinline__ void wide_tile(const CgemmArgs& p, const SliceView& v
         __builtin_amdgcn_sched_barrier(0);
         // lane (r, g) holds row `row`, columns 16 t + 4 g .. + 3 of the block
 #pragma unroll
-        for (int t = 0; t < 4; ++t) {
+        for (int t = 0; t < TW; ++t) {
             const floatx4 cre = REAL ? p1[t] : p1[t] - p2[t];
             const floatx4 cim = REAL ? floatx4{0.f, 0.f, 0.f, 0.f} : p3[t] - p1[t] - p2[t];
             const int col = n0 + kWideBlk * j + 16 * t + 4 * g;
@@ -945,10 +948,23 @@ __device__ __forceinline__ void wide_live(const CgemmArgs& p, const SliceView& v
             return;
         }
     }
-    if (v.real)
-        wide_tile<true, KC, NB>(p, v, x, y, lds);
-    else
-        wide_tile<false, KC, NB>(p, v, x, y, lds);
+    if constexpr (NB == 1) {
+        // the 16-column groups of the device-capped n (the one block of the masked tile)
+        const int tw = (n_live(p) + 15) / 16;
+        if (tw <= 1)
+            v.real ? wide_tile<true, KC, NB, 1>(p, v, x, y, lds) : wide_tile<false, KC, NB, 1>(p, v, x, y, lds);
+        else if (tw == 2)
+            v.real ? wide_tile<true, KC, NB, 2>(p, v, x, y, lds) : wide_tile<false, KC, NB, 2>(p, v, x, y, lds);
+        else if (tw == 3)
+            v.real ? wide_tile<true, KC, NB, 3>(p, v, x, y, lds) : wide_tile<false, KC, NB, 3>(p, v, x, y, lds);
+        else
+            v.real ? wide_tile<true, KC, NB, 4>(p, v, x, y, lds) : wide_tile<false, KC, NB, 4>(p, v, x, y, lds);
+    } else {
+        if (v.real)
+            wide_tile<true, KC, NB>(p, v, x, y, lds);
+        else
+            wide_tile<false, KC, NB>(p, v, x, y, lds);
+    }
 }
 
 // three wavefronts per SIMD for the four-block tile (no spills; measured 7%

@@ -607,9 +607,26 @@ __global__ __launch_bounds__(256) void k_rsvd_check(const float2* __restrict__ c
     // formed on the live la x la block and zero elsewhere
     const int la = min(lact[s], L);
     __shared__ float2 sC[kMaxL * kMaxL], sV[kMaxL * kMaxL];
-    for (int e = tid; e < L * la; e += blockDim.x) {
-        sC[e] = cols[(long long)s * L * L + e];
-        sV[e] = vr[(long long)s * L * L + e];
+    // (every load of a thread issued before any is stored: unconditional
+    // loads of in-range elements, the extra ones not stored)
+    constexpr int kPer = kMaxL * kMaxL / 256;  // elements per thread (blockDim 256)
+    {
+        float2 c[kPer], v[kPer];
+#pragma unroll
+        for (int u = 0; u < kPer; ++u) {
+            const int e = tid + 256 * u;
+            const long long o = (long long)s * L * L + (e < L * la ? e : 0);
+            c[u] = cols[o];
+            v[u] = vr[o];
+        }
+#pragma unroll
+        for (int u = 0; u < kPer; ++u) {
+            const int e = tid + 256 * u;
+            if (e < L * la) {
+                sC[e] = c[u];
+                sV[e] = v[u];
+            }
+        }
     }
     __syncthreads();
     for (int e = tid; e < L * L; e += blockDim.x) {
@@ -625,16 +642,27 @@ __global__ __launch_bounds__(256) void k_rsvd_check(const float2* __restrict__ c
         tr[(long long)s * L * L + e] = (float)vr_;
         ti[(long long)s * L * L + e] = (float)vi_;
     }
-    if (vpr)  // column-major to planar row-major, as k_cm_to_planar
-        for (int e = tid; e < L * L; e += blockDim.x) {
-            const int i = e / L, j = e % L;
-            const long long o = (long long)s * L * L + (long long)j * L + i, d = (long long)s * L * L + e;
-            const float2 v = vr[o], c = cols[o];
-            vpr[d] = v.x;
-            vpi[d] = v.y;
-            cpr[d] = c.x;
-            cpi[d] = c.y;
+    if (vpr) {  // column-major to planar row-major, as k_cm_to_planar (loads first, as above)
+        float2 c[kPer], v[kPer];
+#pragma unroll
+        for (int u = 0; u < kPer; ++u) {
+            const int e = tid + 256 * u, ec = e < L * L ? e : 0;
+            const long long o = (long long)s * L * L + (long long)(ec % L) * L + ec / L;
+            v[u] = vr[o];
+            c[u] = cols[o];
         }
+#pragma unroll
+        for (int u = 0; u < kPer; ++u) {
+            const int e = tid + 256 * u;
+            if (e < L * L) {
+                const long long d = (long long)s * L * L + e;
+                vpr[d] = v[u].x;
+                vpi[d] = v[u].y;
+                cpr[d] = c[u].x;
+                cpi[d] = c[u].y;
+            }
+        }
+    }
 }
 
 // ---------------------------------------------------- a posteriori check --
