@@ -1054,8 +1054,8 @@ int tp_prox_tnn_learned(const float* Y, float* X, int n1, int n2, int n3, float 
         st = gemm_gram(W, ybar, n2, mn, tp::OP_N, W.om, L, sz, W.ya, n1, L, n2, h, rl, s, &gr, gate, width);
         // a basis that only feeds the next power-iteration product takes one
         // (shifted, FP64 Gram) CholeskyQR pass: it needs to be well
-        // conditioned, not orthonormal to working precision; every Y that
-        // the projection Ybar^* Q may use takes CholeskyQR2
+        // conditioned, not orthonormal to working precision; the Y that the
+        // projection Ybar^* Q uses (the last one) takes CholeskyQR2
         if (st == TP_OK)
             st = cholqr(W, W.ya, W.yb, n1, L, h, rl, opts->power_iters > 0 ? 1 : 2, false, s, gr, gate, width);
         for (int it = 0; st == TP_OK && it < opts->power_iters; ++it) {
@@ -1064,7 +1064,9 @@ int tp_prox_tnn_learned(const float* Y, float* X, int n1, int n2, int n3, float 
             if (st == TP_OK) st = cholqr(W, W.za, W.zb, n2, L, h, rl, 1, false, s, g1, gate, width);
             if (st == TP_OK)
                 st = gemm_gram(W, ybar, n2, mn, tp::OP_N, W.za, L, sz, W.ya, n1, L, n2, h, rl, s, &g2, gate, width);
-            if (st == TP_OK) st = cholqr(W, W.ya, W.yb, n1, L, h, rl, 2, false, s, g2, gate, width);
+            if (st == TP_OK)
+                st = cholqr(W, W.ya, W.yb, n1, L, h, rl, it + 1 == opts->power_iters ? 2 : 1, false, s, g2, gate,
+                            width);
         }
         if (st != TP_OK) return st;
         Dyn dk;  // products over the sketch columns
