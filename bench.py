@@ -391,7 +391,8 @@ def learned_block(args, tp, dev):
     }
     # roofline: the learned path's dominant kernel class among those whose
     # work the library accounts (the slice products and the transforms)
-    dom = max(totals, key=lambda k: totals[k]["ms"])
+    accounted = [k for k in totals if totals[k]["bytes"] > 0 or totals[k]["flops"] > 0]
+    dom = max(accounted or list(totals), key=lambda k: totals[k]["ms"])
     d = totals[dom]
     if dom == "jacobi" and d["flops"] > 0:
         ach = d["flops"] / (d["ms"] * 1e-3) / 1e12
