@@ -2,6 +2,7 @@
 // kernel sequence of each operation.  See include/tp.h for the contract.
 #include <cmath>
 #include <cstring>
+#include <initializer_list>
 #include <algorithm>
 #include <utility>
 #include <vector>
@@ -384,16 +385,22 @@ int cholqr3(LearnedLayout& Lw, tp::Planes src, tp::Planes mid, tp::Planes dst, i
     return TP_OK;
 }
 
-// n device ints (and n2 more from src2) copied to dst on the host through a
+// device int ranges copied, one after the other, to dst on the host through a
 // pinned buffer of the calling thread (kept for the life of the process), after the work queued
 // on s before the call: the host-driven form of the learned-rank prox reads
 // its device decisions with this.
-hipError_t read_device_ints(const int* src, int n, int* dst, hipStream_t s, const int* src2 = nullptr, int n2 = 0)
+struct IntRange {
+    const int* src;
+    int n;
+};
+hipError_t read_device_ints(std::initializer_list<IntRange> ranges, int* dst, hipStream_t s)
 {
     thread_local int* pin = nullptr;
     thread_local int cap = 0;
-    if (n + n2 > cap) {
-        const int want = std::max(n + n2, 1024);
+    int total = 0;
+    for (const IntRange& r : ranges) total += r.n;
+    if (total > cap) {
+        const int want = std::max(total, 1024);
         int* p = nullptr;
         const hipError_t e = hipHostMalloc(reinterpret_cast<void**>(&p), (size_t)want * sizeof(int),
                                            hipHostMallocDefault);
@@ -402,12 +409,16 @@ hipError_t read_device_ints(const int* src, int n, int* dst, hipStream_t s, cons
         pin = p;
         cap = want;
     }
-    hipError_t e = hipMemcpyAsync(pin, src, (size_t)n * sizeof(int), hipMemcpyDeviceToHost, s);
-    if (e == hipSuccess && n2 > 0)  // a second range after the first (dst[n .. n + n2))
-        e = hipMemcpyAsync(pin + n, src2, (size_t)n2 * sizeof(int), hipMemcpyDeviceToHost, s);
+    hipError_t e = hipSuccess;
+    int at = 0;
+    for (const IntRange& r : ranges) {  // one after the other in dst
+        if (e == hipSuccess && r.n > 0)
+            e = hipMemcpyAsync(pin + at, r.src, (size_t)r.n * sizeof(int), hipMemcpyDeviceToHost, s);
+        at += r.n;
+    }
     if (e == hipSuccess) e = hipStreamSynchronize(s);
     if (e != hipSuccess) return e;
-    std::memcpy(dst, pin, (size_t)(n + n2) * sizeof(int));
+    std::memcpy(dst, pin, (size_t)total * sizeof(int));
     return hipSuccess;
 }
 
@@ -1041,6 +1052,22 @@ int tp_prox_tnn_learned(const float* Y, float* X, int n1, int n2, int n3, float 
     }
     const long long sy = (long long)n1 * L, sz = (long long)n2 * L, sl = (long long)L * L;
 
+    // Host-driven form: when the first attempt's accuracy rounds end after a
+    // host read, the same read takes the inputs of the wide-retry test (the
+    // fallback flags, counts and widths are final there), and the host
+    // applies the test of k_retry to them; with no retry the fallback count
+    // is known as well, so the steady state waits for the device once.
+    struct {
+        bool valid = false, retry = false;
+        int nfb = 0;
+    } early;
+    std::vector<int> hv;
+    auto count_fb = [&](const int* v) {
+        int c = 0;
+        for (int q = 0; q < h; ++q) c += v[q] ? 1 : 0;
+        return c;
+    };
+
     // One attempt of the randomized SVT, run when *gate != 0 at sketch width *width.
     // (the retry attempt, at the widest sketch, has TP_PARAM_RETRY_ROUNDS
     // accuracy rounds, at most as many as the first)
@@ -1127,9 +1154,25 @@ int tp_prox_tnn_learned(const float* Y, float* X, int n1, int n2, int n3, float 
                                                 (double)opts->accuracy, W.bad, h, W.accpart, fb, run, next, last, s));
             if (last) break;
             if (host) {  // the later rounds run only when this one found an inaccurate slice
-                int more = 0;
-                if (read_device_ints(next, 1, &more, s) != hipSuccess) return TP_ERR_HIP;
-                if (!more) break;
+                const bool pre = a == 0 && opts->retry_wide;
+                hv.resize(2 + 4 * h);
+                const hipError_t e =
+                    pre ? read_device_ints({{next, 1}, {ctl + C_G1, 1}, {fb, h}, {W.kpred, 3 * h}}, hv.data(), s)
+                        : read_device_ints({{next, 1}}, hv.data(), s);
+                if (e != hipSuccess) return TP_ERR_HIP;
+                if (!hv[0] && pre) {  // the wide-retry test (k_retry) on the final flags of this attempt
+                    const int* f = hv.data() + 2;
+                    const int *kp = f + h, *la = kp + h, *pf = la + h;
+                    const int kwide = std::min(std::max(L - opts->oversample, 0), p);
+                    const int lwide = std::min(kwide + opts->oversample, p);
+                    bool any = false;
+                    for (int q = 0; q < h; ++q)
+                        any = any || (hv[1] != 0 && f[q] && !pf[q] && la[q] < lwide && kp[q] < kwide);
+                    early.valid = true;
+                    early.retry = any;
+                    early.nfb = count_fb(f);
+                }
+                if (!hv[0]) break;
             }
             // the next subspace iteration needs no new product: Ybar^* Y is
             // the projection just formed (its orthonormal basis Q2 is in W.za),
@@ -1172,31 +1215,35 @@ int tp_prox_tnn_learned(const float* Y, float* X, int n1, int n2, int n3, float 
     // host-driven form: the number of fallback slices once the host knows it
     // (-1: not read); the fallback flags are final when no retry runs
     int host_nfb = -1;
-    std::vector<int> hv;
-    auto count_fb = [&](const int* v) {
-        int c = 0;
-        for (int q = 0; q < h; ++q) c += v[q] ? 1 : 0;
-        return c;
-    };
     if (opts->retry_wide) {
         // slices whose count check failed below the widest sketch: one retry
         // with kpred = max_rank - oversample (the whole call is recomputed
         // at the retry's width)
-        TP_LAUNCH(tp::K_PREDICT, s,
-                  tp::launch_retry(fb, W.prefb, W.kpred, W.lact, h, p, opts->oversample, L, ctl + C_G1,
-                                   ctl + C_RETRY, s));
-        TP_LAUNCH(tp::K_PREDICT, s,
-                  tp::launch_width(W.kpred, W.lact, W.prefb, fb, h, p, opts->oversample, L, ctl + C_RETRY,
-                                   ctl + C_L2, ctl + C_G2, false, s));
+        // (host-driven, with the test already taken on the host and no retry:
+        // both would only write the zero gates the call started with)
+        if (!(host && early.valid && !early.retry)) {
+            TP_LAUNCH(tp::K_PREDICT, s,
+                      tp::launch_retry(fb, W.prefb, W.kpred, W.lact, h, p, opts->oversample, L, ctl + C_G1,
+                                       ctl + C_RETRY, s));
+            TP_LAUNCH(tp::K_PREDICT, s,
+                      tp::launch_width(W.kpred, W.lact, W.prefb, fb, h, p, opts->oversample, L, ctl + C_RETRY,
+                                       ctl + C_L2, ctl + C_G2, false, s));
+        }
         bool retry = true;
         if (host) {
             // a closed retry changes nothing: its gated launches exit, and the
             // basis and singular values it stores are the first attempt's,
-            // stored again
-            hv.resize(1 + h);
-            if (read_device_ints(ctl + C_G2, 1, hv.data(), s, fb, h) != hipSuccess) return TP_ERR_HIP;
-            retry = hv[0] != 0;
-            if (!retry) host_nfb = count_fb(hv.data() + 1);
+            // stored again (its gate is the retry test's result: a retried
+            // slice has a nonzero width)
+            if (early.valid) {
+                retry = early.retry;
+                if (!retry) host_nfb = early.nfb;
+            } else {
+                hv.resize(1 + h);
+                if (read_device_ints({{ctl + C_G2, 1}, {fb, h}}, hv.data(), s) != hipSuccess) return TP_ERR_HIP;
+                retry = hv[0] != 0;
+                if (!retry) host_nfb = count_fb(hv.data() + 1);
+            }
         }
         if (retry) {
             st = attempt(1, ctl + C_G2, ctl + C_L2);
@@ -1205,7 +1252,7 @@ int tp_prox_tnn_learned(const float* Y, float* X, int n1, int n2, int n3, float 
     }
     if (host && host_nfb < 0) {
         hv.resize(h);
-        if (read_device_ints(fb, h, hv.data(), s) != hipSuccess) return TP_ERR_HIP;
+        if (read_device_ints({{fb, h}}, hv.data(), s) != hipSuccess) return TP_ERR_HIP;
         host_nfb = count_fb(hv.data());
     }
     // fallback slices: the full SVD on a compact batch whose size is known
