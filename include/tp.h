@@ -18,7 +18,9 @@
  *             the matching *_workspace_size query and must be at least that
  *             large.  The library allocates no device memory and does not
  *             synchronise; every call only enqueues kernels on `stream`
- *             (a hipStream_t, NULL for the default stream).
+ *             (a hipStream_t, NULL for the default stream).  Exceptions:
+ *             tp_trpca (its stopping test), and tp_prox_tnn_learned when
+ *             TP_PARAM_LEARNED_HOST is set (see there).
  *   Errors    Arguments are checked on the host before anything is enqueued;
  *             a negative tp_status is returned and nothing runs.  TP_ERR_HIP
  *             reports a failed kernel launch (hipGetLastError).  Outcomes that
@@ -199,7 +201,12 @@ int tp_teye(float* out, int n, int n3, void* stream);
  * (a launch whose gate is closed does nothing).  Like the other entry points
  * it allocates nothing and does not synchronise, so a HIP graph may capture
  * it; each possible accuracy round adds about twenty such launches, so
- * max_power_iters - power_iters is best kept small.
+ * max_power_iters - power_iters is best kept small.  With
+ * TP_PARAM_LEARNED_HOST = 1 the host instead reads those decisions where
+ * they are taken and enqueues only the launches that run (same results; the
+ * call then synchronises `stream`, allocates a small pinned host buffer per
+ * calling thread on first use, and keeps the device-gated form on a
+ * capturing stream).
  * Features (TP_MLP_INPUTS = 12, FP32, per slice; p = min(n1,n2)):
  *   0 log(tau / rms sigma), rms sigma = ||Ybar^(k)||_F / sqrt(p)
  *   1 log(max column norm / tau)
