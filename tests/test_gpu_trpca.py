@@ -83,6 +83,28 @@ def test_trpca_learned_prox(tp):
     assert _rel(Ll, L0) < 1e-3
 
 
+def test_trpca_learned_prox_host_driven_same_bits(tp):
+    """tp_trpca around the learned prox in its host-driven form
+    (TP_PARAM_LEARNED_HOST = 1) takes the same iterations and gives the same
+    bits as with the default, device-gated form."""
+    from paper_1806_07247_amd import rank_model
+    X, _, _ = _instance(96, 8, 4, seed=5)
+    dev = torch.device("cuda:0")
+    Xd = torch.from_numpy(X).to(dev)
+    mlp = rank_model.load(device=dev)
+    lib = tp._lib.load()
+    out = {}
+    try:
+        for mode in (0, 1):
+            assert lib.tp_set_param(12, mode) == 0  # TP_PARAM_LEARNED_HOST
+            out[mode] = tp.tp_trpca(Xd, learned=dict(mlp=mlp, max_rank=32))
+            torch.cuda.synchronize()
+    finally:
+        lib.tp_set_param(12, 0)
+    assert out[0]["iters"] == out[1]["iters"] and out[0]["converged"] == out[1]["converged"]
+    assert torch.equal(out[0]["L"], out[1]["L"]) and torch.equal(out[0]["S"], out[1]["S"])
+
+
 def test_trpca_edges(tp):
     dev = torch.device("cuda:0")
     # zero input: converged after one iteration with L = S = 0
